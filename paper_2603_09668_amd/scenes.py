@@ -1,0 +1,243 @@
+"""Seeded synthetic wind-tunnel scenes (inputs only; no simulation arithmetic).
+
+The paper's scenes (flags, cloth, leaves and plants reconstructed as
+Gaussian splats; Sec. 4, Tab. sim_time with 52k-146k object particles on a
+128^3 grid) are not available, so these generators produce inputs of the
+same shape: thin sheets and ellipsoidal leaf clusters sampled uniformly, per
+region Young's modulus, a pin mask, and a D3Q19 wind tunnel around them.
+
+Everything here is plain data generation with numpy's PCG64; the same arrays
+feed the HIP path and the float64 oracle.  Particle storage order is sorted
+by 4x4x4 cell tile and then by cell, so that nearby particles are nearby in
+memory (the way a densified splat cloud would be stored after a spatial
+sort); the simulation never depends on that order.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# boundary codes per lattice face, same values as the C header
+BC_PERIODIC, BC_BOUNCEBACK, BC_INLET, BC_OUTLET = 0, 1, 2, 3
+FIXED_COROTATED, NEO_HOOKEAN = 0, 1
+
+
+@dataclass
+class Scene:
+    name: str
+    grid: dict                 # nx, ny, nz, dx, origin
+    x: np.ndarray              # (n, 3) float64
+    mass: np.ndarray           # (n,)
+    vol0: np.ndarray           # (n,)
+    region: np.ndarray         # (n,) int32
+    E: np.ndarray              # (R,)
+    nu: np.ndarray             # (R,)
+    pin: np.ndarray            # (N,) uint8, dense node order i + nx (j + ny k)
+    dt: float
+    gravity: tuple
+    material: int
+    bound: int = 3
+    lattice: dict | None = None     # nx, ny, nz, dx, origin
+    lbm: dict | None = None         # tau, u_in, bc, gust_*
+    wind: dict = field(default_factory=dict)
+    seed: int = 0
+
+    @property
+    def n(self):
+        return self.x.shape[0]
+
+
+def _sort_spatially(x, dx, origin):
+    cell = np.floor((x - np.asarray(origin)) / dx).astype(np.int64)
+    tile = cell // 4
+    key = (((tile[:, 2] * 4096 + tile[:, 1]) * 4096 + tile[:, 0]) * 64
+           + (cell[:, 2] % 4) * 16 + (cell[:, 1] % 4) * 4 + (cell[:, 0] % 4))
+    return np.argsort(key, kind="stable")
+
+
+def _pin_boxes(grid, boxes):
+    nx, ny, nz, dx = grid["nx"], grid["ny"], grid["nz"], grid["dx"]
+    o = np.asarray(grid["origin"])
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pos = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1) * dx + o
+    pin = np.zeros(nx * ny * nz, dtype=np.uint8)
+    for lo, hi in boxes:
+        inside = np.all((pos >= np.asarray(lo)) & (pos <= np.asarray(hi)), axis=1)
+        pin[inside] = 1
+    return pin
+
+
+def _cfl_dt(E_max, nu, rho, dx, cfl=0.4):
+    mu = E_max / (2 * (1 + nu))
+    lam = E_max * nu / ((1 + nu) * (1 - 2 * nu))
+    cp = math.sqrt((lam + 2 * mu) / rho)
+    return cfl * dx / cp
+
+
+def sheet_scene(seed: int = 0, n: int = 20_000, res: int = 32):
+    """Small plain-method scene: a 0.5 x 0.5 x 0.02 sheet pinned on one edge.
+
+    32^3 grid (dx = 1/32), fixed-corotated E = 1e4, nu = 0.3, rho = 1,
+    dt = 1e-4; a 32^3 D3Q19 lattice with tau = 0.6, uniform inflow 0.05
+    along +x, bounce-back walls on y and z."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dx = 1.0 / res
+    lo = np.array([0.49, 0.25, 0.25])
+    hi = np.array([0.51, 0.75, 0.75])
+    x = lo + (hi - lo) * rng.random((n, 3))
+    vol = np.prod(hi - lo)
+    grid = dict(nx=res, ny=res, nz=res, dx=dx, origin=(0.0, 0.0, 0.0))
+    order = _sort_spatially(x, dx, grid["origin"])
+    x = x[order]
+    rho = 1.0
+    vol0 = np.full(n, vol / n)
+    pin = _pin_boxes(grid, [((0.49 - 2 * dx, 0.75 - dx, 0.25 - 2 * dx),
+                             (0.51 + 2 * dx, 0.75 + 3 * dx, 0.75 + 2 * dx))])
+    lattice = dict(nx=res, ny=res, nz=res, dx=dx, origin=(0.0, 0.0, 0.0))
+    lbm = dict(tau=0.6, u_in=(0.05, 0.0, 0.0), force=(0.0, 0.0, 0.0),
+               bc=(BC_INLET, BC_OUTLET, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK),
+               gust_amp=0.0, gust_period=1.0, gust_ky=0.0, gust_kz=0.0, gust_phase=0.0)
+    return Scene(name=f"sheet{res}_n{n}", grid=grid, x=x, mass=rho * vol0, vol0=vol0,
+                 region=np.zeros(n, np.int32), E=np.array([1e4]), nu=np.array([0.3]), pin=pin,
+                 dt=1e-4, gravity=(0.0, -9.8, 0.0), material=FIXED_COROTATED, lattice=lattice,
+                 lbm=lbm, wind=dict(mode="lbm", vel_scale=20.0, k_drag=9.8), seed=seed)
+
+
+def _ellipsoid_points(rng, centre, axes, count):
+    pts = np.empty((0, 3))
+    while pts.shape[0] < count:
+        cand = rng.uniform(-1.0, 1.0, (2 * count + 16, 3))
+        cand = cand[np.sum(cand * cand, axis=1) <= 1.0]
+        pts = np.concatenate([pts, cand], axis=0)
+    return centre + pts[:count] * axes
+
+
+def flag_and_leaves_scene(seed: int = 0, n: int = 500_000, res: int = 128, n_clusters: int = 40,
+                          lbm_dims=(128, 64, 64), n_regions: int | None = None,
+                          E_range=(1e3, 1e5), sheet_fraction: float = 0.5):
+    """Paper-scale forward scene: one thin flag sheet plus ellipsoidal leaf clusters.
+
+    Cluster semi-axes uniform in [0.01, 0.05], centres in [0.5, 0.85] x
+    [0.3, 0.7]^2; particle counts proportional to volume; per-region E
+    log-uniform in E_range (``n_regions`` caps the number of distinct
+    materials, cycling regions over them); nu = 0.3, rho = 1; dt from the
+    CFL condition dt = 0.4 dx / c_p at the stiffest E; the sheet's top edge
+    and the top tenth of every cluster are pinned.  LBM tunnel of
+    ``lbm_dims`` nodes at spacing 1/lbm_dims[0] centred on the objects,
+    inflow 0.08 along +x with a seeded 5 % sinusoidal gust."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dx = 1.0 / res
+    grid = dict(nx=res, ny=res, nz=res, dx=dx, origin=(0.0, 0.0, 0.0))
+    s_lo = np.array([0.40, 0.27, 0.27])
+    s_hi = np.array([0.42, 0.73, 0.73])
+    n_sheet = int(round(n * sheet_fraction))
+    axes = rng.uniform(0.01, 0.05, (n_clusters, 3))
+    centres = np.stack([rng.uniform(0.5, 0.85, n_clusters), rng.uniform(0.3, 0.7, n_clusters),
+                        rng.uniform(0.3, 0.7, n_clusters)], axis=1)
+    vols = 4.0 / 3.0 * math.pi * np.prod(axes, axis=1)
+    counts = np.floor(vols / vols.sum() * (n - n_sheet)).astype(np.int64)
+    counts[: (n - n_sheet) - counts.sum()] += 1
+    xs = [s_lo + (s_hi - s_lo) * rng.random((n_sheet, 3))]
+    vol0 = [np.full(n_sheet, np.prod(s_hi - s_lo) / n_sheet)]
+    regions = [np.zeros(n_sheet, np.int32)]
+    pin_boxes = [((s_lo[0] - 2 * dx, s_hi[1] - dx, s_lo[2] - 2 * dx),
+                  (s_hi[0] + 2 * dx, s_hi[1] + 3 * dx, s_hi[2] + 2 * dx))]
+    for c in range(n_clusters):
+        pts = _ellipsoid_points(rng, centres[c], axes[c], int(counts[c]))
+        xs.append(pts)
+        vol0.append(np.full(counts[c], vols[c] / max(counts[c], 1)))
+        regions.append(np.full(counts[c], c + 1, np.int32))
+        top = centres[c][1] + 0.8 * axes[c][1]
+        pin_boxes.append(((centres[c][0] - axes[c][0] - dx, top, centres[c][2] - axes[c][2] - dx),
+                          (centres[c][0] + axes[c][0] + dx, top + axes[c][1] + 2 * dx,
+                           centres[c][2] + axes[c][2] + dx)))
+    x = np.concatenate(xs)
+    vol0 = np.concatenate(vol0)
+    region = np.concatenate(regions)
+    R = n_clusters + 1
+    E = np.exp(rng.uniform(math.log(E_range[0]), math.log(E_range[1]), R))
+    if n_regions is not None:
+        region = region % n_regions
+        E = E[:n_regions]
+        R = n_regions
+    nu = np.full(R, 0.3)
+    order = _sort_spatially(x, dx, grid["origin"])
+    x, vol0, region = x[order], vol0[order], region[order]
+    rho = 1.0
+    dt = _cfl_dt(E.max(), 0.3, rho, dx)
+    pin = _pin_boxes(grid, pin_boxes)
+    lnx, lny, lnz = lbm_dims
+    ldx = 1.0 / lnx
+    lorigin = (0.0, 0.5 - 0.5 * lny * ldx, 0.5 - 0.5 * lnz * ldx)
+    lattice = dict(nx=lnx, ny=lny, nz=lnz, dx=ldx, origin=lorigin)
+    lbm = dict(tau=0.6, u_in=(0.08, 0.0, 0.0), force=(0.0, 0.0, 0.0),
+               bc=(BC_INLET, BC_OUTLET, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK),
+               gust_amp=0.05, gust_period=float(rng.uniform(100, 400)),
+               gust_ky=float(rng.integers(0, 2)), gust_kz=float(rng.integers(0, 2)),
+               gust_phase=float(rng.uniform(0, 2 * math.pi)))
+    return Scene(name=f"flag_leaves{res}_n{n}", grid=grid, x=x, mass=rho * vol0, vol0=vol0,
+                 region=region, E=E, nu=nu, pin=pin, dt=dt, gravity=(0.0, -9.8, 0.0),
+                 material=FIXED_COROTATED, lattice=lattice, lbm=lbm,
+                 wind=dict(mode="lbm", vel_scale=1.0 / 0.08, k_drag=9.8), seed=seed)
+
+
+def smooth_force_field(seed: int, K: int = 8, nw: int = 16, amp: float = 5.0, modes: int = 4,
+                       perturb: float = 0.0, perturb_seed: int | None = None):
+    """Smooth seeded wind-force field W (K, 3, nw^3), a sum of low-frequency
+    cosine modes per slot and component; ``perturb`` adds a relative seeded
+    perturbation of the same kind (used to make a target rollout)."""
+    def field(rng):
+        g = np.linspace(0.0, 1.0, nw)
+        Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+        W = np.zeros((K, 3, nw, nw, nw))
+        for s in range(K):
+            for c in range(3):
+                for _ in range(modes):
+                    kx, ky, kz = rng.integers(0, 3, 3)
+                    ph = rng.uniform(0, 2 * math.pi, 3)
+                    a = rng.normal() / modes
+                    W[s, c] += a * (np.cos(math.pi * kx * X + ph[0]) * np.cos(math.pi * ky * Y + ph[1])
+                                    * np.cos(math.pi * kz * Z + ph[2]))
+        return W
+    W = amp * field(np.random.Generator(np.random.PCG64(seed)))
+    if perturb:
+        ps = seed + 1 if perturb_seed is None else perturb_seed
+        W = W + perturb * amp * field(np.random.Generator(np.random.PCG64(ps)))
+    return W.reshape(K, 3, nw ** 3)
+
+
+def random_particles_in_box(seed: int, n: int, lo, hi):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return lo + (hi - lo) * rng.random((n, 3))
+
+
+def random_state(seed: int, n: int, scale_v: float = 0.1, scale_c: float = 1.0,
+                 scale_f: float = 0.05):
+    """Seeded non-trivial particle state: velocities, affine matrices and
+    deformation gradients near identity (det F > 0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = scale_v * rng.standard_normal((n, 3))
+    C = scale_c * rng.standard_normal((n, 3, 3))
+    F = np.eye(3)[None] + scale_f * rng.standard_normal((n, 3, 3))
+    return v, C, F
+
+
+def wind_tunnel_obstacles(seed: int, dims=(64, 64, 64)):
+    """Surrogate-training lattice: inflow speed uniform in [0.02, 0.1] along +x and
+    1-4 random obstacle boxes with sides of 4-16 cells; returns (u_in, solid
+    (nz, ny, nx) bool, bc)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = dims
+    u = float(rng.uniform(0.02, 0.1))
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    for _ in range(int(rng.integers(1, 5))):
+        s = rng.integers(4, 17, 3)
+        o = np.array([rng.integers(8, nx - 8 - s[0]), rng.integers(2, ny - 2 - s[1]),
+                      rng.integers(2, nz - 2 - s[2])])
+        solid[o[2]:o[2] + s[2], o[1]:o[1] + s[1], o[0]:o[0] + s[0]] = True
+    bc = (BC_INLET, BC_OUTLET, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK)
+    return u, solid, bc
