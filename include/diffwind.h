@@ -1,0 +1,278 @@
+/*
+ * diffwind.h -- C ABI of libdiffwind.so, the MI355X (gfx950) implementation of
+ * the simulation step of DiffWind (ICLR 2026): one MLS-MPM substep with APIC
+ * transfers coupled to a D3Q19 lattice-Boltzmann wind field, with a
+ * hand-written adjoint for every forward call.
+ *
+ * The step is the interaction operator S of Eq. simulation_mpm,
+ *   (x, v, F, C)^{t+1} = S(x, v, F, C, theta, F_w, dt),
+ * split into its three MPM phases (Appendix "Material Point Method": Eq. P2G,
+ * Eq. G2P, Eq. deformation_update), the wind force field mapped onto the MPM
+ * grid (Sec. 3 problem specification, Sec. 3.2; drag relation of Sec. 3.4),
+ * the lattice Boltzmann equation (Eq. lbe, Eq. lbm_sum_v2) and the
+ * particle-to-voxel solid rule (Eq. point2voxel).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All arrays are DEVICE pointers, float32 unless stated, owned by the
+ *    caller.  The library never allocates or frees memory; scratch space is a
+ *    caller-provided workspace sized by mpm_workspace_bytes().
+ *  - Structs (dw_grid, dw_particles, ...) are passed by HOST pointer and read
+ *    before the call returns.
+ *  - Layout is structure-of-arrays, component index slowest:
+ *      particle vectors  x[3][n], v[3][n]             (x[a*n + p])
+ *      particle matrices C[9][n], F[9][n]              (M_ab at [(3a+b)*n + p])
+ *      grid scalars      m[N]                          N = nx*ny*nz
+ *      grid vectors      mv[3][N], v[3][N]             node (i,j,k) at i + nx*(j + ny*k)
+ *      LBM populations   f[19][L]                      L = nx*ny*nz of the lattice, x fastest
+ *  - The deformation gradient is stored shifted by the identity: the F array
+ *    holds H = F - I (rest state all zeros), so float32 keeps its relative
+ *    resolution on small strains; stresses are evaluated from H without
+ *    forming differences of numbers close to one.
+ *  - LBM populations are stored shifted by their lattice weight, f_i - w_i
+ *    (rest fluid is all zeros); this keeps float32 resolution on the small
+ *    deviations from rest.  Direction order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ *    7..18 = (+1,+1,0),(-1,-1,0),(+1,0,+1),(-1,0,-1),(0,+1,+1),(0,-1,-1),
+ *    (+1,-1,0),(-1,+1,0),(+1,0,-1),(-1,0,+1),(0,+1,-1),(0,-1,+1).
+ *  - `stream` is a hipStream_t (torch.cuda.current_stream().cuda_stream on
+ *    PyTorch-ROCm), may be NULL for the null stream.  Every call is
+ *    asynchronous and never synchronises the host.
+ *  - Return codes: DW_OK (0); DW_EINVAL (-1) null pointer, non-positive or
+ *    inconsistent size, unsupported enum value; DW_ERANGE (-2) size beyond
+ *    int32 indexing or a fixed kernel limit; DW_ELAUNCH (-3) the HIP launch
+ *    failed; DW_EWORKSPACE (-4) workspace too small.  dw_last_error() gives a
+ *    message for the last non-zero return on the calling host thread.  No call
+ *    aborts the process.
+ *  - Device-side conditions are OR-ed into the status word, the first int32
+ *    of the MPM workspace (DW_STATUS_* bits); the caller reads it at its sync
+ *    points.  mpm_sort() clears it.
+ *  - Every *_adj call ACCUMULATES (+=) into its *_bar outputs, which the
+ *    caller zeroes once; this lets autograd sum contributions.
+ */
+#ifndef DIFFWIND_H
+#define DIFFWIND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { DW_OK = 0, DW_EINVAL = -1, DW_ERANGE = -2, DW_ELAUNCH = -3, DW_EWORKSPACE = -4 };
+
+/* constitutive models (Appendix "Continuum Mechanics", Eq. constitutive_model) */
+enum { DW_FIXED_COROTATED = 0, DW_NEO_HOOKEAN = 1 };
+
+/* lattice faces: x-, x+, y-, y+, z-, z+ */
+enum { DW_BC_PERIODIC = 0, DW_BC_BOUNCEBACK = 1, DW_BC_INLET = 2, DW_BC_OUTLET = 3 };
+
+/* sources of the per-node wind acceleration */
+enum { DW_WIND_NONE = 0, DW_WIND_FORCE_GRID = 1, DW_WIND_LBM_DRAG = 2, DW_WIND_ACC = 3 };
+
+/* status bits */
+enum {
+  DW_STATUS_OUT_OF_GRID = 1, /* a particle's 27-node stencil left the grid; it was skipped */
+  DW_STATUS_NONFINITE = 2,   /* a NaN/Inf particle position was met */
+  DW_STATUS_INVERTED = 4     /* det F <= 0 met in the stress evaluation */
+};
+
+/* MPM background grid: nodes at origin + dx * (i, j, k); nx, ny, nz >= 3. */
+typedef struct {
+  int nx, ny, nz;
+  float dx;
+  float origin[3];
+} dw_grid;
+
+/* LBM lattice: nodes at origin + dx * (i, j, k).  Solid cells of Eq.
+ * point2voxel are the cells [x_w, x_w + dx). */
+typedef struct {
+  int nx, ny, nz;
+  float dx;
+  float origin[3];
+} dw_lattice;
+
+typedef struct {
+  float dt;          /* substep */
+  float gravity[3];  /* body acceleration */
+  int bound;         /* separating-slip wall depth in nodes (0 = none) */
+  int material;      /* DW_FIXED_COROTATED | DW_NEO_HOOKEAN */
+  int deterministic; /* 1: fixed-order reductions, bit-reproducible P2G */
+} dw_mpm_params;
+
+/* Particle state (x, m, u, C, F) of the appendix five-tuple plus theta:
+ * per-particle rest volume and region index, per-region Young's modulus E
+ * and Poisson ratio nu (Lame parameters by Eq. young_poisson). */
+typedef struct {
+  int n;
+  float *x, *v, *C, *F;   /* [3][n], [3][n], [9][n], [9][n]; F holds F - I */
+  const float *mass;      /* [n] */
+  const float *vol0;      /* [n] */
+  const int32_t *region;  /* [n], values in [0, n_regions) */
+  const float *E, *nu;    /* [n_regions] */
+  int n_regions;
+} dw_particles;
+
+/* Adjoint particle state: same layout as dw_particles' x, v, C, F. */
+typedef struct {
+  int n;
+  float *x, *v, *C, *F;
+} dw_particles_bar;
+
+/* Wind acceleration source for the MPM grid nodes (Sec. 3.2: the force
+ * property of the wind grid acts on the MPM background grid). */
+typedef struct {
+  int mode;            /* DW_WIND_* */
+  /* DW_WIND_FORCE_GRID: vertex-centred grid of nw[0]*nw[1]*nw[2] nodes
+   * spanning [lo, hi], W = [3][nw_z][nw_y][nw_x] (one time slot); positions
+   * outside the box are clamped onto it. */
+  int nw[3];
+  float lo[3], hi[3];
+  const float *W;
+  /* DW_WIND_LBM_DRAG: a = k_drag |U| U with U = vel_scale * trilinear(u);
+   * u = [3][L] lattice velocity (zero on solid nodes); MPM nodes outside the
+   * lattice box get no wind.  Drag relation of Sec. 3.4 with
+   * k_drag = rho_w C_D / 2 times area over mass. */
+  dw_lattice lat;
+  const float *u;
+  float vel_scale, k_drag;
+  /* DW_WIND_ACC: precomputed acceleration [3][N] (e.g. from wind_to_grid) */
+  const float *acc;
+} dw_wind;
+
+typedef struct {
+  float tau;          /* BGK relaxation time, > 0.5; viscosity (tau - 1/2) / 3 */
+  float u_in[3];      /* inlet velocity (lattice units) */
+  float force[3];     /* uniform body-force density (Guo forcing), lattice units */
+  int bc[6];          /* DW_BC_* per face x-, x+, y-, y+, z-, z+; INLET only on x-,
+                         OUTLET only on x+; PERIODIC must pair on an axis */
+  /* inlet gust: u_in * (1 + amp sin(2 pi (t / period + ky j / ny + kz k / nz) + phase)) */
+  float gust_amp, gust_period, gust_ky, gust_kz, gust_phase;
+  int t;              /* step index for the gust */
+} dw_lbm_params;
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message for the last non-zero return on this host thread ("" if none). */
+const char *dw_last_error(void);
+
+/* ------------------------------------------------------------- MPM forward */
+
+/* Bytes of workspace needed by the MPM calls for this grid and up to n_max
+ * particles.  The workspace holds the status word, the cell-tile sort and
+ * the active-tile lists; it persists between calls of one substep. */
+size_t mpm_workspace_bytes(const dw_grid *grid, int n_max);
+
+/* Cell sort (groups particles for the P2G scatter).  Key of particle p =
+ * linear index of the 4x4x4 tile holding its stencil base cell
+ * floor((x_p - origin)/dx - 1/2).  Writes into the workspace: the permutation
+ * grouping particles by tile (order inside a tile unspecified unless
+ * params->deterministic), per-tile ranges, the active cell tiles, and the
+ * active node tiles (4x4x4 node blocks holding a node of some particle's
+ * stencil).  Clears the status word.  x: [3][n]. */
+int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const float *x, int n,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* P2G, Eq. P2G with the MLS-MPM stress term:
+ *   A_p  = m_p C_p - dt V0_p (4/dx^2) tau(F_p),   tau = P F^T (Kirchhoff),
+ *   m_i  = sum_p w_ip m_p,
+ *   mv_i = sum_p w_ip (m_p v_p + A_p (x_i - x_p)),
+ * quadratic B-spline weights w_ip.  Runs mpm_sort first.  OVERWRITES grid_m
+ * [N] and grid_mv [3][N] on every node of every active node tile; nodes
+ * outside active tiles are not written.  Particles whose stencil leaves the
+ * grid are skipped and flagged in the status word. */
+int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p,
+            float *grid_m, float *grid_mv, void *ws, size_t ws_bytes, void *stream);
+
+/* Grid update, explicit integration of Eq. continuum_mechanics on active
+ * nodes: for m_i > 0, v_i = mv_i / m_i + dt (g + a_i) where a_i is the wind
+ * acceleration from `wind` (NULL = none); else v_i = 0.  Separating-slip
+ * walls `bound` nodes deep zero the outward component; pin[i] != 0 (NULL =
+ * no pins) zeroes v_i.  Writes grid_v [3][N] on active node tiles only
+ * (active tiles of the last mpm_sort on this workspace). */
+int mpm_grid_update(const dw_grid *grid, const dw_mpm_params *params, const float *grid_m,
+                    const float *grid_mv, const dw_wind *wind, const uint8_t *pin, float *grid_v,
+                    const void *ws, size_t ws_bytes, void *stream);
+
+/* G2P, Eq. G2P with APIC C and Eq. deformation_update:
+ *   v_p = sum_i w_ip v_i,  C_p = (4/dx^2) sum_i w_ip v_i (x_i - x_p)^T,
+ *   x_p += dt v_p,  F_p <- (I + dt C_p) F_p   (weights at the old x_p;
+ *   stored as H <- H + dt C (I + H)).
+ * Reads in->x, in->F; writes out->x, v, C, F.  `in` and `out` may alias. */
+int mpm_g2p(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
+            const dw_particles *in, dw_particles *out, void *stream);
+
+/* Wind acceleration on every MPM node: acc [3][N] (overwritten). */
+int wind_to_grid(const dw_grid *grid, const dw_wind *wind, float *acc, void *stream);
+
+/* ------------------------------------------------------------- MPM adjoints */
+
+/* Reverse of mpm_p2g, a gather per particle: given m_bar [N] and mv_bar [3][N]
+ * (read at stencil nodes), accumulates into bar->x, v, C, F and E_bar
+ * [n_regions] (NULL to skip).  Mass and volume are constants. */
+int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p,
+                const float *grid_m_bar, const float *grid_mv_bar, dw_particles_bar *bar,
+                float *E_bar, void *stream);
+
+/* Reverse of mpm_grid_update on the active node tiles of `ws` (same sort as
+ * the forward).  Recomputes the wall/pin masks from the forward inputs;
+ * accumulates into grid_m_bar [N], grid_mv_bar [3][N] and acc_bar [3][N]
+ * (d loss / d a_i; NULL to skip). */
+int mpm_grid_update_adj(const dw_grid *grid, const dw_mpm_params *params, const float *grid_m,
+                        const float *grid_mv, const dw_wind *wind, const uint8_t *pin,
+                        const float *grid_v_bar, float *grid_m_bar, float *grid_mv_bar,
+                        float *acc_bar, const void *ws, size_t ws_bytes, void *stream);
+
+/* Reverse of mpm_g2p, a sorted scatter: reads the forward inputs in->x,
+ * in->F and grid_v, the output adjoints out_bar (x, v, C, F; any may be
+ * NULL = zero); accumulates into in_bar->x, in_bar->F and grid_v_bar [3][N].
+ * Uses the sort in `ws`, which must come from mpm_sort on the same in->x. */
+int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
+                const dw_particles *in, const dw_particles_bar *out_bar,
+                dw_particles_bar *in_bar, float *grid_v_bar, const void *ws, size_t ws_bytes,
+                void *stream);
+
+/* Reverse of wind_to_grid / of the wind term of mpm_grid_update: given
+ * acc_bar [3][N], accumulates W_bar [3][nw^3] (FORCE_GRID) or u_bar [3][L]
+ * (LBM_DRAG; the lattice velocity adjoint) -- pass the matching pointer in
+ * `out_bar`. */
+int wind_to_grid_adj(const dw_grid *grid, const dw_wind *wind, const float *acc_bar,
+                     float *out_bar, void *stream);
+
+/* ------------------------------------------------------------------ LBM */
+
+/* One fused pull stream-collide step of Eq. lbe with BGK collision (D3Q19),
+ * moments of Eq. lbm_sum_v2 with the half-force shift and Guo forcing.
+ * Streaming: periodic faces wrap; a source beyond a bounce-back face or on a
+ * solid node gives halfway bounce-back f_i(x) = f*_opp(i)(x); a source beyond
+ * the inlet face gives f^eq(rho = 1, u_in(t)); beyond the outlet face the
+ * source is clamped onto the last plane (zero gradient).  Solid nodes
+ * (solid[i] != 0; NULL = none) output the rest state and u = 0, rho = 1.
+ * f_in, f_out: [19][L] shifted populations, must not alias.  rho_out [L] and
+ * u_out [3][L] are optional (NULL). */
+int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in, float *f_out,
+             const uint8_t *solid, float *rho_out, float *u_out, void *stream);
+
+/* Reverse of lbm_step (a push of the adjoint populations): given f_out_bar
+ * [19][L] and u_out_bar [3][L] (NULL = zero), accumulates f_in_bar [19][L]. */
+int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
+                 const uint8_t *solid, const float *f_out_bar, const float *u_out_bar,
+                 float *f_in_bar, void *stream);
+
+/* Shifted equilibrium populations f^eq(rho, u) - w: rho [L] (NULL = 1) and
+ * u [3][L] (NULL = the uniform params->u_in).  Used to initialise a lattice
+ * and to re-initialise it from macroscopic fields. */
+int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const float *rho,
+                    const float *u, float *f, void *stream);
+
+/* Eq. point2voxel: solid[floor((x_p - origin)/dx)] = 1 for every particle
+ * inside the lattice.  accumulate = 0 clears solid [L] (uint8) first,
+ * 1 ORs into it (static obstacles). */
+int lbm_solid_from_particles(const dw_lattice *lat, const float *x, int n, uint8_t *solid,
+                             int accumulate, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIFFWIND_H */

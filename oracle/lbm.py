@@ -207,10 +207,13 @@ def lbm_step(lat: Lattice, p: LBMParams, f_in, solid=None, t: int = 0):
 def voxelize(lat: Lattice, x):
     """Eq. point2voxel: node x_w is solid iff some particle satisfies
     0 <= x_p,d - x_w,d < dx on every axis, i.e. sits in the cell
-    [x_w, x_w + dx); index floor((x_p - origin) / dx), ignored off-lattice."""
+    [x_w, x_w + dx); index floor((x_p - origin) / dx), ignored off-lattice.
+    The index is computed in the precision of ``x`` (float32 input gives the
+    float32 decision)."""
     nx, ny, nz = lat.dims
     solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
-    idx = torch.floor((x - torch.tensor(lat.origin, dtype=_DT)) / lat.dx).to(torch.int64)
+    o = torch.tensor(lat.origin, dtype=x.dtype)
+    idx = torch.floor((x - o) / torch.tensor(lat.dx, dtype=x.dtype)).to(torch.int64)
     ok = ((idx >= 0) & (idx < torch.tensor([nx, ny, nz]))).all(dim=1)
     idx = idx[ok]
     solid[idx[:, 2], idx[:, 1], idx[:, 0]] = True

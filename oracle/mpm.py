@@ -289,21 +289,35 @@ def substep(grid: Grid, state: dict, mass, vol0, mu_p, lam_p, dt: float, materia
 TILE = 4
 
 
-def cell_tile_keys(x, grid: Grid):
+def stencil_base_f32(x32, grid: Grid):
+    """Stencil base cell decided in float32 the way a float32 implementation
+    decides it: X = (x - origin) * fl32(1/dx), base = floor(X - 1/2), each
+    operation rounded to float32.  Used where the integer decision has to be
+    taken in the kernel's precision."""
+    x32 = x32.to(torch.float32)
+    o = torch.tensor(grid.origin, dtype=torch.float32)
+    inv = torch.tensor(1.0 / grid.dx, dtype=torch.float32)
+    X = (x32 - o) * inv
+    return torch.floor(X - torch.tensor(0.5, dtype=torch.float32)).to(torch.int64)
+
+
+def cell_tile_keys(x, grid: Grid, base=None):
     """Sort key of each particle: linear index of the 4x4x4 tile of its stencil
     base cell, tile (bx, by, bz) = base // 4, key = bx + TX (by + TY bz) with
     TX = ceil(nx / 4), TY = ceil(ny / 4)."""
-    base, _, _ = stencil(x, grid)
+    if base is None:
+        base, _, _ = stencil(x, grid)
     t = base // TILE
     TX = -(-grid.nx // TILE)
     TY = -(-grid.ny // TILE)
     return t[:, 0] + TX * (t[:, 1] + TY * t[:, 2])
 
 
-def active_node_tiles(x, grid: Grid):
+def active_node_tiles(x, grid: Grid, base=None):
     """Sorted list of 4x4x4 node tiles that hold at least one node of some
     particle's 27-node stencil (the nodes a P2G writes and a grid update reads)."""
-    base, _, _ = stencil(x, grid)
+    if base is None:
+        base, _, _ = stencil(x, grid)
     TX = -(-grid.nx // TILE)
     TY = -(-grid.ny // TILE)
     keys = set()

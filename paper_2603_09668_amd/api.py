@@ -1,0 +1,375 @@
+"""ctypes binding of libdiffwind.so: the entry points of include/diffwind.h, same names.
+
+Argument marshalling only: every step runs in the HIP kernels of the
+library.  Tensors are torch CUDA (HIP) tensors, float32 (int32 for region,
+uint8 for masks), contiguous, in the structure-of-arrays layout of the
+header: particle vectors (3, n), matrices (9, n) with M_ab at row 3a+b (the
+deformation gradient stored as F - I), grid
+vectors (3, N), LBM populations (19, L) stored as f_i - w_i.  Calls are
+enqueued on torch's current stream.  A missing library raises; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int, c_size_t, c_void_p
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdiffwind.so")
+
+FIXED_COROTATED, NEO_HOOKEAN = 0, 1
+BC_PERIODIC, BC_BOUNCEBACK, BC_INLET, BC_OUTLET = 0, 1, 2, 3
+WIND_NONE, WIND_FORCE_GRID, WIND_LBM_DRAG, WIND_ACC = 0, 1, 2, 3
+STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED = 1, 2, 4
+
+# exported symbols, in the order of include/diffwind.h
+SYMBOLS = [
+    "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p",
+    "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
+    "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_solid_from_particles",
+]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int), ("dx", c_float), ("origin", c_float * 3)]
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int), ("dx", c_float), ("origin", c_float * 3)]
+
+
+class MPMParams(ctypes.Structure):
+    _fields_ = [("dt", c_float), ("gravity", c_float * 3), ("bound", c_int), ("material", c_int),
+                ("deterministic", c_int)]
+
+
+class Particles(ctypes.Structure):
+    _fields_ = [("n", c_int), ("x", c_void_p), ("v", c_void_p), ("C", c_void_p), ("F", c_void_p),
+                ("mass", c_void_p), ("vol0", c_void_p), ("region", c_void_p), ("E", c_void_p),
+                ("nu", c_void_p), ("n_regions", c_int)]
+
+
+class ParticlesBar(ctypes.Structure):
+    _fields_ = [("n", c_int), ("x", c_void_p), ("v", c_void_p), ("C", c_void_p), ("F", c_void_p)]
+
+
+class Wind(ctypes.Structure):
+    _fields_ = [("mode", c_int), ("nw", c_int * 3), ("lo", c_float * 3), ("hi", c_float * 3),
+                ("W", c_void_p), ("lat", Lattice), ("u", c_void_p), ("vel_scale", c_float),
+                ("k_drag", c_float), ("acc", c_void_p)]
+
+
+class LBMParams(ctypes.Structure):
+    _fields_ = [("tau", c_float), ("u_in", c_float * 3), ("force", c_float * 3), ("bc", c_int * 6),
+                ("gust_amp", c_float), ("gust_period", c_float), ("gust_ky", c_float),
+                ("gust_kz", c_float), ("gust_phase", c_float), ("t", c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdiffwind.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_09668_amd.build` "
+                           "or __graft_entry__.build(); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "dw_last_error": ([], ctypes.c_char_p),
+        "mpm_workspace_bytes": ([POINTER(Grid), c_int], c_size_t),
+        "mpm_sort": ([POINTER(Grid), POINTER(MPMParams), P, c_int, P, c_size_t, P], c_int),
+        "mpm_p2g": ([POINTER(Grid), POINTER(MPMParams), POINTER(Particles), P, P, P, c_size_t, P], c_int),
+        "mpm_grid_update": ([POINTER(Grid), POINTER(MPMParams), P, P, POINTER(Wind), P, P, P, c_size_t, P],
+                            c_int),
+        "mpm_g2p": ([POINTER(Grid), POINTER(MPMParams), P, POINTER(Particles), POINTER(Particles), P], c_int),
+        "wind_to_grid": ([POINTER(Grid), POINTER(Wind), P, P], c_int),
+        "mpm_p2g_adj": ([POINTER(Grid), POINTER(MPMParams), POINTER(Particles), P, P, POINTER(ParticlesBar), P,
+                         P], c_int),
+        "mpm_grid_update_adj": ([POINTER(Grid), POINTER(MPMParams), P, P, POINTER(Wind), P, P, P, P, P, P,
+                                 c_size_t, P], c_int),
+        "mpm_g2p_adj": ([POINTER(Grid), POINTER(MPMParams), P, POINTER(Particles), POINTER(ParticlesBar),
+                         POINTER(ParticlesBar), P, P, c_size_t, P], c_int),
+        "wind_to_grid_adj": ([POINTER(Grid), POINTER(Wind), P, P, P], c_int),
+        "lbm_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
+        "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
+        "lbm_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
+        "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+class DiffWindError(RuntimeError):
+    pass
+
+
+def _check(rc: int, name: str):
+    if rc != 0:
+        msg = lib().dw_last_error().decode(errors="replace")
+        raise DiffWindError(f"{name} returned {rc}: {msg}")
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=torch.float32, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------- structs
+
+def make_grid(nx, ny, nz, dx, origin=(0.0, 0.0, 0.0)) -> Grid:
+    return Grid(int(nx), int(ny), int(nz), float(dx), (c_float * 3)(*origin))
+
+
+def make_lattice(nx, ny, nz, dx=1.0, origin=(0.0, 0.0, 0.0)) -> Lattice:
+    return Lattice(int(nx), int(ny), int(nz), float(dx), (c_float * 3)(*origin))
+
+
+def make_mpm_params(dt, gravity=(0.0, 0.0, 0.0), bound=3, material=FIXED_COROTATED, deterministic=False):
+    return MPMParams(float(dt), (c_float * 3)(*gravity), int(bound), int(material), int(bool(deterministic)))
+
+
+def make_lbm_params(tau, u_in=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0), bc=(BC_PERIODIC,) * 6, gust_amp=0.0,
+                    gust_period=1.0, gust_ky=0.0, gust_kz=0.0, gust_phase=0.0, t=0) -> LBMParams:
+    return LBMParams(float(tau), (c_float * 3)(*u_in), (c_float * 3)(*force), (c_int * 6)(*bc),
+                     float(gust_amp), float(gust_period), float(gust_ky), float(gust_kz), float(gust_phase),
+                     int(t))
+
+
+def wind_none() -> Wind:
+    return Wind(mode=WIND_NONE)
+
+
+def wind_force_grid(W_slot, nw, lo, hi) -> Wind:
+    """W_slot: (3, nw_z*nw_y*nw_x) device float32 (one time slot)."""
+    w = Wind(mode=WIND_FORCE_GRID)
+    w.nw = (c_int * 3)(*nw)
+    w.lo = (c_float * 3)(*lo)
+    w.hi = (c_float * 3)(*hi)
+    w.W = _ptr(W_slot, name="W")
+    w._keep = W_slot
+    return w
+
+
+def wind_lbm_drag(lat: Lattice, u, vel_scale, k_drag) -> Wind:
+    w = Wind(mode=WIND_LBM_DRAG)
+    w.lat = lat
+    w.u = _ptr(u, name="u")
+    w.vel_scale = float(vel_scale)
+    w.k_drag = float(k_drag)
+    w._keep = u
+    return w
+
+
+def wind_acc(acc) -> Wind:
+    w = Wind(mode=WIND_ACC)
+    w.acc = _ptr(acc, name="acc")
+    w._keep = acc
+    return w
+
+
+@dataclass
+class ParticleArrays:
+    """Device particle state in the header's layout."""
+
+    x: torch.Tensor      # (3, n)
+    v: torch.Tensor      # (3, n)
+    C: torch.Tensor      # (9, n)
+    F: torch.Tensor      # (9, n), F - I
+    mass: torch.Tensor   # (n,)
+    vol0: torch.Tensor   # (n,)
+    region: torch.Tensor  # (n,) int32
+    E: torch.Tensor      # (R,)
+    nu: torch.Tensor     # (R,)
+
+    @property
+    def n(self):
+        return self.x.shape[1]
+
+    def struct(self) -> Particles:
+        return Particles(self.n, _ptr(self.x, name="x"), _ptr(self.v, name="v"), _ptr(self.C, name="C"),
+                         _ptr(self.F, name="F"), _ptr(self.mass, name="mass"), _ptr(self.vol0, name="vol0"),
+                         _ptr(self.region, torch.int32, "region"), _ptr(self.E, name="E"),
+                         _ptr(self.nu, name="nu"), int(self.E.numel()))
+
+    def with_state(self, x, v, C, F) -> "ParticleArrays":
+        return ParticleArrays(x, v, C, F, self.mass, self.vol0, self.region, self.E, self.nu)
+
+
+def _bar_struct(n, x=None, v=None, C=None, F=None) -> ParticlesBar:
+    return ParticlesBar(n, _ptr(x, name="x_bar"), _ptr(v, name="v_bar"), _ptr(C, name="C_bar"),
+                        _ptr(F, name="F_bar"))
+
+
+# ------------------------------------------------------------ entry points
+
+def dw_last_error() -> str:
+    return lib().dw_last_error().decode(errors="replace")
+
+
+def mpm_workspace_bytes(grid: Grid, n_max: int) -> int:
+    return int(lib().mpm_workspace_bytes(ctypes.byref(grid), int(n_max)))
+
+
+def alloc_workspace(grid: Grid, n_max: int, device="cuda") -> torch.Tensor:
+    nb = mpm_workspace_bytes(grid, n_max)
+    if nb == 0:
+        raise DiffWindError(f"mpm_workspace_bytes failed: {dw_last_error()}")
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nb]
+
+
+def read_status(ws: torch.Tensor) -> int:
+    return int(ws[:4].view(torch.int32).item())
+
+
+def mpm_sort(grid: Grid, params: MPMParams, x, ws):
+    _check(lib().mpm_sort(ctypes.byref(grid), ctypes.byref(params), _ptr(x, name="x"), int(x.shape[1]),
+                          _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()), "mpm_sort")
+
+
+def mpm_p2g(grid: Grid, params: MPMParams, p: ParticleArrays, grid_m, grid_mv, ws):
+    ps = p.struct()
+    _check(lib().mpm_p2g(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(ps), _ptr(grid_m, name="grid_m"),
+                         _ptr(grid_mv, name="grid_mv"), _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()),
+           "mpm_p2g")
+
+
+def mpm_grid_update(grid: Grid, params: MPMParams, grid_m, grid_mv, wind: Wind | None, pin, grid_v, ws):
+    _check(lib().mpm_grid_update(ctypes.byref(grid), ctypes.byref(params), _ptr(grid_m, name="grid_m"),
+                                 _ptr(grid_mv, name="grid_mv"), ctypes.byref(wind) if wind is not None else None,
+                                 _ptr(pin, torch.uint8, "pin"), _ptr(grid_v, name="grid_v"),
+                                 _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()), "mpm_grid_update")
+
+
+def mpm_g2p(grid: Grid, params: MPMParams, grid_v, p_in: ParticleArrays, x_out, v_out, C_out, F_out):
+    n = p_in.n
+    pin = Particles(n, _ptr(p_in.x, name="x"), None, None, _ptr(p_in.F, name="F"), None, None, None, None, None, 0)
+    pout = Particles(n, _ptr(x_out, name="x_out"), _ptr(v_out, name="v_out"), _ptr(C_out, name="C_out"),
+                     _ptr(F_out, name="F_out"), None, None, None, None, None, 0)
+    _check(lib().mpm_g2p(ctypes.byref(grid), ctypes.byref(params), _ptr(grid_v, name="grid_v"), ctypes.byref(pin),
+                         ctypes.byref(pout), _stream()), "mpm_g2p")
+
+
+def wind_to_grid(grid: Grid, wind: Wind, acc):
+    _check(lib().wind_to_grid(ctypes.byref(grid), ctypes.byref(wind), _ptr(acc, name="acc"), _stream()),
+           "wind_to_grid")
+
+
+def mpm_p2g_adj(grid: Grid, params: MPMParams, p: ParticleArrays, grid_m_bar, grid_mv_bar, x_bar=None, v_bar=None,
+                C_bar=None, F_bar=None, E_bar=None):
+    ps = p.struct()
+    bar = _bar_struct(p.n, x_bar, v_bar, C_bar, F_bar)
+    _check(lib().mpm_p2g_adj(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(ps),
+                             _ptr(grid_m_bar, name="grid_m_bar"), _ptr(grid_mv_bar, name="grid_mv_bar"),
+                             ctypes.byref(bar), _ptr(E_bar, name="E_bar"), _stream()), "mpm_p2g_adj")
+
+
+def mpm_grid_update_adj(grid: Grid, params: MPMParams, grid_m, grid_mv, wind: Wind | None, pin, grid_v_bar,
+                        grid_m_bar, grid_mv_bar, acc_bar, ws):
+    _check(lib().mpm_grid_update_adj(ctypes.byref(grid), ctypes.byref(params), _ptr(grid_m, name="grid_m"),
+                                     _ptr(grid_mv, name="grid_mv"),
+                                     ctypes.byref(wind) if wind is not None else None, _ptr(pin, torch.uint8, "pin"),
+                                     _ptr(grid_v_bar, name="grid_v_bar"), _ptr(grid_m_bar, name="grid_m_bar"),
+                                     _ptr(grid_mv_bar, name="grid_mv_bar"), _ptr(acc_bar, name="acc_bar"),
+                                     _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()), "mpm_grid_update_adj")
+
+
+def mpm_g2p_adj(grid: Grid, params: MPMParams, grid_v, p_in: ParticleArrays, x_out_bar=None, v_out_bar=None,
+                C_out_bar=None, F_out_bar=None, x_bar=None, F_bar=None, grid_v_bar=None, ws=None):
+    n = p_in.n
+    pin = Particles(n, _ptr(p_in.x, name="x"), None, None, _ptr(p_in.F, name="F"), None, None, None, None, None, 0)
+    ob = _bar_struct(n, x_out_bar, v_out_bar, C_out_bar, F_out_bar)
+    ib = _bar_struct(n, x_bar, None, None, F_bar)
+    _check(lib().mpm_g2p_adj(ctypes.byref(grid), ctypes.byref(params), _ptr(grid_v, name="grid_v"),
+                             ctypes.byref(pin), ctypes.byref(ob), ctypes.byref(ib),
+                             _ptr(grid_v_bar, name="grid_v_bar"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+                             _stream()), "mpm_g2p_adj")
+
+
+def wind_to_grid_adj(grid: Grid, wind: Wind, acc_bar, out_bar):
+    _check(lib().wind_to_grid_adj(ctypes.byref(grid), ctypes.byref(wind), _ptr(acc_bar, name="acc_bar"),
+                                  _ptr(out_bar, name="out_bar"), _stream()), "wind_to_grid_adj")
+
+
+def lbm_step(lat: Lattice, params: LBMParams, f_in, f_out, solid=None, rho_out=None, u_out=None):
+    _check(lib().lbm_step(ctypes.byref(lat), ctypes.byref(params), _ptr(f_in, name="f_in"),
+                          _ptr(f_out, name="f_out"), _ptr(solid, torch.uint8, "solid"),
+                          _ptr(rho_out, name="rho_out"), _ptr(u_out, name="u_out"), _stream()), "lbm_step")
+
+
+def lbm_step_adj(lat: Lattice, params: LBMParams, f_in, solid, f_out_bar, u_out_bar, f_in_bar):
+    _check(lib().lbm_step_adj(ctypes.byref(lat), ctypes.byref(params), _ptr(f_in, name="f_in"),
+                              _ptr(solid, torch.uint8, "solid"), _ptr(f_out_bar, name="f_out_bar"),
+                              _ptr(u_out_bar, name="u_out_bar"), _ptr(f_in_bar, name="f_in_bar"), _stream()),
+           "lbm_step_adj")
+
+
+def lbm_equilibrium(lat: Lattice, params: LBMParams, f, rho=None, u=None):
+    _check(lib().lbm_equilibrium(ctypes.byref(lat), ctypes.byref(params), _ptr(rho, name="rho"), _ptr(u, name="u"),
+                                 _ptr(f, name="f"), _stream()), "lbm_equilibrium")
+
+
+def lbm_solid_from_particles(lat: Lattice, x, solid, accumulate=False):
+    _check(lib().lbm_solid_from_particles(ctypes.byref(lat), _ptr(x, name="x"), int(x.shape[1]),
+                                          _ptr(solid, torch.uint8, "solid"), int(bool(accumulate)), _stream()),
+           "lbm_solid_from_particles")
+
+
+def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
+    """Read-only views of the sort results inside an MPM workspace (same layout
+    as the library's): status, tile counts, tile ranges, active tile lists,
+    keys and the permutation.  For inspection and tests."""
+    tile = 4
+    T = (-(-grid.nx // tile)) * (-(-grid.ny // tile)) * (-(-grid.nz // tile))
+    NB = -(-T // 1024)
+    off = 0
+    views = {}
+
+    def take(name, count):
+        nonlocal off
+        views[name] = ws[off:off + 4 * count].view(torch.int32)
+        off += (4 * count + 255) // 256 * 256
+
+    take("header", 64)
+    take("tile_count", T)
+    take("tile_cursor", T)
+    take("node_flag", T)
+    take("tile_start", T + 1)
+    take("cell_tiles", T)
+    take("node_tiles", T)
+    take("block_sums", 3 * NB)
+    take("key", n)
+    take("perm", n)
+    hdr = views["header"]
+    views["status"] = hdr[0]
+    views["n_sorted"] = hdr[3]
+    views["n_node_tiles"] = hdr[4]
+    views["n_cell_tiles"] = hdr[5]
+    views["n_tiles"] = T
+    return views

@@ -1,0 +1,318 @@
+// Internal helpers shared by the libdiffwind kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/diffwind.h"
+
+namespace dw {
+
+// ------------------------------------------------------------ host errors
+int set_error(int code, const char *fmt, ...);
+int check_launch(const char *what);
+
+#define DW_REQUIRE(cond, code, ...)                 \
+  do {                                              \
+    if (!(cond)) return ::dw::set_error(code, __VA_ARGS__); \
+  } while (0)
+
+// -------------------------------------------------------------- geometry
+constexpr int TILE = 4;  // cell / node tiles are 4x4x4
+
+struct GridDev {
+  int nx, ny, nz;
+  int tx, ty, tz;  // tiles per axis
+  float dx, inv_dx;
+  float ox, oy, oz;
+};
+
+inline GridDev make_grid(const dw_grid *g) {
+  GridDev d;
+  d.nx = g->nx; d.ny = g->ny; d.nz = g->nz;
+  d.tx = (g->nx + TILE - 1) / TILE;
+  d.ty = (g->ny + TILE - 1) / TILE;
+  d.tz = (g->nz + TILE - 1) / TILE;
+  d.dx = g->dx;
+  d.inv_dx = 1.0f / g->dx;
+  d.ox = g->origin[0]; d.oy = g->origin[1]; d.oz = g->origin[2];
+  return d;
+}
+
+// Workspace layout (bytes, all 256-aligned):
+//   [0, 256)          header: int32 status, n_cell_tiles, n_node_tiles, scratch
+//   tile_count  [T]   int32
+//   tile_start  [T+1] int32
+//   tile_cursor [T]   int32
+//   node_flag   [T]   int32
+//   cell_tiles  [T]   int32   active cell tiles (tile index)
+//   node_tiles  [T]   int32   active node tiles
+//   block_sums  [2*NB] int32  scan partials
+//   key         [n]   int32
+//   perm        [n]   int32
+struct Workspace {
+  int32_t *status;
+  int32_t *n_cell_tiles;
+  int32_t *n_node_tiles;
+  int32_t *tile_count;
+  int32_t *tile_start;
+  int32_t *tile_cursor;
+  int32_t *node_flag;
+  int32_t *cell_tiles;
+  int32_t *node_tiles;
+  int32_t *block_sums;
+  int32_t *key;
+  int32_t *perm;
+  int32_t *perm_tmp;
+  int64_t n_tiles;
+  int64_t n_scan_blocks;
+  size_t bytes;
+};
+
+constexpr int SCAN_BLOCK = 1024;
+
+size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base);
+int check_grid(const dw_grid *g);
+int check_particles(const dw_particles *p, bool need_state);
+// binds the workspace and checks its size
+int bind_workspace(const dw_grid *g, int n, const void *ws, size_t ws_bytes, Workspace *W);
+
+// fill kernels (a kernel rather than hipMemsetAsync, so the calls stay
+// capturable in HIP graphs); static: every translation unit launches its own
+static __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+static __global__ void k_fill_f32(float *p, int64_t count, float value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+inline unsigned grid_blocks(int64_t work, int block) {
+  int64_t b = (work + block - 1) / block;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ---------------------------------------------------- device math helpers
+struct M3 {
+  float a[9];
+};
+
+__device__ __forceinline__ float det3(const float *m) {
+  return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+         m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+// inverse-transpose (cofactor / det)
+__device__ __forceinline__ void inv_transpose3(const float *m, float det, float *out) {
+  float id = 1.0f / det;
+  out[0] = (m[4] * m[8] - m[5] * m[7]) * id;
+  out[1] = -(m[3] * m[8] - m[5] * m[6]) * id;
+  out[2] = (m[3] * m[7] - m[4] * m[6]) * id;
+  out[3] = -(m[1] * m[8] - m[2] * m[7]) * id;
+  out[4] = (m[0] * m[8] - m[2] * m[6]) * id;
+  out[5] = -(m[0] * m[7] - m[1] * m[6]) * id;
+  out[6] = (m[1] * m[5] - m[2] * m[4]) * id;
+  out[7] = -(m[0] * m[5] - m[2] * m[3]) * id;
+  out[8] = (m[0] * m[4] - m[1] * m[3]) * id;
+}
+
+__device__ __forceinline__ void matmul3(const float *a, const float *b, float *c) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      c[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+}
+
+// c = a * b^T
+__device__ __forceinline__ void matmul3_abt(const float *a, const float *b, float *c) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      c[3 * i + j] = a[3 * i] * b[3 * j] + a[3 * i + 1] * b[3 * j + 1] + a[3 * i + 2] * b[3 * j + 2];
+}
+
+// c = a^T * b
+__device__ __forceinline__ void matmul3_atb(const float *a, const float *b, float *c) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      c[3 * i + j] = a[i] * b[j] + a[3 + i] * b[3 + j] + a[6 + i] * b[6 + j];
+}
+
+// Rotation factor of the polar decomposition F = R S (det F > 0) by the
+// scaled Newton iteration X <- (zeta X + X^{-T} / zeta) / 2,
+// zeta = sqrt(|X^{-1}|_F / |X|_F) (Higham 1986).  F = I gives R = I exactly.
+__device__ __forceinline__ void polar_rotation(const float *F, float *R) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = F[i];
+  for (int it = 0; it < 24; ++it) {
+    float d = det3(R);
+    float Y[9];
+    inv_transpose3(R, d, Y);
+    float nx = 0.f, ny = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      nx += R[i] * R[i];
+      ny += Y[i] * Y[i];
+    }
+    float zeta = sqrtf(sqrtf(ny / nx));
+    float iz = 1.0f / zeta;
+    float delta = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      float r = 0.5f * (zeta * R[i] + iz * Y[i]);
+      float e = r - R[i];
+      delta += e * e;
+      R[i] = r;
+    }
+    if (delta <= 1e-13f) break;
+  }
+}
+
+__device__ __forceinline__ void lame(float E, float nu, float &mu, float &lam) {
+  mu = E / (2.0f * (1.0f + nu));
+  lam = E * nu / ((1.0f + nu) * (1.0f - 2.0f * nu));
+}
+
+// Sum of the principal 2x2 minors of a 3x3 matrix.
+__device__ __forceinline__ float minors2(const float *m) {
+  return m[0] * m[4] - m[1] * m[3] + m[0] * m[8] - m[2] * m[6] + m[4] * m[8] - m[5] * m[7];
+}
+
+// det(I + H) - 1 = tr H + minors2(H) + det H, free of cancellation for small H.
+__device__ __forceinline__ float det_shift(const float *H) {
+  return H[0] + H[4] + H[8] + minors2(H) + det3(H);
+}
+
+// Rotation factor of the polar decomposition F = R S, F = I + H, returned as
+// Y = R - I.  Scaled Newton iteration X <- (zeta X + X^{-T} / zeta) / 2
+// (Higham 1986) written for the deviation Y = X - I:
+//   (I + Y)^{-1} - I = (Y^2 - (1 + tr Y) Y - det(Y) I) / det(I + Y)
+// (Cayley-Hamilton), so no step subtracts two numbers close to 1 and the
+// strain F - R = H - Y keeps float32 relative precision for small strains.
+// H = 0 gives Y = 0 exactly.
+__device__ __forceinline__ void polar_shift(const float *H, float *Y) {
+  float hh = 0.f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    Y[i] = H[i];
+    hh += H[i] * H[i];
+  }
+  for (int it = 0; it < 30; ++it) {
+    float t = Y[0] + Y[4] + Y[8];
+    float Y2[9];
+    matmul3(Y, Y, Y2);
+    float dY = det3(Y);
+    float dA = 1.0f + t + minors2(Y) + dY;  // det(I + Y)
+    float id = 1.0f / dA;
+    // Z = (I + Y)^{-T} - I
+    float Z[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        float v = Y2[3 * j + i] - (1.0f + t) * Y[3 * j + i] - (i == j ? dY : 0.f);
+        Z[3 * i + j] = v * id;
+      }
+    // scaling zeta = sqrt(|X^{-1}|_F / |X|_F), X = I + Y
+    float nx = 0.f, ny = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      float a = Y[i] + ((i % 4) == 0 ? 1.f : 0.f);
+      float b = Z[i] + ((i % 4) == 0 ? 1.f : 0.f);
+      nx += a * a;
+      ny += b * b;
+    }
+    float zeta = sqrtf(sqrtf(ny / nx));
+    float iz = 1.0f / zeta;
+    float c = 0.5f * (zeta - 1.0f) * (zeta - 1.0f) * iz;  // (zeta + 1/zeta)/2 - 1
+    float delta = 0.f, yy = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      float yn = 0.5f * (zeta * Y[i] + iz * Z[i]) + ((i % 4) == 0 ? c : 0.f);
+      float e = yn - Y[i];
+      delta += e * e;
+      yy += yn * yn;
+      Y[i] = yn;
+    }
+    if (delta <= 1e-14f * (yy + hh) || delta == 0.f) break;
+  }
+}
+
+// Kirchhoff stress tau = P F^T from the shifted deformation gradient H = F - I.
+//   fixed-corotated: tau = 2 mu (F - R) F^T + lam (J - 1) J I, F - R = H - (R - I)
+//   Neo-Hookean:     tau = mu (F F^T - I) + lam log(J) I, F F^T - I = H + H^T + H H^T
+__device__ __forceinline__ void kirchhoff_shift(const float *H, float mu, float lam, int material, float *tau,
+                                                int32_t *status) {
+  float Jm1 = det_shift(H);
+  float J = 1.0f + Jm1;
+  if (!(J > 0.f)) {
+    if (status) atomicOr(status, DW_STATUS_INVERTED);
+  }
+  if (material == DW_NEO_HOOKEAN) {
+    float HHt[9];
+    matmul3_abt(H, H, HHt);
+    float l = lam * log1pf(Jm1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) tau[3 * i + j] = mu * (H[3 * i + j] + H[3 * j + i] + HHt[3 * i + j]);
+    tau[0] += l;
+    tau[4] += l;
+    tau[8] += l;
+  } else {
+    float Y[9], D[9], F[9];
+    polar_shift(H, Y);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      D[i] = H[i] - Y[i];
+      F[i] = H[i] + ((i % 4) == 0 ? 1.f : 0.f);
+    }
+    matmul3_abt(D, F, tau);
+    float l = lam * Jm1 * J;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) tau[i] *= 2.0f * mu;
+    tau[0] += l;
+    tau[4] += l;
+    tau[8] += l;
+  }
+}
+
+// Grid coordinate X = (x - origin) / dx of a particle and its stencil base
+// floor(X - 1/2).  Contraction is disabled so that every kernel rounds the
+// same way and a particle lands in the same cell tile in the sort, the
+// transfers and the adjoints.
+__device__ __forceinline__ float grid_coord(float x, float o, float inv_dx) {
+#pragma clang fp contract(off)
+  return (x - o) * inv_dx;
+}
+
+__device__ __forceinline__ int base_of(float X) {
+#pragma clang fp contract(off)
+  return (int)floorf(X - 0.5f);
+}
+
+// Quadratic B-spline weights of nodes base + 0, 1, 2 at fractional position
+// f = X - base in [1/2, 3/2), and their derivatives d w / d f.
+__device__ __forceinline__ void bspline_w(float f, float w[3]) {
+  float a = 1.5f - f, b = f - 1.0f, c = f - 0.5f;
+  w[0] = 0.5f * a * a;
+  w[1] = 0.75f - b * b;
+  w[2] = 0.5f * c * c;
+}
+
+__device__ __forceinline__ void bspline_dw(float f, float dw[3]) {
+  dw[0] = f - 1.5f;
+  dw[1] = -2.0f * (f - 1.0f);
+  dw[2] = f - 0.5f;
+}
+
+__device__ __forceinline__ bool stencil_inside(const GridDev &g, int bx, int by, int bz) {
+  return bx >= 0 && by >= 0 && bz >= 0 && bx + 2 < g.nx && by + 2 < g.ny && bz + 2 < g.nz;
+}
+
+}  // namespace dw

@@ -1,0 +1,363 @@
+// D3Q19 lattice Boltzmann for gfx950: fused pull stream-collide with BGK
+// collision (Eq. lbe), moments with the half-force shift (Eq. lbm_sum_v2),
+// Guo forcing, halfway bounce-back, equilibrium inlet, zero-gradient outlet,
+// and the particle-to-voxel solid rule (Eq. point2voxel).  Populations are
+// stored as f_i - w_i (structure of arrays [19][L], x fastest), so float32
+// keeps its resolution on the deviation from rest.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "dw_internal.h"
+
+namespace dw {
+
+__device__ constexpr int LC[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                      {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, 0, 1},
+                                      {-1, 0, -1}, {0, 1, 1},  {0, -1, -1}, {1, -1, 0}, {-1, 1, 0},
+                                      {1, 0, -1}, {-1, 0, 1},  {0, 1, -1}, {0, -1, 1}};
+__device__ constexpr int LOPP[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+__device__ constexpr float LW[19] = {1.f / 3,  1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18,
+                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36,
+                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+
+struct LbmDev {
+  int nx, ny, nz;
+  int64_t L;
+  float omega;     // 1 / tau
+  float uin[3];
+  float F[3];
+  int bc[6];
+  float gust_amp, gust_inv_period, gust_ky, gust_kz, gust_phase;
+  int t;
+  bool forced;
+};
+
+// Where the population arriving at (i, j, k) in direction q comes from.
+enum { SRC_NORMAL = 0, SRC_BOUNCE = 1, SRC_INLET = 2 };
+
+__device__ __forceinline__ int pull_source(const LbmDev &P, const uint8_t *__restrict__ solid, int i, int j,
+                                           int k, int q, int64_t &src) {
+  int s[3] = {i - LC[q][0], j - LC[q][1], k - LC[q][2]};
+  const int n[3] = {P.nx, P.ny, P.nz};
+  bool bounce = false, inlet = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int lo = P.bc[2 * a], hi = P.bc[2 * a + 1];
+    if (s[a] < 0) {
+      if (lo == DW_BC_PERIODIC) s[a] += n[a];
+      else if (lo == DW_BC_BOUNCEBACK) bounce = true;
+      else if (lo == DW_BC_INLET) inlet = true;
+    } else if (s[a] >= n[a]) {
+      if (hi == DW_BC_PERIODIC) s[a] -= n[a];
+      else if (hi == DW_BC_BOUNCEBACK) bounce = true;
+      else if (hi == DW_BC_OUTLET) s[a] = n[a] - 1;
+    }
+  }
+  if (bounce) return SRC_BOUNCE;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s[a] = min(max(s[a], 0), n[a] - 1);
+  src = s[0] + (int64_t)P.nx * (s[1] + (int64_t)P.ny * s[2]);
+  if (inlet) return SRC_INLET;
+  if (solid && solid[src]) return SRC_BOUNCE;
+  return SRC_NORMAL;
+}
+
+// inlet equilibrium population (shifted) in direction q at inlet-plane (j, k)
+__device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, int k) {
+  float sfac = 1.0f;
+  if (P.gust_amp != 0.f) {
+    float ph = 6.283185307179586f * ((float)P.t * P.gust_inv_period + P.gust_ky * (float)j / (float)P.ny +
+                                     P.gust_kz * (float)k / (float)P.nz) +
+               P.gust_phase;
+    sfac = 1.0f + P.gust_amp * sinf(ph);
+  }
+  float ux = P.uin[0] * sfac, uy = P.uin[1] * sfac, uz = P.uin[2] * sfac;
+  float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+  float uu = ux * ux + uy * uy + uz * uz;
+  return LW[q] * (3.f * cu + 4.5f * cu * cu - 1.5f * uu);
+}
+
+// Pull the 19 shifted populations of fluid node (i, j, k).
+__device__ __forceinline__ void pull_all(const LbmDev &P, const float *__restrict__ fin,
+                                         const uint8_t *__restrict__ solid, int i, int j, int k, int64_t node,
+                                         float f[19]) {
+  bool interior = i > 0 && j > 0 && k > 0 && i < P.nx - 1 && j < P.ny - 1 && k < P.nz - 1;
+  if (interior) {
+    const int64_t sx = 1, sy = P.nx, sz = (int64_t)P.nx * P.ny;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      int64_t src = node - (LC[q][0] * sx + LC[q][1] * sy + LC[q][2] * sz);
+      bool bb = solid && solid[src];
+      f[q] = bb ? fin[(int64_t)LOPP[q] * P.L + node] : fin[(int64_t)q * P.L + src];
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    int64_t src = node;
+    int kind = pull_source(P, solid, i, j, k, q, src);
+    if (kind == SRC_NORMAL) f[q] = fin[(int64_t)q * P.L + src];
+    else if (kind == SRC_BOUNCE) f[q] = fin[(int64_t)LOPP[q] * P.L + node];
+    else {
+      int sj = (int)((src / P.nx) % P.ny), sk = (int)(src / ((int64_t)P.nx * P.ny));
+      f[q] = inlet_feq_shift(P, q, sj, sk);
+    }
+  }
+}
+
+__device__ __forceinline__ void moments(const LbmDev &P, const float f[19], float &rho, float &ux, float &uy,
+                                        float &uz) {
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    drho += f[q];
+    jx += LC[q][0] * f[q];
+    jy += LC[q][1] * f[q];
+    jz += LC[q][2] * f[q];
+  }
+  rho = 1.0f + drho;
+  float ir = 1.0f / rho;
+  ux = (jx + 0.5f * P.F[0]) * ir;
+  uy = (jy + 0.5f * P.F[1]) * ir;
+  uz = (jz + 0.5f * P.F[2]) * ir;
+}
+
+__global__ __launch_bounds__(256) void k_lbm_step(LbmDev P, const float *__restrict__ fin, float *__restrict__ fout,
+                                                  const uint8_t *__restrict__ solid, float *__restrict__ rho_out,
+                                                  float *__restrict__ u_out) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= P.L) return;
+  if (solid && solid[node]) {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) fout[(int64_t)q * P.L + node] = 0.f;
+    if (rho_out) rho_out[node] = 1.f;
+    if (u_out) {
+      u_out[node] = 0.f;
+      u_out[P.L + node] = 0.f;
+      u_out[2 * P.L + node] = 0.f;
+    }
+    return;
+  }
+  int i = (int)(node % P.nx);
+  int j = (int)((node / P.nx) % P.ny);
+  int k = (int)(node / ((int64_t)P.nx * P.ny));
+  float f[19];
+  pull_all(P, fin, solid, i, j, k, node, f);
+  float rho, ux, uy, uz;
+  moments(P, f, rho, ux, uy, uz);
+  float drho = rho - 1.0f;
+  float uu = ux * ux + uy * uy + uz * uz;
+  float om = P.omega;
+  float kf = 1.0f - 0.5f * om;
+  float uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+    float feq = LW[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+    float g = f[q] - om * (f[q] - feq);
+    if (P.forced) {
+      float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
+      g += kf * LW[q] * (3.f * (cF - uF) + 9.f * cu * cF);
+    }
+    fout[(int64_t)q * P.L + node] = g;
+  }
+  if (rho_out) rho_out[node] = rho;
+  if (u_out) {
+    u_out[node] = ux;
+    u_out[P.L + node] = uy;
+    u_out[2 * P.L + node] = uz;
+  }
+}
+
+// Reverse of k_lbm_step: recompute the pulled populations and moments, form
+// the adjoint of the pulled populations through the BGK collision, and push
+// each one back to where it was pulled from (atomics: boundary rules can
+// make two destinations share one source).
+__global__ __launch_bounds__(256) void k_lbm_step_adj(LbmDev P, const float *__restrict__ fin,
+                                                      const uint8_t *__restrict__ solid,
+                                                      const float *__restrict__ gout,
+                                                      const float *__restrict__ ubar_out,
+                                                      float *__restrict__ fin_bar) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= P.L) return;
+  if (solid && solid[node]) return;
+  int i = (int)(node % P.nx);
+  int j = (int)((node / P.nx) % P.ny);
+  int k = (int)(node / ((int64_t)P.nx * P.ny));
+  float f[19];
+  pull_all(P, fin, solid, i, j, k, node, f);
+  float rho, ux, uy, uz;
+  moments(P, f, rho, ux, uy, uz);
+  float uu = ux * ux + uy * uy + uz * uz;
+  float om = P.omega;
+  float kf = 1.0f - 0.5f * om;
+  float g[19];
+  float rbar = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    g[q] = gout[(int64_t)q * P.L + node];
+    float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+    // d feq_q / d rho at fixed u = feq_q / rho
+    rbar += om * g[q] * LW[q] * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
+    // d feq_q / d u = w rho (3 c + 9 (c.u) c - 3 u)
+    float s = om * g[q] * LW[q] * rho;
+    bx += s * (3.f * LC[q][0] + 9.f * cu * LC[q][0] - 3.f * ux);
+    by += s * (3.f * LC[q][1] + 9.f * cu * LC[q][1] - 3.f * uy);
+    bz += s * (3.f * LC[q][2] + 9.f * cu * LC[q][2] - 3.f * uz);
+    if (P.forced) {
+      float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
+      float t = kf * g[q] * LW[q];
+      bx += t * (9.f * cF * LC[q][0] - 3.f * P.F[0]);
+      by += t * (9.f * cF * LC[q][1] - 3.f * P.F[1]);
+      bz += t * (9.f * cF * LC[q][2] - 3.f * P.F[2]);
+    }
+  }
+  if (ubar_out) {
+    bx += ubar_out[node];
+    by += ubar_out[P.L + node];
+    bz += ubar_out[2 * P.L + node];
+  }
+  float ir = 1.0f / rho;
+  float bu = bx * ux + by * uy + bz * uz;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    float fb = (1.f - om) * g[q] + rbar + (bx * LC[q][0] + by * LC[q][1] + bz * LC[q][2] - bu) * ir;
+    int64_t src = node;
+    int kind = pull_source(P, solid, i, j, k, q, src);
+    if (kind == SRC_NORMAL) atomicAdd(&fin_bar[(int64_t)q * P.L + src], fb);
+    else if (kind == SRC_BOUNCE) atomicAdd(&fin_bar[(int64_t)LOPP[q] * P.L + node], fb);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lbm_equilibrium(LbmDev P, const float *__restrict__ rho_in,
+                                                         const float *__restrict__ u_in, float *__restrict__ f) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= P.L) return;
+  float rho = rho_in ? rho_in[node] : 1.f;
+  float ux = u_in ? u_in[node] : P.uin[0];
+  float uy = u_in ? u_in[P.L + node] : P.uin[1];
+  float uz = u_in ? u_in[2 * P.L + node] : P.uin[2];
+  float uu = ux * ux + uy * uy + uz * uz;
+  float drho = rho - 1.f;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+    f[(int64_t)q * P.L + node] = LW[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+  }
+}
+
+__global__ void k_voxelize(int nx, int ny, int nz, float ox, float oy, float oz, float dx,
+                           const float *__restrict__ x, int n, uint8_t *__restrict__ solid) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float qx, qy, qz;
+  {
+#pragma clang fp contract(off)
+    qx = floorf((x[p] - ox) / dx);
+    qy = floorf((x[n + p] - oy) / dx);
+    qz = floorf((x[2 * n + p] - oz) / dx);
+  }
+  // NaN fails every comparison and is dropped here
+  if (!(qx >= 0.f && qy >= 0.f && qz >= 0.f && qx < (float)nx && qy < (float)ny && qz < (float)nz)) return;
+  int64_t idx = (int64_t)qx + (int64_t)nx * ((int64_t)qy + (int64_t)ny * (int64_t)qz);
+  solid[idx] = 1;
+}
+
+__global__ void k_fill_u8(uint8_t *p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+static int make_lbm(const dw_lattice *lat, const dw_lbm_params *prm, LbmDev *P) {
+  DW_REQUIRE(lat && prm, DW_EINVAL, "lbm: lattice / params is NULL");
+  DW_REQUIRE(lat->nx >= 1 && lat->ny >= 1 && lat->nz >= 1, DW_EINVAL, "lbm: lattice dims must be >= 1");
+  int64_t L = (int64_t)lat->nx * lat->ny * lat->nz;
+  DW_REQUIRE(L * 19 < (int64_t)INT_MAX * 64, DW_ERANGE, "lbm: lattice too large");
+  DW_REQUIRE(prm->tau > 0.5f, DW_EINVAL, "lbm: tau must be > 1/2 (got %g)", (double)prm->tau);
+  for (int a = 0; a < 3; ++a) {
+    int lo = prm->bc[2 * a], hi = prm->bc[2 * a + 1];
+    DW_REQUIRE(lo >= 0 && lo <= 3 && hi >= 0 && hi <= 3, DW_EINVAL, "lbm: unknown boundary code");
+    DW_REQUIRE((lo == DW_BC_PERIODIC) == (hi == DW_BC_PERIODIC), DW_EINVAL,
+               "lbm: periodic faces must pair on axis %d", a);
+    DW_REQUIRE(lo != DW_BC_OUTLET && hi != DW_BC_INLET, DW_EINVAL,
+               "lbm: inlet only on a low face, outlet only on a high face");
+    DW_REQUIRE(a == 0 || (lo != DW_BC_INLET && hi != DW_BC_OUTLET), DW_EINVAL,
+               "lbm: inlet / outlet are supported on the x faces only");
+  }
+  DW_REQUIRE(prm->gust_amp == 0.f || prm->gust_period != 0.f, DW_EINVAL, "lbm: gust period must be non-zero");
+  P->nx = lat->nx;
+  P->ny = lat->ny;
+  P->nz = lat->nz;
+  P->L = L;
+  P->omega = 1.0f / prm->tau;
+  for (int a = 0; a < 3; ++a) {
+    P->uin[a] = prm->u_in[a];
+    P->F[a] = prm->force[a];
+  }
+  for (int a = 0; a < 6; ++a) P->bc[a] = prm->bc[a];
+  P->gust_amp = prm->gust_amp;
+  P->gust_inv_period = prm->gust_amp != 0.f ? 1.0f / prm->gust_period : 0.f;
+  P->gust_ky = prm->gust_ky;
+  P->gust_kz = prm->gust_kz;
+  P->gust_phase = prm->gust_phase;
+  P->t = prm->t;
+  P->forced = prm->force[0] != 0.f || prm->force[1] != 0.f || prm->force[2] != 0.f;
+  return DW_OK;
+}
+
+}  // namespace dw
+
+using namespace dw;
+
+extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in, float *f_out,
+                        const uint8_t *solid, float *rho_out, float *u_out, void *stream) {
+  LbmDev P;
+  int rc = make_lbm(lat, params, &P);
+  if (rc) return rc;
+  DW_REQUIRE(f_in && f_out, DW_EINVAL, "lbm_step: f_in / f_out is NULL");
+  DW_REQUIRE(f_in != f_out, DW_EINVAL, "lbm_step: f_in and f_out must not alias");
+  hipLaunchKernelGGL(k_lbm_step, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, f_in, f_out,
+                     solid, rho_out, u_out);
+  return check_launch("lbm_step");
+}
+
+extern "C" int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
+                            const uint8_t *solid, const float *f_out_bar, const float *u_out_bar, float *f_in_bar,
+                            void *stream) {
+  LbmDev P;
+  int rc = make_lbm(lat, params, &P);
+  if (rc) return rc;
+  DW_REQUIRE(f_in && f_out_bar && f_in_bar, DW_EINVAL, "lbm_step_adj: f_in / f_out_bar / f_in_bar is NULL");
+  hipLaunchKernelGGL(k_lbm_step_adj, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, f_in,
+                     solid, f_out_bar, u_out_bar, f_in_bar);
+  return check_launch("lbm_step_adj");
+}
+
+extern "C" int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const float *rho,
+                               const float *u, float *f, void *stream) {
+  LbmDev P;
+  dw_lbm_params prm = *params;
+  if (prm.tau <= 0.5f) prm.tau = 1.0f;  // tau plays no role here
+  int rc = make_lbm(lat, &prm, &P);
+  if (rc) return rc;
+  DW_REQUIRE(f, DW_EINVAL, "lbm_equilibrium: f is NULL");
+  hipLaunchKernelGGL(k_lbm_equilibrium, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, rho,
+                     u, f);
+  return check_launch("lbm_equilibrium");
+}
+
+extern "C" int lbm_solid_from_particles(const dw_lattice *lat, const float *x, int n, uint8_t *solid,
+                                        int accumulate, void *stream) {
+  DW_REQUIRE(lat && solid, DW_EINVAL, "lbm_solid_from_particles: lattice / solid is NULL");
+  DW_REQUIRE(lat->nx >= 1 && lat->ny >= 1 && lat->nz >= 1 && lat->dx > 0.f, DW_EINVAL,
+             "lbm_solid_from_particles: bad lattice");
+  DW_REQUIRE(n >= 0 && (n == 0 || x), DW_EINVAL, "lbm_solid_from_particles: bad particles");
+  hipStream_t s = (hipStream_t)stream;
+  int64_t L = (int64_t)lat->nx * lat->ny * lat->nz;
+  if (!accumulate) hipLaunchKernelGGL(k_fill_u8, dim3(grid_blocks(L, 1024)), dim3(256), 0, s, solid, L);
+  if (n > 0)
+    hipLaunchKernelGGL(k_voxelize, dim3(grid_blocks(n, 256)), dim3(256), 0, s, lat->nx, lat->ny, lat->nz,
+                       lat->origin[0], lat->origin[1], lat->origin[2], lat->dx, x, n, solid);
+  return check_launch("lbm_solid_from_particles");
+}

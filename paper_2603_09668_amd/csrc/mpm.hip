@@ -1,0 +1,586 @@
+// MLS-MPM forward path for gfx950: cell-tile sort, tile-local P2G scatter,
+// active-tile grid update with wind coupling, coalesced G2P gather.
+//
+// Equations: Eq. P2G, Eq. G2P and Eq. deformation_update of the paper's
+// appendix ("Material Point Method"), the MLS-MPM stress term
+// A_p = m_p C_p - dt V0_p (4/dx^2) tau_p, and the explicit grid update of
+// Eq. continuum_mechanics with the wind force field on the MPM grid (Sec. 3.2).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "dw_internal.h"
+#include "dw_kernels.h"
+
+namespace dw {
+
+// ------------------------------------------------------------------ sort
+
+__global__ void k_sort_keys(GridDev g, const float *__restrict__ x, int n, int32_t *__restrict__ key,
+                            int32_t *__restrict__ tile_count, int32_t *__restrict__ node_flag,
+                            int32_t *__restrict__ status) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float X = grid_coord(x[p], g.ox, g.inv_dx);
+  float Y = grid_coord(x[n + p], g.oy, g.inv_dx);
+  float Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
+  if (!(isfinite(X) && isfinite(Y) && isfinite(Z))) {
+    atomicOr(status, DW_STATUS_NONFINITE);
+    key[p] = -1;
+    return;
+  }
+  // guard the float -> int conversion before it can overflow
+  const float lim = 1.0e9f;
+  if (fabsf(X) > lim || fabsf(Y) > lim || fabsf(Z) > lim) {
+    atomicOr(status, DW_STATUS_OUT_OF_GRID);
+    key[p] = -1;
+    return;
+  }
+  int bx = base_of(X), by = base_of(Y), bz = base_of(Z);
+  if (!stencil_inside(g, bx, by, bz)) {
+    atomicOr(status, DW_STATUS_OUT_OF_GRID);
+    key[p] = -1;
+    return;
+  }
+  int tx = bx >> 2, ty = by >> 2, tz = bz >> 2;
+  int k = tx + g.tx * (ty + g.ty * tz);
+  key[p] = k;
+  atomicAdd(&tile_count[k], 1);
+  int ux = (bx + 2) >> 2, uy = (by + 2) >> 2, uz = (bz + 2) >> 2;
+  for (int cz = tz; cz <= uz; ++cz)
+    for (int cy = ty; cy <= uy; ++cy)
+      for (int cx = tx; cx <= ux; ++cx) node_flag[cx + g.tx * (cy + g.ty * cz)] = 1;
+}
+
+// wave64 inclusive scan
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// block-wide exclusive scan of a 1024-thread block; returns the block total in *total
+__device__ __forceinline__ int block_excl_scan(int v, int *lds, int *total) {
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int inc = wave_incl_scan(v);
+  if (lane == 63) lds[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    int s = lane < (int)(blockDim.x >> 6) ? lds[lane] : 0;
+    int si = wave_incl_scan(s);
+    if (lane < (int)(blockDim.x >> 6)) lds[32 + lane] = si - s;
+    if (lane == (int)(blockDim.x >> 6) - 1) lds[31] = si;
+  }
+  __syncthreads();
+  int res = inc - v + lds[32 + wid];
+  *total = lds[31];
+  __syncthreads();
+  return res;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *__restrict__ count,
+                                                            const int32_t *__restrict__ flag, int64_t T,
+                                                            int32_t *__restrict__ block_sums, int64_t NB) {
+  __shared__ int lds[128];
+  int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+  int c = i < T ? count[i] : 0;
+  int f = i < T ? (flag[i] != 0) : 0;
+  int nz = c > 0;
+  int tc, tf, tn;
+  block_excl_scan(c, lds, &tc);
+  block_excl_scan(f, lds, &tf);
+  block_excl_scan(nz, lds, &tn);
+  if (threadIdx.x == 0) {
+    block_sums[blockIdx.x] = tc;
+    block_sums[NB + blockIdx.x] = tf;
+    block_sums[2 * NB + blockIdx.x] = tn;
+  }
+}
+
+// single block: exclusive scan of the three block-sum rows, in place; writes totals
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int32_t *__restrict__ block_sums, int64_t NB,
+                                                         int32_t *__restrict__ totals /* [3] */) {
+  __shared__ int lds[128];
+  for (int r = 0; r < 3; ++r) {
+    int carry = 0;
+    for (int64_t b0 = 0; b0 < NB; b0 += SCAN_BLOCK) {
+      int64_t b = b0 + threadIdx.x;
+      int v = b < NB ? block_sums[r * NB + b] : 0;
+      int tot;
+      int ex = block_excl_scan(v, lds, &tot);
+      if (b < NB) block_sums[r * NB + b] = ex + carry;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) totals[r] = carry;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
+    const int32_t *__restrict__ count, const int32_t *__restrict__ flag, int64_t T,
+    const int32_t *__restrict__ block_sums, int64_t NB, int32_t *__restrict__ tile_start,
+    int32_t *__restrict__ cell_tiles, int32_t *__restrict__ node_tiles) {
+  __shared__ int lds[128];
+  int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+  int c = i < T ? count[i] : 0;
+  int f = i < T ? (flag[i] != 0) : 0;
+  int nz = c > 0;
+  int tc, tf, tn;
+  int ec = block_excl_scan(c, lds, &tc) + block_sums[blockIdx.x];
+  int ef = block_excl_scan(f, lds, &tf) + block_sums[NB + blockIdx.x];
+  int en = block_excl_scan(nz, lds, &tn) + block_sums[2 * NB + blockIdx.x];
+  if (i < T) {
+    tile_start[i] = ec;
+    if (nz) cell_tiles[en] = (int)i;
+    if (f) node_tiles[ef] = (int)i;
+    if (i == T - 1) tile_start[T] = ec + c;
+  }
+}
+
+__global__ void k_sort_scatter(const int32_t *__restrict__ key, int n, const int32_t *__restrict__ tile_start,
+                               int32_t *__restrict__ cursor, int32_t *__restrict__ perm) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int k = key[p];
+  if (k < 0) return;
+  int pos = tile_start[k] + atomicAdd(&cursor[k], 1);
+  perm[pos] = p;
+}
+
+// Deterministic mode: sort each tile's segment by particle index (rank by count).
+__global__ __launch_bounds__(256) void k_sort_segments(const int32_t *__restrict__ tile_start,
+                                                       const int32_t *__restrict__ cell_tiles,
+                                                       const int32_t *__restrict__ n_tiles,
+                                                       const int32_t *__restrict__ in,
+                                                       int32_t *__restrict__ out) {
+  __shared__ int32_t chunk[1024];
+  int nt = *n_tiles;
+  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+    int tile = cell_tiles[it];
+    int beg = tile_start[tile], end = tile_start[tile + 1];
+    for (int j0 = beg; j0 < end; j0 += blockDim.x) {
+      int j = j0 + threadIdx.x;
+      int mine = j < end ? in[j] : 0x7fffffff;
+      int rank = 0;
+      for (int c0 = beg; c0 < end; c0 += 1024) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < 1024; q += blockDim.x) chunk[q] = (c0 + q < end) ? in[c0 + q] : 0x7fffffff;
+        __syncthreads();
+        int lim = min(1024, end - c0);
+        for (int q = 0; q < lim; ++q) rank += chunk[q] < mine;
+      }
+      if (j < end) out[beg + rank] = mine;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ P2G
+
+__global__ __launch_bounds__(256) void k_grid_clear(GridDev g, const int32_t *__restrict__ node_tiles,
+                                                    const int32_t *__restrict__ n_tiles, float *__restrict__ gm,
+                                                    float *__restrict__ gmv, int64_t N) {
+  int nt = *n_tiles;
+  int sub = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int it = blockIdx.x * 4 + sub; it < nt; it += gridDim.x * 4) {
+    int t = node_tiles[it];
+    int tx = t % g.tx, ty = (t / g.tx) % g.ty, tz = t / (g.tx * g.ty);
+    int i = tx * 4 + (l & 3), j = ty * 4 + ((l >> 2) & 3), k = tz * 4 + (l >> 4);
+    if (i < g.nx && j < g.ny && k < g.nz) {
+      int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+      gm[node] = 0.f;
+      gmv[node] = 0.f;
+      gmv[N + node] = 0.f;
+      gmv[2 * N + node] = 0.f;
+    }
+  }
+}
+
+struct PView {
+  const float *x, *v, *C, *F, *mass, *vol0, *E, *nu;
+  const int32_t *region;
+  int n, n_regions;
+};
+
+constexpr int P2G_L = 6;        // local node extent of a cell tile's stencils
+constexpr int P2G_NODES = 216;  // 6^3
+
+// One workgroup per active cell tile (persistent over the tile list).  Each
+// thread walks a contiguous run of the tile's particles, accumulating the 27
+// nodes x 4 values in registers while consecutive particles share a stencil
+// base cell, and flushes to the LDS tile with ds_add_f32 when the cell
+// changes.  The LDS tile is then added into the global grid with hardware
+// float atomics (only nodes that received mass).
+__global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int material,
+                                             const int32_t *__restrict__ perm,
+                                             const int32_t *__restrict__ tile_start,
+                                             const int32_t *__restrict__ cell_tiles,
+                                             const int32_t *__restrict__ n_tiles, float *__restrict__ gm,
+                                             float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status) {
+  __shared__ float s_acc[4][P2G_NODES];
+  const int n = P.n;
+  const float kstress = dt * 4.0f * g.inv_dx * g.inv_dx;
+  int nt = *n_tiles;
+  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+    int tile = cell_tiles[it];
+    int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
+    for (int q = threadIdx.x; q < 4 * P2G_NODES; q += blockDim.x) (&s_acc[0][0])[q] = 0.f;
+    __syncthreads();
+    int beg = tile_start[tile], end = tile_start[tile + 1];
+    int cnt = end - beg;
+    int per = (cnt + blockDim.x - 1) / blockDim.x;
+    int j0 = beg + threadIdx.x * per;
+    int j1 = min(j0 + per, end);
+    float acc[4][27];
+    int cur = -1;
+    for (int j = j0; j < j1; ++j) {
+      int p = perm[j];
+      float X = grid_coord(P.x[p], g.ox, g.inv_dx);
+      float Y = grid_coord(P.x[n + p], g.oy, g.inv_dx);
+      float Z = grid_coord(P.x[2 * n + p], g.oz, g.inv_dx);
+      int bx = base_of(X), by = base_of(Y), bz = base_of(Z);
+      int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
+      if ((unsigned)lx > 3u || (unsigned)ly > 3u || (unsigned)lz > 3u) {
+        atomicOr(status, DW_STATUS_OUT_OF_GRID);
+        continue;
+      }
+      float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
+      float wx[3], wy[3], wz[3];
+      {
+        float a = 1.5f - fx, b = fx - 1.0f, c = fx - 0.5f;
+        wx[0] = 0.5f * a * a; wx[1] = 0.75f - b * b; wx[2] = 0.5f * c * c;
+        a = 1.5f - fy; b = fy - 1.0f; c = fy - 0.5f;
+        wy[0] = 0.5f * a * a; wy[1] = 0.75f - b * b; wy[2] = 0.5f * c * c;
+        a = 1.5f - fz; b = fz - 1.0f; c = fz - 0.5f;
+        wz[0] = 0.5f * a * a; wz[1] = 0.75f - b * b; wz[2] = 0.5f * c * c;
+      }
+      float H[9], Cm[9], tau[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        H[q] = P.F[q * n + p];
+        Cm[q] = P.C[q * n + p];
+      }
+      float m = P.mass[p], V0 = P.vol0[p];
+      int r = P.region[p];
+      float mu, lam;
+      lame(P.E[r], P.nu[r], mu, lam);
+      kirchhoff_shift(H, mu, lam, material, tau, status);
+      float A[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) A[q] = m * Cm[q] - kstress * V0 * tau[q];
+      float mvx = m * P.v[p], mvy = m * P.v[n + p], mvz = m * P.v[2 * n + p];
+      // mv contribution at offset o: w * (m v + A (o - f) dx)
+      float dx = g.dx;
+      float Af0 = -(A[0] * fx + A[1] * fy + A[2] * fz) * dx;
+      float Af1 = -(A[3] * fx + A[4] * fy + A[5] * fz) * dx;
+      float Af2 = -(A[6] * fx + A[7] * fy + A[8] * fz) * dx;
+      int cell = lx + 4 * (ly + 4 * lz);
+      if (cell != cur) {
+        if (cur >= 0) {
+          int cx = cur & 3, cy = (cur >> 2) & 3, cz = cur >> 4;
+#pragma unroll
+          for (int o = 0; o < 27; ++o) {
+            int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
+            int li = (cx + ox) + P2G_L * ((cy + oy) + P2G_L * (cz + oz));
+            atomicAdd(&s_acc[0][li], acc[0][o]);
+            atomicAdd(&s_acc[1][li], acc[1][o]);
+            atomicAdd(&s_acc[2][li], acc[2][o]);
+            atomicAdd(&s_acc[3][li], acc[3][o]);
+          }
+        }
+#pragma unroll
+        for (int o = 0; o < 27; ++o) acc[0][o] = acc[1][o] = acc[2][o] = acc[3][o] = 0.f;
+        cur = cell;
+      }
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
+        float w = wx[ox] * wy[oy] * wz[oz];
+        float ddx = (float)ox * dx, ddy = (float)oy * dx, ddz = (float)oz * dx;
+        acc[0][o] += w * m;
+        acc[1][o] += w * (mvx + Af0 + A[0] * ddx + A[1] * ddy + A[2] * ddz);
+        acc[2][o] += w * (mvy + Af1 + A[3] * ddx + A[4] * ddy + A[5] * ddz);
+        acc[3][o] += w * (mvz + Af2 + A[6] * ddx + A[7] * ddy + A[8] * ddz);
+      }
+    }
+    if (cur >= 0) {
+      int cx = cur & 3, cy = (cur >> 2) & 3, cz = cur >> 4;
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
+        int li = (cx + ox) + P2G_L * ((cy + oy) + P2G_L * (cz + oz));
+        atomicAdd(&s_acc[0][li], acc[0][o]);
+        atomicAdd(&s_acc[1][li], acc[1][o]);
+        atomicAdd(&s_acc[2][li], acc[2][o]);
+        atomicAdd(&s_acc[3][li], acc[3][o]);
+      }
+    }
+    __syncthreads();
+    for (int li = threadIdx.x; li < P2G_NODES; li += blockDim.x) {
+      float mm = s_acc[0][li];
+      if (mm != 0.f) {
+        int ix = li % P2G_L, iy = (li / P2G_L) % P2G_L, iz = li / (P2G_L * P2G_L);
+        int gi = 4 * tx + ix, gj = 4 * ty + iy, gk = 4 * tz + iz;
+        int64_t node = gi + (int64_t)g.nx * (gj + (int64_t)g.ny * gk);
+        atomicAdd(&gm[node], mm);
+        atomicAdd(&gmv[node], s_acc[1][li]);
+        atomicAdd(&gmv[N + node], s_acc[2][li]);
+        atomicAdd(&gmv[2 * N + node], s_acc[3][li]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ grid update
+
+__global__ __launch_bounds__(256) void k_grid_update(GridDev g, float dt, float gx, float gy, float gz,
+                                                     int bound, const float *__restrict__ gm,
+                                                     const float *__restrict__ gmv, WindDev wind,
+                                                     const uint8_t *__restrict__ pin,
+                                                     const int32_t *__restrict__ node_tiles,
+                                                     const int32_t *__restrict__ n_tiles, float *__restrict__ gv,
+                                                     int64_t N) {
+  int nt = *n_tiles;
+  int sub = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int it = blockIdx.x * 4 + sub; it < nt; it += gridDim.x * 4) {
+    int t = node_tiles[it];
+    int tx = t % g.tx, ty = (t / g.tx) % g.ty, tz = t / (g.tx * g.ty);
+    int i = tx * 4 + (l & 3), j = ty * 4 + ((l >> 2) & 3), k = tz * 4 + (l >> 4);
+    if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
+    int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    float m = gm[node];
+    float vx = 0.f, vy = 0.f, vz = 0.f;
+    if (m > 0.f) {
+      float ax = 0.f, ay = 0.f, az = 0.f;
+      wind_at_node(wind, g, i, j, k, node, ax, ay, az);
+      float im = 1.0f / m;
+      vx = gmv[node] * im + dt * (gx + ax);
+      vy = gmv[N + node] * im + dt * (gy + ay);
+      vz = gmv[2 * N + node] * im + dt * (gz + az);
+      if ((i < bound && vx < 0.f) || (i >= g.nx - bound && vx > 0.f)) vx = 0.f;
+      if ((j < bound && vy < 0.f) || (j >= g.ny - bound && vy > 0.f)) vy = 0.f;
+      if ((k < bound && vz < 0.f) || (k >= g.nz - bound && vz > 0.f)) vz = 0.f;
+      if (pin && pin[node]) vx = vy = vz = 0.f;
+    }
+    gv[node] = vx;
+    gv[N + node] = vy;
+    gv[2 * N + node] = vz;
+  }
+}
+
+// ------------------------------------------------------------------ G2P
+
+__global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
+                                             const float *xin, const float *Fin, float *xout, float *vout,
+                                             float *Cout, float *Fout, int n, int32_t *__restrict__ status) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float px = xin[p], py = xin[n + p], pz = xin[2 * n + p];
+  float X = grid_coord(px, g.ox, g.inv_dx);
+  float Y = grid_coord(py, g.oy, g.inv_dx);
+  float Z = grid_coord(pz, g.oz, g.inv_dx);
+  float F[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) F[q] = Fin[q * n + p];
+  bool ok = isfinite(X) && isfinite(Y) && isfinite(Z) && fabsf(X) < 1e9f && fabsf(Y) < 1e9f && fabsf(Z) < 1e9f;
+  int bx = 0, by = 0, bz = 0;
+  if (ok) {
+    bx = base_of(X); by = base_of(Y); bz = base_of(Z);
+    ok = stencil_inside(g, bx, by, bz);
+  }
+  if (!ok) {
+    if (status) atomicOr(status, DW_STATUS_OUT_OF_GRID);
+    xout[p] = px; xout[n + p] = py; xout[2 * n + p] = pz;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) vout[q * n + p] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      Cout[q * n + p] = 0.f;
+      Fout[q * n + p] = F[q];
+    }
+    return;
+  }
+  float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
+  float wx[3], wy[3], wz[3];
+  {
+    float a = 1.5f - fx, b = fx - 1.0f, c = fx - 0.5f;
+    wx[0] = 0.5f * a * a; wx[1] = 0.75f - b * b; wx[2] = 0.5f * c * c;
+    a = 1.5f - fy; b = fy - 1.0f; c = fy - 0.5f;
+    wy[0] = 0.5f * a * a; wy[1] = 0.75f - b * b; wy[2] = 0.5f * c * c;
+    a = 1.5f - fz; b = fz - 1.0f; c = fz - 0.5f;
+    wz[0] = 0.5f * a * a; wz[1] = 0.75f - b * b; wz[2] = 0.5f * c * c;
+  }
+  float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+  float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) {
+      int64_t row = (bx) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+#pragma unroll
+      for (int ox = 0; ox < 3; ++ox) {
+        int64_t node = row + ox;
+        float w = wx[ox] * wy[oy] * wz[oz];
+        float a = gv[node], b = gv[N + node], c = gv[2 * N + node];
+        float dxo = (float)ox - fx, dyo = (float)oy - fy, dzo = (float)oz - fz;
+        v0 += w * a; v1 += w * b; v2 += w * c;
+        float wa = w * a, wb = w * b, wc = w * c;
+        B[0] += wa * dxo; B[1] += wa * dyo; B[2] += wa * dzo;
+        B[3] += wb * dxo; B[4] += wb * dyo; B[5] += wb * dzo;
+        B[6] += wc * dxo; B[7] += wc * dyo; B[8] += wc * dzo;
+      }
+    }
+  // C = (4/dx^2) sum w v d^T with d = (o - f) dx  ->  (4/dx) sum w v (o - f)^T
+  float kc = 4.0f * g.inv_dx;
+  float Cn[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Cn[q] = kc * B[q];
+  xout[p] = px + dt * v0;
+  xout[n + p] = py + dt * v1;
+  xout[2 * n + p] = pz + dt * v2;
+  vout[p] = v0;
+  vout[n + p] = v1;
+  vout[2 * n + p] = v2;
+  // F <- (I + dt C) F with F = I + H stored as H:  H <- H + dt C + dt C H
+  float G[9], CH[9], Fn[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) G[q] = dt * Cn[q];
+  matmul3(G, F, CH);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Fn[q] = F[q] + G[q] + CH[q];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    Cout[q * n + p] = Cn[q];
+    Fout[q * n + p] = Fn[q];
+  }
+}
+
+}  // namespace dw
+
+// =================================================================== C ABI
+
+namespace dw {
+
+constexpr int PERSISTENT_BLOCKS = 2048;
+
+static PView make_pview(const dw_particles *p) {
+  PView v;
+  v.x = p->x; v.v = p->v; v.C = p->C; v.F = p->F;
+  v.mass = p->mass; v.vol0 = p->vol0; v.E = p->E; v.nu = p->nu;
+  v.region = p->region;
+  v.n = p->n;
+  v.n_regions = p->n_regions;
+  return v;
+}
+
+int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, const Workspace &W,
+             hipStream_t s) {
+  GridDev g = make_grid(grid);
+  int64_t T = W.n_tiles, NB = W.n_scan_blocks;
+  // header + tile_count + tile_cursor + node_flag are contiguous: clear them
+  int64_t clear_words = (int64_t)((char *)W.tile_start - (char *)W.status) / 4;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_blocks(clear_words, 256)), dim3(256), 0, s, W.status, clear_words, 0);
+  if (n > 0)
+    hipLaunchKernelGGL(k_sort_keys, dim3(grid_blocks(n, 256)), dim3(256), 0, s, g, x, n, W.key, W.tile_count,
+                       W.node_flag, W.status);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
+                     W.block_sums, NB);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, W.block_sums, NB, W.status + 3);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
+                     W.block_sums, NB, W.tile_start, W.cell_tiles, W.node_tiles);
+  if (n > 0) {
+    int32_t *dst = deterministic ? W.perm_tmp : W.perm;
+    hipLaunchKernelGGL(k_sort_scatter, dim3(grid_blocks(n, 256)), dim3(256), 0, s, W.key, n, W.tile_start,
+                       W.tile_cursor, dst);
+    if (deterministic)
+      hipLaunchKernelGGL(k_sort_segments, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, W.tile_start, W.cell_tiles,
+                         W.n_cell_tiles, W.perm_tmp, W.perm);
+  }
+  return check_launch("mpm_sort");
+}
+
+}  // namespace dw
+
+using namespace dw;
+
+extern "C" int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const float *x, int n, void *ws,
+                        size_t ws_bytes, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  DW_REQUIRE(n >= 0, DW_EINVAL, "mpm_sort: n must be >= 0");
+  DW_REQUIRE(n == 0 || x, DW_EINVAL, "mpm_sort: x is NULL");
+  Workspace W;
+  rc = bind_workspace(grid, n, ws, ws_bytes, &W);
+  if (rc) return rc;
+  return run_sort(grid, params ? params->deterministic : 0, x, n, W, (hipStream_t)stream);
+}
+
+extern "C" int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p, float *grid_m,
+                       float *grid_mv, void *ws, size_t ws_bytes, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  DW_REQUIRE(params, DW_EINVAL, "mpm_p2g: params is NULL");
+  DW_REQUIRE(params->material == DW_FIXED_COROTATED || params->material == DW_NEO_HOOKEAN, DW_EINVAL,
+             "mpm_p2g: unknown material %d", params->material);
+  rc = check_particles(p, true);
+  if (rc) return rc;
+  DW_REQUIRE(grid_m && grid_mv, DW_EINVAL, "mpm_p2g: grid_m / grid_mv is NULL");
+  Workspace W;
+  rc = bind_workspace(grid, p->n, ws, ws_bytes, &W);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = run_sort(grid, params->deterministic, p->x, p->n, W, s);
+  if (rc) return rc;
+  GridDev g = make_grid(grid);
+  int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  hipLaunchKernelGGL(k_grid_clear, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
+                     grid_m, grid_mv, N);
+  if (p->n > 0)
+    hipLaunchKernelGGL(k_p2g, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, make_pview(p), params->dt,
+                       params->material, W.perm, W.tile_start, W.cell_tiles, W.n_cell_tiles, grid_m, grid_mv, N,
+                       W.status);
+  return check_launch("mpm_p2g");
+}
+
+extern "C" int mpm_grid_update(const dw_grid *grid, const dw_mpm_params *params, const float *grid_m,
+                               const float *grid_mv, const dw_wind *wind, const uint8_t *pin, float *grid_v,
+                               const void *ws, size_t ws_bytes, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  DW_REQUIRE(params, DW_EINVAL, "mpm_grid_update: params is NULL");
+  DW_REQUIRE(grid_m && grid_mv && grid_v, DW_EINVAL, "mpm_grid_update: grid arrays must be set");
+  DW_REQUIRE(params->bound >= 0, DW_EINVAL, "mpm_grid_update: bound must be >= 0");
+  Workspace W;
+  rc = bind_workspace(grid, 0, ws, ws_bytes, &W);
+  if (rc) return rc;
+  WindDev wd;
+  rc = make_wind(wind, grid, &wd);
+  if (rc) return rc;
+  GridDev g = make_grid(grid);
+  int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  hipLaunchKernelGGL(k_grid_update, dim3(PERSISTENT_BLOCKS), dim3(256), 0, (hipStream_t)stream, g, params->dt,
+                     params->gravity[0], params->gravity[1], params->gravity[2], params->bound, grid_m, grid_mv,
+                     wd, pin, W.node_tiles, W.n_node_tiles, grid_v, N);
+  return check_launch("mpm_grid_update");
+}
+
+extern "C" int mpm_g2p(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
+                       const dw_particles *in, dw_particles *out, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  DW_REQUIRE(params && grid_v, DW_EINVAL, "mpm_g2p: params / grid_v is NULL");
+  DW_REQUIRE(in && out && in->n == out->n && in->n >= 0, DW_EINVAL, "mpm_g2p: in / out mismatch");
+  if (in->n == 0) return DW_OK;
+  DW_REQUIRE(in->x && in->F && out->x && out->v && out->C && out->F, DW_EINVAL,
+             "mpm_g2p: in->x, in->F, out->x, v, C, F must be set");
+  DW_REQUIRE((int64_t)in->n * 9 < (int64_t)INT_MAX, DW_ERANGE, "mpm_g2p: too many particles");
+  GridDev g = make_grid(grid);
+  int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  hipLaunchKernelGGL(k_g2p, dim3(grid_blocks(in->n, 256)), dim3(256), 0, (hipStream_t)stream, g, params->dt,
+                     grid_v, N, in->x, in->F, out->x, out->v, out->C, out->F, in->n, (int32_t *)nullptr);
+  return check_launch("mpm_g2p");
+}

@@ -1,0 +1,489 @@
+// Hand-written adjoints of the MPM substep for gfx950.
+//
+// Reverse P2G is a gather per particle (each particle reads the grid adjoint
+// at its 27 stencil nodes); reverse G2P is a sorted scatter (particles
+// grouped by cell tile, grid adjoint accumulated in an LDS tile and added to
+// the global grid with float atomics); reverse grid update is pointwise over
+// the active node tiles.  All adjoint outputs accumulate (+=).
+//
+// Forward definitions differentiated here: Eq. P2G with the MLS-MPM stress
+// term A = m C - dt V0 (4/dx^2) tau(F), the explicit grid update of
+// Eq. continuum_mechanics with the wind acceleration, Eq. G2P with the APIC
+// affine matrix and Eq. deformation_update.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "dw_internal.h"
+#include "dw_kernels.h"
+
+namespace dw {
+
+// skew(y) as a 3x3 matrix
+__device__ __forceinline__ void cross_matrix(const float y[3], float Z[9]) {
+  Z[0] = 0.f;   Z[1] = -y[2]; Z[2] = y[1];
+  Z[3] = y[2];  Z[4] = 0.f;   Z[5] = -y[0];
+  Z[6] = -y[1]; Z[7] = y[0];  Z[8] = 0.f;
+}
+
+// Vector-Jacobian product of the polar rotation R(F), F = R S:
+// dR = R W with W skew solving S W + W S = R^T dF - dF^T R; in vector form
+// (tr(S) I - S) w = k.  For a cotangent Rbar this gives
+// Fbar += 2 R [y]x with y = (tr(S) I - S)^{-1} g, g the axial vector of
+// skew(R^T Rbar).
+__device__ __forceinline__ void polar_vjp(const float *F, const float *R, const float *Rbar, float *Fbar) {
+  float S[9], G[9];
+  matmul3_atb(R, F, S);
+  matmul3_atb(R, Rbar, G);
+  float g[3] = {0.5f * (G[7] - G[5]), 0.5f * (G[2] - G[6]), 0.5f * (G[3] - G[1])};
+  float tr = S[0] + S[4] + S[8];
+  float M[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) M[q] = -0.5f * (S[q] + S[(q % 3) * 3 + q / 3]);
+  M[0] += tr;
+  M[4] += tr;
+  M[8] += tr;
+  float d = det3(M);
+  float MiT[9];
+  inv_transpose3(M, d, MiT);  // M symmetric: inverse = inverse-transpose
+  float y[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) y[a] = MiT[3 * a] * g[0] + MiT[3 * a + 1] * g[1] + MiT[3 * a + 2] * g[2];
+  float Z[9], RZ[9];
+  cross_matrix(y, Z);
+  matmul3(R, Z, RZ);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Fbar[q] += 2.0f * RZ[q];
+}
+
+// Vector-Jacobian product of the Kirchhoff stress tau(F; mu, lam), F = I + H.
+//   Neo-Hookean: tau = mu (F F^T - I) + lam log J I
+//     Fbar += mu (tb + tb^T) F + lam tr(tb) F^{-T}
+//   fixed-corotated: tau = 2 mu (F - R) F^T + lam (J - 1) J I
+//     Fbar += 2 mu tb F + 2 mu tb^T (F - R) + polar_vjp(Rbar = -2 mu tb F)
+//             + lam (2J - 1) J tr(tb) F^{-T}
+// Also returns the cotangents of mu and lam.
+__device__ __forceinline__ void kirchhoff_vjp(const float *H, float mu, float lam, int material, const float *tb,
+                                              float *Fbar, float &mu_bar, float &lam_bar) {
+  float F[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) F[q] = H[q] + ((q % 4) == 0 ? 1.f : 0.f);
+  float Jm1 = det_shift(H);
+  float J = 1.0f + Jm1;
+  float FiT[9];
+  inv_transpose3(F, J, FiT);
+  float trt = tb[0] + tb[4] + tb[8];
+  if (material == DW_NEO_HOOKEAN) {
+    float S[9], SF[9], HHt[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) S[q] = tb[q] + tb[(q % 3) * 3 + q / 3];
+    matmul3(S, F, SF);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Fbar[q] += mu * SF[q] + lam * trt * FiT[q];
+    matmul3_abt(H, H, HHt);
+    float mb = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) mb += tb[3 * i + j] * (H[3 * i + j] + H[3 * j + i] + HHt[3 * i + j]);
+    mu_bar = mb;
+    lam_bar = trt * log1pf(Jm1);
+  } else {
+    float Y[9], R[9], D[9], TF[9], TtD[9], Rb[9], DFt[9];
+    polar_shift(H, Y);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      D[q] = H[q] - Y[q];
+      R[q] = Y[q] + ((q % 4) == 0 ? 1.f : 0.f);
+    }
+    matmul3(tb, F, TF);
+    matmul3_atb(tb, D, TtD);
+    float cj = lam * (2.f * J - 1.f) * J * trt;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      Fbar[q] += 2.f * mu * (TF[q] + TtD[q]) + cj * FiT[q];
+      Rb[q] = -2.f * mu * TF[q];
+    }
+    polar_vjp(F, R, Rb, Fbar);
+    matmul3_abt(D, F, DFt);
+    float mb = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) mb += tb[q] * DFt[q];
+    mu_bar = 2.f * mb;
+    lam_bar = trt * Jm1 * J;
+  }
+}
+
+// sum over the 64 lanes of a wave
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct PAdj {
+  const float *x, *v, *C, *F, *mass, *vol0, *E, *nu;
+  const int32_t *region;
+  int n;
+  float *xb, *vb, *Cb, *Fb, *Eb;
+};
+
+// ---------------------------------------------------------- reverse P2G
+__global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, int material,
+                                                 const float *__restrict__ mbar, const float *__restrict__ mvbar,
+                                                 int64_t N) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  bool live = p < P.n;
+  const int n = P.n;
+  float Ebar_p = 0.f;
+  int r = 0;
+  if (live) {
+    float X = grid_coord(P.x[p], g.ox, g.inv_dx);
+    float Y = grid_coord(P.x[n + p], g.oy, g.inv_dx);
+    float Z = grid_coord(P.x[2 * n + p], g.oz, g.inv_dx);
+    bool ok = isfinite(X) && isfinite(Y) && isfinite(Z) && fabsf(X) < 1e9f && fabsf(Y) < 1e9f && fabsf(Z) < 1e9f;
+    int bx = 0, by = 0, bz = 0;
+    if (ok) {
+      bx = base_of(X); by = base_of(Y); bz = base_of(Z);
+      ok = stencil_inside(g, bx, by, bz);
+    }
+    if (ok) {
+      float f[3] = {X - (float)bx, Y - (float)by, Z - (float)bz};
+      float w[3][3], dw[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bspline_w(f[a], w[a]);
+        bspline_dw(f[a], dw[a]);
+      }
+      float F[9], Cm[9], tau[9], A[9];  // F holds H = F - I
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        F[q] = P.F[q * n + p];
+        Cm[q] = P.C[q * n + p];
+      }
+      float m = P.mass[p], V0 = P.vol0[p];
+      r = P.region[p];
+      float Er = P.E[r], nur = P.nu[r];
+      float mu, lam;
+      lame(Er, nur, mu, lam);
+      kirchhoff_shift(F, mu, lam, material, tau, nullptr);
+      float ks = dt * 4.0f * g.inv_dx * g.inv_dx;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) A[q] = m * Cm[q] - ks * V0 * tau[q];
+      float mom[3] = {m * P.v[p], m * P.v[n + p], m * P.v[2 * n + p]};
+      float vbar[3] = {0.f, 0.f, 0.f}, xbar[3] = {0.f, 0.f, 0.f};
+      float Abar[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      const float dx = g.dx;
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+          for (int ox = 0; ox < 3; ++ox) {
+            int64_t node = (bx + ox) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+            float wt = w[0][ox] * w[1][oy] * w[2][oz];
+            float gw[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * g.inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * g.inv_dx,
+                           w[0][ox] * w[1][oy] * dw[2][oz] * g.inv_dx};
+            float d[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
+            float mb = mbar[node];
+            float gb[3] = {mvbar[node], mvbar[N + node], mvbar[2 * N + node]};
+            float c[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) c[a] = mom[a] + A[3 * a] * d[0] + A[3 * a + 1] * d[1] + A[3 * a + 2] * d[2];
+            float s = m * mb + gb[0] * c[0] + gb[1] * c[1] + gb[2] * c[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              vbar[a] += wt * m * gb[a];
+              // d (A d) / d x = -A   ->   -w A^T gb
+              xbar[a] += gw[a] * s - wt * (A[a] * gb[0] + A[3 + a] * gb[1] + A[6 + a] * gb[2]);
+#pragma unroll
+              for (int b = 0; b < 3; ++b) Abar[3 * a + b] += wt * gb[a] * d[b];
+            }
+          }
+      if (P.vb) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P.vb[a * n + p] += vbar[a];
+      }
+      if (P.xb) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P.xb[a * n + p] += xbar[a];
+      }
+      if (P.Cb) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) P.Cb[q * n + p] += m * Abar[q];
+      }
+      if (P.Fb || P.Eb) {
+        float tb[9], Fb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 9; ++q) tb[q] = -ks * V0 * Abar[q];
+        float mu_b, lam_b;
+        kirchhoff_vjp(F, mu, lam, material, tb, Fb, mu_b, lam_b);
+        if (P.Fb) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) P.Fb[q * n + p] += Fb[q];
+        }
+        // Eq. young_poisson: d mu / d E = 1 / (2 (1 + nu)), d lam / d E = nu / ((1 + nu)(1 - 2 nu))
+        Ebar_p = mu_b / (2.f * (1.f + nur)) + lam_b * nur / ((1.f + nur) * (1.f - 2.f * nur));
+      }
+    }
+  }
+  if (P.Eb) {
+    // regions are usually uniform across a wave: reduce there, else per-lane atomics
+    int r0 = __shfl(r, 0, 64);
+    bool uniform = __all(!live || r == r0);
+    if (uniform) {
+      float s = wave_sum(live ? Ebar_p : 0.f);
+      if ((threadIdx.x & 63) == 0 && s != 0.f) atomicAdd(&P.Eb[r0], s);
+    } else if (live && Ebar_p != 0.f) {
+      atomicAdd(&P.Eb[r], Ebar_p);
+    }
+  }
+}
+
+// --------------------------------------------------- reverse grid update
+__global__ __launch_bounds__(256) void k_grid_update_adj(GridDev g, float dt, float gx, float gy, float gz,
+                                                         int bound, const float *__restrict__ gm,
+                                                         const float *__restrict__ gmv, WindDev wind,
+                                                         const uint8_t *__restrict__ pin,
+                                                         const int32_t *__restrict__ node_tiles,
+                                                         const int32_t *__restrict__ n_tiles,
+                                                         const float *__restrict__ gvb, float *__restrict__ gmb,
+                                                         float *__restrict__ gmvb, float *__restrict__ accb,
+                                                         int64_t N) {
+  int nt = *n_tiles;
+  int sub = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int it = blockIdx.x * 4 + sub; it < nt; it += gridDim.x * 4) {
+    int t = node_tiles[it];
+    int tx = t % g.tx, ty = (t / g.tx) % g.ty, tz = t / (g.tx * g.ty);
+    int i = tx * 4 + (l & 3), j = ty * 4 + ((l >> 2) & 3), k = tz * 4 + (l >> 4);
+    if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
+    int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    float m = gm[node];
+    if (!(m > 0.f)) continue;
+    if (pin && pin[node]) continue;
+    float ax, ay, az;
+    wind_at_node(wind, g, i, j, k, node, ax, ay, az);
+    float im = 1.0f / m;
+    float mv[3] = {gmv[node], gmv[N + node], gmv[2 * N + node]};
+    float v[3] = {mv[0] * im + dt * (gx + ax), mv[1] * im + dt * (gy + ay), mv[2] * im + dt * (gz + az)};
+    float vb[3] = {gvb[node], gvb[N + node], gvb[2 * N + node]};
+    if ((i < bound && v[0] < 0.f) || (i >= g.nx - bound && v[0] > 0.f)) vb[0] = 0.f;
+    if ((j < bound && v[1] < 0.f) || (j >= g.ny - bound && v[1] > 0.f)) vb[1] = 0.f;
+    if ((k < bound && v[2] < 0.f) || (k >= g.nz - bound && v[2] > 0.f)) vb[2] = 0.f;
+    if (gmvb) {
+      gmvb[node] += vb[0] * im;
+      gmvb[N + node] += vb[1] * im;
+      gmvb[2 * N + node] += vb[2] * im;
+    }
+    if (gmb) gmb[node] += -(vb[0] * mv[0] + vb[1] * mv[1] + vb[2] * mv[2]) * im * im;
+    if (accb) {
+      accb[node] += dt * vb[0];
+      accb[N + node] += dt * vb[1];
+      accb[2 * N + node] += dt * vb[2];
+    }
+  }
+}
+
+// ---------------------------------------------------------- reverse G2P
+constexpr int ADJ_L = 6;
+constexpr int ADJ_NODES = 216;
+
+__global__ __launch_bounds__(256) void k_g2p_adj(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
+                                                 const float *__restrict__ x, const float *__restrict__ F, int n,
+                                                 const float *__restrict__ xob, const float *__restrict__ vob,
+                                                 const float *__restrict__ Cob, const float *__restrict__ Fob,
+                                                 float *__restrict__ xb, float *__restrict__ Fb,
+                                                 float *__restrict__ gvb, const int32_t *__restrict__ perm,
+                                                 const int32_t *__restrict__ tile_start,
+                                                 const int32_t *__restrict__ cell_tiles,
+                                                 const int32_t *__restrict__ n_tiles) {
+  __shared__ float s_acc[3][ADJ_NODES];
+  int nt = *n_tiles;
+  const float kc = 4.0f * g.inv_dx;
+  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+    int tile = cell_tiles[it];
+    int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
+    for (int q = threadIdx.x; q < 3 * ADJ_NODES; q += blockDim.x) (&s_acc[0][0])[q] = 0.f;
+    __syncthreads();
+    int beg = tile_start[tile], end = tile_start[tile + 1];
+    for (int j = beg + threadIdx.x; j < end; j += blockDim.x) {
+      int p = perm[j];
+      float X = grid_coord(x[p], g.ox, g.inv_dx);
+      float Y = grid_coord(x[n + p], g.oy, g.inv_dx);
+      float Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
+      int bx = base_of(X), by = base_of(Y), bz = base_of(Z);
+      int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
+      if ((unsigned)lx > 3u || (unsigned)ly > 3u || (unsigned)lz > 3u) continue;
+      float f[3] = {X - (float)bx, Y - (float)by, Z - (float)bz};
+      float w[3][3], dw[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bspline_w(f[a], w[a]);
+        bspline_dw(f[a], dw[a]);
+      }
+      // forward gather: v_p and C_p
+      float vp[3] = {0.f, 0.f, 0.f};
+      float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+          for (int ox = 0; ox < 3; ++ox) {
+            int64_t node = (bx + ox) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+            float wt = w[0][ox] * w[1][oy] * w[2][oz];
+            float vi[3] = {gv[node], gv[N + node], gv[2 * N + node]};
+            float o[3] = {(float)ox - f[0], (float)oy - f[1], (float)oz - f[2]};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              vp[a] += wt * vi[a];
+#pragma unroll
+              for (int b = 0; b < 3; ++b) B[3 * a + b] += wt * vi[a] * o[b];
+            }
+          }
+      float Cn[9], Fp[9], Fo[9], Cbt[9], vbt[3];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        Cn[q] = kc * B[q];
+        Fp[q] = F[q * n + p] + ((q % 4) == 0 ? 1.f : 0.f);  // stored as F - I
+        Fo[q] = Fob ? Fob[q * n + p] : 0.f;
+        Cbt[q] = Cob ? Cob[q * n + p] : 0.f;
+      }
+      // F' = (I + dt C) F:  Fbar += (I + dt C)^T Fbar',  Cbar += dt Fbar' F^T
+      if (Fob) {
+        float G[9], GtFo[9], FoFt[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) G[q] = dt * Cn[q];
+        G[0] += 1.f; G[4] += 1.f; G[8] += 1.f;
+        matmul3_atb(G, Fo, GtFo);
+        matmul3_abt(Fo, Fp, FoFt);
+        if (Fb) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) Fb[q * n + p] += GtFo[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Cbt[q] += dt * FoFt[q];
+      }
+      // x' = x + dt v_p
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float xo = xob ? xob[a * n + p] : 0.f;
+        vbt[a] = (vob ? vob[a * n + p] : 0.f) + dt * xo;
+      }
+      float xbar[3] = {xob ? xob[p] : 0.f, xob ? xob[n + p] : 0.f, xob ? xob[2 * n + p] : 0.f};
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+          for (int ox = 0; ox < 3; ++ox) {
+            int64_t node = (bx + ox) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+            float wt = w[0][ox] * w[1][oy] * w[2][oz];
+            float gw[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * g.inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * g.inv_dx,
+                           w[0][ox] * w[1][oy] * dw[2][oz] * g.inv_dx};
+            float o[3] = {(float)ox - f[0], (float)oy - f[1], (float)oz - f[2]};
+            float vi[3] = {gv[node], gv[N + node], gv[2 * N + node]};
+            // C = kc sum w v o^T: v_i bar += w (vbt + kc Cbt o)
+            float Co[3], CtV[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              Co[a] = Cbt[3 * a] * o[0] + Cbt[3 * a + 1] * o[1] + Cbt[3 * a + 2] * o[2];
+              CtV[a] = Cbt[a] * vi[0] + Cbt[3 + a] * vi[1] + Cbt[6 + a] * vi[2];
+            }
+            float s = vi[0] * vbt[0] + vi[1] * vbt[1] + vi[2] * vbt[2] + kc * (vi[0] * Co[0] + vi[1] * Co[1] + vi[2] * Co[2]);
+            // d o / d x = -inv_dx I
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xbar[a] += gw[a] * s - wt * kc * g.inv_dx * CtV[a];
+            int li = (lx + ox) + ADJ_L * ((ly + oy) + ADJ_L * (lz + oz));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) atomicAdd(&s_acc[a][li], wt * (vbt[a] + kc * Co[a]));
+          }
+      if (xb) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xb[a * n + p] += xbar[a];
+      }
+    }
+    __syncthreads();
+    for (int li = threadIdx.x; li < ADJ_NODES; li += blockDim.x) {
+      float a0 = s_acc[0][li], a1 = s_acc[1][li], a2 = s_acc[2][li];
+      if (a0 != 0.f || a1 != 0.f || a2 != 0.f) {
+        int ix = li % ADJ_L, iy = (li / ADJ_L) % ADJ_L, iz = li / (ADJ_L * ADJ_L);
+        int64_t node = (4 * tx + ix) + (int64_t)g.nx * ((4 * ty + iy) + (int64_t)g.ny * (4 * tz + iz));
+        atomicAdd(&gvb[node], a0);
+        atomicAdd(&gvb[N + node], a1);
+        atomicAdd(&gvb[2 * N + node], a2);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace dw
+
+using namespace dw;
+
+extern "C" int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p,
+                           const float *grid_m_bar, const float *grid_mv_bar, dw_particles_bar *bar, float *E_bar,
+                           void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  DW_REQUIRE(params, DW_EINVAL, "mpm_p2g_adj: params is NULL");
+  DW_REQUIRE(params->material == DW_FIXED_COROTATED || params->material == DW_NEO_HOOKEAN, DW_EINVAL,
+             "mpm_p2g_adj: unknown material");
+  rc = check_particles(p, true);
+  if (rc) return rc;
+  DW_REQUIRE(grid_m_bar && grid_mv_bar, DW_EINVAL, "mpm_p2g_adj: grid adjoints must be set");
+  DW_REQUIRE(bar && bar->n == p->n, DW_EINVAL, "mpm_p2g_adj: bar->n must equal p->n");
+  if (p->n == 0) return DW_OK;
+  PAdj P;
+  P.x = p->x; P.v = p->v; P.C = p->C; P.F = p->F; P.mass = p->mass; P.vol0 = p->vol0;
+  P.E = p->E; P.nu = p->nu; P.region = p->region; P.n = p->n;
+  P.xb = bar->x; P.vb = bar->v; P.Cb = bar->C; P.Fb = bar->F; P.Eb = E_bar;
+  GridDev g = make_grid(grid);
+  int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  hipLaunchKernelGGL(k_p2g_adj, dim3(grid_blocks(p->n, 256)), dim3(256), 0, (hipStream_t)stream, g, P, params->dt,
+                     params->material, grid_m_bar, grid_mv_bar, N);
+  return check_launch("mpm_p2g_adj");
+}
+
+extern "C" int mpm_grid_update_adj(const dw_grid *grid, const dw_mpm_params *params, const float *grid_m,
+                                   const float *grid_mv, const dw_wind *wind, const uint8_t *pin,
+                                   const float *grid_v_bar, float *grid_m_bar, float *grid_mv_bar, float *acc_bar,
+                                   const void *ws, size_t ws_bytes, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  DW_REQUIRE(params && grid_m && grid_mv && grid_v_bar, DW_EINVAL, "mpm_grid_update_adj: missing argument");
+  Workspace W;
+  rc = bind_workspace(grid, 0, ws, ws_bytes, &W);
+  if (rc) return rc;
+  WindDev wd;
+  rc = make_wind(wind, grid, &wd);
+  if (rc) return rc;
+  GridDev g = make_grid(grid);
+  int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  hipLaunchKernelGGL(k_grid_update_adj, dim3(2048), dim3(256), 0, (hipStream_t)stream, g, params->dt,
+                     params->gravity[0], params->gravity[1], params->gravity[2], params->bound, grid_m, grid_mv, wd,
+                     pin, W.node_tiles, W.n_node_tiles, grid_v_bar, grid_m_bar, grid_mv_bar, acc_bar, N);
+  return check_launch("mpm_grid_update_adj");
+}
+
+extern "C" int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
+                           const dw_particles *in, const dw_particles_bar *out_bar, dw_particles_bar *in_bar,
+                           float *grid_v_bar, const void *ws, size_t ws_bytes, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  DW_REQUIRE(params && grid_v && in && out_bar && in_bar && grid_v_bar, DW_EINVAL,
+             "mpm_g2p_adj: missing argument");
+  DW_REQUIRE(in->n >= 0 && out_bar->n == in->n && in_bar->n == in->n, DW_EINVAL, "mpm_g2p_adj: size mismatch");
+  if (in->n == 0) return DW_OK;
+  DW_REQUIRE(in->x && in->F, DW_EINVAL, "mpm_g2p_adj: in->x / in->F is NULL");
+  Workspace W;
+  rc = bind_workspace(grid, in->n, ws, ws_bytes, &W);
+  if (rc) return rc;
+  GridDev g = make_grid(grid);
+  int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  hipLaunchKernelGGL(k_g2p_adj, dim3(2048), dim3(256), 0, (hipStream_t)stream, g, params->dt, grid_v, N, in->x,
+                     in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F, grid_v_bar,
+                     W.perm, W.tile_start, W.cell_tiles, W.n_cell_tiles);
+  return check_launch("mpm_g2p_adj");
+}

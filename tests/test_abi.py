@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/diffwind.h declares, its struct layouts match the ctypes
+mirrors, and argument errors come back as codes (no GPU needed: every call
+below fails validation before touching the device)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2603_09668_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "diffwind.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(api.LIB_PATH), reason="libdiffwind.so not built")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return [n for n in names if n not in ("if", "while")]
+
+
+def test_every_declared_symbol_is_exported():
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    L = ctypes.CDLL(api.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(declared) == sorted(api.SYMBOLS)
+
+
+def test_struct_layout_matches_header():
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "diffwind.h"
+#define P(T) printf(#T " %zu\n", sizeof(T));
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  P(dw_grid) P(dw_lattice) P(dw_mpm_params) P(dw_particles) P(dw_particles_bar) P(dw_wind) P(dw_lbm_params)
+  O(dw_wind, W) O(dw_wind, lat) O(dw_wind, u) O(dw_wind, acc) O(dw_particles, n_regions) O(dw_lbm_params, t)
+  O(dw_lbm_params, bc) O(dw_mpm_params, deterministic)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    mirror = {"dw_grid": api.Grid, "dw_lattice": api.Lattice, "dw_mpm_params": api.MPMParams,
+              "dw_particles": api.Particles, "dw_particles_bar": api.ParticlesBar, "dw_wind": api.Wind,
+              "dw_lbm_params": api.LBMParams}
+    for name, cls in mirror.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+    assert int(got["dw_wind.W"]) == api.Wind.W.offset
+    assert int(got["dw_wind.lat"]) == api.Wind.lat.offset
+    assert int(got["dw_wind.u"]) == api.Wind.u.offset
+    assert int(got["dw_wind.acc"]) == api.Wind.acc.offset
+    assert int(got["dw_particles.n_regions"]) == api.Particles.n_regions.offset
+    assert int(got["dw_lbm_params.t"]) == api.LBMParams.t.offset
+    assert int(got["dw_lbm_params.bc"]) == api.LBMParams.bc.offset
+    assert int(got["dw_mpm_params.deterministic"]) == api.MPMParams.deterministic.offset
+
+
+def test_workspace_size_is_host_only_and_grows_with_n():
+    g = api.make_grid(32, 32, 32, 1 / 32)
+    a = api.mpm_workspace_bytes(g, 0)
+    b = api.mpm_workspace_bytes(g, 1000)
+    assert a > 0 and b >= a + 3 * 4 * 1000
+    bad = api.make_grid(2, 32, 32, 1 / 32)
+    assert api.mpm_workspace_bytes(bad, 10) == 0
+
+
+def test_argument_errors_are_codes():
+    L = api.lib()
+    g = api.make_grid(16, 16, 16, 1 / 16)
+    prm = api.make_mpm_params(1e-4)
+    # null workspace
+    rc = L.mpm_sort(ctypes.byref(g), ctypes.byref(prm), ctypes.c_void_p(16), 10, None, 0, None)
+    assert rc == -1 and "workspace" in api.dw_last_error()
+    # workspace too small (aligned fake pointer, never dereferenced)
+    rc = L.mpm_sort(ctypes.byref(g), ctypes.byref(prm), ctypes.c_void_p(256), 10, ctypes.c_void_p(256), 8, None)
+    assert rc == -4
+    bad = api.make_grid(16, 0, 16, 1 / 16)
+    assert L.mpm_sort(ctypes.byref(bad), ctypes.byref(prm), None, 0, ctypes.c_void_p(256), 1 << 20, None) == -1
+    lat = api.make_lattice(8, 8, 8)
+    lp = api.make_lbm_params(0.5)  # tau must exceed 1/2
+    assert L.lbm_step(ctypes.byref(lat), ctypes.byref(lp), ctypes.c_void_p(256), ctypes.c_void_p(512), None, None,
+                      None, None) == -1
+    lp = api.make_lbm_params(0.6, bc=(api.BC_PERIODIC, api.BC_BOUNCEBACK, 0, 0, 0, 0))
+    assert L.lbm_step(ctypes.byref(lat), ctypes.byref(lp), ctypes.c_void_p(256), ctypes.c_void_p(512), None, None,
+                      None, None) == -1
+    assert "periodic" in api.dw_last_error()
+    lp = api.make_lbm_params(0.6)
+    assert L.lbm_step(ctypes.byref(lat), ctypes.byref(lp), ctypes.c_void_p(256), ctypes.c_void_p(256), None, None,
+                      None, None) == -1
+    w = api.Wind(mode=7)
+    assert L.wind_to_grid(ctypes.byref(g), ctypes.byref(w), ctypes.c_void_p(256), None) == -1

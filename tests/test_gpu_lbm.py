@@ -1,0 +1,175 @@
+"""GPU parity of the LBM entry points against the float64 oracle.
+
+Populations are compared as f_i - w_i (the library's storage) with the
+norm-wise relative error against max_i |f_i - w_i|; velocities against the
+inflow speed.  The voxel mask is integer work and is compared bit-exactly,
+with the cell index decided in float32 on both sides."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbm as olbm
+from paper_2603_09668_amd import api, scenes
+
+from gpu_util import DEV, f32, rel, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+WQ = olbm.W.view(19, 1, 1, 1)
+
+
+def _random_state(dims, seed, u0=(0.05, 0.0, 0.0)):
+    nx, ny, nz = dims
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.01 * torch.tensor(rng.standard_normal((nz, ny, nx)))
+    u = torch.tensor(u0, dtype=torch.float64).view(3, 1, 1, 1) + 0.02 * torch.tensor(
+        rng.standard_normal((3, nz, ny, nx)))
+    f = olbm.equilibrium(rho, u) + 1e-4 * torch.tensor(rng.standard_normal((19, nz, ny, nx)))
+    # both sides start from the same float32 shifted populations
+    fs = f32(f - WQ)
+    return fs + WQ, fs
+
+
+def _params(tau=0.6, u_in=(0.05, 0.0, 0.0), force=(0.0, 0.0, 0.0), bc=None, gust=(0.0, 1.0, 0.0, 0.0, 0.0), t=0):
+    bc = bc or (olbm.INLET, olbm.OUTLET, olbm.BOUNCEBACK, olbm.BOUNCEBACK, olbm.BOUNCEBACK, olbm.BOUNCEBACK)
+    op = olbm.LBMParams(tau=tau, u_in=u_in, force=force, bc=bc, gust_amp=gust[0], gust_period=gust[1],
+                        gust_ky=gust[2], gust_kz=gust[3], gust_phase=gust[4])
+    ap = api.make_lbm_params(tau, u_in, force, bc, *gust, t=t)
+    return op, ap
+
+
+CASES = {
+    "tunnel": dict(dims=(24, 20, 16), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 200.0, 1.0, 1.0, 0.3)),
+    "periodic_forced": dict(dims=(12, 10, 8), bc=(0,) * 6, force=(1e-4, -2e-5, 3e-5), gust=(0.0, 1.0, 0, 0, 0)),
+    "channel": dict(dims=(17, 9, 11), bc=(0, 0, 1, 1, 0, 0), force=(1e-5, 0.0, 0.0), gust=(0.0, 1.0, 0, 0, 0)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_lbm_step_parity(case):
+    c = CASES[case]
+    nx, ny, nz = c["dims"]
+    say(f"lbm_step {case} {c['dims']}")
+    f, fs = _random_state(c["dims"], 1)
+    solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
+    solid[nz // 3:nz // 3 + 4, ny // 3:ny // 3 + 3, nx // 2:nx // 2 + 5] = True
+    t = 17
+    op, ap = _params(force=c["force"], bc=c["bc"], gust=c["gust"], t=t)
+    lat = olbm.Lattice(nx, ny, nz)
+    alat = api.make_lattice(nx, ny, nz)
+    fo, rho, u = olbm.lbm_step(lat, op, f, solid, t)
+    L = nx * ny * nz
+    fin = fs.reshape(19, L).float().to(DEV).contiguous()
+    fout = torch.empty_like(fin)
+    rho_d = torch.empty(L, device=DEV)
+    u_d = torch.empty(3, L, device=DEV)
+    api.lbm_step(alat, ap, fin, fout, solid.reshape(-1).to(torch.uint8).to(DEV), rho_d, u_d)
+    torch.cuda.synchronize()
+    ref = (fo - WQ).reshape(19, L)
+    assert rel(fout.cpu(), ref) < TOL
+    assert (u_d.cpu().double() - u.reshape(3, L)).abs().max().item() / 0.05 < TOL
+    assert (rho_d.cpu().double() - rho.reshape(L)).abs().max().item() < 1e-6
+
+
+def test_lbm_multistep_parity():
+    say("lbm_step tunnel x40")
+    dims = (20, 16, 12)
+    nx, ny, nz = dims
+    f, fs = _random_state(dims, 2)
+    solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
+    solid[4:8, 5:9, 8:11] = True
+    lat = olbm.Lattice(nx, ny, nz)
+    alat = api.make_lattice(nx, ny, nz)
+    L = nx * ny * nz
+    a = fs.reshape(19, L).float().to(DEV).contiguous()
+    b = torch.empty_like(a)
+    sd = solid.reshape(-1).to(torch.uint8).to(DEV)
+    for t in range(40):
+        op, ap = _params(gust=(0.05, 50.0, 1.0, 0.0, 0.1), t=t)
+        f, _, _ = olbm.lbm_step(lat, op, f, solid, t)
+        api.lbm_step(alat, ap, a, b, sd)
+        a, b = b, a
+    torch.cuda.synchronize()
+    assert rel(a.cpu(), (f - WQ).reshape(19, L)) < 2e-4
+
+
+def test_periodic_mass_conservation():
+    say("lbm_step periodic mass")
+    dims = (32, 24, 16)
+    nx, ny, nz = dims
+    _, fs = _random_state(dims, 3)
+    L = nx * ny * nz
+    alat = api.make_lattice(nx, ny, nz)
+    ap = api.make_lbm_params(0.7)
+    a = fs.reshape(19, L).float().to(DEV).contiguous()
+    b = torch.empty_like(a)
+    m0 = a.double().sum().item()
+    for t in range(200):
+        api.lbm_step(alat, ap, a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    # shifted total mass: deviation from L, conserved up to float32 round-off
+    assert abs(a.double().sum().item() - m0) < 1e-6 * L
+
+
+def test_poiseuille_on_gpu():
+    say("lbm_step poiseuille")
+    H = 16
+    tau = 0.5 + math.sqrt(3.0 / 16.0)
+    g = 1e-5
+    alat = api.make_lattice(4, H, 4)
+    ap = api.make_lbm_params(tau, force=(g, 0.0, 0.0), bc=(0, 0, 1, 1, 0, 0))
+    L = 4 * H * 4
+    a = torch.zeros(19, L, device=DEV)
+    b = torch.empty_like(a)
+    u = torch.empty(3, L, device=DEV)
+    for t in range(6000):
+        api.lbm_step(alat, ap, a, b, None, None, u)
+        a, b = b, a
+    torch.cuda.synchronize()
+    nu = (tau - 0.5) / 3.0
+    y = torch.arange(H, dtype=torch.float64) + 0.5
+    exact = g / (2 * nu) * y * (H - y)
+    prof = u[0].cpu().double().view(4, H, 4)[1, :, 2]
+    assert (prof - exact).abs().max().item() / exact.max().item() < 2e-4
+
+
+def test_equilibrium_parity():
+    say("lbm_equilibrium")
+    dims = (10, 8, 6)
+    nx, ny, nz = dims
+    rng = np.random.default_rng(4)
+    rho = f32(1.0 + 0.02 * rng.standard_normal((nz, ny, nx)))
+    u = f32(0.05 * rng.standard_normal((3, nz, ny, nx)))
+    L = nx * ny * nz
+    alat = api.make_lattice(nx, ny, nz)
+    f = torch.empty(19, L, device=DEV)
+    api.lbm_equilibrium(alat, api.make_lbm_params(0.6), f, rho.reshape(L).float().to(DEV),
+                        u.reshape(3, L).float().to(DEV).contiguous())
+    torch.cuda.synchronize()
+    ref = (olbm.equilibrium(rho, u) - WQ).reshape(19, L)
+    assert rel(f.cpu(), ref) < TOL
+
+
+def test_voxelize_bit_exact():
+    say("lbm_solid_from_particles")
+    sc = scenes.flag_and_leaves_scene(seed=5, n=40_000, res=64, n_clusters=8, lbm_dims=(64, 32, 32))
+    lat = sc.lattice
+    olat = olbm.Lattice(lat["nx"], lat["ny"], lat["nz"], lat["dx"], lat["origin"])
+    alat = api.make_lattice(lat["nx"], lat["ny"], lat["nz"], lat["dx"], lat["origin"])
+    x32 = torch.as_tensor(sc.x).float()
+    ref = olbm.voxelize(olat, x32)
+    solid = torch.full((olat.n_nodes,), 7, dtype=torch.uint8, device=DEV)
+    api.lbm_solid_from_particles(alat, x32.T.contiguous().to(DEV), solid, accumulate=False)
+    torch.cuda.synchronize()
+    assert torch.equal(solid.cpu().bool().view(olat.nz, olat.ny, olat.nx), ref)
+    # accumulate mode ORs into an existing mask
+    extra = torch.zeros_like(solid)
+    extra[:10] = 1
+    api.lbm_solid_from_particles(alat, x32.T.contiguous().to(DEV), extra, accumulate=True)
+    torch.cuda.synchronize()
+    expect = ref.reshape(-1).clone()
+    expect[:10] = True
+    assert torch.equal(extra.cpu().bool(), expect)
