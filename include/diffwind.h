@@ -149,6 +149,12 @@ typedef struct {
   /* inlet gust: u_in * (1 + amp sin(2 pi (t / period + ky j / ny + kz k / nz) + phase)) */
   float gust_amp, gust_period, gust_ky, gust_kz, gust_phase;
   int t;              /* step index for the gust */
+  /* Optional device step counter (lets one captured HIP graph serve every
+   * step): if t_in is not NULL the step index is read from *t_in instead of
+   * t, and lbm_step writes index + 1 to *t_out (if not NULL; t_out must not
+   * alias t_in -- swap the two like the population buffers). */
+  const int32_t *t_in;
+  int32_t *t_out;
 } dw_lbm_params;
 
 /* ---------------------------------------------------------------- errors */
@@ -177,10 +183,11 @@ int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const float *x, i
  *   A_p  = m_p C_p - dt V0_p (4/dx^2) tau(F_p),   tau = P F^T (Kirchhoff),
  *   m_i  = sum_p w_ip m_p,
  *   mv_i = sum_p w_ip (m_p v_p + A_p (x_i - x_p)),
- * quadratic B-spline weights w_ip.  Runs mpm_sort first.  OVERWRITES grid_m
- * [N] and grid_mv [3][N] on every node of every active node tile; nodes
- * outside active tiles are not written.  Particles whose stencil leaves the
- * grid are skipped and flagged in the status word. */
+ * quadratic B-spline weights w_ip.  Uses the sort that mpm_sort() left in
+ * `ws` for the same p->x (call it first).  OVERWRITES grid_m [N] and grid_mv
+ * [3][N] on every node of every active node tile; nodes outside active tiles
+ * are not written.  Particles whose stencil leaves the grid are skipped and
+ * flagged in the status word. */
 int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p,
             float *grid_m, float *grid_mv, void *ws, size_t ws_bytes, void *stream);
 

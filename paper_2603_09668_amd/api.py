@@ -66,7 +66,8 @@ class Wind(ctypes.Structure):
 class LBMParams(ctypes.Structure):
     _fields_ = [("tau", c_float), ("u_in", c_float * 3), ("force", c_float * 3), ("bc", c_int * 6),
                 ("gust_amp", c_float), ("gust_period", c_float), ("gust_ky", c_float),
-                ("gust_kz", c_float), ("gust_phase", c_float), ("t", c_int)]
+                ("gust_kz", c_float), ("gust_phase", c_float), ("t", c_int), ("t_in", c_void_p),
+                ("t_out", c_void_p)]
 
 
 _lib = None
@@ -154,10 +155,12 @@ def make_mpm_params(dt, gravity=(0.0, 0.0, 0.0), bound=3, material=FIXED_COROTAT
 
 
 def make_lbm_params(tau, u_in=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0), bc=(BC_PERIODIC,) * 6, gust_amp=0.0,
-                    gust_period=1.0, gust_ky=0.0, gust_kz=0.0, gust_phase=0.0, t=0) -> LBMParams:
+                    gust_period=1.0, gust_ky=0.0, gust_kz=0.0, gust_phase=0.0, t=0, t_in=None,
+                    t_out=None) -> LBMParams:
+    """t_in / t_out: optional device int32 step counters (see the header)."""
     return LBMParams(float(tau), (c_float * 3)(*u_in), (c_float * 3)(*force), (c_int * 6)(*bc),
                      float(gust_amp), float(gust_period), float(gust_ky), float(gust_kz), float(gust_phase),
-                     int(t))
+                     int(t), _ptr(t_in, torch.int32, "t_in"), _ptr(t_out, torch.int32, "t_out"))
 
 
 def wind_none() -> Wind:
@@ -363,13 +366,18 @@ def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
     take("tile_start", T + 1)
     take("cell_tiles", T)
     take("node_tiles", T)
-    take("block_sums", 3 * NB)
+    take("block_sums", 4 * NB)
     take("key", n)
     take("perm", n)
+    take("perm_tmp", n)
+    max_items = T + n // 512 + 1
+    take("item_tile", max_items)
+    take("item_begin", max_items)
     hdr = views["header"]
     views["status"] = hdr[0]
     views["n_sorted"] = hdr[3]
     views["n_node_tiles"] = hdr[4]
     views["n_cell_tiles"] = hdr[5]
+    views["n_items"] = hdr[6]
     views["n_tiles"] = T
     return views

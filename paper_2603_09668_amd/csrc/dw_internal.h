@@ -64,12 +64,16 @@ struct Workspace {
   int32_t *key;
   int32_t *perm;
   int32_t *perm_tmp;
+  int32_t *n_items;     // work items: chunks of <= WORK_CHUNK particles of one cell tile
+  int32_t *item_tile;
+  int32_t *item_begin;
   int64_t n_tiles;
   int64_t n_scan_blocks;
   size_t bytes;
 };
 
 constexpr int SCAN_BLOCK = 1024;
+constexpr int WORK_CHUNK = 512;  // particles per scatter work item
 
 size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base);
 int check_grid(const dw_grid *g);
@@ -94,10 +98,6 @@ inline unsigned grid_blocks(int64_t work, int block) {
 }
 
 // ---------------------------------------------------- device math helpers
-struct M3 {
-  float a[9];
-};
-
 __device__ __forceinline__ float det3(const float *m) {
   return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
          m[2] * (m[3] * m[7] - m[4] * m[6]);
@@ -143,36 +143,6 @@ __device__ __forceinline__ void matmul3_atb(const float *a, const float *b, floa
       c[3 * i + j] = a[i] * b[j] + a[3 + i] * b[3 + j] + a[6 + i] * b[6 + j];
 }
 
-// Rotation factor of the polar decomposition F = R S (det F > 0) by the
-// scaled Newton iteration X <- (zeta X + X^{-T} / zeta) / 2,
-// zeta = sqrt(|X^{-1}|_F / |X|_F) (Higham 1986).  F = I gives R = I exactly.
-__device__ __forceinline__ void polar_rotation(const float *F, float *R) {
-#pragma unroll
-  for (int i = 0; i < 9; ++i) R[i] = F[i];
-  for (int it = 0; it < 24; ++it) {
-    float d = det3(R);
-    float Y[9];
-    inv_transpose3(R, d, Y);
-    float nx = 0.f, ny = 0.f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      nx += R[i] * R[i];
-      ny += Y[i] * Y[i];
-    }
-    float zeta = sqrtf(sqrtf(ny / nx));
-    float iz = 1.0f / zeta;
-    float delta = 0.f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      float r = 0.5f * (zeta * R[i] + iz * Y[i]);
-      float e = r - R[i];
-      delta += e * e;
-      R[i] = r;
-    }
-    if (delta <= 1e-13f) break;
-  }
-}
-
 __device__ __forceinline__ void lame(float E, float nu, float &mu, float &lam) {
   mu = E / (2.0f * (1.0f + nu));
   lam = E * nu / ((1.0f + nu) * (1.0f - 2.0f * nu));
@@ -202,7 +172,7 @@ __device__ __forceinline__ void polar_shift(const float *H, float *Y) {
     Y[i] = H[i];
     hh += H[i] * H[i];
   }
-  for (int it = 0; it < 30; ++it) {
+  for (int it = 0; it < 16; ++it) {
     float t = Y[0] + Y[4] + Y[8];
     float Y2[9];
     matmul3(Y, Y, Y2);
@@ -239,7 +209,9 @@ __device__ __forceinline__ void polar_shift(const float *H, float *Y) {
       yy += yn * yn;
       Y[i] = yn;
     }
-    if (delta <= 1e-14f * (yy + hh) || delta == 0.f) break;
+    // quadratic convergence: a relative step below 1e-6 leaves an error of
+    // order 1e-12, under float32 round-off, so stop there
+    if (delta <= 1e-12f * (yy + hh)) break;
   }
 }
 

@@ -30,6 +30,8 @@ struct LbmDev {
   int bc[6];
   float gust_amp, gust_inv_period, gust_ky, gust_kz, gust_phase;
   int t;
+  const int32_t *t_in;
+  int32_t *t_out;
   bool forced;
 };
 
@@ -37,7 +39,7 @@ struct LbmDev {
 enum { SRC_NORMAL = 0, SRC_BOUNCE = 1, SRC_INLET = 2 };
 
 __device__ __forceinline__ int pull_source(const LbmDev &P, const uint8_t *__restrict__ solid, int i, int j,
-                                           int k, int q, int64_t &src) {
+                                           int k, int q, int64_t &src, int &sj, int &sk) {
   int s[3] = {i - LC[q][0], j - LC[q][1], k - LC[q][2]};
   const int n[3] = {P.nx, P.ny, P.nz};
   bool bounce = false, inlet = false;
@@ -58,6 +60,8 @@ __device__ __forceinline__ int pull_source(const LbmDev &P, const uint8_t *__res
 #pragma unroll
   for (int a = 0; a < 3; ++a) s[a] = min(max(s[a], 0), n[a] - 1);
   src = s[0] + (int64_t)P.nx * (s[1] + (int64_t)P.ny * s[2]);
+  sj = s[1];
+  sk = s[2];
   if (inlet) return SRC_INLET;
   if (solid && solid[src]) return SRC_BOUNCE;
   return SRC_NORMAL;
@@ -67,7 +71,8 @@ __device__ __forceinline__ int pull_source(const LbmDev &P, const uint8_t *__res
 __device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, int k) {
   float sfac = 1.0f;
   if (P.gust_amp != 0.f) {
-    float ph = 6.283185307179586f * ((float)P.t * P.gust_inv_period + P.gust_ky * (float)j / (float)P.ny +
+    int t = P.t_in ? *P.t_in : P.t;
+    float ph = 6.283185307179586f * ((float)t * P.gust_inv_period + P.gust_ky * (float)j / (float)P.ny +
                                      P.gust_kz * (float)k / (float)P.nz) +
                P.gust_phase;
     sfac = 1.0f + P.gust_amp * sinf(ph);
@@ -78,30 +83,29 @@ __device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, 
   return LW[q] * (3.f * cu + 4.5f * cu * cu - 1.5f * uu);
 }
 
-// Pull the 19 shifted populations of fluid node (i, j, k).
+// Pull the 19 shifted populations of fluid node (i, j, k).  A source inside
+// the lattice needs only the solid test; the boundary rules run only for the
+// few lanes whose source leaves the lattice (the inlet and outlet columns
+// sit in every x-row, so the general rule must not be taken per node).
 __device__ __forceinline__ void pull_all(const LbmDev &P, const float *__restrict__ fin,
                                          const uint8_t *__restrict__ solid, int i, int j, int k, int64_t node,
                                          float f[19]) {
-  bool interior = i > 0 && j > 0 && k > 0 && i < P.nx - 1 && j < P.ny - 1 && k < P.nz - 1;
-  if (interior) {
-    const int64_t sx = 1, sy = P.nx, sz = (int64_t)P.nx * P.ny;
-#pragma unroll
-    for (int q = 0; q < 19; ++q) {
-      int64_t src = node - (LC[q][0] * sx + LC[q][1] * sy + LC[q][2] * sz);
-      bool bb = solid && solid[src];
-      f[q] = bb ? fin[(int64_t)LOPP[q] * P.L + node] : fin[(int64_t)q * P.L + src];
-    }
-    return;
-  }
+  const int64_t sy = P.nx, sz = (int64_t)P.nx * P.ny;
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
-    int64_t src = node;
-    int kind = pull_source(P, solid, i, j, k, q, src);
-    if (kind == SRC_NORMAL) f[q] = fin[(int64_t)q * P.L + src];
-    else if (kind == SRC_BOUNCE) f[q] = fin[(int64_t)LOPP[q] * P.L + node];
-    else {
-      int sj = (int)((src / P.nx) % P.ny), sk = (int)(src / ((int64_t)P.nx * P.ny));
-      f[q] = inlet_feq_shift(P, q, sj, sk);
+    int si = i - LC[q][0], sj = j - LC[q][1], sk = k - LC[q][2];
+    bool inside = (unsigned)si < (unsigned)P.nx && (unsigned)sj < (unsigned)P.ny && (unsigned)sk < (unsigned)P.nz;
+    if (inside) {
+      int64_t src = node - (LC[q][0] + LC[q][1] * sy + LC[q][2] * sz);
+      bool bb = solid && solid[src];
+      f[q] = bb ? fin[(int64_t)LOPP[q] * P.L + node] : fin[(int64_t)q * P.L + src];
+    } else {
+      int64_t src = node;
+      int ssj = 0, ssk = 0;
+      int kind = pull_source(P, solid, i, j, k, q, src, ssj, ssk);
+      if (kind == SRC_NORMAL) f[q] = fin[(int64_t)q * P.L + src];
+      else if (kind == SRC_BOUNCE) f[q] = fin[(int64_t)LOPP[q] * P.L + node];
+      else f[q] = inlet_feq_shift(P, q, ssj, ssk);
     }
   }
 }
@@ -123,11 +127,13 @@ __device__ __forceinline__ void moments(const LbmDev &P, const float f[19], floa
   uz = (jz + 0.5f * P.F[2]) * ir;
 }
 
-__global__ __launch_bounds__(256) void k_lbm_step(LbmDev P, const float *__restrict__ fin, float *__restrict__ fout,
+__global__ __launch_bounds__(128) void k_lbm_step(LbmDev P, const float *__restrict__ fin, float *__restrict__ fout,
                                                   const uint8_t *__restrict__ solid, float *__restrict__ rho_out,
                                                   float *__restrict__ u_out) {
-  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= P.L) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
+  if (i >= P.nx) return;
+  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
   if (solid && solid[node]) {
 #pragma unroll
     for (int q = 0; q < 19; ++q) fout[(int64_t)q * P.L + node] = 0.f;
@@ -139,9 +145,6 @@ __global__ __launch_bounds__(256) void k_lbm_step(LbmDev P, const float *__restr
     }
     return;
   }
-  int i = (int)(node % P.nx);
-  int j = (int)((node / P.nx) % P.ny);
-  int k = (int)(node / ((int64_t)P.nx * P.ny));
   float f[19];
   pull_all(P, fin, solid, i, j, k, node, f);
   float rho, ux, uy, uz;
@@ -174,17 +177,15 @@ __global__ __launch_bounds__(256) void k_lbm_step(LbmDev P, const float *__restr
 // the adjoint of the pulled populations through the BGK collision, and push
 // each one back to where it was pulled from (atomics: boundary rules can
 // make two destinations share one source).
-__global__ __launch_bounds__(256) void k_lbm_step_adj(LbmDev P, const float *__restrict__ fin,
+__global__ __launch_bounds__(128) void k_lbm_step_adj(LbmDev P, const float *__restrict__ fin,
                                                       const uint8_t *__restrict__ solid,
                                                       const float *__restrict__ gout,
                                                       const float *__restrict__ ubar_out,
                                                       float *__restrict__ fin_bar) {
-  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= P.L) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= P.nx) return;
+  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
   if (solid && solid[node]) return;
-  int i = (int)(node % P.nx);
-  int j = (int)((node / P.nx) % P.ny);
-  int k = (int)(node / ((int64_t)P.nx * P.ny));
   float f[19];
   pull_all(P, fin, solid, i, j, k, node, f);
   float rho, ux, uy, uz;
@@ -224,7 +225,8 @@ __global__ __launch_bounds__(256) void k_lbm_step_adj(LbmDev P, const float *__r
   for (int q = 0; q < 19; ++q) {
     float fb = (1.f - om) * g[q] + rbar + (bx * LC[q][0] + by * LC[q][1] + bz * LC[q][2] - bu) * ir;
     int64_t src = node;
-    int kind = pull_source(P, solid, i, j, k, q, src);
+    int ssj, ssk;
+    int kind = pull_source(P, solid, i, j, k, q, src, ssj, ssk);
     if (kind == SRC_NORMAL) atomicAdd(&fin_bar[(int64_t)q * P.L + src], fb);
     else if (kind == SRC_BOUNCE) atomicAdd(&fin_bar[(int64_t)LOPP[q] * P.L + node], fb);
   }
@@ -269,11 +271,18 @@ __global__ void k_fill_u8(uint8_t *p, int64_t count) {
     p[i] = 0;
 }
 
+// launch shape: threads along x, one block row per (y, z) line
+constexpr int LBM_BLOCK = 128;
+static dim3 lbm_grid(const LbmDev &P) {
+  return dim3((unsigned)((P.nx + LBM_BLOCK - 1) / LBM_BLOCK), (unsigned)P.ny, (unsigned)P.nz);
+}
+
 static int make_lbm(const dw_lattice *lat, const dw_lbm_params *prm, LbmDev *P) {
   DW_REQUIRE(lat && prm, DW_EINVAL, "lbm: lattice / params is NULL");
   DW_REQUIRE(lat->nx >= 1 && lat->ny >= 1 && lat->nz >= 1, DW_EINVAL, "lbm: lattice dims must be >= 1");
   int64_t L = (int64_t)lat->nx * lat->ny * lat->nz;
   DW_REQUIRE(L * 19 < (int64_t)INT_MAX * 64, DW_ERANGE, "lbm: lattice too large");
+  DW_REQUIRE(lat->ny <= 65535 && lat->nz <= 65535, DW_ERANGE, "lbm: ny, nz must be <= 65535");
   DW_REQUIRE(prm->tau > 0.5f, DW_EINVAL, "lbm: tau must be > 1/2 (got %g)", (double)prm->tau);
   for (int a = 0; a < 3; ++a) {
     int lo = prm->bc[2 * a], hi = prm->bc[2 * a + 1];
@@ -302,6 +311,9 @@ static int make_lbm(const dw_lattice *lat, const dw_lbm_params *prm, LbmDev *P) 
   P->gust_kz = prm->gust_kz;
   P->gust_phase = prm->gust_phase;
   P->t = prm->t;
+  P->t_in = prm->t_in;
+  P->t_out = prm->t_out;
+  DW_REQUIRE(!prm->t_out || (const int32_t *)prm->t_out != prm->t_in, DW_EINVAL, "lbm: t_out must not alias t_in");
   P->forced = prm->force[0] != 0.f || prm->force[1] != 0.f || prm->force[2] != 0.f;
   return DW_OK;
 }
@@ -317,8 +329,8 @@ extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, cons
   if (rc) return rc;
   DW_REQUIRE(f_in && f_out, DW_EINVAL, "lbm_step: f_in / f_out is NULL");
   DW_REQUIRE(f_in != f_out, DW_EINVAL, "lbm_step: f_in and f_out must not alias");
-  hipLaunchKernelGGL(k_lbm_step, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, f_in, f_out,
-                     solid, rho_out, u_out);
+  hipLaunchKernelGGL(k_lbm_step, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, f_out, solid,
+                     rho_out, u_out);
   return check_launch("lbm_step");
 }
 
@@ -329,8 +341,8 @@ extern "C" int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, 
   int rc = make_lbm(lat, params, &P);
   if (rc) return rc;
   DW_REQUIRE(f_in && f_out_bar && f_in_bar, DW_EINVAL, "lbm_step_adj: f_in / f_out_bar / f_in_bar is NULL");
-  hipLaunchKernelGGL(k_lbm_step_adj, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, f_in,
-                     solid, f_out_bar, u_out_bar, f_in_bar);
+  hipLaunchKernelGGL(k_lbm_step_adj, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, solid,
+                     f_out_bar, u_out_bar, f_in_bar);
   return check_launch("lbm_step_adj");
 }
 

@@ -16,40 +16,59 @@ namespace dw {
 
 // ------------------------------------------------------------------ sort
 
+// Wave-aggregated keyed atomicAdd: lanes holding equal keys share one
+// global atomic (particles are spatially coherent, so a wave usually holds one
+// or two keys).  Returns base + rank of the lane among the lanes with its key
+// (lane order).  Every lane of the wave must call it.
+__device__ __forceinline__ int wave_keyed_add(int32_t *counters, int key, bool active) {
+  unsigned long long pending = __ballot(active);
+  const int lane = threadIdx.x & 63;
+  int result = 0;
+  while (pending) {
+    int leader = __ffsll((unsigned long long)pending) - 1;
+    int k = __shfl(key, leader, 64);
+    bool mine = active && key == k;
+    unsigned long long same = __ballot(mine);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[k], (int)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if (mine) result = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+    pending &= ~same;
+  }
+  return result;
+}
+
 __global__ void k_sort_keys(GridDev g, const float *__restrict__ x, int n, int32_t *__restrict__ key,
                             int32_t *__restrict__ tile_count, int32_t *__restrict__ node_flag,
                             int32_t *__restrict__ status) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  float X = grid_coord(x[p], g.ox, g.inv_dx);
-  float Y = grid_coord(x[n + p], g.oy, g.inv_dx);
-  float Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
-  if (!(isfinite(X) && isfinite(Y) && isfinite(Z))) {
-    atomicOr(status, DW_STATUS_NONFINITE);
-    key[p] = -1;
-    return;
+  bool live = p < n;
+  int k = -1;
+  int bx = 0, by = 0, bz = 0;
+  if (live) {
+    float X = grid_coord(x[p], g.ox, g.inv_dx);
+    float Y = grid_coord(x[n + p], g.oy, g.inv_dx);
+    float Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
+    const float lim = 1.0e9f;  // guard the float -> int conversion
+    if (!(isfinite(X) && isfinite(Y) && isfinite(Z))) {
+      atomicOr(status, DW_STATUS_NONFINITE);
+    } else if (fabsf(X) > lim || fabsf(Y) > lim || fabsf(Z) > lim) {
+      atomicOr(status, DW_STATUS_OUT_OF_GRID);
+    } else {
+      bx = base_of(X); by = base_of(Y); bz = base_of(Z);
+      if (stencil_inside(g, bx, by, bz)) k = (bx >> 2) + g.tx * ((by >> 2) + g.ty * (bz >> 2));
+      else atomicOr(status, DW_STATUS_OUT_OF_GRID);
+    }
+    key[p] = k;
   }
-  // guard the float -> int conversion before it can overflow
-  const float lim = 1.0e9f;
-  if (fabsf(X) > lim || fabsf(Y) > lim || fabsf(Z) > lim) {
-    atomicOr(status, DW_STATUS_OUT_OF_GRID);
-    key[p] = -1;
-    return;
+  wave_keyed_add(tile_count, k, k >= 0);
+  if (k >= 0) {
+    int tx = bx >> 2, ty = by >> 2, tz = bz >> 2;
+    int ux = (bx + 2) >> 2, uy = (by + 2) >> 2, uz = (bz + 2) >> 2;
+    for (int cz = tz; cz <= uz; ++cz)
+      for (int cy = ty; cy <= uy; ++cy)
+        for (int cx = tx; cx <= ux; ++cx) node_flag[cx + g.tx * (cy + g.ty * cz)] = 1;
   }
-  int bx = base_of(X), by = base_of(Y), bz = base_of(Z);
-  if (!stencil_inside(g, bx, by, bz)) {
-    atomicOr(status, DW_STATUS_OUT_OF_GRID);
-    key[p] = -1;
-    return;
-  }
-  int tx = bx >> 2, ty = by >> 2, tz = bz >> 2;
-  int k = tx + g.tx * (ty + g.ty * tz);
-  key[p] = k;
-  atomicAdd(&tile_count[k], 1);
-  int ux = (bx + 2) >> 2, uy = (by + 2) >> 2, uz = (bz + 2) >> 2;
-  for (int cz = tz; cz <= uz; ++cz)
-    for (int cy = ty; cy <= uy; ++cy)
-      for (int cx = tx; cx <= ux; ++cx) node_flag[cx + g.tx * (cy + g.ty * cz)] = 1;
 }
 
 // wave64 inclusive scan
@@ -90,22 +109,25 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *__res
   int c = i < T ? count[i] : 0;
   int f = i < T ? (flag[i] != 0) : 0;
   int nz = c > 0;
-  int tc, tf, tn;
+  int ch = (c + WORK_CHUNK - 1) / WORK_CHUNK;
+  int tc, tf, tn, th;
   block_excl_scan(c, lds, &tc);
   block_excl_scan(f, lds, &tf);
   block_excl_scan(nz, lds, &tn);
+  block_excl_scan(ch, lds, &th);
   if (threadIdx.x == 0) {
     block_sums[blockIdx.x] = tc;
     block_sums[NB + blockIdx.x] = tf;
     block_sums[2 * NB + blockIdx.x] = tn;
+    block_sums[3 * NB + blockIdx.x] = th;
   }
 }
 
-// single block: exclusive scan of the three block-sum rows, in place; writes totals
+// single block: exclusive scan of the four block-sum rows, in place; writes totals
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int32_t *__restrict__ block_sums, int64_t NB,
-                                                         int32_t *__restrict__ totals /* [3] */) {
+                                                         int32_t *__restrict__ totals /* [4] */) {
   __shared__ int lds[128];
-  for (int r = 0; r < 3; ++r) {
+  for (int r = 0; r < 4; ++r) {
     int carry = 0;
     for (int64_t b0 = 0; b0 < NB; b0 += SCAN_BLOCK) {
       int64_t b = b0 + threadIdx.x;
@@ -120,23 +142,33 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int32_t *__restrict__ b
   }
 }
 
+// Final pass: tile offsets, the compacted active cell / node tile lists and
+// the work items (a cell tile cut into chunks of at most WORK_CHUNK sorted
+// particles: item = (tile, first particle)).
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
     const int32_t *__restrict__ count, const int32_t *__restrict__ flag, int64_t T,
     const int32_t *__restrict__ block_sums, int64_t NB, int32_t *__restrict__ tile_start,
-    int32_t *__restrict__ cell_tiles, int32_t *__restrict__ node_tiles) {
+    int32_t *__restrict__ cell_tiles, int32_t *__restrict__ node_tiles, int32_t *__restrict__ item_tile,
+    int32_t *__restrict__ item_begin) {
   __shared__ int lds[128];
   int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
   int c = i < T ? count[i] : 0;
   int f = i < T ? (flag[i] != 0) : 0;
   int nz = c > 0;
-  int tc, tf, tn;
+  int ch = (c + WORK_CHUNK - 1) / WORK_CHUNK;
+  int tc, tf, tn, th;
   int ec = block_excl_scan(c, lds, &tc) + block_sums[blockIdx.x];
   int ef = block_excl_scan(f, lds, &tf) + block_sums[NB + blockIdx.x];
   int en = block_excl_scan(nz, lds, &tn) + block_sums[2 * NB + blockIdx.x];
+  int eh = block_excl_scan(ch, lds, &th) + block_sums[3 * NB + blockIdx.x];
   if (i < T) {
     tile_start[i] = ec;
     if (nz) cell_tiles[en] = (int)i;
     if (f) node_tiles[ef] = (int)i;
+    for (int q = 0; q < ch; ++q) {
+      item_tile[eh + q] = (int)i;
+      item_begin[eh + q] = ec + q * WORK_CHUNK;
+    }
     if (i == T - 1) tile_start[T] = ec + c;
   }
 }
@@ -144,11 +176,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
 __global__ void k_sort_scatter(const int32_t *__restrict__ key, int n, const int32_t *__restrict__ tile_start,
                                int32_t *__restrict__ cursor, int32_t *__restrict__ perm) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int k = key[p];
-  if (k < 0) return;
-  int pos = tile_start[k] + atomicAdd(&cursor[k], 1);
-  perm[pos] = p;
+  int k = p < n ? key[p] : -1;
+  int r = wave_keyed_add(cursor, k, k >= 0);
+  if (k >= 0) perm[tile_start[k] + r] = p;
 }
 
 // Deterministic mode: sort each tile's segment by particle index (rank by count).
@@ -207,56 +237,73 @@ struct PView {
 
 constexpr int P2G_L = 6;        // local node extent of a cell tile's stencils
 constexpr int P2G_NODES = 216;  // 6^3
+constexpr int P2G_DAT = 16;     // staged floats per particle: f(3), m, m v - A f dx (3), A dx (9)
 
-// One workgroup per active cell tile (persistent over the tile list).  Each
-// thread walks a contiguous run of the tile's particles, accumulating the 27
-// nodes x 4 values in registers while consecutive particles share a stencil
-// base cell, and flushes to the LDS tile with ds_add_f32 when the cell
-// changes.  The LDS tile is then added into the global grid with hardware
-// float atomics (only nodes that received mass).
+// One workgroup (4 waves) per work item -- a chunk of at most WORK_CHUNK
+// sorted particles of one cell tile -- persistent over the item list, so a
+// dense tile is spread over several workgroups.  No float atomics in LDS:
+// Pass A: every thread takes particles of the item, loads their state and
+//   computes the stress (the polar decomposition), the MLS affine matrix A
+//   and the momentum; it stages per particle the fractional position f,
+//   m, q = m v - A f dx and A dx (16 floats, structure of arrays in LDS).
+// Pass B: a 64-bin counting sort in LDS groups the staged particles by cell
+//   and compacts the list of occupied cells.
+// Pass C: a wave takes two occupied cells at a time; in each half-wave lane
+//   o < 27 owns stencil offset o = (ox, oy, oz) of its cell and sums, over
+//   the cell's particles, w_o(f) (m, q + (A dx) o) in four registers.  The
+//   27 lanes of a cell read the same staged particle (an LDS broadcast).
+//   Each (cell, offset) partial sum is stored to LDS.
+// Pass D: the thread owning node n of the 6^3 tile region adds, in a fixed
+//   order, the partials of the occupied cells whose stencil covers n, and
+//   adds the node's total into the global grid with a hardware float atomic
+//   (nodes that received mass only).
 __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int material,
                                              const int32_t *__restrict__ perm,
                                              const int32_t *__restrict__ tile_start,
-                                             const int32_t *__restrict__ cell_tiles,
-                                             const int32_t *__restrict__ n_tiles, float *__restrict__ gm,
+                                             const int32_t *__restrict__ item_tile,
+                                             const int32_t *__restrict__ item_begin,
+                                             const int32_t *__restrict__ n_items, float *__restrict__ gm,
                                              float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status) {
-  __shared__ float s_acc[4][P2G_NODES];
+  __shared__ float s_dat[P2G_DAT][WORK_CHUNK];
+  __shared__ float s_part[64][27][4];
+  __shared__ int s_cnt[64], s_off[64], s_cur[64];
+  __shared__ unsigned char s_act[64];
+  __shared__ int s_nact;
+  __shared__ short s_list[WORK_CHUNK];
+  __shared__ unsigned char s_cell[WORK_CHUNK];
   const int n = P.n;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const float kstress = dt * 4.0f * g.inv_dx * g.inv_dx;
-  int nt = *n_tiles;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
-    int tile = cell_tiles[it];
+  const float dx = g.dx;
+  // per-lane stencil offset and the weight polynomials w_o(f) = a + b f + c f^2
+  const int half = lane >> 5, o = lane & 31;
+  const int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
+  auto coef = [](int oo, float &a, float &b, float &c) {
+    // w0 = (3/2 - f)^2 / 2, w1 = 3/4 - (f - 1)^2, w2 = (f - 1/2)^2 / 2
+    if (oo == 0) { a = 1.125f; b = -1.5f; c = 0.5f; }
+    else if (oo == 1) { a = -0.25f; b = 2.0f; c = -1.0f; }
+    else { a = 0.125f; b = -0.5f; c = 0.5f; }
+  };
+  float ax_, bx_, cx_, ay_, by_, cy_, az_, bz_, cz_;
+  coef(ox, ax_, bx_, cx_);
+  coef(oy, ay_, by_, cy_);
+  coef(oz, az_, bz_, cz_);
+  const float fox = (float)ox, foy = (float)oy, foz = (float)oz;
+  int ni = *n_items;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    int tile = item_tile[it];
+    int b0 = item_begin[it];
+    int nb = min(WORK_CHUNK, tile_start[tile + 1] - b0);
     int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
-    for (int q = threadIdx.x; q < 4 * P2G_NODES; q += blockDim.x) (&s_acc[0][0])[q] = 0.f;
+    if (tid < 64) s_cnt[tid] = 0;
     __syncthreads();
-    int beg = tile_start[tile], end = tile_start[tile + 1];
-    int cnt = end - beg;
-    int per = (cnt + blockDim.x - 1) / blockDim.x;
-    int j0 = beg + threadIdx.x * per;
-    int j1 = min(j0 + per, end);
-    float acc[4][27];
-    int cur = -1;
-    for (int j = j0; j < j1; ++j) {
-      int p = perm[j];
+    // pass A: per-particle quantities into LDS, cell histogram
+    for (int j = tid; j < nb; j += blockDim.x) {
+      int p = perm[b0 + j];
       float X = grid_coord(P.x[p], g.ox, g.inv_dx);
       float Y = grid_coord(P.x[n + p], g.oy, g.inv_dx);
       float Z = grid_coord(P.x[2 * n + p], g.oz, g.inv_dx);
       int bx = base_of(X), by = base_of(Y), bz = base_of(Z);
-      int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
-      if ((unsigned)lx > 3u || (unsigned)ly > 3u || (unsigned)lz > 3u) {
-        atomicOr(status, DW_STATUS_OUT_OF_GRID);
-        continue;
-      }
-      float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
-      float wx[3], wy[3], wz[3];
-      {
-        float a = 1.5f - fx, b = fx - 1.0f, c = fx - 0.5f;
-        wx[0] = 0.5f * a * a; wx[1] = 0.75f - b * b; wx[2] = 0.5f * c * c;
-        a = 1.5f - fy; b = fy - 1.0f; c = fy - 0.5f;
-        wy[0] = 0.5f * a * a; wy[1] = 0.75f - b * b; wy[2] = 0.5f * c * c;
-        a = 1.5f - fz; b = fz - 1.0f; c = fz - 0.5f;
-        wz[0] = 0.5f * a * a; wz[1] = 0.75f - b * b; wz[2] = 0.5f * c * c;
-      }
       float H[9], Cm[9], tau[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -264,71 +311,107 @@ __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int m
         Cm[q] = P.C[q * n + p];
       }
       float m = P.mass[p], V0 = P.vol0[p];
+      float vx = P.v[p], vy = P.v[n + p], vz = P.v[2 * n + p];
       int r = P.region[p];
       float mu, lam;
       lame(P.E[r], P.nu[r], mu, lam);
+      int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
+      unsigned char c = 255;
+      if ((unsigned)lx <= 3u && (unsigned)ly <= 3u && (unsigned)lz <= 3u) {
+        c = (unsigned char)(lx + 4 * (ly + 4 * lz));
+        atomicAdd(&s_cnt[c], 1);
+      } else {
+        atomicOr(status, DW_STATUS_OUT_OF_GRID);
+      }
+      s_cell[j] = c;
       kirchhoff_shift(H, mu, lam, material, tau, status);
+      float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
       float A[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) A[q] = m * Cm[q] - kstress * V0 * tau[q];
-      float mvx = m * P.v[p], mvy = m * P.v[n + p], mvz = m * P.v[2 * n + p];
-      // mv contribution at offset o: w * (m v + A (o - f) dx)
-      float dx = g.dx;
-      float Af0 = -(A[0] * fx + A[1] * fy + A[2] * fz) * dx;
-      float Af1 = -(A[3] * fx + A[4] * fy + A[5] * fz) * dx;
-      float Af2 = -(A[6] * fx + A[7] * fy + A[8] * fz) * dx;
-      int cell = lx + 4 * (ly + 4 * lz);
-      if (cell != cur) {
-        if (cur >= 0) {
-          int cx = cur & 3, cy = (cur >> 2) & 3, cz = cur >> 4;
+      for (int q = 0; q < 9; ++q) A[q] = (m * Cm[q] - kstress * V0 * tau[q]) * dx;
+      s_dat[0][j] = fx;
+      s_dat[1][j] = fy;
+      s_dat[2][j] = fz;
+      s_dat[3][j] = m;
+      s_dat[4][j] = m * vx - (A[0] * fx + A[1] * fy + A[2] * fz);
+      s_dat[5][j] = m * vy - (A[3] * fx + A[4] * fy + A[5] * fz);
+      s_dat[6][j] = m * vz - (A[6] * fx + A[7] * fy + A[8] * fz);
 #pragma unroll
-          for (int o = 0; o < 27; ++o) {
-            int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
-            int li = (cx + ox) + P2G_L * ((cy + oy) + P2G_L * (cz + oz));
-            atomicAdd(&s_acc[0][li], acc[0][o]);
-            atomicAdd(&s_acc[1][li], acc[1][o]);
-            atomicAdd(&s_acc[2][li], acc[2][o]);
-            atomicAdd(&s_acc[3][li], acc[3][o]);
-          }
-        }
-#pragma unroll
-        for (int o = 0; o < 27; ++o) acc[0][o] = acc[1][o] = acc[2][o] = acc[3][o] = 0.f;
-        cur = cell;
-      }
-#pragma unroll
-      for (int o = 0; o < 27; ++o) {
-        int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
-        float w = wx[ox] * wy[oy] * wz[oz];
-        float ddx = (float)ox * dx, ddy = (float)oy * dx, ddz = (float)oz * dx;
-        acc[0][o] += w * m;
-        acc[1][o] += w * (mvx + Af0 + A[0] * ddx + A[1] * ddy + A[2] * ddz);
-        acc[2][o] += w * (mvy + Af1 + A[3] * ddx + A[4] * ddy + A[5] * ddz);
-        acc[3][o] += w * (mvz + Af2 + A[6] * ddx + A[7] * ddy + A[8] * ddz);
-      }
+      for (int q = 0; q < 9; ++q) s_dat[7 + q][j] = A[q];
     }
-    if (cur >= 0) {
-      int cx = cur & 3, cy = (cur >> 2) & 3, cz = cur >> 4;
+    __syncthreads();
+    // pass B: group by cell, compact the occupied cells
+    if (wid == 0) {
+      int v = s_cnt[lane];
+      int inc = v;
 #pragma unroll
-      for (int o = 0; o < 27; ++o) {
-        int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
-        int li = (cx + ox) + P2G_L * ((cy + oy) + P2G_L * (cz + oz));
-        atomicAdd(&s_acc[0][li], acc[0][o]);
-        atomicAdd(&s_acc[1][li], acc[1][o]);
-        atomicAdd(&s_acc[2][li], acc[2][o]);
-        atomicAdd(&s_acc[3][li], acc[3][o]);
+      for (int sh = 1; sh < 64; sh <<= 1) {
+        int t = __shfl_up(inc, sh, 64);
+        if (lane >= sh) inc += t;
+      }
+      s_off[lane] = inc - v;
+      s_cur[lane] = inc - v;
+      unsigned long long occ = __ballot(v > 0);
+      if (v > 0) s_act[__popcll(occ & ((1ull << lane) - 1ull))] = (unsigned char)lane;
+      if (lane == 0) s_nact = (int)__popcll(occ);
+    }
+    __syncthreads();
+    for (int j = tid; j < nb; j += blockDim.x) {
+      unsigned char c = s_cell[j];
+      if (c != 255) s_list[atomicAdd(&s_cur[c], 1)] = (short)j;
+    }
+    __syncthreads();
+    // pass C: (cell, stencil offset) partial sums
+    {
+      const int nact = s_nact;
+      for (int u = wid; 2 * u < nact; u += 4) {
+        int ci = 2 * u + half;
+        int c = -1, cnt = 0, off = 0;
+        if (ci < nact && o < 27) {
+          c = s_act[ci];
+          cnt = s_cnt[c];
+          off = s_off[c];
+        }
+        float am = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        for (int k = 0; k < cnt; ++k) {
+          int j = s_list[off + k];
+          float fx = s_dat[0][j], fy = s_dat[1][j], fz = s_dat[2][j];
+          float w = (ax_ + fx * (bx_ + cx_ * fx)) * (ay_ + fy * (by_ + cy_ * fy)) * (az_ + fz * (bz_ + cz_ * fz));
+          am += w * s_dat[3][j];
+          a0 += w * (s_dat[4][j] + s_dat[7][j] * fox + s_dat[8][j] * foy + s_dat[9][j] * foz);
+          a1 += w * (s_dat[5][j] + s_dat[10][j] * fox + s_dat[11][j] * foy + s_dat[12][j] * foz);
+          a2 += w * (s_dat[6][j] + s_dat[13][j] * fox + s_dat[14][j] * foy + s_dat[15][j] * foz);
+        }
+        if (c >= 0) {
+          s_part[c][o][0] = am;
+          s_part[c][o][1] = a0;
+          s_part[c][o][2] = a1;
+          s_part[c][o][3] = a2;
+        }
       }
     }
     __syncthreads();
-    for (int li = threadIdx.x; li < P2G_NODES; li += blockDim.x) {
-      float mm = s_acc[0][li];
-      if (mm != 0.f) {
-        int ix = li % P2G_L, iy = (li / P2G_L) % P2G_L, iz = li / (P2G_L * P2G_L);
-        int gi = 4 * tx + ix, gj = 4 * ty + iy, gk = 4 * tz + iz;
-        int64_t node = gi + (int64_t)g.nx * (gj + (int64_t)g.ny * gk);
-        atomicAdd(&gm[node], mm);
-        atomicAdd(&gmv[node], s_acc[1][li]);
-        atomicAdd(&gmv[N + node], s_acc[2][li]);
-        atomicAdd(&gmv[2 * N + node], s_acc[3][li]);
+    // pass D: node owners gather the covering cells' partials
+    if (tid < P2G_NODES) {
+      int nx_ = tid % P2G_L, ny_ = (tid / P2G_L) % P2G_L, nz_ = tid / (P2G_L * P2G_L);
+      float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      for (int cz = max(0, nz_ - 2); cz <= min(3, nz_); ++cz)
+        for (int cy = max(0, ny_ - 2); cy <= min(3, ny_); ++cy)
+          for (int cx = max(0, nx_ - 2); cx <= min(3, nx_); ++cx) {
+            int c = cx + 4 * (cy + 4 * cz);
+            if (s_cnt[c] == 0) continue;
+            int oo = (nx_ - cx) + 3 * ((ny_ - cy) + 3 * (nz_ - cz));
+            sm += s_part[c][oo][0];
+            s0 += s_part[c][oo][1];
+            s1 += s_part[c][oo][2];
+            s2 += s_part[c][oo][3];
+          }
+      if (sm != 0.f) {
+        int64_t node = (4 * tx + nx_) + (int64_t)g.nx * ((4 * ty + ny_) + (int64_t)g.ny * (4 * tz + nz_));
+        atomicAdd(&gm[node], sm);
+        atomicAdd(&gmv[node], s0);
+        atomicAdd(&gmv[N + node], s1);
+        atomicAdd(&gmv[2 * N + node], s2);
       }
     }
     __syncthreads();
@@ -491,7 +574,7 @@ int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, cons
                      W.block_sums, NB);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, W.block_sums, NB, W.status + 3);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
-                     W.block_sums, NB, W.tile_start, W.cell_tiles, W.node_tiles);
+                     W.block_sums, NB, W.tile_start, W.cell_tiles, W.node_tiles, W.item_tile, W.item_begin);
   if (n > 0) {
     int32_t *dst = deterministic ? W.perm_tmp : W.perm;
     hipLaunchKernelGGL(k_sort_scatter, dim3(grid_blocks(n, 256)), dim3(256), 0, s, W.key, n, W.tile_start,
@@ -533,16 +616,14 @@ extern "C" int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const d
   rc = bind_workspace(grid, p->n, ws, ws_bytes, &W);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  rc = run_sort(grid, params->deterministic, p->x, p->n, W, s);
-  if (rc) return rc;
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
   hipLaunchKernelGGL(k_grid_clear, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
                      grid_m, grid_mv, N);
   if (p->n > 0)
     hipLaunchKernelGGL(k_p2g, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, make_pview(p), params->dt,
-                       params->material, W.perm, W.tile_start, W.cell_tiles, W.n_cell_tiles, grid_m, grid_mv, N,
-                       W.status);
+                       params->material, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, grid_m,
+                       grid_mv, N, W.status);
   return check_launch("mpm_p2g");
 }
 

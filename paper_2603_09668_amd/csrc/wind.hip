@@ -6,10 +6,16 @@
 
 namespace dw {
 
-__global__ __launch_bounds__(256) void k_wind_to_grid(GridDev g, WindDev w, float *__restrict__ acc, int64_t N) {
-  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  int i = (int)(node % g.nx), j = (int)((node / g.nx) % g.ny), k = (int)(node / ((int64_t)g.nx * g.ny));
+// launch shape: threads along x, one block row per (y, z) line
+constexpr int WIND_BLOCK = 128;
+static dim3 node_grid(const GridDev &g) {
+  return dim3((unsigned)((g.nx + WIND_BLOCK - 1) / WIND_BLOCK), (unsigned)g.ny, (unsigned)g.nz);
+}
+
+__global__ __launch_bounds__(128) void k_wind_to_grid(GridDev g, WindDev w, float *__restrict__ acc, int64_t N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
   float ax, ay, az;
   wind_at_node(w, g, i, j, k, node, ax, ay, az);
   acc[node] = ax;
@@ -60,13 +66,13 @@ __global__ __launch_bounds__(256) void k_force_grid_adj_lds(GridDev g, WindDev w
     if (s[q] != 0.f) atomicAdd(&Wbar[q], s[q]);
 }
 
-__global__ __launch_bounds__(256) void k_force_grid_adj_global(GridDev g, WindDev w, const float *__restrict__ abar,
+__global__ __launch_bounds__(128) void k_force_grid_adj_global(GridDev g, WindDev w, const float *__restrict__ abar,
                                                                int64_t N, float *__restrict__ Wbar) {
-  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
   float bx = abar[node], by = abar[N + node], bz = abar[2 * N + node];
   if (bx == 0.f && by == 0.f && bz == 0.f) return;
-  int i = (int)(node % g.nx), j = (int)((node / g.nx) % g.ny), k = (int)(node / ((int64_t)g.nx * g.ny));
   float px = g.ox + g.dx * (float)i, py = g.oy + g.dx * (float)j, pz = g.oz + g.dx * (float)k;
   float qx = fminf(fmaxf((px - w.lox) * w.sx, 0.f), (float)(w.nwx - 1));
   float qy = fminf(fmaxf((py - w.loy) * w.sy, 0.f), (float)(w.nwy - 1));
@@ -90,13 +96,13 @@ __global__ __launch_bounds__(256) void k_force_grid_adj_global(GridDev g, WindDe
 // Transpose of the drag mode: a = k |U| U, U = s * trilinear(u), so
 // dL/dU = k (|U| abar + U (U . abar) / |U|) and u_bar gets s times its
 // trilinear transpose.
-__global__ __launch_bounds__(256) void k_drag_adj(GridDev g, WindDev w, const float *__restrict__ abar, int64_t N,
+__global__ __launch_bounds__(128) void k_drag_adj(GridDev g, WindDev w, const float *__restrict__ abar, int64_t N,
                                                   float *__restrict__ ubar) {
-  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
   float bx = abar[node], by = abar[N + node], bz = abar[2 * N + node];
   if (bx == 0.f && by == 0.f && bz == 0.f) return;
-  int i = (int)(node % g.nx), j = (int)((node / g.nx) % g.ny), k = (int)(node / ((int64_t)g.nx * g.ny));
   float px = g.ox + g.dx * (float)i, py = g.oy + g.dx * (float)j, pz = g.oz + g.dx * (float)k;
   float qx = (px - w.lox_l) * w.inv_ldx, qy = (py - w.loy_l) * w.inv_ldx, qz = (pz - w.loz_l) * w.inv_ldx;
   if (!(qx >= 0.f && qy >= 0.f && qz >= 0.f && qx <= (float)(w.lnx - 1) && qy <= (float)(w.lny - 1) &&
@@ -143,7 +149,7 @@ extern "C" int wind_to_grid(const dw_grid *grid, const dw_wind *wind, float *acc
   DW_REQUIRE(wd.mode != DW_WIND_ACC || wd.acc != acc, DW_EINVAL, "wind_to_grid: acc aliases the input");
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
-  hipLaunchKernelGGL(k_wind_to_grid, dim3(grid_blocks(N, 256)), dim3(256), 0, (hipStream_t)stream, g, wd, acc, N);
+  hipLaunchKernelGGL(k_wind_to_grid, node_grid(g), dim3(WIND_BLOCK), 0, (hipStream_t)stream, g, wd, acc, N);
   return check_launch("wind_to_grid");
 }
 
@@ -166,11 +172,10 @@ extern "C" int wind_to_grid_adj(const dw_grid *grid, const dw_wind *wind, const 
       if (blocks > 512) blocks = 512;
       hipLaunchKernelGGL(k_force_grid_adj_lds, dim3(blocks), dim3(256), 0, s, g, wd, acc_bar, N, out_bar);
     } else {
-      hipLaunchKernelGGL(k_force_grid_adj_global, dim3(grid_blocks(N, 256)), dim3(256), 0, s, g, wd, acc_bar, N,
-                         out_bar);
+      hipLaunchKernelGGL(k_force_grid_adj_global, node_grid(g), dim3(WIND_BLOCK), 0, s, g, wd, acc_bar, N, out_bar);
     }
   } else {
-    hipLaunchKernelGGL(k_drag_adj, dim3(grid_blocks(N, 256)), dim3(256), 0, s, g, wd, acc_bar, N, out_bar);
+    hipLaunchKernelGGL(k_drag_adj, node_grid(g), dim3(WIND_BLOCK), 0, s, g, wd, acc_bar, N, out_bar);
   }
   return check_launch("wind_to_grid_adj");
 }

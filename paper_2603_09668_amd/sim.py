@@ -1,0 +1,117 @@
+"""Device-resident coupled simulation: one MPM substep driven by a D3Q19 LBM wind.
+
+One coupled step runs, on torch's current stream:
+  1. lbm_solid_from_particles  -- solid mask from the particles (Eq. point2voxel)
+  2. lbm_step                  -- R fused stream-collide steps, velocity output
+  3. mpm_sort                  -- cell-tile grouping of the particles
+  4. mpm_p2g                   -- Eq. P2G with the MLS stress term
+  5. mpm_grid_update           -- gravity, LBM drag wind (Sec. 3.4), walls, pins
+  6. mpm_g2p                   -- Eq. G2P, APIC C, Eq. deformation_update (in place)
+All buffers are allocated once here; a step allocates nothing, and every
+launch has a data-independent shape (persistent kernels read their work
+counts from device memory), so a pair of substeps can be captured once in a
+HIP graph and replayed: `capture()` / `replay()`.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import api
+
+
+class CoupledSim:
+    def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1):
+        self.scene = scene
+        self.device = device
+        self.R = int(lbm_steps_per_substep)
+        g = scene.grid
+        self.grid = api.make_grid(g["nx"], g["ny"], g["nz"], g["dx"], g["origin"])
+        self.N = g["nx"] * g["ny"] * g["nz"]
+        n = scene.n
+        f32 = dict(dtype=torch.float32, device=device)
+        self.p = api.ParticleArrays(
+            x=torch.tensor(np.ascontiguousarray(scene.x.T), **f32),
+            v=torch.zeros(3, n, **f32), C=torch.zeros(9, n, **f32), F=torch.zeros(9, n, **f32),
+            mass=torch.tensor(scene.mass, **f32), vol0=torch.tensor(scene.vol0, **f32),
+            region=torch.tensor(scene.region, dtype=torch.int32, device=device),
+            E=torch.tensor(scene.E, **f32), nu=torch.tensor(scene.nu, **f32))
+        self.ws = api.alloc_workspace(self.grid, n, device)
+        self.gm = torch.zeros(self.N, **f32)
+        self.gmv = torch.zeros(3, self.N, **f32)
+        self.gv = torch.zeros(3, self.N, **f32)
+        self.pin = torch.tensor(scene.pin, dtype=torch.uint8, device=device)
+        self.prm = api.make_mpm_params(scene.dt, scene.gravity, scene.bound, scene.material)
+        lat = scene.lattice
+        self.lat = api.make_lattice(lat["nx"], lat["ny"], lat["nz"], lat["dx"], lat["origin"])
+        self.L = lat["nx"] * lat["ny"] * lat["nz"]
+        lb = scene.lbm
+        self.lbm_kw = dict(tau=lb["tau"], u_in=lb["u_in"], force=lb["force"], bc=lb["bc"], gust_amp=lb["gust_amp"],
+                           gust_period=lb["gust_period"], gust_ky=lb["gust_ky"], gust_kz=lb["gust_kz"],
+                           gust_phase=lb["gust_phase"])
+        self.t = 0
+        # device step counters for the inlet gust, ping-ponged with the populations
+        self.t_a = torch.zeros(1, dtype=torch.int32, device=device)
+        self.t_b = torch.zeros(1, dtype=torch.int32, device=device)
+        self.graph = None
+        self.fa = torch.empty(19, self.L, **f32)
+        self.fb = torch.empty(19, self.L, **f32)
+        api.lbm_equilibrium(self.lat, api.make_lbm_params(**self.lbm_kw), self.fa)
+        self.solid = torch.zeros(self.L, dtype=torch.uint8, device=device)
+        self.u = torch.zeros(3, self.L, **f32)
+        self.wind = api.wind_lbm_drag(self.lat, self.u, scene.wind["vel_scale"], scene.wind["k_drag"])
+
+    # -------------------------------------------------------------- phases
+    def voxelize(self):
+        api.lbm_solid_from_particles(self.lat, self.p.x, self.solid)
+
+    def lbm(self):
+        for _ in range(self.R):
+            prm = api.make_lbm_params(**self.lbm_kw, t_in=self.t_a, t_out=self.t_b)
+            api.lbm_step(self.lat, prm, self.fa, self.fb, self.solid, None, self.u)
+            self.fa, self.fb = self.fb, self.fa
+            self.t_a, self.t_b = self.t_b, self.t_a
+            self.t += 1
+
+    def sort(self):
+        api.mpm_sort(self.grid, self.prm, self.p.x, self.ws)
+
+    def p2g(self):
+        api.mpm_p2g(self.grid, self.prm, self.p, self.gm, self.gmv, self.ws)
+
+    def grid_update(self):
+        api.mpm_grid_update(self.grid, self.prm, self.gm, self.gmv, self.wind, self.pin, self.gv, self.ws)
+
+    def g2p(self):
+        p = self.p
+        api.mpm_g2p(self.grid, self.prm, self.gv, p, p.x, p.v, p.C, p.F)
+
+    PHASES = ("voxelize", "lbm", "sort", "p2g", "grid_update", "g2p")
+
+    def step(self):
+        for ph in self.PHASES:
+            getattr(self, ph)()
+
+    def capture(self, substeps: int = 2):
+        """Record `substeps` coupled substeps (an even number of LBM steps, so
+        the ping-pong buffers return to their roles) in one HIP graph."""
+        if (substeps * self.R) % 2:
+            raise ValueError("capture an even number of LBM steps")
+        t_host = self.t
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            for _ in range(substeps):
+                self.step()
+        self.t = t_host
+        self.graph_substeps = substeps
+
+    def replay(self):
+        self.graph.replay()
+        self.t += self.graph_substeps * self.R
+
+    def status(self) -> int:
+        return api.read_status(self.ws)
+
+    def active_nodes(self) -> int:
+        V = api.workspace_views(self.grid, self.p.n, self.ws)
+        return int(V["n_node_tiles"]) * 64

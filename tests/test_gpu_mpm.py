@@ -75,6 +75,7 @@ def test_p2g_parity(material, scene_name, request):
     gm = torch.zeros(N, device=DEV)
     gmv = torch.zeros(3, N, device=DEV)
     prm = api.make_mpm_params(sc.dt, material=material)
+    api.mpm_sort(g, prm, dev.x, ws)
     api.mpm_p2g(g, prm, dev, gm, gmv, ws)
     torch.cuda.synchronize()
     mu, lam = _mu_lam(st)
@@ -93,6 +94,7 @@ def test_p2g_overwrites_active_tiles(sheet):
     gm = torch.zeros(N, device=DEV)
     gmv = torch.zeros(3, N, device=DEV)
     prm = api.make_mpm_params(sheet.dt)
+    api.mpm_sort(g, prm, dev.x, ws)
     api.mpm_p2g(g, prm, dev, gm, gmv, ws)
     m1, mv1 = gm.clone(), gmv.clone()
     api.mpm_p2g(g, prm, dev, gm, gmv, ws)
@@ -191,6 +193,7 @@ def _gpu_rollout(sc, dev, steps, W=None, nw=None, material=api.FIXED_COROTATED):
     p = dev
     for s in range(steps):
         wind = None if W is None else api.wind_force_grid(W[s * W.shape[0] // steps], nw, (0, 0, 0), (1, 1, 1))
+        api.mpm_sort(g, prm, p.x, ws)
         api.mpm_p2g(g, prm, p, gm, gmv, ws)
         api.mpm_grid_update(g, prm, gm, gmv, wind, pin, gv, ws)
         xo, vo, Co, Fo = (torch.empty_like(p.x), torch.empty_like(p.v), torch.empty_like(p.C), torch.empty_like(p.F))
@@ -235,6 +238,7 @@ def test_rest_state_is_exact(sheet):
     ws = api.alloc_workspace(g, sc.n)
     gm, gmv, gv = torch.zeros(N, device=DEV), torch.zeros(3, N, device=DEV), torch.zeros(3, N, device=DEV)
     prm = api.make_mpm_params(sc.dt, bound=3)
+    api.mpm_sort(g, prm, dev.x, ws)
     api.mpm_p2g(g, prm, dev, gm, gmv, ws)
     api.mpm_grid_update(g, prm, gm, gmv, None, None, gv, ws)
     xo, vo, Co, Fo = (torch.empty_like(dev.x), torch.empty_like(dev.v), torch.empty_like(dev.C),
@@ -282,7 +286,9 @@ def test_out_of_grid_particle_is_flagged(sheet):
     N = sheet.grid["nx"] ** 3
     ws = api.alloc_workspace(g, sheet.n)
     gm, gmv = torch.zeros(N, device=DEV), torch.zeros(3, N, device=DEV)
-    api.mpm_p2g(g, api.make_mpm_params(sheet.dt), dev2, gm, gmv, ws)
+    prm = api.make_mpm_params(sheet.dt)
+    api.mpm_sort(g, prm, dev2.x, ws)
+    api.mpm_p2g(g, prm, dev2, gm, gmv, ws)
     torch.cuda.synchronize()
     assert api.read_status(ws) & api.STATUS_OUT_OF_GRID
     # the other particles are all deposited
@@ -300,6 +306,7 @@ def test_empty_particle_set(sheet):
     p = api.ParticleArrays(e, e.clone(), e9, e9.clone(), z, z.clone(), torch.empty(0, dtype=torch.int32, device=DEV),
                            torch.ones(1, device=DEV), torch.full((1,), 0.3, device=DEV))
     gm, gmv = torch.zeros(N, device=DEV), torch.zeros(3, N, device=DEV)
+    api.mpm_sort(g, api.make_mpm_params(1e-4), p.x, ws)
     api.mpm_p2g(g, api.make_mpm_params(1e-4), p, gm, gmv, ws)
     torch.cuda.synchronize()
     assert gm.abs().max().item() == 0
