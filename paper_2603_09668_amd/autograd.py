@@ -1,0 +1,132 @@
+"""Differentiable MPM rollouts through the hand-written adjoints, with substep
+checkpointing.
+
+The reconstruction of Sec. 3.3 optimises the wind force field F_w (and can
+differentiate the material parameters theta) by gradient descent through the
+simulation S of Eq. simulation_mpm.  `Rollout` runs n substeps of S on the
+device with a force-grid wind (one field per time slot, piecewise constant
+over the substeps) and exposes them to torch as one autograd Function.
+
+Memory: the forward keeps the particle state every `ckpt` substeps only.  The
+backward walks the segments in reverse; for each it re-runs the segment from
+its checkpoint, keeping the per-substep particle states, then for every
+substep (last first) recomputes that substep's grid (sort, P2G, grid update)
+and applies the adjoints in reverse order: G2P adjoint (sorted scatter into
+the grid adjoint), grid-update adjoint, wind transpose into W_bar, P2G adjoint
+(per-particle gather, also giving E_bar).  Every step runs in the library's
+HIP kernels; torch provides device memory, zero-fills and the final loss.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class RolloutPlan:
+    """Device buffers and constants for rollouts of one particle set on one grid."""
+
+    def __init__(self, grid: dict, n: int, mass, vol0, region, nu, pin, dt: float, gravity, material: int,
+                 bound: int, nw, box_lo, box_hi, K: int, n_sub: int, ckpt: int = 16, device="cuda"):
+        self.grid = api.make_grid(grid["nx"], grid["ny"], grid["nz"], grid["dx"], grid["origin"])
+        self.N = grid["nx"] * grid["ny"] * grid["nz"]
+        self.n = n
+        self.mass, self.vol0, self.region, self.nu = mass, vol0, region, nu
+        self.pin = pin
+        self.prm = api.make_mpm_params(dt, gravity, bound, material)
+        self.nw, self.box_lo, self.box_hi, self.K = tuple(nw), tuple(box_lo), tuple(box_hi), K
+        self.n_sub, self.ckpt = n_sub, ckpt
+        f = dict(dtype=torch.float32, device=device)
+        self.ws = api.alloc_workspace(self.grid, n, device)
+        self.gm = torch.zeros(self.N, **f)
+        self.gmv = torch.zeros(3, self.N, **f)
+        self.gv = torch.zeros(3, self.N, **f)
+        self.gvb = torch.zeros(3, self.N, **f)
+        self.gmb = torch.zeros(self.N, **f)
+        self.gmvb = torch.zeros(3, self.N, **f)
+        self.accb = torch.zeros(3, self.N, **f)
+
+    def slot(self, s: int) -> int:
+        return s * self.K // self.n_sub
+
+    def particles(self, x, v, C, H, E):
+        return api.ParticleArrays(x, v, C, H, self.mass, self.vol0, self.region, E, self.nu)
+
+    def wind(self, W, s):
+        return api.wind_force_grid(W[self.slot(s)], self.nw, self.box_lo, self.box_hi)
+
+    # --------------------------------------------------------------- forward
+    def substep(self, p: api.ParticleArrays, W, s: int, out=None):
+        """One substep; in place unless `out` = (x, v, C, H) buffers are given."""
+        api.mpm_sort(self.grid, self.prm, p.x, self.ws)
+        api.mpm_p2g(self.grid, self.prm, p, self.gm, self.gmv, self.ws)
+        api.mpm_grid_update(self.grid, self.prm, self.gm, self.gmv, self.wind(W, s), self.pin, self.gv, self.ws)
+        if out is None:
+            api.mpm_g2p(self.grid, self.prm, self.gv, p, p.x, p.v, p.C, p.F)
+            return p
+        api.mpm_g2p(self.grid, self.prm, self.gv, p, *out)
+        return self.particles(*out, p.E)
+
+    # -------------------------------------------------------------- backward
+    def substep_adjoint(self, p: api.ParticleArrays, W, s: int, bar_out, bar_in, W_bar, E_bar):
+        """Adjoint of substep s at input state p: adds into bar_in = (x, v, C, H)
+        adjoints of the inputs, W_bar and E_bar, given bar_out of the outputs."""
+        g, prm = self.grid, self.prm
+        wind = self.wind(W, s)
+        api.mpm_sort(g, prm, p.x, self.ws)
+        api.mpm_p2g(g, prm, p, self.gm, self.gmv, self.ws)
+        api.mpm_grid_update(g, prm, self.gm, self.gmv, wind, self.pin, self.gv, self.ws)
+        for t in (self.gvb, self.gmb, self.gmvb, self.accb):
+            t.zero_()
+        xb, vb, Cb, Hb = bar_in
+        api.mpm_g2p_adj(g, prm, self.gv, p, *bar_out, x_bar=xb, F_bar=Hb, grid_v_bar=self.gvb, ws=self.ws)
+        api.mpm_grid_update_adj(g, prm, self.gm, self.gmv, wind, self.pin, self.gvb, self.gmb, self.gmvb,
+                                self.accb, self.ws)
+        api.wind_to_grid_adj(g, wind, self.accb, W_bar[self.slot(s)])
+        api.mpm_p2g_adj(g, prm, p, self.gmb, self.gmvb, xb, vb, Cb, Hb, E_bar)
+
+
+class _RolloutFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan: RolloutPlan, W, E, x0, v0, C0, H0):
+        W = W.detach().contiguous()
+        E = E.detach().contiguous()
+        state = [t.detach().clone() for t in (x0, v0, C0, H0)]
+        ckpts = []
+        for s in range(plan.n_sub):
+            if s % plan.ckpt == 0:
+                ckpts.append([t.clone() for t in state])
+            plan.substep(plan.particles(*state, E), W, s)
+        ctx.plan = plan
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(W, E)
+        return tuple(state)
+
+    @staticmethod
+    def backward(ctx, xb, vb, Cb, Hb):
+        plan = ctx.plan
+        W, E = ctx.saved_tensors
+        bar = [torch.zeros_like(t) if b is None else b.contiguous().clone()
+               for b, t in zip((xb, vb, Cb, Hb), ctx.ckpts[0])]
+        W_bar = torch.zeros_like(W)
+        E_bar = torch.zeros_like(E)
+        for seg in reversed(range(len(ctx.ckpts))):
+            s0 = seg * plan.ckpt
+            s1 = min(s0 + plan.ckpt, plan.n_sub)
+            states = [[t.clone() for t in ctx.ckpts[seg]]]
+            for s in range(s0, s1 - 1):
+                nxt = [torch.empty_like(t) for t in states[-1]]
+                plan.substep(plan.particles(*states[-1], E), W, s, out=nxt)
+                states.append(nxt)
+            for s in reversed(range(s0, s1)):
+                st = states[s - s0]
+                bar_in = [torch.zeros_like(t) for t in st]
+                plan.substep_adjoint(plan.particles(*st, E), W, s, bar, bar_in, W_bar, E_bar)
+                bar = bar_in
+        return (None, W_bar, E_bar, *bar)
+
+
+def rollout(plan: RolloutPlan, W, E, x0, v0, C0, H0):
+    """Differentiable n-substep rollout: returns the final (x, v, C, H), with
+    gradients flowing to W (K, 3, nw^3), E (n_regions,) and the initial state."""
+    return _RolloutFn.apply(plan, W, E, x0, v0, C0, H0)
