@@ -97,7 +97,11 @@ typedef struct {
   float gravity[3];  /* body acceleration */
   int bound;         /* separating-slip wall depth in nodes (0 = none) */
   int material;      /* DW_FIXED_COROTATED | DW_NEO_HOOKEAN */
-  int deterministic; /* 1: fixed-order reductions, bit-reproducible P2G */
+  int deterministic; /* 1: fixed-order reductions: the sort orders each tile's
+                        particles by index and P2G sums in a fixed order
+                        without atomics, so sort + P2G + grid update + G2P
+                        are bit-reproducible run to run (needs a workspace
+                        sized with deterministic != 0) */
 } dw_mpm_params;
 
 /* Particle state (x, m, u, C, F) of the appendix five-tuple plus theta:
@@ -166,8 +170,12 @@ const char *dw_last_error(void);
 
 /* Bytes of workspace needed by the MPM calls for this grid and up to n_max
  * particles.  The workspace holds the status word, the cell-tile sort and
- * the active-tile lists; it persists between calls of one substep. */
-size_t mpm_workspace_bytes(const dw_grid *grid, int n_max);
+ * the active-tile lists; it persists between calls of one substep.
+ * deterministic != 0 adds the scratch of the fixed-order P2G (a 6^3 x 4
+ * float partial block per work item: about 3.5 KB x (grid tiles + n/512)).
+ * A deterministic workspace also serves the default mode.  Returns 0 on a
+ * bad grid or n_max < 0. */
+size_t mpm_workspace_bytes(const dw_grid *grid, int n_max, int deterministic);
 
 /* Cell sort (groups particles for the P2G scatter).  Key of particle p =
  * linear index of the 4x4x4 tile holding its stencil base cell

@@ -85,7 +85,7 @@ def lib():
     P = c_void_p
     sig = {
         "dw_last_error": ([], ctypes.c_char_p),
-        "mpm_workspace_bytes": ([POINTER(Grid), c_int], c_size_t),
+        "mpm_workspace_bytes": ([POINTER(Grid), c_int, c_int], c_size_t),
         "mpm_sort": ([POINTER(Grid), POINTER(MPMParams), P, c_int, P, c_size_t, P], c_int),
         "mpm_p2g": ([POINTER(Grid), POINTER(MPMParams), POINTER(Particles), P, P, P, c_size_t, P], c_int),
         "mpm_grid_update": ([POINTER(Grid), POINTER(MPMParams), P, P, POINTER(Wind), P, P, P, c_size_t, P],
@@ -234,12 +234,12 @@ def dw_last_error() -> str:
     return lib().dw_last_error().decode(errors="replace")
 
 
-def mpm_workspace_bytes(grid: Grid, n_max: int) -> int:
-    return int(lib().mpm_workspace_bytes(ctypes.byref(grid), int(n_max)))
+def mpm_workspace_bytes(grid: Grid, n_max: int, deterministic: bool = False) -> int:
+    return int(lib().mpm_workspace_bytes(ctypes.byref(grid), int(n_max), int(bool(deterministic))))
 
 
-def alloc_workspace(grid: Grid, n_max: int, device="cuda") -> torch.Tensor:
-    nb = mpm_workspace_bytes(grid, n_max)
+def alloc_workspace(grid: Grid, n_max: int, device="cuda", deterministic: bool = False) -> torch.Tensor:
+    nb = mpm_workspace_bytes(grid, n_max, deterministic)
     if nb == 0:
         raise DiffWindError(f"mpm_workspace_bytes failed: {dw_last_error()}")
     ws = torch.empty(nb + 256, dtype=torch.uint8, device=device)
@@ -373,6 +373,7 @@ def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
     max_items = T + n // 512 + 1
     take("item_tile", max_items)
     take("item_begin", max_items)
+    take("item_first", T)
     hdr = views["header"]
     views["status"] = hdr[0]
     views["n_sorted"] = hdr[3]

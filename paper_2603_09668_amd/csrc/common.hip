@@ -28,7 +28,7 @@ int check_launch(const char *what) {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base) {
+size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base, int deterministic) {
   GridDev d = make_grid(g);
   int64_t T = (int64_t)d.tx * d.ty * d.tz;
   int64_t NB = (T + SCAN_BLOCK - 1) / SCAN_BLOCK;
@@ -59,16 +59,19 @@ size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base) 
   int64_t max_items = T + (int64_t)n_max / WORK_CHUNK + 1;
   ws->item_tile = take(sizeof(int32_t) * max_items);
   ws->item_begin = take(sizeof(int32_t) * max_items);
+  ws->item_first = take(sizeof(int32_t) * T);
+  // the deterministic scratch ends the layout, so the two sizes share a prefix
+  ws->item_part = deterministic ? (float *)take(sizeof(float) * 4 * 216 * (size_t)max_items) : nullptr;
   ws->n_tiles = T;
   ws->n_scan_blocks = NB;
   ws->bytes = off;
   return off;
 }
 
-int bind_workspace(const dw_grid *g, int n, const void *ws, size_t ws_bytes, Workspace *W) {
+int bind_workspace(const dw_grid *g, int n, const void *ws, size_t ws_bytes, Workspace *W, int deterministic) {
   DW_REQUIRE(ws, DW_EINVAL, "workspace is NULL");
   DW_REQUIRE(((uintptr_t)ws & 255) == 0, DW_EINVAL, "workspace must be 256-byte aligned");
-  size_t need = workspace_layout(g, n, W, const_cast<void *>(ws));
+  size_t need = workspace_layout(g, n, W, const_cast<void *>(ws), deterministic);
   DW_REQUIRE(ws_bytes >= need, DW_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   return DW_OK;
 }
@@ -150,8 +153,8 @@ int check_particles(const dw_particles *p, bool need_state) {
 
 extern "C" const char *dw_last_error(void) { return dw::g_err; }
 
-extern "C" size_t mpm_workspace_bytes(const dw_grid *grid, int n_max) {
+extern "C" size_t mpm_workspace_bytes(const dw_grid *grid, int n_max, int deterministic) {
   if (!grid || n_max < 0 || dw::check_grid(grid) != DW_OK) return 0;
   dw::Workspace ws;
-  return dw::workspace_layout(grid, n_max, &ws, nullptr);
+  return dw::workspace_layout(grid, n_max, &ws, nullptr, deterministic);
 }

@@ -67,6 +67,8 @@ struct Workspace {
   int32_t *n_items;     // work items: chunks of <= WORK_CHUNK particles of one cell tile
   int32_t *item_tile;
   int32_t *item_begin;
+  int32_t *item_first;  // first work item of each cell tile
+  float *item_part;     // deterministic mode: 6^3 x 4 partial node block per work item
   int64_t n_tiles;
   int64_t n_scan_blocks;
   size_t bytes;
@@ -75,11 +77,11 @@ struct Workspace {
 constexpr int SCAN_BLOCK = 1024;
 constexpr int WORK_CHUNK = 512;  // particles per scatter work item
 
-size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base);
+size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base, int deterministic = 0);
 int check_grid(const dw_grid *g);
 int check_particles(const dw_particles *p, bool need_state);
 // binds the workspace and checks its size
-int bind_workspace(const dw_grid *g, int n, const void *ws, size_t ws_bytes, Workspace *W);
+int bind_workspace(const dw_grid *g, int n, const void *ws, size_t ws_bytes, Workspace *W, int deterministic = 0);
 
 // fill kernels (a kernel rather than hipMemsetAsync, so the calls stay
 // capturable in HIP graphs); static: every translation unit launches its own

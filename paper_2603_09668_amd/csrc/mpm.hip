@@ -149,7 +149,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
     const int32_t *__restrict__ count, const int32_t *__restrict__ flag, int64_t T,
     const int32_t *__restrict__ block_sums, int64_t NB, int32_t *__restrict__ tile_start,
     int32_t *__restrict__ cell_tiles, int32_t *__restrict__ node_tiles, int32_t *__restrict__ item_tile,
-    int32_t *__restrict__ item_begin) {
+    int32_t *__restrict__ item_begin, int32_t *__restrict__ item_first) {
   __shared__ int lds[128];
   int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
   int c = i < T ? count[i] : 0;
@@ -163,6 +163,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
   int eh = block_excl_scan(ch, lds, &th) + block_sums[3 * NB + blockIdx.x];
   if (i < T) {
     tile_start[i] = ec;
+    item_first[i] = eh;
     if (nz) cell_tiles[en] = (int)i;
     if (f) node_tiles[ef] = (int)i;
     for (int q = 0; q < ch; ++q) {
@@ -257,13 +258,15 @@ constexpr int P2G_DAT = 16;     // staged floats per particle: f(3), m, m v - A 
 //   order, the partials of the occupied cells whose stencil covers n, and
 //   adds the node's total into the global grid with a hardware float atomic
 //   (nodes that received mass only).
+template <bool DET>
 __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int material,
                                              const int32_t *__restrict__ perm,
                                              const int32_t *__restrict__ tile_start,
                                              const int32_t *__restrict__ item_tile,
                                              const int32_t *__restrict__ item_begin,
                                              const int32_t *__restrict__ n_items, float *__restrict__ gm,
-                                             float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status) {
+                                             float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status,
+                                             float *__restrict__ item_part) {
   __shared__ float s_dat[P2G_DAT][WORK_CHUNK];
   __shared__ float s_part[64][27][4];
   __shared__ int s_cnt[64], s_off[64], s_cur[64];
@@ -358,7 +361,15 @@ __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int m
     __syncthreads();
     for (int j = tid; j < nb; j += blockDim.x) {
       unsigned char c = s_cell[j];
-      if (c != 255) s_list[atomicAdd(&s_cur[c], 1)] = (short)j;
+      if (c == 255) continue;
+      if (DET) {
+        // fixed order: rank among the earlier staged particles of the same cell
+        int rank = 0;
+        for (int q = 0; q < j; ++q) rank += s_cell[q] == c;
+        s_list[s_off[c] + rank] = (short)j;
+      } else {
+        s_list[atomicAdd(&s_cur[c], 1)] = (short)j;
+      }
     }
     __syncthreads();
     // pass C: (cell, stencil offset) partial sums
@@ -406,7 +417,13 @@ __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int m
             s1 += s_part[c][oo][2];
             s2 += s_part[c][oo][3];
           }
-      if (sm != 0.f) {
+      if (DET) {
+        float *dst = item_part + ((int64_t)it * P2G_NODES + tid) * 4;
+        dst[0] = sm;
+        dst[1] = s0;
+        dst[2] = s1;
+        dst[3] = s2;
+      } else if (sm != 0.f) {
         int64_t node = (4 * tx + nx_) + (int64_t)g.nx * ((4 * ty + ny_) + (int64_t)g.ny * (4 * tz + nz_));
         atomicAdd(&gm[node], sm);
         atomicAdd(&gmv[node], s0);
@@ -415,6 +432,55 @@ __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int m
       }
     }
     __syncthreads();
+  }
+}
+
+// Deterministic mode, second pass: every node of an active node tile sums,
+// in a fixed order (cell tile z, y, x, then work item), the partial node
+// blocks of the work items whose 6^3 region covers it, and overwrites the
+// grid.  Bit-reproducible given a deterministic particle order.
+__global__ __launch_bounds__(256) void k_p2g_det_gather(GridDev g, const int32_t *__restrict__ node_tiles,
+                                                        const int32_t *__restrict__ n_tiles,
+                                                        const int32_t *__restrict__ tile_count,
+                                                        const int32_t *__restrict__ item_first,
+                                                        const float *__restrict__ item_part, float *__restrict__ gm,
+                                                        float *__restrict__ gmv, int64_t N) {
+  int nt = *n_tiles;
+  int sub = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int it = blockIdx.x * 4 + sub; it < nt; it += gridDim.x * 4) {
+    int t = node_tiles[it];
+    int tx = t % g.tx, ty = (t / g.tx) % g.ty, tz = t / (g.tx * g.ty);
+    int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    int i = tx * 4 + lx, j = ty * 4 + ly, k = tz * 4 + lz;
+    if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
+    float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int dz = 1; dz >= 0; --dz) {
+      int cz = tz - dz, oz = lz + 4 * dz;
+      if (cz < 0 || oz > 5) continue;
+      for (int dy = 1; dy >= 0; --dy) {
+        int cy = ty - dy, oy = ly + 4 * dy;
+        if (cy < 0 || oy > 5) continue;
+        for (int dxx = 1; dxx >= 0; --dxx) {
+          int cx = tx - dxx, ox = lx + 4 * dxx;
+          if (cx < 0 || ox > 5) continue;
+          int ct = cx + g.tx * (cy + g.ty * cz);
+          int nitem = (tile_count[ct] + WORK_CHUNK - 1) / WORK_CHUNK;
+          int li = ox + P2G_L * (oy + P2G_L * oz);
+          for (int q = 0; q < nitem; ++q) {
+            const float *src = item_part + ((int64_t)(item_first[ct] + q) * P2G_NODES + li) * 4;
+            sm += src[0];
+            s0 += src[1];
+            s1 += src[2];
+            s2 += src[3];
+          }
+        }
+      }
+    }
+    int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    gm[node] = sm;
+    gmv[node] = s0;
+    gmv[N + node] = s1;
+    gmv[2 * N + node] = s2;
   }
 }
 
@@ -574,7 +640,8 @@ int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, cons
                      W.block_sums, NB);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, W.block_sums, NB, W.status + 3);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
-                     W.block_sums, NB, W.tile_start, W.cell_tiles, W.node_tiles, W.item_tile, W.item_begin);
+                     W.block_sums, NB, W.tile_start, W.cell_tiles, W.node_tiles, W.item_tile, W.item_begin,
+                     W.item_first);
   if (n > 0) {
     int32_t *dst = deterministic ? W.perm_tmp : W.perm;
     hipLaunchKernelGGL(k_sort_scatter, dim3(grid_blocks(n, 256)), dim3(256), 0, s, W.key, n, W.tile_start,
@@ -613,17 +680,27 @@ extern "C" int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const d
   if (rc) return rc;
   DW_REQUIRE(grid_m && grid_mv, DW_EINVAL, "mpm_p2g: grid_m / grid_mv is NULL");
   Workspace W;
-  rc = bind_workspace(grid, p->n, ws, ws_bytes, &W);
+  rc = bind_workspace(grid, p->n, ws, ws_bytes, &W, params->deterministic);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  if (params->deterministic) {
+    DW_REQUIRE(W.item_part, DW_EWORKSPACE, "mpm_p2g: deterministic mode needs a deterministic workspace");
+    if (p->n > 0)
+      hipLaunchKernelGGL(k_p2g<true>, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, make_pview(p), params->dt,
+                         params->material, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, grid_m,
+                         grid_mv, N, W.status, W.item_part);
+    hipLaunchKernelGGL(k_p2g_det_gather, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
+                       W.tile_count, W.item_first, W.item_part, grid_m, grid_mv, N);
+    return check_launch("mpm_p2g");
+  }
   hipLaunchKernelGGL(k_grid_clear, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
                      grid_m, grid_mv, N);
   if (p->n > 0)
-    hipLaunchKernelGGL(k_p2g, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, make_pview(p), params->dt,
+    hipLaunchKernelGGL(k_p2g<false>, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, make_pview(p), params->dt,
                        params->material, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, grid_m,
-                       grid_mv, N, W.status);
+                       grid_mv, N, W.status, (float *)nullptr);
   return check_launch("mpm_p2g");
 }
 

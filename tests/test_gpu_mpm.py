@@ -312,3 +312,65 @@ def test_empty_particle_set(sheet):
     assert gm.abs().max().item() == 0
     V = api.workspace_views(g, 0, ws)
     assert int(V["n_cell_tiles"]) == 0 and int(V["n_node_tiles"]) == 0
+
+
+def _det_rollout(sc, steps, deterministic):
+    st, dev = scene_state(sc, seed=31, scale_f=0.01)
+    g = api_grid(sc.grid)
+    N = sc.grid["nx"] * sc.grid["ny"] * sc.grid["nz"]
+    ws = api.alloc_workspace(g, sc.n, deterministic=deterministic)
+    gm, gmv, gv = torch.zeros(N, device=DEV), torch.zeros(3, N, device=DEV), torch.zeros(3, N, device=DEV)
+    prm = api.make_mpm_params(sc.dt, gravity=sc.gravity, bound=3, deterministic=deterministic)
+    pin = torch.as_tensor(sc.pin).to(DEV)
+    p = dev
+    for s in range(steps):
+        api.mpm_sort(g, prm, p.x, ws)
+        api.mpm_p2g(g, prm, p, gm, gmv, ws)
+        api.mpm_grid_update(g, prm, gm, gmv, None, pin, gv, ws)
+        api.mpm_g2p(g, prm, gv, p, p.x, p.v, p.C, p.F)
+    torch.cuda.synchronize()
+    return p, gm, gmv, api.read_status(ws)
+
+
+def test_deterministic_mode_is_bit_reproducible(leaves):
+    say("deterministic rollout x2")
+    a, gma, gmva, sa = _det_rollout(leaves, 20, True)
+    b, gmb, gmvb, sb = _det_rollout(leaves, 20, True)
+    assert sa == 0 and sb == 0
+    for name in ("x", "v", "C", "F"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    assert torch.equal(gma, gmb) and torch.equal(gmva, gmvb)
+    c, gmc, gmvc, _ = _det_rollout(leaves, 20, False)
+    assert rel(vec_from_dev(a.v), vec_from_dev(c.v)) < 1e-5
+
+
+def test_deterministic_p2g_matches_oracle(leaves):
+    say("mpm_p2g deterministic vs oracle")
+    sc = leaves
+    st, dev = scene_state(sc, seed=32)
+    g = api_grid(sc.grid)
+    og = oracle_grid(sc.grid)
+    ws = api.alloc_workspace(g, sc.n, deterministic=True)
+    gm = torch.full((og.n_nodes,), 7.0, device=DEV)  # dirty: active tiles are overwritten
+    gmv = torch.zeros(3, og.n_nodes, device=DEV)
+    prm = api.make_mpm_params(sc.dt, deterministic=True)
+    api.mpm_sort(g, prm, dev.x, ws)
+    api.mpm_p2g(g, prm, dev, gm, gmv, ws)
+    torch.cuda.synchronize()
+    mu, lam = _mu_lam(st)
+    om, omv = ompm.p2g(og, st["x"], st["v"], st["C"], st["F"], st["mass"], st["vol0"], mu, lam, sc.dt,
+                       api.FIXED_COROTATED)
+    V = api.workspace_views(g, sc.n, ws)
+    tiles = V["node_tiles"][:int(V["n_node_tiles"])].cpu().long()
+    # compare on the active node tiles (the rest keeps the dirty value)
+    nx = sc.grid["nx"]
+    T = nx // 4
+    loc = torch.stack(torch.meshgrid(torch.arange(4), torch.arange(4), torch.arange(4), indexing="ij"), -1).reshape(-1, 3)
+    tz, ty, tx = tiles // (T * T), (tiles // T) % T, tiles % T
+    k = (tz[:, None] * 4 + loc[None, :, 0]).reshape(-1)
+    j = (ty[:, None] * 4 + loc[None, :, 1]).reshape(-1)
+    i = (tx[:, None] * 4 + loc[None, :, 2]).reshape(-1)
+    nodes = i + nx * (j + nx * k)
+    assert rel(gm.cpu()[nodes], om[nodes]) < TOL
+    assert rel(gmv.cpu().T[nodes], omv[nodes]) < TOL
+    assert rel(gm.cpu()[nodes].sum(), om.sum()) < 1e-6
