@@ -286,6 +286,78 @@ int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const fl
 int lbm_solid_from_particles(const dw_lattice *lat, const float *x, int n, uint8_t *solid,
                              int accumulate, void *stream);
 
+/* ------------------------------------------------------ wind surrogate */
+
+/* A learned stand-in for k LBM steps (the paper has no learned wind model;
+ * the lattice Boltzmann step of Eq. lbe is its fallback and judge):
+ *   u_{t+k} = u_t + s * net(u_t / s),
+ *   net = conv(32->3) o silu o conv(32->32) o silu o conv(32->32) o silu o conv(3->32),
+ * 3x3x3 kernels with zero padding, s the per-field inflow speed.  Fields are
+ * batches of B lattices of nx * ny * nz voxels (any sizes; multiples of 16 in
+ * x and 4 in y, z fill every tile).  Velocities are float [B][3][L] (as lbm_step writes u); activations
+ * are BF16 (uint16 storage) channels-last [B][L][C] with C = 8 for
+ * 3-channel fields (zero padded) and 32 otherwise; weights are kept in FP32
+ * [cout][cin][27] (tap = 9 dz + 3 dy + dx) and packed to BF16 MFMA fragments
+ * for the kernels; all products accumulate in FP32. */
+enum { DW_CONV_HIDDEN = 0, DW_CONV_OUTPUT = 1, DW_CONV_DGRAD = 2 };
+
+/* Number of BF16 elements of a packed weight buffer for a layer cin -> cout
+ * (as a forward layer; the data-gradient packing of that layer has the size
+ * of conv_packed_weight_elems(cout, cin)). */
+size_t conv_packed_weight_elems(int cin, int cout);
+
+/* Pack FP32 weights w [cout][cin][27] into BF16 fragments.  flip = 0: the
+ * forward layer; flip = 1: its transposed convolution (taps mirrored, cin and
+ * cout exchanged) used for the data gradient.  cin, cout in {3, 32}. */
+int conv_pack_weights(const float *w, int cin, int cout, int flip, uint16_t *wk, void *stream);
+
+/* x0 [B][L][8] = BF16(u [B][3][L] / scale[b]), channels 3..7 zero. */
+int conv_prep_input(int B, int nx, int ny, int nz, const float *u, const float *scale, uint16_t *x0,
+                    void *stream);
+
+/* One convolution layer on MFMA.
+ *  DW_CONV_HIDDEN (cin 3 or 32 -> cout 32): y = BF16(silu(conv(x) + bias)),
+ *     zpre (nullable) = BF16(conv(x) + bias) kept for the backward pass.
+ *  DW_CONV_OUTPUT (32 -> 3): u_out[b][c] = u[b][c] + scale[b] (conv(x) + bias)[c].
+ *  DW_CONV_DGRAD (for the layer cin -> cout, cin = 32): x is the gradient of the
+ *     layer's output pre-activation (channels 8 if cout = 3, else 32), wk the
+ *     flip = 1 packing; y = BF16(conv^T(x) * silu'(zgate)) is the gradient of
+ *     the previous layer's pre-activation (zgate = that layer's zpre). */
+int conv3d_bf16(int B, int nx, int ny, int nz, int cin, int cout, int epilogue, const uint16_t *x,
+                const uint16_t *wk, const float *bias, uint16_t *y, uint16_t *zpre, const uint16_t *zgate,
+                const float *u, const float *scale, float *u_out, void *stream);
+
+/* Floats of scratch that conv3d_bf16_wgrad needs. */
+size_t conv_wgrad_scratch_floats(void);
+
+/* Weight and bias gradients of the layer cin -> cout on MFMA:
+ *   dw[co][ci][tap] = sum over the batch and voxels of dz[v][co] x[v + off(tap)][ci],
+ *   db[co] = sum over voxels of dz[v][co]   (db nullable),
+ * x the layer input (channels 8 if cin = 3, else 32), dz the gradient of the
+ * layer's pre-activation output (channels 8 if cout = 3, else 32).  FP32
+ * results, summed in a fixed order (bit-reproducible); accumulate = 1 adds to
+ * dw, db instead of overwriting. */
+int conv3d_bf16_wgrad(int B, int nx, int ny, int nz, int cin, int cout, const uint16_t *x, const uint16_t *dz,
+                      float *dw, float *db, int accumulate, float *scratch, void *stream);
+
+/* Mean squared error of the scaled increments, mean over b, c, v of
+ * ((u_out - u_tgt) / scale_b)^2, and its gradient with respect to the net
+ * output, written as BF16 dy [B][L][8].  loss_part receives one partial sum
+ * per 256 voxels (their sum is the loss). */
+int conv_mse_grad(int B, int nx, int ny, int nz, const float *u_out, const float *u_tgt, const float *scale,
+                  uint16_t *dy, float *loss_part, void *stream);
+
+/* One Adam step (Kingma & Ba 2015) on n FP32 parameters; step counts from 1. */
+int adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+              int step, void *stream);
+
+/* Checks of velocity fields u [B][3][L]: out[b][0..2] += (sum of squared
+ * central-difference divergence over interior fluid nodes, number of such
+ * nodes, kinetic energy 1/2 sum |u|^2 over fluid nodes); solid [B][L] (one
+ * mask per field, nonzero = solid) or NULL.  out is added to (zero it first);
+ * the order of the float additions is not fixed. */
+int field_stats(int B, int nx, int ny, int nz, const float *u, const uint8_t *solid, float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

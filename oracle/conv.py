@@ -5,9 +5,9 @@ velocity field by k lattice steps in one call and is judged against the LBM
 of Eq. lbe.  Network (fixed by the workload definition): four 3x3x3
 convolutions with zero "same" padding, channels 3 -> 32 -> 32 -> 32 -> 3,
 SiLU after the first three, residual output scaled by the per-sample inflow
-speed s:
+speed s and a fixed output gain g:
 
-    u_{t+k} = u_t + s * net(u_t / s).
+    u_{t+k} = u_t + g s * net(u_t / s).
 
 Layout here is torch's NCDHW (batch, channel, z, y, x).  The convolution is
 ``torch.nn.functional.conv3d`` (a library routine) in float64; its gradients
@@ -19,10 +19,13 @@ Field checks used to accept or reject a surrogate prediction:
   reduced to its RMS over interior fluid nodes;
 * kinetic energy 1/2 sum |u|^2 over fluid nodes.
 
-Pins (tests/test_oracle_conv.py): central finite differences of the loss
-against autograd, a direct 27-tap loop against the library convolution on a
-tiny input, and the divergence of analytic fields (zero for a solenoidal
-field, the closed form for a linear one).
+Training uses Adam (Kingma & Ba 2015) on the mean squared error of the
+scaled increments, mean over (b, c, voxel) of ((u_out - u_tgt) / s_b)^2.
+
+Pins (tests/test_oracle_wind_conv.py): central finite differences of the
+loss against autograd, a direct 27-tap loop against the library convolution
+on a tiny input, the divergence of analytic fields (zero for a solenoidal
+field, the closed form for a linear one), and Adam against torch.optim.Adam.
 """
 from __future__ import annotations
 
@@ -46,10 +49,11 @@ def net(h, weights, biases):
     return h
 
 
-def surrogate_forward(u, weights, biases, scale):
-    """u (B, 3, D, H, W); scale (B,) per-sample inflow speed."""
+def surrogate_forward(u, weights, biases, scale, gain=1.0):
+    """u (B, 3, D, H, W); scale (B,) per-sample inflow speed; the increment
+    is multiplied by the fixed output gain g (u + g s net(u / s))."""
     s = scale.view(-1, 1, 1, 1, 1)
-    return u + net(u / s, weights, biases) * s
+    return u + net(u / s, weights, biases) * (s * gain)
 
 
 def conv3d_direct(x, w, b):
@@ -82,3 +86,19 @@ def kinetic_energy(u, fluid=None):
     if fluid is not None:
         e = e[fluid]
     return e.sum()
+
+
+def increment_mse(u_out, u_tgt, scale):
+    """Mean over (b, c, voxel) of ((u_out - u_tgt) / s_b)^2."""
+    s = scale.view(-1, *([1] * (u_out.dim() - 1)))
+    return (((u_out - u_tgt) / s) ** 2).mean()
+
+
+def adam_step(p, g, m, v, lr, b1, b2, eps, step):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) with bias correction;
+    returns new (p, m, v); step counts from 1."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return p - lr * mh / (torch.sqrt(vh) + eps), m, v

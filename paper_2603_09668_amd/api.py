@@ -31,7 +31,10 @@ SYMBOLS = [
     "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p",
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
     "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_solid_from_particles",
+    "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
+    "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats",
 ]
+CONV_HIDDEN, CONV_OUTPUT, CONV_DGRAD = 0, 1, 2
 
 
 class Grid(ctypes.Structure):
@@ -103,6 +106,15 @@ def lib():
         "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
+        "conv_packed_weight_elems": ([c_int, c_int], c_size_t),
+        "conv_pack_weights": ([P, c_int, c_int, c_int, P, P], c_int),
+        "conv_prep_input": ([c_int, c_int, c_int, c_int, P, P, P, P], c_int),
+        "conv3d_bf16": ([c_int, c_int, c_int, c_int, c_int, c_int, c_int, P, P, P, P, P, P, P, P, P, P], c_int),
+        "conv_wgrad_scratch_floats": ([], c_size_t),
+        "conv3d_bf16_wgrad": ([c_int, c_int, c_int, c_int, c_int, c_int, P, P, P, P, c_int, P, P], c_int),
+        "conv_mse_grad": ([c_int, c_int, c_int, c_int, P, P, P, P, P, P], c_int),
+        "adam_step": ([P, P, P, P, ctypes.c_int64, c_float, c_float, c_float, c_float, c_int, P], c_int),
+        "field_stats": ([c_int, c_int, c_int, c_int, P, P, P, P], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -382,3 +394,63 @@ def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
     views["n_items"] = hdr[6]
     views["n_tiles"] = T
     return views
+
+
+# ---------------------------------------------------------------- surrogate
+# BF16 tensors are torch.bfloat16 on the Python side (uint16 storage in C).
+
+def _bf(t, name):
+    return _ptr(t, torch.bfloat16, name)
+
+
+def conv_packed_weight_elems(cin: int, cout: int) -> int:
+    return int(lib().conv_packed_weight_elems(int(cin), int(cout)))
+
+
+def conv_pack_weights(w, cin, cout, flip, wk):
+    _check(lib().conv_pack_weights(_ptr(w, name="w"), int(cin), int(cout), int(flip), _bf(wk, "wk"), _stream()),
+           "conv_pack_weights")
+
+
+def conv_prep_input(dims, u, scale, x0):
+    B, nx, ny, nz = dims
+    _check(lib().conv_prep_input(B, nx, ny, nz, _ptr(u, name="u"), _ptr(scale, name="scale"), _bf(x0, "x0"),
+                                 _stream()), "conv_prep_input")
+
+
+def conv3d_bf16(dims, cin, cout, epilogue, x, wk, bias=None, y=None, zpre=None, zgate=None, u=None, scale=None,
+                u_out=None):
+    B, nx, ny, nz = dims
+    _check(lib().conv3d_bf16(B, nx, ny, nz, int(cin), int(cout), int(epilogue), _bf(x, "x"), _bf(wk, "wk"),
+                             _ptr(bias, name="bias"), _bf(y, "y"), _bf(zpre, "zpre"), _bf(zgate, "zgate"),
+                             _ptr(u, name="u"), _ptr(scale, name="scale"), _ptr(u_out, name="u_out"), _stream()),
+           "conv3d_bf16")
+
+
+def conv_wgrad_scratch_floats() -> int:
+    return int(lib().conv_wgrad_scratch_floats())
+
+
+def conv3d_bf16_wgrad(dims, cin, cout, x, dz, dw, db, scratch, accumulate=False):
+    B, nx, ny, nz = dims
+    _check(lib().conv3d_bf16_wgrad(B, nx, ny, nz, int(cin), int(cout), _bf(x, "x"), _bf(dz, "dz"),
+                                   _ptr(dw, name="dw"), _ptr(db, name="db"), int(bool(accumulate)),
+                                   _ptr(scratch, name="scratch"), _stream()), "conv3d_bf16_wgrad")
+
+
+def conv_mse_grad(dims, u_out, u_tgt, scale, dy, loss_part):
+    B, nx, ny, nz = dims
+    _check(lib().conv_mse_grad(B, nx, ny, nz, _ptr(u_out, name="u_out"), _ptr(u_tgt, name="u_tgt"),
+                               _ptr(scale, name="scale"), _bf(dy, "dy"), _ptr(loss_part, name="loss_part"),
+                               _stream()), "conv_mse_grad")
+
+
+def adam_step(p, g, m, v, lr, b1, b2, eps, step):
+    _check(lib().adam_step(_ptr(p, name="p"), _ptr(g, name="g"), _ptr(m, name="m"), _ptr(v, name="v"), p.numel(),
+                           float(lr), float(b1), float(b2), float(eps), int(step), _stream()), "adam_step")
+
+
+def field_stats(dims, u, solid, out):
+    B, nx, ny, nz = dims
+    _check(lib().field_stats(B, nx, ny, nz, _ptr(u, name="u"), _ptr(solid, torch.uint8, "solid"),
+                             _ptr(out, name="out"), _stream()), "field_stats")

@@ -1,0 +1,622 @@
+// BF16 MFMA 3x3x3 convolutions of the wind surrogate (gfx950), FP32 accumulation.
+//
+// The surrogate advances a wind velocity field k LBM steps at once:
+//   u_{t+k} = u_t + s * net(u_t / s),  net = conv(32->3) o silu o conv(32->32)
+//   o silu o conv(32->32) o silu o conv(3->32),  3x3x3 kernels, zero padding,
+// s the per-field inflow speed.  It is judged against the lattice Boltzmann
+// step of Eq. lbe.
+//
+// Implicit GEMM per layer: M = output channels (tiles of 16), N = a row of 16
+// voxels along x, K = (tap, input channel).  Activations are channels-last
+// BF16 [B][nz][ny][nx][C] with C padded to 8 (3-channel fields) or 32.  One
+// v_mfma_f32_16x16x32_bf16 consumes K = 32: one tap of 32 channels, or four
+// taps of 8 (padded) channels.  A workgroup (4 waves) stages a zero-padded
+// input patch of 16 x 4 x 4 output voxels (18 x 6 x 6 input voxels) in LDS;
+// the weight fragments of the whole layer stay in registers for the life of
+// the persistent workgroup.  Lane layout of the 16x16x32 MFMA: lane l holds
+// A[l % 16][8 (l / 16) .. +8], B[8 (l / 16) .. +8][l % 16] and
+// D[4 (l / 16) .. +4][l % 16].
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <climits>
+
+#include "dw_internal.h"
+
+namespace dw {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+  float sg = 1.0f / (1.0f + __expf(-z));
+  return sg * (1.0f + z * (1.0f - sg));
+}
+
+constexpr int CT_X = 16, CT_Y = 4, CT_Z = 4;              // output voxels per workgroup tile
+constexpr int PX = CT_X + 2, PY = CT_Y + 2, PZ = CT_Z + 2;  // staged input patch
+
+struct ConvGeom {
+  int B, nx, ny, nz;
+  int64_t L;  // voxels per field
+  int tiles_x, tiles_y, tiles_z;
+  int64_t n_tiles;
+};
+
+// Stage the zero-padded input patch of tile (b, tx, ty, tz) into LDS,
+// layout [z][y][x][CINP] (16-byte vectors of 8 channels).
+template <int CINP>
+__device__ __forceinline__ void stage_patch(const ConvGeom &G, const uint16_t *__restrict__ x, int b, int x0,
+                                            int y0, int z0, uint16_t *s_in) {
+  constexpr int VEC = CINP / 8;
+  constexpr int NV = PZ * PY * PX * VEC;
+  for (int q = threadIdx.x; q < NV; q += blockDim.x) {
+    int v = q % VEC, vox = q / VEC;
+    int xx = vox % PX, yy = (vox / PX) % PY, zz = vox / (PX * PY);
+    int gx = x0 + xx - 1, gy = y0 + yy - 1, gz = z0 + zz - 1;
+    uint4 val = make_uint4(0, 0, 0, 0);
+    if (gx >= 0 && gy >= 0 && gz >= 0 && gx < G.nx && gy < G.ny && gz < G.nz) {
+      int64_t gi = (int64_t)b * G.L + gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz);
+      val = *reinterpret_cast<const uint4 *>(x + gi * CINP + v * 8);
+    }
+    *reinterpret_cast<uint4 *>(s_in + (int64_t)vox * CINP + v * 8) = val;
+  }
+}
+
+// Packed weights: [chunk][COUTP][32] bf16, see conv_pack_weights.
+template <int CINP, int COUTP, int EPI>
+__global__ __launch_bounds__(256) void k_conv(ConvGeom G, const uint16_t *__restrict__ x,
+                                              const uint16_t *__restrict__ wk, const float *__restrict__ bias,
+                                              int cout, uint16_t *__restrict__ y, uint16_t *__restrict__ zpre,
+                                              const uint16_t *__restrict__ zgate, const float *__restrict__ u,
+                                              const float *__restrict__ scale, float *__restrict__ u_out) {
+  constexpr int NCHUNK = CINP == 32 ? 27 : 7;
+  constexpr int MT = COUTP / 16;
+  __shared__ __attribute__((aligned(16))) uint16_t s_in[PZ * PY * PX * CINP];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  // weight fragments for the whole layer, kept in registers
+  bf16x8 wf[NCHUNK][MT];
+#pragma unroll
+  for (int c = 0; c < NCHUNK; ++c)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      wf[c][mt] = *reinterpret_cast<const bf16x8 *>(wk + ((int64_t)(c * COUTP + mt * 16 + r16) * 32 + g * 8));
+  for (int64_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
+    int tx = (int)(t % G.tiles_x);
+    int ty = (int)((t / G.tiles_x) % G.tiles_y);
+    int64_t r = t / ((int64_t)G.tiles_x * G.tiles_y);
+    int tz = (int)(r % G.tiles_z);
+    int b = (int)(r / G.tiles_z);
+    int x0 = tx * CT_X, y0 = ty * CT_Y, z0 = tz * CT_Z;
+    __syncthreads();
+    stage_patch<CINP>(G, x, b, x0, y0, z0, s_in);
+    __syncthreads();
+    // each wave: 4 rows (fixed z, y), two at a time
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+      int rowA = wid * 4 + pr * 2;
+      floatx4 acc[2][MT];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[i][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < NCHUNK; ++c) {
+        int tap, coff;
+        if (CINP == 32) {
+          tap = c;
+          coff = g * 8;
+        } else {
+          tap = 4 * c + g;
+          coff = 0;
+        }
+        bool live = tap < 27;
+        int tt = live ? tap : 0;
+        int dz = tt / 9, dy = (tt / 3) % 3, dxx = tt % 3;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          int row = rowA + i;
+          int ry = row % CT_Y, rz = row / CT_Y;
+          int vox = (r16 + dxx) + PX * ((ry + dy) + PY * (rz + dz));
+          bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(s_in + vox * CINP + coff);
+          if (!live) bfr = bf16x8{};
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[i][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[c][mt], bfr, acc[i][mt], 0, 0, 0);
+        }
+      }
+      // epilogue: lane holds channels mt*16 + 4g + j of voxel r16 of the row
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        int row = rowA + i;
+        int gx = x0 + r16, gy = y0 + row % CT_Y, gz = z0 + row / CT_Y;
+        if (gx >= G.nx || gy >= G.ny || gz >= G.nz) continue;  // ragged edge tile
+        int64_t vi = gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz);
+        int64_t gv = (int64_t)b * G.L + vi;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          int co0 = mt * 16 + 4 * g;
+          if (EPI == DW_CONV_HIDDEN) {
+            uint16_t o[4], zz[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              float zv = acc[i][mt][j] + bias[co0 + j];
+              zz[j] = f2bf(zv);
+              o[j] = f2bf(silu(zv));
+            }
+            uint2 ov = make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+            *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) = ov;
+            if (zpre) {
+              uint2 zvv = make_uint2(zz[0] | ((uint32_t)zz[1] << 16), zz[2] | ((uint32_t)zz[3] << 16));
+              *reinterpret_cast<uint2 *>(zpre + gv * COUTP + co0) = zvv;
+            }
+          } else if (EPI == DW_CONV_OUTPUT) {
+            float sb = scale[b];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              int co = co0 + j;
+              if (co < cout) {
+                int64_t ui = ((int64_t)b * cout + co) * G.L + vi;
+                u_out[ui] = u[ui] + sb * (acc[i][mt][j] + bias[co]);
+              }
+            }
+          } else {  // DW_CONV_DGRAD: gradient through the previous silu
+            uint2 zg = *reinterpret_cast<const uint2 *>(zgate + gv * COUTP + co0);
+            uint16_t zs[4] = {(uint16_t)(zg.x & 0xffff), (uint16_t)(zg.x >> 16), (uint16_t)(zg.y & 0xffff),
+                              (uint16_t)(zg.y >> 16)};
+            uint16_t o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[j] = f2bf(acc[i][mt][j] * silu_grad(bf2f(zs[j])));
+            uint2 ov = make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+            *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) = ov;
+          }
+        }
+      }
+    }
+  }
+}
+
+// u [B][3][L] float -> BF16 channels-last [B][L][8], scaled by 1/scale[b], padded with zeros
+__global__ void k_conv_prep_input(ConvGeom G, const float *__restrict__ u, const float *__restrict__ scale,
+                                  uint16_t *__restrict__ x0) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)G.B * G.L) return;
+  int b = (int)(q / G.L);
+  int64_t v = q - (int64_t)b * G.L;
+  float is = 1.0f / scale[b];
+  uint16_t h[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) h[c] = c < 3 ? f2bf(u[((int64_t)b * 3 + c) * G.L + v] * is) : (uint16_t)0;
+  uint4 val = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                         h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
+  *reinterpret_cast<uint4 *>(x0 + q * 8) = val;
+}
+
+// Pack FP32 weights w[cout][cin][27] (torch layout, tap = 9 dz + 3 dy + dx)
+// into [chunk][COUTP][32] BF16 fragments.  flip != 0 packs the weights of
+// the transposed convolution instead (data gradient): taps mirrored
+// (26 - tap) and the roles of cin and cout exchanged.
+__global__ void k_conv_pack(const float *__restrict__ w, int cin, int cout, int flip, int cinp, int coutp,
+                            uint16_t *__restrict__ wk) {
+  int nchunk = cinp == 32 ? 27 : 7;
+  int64_t total = (int64_t)nchunk * coutp * 32;
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= total) return;
+  int k = (int)(q % 32);
+  int m = (int)((q / 32) % coutp);
+  int c = (int)(q / (32 * coutp));
+  int tap, ci;
+  if (cinp == 32) {
+    tap = c;
+    ci = k;
+  } else {
+    tap = 4 * c + k / 8;
+    ci = k % 8;
+  }
+  // the packed layer maps `cin_l` input channels to `cout_l` outputs
+  int cin_l = flip ? cout : cin, cout_l = flip ? cin : cout;
+  float val = 0.f;
+  if (tap < 27 && ci < cin_l && m < cout_l) {
+    if (flip) val = w[((int64_t)ci * cin + m) * 27 + (26 - tap)];  // w[co = ci][ci = m][mirrored tap]
+    else val = w[((int64_t)m * cin + ci) * 27 + tap];
+  }
+  wk[q] = f2bf(val);
+}
+
+// Weight gradient of one layer on MFMA:
+//   dW[tap][co][ci] = sum over voxels v of dz[v][co] * x[v + off(tap)][ci]
+// (x zero-padded), M = co, K = 32 voxels per MFMA (two rows of 16), N =
+// (dz, dy, ci) of one x-shift dx.  Per tile the output gradient is staged
+// transposed as [co][256 voxels] and, once per dx, the input patch transposed
+// and shifted as [ci][z][y][16 x], so every fragment is one aligned 16-byte
+// LDS read.  Each wave owns a fixed quarter of the (dx, n-tile, m-tile)
+// combinations and accumulates it over all its tiles; the workgroup's partial
+// sums go to part[block][27][COUTP][CINP] and conv_wgrad_reduce adds the
+// blocks in a fixed order.
+template <int CINP, int COUTP>
+__global__ __launch_bounds__(256) void k_conv_wgrad(ConvGeom G, const uint16_t *__restrict__ x,
+                                                    const uint16_t *__restrict__ dz, int zs, int cout,
+                                                    float *__restrict__ part) {
+  constexpr int MT = COUTP / 16;
+  constexpr int NPASS = 9 * CINP;                // n extent per dx pass
+  constexpr int NT = (NPASS + 15) / 16;          // n tiles per pass
+  constexpr int QP = NT * MT;                    // combinations per pass
+  constexpr int NQ = (3 * QP + 3) / 4;           // accumulators per wave
+  __shared__ __attribute__((aligned(16))) uint16_t s_dz[COUTP * 256];
+  __shared__ __attribute__((aligned(16))) uint16_t s_x[CINP * PZ * PY * 16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  floatx4 acc[NQ];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) acc[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
+    int tx = (int)(t % G.tiles_x);
+    int ty = (int)((t / G.tiles_x) % G.tiles_y);
+    int64_t r = t / ((int64_t)G.tiles_x * G.tiles_y);
+    int tz = (int)(r % G.tiles_z);
+    int b = (int)(r / G.tiles_z);
+    int x0 = tx * CT_X, y0 = ty * CT_Y, z0 = tz * CT_Z;
+    __syncthreads();
+    for (int q = threadIdx.x; q < COUTP * 256; q += blockDim.x) {
+      int v = q % 256, co = q / 256;
+      int row = v / 16, xx = v % 16;
+      int gx = x0 + xx, gy = y0 + row % CT_Y, gz = z0 + row / CT_Y;
+      bool in = co < cout && gx < G.nx && gy < G.ny && gz < G.nz;
+      int64_t gv = (int64_t)b * G.L + gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz);
+      s_dz[q] = in ? dz[gv * zs + co] : (uint16_t)0;
+    }
+#pragma unroll 1
+    for (int dx = 0; dx < 3; ++dx) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < CINP * PZ * PY * 16; q += blockDim.x) {
+        int xx = q % 16, yy = (q / 16) % PY, zz = (q / (16 * PY)) % PZ, ci = q / (16 * PY * PZ);
+        int gx = x0 - 1 + dx + xx, gy = y0 - 1 + yy, gz = z0 - 1 + zz;
+        uint16_t val = 0;
+        if (gx >= 0 && gy >= 0 && gz >= 0 && gx < G.nx && gy < G.ny && gz < G.nz)
+          val = x[((int64_t)b * G.L + gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz)) * CINP + ci];
+        s_x[q] = val;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) {
+        int qg = a * 4 + wid;
+        if (qg >= 3 * QP || qg / QP != dx) continue;
+        int qq = qg % QP;
+        int mt = qq % MT, nt = qq / MT;
+        int n = nt * 16 + r16;
+        bool nlive = n < NPASS;
+        int dzdy = nlive ? n / CINP : 0, ci = nlive ? n % CINP : 0;
+        int ddz = dzdy / 3, ddy = dzdy % 3;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          int row = 2 * ks + (g >> 1), xo = 8 * (g & 1);
+          bf16x8 af = *reinterpret_cast<const bf16x8 *>(s_dz + (mt * 16 + r16) * 256 + row * 16 + xo);
+          int rz = row / CT_Y, ry = row % CT_Y;
+          bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(s_x + ((ci * PZ + rz + ddz) * PY + ry + ddy) * 16 + xo);
+          if (!nlive) bfr = bf16x8{};
+          acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[a], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // lane holds D[co = mt*16 + 4g + j][n = nt*16 + r16]
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) {
+    int qg = a * 4 + wid;
+    if (qg >= 3 * QP) continue;
+    int dx = qg / QP, qq = qg % QP;
+    int mt = qq % MT, nt = qq / MT;
+    int n = nt * 16 + r16;
+    if (n >= NPASS) continue;
+    int dzdy = n / CINP, ci = n % CINP;
+    int tap = (dzdy / 3) * 9 + (dzdy % 3) * 3 + dx;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int co = mt * 16 + 4 * g + j;
+      part[(((int64_t)blockIdx.x * 27 + tap) * COUTP + co) * CINP + ci] = acc[a][j];
+    }
+  }
+}
+
+// dW[co][ci][tap] (+)= sum over blocks of part[block][tap][co][ci], fixed order
+__global__ void k_conv_wgrad_reduce(const float *__restrict__ part, int nblocks, int cinp, int coutp, int cin,
+                                    int cout, float *__restrict__ dw, int accumulate) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= cout * cin * 27) return;
+  int tap = q % 27, ci = (q / 27) % cin, co = q / (27 * cin);
+  float s = 0.f;
+  for (int k = 0; k < nblocks; ++k) s += part[(((int64_t)k * 27 + tap) * coutp + co) * cinp + ci];
+  dw[q] = accumulate ? dw[q] + s : s;
+}
+
+// bias gradient: db[c] = sum over voxels of dz[v][c], per-block partials
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ dz, int64_t nvox, int zs, int c,
+                                                   float *__restrict__ part) {
+  __shared__ float red[256];
+  int ch = threadIdx.x % 32, ph = threadIdx.x / 32;
+  float s = 0.f;
+  if (ch < c)
+    for (int64_t v = (int64_t)blockIdx.x * 8 + ph; v < nvox; v += (int64_t)gridDim.x * 8) s += bf2f(dz[v * zs + ch]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    float t = 0.f;
+    for (int k = 0; k < 8; ++k) t += red[k * 32 + threadIdx.x];
+    part[blockIdx.x * 32 + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_bias_grad_reduce(const float *__restrict__ part, int nblocks, int c, float *__restrict__ db,
+                                   int accumulate) {
+  int q = threadIdx.x;
+  if (q >= c) return;
+  float s = 0.f;
+  for (int k = 0; k < nblocks; ++k) s += part[k * 32 + q];
+  db[q] = accumulate ? db[q] + s : s;
+}
+
+// Loss L = mean over b, c, v of ((u_out - u_tgt) / s_b)^2 and its gradient
+// with respect to the net output y (u_out = u + s y): dL/dy = 2 (u_out -
+// u_tgt) / (s_b count), written as BF16 [B][L][8]; per-block loss partials.
+__global__ __launch_bounds__(256) void k_mse_grad(ConvGeom G, const float *__restrict__ u_out,
+                                                  const float *__restrict__ u_tgt, const float *__restrict__ scale,
+                                                  uint16_t *__restrict__ dy, float *__restrict__ loss_part) {
+  __shared__ float red[256];
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  double cnt = 3.0 * (double)G.B * (double)G.L;
+  if (q < (int64_t)G.B * G.L) {
+    int b = (int)(q / G.L);
+    int64_t v = q - (int64_t)b * G.L;
+    float is = 1.0f / scale[b];
+    uint16_t h[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) h[c] = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int64_t ui = ((int64_t)b * 3 + c) * G.L + v;
+      float d = (u_out[ui] - u_tgt[ui]) * is;
+      l += d * d;
+      h[c] = f2bf((float)(2.0 * d / cnt));
+    }
+    uint4 val = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16), 0, 0);
+    *reinterpret_cast<uint4 *>(dy + q * 8) = val;
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = (float)(red[0] / cnt);
+}
+
+// Adam (Kingma & Ba 2015) on FP32 parameters.
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.f - b1) * gi;
+  float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// Per-field checks of a velocity field u [B][3][L]: sum of squared
+// central-difference divergence over interior fluid nodes, their count, and
+// the kinetic energy 1/2 sum |u|^2 over fluid nodes.  out [B][3] is added to
+// (the caller zeroes it).  solid [B][L] (nullable): one mask per field.
+__global__ __launch_bounds__(256) void k_field_stats(ConvGeom G, const float *__restrict__ u,
+                                                     const uint8_t *__restrict__ solid, float *__restrict__ out) {
+  __shared__ float r0[256], r1[256], r2[256];
+  int b = blockIdx.y;
+  float dsum = 0.f, dcnt = 0.f, ke = 0.f;
+  const float *ux = u + (int64_t)b * 3 * G.L, *uy = ux + G.L, *uz = uy + G.L;
+  const uint8_t *sb = solid ? solid + (int64_t)b * G.L : nullptr;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < G.L; v += (int64_t)gridDim.x * blockDim.x) {
+    if (sb && sb[v]) continue;
+    ke += 0.5f * (ux[v] * ux[v] + uy[v] * uy[v] + uz[v] * uz[v]);
+    int i = (int)(v % G.nx), j = (int)((v / G.nx) % G.ny), k = (int)(v / ((int64_t)G.nx * G.ny));
+    if (i > 0 && j > 0 && k > 0 && i < G.nx - 1 && j < G.ny - 1 && k < G.nz - 1) {
+      int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
+      float d = 0.5f * (ux[v + 1] - ux[v - 1] + uy[v + sy] - uy[v - sy] + uz[v + sz] - uz[v - sz]);
+      dsum += d * d;
+      dcnt += 1.f;
+    }
+  }
+  r0[threadIdx.x] = dsum;
+  r1[threadIdx.x] = dcnt;
+  r2[threadIdx.x] = ke;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r0[threadIdx.x] += r0[threadIdx.x + o];
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+      r2[threadIdx.x] += r2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[b * 3 + 0], r0[0]);
+    atomicAdd(&out[b * 3 + 1], r1[0]);
+    atomicAdd(&out[b * 3 + 2], r2[0]);
+  }
+}
+
+static int make_geom(int B, int nx, int ny, int nz, ConvGeom *G) {
+  DW_REQUIRE(B >= 1 && nx >= 1 && ny >= 1 && nz >= 1, DW_EINVAL, "conv: bad field size");
+  DW_REQUIRE(nx <= (1 << 20) && ny <= (1 << 20) && nz <= (1 << 20), DW_ERANGE, "conv: field too large");
+  G->B = B;
+  G->nx = nx;
+  G->ny = ny;
+  G->nz = nz;
+  G->L = (int64_t)nx * ny * nz;
+  DW_REQUIRE(G->L * B * 32 < ((int64_t)1 << 40), DW_ERANGE, "conv: field too large");
+  G->tiles_x = (nx + CT_X - 1) / CT_X;  // edge tiles may be partial
+  G->tiles_y = (ny + CT_Y - 1) / CT_Y;
+  G->tiles_z = (nz + CT_Z - 1) / CT_Z;
+  G->n_tiles = (int64_t)G->tiles_x * G->tiles_y * G->tiles_z * B;
+  return DW_OK;
+}
+
+static unsigned conv_blocks(const ConvGeom &G) {
+  int64_t b = G.n_tiles < 2048 ? G.n_tiles : 2048;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace dw
+
+using namespace dw;
+
+extern "C" int conv_pack_weights(const float *w, int cin, int cout, int flip, uint16_t *wk, void *stream) {
+  DW_REQUIRE(w && wk, DW_EINVAL, "conv_pack_weights: NULL pointer");
+  DW_REQUIRE((cin == 3 || cin == 32) && (cout == 3 || cout == 32), DW_EINVAL,
+             "conv_pack_weights: channels must be 3 or 32");
+  int cin_l = flip ? cout : cin, cout_l = flip ? cin : cout;
+  int cinp = cin_l == 3 ? 8 : 32, coutp = cout_l == 3 ? 16 : 32;
+  int nchunk = cinp == 32 ? 27 : 7;
+  int64_t total = (int64_t)nchunk * coutp * 32;
+  hipLaunchKernelGGL(k_conv_pack, dim3(grid_blocks(total, 256)), dim3(256), 0, (hipStream_t)stream, w, cin, cout,
+                     flip, cinp, coutp, wk);
+  return check_launch("conv_pack_weights");
+}
+
+extern "C" size_t conv_packed_weight_elems(int cin, int cout) {
+  int cinp = cin == 3 ? 8 : 32, coutp = cout == 3 ? 16 : 32;
+  return (size_t)(cinp == 32 ? 27 : 7) * coutp * 32;
+}
+
+extern "C" int conv_prep_input(int B, int nx, int ny, int nz, const float *u, const float *scale, uint16_t *x0,
+                               void *stream) {
+  ConvGeom G;
+  int rc = make_geom(B, nx, ny, nz, &G);
+  if (rc) return rc;
+  DW_REQUIRE(u && scale && x0, DW_EINVAL, "conv_prep_input: NULL pointer");
+  hipLaunchKernelGGL(k_conv_prep_input, dim3(grid_blocks((int64_t)B * G.L, 256)), dim3(256), 0,
+                     (hipStream_t)stream, G, u, scale, x0);
+  return check_launch("conv_prep_input");
+}
+
+extern "C" int conv3d_bf16(int B, int nx, int ny, int nz, int cin, int cout, int epilogue, const uint16_t *x,
+                           const uint16_t *wk, const float *bias, uint16_t *y, uint16_t *zpre, const uint16_t *zgate,
+                           const float *u, const float *scale, float *u_out, void *stream) {
+  ConvGeom G;
+  int rc = make_geom(B, nx, ny, nz, &G);
+  if (rc) return rc;
+  DW_REQUIRE(x && wk, DW_EINVAL, "conv3d_bf16: x / weights NULL");
+  DW_REQUIRE((cin == 3 || cin == 32) && (cout == 3 || cout == 32), DW_EINVAL, "conv3d_bf16: channels 3 or 32");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned nb = conv_blocks(G);
+  if (epilogue == DW_CONV_HIDDEN) {
+    DW_REQUIRE(cout == 32 && bias && y, DW_EINVAL, "conv3d_bf16: hidden layer needs cout 32, bias, y");
+    if (cin == 3)
+      hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, x, wk, bias, cout, y, zpre,
+                         nullptr, nullptr, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, x, wk, bias, cout, y,
+                         zpre, nullptr, nullptr, nullptr, nullptr);
+  } else if (epilogue == DW_CONV_OUTPUT) {
+    DW_REQUIRE(cin == 32 && cout == 3 && bias && u && scale && u_out, DW_EINVAL,
+               "conv3d_bf16: output layer needs 32 -> 3, bias, u, scale, u_out");
+    hipLaunchKernelGGL((k_conv<32, 16, DW_CONV_OUTPUT>), dim3(nb), dim3(256), 0, s, G, x, wk, bias, cout, nullptr,
+                       nullptr, nullptr, u, scale, u_out);
+  } else if (epilogue == DW_CONV_DGRAD) {
+    // transposed convolution of the gradient: input channels = the layer's cout
+    DW_REQUIRE(cin == 32 && y && zgate, DW_EINVAL, "conv3d_bf16: data gradient needs cin 32 (the layer input), y, zgate");
+    if (cout == 3)
+      hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, x, wk, nullptr, 32, y,
+                         nullptr, zgate, nullptr, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, x, wk, nullptr, 32, y,
+                         nullptr, zgate, nullptr, nullptr, nullptr);
+  } else {
+    return set_error(DW_EINVAL, "conv3d_bf16: unknown epilogue %d", epilogue);
+  }
+  return check_launch("conv3d_bf16");
+}
+
+constexpr int WGRAD_BLOCKS = 512;
+constexpr int BGRAD_BLOCKS = 256;
+
+extern "C" size_t conv_wgrad_scratch_floats(void) {
+  return (size_t)WGRAD_BLOCKS * 27 * 32 * 32 + (size_t)BGRAD_BLOCKS * 32;
+}
+
+extern "C" int conv3d_bf16_wgrad(int B, int nx, int ny, int nz, int cin, int cout, const uint16_t *x,
+                                 const uint16_t *dz, float *dw, float *db, int accumulate, float *scratch,
+                                 void *stream) {
+  ConvGeom G;
+  int rc = make_geom(B, nx, ny, nz, &G);
+  if (rc) return rc;
+  DW_REQUIRE(x && dz && dw && scratch, DW_EINVAL, "conv3d_bf16_wgrad: NULL pointer");
+  DW_REQUIRE((cin == 3 || cin == 32) && (cout == 3 || cout == 32), DW_EINVAL, "conv3d_bf16_wgrad: channels");
+  hipStream_t s = (hipStream_t)stream;
+  int cinp = cin == 3 ? 8 : 32, coutp = cout == 3 ? 16 : 32, zs = cout == 3 ? 8 : 32;
+  unsigned nb = (unsigned)(G.n_tiles < WGRAD_BLOCKS ? G.n_tiles : WGRAD_BLOCKS);
+  if (cinp == 8 && coutp == 32)
+    hipLaunchKernelGGL((k_conv_wgrad<8, 32>), dim3(nb), dim3(256), 0, s, G, x, dz, zs, cout, scratch);
+  else if (cinp == 32 && coutp == 32)
+    hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, s, G, x, dz, zs, cout, scratch);
+  else if (cinp == 32 && coutp == 16)
+    hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, s, G, x, dz, zs, cout, scratch);
+  else
+    return set_error(DW_EINVAL, "conv3d_bf16_wgrad: unsupported layer %d -> %d", cin, cout);
+  hipLaunchKernelGGL(k_conv_wgrad_reduce, dim3(grid_blocks((int64_t)cout * cin * 27, 256)), dim3(256), 0, s,
+                     scratch, (int)nb, cinp, coutp, cin, cout, dw, accumulate);
+  if (db) {
+    float *bpart = scratch + (size_t)WGRAD_BLOCKS * 27 * 32 * 32;
+    hipLaunchKernelGGL(k_bias_grad, dim3(BGRAD_BLOCKS), dim3(256), 0, s, dz, (int64_t)B * G.L, zs, cout, bpart);
+    hipLaunchKernelGGL(k_bias_grad_reduce, dim3(1), dim3(32), 0, s, bpart, BGRAD_BLOCKS, cout, db, accumulate);
+  }
+  return check_launch("conv3d_bf16_wgrad");
+}
+
+extern "C" int conv_mse_grad(int B, int nx, int ny, int nz, const float *u_out, const float *u_tgt,
+                             const float *scale, uint16_t *dy, float *loss_part, void *stream) {
+  ConvGeom G;
+  int rc = make_geom(B, nx, ny, nz, &G);
+  if (rc) return rc;
+  DW_REQUIRE(u_out && u_tgt && scale && dy && loss_part, DW_EINVAL, "conv_mse_grad: NULL pointer");
+  hipLaunchKernelGGL(k_mse_grad, dim3(grid_blocks((int64_t)B * G.L, 256)), dim3(256), 0, (hipStream_t)stream, G,
+                     u_out, u_tgt, scale, dy, loss_part);
+  return check_launch("conv_mse_grad");
+}
+
+extern "C" int adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                         float eps, int step, void *stream) {
+  DW_REQUIRE(p && g && m && v && n >= 0 && step >= 1, DW_EINVAL, "adam_step: bad arguments");
+  float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid_blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr, b1, b2,
+                     eps, bc1, bc2);
+  return check_launch("adam_step");
+}
+
+extern "C" int field_stats(int B, int nx, int ny, int nz, const float *u, const uint8_t *solid, float *out,
+                           void *stream) {
+  DW_REQUIRE(B >= 1 && nx >= 1 && ny >= 1 && nz >= 1 && B <= 65535, DW_EINVAL, "field_stats: bad size");
+  DW_REQUIRE(u && out, DW_EINVAL, "field_stats: NULL pointer");
+  ConvGeom G{};
+  G.B = B;
+  G.nx = nx;
+  G.ny = ny;
+  G.nz = nz;
+  G.L = (int64_t)nx * ny * nz;
+  unsigned bx = grid_blocks(G.L, 256);
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_field_stats, dim3(bx, B), dim3(256), 0, (hipStream_t)stream, G, u, solid, out);
+  return check_launch("field_stats");
+}

@@ -126,3 +126,26 @@ def test_divergence_of_analytic_fields():
     u = torch.stack([2 * x, -y, 3 * z])
     assert abs(conv.divergence_rms(u).item() - 4.0) < 1e-13
     assert abs(conv.kinetic_energy(torch.ones(3, 2, 2, 2, dtype=DT)).item() - 12.0) < 1e-15
+
+
+def test_adam_matches_torch_optimizer():
+    """The oracle's Adam step against torch.optim.Adam over several steps."""
+    rng = np.random.default_rng(3)
+    p0 = torch.tensor(rng.standard_normal(50))
+    grads = [torch.tensor(rng.standard_normal(50)) for _ in range(5)]
+    q = p0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([q], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.clone(), torch.zeros(50, dtype=DT), torch.zeros(50, dtype=DT)
+    for k, g in enumerate(grads):
+        q.grad = g.clone()
+        opt.step()
+        p, m, v = conv.adam_step(p, g, m, v, 1e-2, 0.9, 0.999, 1e-8, k + 1)
+    assert (p - q.detach()).abs().max() < 1e-14
+
+
+def test_increment_mse_closed_form():
+    u = torch.zeros(2, 3, 4, dtype=DT)
+    t = torch.ones(2, 3, 4, dtype=DT)
+    s = torch.tensor([1.0, 2.0], dtype=DT)
+    # field 0 contributes 1 per element, field 1 contributes 1/4
+    assert abs(conv.increment_mse(u, t, s).item() - 0.625) < 1e-15
