@@ -10,7 +10,10 @@ and a 128x64x64 D3Q19 lattice with inflow 0.08 and a 5 % seeded gust.
 Prints one JSON line: particle-substeps/s for the whole step, the LBM MLUPS
 of a standalone stream-collide loop, per-phase times from HIP events on the
 launch stream, the roofline of the dominant kernel and the float64 CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  The wind-surrogate
+leg trains the BF16 conv net on 2000 LBM pairs of 64^3 wind tunnels (1800
+train / 200 held out), then reports its held-out wind error against the LBM
+and the speedup of one batched call over the 8 LBM steps it replaces.
 """
 from __future__ import annotations
 
@@ -21,6 +24,8 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+METRIC = "particle-substeps/s, LBM MLUPS; surrogate-vs-LBM speedup at \u22642% wind error"
 
 
 def _args():
@@ -31,8 +36,99 @@ def _args():
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-substeps", type=int, default=3)
+    ap.add_argument("--cpu-substeps", type=int, default=12)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-only", action="store_true", help="run only the wind-surrogate leg (profiling)")
+    ap.add_argument("--sg-rollouts", type=int, default=250)
+    ap.add_argument("--sg-steps", type=int, default=1000)
     return ap.parse_args()
+
+
+def _graph_ms(fn, reps=5):
+    """Average time of fn() captured in a HIP graph, by events on the stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    gph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gph):
+        fn()
+    gph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        gph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _surrogate_leg(n_rollouts, train_steps):
+    """Train the wind surrogate on LBM pairs of 64^3 wind tunnels and compare
+    it with the LBM on held-out fields: error and speed of a batch of 16."""
+    import torch
+    from paper_2603_09668_amd import api, scenes
+    from paper_2603_09668_amd import surrogate as sg
+    dims3 = (64, 64, 64)
+    nx, ny, nz = dims3
+    L = nx * ny * nz
+    t0 = time.perf_counter()
+    U0, U1, S, M = sg.lbm_pairs(n_rollouts, 8, dims=dims3, seed=0)
+    n_train = (n_rollouts - n_rollouts // 10) * 8
+    t_data = time.perf_counter() - t0
+    print(f"[bench] surrogate data: {U0.shape[0]} pairs in {t_data:.1f} s", file=sys.stderr, flush=True)
+    net = sg.Surrogate(seed=0)
+    t0 = time.perf_counter()
+    tr = (U0[:n_train], U1[:n_train], S[:n_train])
+    sg.train(net, *tr, (16, *dims3), steps=int(train_steps * 0.7), batch=16, lr=1e-3, seed=0)
+    sg.train(net, *tr, (16, *dims3), steps=train_steps - int(train_steps * 0.7), batch=16, lr=2e-4, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"[bench] surrogate trained: {train_steps} steps in {t_train:.1f} s", file=sys.stderr, flush=True)
+    H0, H1, HS, HM = U0[n_train:], U1[n_train:], S[n_train:], M[n_train:]
+    errs, errs_id, ok = [], [], []
+    for i in range(0, H0.shape[0], 16):
+        u0, u1, s_, m_ = H0[i:i + 16], H1[i:i + 16], HS[i:i + 16], M[n_train + i:n_train + i + 16]
+        dims = (u0.shape[0], *dims3)
+        out = torch.empty_like(u0)
+        net.forward(u0, s_, out, dims)
+        errs.append(sg.rel_error(out, u1, m_))
+        errs_id.append(sg.rel_error(u0, u1, m_))
+        ok.append(sg.check_fields(u0, out, dims, m_))
+    e, e_id, ok = torch.cat(errs), torch.cat(errs_id), torch.cat(ok)
+    # speed: one call on 16 fields against 16 x 8 LBM steps, both as HIP graphs
+    B = 16
+    ub, sb = U0[:B].contiguous(), S[:B].contiguous()
+    ob = torch.empty_like(ub)
+    t_sur = _graph_ms(lambda: net.forward(ub, sb, ob, (B, *dims3)))
+    spd, solid_np, bc = scenes.wind_tunnel_obstacles(0, dims3)
+    lat = api.make_lattice(nx, ny, nz)
+    solid = torch.tensor(solid_np.reshape(-1), dtype=torch.uint8, device="cuda")
+    kw = dict(tau=0.6, u_in=(spd, 0.0, 0.0), bc=bc)
+    fa = torch.empty(19, L, device="cuda")
+    fb = torch.empty_like(fa)
+    uo = torch.empty(3, L, device="cuda")
+    api.lbm_equilibrium(lat, api.make_lbm_params(**kw), fa)
+    prms = [api.make_lbm_params(**kw, t=j + 1) for j in range(8)]
+
+    def lbm_block():
+        for _ in range(B):
+            for j in range(8):
+                api.lbm_step(lat, prms[j], fa if j % 2 == 0 else fb, fb if j % 2 == 0 else fa, solid, None,
+                             uo if j == 7 else None)
+
+    t_lbm = _graph_ms(lbm_block)
+    flops = 120_960 * L * B
+    tfl = flops / (t_sur * 1e-3) / 1e12
+    return {"speedup": t_lbm / t_sur, "wind_error_mean": e.mean().item(), "wind_error_max": e.max().item(),
+            "persistence_error_mean": e_id.mean().item(), "persistence_error_max": e_id.max().item(),
+            "accepted_by_checks": ok.float().mean().item(), "ms_surrogate_b16": t_sur, "ms_lbm_8steps_b16": t_lbm,
+            "roofline": {"bound": "mfma", "achieved": tfl, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tfl / BF16_PEAK_TFLOPS, "flop_per_voxel": 120_960},
+            "config": {"workload": "64^3 wind tunnels with 1-4 obstacle boxes, inflow 0.02-0.1, tau 0.6; "
+                                   "pairs (u_t, u_t+8), t in [200, 1000]; inference batch 16",
+                       "pairs": int(U0.shape[0]), "train_pairs": n_train, "train_steps": train_steps,
+                       "train_s": t_train, "data_s": t_data}}
 
 
 def _cpu_baseline(scene, substeps):
@@ -82,6 +178,10 @@ def main():
     import torch
     from paper_2603_09668_amd import api, scenes
     from paper_2603_09668_amd.sim import CoupledSim
+
+    if a.surrogate_only:
+        print(json.dumps({"metric": METRIC, "surrogate": _surrogate_leg(a.sg_rollouts, a.sg_steps)}), flush=True)
+        return
 
     scene = scenes.flag_and_leaves_scene(seed=0, n=a.n, res=a.res, lbm_dims=(a.res, a.res // 2, a.res // 2))
     sim = CoupledSim(scene)
@@ -149,7 +249,7 @@ def main():
     dominant = max(phases, key=lambda ph: ph_ms[ph])
     ach = bytes_per.get(dominant, 0) / (ph_ms[dominant] * 1e-3) / 1e9
     out = {
-        "metric": "particle-substeps/s",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-substeps/s",
         "n_gpus": 1,
@@ -174,6 +274,12 @@ def main():
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes": bytes_per.get(dominant)},
     }
+    if not a.no_surrogate:
+        del sim, scratch
+        torch.cuda.empty_cache()
+        sgo = _surrogate_leg(a.sg_rollouts, a.sg_steps)
+        out["surrogate_speedup"] = sgo["speedup"]
+        out["surrogate"] = sgo
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(scene, a.cpu_substeps)
     print(json.dumps(out), flush=True)

@@ -53,134 +53,248 @@ struct ConvGeom {
   int64_t n_tiles;
 };
 
-// Stage the zero-padded input patch of tile (b, tx, ty, tz) into LDS,
-// layout [z][y][x][CINP] (16-byte vectors of 8 channels).
+// ----------------------------------------------------------------- forward
+//
+// Forward / data-gradient layer.  A workgroup (4 waves, 2 resident per CU)
+// owns output tiles of FX x FY x FZ voxels; per tile it copies the
+// zero-padded input patch (FX+2) x (FY+2) x (FZ+2) into LDS with
+// buffer_load ... lds (channels-last, 16-byte chunks of 8 channels), then:
+//  * 32-channel inputs: wave w computes a 4 (y) x RZ (z) block of output
+//    rows for one 16-channel m-tile, holding that m-tile's 27 weight
+//    fragments in registers for the life of the kernel.  For each x-shift
+//    it walks the (RZ+2) x 6 input rows; every fragment read from LDS feeds
+//    up to 9 MFMAs (all (dz, dy) taps that map it onto an output row).
+//  * 8-channel inputs (3 channels padded): K = 32 spans 4 taps; each wave
+//    computes 8 whole rows, all m-tiles, two rows at a time.
+// The 4 chunks of a voxel's 32 channels are stored permuted by swz(x) so the
+// 16 lanes of a fragment read (16 consecutive x) spread over the LDS banks.
+
+constexpr int FX = 16, FY = 4, FZ = 8;                 // output tile
+constexpr int QX = FX + 2, QY = FY + 2, QZ = FZ + 2;   // input patch
+constexpr int QVOX = QX * QY * QZ;
+
+struct FwdTiles {
+  int tx, ty, tz, n;  // tiles per axis, total over the batch
+};
+
+struct TileOrigin {
+  int b, x0, y0, z0;
+};
+__device__ __forceinline__ TileOrigin fwd_tile(const FwdTiles &T, int t) {
+  TileOrigin o;
+  o.x0 = (t % T.tx) * FX;
+  int r = t / T.tx;
+  o.y0 = (r % T.ty) * FY;
+  r /= T.ty;
+  o.z0 = (r % T.tz) * FZ;
+  o.b = r / T.tz;
+  return o;
+}
+
+// chunk c of a patch voxel with x index xx is stored at position c ^ swz(xx)
+__device__ __forceinline__ int swz(int xx) { return ((xx >> 2) & 1) | (xx & 2); }
+
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// Copy the zero-padded input patch of a tile into LDS.  Chunk q of the patch
+// lands at s_in + 16 q (each wave fills 64 consecutive chunks per
+// instruction); voxels outside the field, and chunks past the patch up to the
+// wave's 64, get an offset beyond the buffer's size, which the hardware
+// returns as zeros: s_in must hold the patch rounded up to 64 chunks.
 template <int CINP>
-__device__ __forceinline__ void stage_patch(const ConvGeom &G, const uint16_t *__restrict__ x, int b, int x0,
-                                            int y0, int z0, uint16_t *s_in) {
+__device__ __forceinline__ void stage_patch(const ConvGeom &G, const uint16_t *__restrict__ x,
+                                            const TileOrigin &o, uint16_t *s_in) {
   constexpr int VEC = CINP / 8;
-  constexpr int NV = PZ * PY * PX * VEC;
-  for (int q = threadIdx.x; q < NV; q += blockDim.x) {
-    int v = q % VEC, vox = q / VEC;
-    int xx = vox % PX, yy = (vox / PX) % PY, zz = vox / (PX * PY);
-    int gx = x0 + xx - 1, gy = y0 + yy - 1, gz = z0 + zz - 1;
-    uint4 val = make_uint4(0, 0, 0, 0);
-    if (gx >= 0 && gy >= 0 && gz >= 0 && gx < G.nx && gy < G.ny && gz < G.nz) {
-      int64_t gi = (int64_t)b * G.L + gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz);
-      val = *reinterpret_cast<const uint4 *>(x + gi * CINP + v * 8);
+  constexpr int NV = QVOX * VEC;
+  constexpr int ITER = (NV + 255) / 256;
+  const uint16_t *field = x + (int64_t)o.b * G.L * CINP;
+  __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)field, (short)0, (int)(G.L * CINP * 2), 0x00020000);
+  const int wid = threadIdx.x >> 6;
+  int lane = threadIdx.x & 63;
+  // recompute the per-lane patch coordinates for every tile rather than
+  // keeping ITER x 4 of them live across the tile loop
+  asm volatile("" : "+v"(lane));
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    int q0 = it * 256 + wid * 64;  // first chunk of this wave (uniform)
+    if (q0 >= NV) break;
+    int q = q0 + lane;
+    int v = q / VEC, p = q % VEC;
+    int xx = v % QX, yy = (v / QX) % QY, zz = v / (QX * QY);
+    int c = VEC == 4 ? (p ^ swz(xx)) : p;  // channel chunk stored at position p
+    int gx = o.x0 + xx - 1, gy = o.y0 + yy - 1, gz = o.z0 + zz - 1;
+    bool in = q < NV && gx >= 0 && gy >= 0 && gz >= 0 && gx < G.nx && gy < G.ny && gz < G.nz;
+    unsigned off = in ? (unsigned)(((gx + G.nx * (gy + G.ny * gz)) * CINP + c * 8) * 2) : 0x80000000u;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_ptr_t)(s_in + q0 * 8), 16, off, 0, 0, 0);
+  }
+}
+
+// Epilogue of one output row: lane holds channels co0 .. co0 + 3 of voxel
+// x0 + r16 (acc = those 4 sums).
+template <int COUTP, int EPI>
+__device__ __forceinline__ void conv_epilogue(const ConvGeom &G, const TileOrigin &o, int gy, int gz, int r16,
+                                              int co0, floatx4 acc, const float *s_bias, int cout,
+                                              uint16_t *__restrict__ y, uint16_t *__restrict__ zpre,
+                                              const uint16_t *__restrict__ zgate, const float *__restrict__ u,
+                                              float sb, float *__restrict__ u_out) {
+  int gx = o.x0 + r16;
+  if (gx >= G.nx || gy >= G.ny || gz >= G.nz) return;  // ragged edge tile
+  int64_t vi = gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz);
+  int64_t gv = (int64_t)o.b * G.L + vi;
+  if (EPI == DW_CONV_HIDDEN) {
+    uint16_t ob[4], zz[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float zv = acc[j] + s_bias[co0 + j];
+      zz[j] = f2bf(zv);
+      ob[j] = f2bf(silu(zv));
     }
-    *reinterpret_cast<uint4 *>(s_in + (int64_t)vox * CINP + v * 8) = val;
+    *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) =
+        make_uint2(ob[0] | ((uint32_t)ob[1] << 16), ob[2] | ((uint32_t)ob[3] << 16));
+    if (zpre)
+      *reinterpret_cast<uint2 *>(zpre + gv * COUTP + co0) =
+          make_uint2(zz[0] | ((uint32_t)zz[1] << 16), zz[2] | ((uint32_t)zz[3] << 16));
+  } else if (EPI == DW_CONV_OUTPUT) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int co = co0 + j;
+      if (co < cout) {
+        int64_t ui = ((int64_t)o.b * cout + co) * G.L + vi;
+        u_out[ui] = u[ui] + sb * (acc[j] + s_bias[co]);
+      }
+    }
+  } else {  // DW_CONV_DGRAD: gradient through the previous layer's silu
+    uint2 zg = *reinterpret_cast<const uint2 *>(zgate + gv * COUTP + co0);
+    float zf[4] = {bf2f((uint16_t)(zg.x & 0xffff)), bf2f((uint16_t)(zg.x >> 16)), bf2f((uint16_t)(zg.y & 0xffff)),
+                   bf2f((uint16_t)(zg.y >> 16))};
+    uint16_t ob[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ob[j] = f2bf(acc[j] * silu_grad(zf[j]));
+    *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) =
+        make_uint2(ob[0] | ((uint32_t)ob[1] << 16), ob[2] | ((uint32_t)ob[3] << 16));
   }
 }
 
 // Packed weights: [chunk][COUTP][32] bf16, see conv_pack_weights.
 template <int CINP, int COUTP, int EPI>
-__global__ __launch_bounds__(256) void k_conv(ConvGeom G, const uint16_t *__restrict__ x,
-                                              const uint16_t *__restrict__ wk, const float *__restrict__ bias,
-                                              int cout, uint16_t *__restrict__ y, uint16_t *__restrict__ zpre,
-                                              const uint16_t *__restrict__ zgate, const float *__restrict__ u,
-                                              const float *__restrict__ scale, float *__restrict__ u_out) {
-  constexpr int NCHUNK = CINP == 32 ? 27 : 7;
+__global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const uint16_t *__restrict__ x,
+                                                 const uint16_t *__restrict__ wk, const float *__restrict__ bias,
+                                                 int cout, uint16_t *__restrict__ y, uint16_t *__restrict__ zpre,
+                                                 const uint16_t *__restrict__ zgate, const float *__restrict__ u,
+                                                 const float *__restrict__ scale, float *__restrict__ u_out) {
   constexpr int MT = COUTP / 16;
-  __shared__ __attribute__((aligned(16))) uint16_t s_in[PZ * PY * PX * CINP];
+  constexpr int PATCH = (QVOX * CINP / 8 + 63) / 64 * 64 * 8;  // bf16 elements, whole waves of chunks
+  __shared__ __attribute__((aligned(16))) uint16_t s_in[PATCH];
+  __shared__ float s_bias[32];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  // weight fragments for the whole layer, kept in registers
-  bf16x8 wf[NCHUNK][MT];
+  if (threadIdx.x < 32) s_bias[threadIdx.x] = (bias && (int)threadIdx.x < cout) ? bias[threadIdx.x] : 0.f;
+
+  if constexpr (CINP == 32) {
+    // wave -> (m-tile, z block)
+    constexpr int RZ = MT == 2 ? 4 : 2;
+    const int mt = MT == 2 ? (wid & 1) : 0;
+    const int zb = MT == 2 ? (wid >> 1) * 4 : wid * 2;
+    bf16x8 wf[27];
 #pragma unroll
-  for (int c = 0; c < NCHUNK; ++c)
+    for (int tap = 0; tap < 27; ++tap)
+      wf[tap] = *reinterpret_cast<const bf16x8 *>(wk + ((tap * COUTP + mt * 16 + r16) * 32 + g * 8));
+    for (int t = blockIdx.x; t < T.n; t += gridDim.x) {
+      const TileOrigin o = fwd_tile(T, t);
+      __syncthreads();  // the previous tile's reads of s_in are done
+      stage_patch<CINP>(G, x, o, s_in);
+      __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies have landed
+      __syncthreads();
+      floatx4 acc[RZ][FY];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      wf[c][mt] = *reinterpret_cast<const bf16x8 *>(wk + ((int64_t)(c * COUTP + mt * 16 + r16) * 32 + g * 8));
-  for (int64_t t = blockIdx.x; t < G.n_tiles; t += gridDim.x) {
-    int tx = (int)(t % G.tiles_x);
-    int ty = (int)((t / G.tiles_x) % G.tiles_y);
-    int64_t r = t / ((int64_t)G.tiles_x * G.tiles_y);
-    int tz = (int)(r % G.tiles_z);
-    int b = (int)(r / G.tiles_z);
-    int x0 = tx * CT_X, y0 = ty * CT_Y, z0 = tz * CT_Z;
-    __syncthreads();
-    stage_patch<CINP>(G, x, b, x0, y0, z0, s_in);
-    __syncthreads();
-    // each wave: 4 rows (fixed z, y), two at a time
+      for (int zo = 0; zo < RZ; ++zo)
 #pragma unroll
-    for (int pr = 0; pr < 2; ++pr) {
-      int rowA = wid * 4 + pr * 2;
-      floatx4 acc[2][MT];
+        for (int yo = 0; yo < FY; ++yo) acc[zo][yo] = floatx4{0.f, 0.f, 0.f, 0.f};
+      // lane's fragment offset per x-shift; every read below adds a constant.
+      // The empty asm keeps the compiler from hoisting 108 precomputed
+      // addresses out of the tile loop (which costs 108 registers).
+      int base[3];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int dx = 0; dx < 3; ++dx) base[dx] = (r16 + dx + QX * QY * zb) * 32 + (g ^ swz(r16 + dx)) * 8;
+      asm volatile("" : "+v"(base[0]), "+v"(base[1]), "+v"(base[2]));
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[i][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
-      for (int c = 0; c < NCHUNK; ++c) {
-        int tap, coff;
-        if (CINP == 32) {
-          tap = c;
-          coff = g * 8;
-        } else {
-          tap = 4 * c + g;
-          coff = 0;
-        }
-        bool live = tap < 27;
-        int tt = live ? tap : 0;
-        int dz = tt / 9, dy = (tt / 3) % 3, dxx = tt % 3;
+        for (int zi = 0; zi < RZ + 2; ++zi) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          int row = rowA + i;
-          int ry = row % CT_Y, rz = row / CT_Y;
-          int vox = (r16 + dxx) + PX * ((ry + dy) + PY * (rz + dz));
-          bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(s_in + vox * CINP + coff);
-          if (!live) bfr = bf16x8{};
+          for (int yi = 0; yi < QY; ++yi) {
+            bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(s_in + base[dx] + QX * (yi + QY * zi) * 32);
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-            acc[i][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[c][mt], bfr, acc[i][mt], 0, 0, 0);
-        }
-      }
-      // epilogue: lane holds channels mt*16 + 4g + j of voxel r16 of the row
+            for (int dz = 0; dz < 3; ++dz) {
+              const int zo = zi - dz;
+              if (zo < 0 || zo >= RZ) continue;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        int row = rowA + i;
-        int gx = x0 + r16, gy = y0 + row % CT_Y, gz = z0 + row / CT_Y;
-        if (gx >= G.nx || gy >= G.ny || gz >= G.nz) continue;  // ragged edge tile
-        int64_t vi = gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz);
-        int64_t gv = (int64_t)b * G.L + vi;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          int co0 = mt * 16 + 4 * g;
-          if (EPI == DW_CONV_HIDDEN) {
-            uint16_t o[4], zz[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              float zv = acc[i][mt][j] + bias[co0 + j];
-              zz[j] = f2bf(zv);
-              o[j] = f2bf(silu(zv));
-            }
-            uint2 ov = make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
-            *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) = ov;
-            if (zpre) {
-              uint2 zvv = make_uint2(zz[0] | ((uint32_t)zz[1] << 16), zz[2] | ((uint32_t)zz[3] << 16));
-              *reinterpret_cast<uint2 *>(zpre + gv * COUTP + co0) = zvv;
-            }
-          } else if (EPI == DW_CONV_OUTPUT) {
-            float sb = scale[b];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              int co = co0 + j;
-              if (co < cout) {
-                int64_t ui = ((int64_t)b * cout + co) * G.L + vi;
-                u_out[ui] = u[ui] + sb * (acc[i][mt][j] + bias[co]);
+              for (int dy = 0; dy < 3; ++dy) {
+                const int yo = yi - dy;
+                if (yo < 0 || yo >= FY) continue;
+                acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[9 * dz + 3 * dy + dx], bfr, acc[zo][yo],
+                                                                      0, 0, 0);
               }
             }
-          } else {  // DW_CONV_DGRAD: gradient through the previous silu
-            uint2 zg = *reinterpret_cast<const uint2 *>(zgate + gv * COUTP + co0);
-            uint16_t zs[4] = {(uint16_t)(zg.x & 0xffff), (uint16_t)(zg.x >> 16), (uint16_t)(zg.y & 0xffff),
-                              (uint16_t)(zg.y >> 16)};
-            uint16_t o[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) o[j] = f2bf(acc[i][mt][j] * silu_grad(bf2f(zs[j])));
-            uint2 ov = make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
-            *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) = ov;
           }
+        }
+      }
+      const float sb = EPI == DW_CONV_OUTPUT ? scale[o.b] : 0.f;
+#pragma unroll
+      for (int zo = 0; zo < RZ; ++zo)
+#pragma unroll
+        for (int yo = 0; yo < FY; ++yo)
+          conv_epilogue<COUTP, EPI>(G, o, o.y0 + yo, o.z0 + zb + zo, r16, mt * 16 + 4 * g, acc[zo][yo], s_bias,
+                                    cout, y, zpre, zgate, u, sb, u_out);
+    }
+  } else {
+    // 8-channel input: chunk c covers taps 4c .. 4c + 3 (lane group g: tap 4c + g)
+    bf16x8 wf[7][MT];
+#pragma unroll
+    for (int c = 0; c < 7; ++c)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        wf[c][m] = *reinterpret_cast<const bf16x8 *>(wk + ((c * COUTP + m * 16 + r16) * 32 + g * 8));
+    for (int t = blockIdx.x; t < T.n; t += gridDim.x) {
+      const TileOrigin o = fwd_tile(T, t);
+      __syncthreads();
+      stage_patch<CINP>(G, x, o, s_in);
+      __builtin_amdgcn_s_waitcnt(0x0f70);
+      __syncthreads();
+      const float sb = EPI == DW_CONV_OUTPUT ? scale[o.b] : 0.f;
+#pragma unroll
+      for (int pr = 0; pr < 4; ++pr) {
+        floatx4 acc[2][MT];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int m = 0; m < MT; ++m) acc[i][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          const int tap = 4 * c + g;
+          const bool live = tap < 27;
+          const int tt = live ? tap : 0;
+          const int dz = tt / 9, dy = (tt / 3) % 3, dxx = tt % 3;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int row = wid * 8 + pr * 2 + i;  // row = yo + FY * zo
+            const int yo = row % FY, zo = row / FY;
+            int v = (r16 + dxx) + QX * ((yo + dy) + QY * (zo + dz));
+            bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(s_in + v * 8);
+            if (!live) bfr = bf16x8{};
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+              acc[i][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[c][m], bfr, acc[i][m], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int row = wid * 8 + pr * 2 + i;
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+            conv_epilogue<COUTP, EPI>(G, o, o.y0 + row % FY, o.z0 + row / FY, r16, m * 16 + 4 * g, acc[i][m], s_bias,
+                                      cout, y, zpre, zgate, u, sb, u_out);
         }
       }
     }
@@ -465,7 +579,9 @@ static int make_geom(int B, int nx, int ny, int nz, ConvGeom *G) {
   G->ny = ny;
   G->nz = nz;
   G->L = (int64_t)nx * ny * nz;
-  DW_REQUIRE(G->L * B * 32 < ((int64_t)1 << 40), DW_ERANGE, "conv: field too large");
+  // byte offsets within one field's 32-channel activations fit 31 bits
+  DW_REQUIRE(G->L * 64 < ((int64_t)1 << 31), DW_ERANGE, "conv: field too large (at most 2^25 voxels)");
+  DW_REQUIRE(G->L * B < ((int64_t)1 << 31), DW_ERANGE, "conv: batch too large (at most 2^31 voxels)");
   G->tiles_x = (nx + CT_X - 1) / CT_X;  // edge tiles may be partial
   G->tiles_y = (ny + CT_Y - 1) / CT_Y;
   G->tiles_z = (nz + CT_Z - 1) / CT_Z;
@@ -473,10 +589,17 @@ static int make_geom(int B, int nx, int ny, int nz, ConvGeom *G) {
   return DW_OK;
 }
 
-static unsigned conv_blocks(const ConvGeom &G) {
-  int64_t b = G.n_tiles < 2048 ? G.n_tiles : 2048;
-  return (unsigned)(b < 1 ? 1 : b);
+static FwdTiles fwd_tiles(const ConvGeom &G) {
+  FwdTiles T;
+  T.tx = (G.nx + FX - 1) / FX;
+  T.ty = (G.ny + FY - 1) / FY;
+  T.tz = (G.nz + FZ - 1) / FZ;
+  T.n = T.tx * T.ty * T.tz * G.B;
+  return T;
 }
+
+// persistent grid: two workgroups per CU
+static unsigned fwd_blocks(const FwdTiles &T) { return (unsigned)(T.n < 512 ? T.n : 512); }
 
 }  // namespace dw
 
@@ -520,28 +643,29 @@ extern "C" int conv3d_bf16(int B, int nx, int ny, int nz, int cin, int cout, int
   DW_REQUIRE(x && wk, DW_EINVAL, "conv3d_bf16: x / weights NULL");
   DW_REQUIRE((cin == 3 || cin == 32) && (cout == 3 || cout == 32), DW_EINVAL, "conv3d_bf16: channels 3 or 32");
   hipStream_t s = (hipStream_t)stream;
-  unsigned nb = conv_blocks(G);
+  const FwdTiles T = fwd_tiles(G);
+  const unsigned nb = fwd_blocks(T);
   if (epilogue == DW_CONV_HIDDEN) {
     DW_REQUIRE(cout == 32 && bias && y, DW_EINVAL, "conv3d_bf16: hidden layer needs cout 32, bias, y");
     if (cin == 3)
-      hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, x, wk, bias, cout, y, zpre,
+      hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, T, x, wk, bias, cout, y, zpre,
                          nullptr, nullptr, nullptr, nullptr);
     else
-      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, x, wk, bias, cout, y,
+      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, T, x, wk, bias, cout, y,
                          zpre, nullptr, nullptr, nullptr, nullptr);
   } else if (epilogue == DW_CONV_OUTPUT) {
     DW_REQUIRE(cin == 32 && cout == 3 && bias && u && scale && u_out, DW_EINVAL,
                "conv3d_bf16: output layer needs 32 -> 3, bias, u, scale, u_out");
-    hipLaunchKernelGGL((k_conv<32, 16, DW_CONV_OUTPUT>), dim3(nb), dim3(256), 0, s, G, x, wk, bias, cout, nullptr,
+    hipLaunchKernelGGL((k_conv<32, 16, DW_CONV_OUTPUT>), dim3(nb), dim3(256), 0, s, G, T, x, wk, bias, cout, nullptr,
                        nullptr, nullptr, u, scale, u_out);
   } else if (epilogue == DW_CONV_DGRAD) {
     // transposed convolution of the gradient: input channels = the layer's cout
     DW_REQUIRE(cin == 32 && y && zgate, DW_EINVAL, "conv3d_bf16: data gradient needs cin 32 (the layer input), y, zgate");
     if (cout == 3)
-      hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, x, wk, nullptr, 32, y,
+      hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, T, x, wk, nullptr, 32, y,
                          nullptr, zgate, nullptr, nullptr, nullptr);
     else
-      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, x, wk, nullptr, 32, y,
+      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, T, x, wk, nullptr, 32, y,
                          nullptr, zgate, nullptr, nullptr, nullptr);
   } else {
     return set_error(DW_EINVAL, "conv3d_bf16: unknown epilogue %d", epilogue);

@@ -392,3 +392,96 @@ def test_training_reduces_loss_and_fallback():
         assert not bool(ok[0])
         assert torch.equal(uo[0], ref)
     assert wind.fallbacks == 2
+
+
+def _time_ms(fn, reps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    fn()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        fn()
+    ev[1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / reps
+
+
+def test_surrogate_gain_over_lbm():
+    """What the trained net gains over plain LBM on 64^3 wind tunnels with
+    obstacles: a batch of 16 surrogate calls (8 lattice steps each) is faster
+    than the 16 x 8 LBM steps it replaces, at <= 2 % relative wind error on
+    held-out fields, measured against the library's LBM and, on one field,
+    against the float64 oracle LBM.  Persistence (u_{t+8} = u_t) is printed as
+    the floor the net must beat."""
+    from oracle import lbm as olbm
+    from paper_2603_09668_amd import scenes
+
+    say("surrogate gain 64^3")
+    dims3 = (64, 64, 64)
+    nx, ny, nz = dims3
+    L = nx * ny * nz
+    U0, U1, S, M = sg.lbm_pairs(24, 8, dims=dims3, seed=0)
+    H0, H1, HS, HM = sg.lbm_pairs(4, 4, dims=dims3, seed=99)
+    net = sg.Surrogate(seed=0)
+    sg.train(net, U0, U1, S, (16, *dims3), steps=300, batch=16, lr=1e-3, seed=0)
+    sg.train(net, U0, U1, S, (16, *dims3), steps=200, batch=16, lr=2e-4, seed=1)
+    out = torch.empty_like(H0)
+    net.forward(H0, HS, out, (H0.shape[0], *dims3))
+    e_s = sg.rel_error(out, H1, HM)
+    e_id = sg.rel_error(H0, H1, HM)
+    say(f"  held-out error: surrogate mean {e_s.mean():.4e} max {e_s.max():.4e}; "
+        f"persistence mean {e_id.mean():.4e} max {e_id.max():.4e}")
+    assert e_s.max().item() <= 0.02
+    assert e_s.mean().item() <= e_id.mean().item()
+    assert bool(sg.check_fields(H0, out, (H0.shape[0], *dims3), HM).all())
+
+    # one held-out field against the float64 oracle LBM
+    spd, solid_np, bc = scenes.wind_tunnel_obstacles(7777, dims3)
+    lat = api.make_lattice(nx, ny, nz)
+    solid = torch.tensor(solid_np.reshape(-1), dtype=torch.uint8, device=DEV)
+    kw = dict(tau=0.6, u_in=(spd, 0.0, 0.0), bc=bc)
+    fa = torch.empty(19, L, device=DEV)
+    fb = torch.empty_like(fa)
+    u = torch.empty(3, L, device=DEV)
+    api.lbm_equilibrium(lat, api.make_lbm_params(**kw), fa)
+    t0 = 240
+    for t in range(1, t0 + 1):
+        api.lbm_step(lat, api.make_lbm_params(**kw, t=t), fa, fb, solid, None, u)
+        fa, fb = fb, fa
+    f_t, u_t = fa.clone(), u.clone()
+    for t in range(t0 + 1, t0 + 9):
+        api.lbm_step(lat, api.make_lbm_params(**kw, t=t), fa, fb, solid, None, u)
+        fa, fb = fb, fa
+    u_gpu = u.clone()
+    olat = olbm.Lattice(nx, ny, nz)
+    op = olbm.LBMParams(tau=0.6, u_in=(spd, 0.0, 0.0), bc=bc)
+    f = f_t.double().cpu().view(19, nz, ny, nx) + olbm.W.view(19, 1, 1, 1)
+    sol = torch.tensor(solid_np)
+    for t in range(t0 + 1, t0 + 9):
+        f, _, u_o = olbm.lbm_step(olat, op, f, sol, t)
+    u_ref = u_o.reshape(1, 3, L)
+    fluid = torch.tensor(~solid_np.reshape(1, -1))
+    e_lbm = sg.rel_error(u_gpu.double().cpu().view(1, 3, L), u_ref, ~fluid)
+    u_s = torch.empty(1, 3, L, device=DEV)
+    net.forward(u_t.view(1, 3, L), torch.tensor([spd], device=DEV), u_s, (1, *dims3))
+    e_o = sg.rel_error(u_s.double().cpu(), u_ref, ~fluid)
+    say(f"  vs float64 oracle LBM: library LBM {e_lbm.item():.2e}, surrogate {e_o.item():.4e}")
+    assert e_lbm.item() < 1e-5 and e_o.item() <= 0.02
+
+    # speed: 16 fields, one surrogate call vs 8 LBM steps each
+    B = 16
+    ub = U0[:B].contiguous()
+    ob = torch.empty_like(ub)
+    t_sur = _time_ms(lambda: net.forward(ub, S[:B], ob, (B, *dims3)), 10)
+    prms = [api.make_lbm_params(**kw, t=t) for t in range(8)]
+
+    def lbm16():
+        a, b = fa, fb
+        for _ in range(B):
+            for j in range(8):
+                api.lbm_step(lat, prms[j], a, b, solid, None, u if j == 7 else None)
+                a, b = b, a
+
+    t_lbm = _time_ms(lbm16, 3)
+    say(f"  16 fields: surrogate {t_sur:.3f} ms, 8 LBM steps {t_lbm:.3f} ms, speedup {t_lbm / t_sur:.2f}x")
+    assert t_sur < t_lbm
