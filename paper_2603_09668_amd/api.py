@@ -356,6 +356,9 @@ def lbm_solid_from_particles(lat: Lattice, x, solid, accumulate=False):
            "lbm_solid_from_particles")
 
 
+WORK_CHUNK = 512  # particles per scatter work item (the library's constant)
+
+
 def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
     """Read-only views of the sort results inside an MPM workspace (same layout
     as the library's): status, tile counts, tile ranges, active tile lists,
@@ -382,7 +385,7 @@ def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
     take("key", n)
     take("perm", n)
     take("perm_tmp", n)
-    max_items = T + n // 512 + 1
+    max_items = T + n // WORK_CHUNK + 1
     take("item_tile", max_items)
     take("item_begin", max_items)
     take("item_first", T)

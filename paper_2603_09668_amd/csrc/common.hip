@@ -40,7 +40,7 @@ size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base, 
     return (int32_t *)p;
   };
   int32_t *hdr = take(256);
-  // hdr[0] status; hdr[3..6] scan totals: sorted particles, active node
+  // hdr[0] status; hdr[8..9] P2G work-item tickets; hdr[3..6] scan totals: sorted particles, active node
   // tiles, active cell tiles, work items
   ws->status = hdr;
   ws->n_node_tiles = hdr ? hdr + 4 : nullptr;

@@ -239,113 +239,148 @@ struct PView {
 constexpr int P2G_L = 6;        // local node extent of a cell tile's stencils
 constexpr int P2G_NODES = 216;  // 6^3
 constexpr int P2G_DAT = 16;     // staged floats per particle: f(3), m, m v - A f dx (3), A dx (9)
+constexpr int P2G_UNIT = 64;    // particles per pass-C unit (16 MFMA steps)
+constexpr int P2G_MAX_UNITS = 64 + WORK_CHUNK / P2G_UNIT;  // bounds the sum over cells of ceil(count / unit)
+constexpr int P2G_THREADS = WORK_CHUNK;
+constexpr int P2G_WAVES = P2G_THREADS / 64;
+constexpr int P2G_PER_CU = 1024 / P2G_THREADS;  // resident workgroups per compute unit
 
-// One workgroup (4 waves) per work item -- a chunk of at most WORK_CHUNK
-// sorted particles of one cell tile -- persistent over the item list, so a
-// dense tile is spread over several workgroups.  No float atomics in LDS:
-// Pass A: every thread takes particles of the item, loads their state and
-//   computes the stress (the polar decomposition), the MLS affine matrix A
-//   and the momentum; it stages per particle the fractional position f,
-//   m, q = m v - A f dx and A dx (16 floats, structure of arrays in LDS).
-// Pass B: a 64-bin counting sort in LDS groups the staged particles by cell
-//   and compacts the list of occupied cells.
-// Pass C: a wave takes two occupied cells at a time; in each half-wave lane
-//   o < 27 owns stencil offset o = (ox, oy, oz) of its cell and sums, over
-//   the cell's particles, w_o(f) (m, q + (A dx) o) in four registers.  The
-//   27 lanes of a cell read the same staged particle (an LDS broadcast).
-//   Each (cell, offset) partial sum is stored to LDS.
-// Pass D: the thread owning node n of the 6^3 tile region adds, in a fixed
-//   order, the partials of the occupied cells whose stencil covers n, and
-//   adds the node's total into the global grid with a hardware float atomic
-//   (nodes that received mass only).
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// Stencil weight polynomial of offset component oo: w = a + b f + c f^2,
+// w0 = (3/2 - f)^2 / 2, w1 = 3/4 - (f - 1)^2, w2 = (f - 1/2)^2 / 2.
+__device__ __forceinline__ void p2g_coef(int oo, float &a, float &b, float &c) {
+  if (oo == 0) { a = 1.125f; b = -1.5f; c = 0.5f; }
+  else if (oo == 1) { a = -0.25f; b = 2.0f; c = -1.0f; }
+  else { a = 0.125f; b = -0.5f; c = 0.5f; }
+}
+
+// One workgroup (8 waves) per work item -- a chunk of at most WORK_CHUNK
+// sorted particles of one cell tile, so a dense tile is spread over several
+// workgroups.  The grid is as many workgroups as fit at once; each draws
+// items from a ticket counter until the list is done.  No float atomics in LDS:
+// Pass A1: thread j takes the item's particle j, finds its cell in the tile
+//   (LDS histogram) and issues the loads of the rest of its state.
+// Pass B: exclusive scan of the 64 cell counts; each cell is cut into units
+//   of at most P2G_UNIT particles.
+// Pass A2: the thread computes the stress (the polar decomposition), the
+//   MLS affine matrix A and the momentum and stages, at its particle's slot
+//   in cell order, f, m, q = m v - A f dx and A dx (16 floats, structure of
+//   arrays in LDS).
+// Pass C: per unit, one wave forms on the matrix cores (fp32 MFMA 16x16x4)
+//   the product Feat (13 x n) W (n x 27): Feat holds m, q and A dx of the
+//   unit's particles, W their 27 stencil weights w_o(f); four particles per
+//   MFMA, offsets in two 16-column tiles.  For offset o = (ox, oy, oz) the
+//   node contribution (sum w m, sum w q + (sum w A dx) o) is a linear
+//   combination of the 13 sums; the rows are ordered so that the four rows a
+//   lane holds give one node value, (1, ox, oy, oz) . rows.  The 27 x 4
+//   results go to distinct entries of the wave's own 6^3 node block in LDS
+//   (plain adds).
+// Pass D: the thread owning node n of the 6^3 region adds the 8 wave blocks
+//   in a fixed order and adds the total into the global grid with a
+//   hardware float atomic (nodes that received mass only).
 template <bool DET>
-__global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int material,
-                                             const int32_t *__restrict__ perm,
-                                             const int32_t *__restrict__ tile_start,
-                                             const int32_t *__restrict__ item_tile,
-                                             const int32_t *__restrict__ item_begin,
-                                             const int32_t *__restrict__ n_items, float *__restrict__ gm,
-                                             float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status,
-                                             float *__restrict__ item_part) {
-  __shared__ float s_dat[P2G_DAT][WORK_CHUNK];
-  __shared__ float s_part[64][27][4];
+__global__ __launch_bounds__(P2G_THREADS) void k_p2g(GridDev g, PView P, float dt, int material,
+                                                     const int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ tile_start,
+                                                     const int32_t *__restrict__ item_tile,
+                                                     const int32_t *__restrict__ item_begin,
+                                                     const int32_t *__restrict__ n_items, float *__restrict__ gm,
+                                                     float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status,
+                                                     float *__restrict__ item_part) {
+  static_assert(WORK_CHUNK == P2G_THREADS, "one staged particle per thread");
+  // staged particles in cell order; rows padded by 4 floats so that the 13
+  // feature rows read by one MFMA operand fall into distinct LDS banks
+  __shared__ float s_dat[P2G_DAT][WORK_CHUNK + 4];
+  __shared__ __attribute__((aligned(16))) float s_node[P2G_WAVES][P2G_NODES][4];  // per-wave node sums
   __shared__ int s_cnt[64], s_off[64], s_cur[64];
-  __shared__ unsigned char s_act[64];
-  __shared__ int s_nact;
-  __shared__ short s_list[WORK_CHUNK];
+  __shared__ int s_udesc[P2G_MAX_UNITS];  // unit: first slot | count << 10 | node base << 17
+  __shared__ int s_nunits, s_next;
   __shared__ unsigned char s_cell[WORK_CHUNK];
   const int n = P.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const float kstress = dt * 4.0f * g.inv_dx * g.inv_dx;
   const float dx = g.dx;
-  // per-lane stencil offset and the weight polynomials w_o(f) = a + b f + c f^2
-  const int half = lane >> 5, o = lane & 31;
-  const int ox = o % 3, oy = (o / 3) % 3, oz = o / 9;
-  auto coef = [](int oo, float &a, float &b, float &c) {
-    // w0 = (3/2 - f)^2 / 2, w1 = 3/4 - (f - 1)^2, w2 = (f - 1/2)^2 / 2
-    if (oo == 0) { a = 1.125f; b = -1.5f; c = 0.5f; }
-    else if (oo == 1) { a = -0.25f; b = 2.0f; c = -1.0f; }
-    else { a = 0.125f; b = -0.5f; c = 0.5f; }
-  };
-  float ax_, bx_, cx_, ay_, by_, cy_, az_, bz_, cz_;
-  coef(ox, ax_, bx_, cx_);
-  coef(oy, ay_, by_, cy_);
-  coef(oz, az_, bz_, cz_);
-  const float fox = (float)ox, foy = (float)oy, foz = (float)oz;
-  int ni = *n_items;
-  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
-    int tile = item_tile[it];
-    int b0 = item_begin[it];
-    int nb = min(WORK_CHUNK, tile_start[tile + 1] - b0);
-    int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
+  // MFMA 16x16x4 roles: r16 = row of the feature operand / column (stencil
+  // offset within a 16-wide tile) of the weight operand, kq = particle slot
+  const int r16 = lane & 15, kq = lane >> 4;
+  // staged feature of operand row r16, grouped so that result rows 4 kq ..
+  // 4 kq + 3 (held by lane group kq) all feed node value kq:
+  //   rows 0-3: m, -, -, -;  rows 4 + 4d .. 7 + 4d: q_d, (A dx)_d0, (A dx)_d1, (A dx)_d2
+  const int feat = r16 == 0 ? 3 : (r16 < 4 ? -1 : ((r16 & 3) == 0 ? 3 + (r16 >> 2) : 7 + 3 * ((r16 >> 2) - 1) + (r16 & 3) - 1));
+  // the two stencil offsets of this lane (tiles 0 and 1) and their weights
+  int oo[2], onode[2];
+  float cfa[2][3], cfb[2][3], cfc[2][3], fo[2][3];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    int o = t * 16 + r16;
+    oo[t] = o;
+    int oc = o < 27 ? o : 0;
+    int ox = oc % 3, oy = (oc / 3) % 3, oz = oc / 9;
+    onode[t] = ox + P2G_L * (oy + P2G_L * oz);  // node offset in the 6^3 region
+    p2g_coef(ox, cfa[t][0], cfb[t][0], cfc[t][0]);
+    p2g_coef(oy, cfa[t][1], cfb[t][1], cfc[t][1]);
+    p2g_coef(oz, cfa[t][2], cfb[t][2], cfc[t][2]);
+    fo[t][0] = (float)ox;
+    fo[t][1] = (float)oy;
+    fo[t][2] = (float)oz;
+  }
+  float *s_node_flat = &s_node[0][0][0];
+  const int ni = *n_items;
+  // items are handed out by a ticket counter (header word 8, cleared by the
+  // sort); the next ticket is drawn during the current item
+  int32_t *ticket = status + 8;
+  if (tid == 0) s_next = atomicAdd(ticket, 1);
+  __syncthreads();
+  for (int it = s_next; it < ni; it = s_next) {
+    const int tile = item_tile[it];
+    const int b0 = item_begin[it];
+    const int nb = min(WORK_CHUNK, tile_start[tile + 1] - b0);
+    const int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
     if (tid < 64) s_cnt[tid] = 0;
+    for (int q = tid; q < P2G_WAVES * P2G_NODES; q += P2G_THREADS)
+      reinterpret_cast<float4 *>(s_node_flat)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    // pass A: per-particle quantities into LDS, cell histogram
-    for (int j = tid; j < nb; j += blockDim.x) {
-      int p = perm[b0 + j];
-      float X = grid_coord(P.x[p], g.ox, g.inv_dx);
-      float Y = grid_coord(P.x[n + p], g.oy, g.inv_dx);
-      float Z = grid_coord(P.x[2 * n + p], g.oz, g.inv_dx);
-      int bx = base_of(X), by = base_of(Y), bz = base_of(Z);
-      float H[9], Cm[9], tau[9];
+    // pass A1: this thread's particle -> cell and histogram; the rest of its
+    // state is loaded now and consumed after the scan
+    const int j = tid;
+    const bool has = j < nb;
+    const int p = has ? perm[b0 + j] : 0;
+    float X = 0.f, Y = 0.f, Z = 0.f, H[9], Cm[9], m = 0.f, V0 = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, Er = 0.f,
+          nur = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) H[q] = Cm[q] = 0.f;
+    unsigned char c = 255;
+    if (has) {
+      X = grid_coord(P.x[p], g.ox, g.inv_dx);
+      Y = grid_coord(P.x[n + p], g.oy, g.inv_dx);
+      Z = grid_coord(P.x[2 * n + p], g.oz, g.inv_dx);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         H[q] = P.F[q * n + p];
         Cm[q] = P.C[q * n + p];
       }
-      float m = P.mass[p], V0 = P.vol0[p];
-      float vx = P.v[p], vy = P.v[n + p], vz = P.v[2 * n + p];
-      int r = P.region[p];
-      float mu, lam;
-      lame(P.E[r], P.nu[r], mu, lam);
-      int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
-      unsigned char c = 255;
+      m = P.mass[p];
+      V0 = P.vol0[p];
+      vx = P.v[p];
+      vy = P.v[n + p];
+      vz = P.v[2 * n + p];
+      const int r = P.region[p];
+      Er = P.E[r];
+      nur = P.nu[r];
+      const int lx = base_of(X) - 4 * tx, ly = base_of(Y) - 4 * ty, lz = base_of(Z) - 4 * tz;
       if ((unsigned)lx <= 3u && (unsigned)ly <= 3u && (unsigned)lz <= 3u) {
         c = (unsigned char)(lx + 4 * (ly + 4 * lz));
         atomicAdd(&s_cnt[c], 1);
       } else {
         atomicOr(status, DW_STATUS_OUT_OF_GRID);
       }
-      s_cell[j] = c;
-      kirchhoff_shift(H, mu, lam, material, tau, status);
-      float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
-      float A[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) A[q] = (m * Cm[q] - kstress * V0 * tau[q]) * dx;
-      s_dat[0][j] = fx;
-      s_dat[1][j] = fy;
-      s_dat[2][j] = fz;
-      s_dat[3][j] = m;
-      s_dat[4][j] = m * vx - (A[0] * fx + A[1] * fy + A[2] * fz);
-      s_dat[5][j] = m * vy - (A[3] * fx + A[4] * fy + A[5] * fz);
-      s_dat[6][j] = m * vz - (A[6] * fx + A[7] * fy + A[8] * fz);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) s_dat[7 + q][j] = A[q];
     }
+    s_cell[j] = c;
     __syncthreads();
-    // pass B: group by cell, compact the occupied cells
+    // pass B: cell offsets (exclusive scan) and units (wave 0)
     if (wid == 0) {
-      int v = s_cnt[lane];
+      const int v = s_cnt[lane];
       int inc = v;
 #pragma unroll
       for (int sh = 1; sh < 64; sh <<= 1) {
@@ -354,69 +389,133 @@ __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int m
       }
       s_off[lane] = inc - v;
       s_cur[lane] = inc - v;
-      unsigned long long occ = __ballot(v > 0);
-      if (v > 0) s_act[__popcll(occ & ((1ull << lane) - 1ull))] = (unsigned char)lane;
-      if (lane == 0) s_nact = (int)__popcll(occ);
+      // cell `lane` cut into ceil(v / P2G_UNIT) units, numbered cell by cell
+      const int nu = (v + P2G_UNIT - 1) / P2G_UNIT;
+      int uinc = nu;
+#pragma unroll
+      for (int sh = 1; sh < 64; sh <<= 1) {
+        int t = __shfl_up(uinc, sh, 64);
+        if (lane >= sh) uinc += t;
+      }
+      const int u0 = uinc - nu;
+      const int nbase = (lane & 3) + P2G_L * (((lane >> 2) & 3) + P2G_L * (lane >> 4));
+      for (int q = 0; q < nu; ++q) {
+        const int first = inc - v + q * P2G_UNIT;
+        s_udesc[u0 + q] = first | (min(P2G_UNIT, v - q * P2G_UNIT) << 10) | (nbase << 17);
+      }
+      if (lane == 63) s_nunits = uinc;
     }
     __syncthreads();
-    for (int j = tid; j < nb; j += blockDim.x) {
-      unsigned char c = s_cell[j];
-      if (c == 255) continue;
+    // pass A2: stress, APIC matrix and momentum, staged at the particle's
+    // slot in cell order
+    if (c != 255) {
+      int slot;
       if (DET) {
-        // fixed order: rank among the earlier staged particles of the same cell
+        // fixed order: rank among the item's earlier particles of the same cell
         int rank = 0;
         for (int q = 0; q < j; ++q) rank += s_cell[q] == c;
-        s_list[s_off[c] + rank] = (short)j;
+        slot = s_off[c] + rank;
       } else {
-        s_list[atomicAdd(&s_cur[c], 1)] = (short)j;
+        slot = atomicAdd(&s_cur[c], 1);
       }
+      float mu, lam, tau[9];
+      lame(Er, nur, mu, lam);
+      kirchhoff_shift(H, mu, lam, material, tau, status);
+      const float fx = X - (float)base_of(X), fy = Y - (float)base_of(Y), fz = Z - (float)base_of(Z);
+      float A[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) A[q] = (m * Cm[q] - kstress * V0 * tau[q]) * dx;
+      s_dat[0][slot] = fx;
+      s_dat[1][slot] = fy;
+      s_dat[2][slot] = fz;
+      s_dat[3][slot] = m;
+      s_dat[4][slot] = m * vx - (A[0] * fx + A[1] * fy + A[2] * fz);
+      s_dat[5][slot] = m * vy - (A[3] * fx + A[4] * fy + A[5] * fz);
+      s_dat[6][slot] = m * vz - (A[6] * fx + A[7] * fy + A[8] * fz);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) s_dat[7 + q][slot] = A[q];
     }
     __syncthreads();
-    // pass C: (cell, stencil offset) partial sums
+    // pass C: per unit, Feat (13 x n) W (n x 27) on the matrix cores, added
+    // into this wave's node block; a wave works on two units at once
     {
-      const int nact = s_nact;
-      for (int u = wid; 2 * u < nact; u += 4) {
-        int ci = 2 * u + half;
-        int c = -1, cnt = 0, off = 0;
-        if (ci < nact && o < 27) {
-          c = s_act[ci];
-          cnt = s_cnt[c];
-          off = s_off[c];
+      const int nunits = s_nunits;
+      float(*wnode)[4] = s_node[wid];
+      for (int u = wid; u < nunits; u += 2 * P2G_WAVES) {
+        int k0[2], kn[2], cb[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int ue = u + e * P2G_WAVES;
+          const int d = ue < nunits ? s_udesc[ue] : 0;
+          k0[e] = d & 1023;
+          kn[e] = (d >> 10) & 127;
+          cb[e] = d >> 17;
         }
-        float am = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
-        for (int k = 0; k < cnt; ++k) {
-          int j = s_list[off + k];
-          float fx = s_dat[0][j], fy = s_dat[1][j], fz = s_dat[2][j];
-          float w = (ax_ + fx * (bx_ + cx_ * fx)) * (ay_ + fy * (by_ + cy_ * fy)) * (az_ + fz * (bz_ + cz_ * fz));
-          am += w * s_dat[3][j];
-          a0 += w * (s_dat[4][j] + s_dat[7][j] * fox + s_dat[8][j] * foy + s_dat[9][j] * foz);
-          a1 += w * (s_dat[5][j] + s_dat[10][j] * fox + s_dat[11][j] * foy + s_dat[12][j] * foz);
-          a2 += w * (s_dat[6][j] + s_dat[13][j] * fox + s_dat[14][j] * foy + s_dat[15][j] * foz);
+        floatx4_t acc[2][2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) acc[e][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        const int len = max(kn[0], kn[1]);
+        for (int kk = 0; kk < len; kk += 8) {
+          // LDS reads of both units' next eight particles first
+          float f3[2][2][3], av[2][2];
+          bool live[2][2];
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int r = kk + 4 * h + kq;
+              live[e][h] = r < kn[e];
+              const int jj = k0[e] + (live[e][h] ? r : 0);
+              f3[e][h][0] = s_dat[0][jj];
+              f3[e][h][1] = s_dat[1][jj];
+              f3[e][h][2] = s_dat[2][jj];
+              av[e][h] = (live[e][h] && feat >= 0) ? s_dat[feat < 0 ? 0 : feat][jj] : 0.f;
+            }
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+              for (int t = 0; t < 2; ++t) {
+                float w = 1.f;
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                  w *= cfa[t][d] + f3[e][h][d] * (cfb[t][d] + cfc[t][d] * f3[e][h][d]);
+                w = (live[e][h] && oo[t] < 27) ? w : 0.f;
+                acc[e][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e][h], w, acc[e][t], 0, 0, 0);
+              }
         }
-        if (c >= 0) {
-          s_part[c][o][0] = am;
-          s_part[c][o][1] = a0;
-          s_part[c][o][2] = a1;
-          s_part[c][o][3] = a2;
+        // lane (kq, r16) holds rows 4 kq + i of column r16 (offset o) of each
+        // tile: node value kq of node cell + o is row 4 kq + (1, ox, oy, oz).
+        // A unit's 27 offsets reach 27 distinct nodes and the four lane
+        // groups write the four values: plain adds (a wave's units are
+        // added one after the other).
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (kn[e] == 0) continue;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const floatx4_t a4 = acc[e][t];
+            const float v = a4[0] + fo[t][0] * a4[1] + fo[t][1] * a4[2] + fo[t][2] * a4[3];
+            if (oo[t] < 27) wnode[cb[e] + onode[t]][kq] += v;
+          }
         }
       }
     }
     __syncthreads();
-    // pass D: node owners gather the covering cells' partials
+    // pass D: node owners add the wave blocks in a fixed order
+    if (tid == 0) s_next = atomicAdd(ticket, 1);
     if (tid < P2G_NODES) {
-      int nx_ = tid % P2G_L, ny_ = (tid / P2G_L) % P2G_L, nz_ = tid / (P2G_L * P2G_L);
       float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
-      for (int cz = max(0, nz_ - 2); cz <= min(3, nz_); ++cz)
-        for (int cy = max(0, ny_ - 2); cy <= min(3, ny_); ++cy)
-          for (int cx = max(0, nx_ - 2); cx <= min(3, nx_); ++cx) {
-            int c = cx + 4 * (cy + 4 * cz);
-            if (s_cnt[c] == 0) continue;
-            int oo = (nx_ - cx) + 3 * ((ny_ - cy) + 3 * (nz_ - cz));
-            sm += s_part[c][oo][0];
-            s0 += s_part[c][oo][1];
-            s1 += s_part[c][oo][2];
-            s2 += s_part[c][oo][3];
-          }
+#pragma unroll
+      for (int w = 0; w < P2G_WAVES; ++w) {
+        sm += s_node[w][tid][0];
+        s0 += s_node[w][tid][1];
+        s1 += s_node[w][tid][2];
+        s2 += s_node[w][tid][3];
+      }
       if (DET) {
         float *dst = item_part + ((int64_t)it * P2G_NODES + tid) * 4;
         dst[0] = sm;
@@ -424,7 +523,8 @@ __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int m
         dst[2] = s1;
         dst[3] = s2;
       } else if (sm != 0.f) {
-        int64_t node = (4 * tx + nx_) + (int64_t)g.nx * ((4 * ty + ny_) + (int64_t)g.ny * (4 * tz + nz_));
+        const int nx_ = tid % P2G_L, ny_ = (tid / P2G_L) % P2G_L, nz_ = tid / (P2G_L * P2G_L);
+        const int64_t node = (4 * tx + nx_) + (int64_t)g.nx * ((4 * ty + ny_) + (int64_t)g.ny * (4 * tz + nz_));
         atomicAdd(&gm[node], sm);
         atomicAdd(&gmv[node], s0);
         atomicAdd(&gmv[N + node], s1);
@@ -432,6 +532,14 @@ __global__ __launch_bounds__(256) void k_p2g(GridDev g, PView P, float dt, int m
       }
     }
     __syncthreads();
+  }
+  // the last workgroup to finish rewinds the counters for the next call
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(ticket + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(ticket, 0);
+      atomicExch(ticket + 1, 0);
+    }
   }
 }
 
@@ -616,6 +724,20 @@ namespace dw {
 
 constexpr int PERSISTENT_BLOCKS = 2048;
 
+// P2G grid: the workgroups that fit at once (two per compute unit), which
+// then draw work items from the ticket counter
+static unsigned p2g_blocks() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 512;
+  if (cus[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cus[dev] = c;
+  }
+  return (unsigned)(P2G_PER_CU * cus[dev]);
+}
+
 static PView make_pview(const dw_particles *p) {
   PView v;
   v.x = p->x; v.v = p->v; v.C = p->C; v.F = p->F;
@@ -688,7 +810,7 @@ extern "C" int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const d
   if (params->deterministic) {
     DW_REQUIRE(W.item_part, DW_EWORKSPACE, "mpm_p2g: deterministic mode needs a deterministic workspace");
     if (p->n > 0)
-      hipLaunchKernelGGL(k_p2g<true>, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, make_pview(p), params->dt,
+      hipLaunchKernelGGL(k_p2g<true>, dim3(p2g_blocks()), dim3(P2G_THREADS), 0, s, g, make_pview(p), params->dt,
                          params->material, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, grid_m,
                          grid_mv, N, W.status, W.item_part);
     hipLaunchKernelGGL(k_p2g_det_gather, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
@@ -698,7 +820,7 @@ extern "C" int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const d
   hipLaunchKernelGGL(k_grid_clear, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
                      grid_m, grid_mv, N);
   if (p->n > 0)
-    hipLaunchKernelGGL(k_p2g<false>, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, make_pview(p), params->dt,
+    hipLaunchKernelGGL(k_p2g<false>, dim3(p2g_blocks()), dim3(P2G_THREADS), 0, s, g, make_pview(p), params->dt,
                        params->material, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, grid_m,
                        grid_mv, N, W.status, (float *)nullptr);
   return check_launch("mpm_p2g");
