@@ -217,6 +217,19 @@ int mpm_grid_update(const dw_grid *grid, const dw_mpm_params *params, const floa
 int mpm_g2p(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
             const dw_particles *in, dw_particles *out, void *stream);
 
+/* Memory layout, not physics: writes the particles in the order of the
+ * permutation that the last mpm_sort() left in `ws` (grouped by 4x4x4 cell
+ * tile), out->a[i] = in->a[perm[i]] for x, v, C, F, mass, vol0 and region
+ * (in->n entries; E and nu are per region and not touched).  Keeping the
+ * arrays in this order lets P2G and G2P read particles of a tile from
+ * neighbouring memory; particles move little per substep, so a reorder now
+ * and then keeps it so.  perm_out [n] (NULL to skip) receives perm, i.e. the
+ * old index of each new particle.  `in` and `out` must not share arrays;
+ * out's mass, vol0 and region are written although the struct declares
+ * them const (they are inputs everywhere else). */
+int mpm_reorder(const dw_grid *grid, const dw_particles *in, dw_particles *out, int32_t *perm_out,
+                const void *ws, size_t ws_bytes, void *stream);
+
 /* Wind acceleration on every MPM node: acc [3][N] (overwritten). */
 int wind_to_grid(const dw_grid *grid, const dw_wind *wind, float *acc, void *stream);
 

@@ -28,7 +28,7 @@ STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED = 1, 2, 4
 
 # exported symbols, in the order of include/diffwind.h
 SYMBOLS = [
-    "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p",
+    "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_reorder",
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
     "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_solid_from_particles",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
@@ -94,6 +94,7 @@ def lib():
         "mpm_grid_update": ([POINTER(Grid), POINTER(MPMParams), P, P, POINTER(Wind), P, P, P, c_size_t, P],
                             c_int),
         "mpm_g2p": ([POINTER(Grid), POINTER(MPMParams), P, POINTER(Particles), POINTER(Particles), P], c_int),
+        "mpm_reorder": ([POINTER(Grid), POINTER(Particles), POINTER(Particles), P, P, c_size_t, P], c_int),
         "wind_to_grid": ([POINTER(Grid), POINTER(Wind), P, P], c_int),
         "mpm_p2g_adj": ([POINTER(Grid), POINTER(MPMParams), POINTER(Particles), P, P, POINTER(ParticlesBar), P,
                          P], c_int),
@@ -266,6 +267,17 @@ def read_status(ws: torch.Tensor) -> int:
 def mpm_sort(grid: Grid, params: MPMParams, x, ws):
     _check(lib().mpm_sort(ctypes.byref(grid), ctypes.byref(params), _ptr(x, name="x"), int(x.shape[1]),
                           _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()), "mpm_sort")
+
+
+def mpm_reorder(grid: Grid, p: ParticleArrays, ws, perm_out=None) -> ParticleArrays:
+    """New particle arrays in the order of the last mpm_sort (see the header)."""
+    out = ParticleArrays(torch.empty_like(p.x), torch.empty_like(p.v), torch.empty_like(p.C), torch.empty_like(p.F),
+                         torch.empty_like(p.mass), torch.empty_like(p.vol0), torch.empty_like(p.region), p.E, p.nu)
+    pi, po = p.struct(), out.struct()
+    _check(lib().mpm_reorder(ctypes.byref(grid), ctypes.byref(pi), ctypes.byref(po),
+                             _ptr(perm_out, torch.int32, "perm_out"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+                             _stream()), "mpm_reorder")
+    return out
 
 
 def mpm_p2g(grid: Grid, params: MPMParams, p: ParticleArrays, grid_m, grid_mv, ws):

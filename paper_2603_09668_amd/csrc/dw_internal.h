@@ -161,18 +161,54 @@ __device__ __forceinline__ float det_shift(const float *H) {
 }
 
 // Rotation factor of the polar decomposition F = R S, F = I + H, returned as
-// Y = R - I.  Scaled Newton iteration X <- (zeta X + X^{-T} / zeta) / 2
-// (Higham 1986) written for the deviation Y = X - I:
+// Y = R - I, with every step written for the deviation Y = X - I so that no
+// step subtracts two numbers close to 1 and the strain F - R = H - Y keeps
+// float32 relative precision for small strains.  H = 0 gives Y = 0 exactly.
+// Stretches near 1 (|F^T F - I|_F < 1/2): Newton-Schulz iteration
+//   X <- X (3 I - X^T X) / 2, i.e. S = X^T X - I = Y + Y^T + Y^T Y,
+//   Y <- Y - (S + Y S) / 2,
+// quadratically convergent there and free of divisions.  Otherwise (or if it
+// has not converged in 6 steps) the scaled Newton iteration
+// X <- (zeta X + X^{-T} / zeta) / 2 (Higham 1986) continues, with
 //   (I + Y)^{-1} - I = (Y^2 - (1 + tr Y) Y - det(Y) I) / det(I + Y)
-// (Cayley-Hamilton), so no step subtracts two numbers close to 1 and the
-// strain F - R = H - Y keeps float32 relative precision for small strains.
-// H = 0 gives Y = 0 exactly.
+// (Cayley-Hamilton).  Both stop once a step is below 1e-6 of |Y| + |H|: the
+// error left is then of order 1e-12, under float32 round-off.
 __device__ __forceinline__ void polar_shift(const float *H, float *Y) {
   float hh = 0.f;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     Y[i] = H[i];
     hh += H[i] * H[i];
+  }
+  {
+    float S[9], s2 = 0.f;
+    matmul3_atb(Y, Y, S);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) S[3 * i + j] += Y[3 * i + j] + Y[3 * j + i];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s2 += S[i] * S[i];
+    if (s2 < 0.25f) {
+      for (int it = 0; it < 6; ++it) {
+        float YS[9];
+        matmul3(Y, S, YS);
+        float delta = 0.f, yy = 0.f;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          float e = 0.5f * (S[i] + YS[i]);
+          Y[i] -= e;
+          delta += e * e;
+          yy += Y[i] * Y[i];
+        }
+        if (delta <= 1e-12f * (yy + hh)) return;
+        matmul3_atb(Y, Y, S);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) S[3 * i + j] += Y[3 * i + j] + Y[3 * j + i];
+      }
+    }
   }
   for (int it = 0; it < 16; ++it) {
     float t = Y[0] + Y[4] + Y[8];
@@ -211,8 +247,6 @@ __device__ __forceinline__ void polar_shift(const float *H, float *Y) {
       yy += yn * yn;
       Y[i] = yn;
     }
-    // quadratic convergence: a relative step below 1e-6 leaves an error of
-    // order 1e-12, under float32 round-off, so stop there
     if (delta <= 1e-12f * (yy + hh)) break;
   }
 }

@@ -280,7 +280,7 @@ __device__ __forceinline__ void p2g_coef(int oo, float &a, float &b, float &c) {
 //   in a fixed order and adds the total into the global grid with a
 //   hardware float atomic (nodes that received mass only).
 template <bool DET>
-__global__ __launch_bounds__(P2G_THREADS) void k_p2g(GridDev g, PView P, float dt, int material,
+__global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_p2g(GridDev g, PView P, float dt, int material,
                                                      const int32_t *__restrict__ perm,
                                                      const int32_t *__restrict__ tile_start,
                                                      const int32_t *__restrict__ item_tile,
@@ -592,6 +592,34 @@ __global__ __launch_bounds__(256) void k_p2g_det_gather(GridDev g, const int32_t
   }
 }
 
+// ---------------------------------------------------------------- reorder
+
+// out[i] = in[perm[i]] for every per-particle array (SoA, n entries each)
+__global__ __launch_bounds__(256) void k_reorder(PView in, float *__restrict__ x, float *__restrict__ v,
+                                                 float *__restrict__ C, float *__restrict__ F,
+                                                 float *__restrict__ mass, float *__restrict__ vol0,
+                                                 int32_t *__restrict__ region, const int32_t *__restrict__ perm,
+                                                 int32_t *__restrict__ perm_out) {
+  const int n = in.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = perm[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    x[d * n + i] = in.x[d * n + p];
+    v[d * n + i] = in.v[d * n + p];
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    C[q * n + i] = in.C[q * n + p];
+    F[q * n + i] = in.F[q * n + p];
+  }
+  mass[i] = in.mass[p];
+  vol0[i] = in.vol0[p];
+  region[i] = in.region[p];
+  if (perm_out) perm_out[i] = p;
+}
+
 // ------------------------------------------------------------ grid update
 
 __global__ __launch_bounds__(256) void k_grid_update(GridDev g, float dt, float gx, float gy, float gz,
@@ -789,6 +817,29 @@ extern "C" int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const 
   rc = bind_workspace(grid, n, ws, ws_bytes, &W);
   if (rc) return rc;
   return run_sort(grid, params ? params->deterministic : 0, x, n, W, (hipStream_t)stream);
+}
+
+extern "C" int mpm_reorder(const dw_grid *grid, const dw_particles *in, dw_particles *out, int32_t *perm_out,
+                           const void *ws, size_t ws_bytes, void *stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  rc = check_particles(in, true);
+  if (rc) return rc;
+  DW_REQUIRE(out && out->n == in->n, DW_EINVAL, "mpm_reorder: out must hold in->n particles");
+  DW_REQUIRE(out->x && out->v && out->C && out->F && out->mass && out->vol0 && out->region, DW_EINVAL,
+             "mpm_reorder: out arrays must not be NULL");
+  DW_REQUIRE(out->x != in->x && out->v != in->v && out->C != in->C && out->F != in->F && out->mass != in->mass &&
+                 out->vol0 != in->vol0 && out->region != in->region,
+             DW_EINVAL, "mpm_reorder: in and out must not share arrays");
+  Workspace W;
+  rc = bind_workspace(grid, in->n, ws, ws_bytes, &W, 0);
+  if (rc) return rc;
+  if (in->n > 0)
+    hipLaunchKernelGGL(k_reorder, dim3(grid_blocks(in->n, 256)), dim3(256), 0, (hipStream_t)stream,
+                       make_pview(in), out->x, out->v, out->C, out->F, const_cast<float *>(out->mass),
+                       const_cast<float *>(out->vol0), const_cast<int32_t *>(out->region), W.perm,
+                       perm_out);
+  return check_launch("mpm_reorder");
 }
 
 extern "C" int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p, float *grid_m,

@@ -21,7 +21,7 @@ from . import api
 
 
 class CoupledSim:
-    def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1):
+    def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1, reorder: bool = True):
         self.scene = scene
         self.device = device
         self.R = int(lbm_steps_per_substep)
@@ -60,6 +60,23 @@ class CoupledSim:
         self.solid = torch.zeros(self.L, dtype=torch.uint8, device=device)
         self.u = torch.zeros(3, self.L, **f32)
         self.wind = api.wind_lbm_drag(self.lat, self.u, scene.wind["vel_scale"], scene.wind["k_drag"])
+        # order[i] = scene index of particle i
+        self.order = torch.arange(n, dtype=torch.int32, device=device)
+        if reorder:
+            self.reorder()
+
+    def in_scene_order(self, t):
+        """A per-particle array (.., n) back in the scene's particle order."""
+        out = torch.empty_like(t)
+        out[..., self.order.long()] = t
+        return out
+
+    def reorder(self):
+        """Store the particles in cell-tile order (memory layout only)."""
+        self.sort()
+        perm = torch.empty(self.p.n, dtype=torch.int32, device=self.device)
+        self.p = api.mpm_reorder(self.grid, self.p, self.ws, perm_out=perm)
+        self.order = self.order[perm.long()]
 
     # -------------------------------------------------------------- phases
     def voxelize(self):

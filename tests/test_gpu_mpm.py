@@ -62,6 +62,54 @@ def test_sort_matches_definition(sheet, leaves):
         assert V["node_tiles"][:nnode].cpu().tolist() == ompm.active_node_tiles(None, og, base=base)
 
 
+def test_reorder_is_the_sort_permutation(leaves):
+    """mpm_reorder writes every per-particle array in the sort's order,
+    bit for bit, and the result is grouped by cell tile; a substep of the
+    reordered set equals the original substep, permuted."""
+    sc = leaves
+    say(f"mpm_reorder {sc.name}")
+    st, dev = scene_state(sc)
+    g = api_grid(sc.grid)
+    og = oracle_grid(sc.grid)
+    ws = api.alloc_workspace(g, sc.n)
+    prm = api.make_mpm_params(sc.dt, sc.gravity, sc.bound, sc.material)
+    rng = np.random.default_rng(3)
+    dev = dev.with_state(dev.x, torch.tensor(rng.standard_normal((3, sc.n)), dtype=torch.float32, device=DEV),
+                         torch.tensor(0.1 * rng.standard_normal((9, sc.n)), dtype=torch.float32, device=DEV),
+                         torch.tensor(0.01 * rng.standard_normal((9, sc.n)), dtype=torch.float32, device=DEV))
+    api.mpm_sort(g, prm, dev.x, ws)
+    perm = torch.empty(sc.n, dtype=torch.int32, device=DEV)
+    out = api.mpm_reorder(g, dev, ws, perm_out=perm)
+    V = api.workspace_views(g, sc.n, ws)
+    assert torch.equal(perm, V["perm"][:sc.n])
+    pl = perm.long()
+    for name in ("x", "v", "C", "F"):
+        assert torch.equal(getattr(out, name), getattr(dev, name)[:, pl]), name
+    for name in ("mass", "vol0", "region"):
+        assert torch.equal(getattr(out, name), getattr(dev, name)[pl]), name
+    base = ompm.stencil_base_f32(torch.as_tensor(out.x.T.double().cpu()), og)
+    keys = ompm.cell_tile_keys(None, og, base=base)
+    assert torch.all(keys[1:] >= keys[:-1])
+    # one substep on each order
+    N = sc.grid["nx"] * sc.grid["ny"] * sc.grid["nz"]
+    res = []
+    for p in (dev, out):
+        gm, gmv, gv = torch.zeros(N, device=DEV), torch.zeros(3, N, device=DEV), torch.zeros(3, N, device=DEV)
+        api.mpm_sort(g, prm, p.x, ws)
+        api.mpm_p2g(g, prm, p, gm, gmv, ws)
+        api.mpm_grid_update(g, prm, gm, gmv, api.wind_none(), None, gv, ws)
+        o = [torch.empty_like(t) for t in (p.x, p.v, p.C, p.F)]
+        api.mpm_g2p(g, prm, gv, p, *o)
+        res.append(o)
+    for a, b in zip(res[0], res[1]):
+        assert rel(b, a[:, pl]) < 1e-5
+    # in and out sharing arrays is refused before any launch
+    same = dev.struct()
+    rc = api.lib().mpm_reorder(api.ctypes.byref(g), api.ctypes.byref(same), api.ctypes.byref(same), None,
+                               api._ptr(ws, torch.uint8, "ws"), ws.numel(), api._stream())
+    assert rc != 0 and "share" in api.dw_last_error()
+
+
 @pytest.mark.parametrize("material", [api.FIXED_COROTATED, api.NEO_HOOKEAN])
 @pytest.mark.parametrize("scene_name", ["sheet", "leaves"])
 def test_p2g_parity(material, scene_name, request):
