@@ -35,6 +35,10 @@ struct LbmDev {
   bool forced;
 };
 
+// launch shape: threads along x, one block row per (y, z) line
+constexpr int LBM_BLOCK = 128;
+constexpr int SOL_W = LBM_BLOCK + 8;  // staged solid bytes per row: x0 - 4 .. x0 + LBM_BLOCK + 3
+
 // Where the population arriving at (i, j, k) in direction q comes from.
 enum { SRC_NORMAL = 0, SRC_BOUNCE = 1, SRC_INLET = 2 };
 
@@ -83,13 +87,57 @@ __device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, 
   return LW[q] * (3.f * cu + 4.5f * cu * cu - 1.5f * uu);
 }
 
+// Solid flags of the 3 x 3 (y, z) rows around this block's row,
+// x0 - 4 .. x0 + LBM_BLOCK + 3, staged in LDS: row r = (dy + 1) + 3 (dz + 1).
+// Rows outside the lattice read as fluid (their sources take the boundary
+// rules, which look at the solid array themselves).  Whole 4-byte words are
+// loaded where the row is 4-byte aligned.
+constexpr int SOL_WORDS = 9 * (SOL_W / 4);
+constexpr int SOL_PER_THREAD = (SOL_WORDS + LBM_BLOCK - 1) / LBM_BLOCK;
+
+__device__ __forceinline__ void load_solid_rows(const LbmDev &P, const uint8_t *__restrict__ solid, int x0, int j,
+                                                int k, uint32_t v[SOL_PER_THREAD]) {
+  constexpr int WORDS = SOL_W / 4;
+  const bool aligned = (P.nx & 3) == 0 && (((uintptr_t)solid) & 3) == 0;
+#pragma unroll
+  for (int u = 0; u < SOL_PER_THREAD; ++u) {
+    const int q = threadIdx.x + u * LBM_BLOCK;
+    v[u] = 0;
+    if (q >= SOL_WORDS) continue;
+    const int r = q / WORDS, w = q % WORDS;
+    const int jj = j + r % 3 - 1, kk = k + r / 3 - 1;
+    const int xs = x0 - 4 + 4 * w;
+    if ((unsigned)jj < (unsigned)P.ny && (unsigned)kk < (unsigned)P.nz) {
+      const int64_t row = (int64_t)P.nx * (jj + (int64_t)P.ny * kk);
+      if (aligned && xs >= 0 && xs + 3 < P.nx) {
+        v[u] = *reinterpret_cast<const uint32_t *>(solid + row + xs);
+      } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (xs + b >= 0 && xs + b < P.nx) v[u] |= (uint32_t)solid[row + xs + b] << (8 * b);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void store_solid_rows(const uint32_t v[SOL_PER_THREAD], uint8_t (*s_sol)[SOL_W]) {
+#pragma unroll
+  for (int u = 0; u < SOL_PER_THREAD; ++u) {
+    const int q = threadIdx.x + u * LBM_BLOCK;
+    if (q < SOL_WORDS) reinterpret_cast<uint32_t *>(&s_sol[0][0])[q] = v[u];
+  }
+}
+
 // Pull the 19 shifted populations of fluid node (i, j, k).  A source inside
-// the lattice needs only the solid test; the boundary rules run only for the
+// the lattice is read unconditionally and replaced by the bounce-back value
+// when the staged solid flag says so; the boundary rules run only for the
 // few lanes whose source leaves the lattice (the inlet and outlet columns
 // sit in every x-row, so the general rule must not be taken per node).
+// SOL: 0 = no solid nodes, 1 = flags staged in s_sol, 2 = flags read from `solid`
+template <int SOL>
 __device__ __forceinline__ void pull_all(const LbmDev &P, const float *__restrict__ fin,
-                                         const uint8_t *__restrict__ solid, int i, int j, int k, int64_t node,
-                                         float f[19]) {
+                                         const uint8_t *__restrict__ solid, const uint8_t (*s_sol)[SOL_W], int i,
+                                         int j, int k, int x0, int64_t node, float f[19]) {
   const int64_t sy = P.nx, sz = (int64_t)P.nx * P.ny;
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
@@ -97,8 +145,11 @@ __device__ __forceinline__ void pull_all(const LbmDev &P, const float *__restric
     bool inside = (unsigned)si < (unsigned)P.nx && (unsigned)sj < (unsigned)P.ny && (unsigned)sk < (unsigned)P.nz;
     if (inside) {
       int64_t src = node - (LC[q][0] + LC[q][1] * sy + LC[q][2] * sz);
-      bool bb = solid && solid[src];
-      f[q] = bb ? fin[(int64_t)LOPP[q] * P.L + node] : fin[(int64_t)q * P.L + src];
+      float v = fin[(int64_t)q * P.L + src];
+      const bool bb = SOL == 1 ? s_sol[(1 - LC[q][1]) + 3 * (1 - LC[q][2])][si - x0 + 4] != 0
+                              : (SOL == 2 && solid[src] != 0);
+      if (bb) v = fin[(int64_t)LOPP[q] * P.L + node];
+      f[q] = v;
     } else {
       int64_t src = node;
       int ssj = 0, ssk = 0;
@@ -127,14 +178,28 @@ __device__ __forceinline__ void moments(const LbmDev &P, const float f[19], floa
   uz = (jz + 0.5f * P.F[2]) * ir;
 }
 
-__global__ __launch_bounds__(128) void k_lbm_step(LbmDev P, const float *__restrict__ fin, float *__restrict__ fout,
-                                                  const uint8_t *__restrict__ solid, float *__restrict__ rho_out,
-                                                  float *__restrict__ u_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+template <bool SOLID>
+__global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *__restrict__ fin,
+                                                        float *__restrict__ fout, const uint8_t *__restrict__ solid,
+                                                        float *__restrict__ rho_out, float *__restrict__ u_out) {
+  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  const int x0 = blockIdx.x * LBM_BLOCK;
+  const int i = x0 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
   if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
-  if (i >= P.nx) return;
   const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
-  if (solid && solid[node]) {
+  float f[19];
+  if (SOLID) {
+    uint32_t sv[SOL_PER_THREAD];
+    load_solid_rows(P, solid, x0, j, k, sv);
+    store_solid_rows(sv, s_sol);
+    __syncthreads();
+    if (i >= P.nx) return;
+    if (!s_sol[4][i - x0 + 4]) pull_all<1>(P, fin, solid, s_sol, i, j, k, x0, node, f);
+  } else {
+    if (i >= P.nx) return;
+    pull_all<0>(P, fin, solid, s_sol, i, j, k, x0, node, f);
+  }
+  if (SOLID && s_sol[4][i - x0 + 4]) {
 #pragma unroll
     for (int q = 0; q < 19; ++q) fout[(int64_t)q * P.L + node] = 0.f;
     if (rho_out) rho_out[node] = 1.f;
@@ -145,8 +210,6 @@ __global__ __launch_bounds__(128) void k_lbm_step(LbmDev P, const float *__restr
     }
     return;
   }
-  float f[19];
-  pull_all(P, fin, solid, i, j, k, node, f);
   float rho, ux, uy, uz;
   moments(P, f, rho, ux, uy, uz);
   float drho = rho - 1.0f;
@@ -187,7 +250,7 @@ __global__ __launch_bounds__(128) void k_lbm_step_adj(LbmDev P, const float *__r
   const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
   if (solid && solid[node]) return;
   float f[19];
-  pull_all(P, fin, solid, i, j, k, node, f);
+  pull_all<2>(P, fin, solid, nullptr, i, j, k, 0, node, f);
   float rho, ux, uy, uz;
   moments(P, f, rho, ux, uy, uz);
   float uu = ux * ux + uy * uy + uz * uz;
@@ -271,8 +334,6 @@ __global__ void k_fill_u8(uint8_t *p, int64_t count) {
     p[i] = 0;
 }
 
-// launch shape: threads along x, one block row per (y, z) line
-constexpr int LBM_BLOCK = 128;
 static dim3 lbm_grid(const LbmDev &P) {
   return dim3((unsigned)((P.nx + LBM_BLOCK - 1) / LBM_BLOCK), (unsigned)P.ny, (unsigned)P.nz);
 }
@@ -329,8 +390,12 @@ extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, cons
   if (rc) return rc;
   DW_REQUIRE(f_in && f_out, DW_EINVAL, "lbm_step: f_in / f_out is NULL");
   DW_REQUIRE(f_in != f_out, DW_EINVAL, "lbm_step: f_in and f_out must not alias");
-  hipLaunchKernelGGL(k_lbm_step, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, f_out, solid,
-                     rho_out, u_out);
+  if (solid)
+    hipLaunchKernelGGL(k_lbm_step<true>, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, f_out, solid,
+                       rho_out, u_out);
+  else
+    hipLaunchKernelGGL(k_lbm_step<false>, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, f_out,
+                       solid, rho_out, u_out);
   return check_launch("lbm_step");
 }
 
