@@ -39,6 +39,8 @@ def _args():
     ap.add_argument("--cpu-substeps", type=int, default=12)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-only", action="store_true", help="run only the wind-surrogate leg (profiling)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     ap.add_argument("--sg-rollouts", type=int, default=250)
     ap.add_argument("--sg-steps", type=int, default=1000)
     return ap.parse_args()
@@ -179,6 +181,12 @@ def main():
     from paper_2603_09668_amd import api, scenes
     from paper_2603_09668_amd.sim import CoupledSim
 
+    if a.copy_mib > 0:
+        src = torch.ones(a.copy_mib << 18, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if a.surrogate_only:
         print(json.dumps({"metric": METRIC, "surrogate": _surrogate_leg(a.sg_rollouts, a.sg_steps)}), flush=True)
         return

@@ -659,6 +659,10 @@ __global__ __launch_bounds__(256) void k_grid_update(GridDev g, float dt, float 
 
 // ------------------------------------------------------------------ G2P
 
+struct Float3 {
+  float v[3];
+};
+
 __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
                                              const float *xin, const float *Fin, float *xout, float *vout,
                                              float *Cout, float *Fout, int n, int32_t *__restrict__ status) {
@@ -706,11 +710,16 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
 #pragma unroll
     for (int oy = 0; oy < 3; ++oy) {
       int64_t row = (bx) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+      // the three x-neighbours of a stencil row are contiguous: one 12-byte
+      // load per velocity component
+      Float3 ra, rb, rc;
+      __builtin_memcpy(&ra, gv + row, sizeof(Float3));
+      __builtin_memcpy(&rb, gv + N + row, sizeof(Float3));
+      __builtin_memcpy(&rc, gv + 2 * N + row, sizeof(Float3));
 #pragma unroll
       for (int ox = 0; ox < 3; ++ox) {
-        int64_t node = row + ox;
         float w = wx[ox] * wy[oy] * wz[oz];
-        float a = gv[node], b = gv[N + node], c = gv[2 * N + node];
+        float a = ra.v[ox], b = rb.v[ox], c = rc.v[ox];
         float dxo = (float)ox - fx, dyo = (float)oy - fy, dzo = (float)oz - fz;
         v0 += w * a; v1 += w * b; v2 += w * c;
         float wa = w * a, wb = w * b, wc = w * c;
