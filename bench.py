@@ -13,7 +13,9 @@ launch stream, the roofline of the dominant kernel and the float64 CPU
 oracle timed on a bounded sample of the same workload.  The wind-surrogate
 leg trains the BF16 conv net on 2000 LBM pairs of 64^3 wind tunnels (1800
 train / 200 held out), then reports its held-out wind error against the LBM
-and the speedup of one batched call over the 8 LBM steps it replaces.
+and the speedup of one batched call over the 8 LBM steps it replaces.  The
+adjoint leg times a 256-substep differentiable rollout (256k particles, 96^3,
+checkpoints every 16) forward and backward, with a finite-difference check.
 """
 from __future__ import annotations
 
@@ -43,6 +45,9 @@ def _args():
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     ap.add_argument("--sg-rollouts", type=int, default=250)
     ap.add_argument("--sg-steps", type=int, default=1000)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint leg (profiling)")
+    ap.add_argument("--fd", type=int, default=20, help="finite-difference coordinates in the adjoint leg")
     return ap.parse_args()
 
 
@@ -133,6 +138,84 @@ def _surrogate_leg(n_rollouts, train_steps):
                        "train_s": t_train, "data_s": t_data}}
 
 
+def _adjoint_leg(n, res, n_sub, ckpt, n_fd):
+    """Reconstruction-style gradient: a rollout of `n_sub` substeps driven by a
+    16^3 x 8 wind force grid, loss = |x_T - x_target|^2 against a rollout
+    under a perturbed field, gradient with respect to the force grid and the
+    per-region E through the hand-written adjoints with checkpoints every
+    `ckpt` substeps; timed forward and backward, and checked by central
+    differences of the same GPU forward on `n_fd` seeded coordinates."""
+    import numpy as np
+    import torch
+    from paper_2603_09668_amd import api, scenes
+    from paper_2603_09668_amd.autograd import RolloutPlan, rollout
+    sc = scenes.flag_and_leaves_scene(seed=3, n=n, res=res, lbm_dims=(res, res // 2, res // 2))
+    dev = "cuda"
+    f32 = dict(dtype=torch.float32, device=dev)
+    x0 = torch.tensor(np.ascontiguousarray(sc.x.T), **f32)
+    mass, vol0 = torch.tensor(sc.mass, **f32), torch.tensor(sc.vol0, **f32)
+    region = torch.tensor(sc.region, dtype=torch.int32, device=dev)
+    E0, nu = torch.tensor(sc.E, **f32), torch.tensor(sc.nu, **f32)
+    pin = torch.tensor(sc.pin, dtype=torch.uint8, device=dev)
+    K, nw = 8, 16
+    plan = RolloutPlan(sc.grid, sc.n, mass, vol0, region, nu, pin, sc.dt, sc.gravity, sc.material, sc.bound,
+                       (nw,) * 3, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), K, n_sub, ckpt, device=dev)
+    # particles in the sort's order (memory layout only)
+    api.mpm_sort(plan.grid, plan.prm, x0, plan.ws)
+    pa = api.mpm_reorder(plan.grid, api.ParticleArrays(x0, torch.zeros(3, sc.n, **f32), torch.zeros(9, sc.n, **f32),
+                                                       torch.zeros(9, sc.n, **f32), mass, vol0, region, E0, nu),
+                         plan.ws)
+    plan.mass, plan.vol0, plan.region = pa.mass, pa.vol0, pa.region
+    x0 = pa.x
+    z3, z9 = torch.zeros(3, sc.n, **f32), torch.zeros(9, sc.n, **f32)
+    amp = 200.0
+    Wt = torch.tensor(scenes.smooth_force_field(7, K=K, nw=nw, amp=amp, perturb=0.3), **f32)
+    W0 = torch.tensor(scenes.smooth_force_field(7, K=K, nw=nw, amp=amp), **f32)
+    with torch.no_grad():
+        xt = rollout(plan, Wt, E0, x0, z3, z9, z9.clone())[0].clone()
+
+    def loss_of(W, E):
+        return ((rollout(plan, W, E, x0, z3, z9, z9.clone())[0] - xt) ** 2).sum()
+
+    W = W0.clone().requires_grad_(True)
+    E = E0.clone().requires_grad_(True)
+    loss_of(W, E).backward()  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    W.grad = None
+    E.grad = None
+    torch.cuda.synchronize()
+    ev[0].record()
+    L = loss_of(W, E)
+    ev[1].record()
+    L.backward()
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_fwd, t_bwd = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    gW = W.grad.detach().clone()
+    # central differences on seeded coordinates of the force grid
+    rng = np.random.default_rng(11)
+    flat = gW.reshape(-1)
+    top = torch.topk(flat.abs(), 200).indices.cpu().numpy()
+    coords = rng.choice(top, n_fd, replace=False)
+    errs = []
+    with torch.no_grad():
+        for c in coords:
+            h = 0.05 * amp
+            Wp, Wm = W0.clone().reshape(-1), W0.clone().reshape(-1)
+            Wp[c] += h
+            Wm[c] -= h
+            fd = (loss_of(Wp.reshape(W0.shape), E0) - loss_of(Wm.reshape(W0.shape), E0)).item() / (2 * h)
+            errs.append(abs(fd - flat[c].item()) / max(abs(fd), 1e-30))
+    errs = np.array(errs) if errs else np.zeros(1)
+    return {"ms_forward": t_fwd, "ms_backward": t_bwd, "us_per_substep_forward": 1e3 * t_fwd / n_sub,
+            "us_per_substep_backward": 1e3 * t_bwd / n_sub, "loss": L.item(),
+            "fd_check": {"coordinates": int(n_fd), "rel_err_median": float(np.median(errs)),
+                         "rel_err_max": float(errs.max()), "step": "0.05 x field amplitude, float32 forward"},
+            "config": {"workload": f"reconstruction gradient: {sc.n} particles, {res}^3 grid, {n_sub} substeps, "
+                                   f"checkpoint every {ckpt}, 16^3 x 8 force grid and per-region E",
+                       "particles": sc.n, "grid": res, "substeps": n_sub, "checkpoint_every": ckpt}}
+
+
 def _cpu_baseline(scene, substeps):
     """The float64 oracle on the host: `substeps` coupled substeps (LBM step,
     drag wind, MPM substep) of the full scene."""
@@ -187,6 +270,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.adjoint_only:
+        print(json.dumps({"metric": METRIC, "adjoint": _adjoint_leg(256_000, 96, 256, 16, a.fd)}), flush=True)
+        return
     if a.surrogate_only:
         print(json.dumps({"metric": METRIC, "surrogate": _surrogate_leg(a.sg_rollouts, a.sg_steps)}), flush=True)
         return
@@ -288,6 +374,8 @@ def main():
         sgo = _surrogate_leg(a.sg_rollouts, a.sg_steps)
         out["surrogate_speedup"] = sgo["speedup"]
         out["surrogate"] = sgo
+    if not a.no_adjoint:
+        out["adjoint"] = _adjoint_leg(256_000, 96, 256, 16, a.fd)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(scene, a.cpu_substeps)
     print(json.dumps(out), flush=True)

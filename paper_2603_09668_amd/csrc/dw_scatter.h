@@ -1,0 +1,180 @@
+// Tile scatter on the matrix cores, shared by P2G and the reverse of G2P.
+//
+// Both add, for every particle p of a cell tile and every stencil offset
+// o = (ox, oy, oz) in {0,1,2}^3, the value w_o(f_p) (q_p + A_p o) into node
+// base_p + o of the tile's 6^3 node region, with f_p the particle's position
+// in its base cell (in cells), w_o the quadratic B-spline weight, q_p a
+// 3-vector and A_p a 3x3 matrix (P2G also adds w_o m_p as a fourth value).
+// A workgroup stages its particles in LDS in cell order (16 floats each:
+// f, m, q, A row-major), cuts each cell into units of at most SC_UNIT
+// particles, and per unit forms Feat (13 x n) W (n x 27) with fp32 MFMA
+// 16x16x4 (four particles per step, offsets in two 16-column tiles), the
+// rows ordered so that the four result rows a lane holds give one node
+// value: (1, ox, oy, oz) . rows.  Every wave adds its units' 27 x 4 values
+// into its own 6^3 node block in LDS (a unit's 27 offsets reach 27 distinct
+// nodes: plain adds); the node owners then add the wave blocks.
+#pragma once
+
+#include "dw_internal.h"
+
+namespace dw {
+
+constexpr int SC_L = 6;           // local node extent of a cell tile's stencils
+constexpr int SC_NODES = 216;     // 6^3
+constexpr int SC_DAT = 16;        // staged floats per particle: f(3), m, q(3), A(9)
+constexpr int SC_UNIT = 64;       // particles per unit (16 MFMA steps)
+constexpr int SC_MAX_UNITS = 64 + WORK_CHUNK / SC_UNIT;  // bounds the sum over cells of ceil(count / unit)
+constexpr int SC_THREADS = WORK_CHUNK;
+constexpr int SC_WAVES = SC_THREADS / 64;
+constexpr int SC_PITCH = WORK_CHUNK + 4;  // staged rows padded: the 13 feature rows of one operand hit distinct banks
+
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// Stencil weight polynomial of offset component oo: w = a + b f + c f^2,
+// w0 = (3/2 - f)^2 / 2, w1 = 3/4 - (f - 1)^2, w2 = (f - 1/2)^2 / 2.
+__device__ __forceinline__ void sc_coef(int oo, float &a, float &b, float &c) {
+  if (oo == 0) { a = 1.125f; b = -1.5f; c = 0.5f; }
+  else if (oo == 1) { a = -0.25f; b = 2.0f; c = -1.0f; }
+  else { a = 0.125f; b = -0.5f; c = 0.5f; }
+}
+
+// Per-lane constants of the MFMA 16x16x4 roles: r16 = row of the feature
+// operand / column (offset within a 16-wide tile) of the weight operand,
+// kq = particle slot of the step.
+struct ScLane {
+  int kq, feat;
+  int oo[2], onode[2];
+  float cfa[2][3], cfb[2][3], cfc[2][3], fo[2][3];
+};
+
+__device__ __forceinline__ ScLane sc_lane(int lane) {
+  ScLane L;
+  const int r16 = lane & 15;
+  L.kq = lane >> 4;
+  // staged feature of operand row r16, grouped so that result rows 4 kq ..
+  // 4 kq + 3 (held by lane group kq) all feed node value kq:
+  //   rows 0-3: m, -, -, -;  rows 4 + 4d .. 7 + 4d: q_d, A_d0, A_d1, A_d2
+  L.feat = r16 == 0 ? 3 : (r16 < 4 ? -1 : ((r16 & 3) == 0 ? 3 + (r16 >> 2) : 7 + 3 * ((r16 >> 2) - 1) + (r16 & 3) - 1));
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int o = t * 16 + r16;
+    L.oo[t] = o;
+    const int oc = o < 27 ? o : 0;
+    const int ox = oc % 3, oy = (oc / 3) % 3, oz = oc / 9;
+    L.onode[t] = ox + SC_L * (oy + SC_L * oz);
+    sc_coef(ox, L.cfa[t][0], L.cfb[t][0], L.cfc[t][0]);
+    sc_coef(oy, L.cfa[t][1], L.cfb[t][1], L.cfc[t][1]);
+    sc_coef(oz, L.cfa[t][2], L.cfb[t][2], L.cfc[t][2]);
+    L.fo[t][0] = (float)ox;
+    L.fo[t][1] = (float)oy;
+    L.fo[t][2] = (float)oz;
+  }
+  return L;
+}
+
+// Wave 0: exclusive scan of the 64 cell counts into s_off / s_cur and the
+// unit descriptors (first slot | count << 10 | node base << 17).
+__device__ __forceinline__ void sc_scan_units(int lane, const int *s_cnt, int *s_off, int *s_cur, int *s_udesc,
+                                              int *s_nunits) {
+  const int v = s_cnt[lane];
+  int inc = v;
+#pragma unroll
+  for (int sh = 1; sh < 64; sh <<= 1) {
+    int t = __shfl_up(inc, sh, 64);
+    if (lane >= sh) inc += t;
+  }
+  s_off[lane] = inc - v;
+  s_cur[lane] = inc - v;
+  const int nu = (v + SC_UNIT - 1) / SC_UNIT;
+  int uinc = nu;
+#pragma unroll
+  for (int sh = 1; sh < 64; sh <<= 1) {
+    int t = __shfl_up(uinc, sh, 64);
+    if (lane >= sh) uinc += t;
+  }
+  const int u0 = uinc - nu;
+  const int nbase = (lane & 3) + SC_L * (((lane >> 2) & 3) + SC_L * (lane >> 4));
+  for (int q = 0; q < nu; ++q) s_udesc[u0 + q] = (inc - v + q * SC_UNIT) | (min(SC_UNIT, v - q * SC_UNIT) << 10) | (nbase << 17);
+  if (lane == 63) *s_nunits = uinc;
+}
+
+// Stage one particle at `slot`: f, m, q, A (A row-major).
+__device__ __forceinline__ void sc_stage(float (*s_dat)[SC_PITCH], int slot, const float f[3], float m, const float q[3],
+                                         const float A[9]) {
+  s_dat[0][slot] = f[0];
+  s_dat[1][slot] = f[1];
+  s_dat[2][slot] = f[2];
+  s_dat[3][slot] = m;
+  s_dat[4][slot] = q[0];
+  s_dat[5][slot] = q[1];
+  s_dat[6][slot] = q[2];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s_dat[7 + k][slot] = A[k];
+}
+
+// Pass over the units on the matrix cores; wave `wid` adds into wnode.
+// Two units per wave at a time.
+__device__ __forceinline__ void sc_units_mfma(const ScLane &L, int wid, const float (*s_dat)[SC_PITCH],
+                                              const int *s_udesc, int nunits, float (*wnode)[4]) {
+  for (int u = wid; u < nunits; u += 2 * SC_WAVES) {
+    int k0[2], kn[2], cb[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int ue = u + e * SC_WAVES;
+      const int d = ue < nunits ? s_udesc[ue] : 0;
+      k0[e] = d & 1023;
+      kn[e] = (d >> 10) & 127;
+      cb[e] = d >> 17;
+    }
+    floatx4_t acc[2][2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[e][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    const int len = max(kn[0], kn[1]);
+    for (int kk = 0; kk < len; kk += 8) {
+      // LDS reads of both units' next eight particles first
+      float f3[2][2][3], av[2][2];
+      bool live[2][2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = kk + 4 * h + L.kq;
+          live[e][h] = r < kn[e];
+          const int jj = k0[e] + (live[e][h] ? r : 0);
+          f3[e][h][0] = s_dat[0][jj];
+          f3[e][h][1] = s_dat[1][jj];
+          f3[e][h][2] = s_dat[2][jj];
+          av[e][h] = (live[e][h] && L.feat >= 0) ? s_dat[L.feat < 0 ? 0 : L.feat][jj] : 0.f;
+        }
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            float w = 1.f;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              w *= L.cfa[t][d] + f3[e][h][d] * (L.cfb[t][d] + L.cfc[t][d] * f3[e][h][d]);
+            w = (live[e][h] && L.oo[t] < 27) ? w : 0.f;
+            acc[e][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e][h], w, acc[e][t], 0, 0, 0);
+          }
+    }
+    // lane (kq, r16) holds rows 4 kq + i of column r16 (offset o) of each
+    // tile: node value kq of node cell + o is row 4 kq + (1, ox, oy, oz).
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (kn[e] == 0) continue;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const floatx4_t a4 = acc[e][t];
+        const float v = a4[0] + L.fo[t][0] * a4[1] + L.fo[t][1] * a4[2] + L.fo[t][2] * a4[3];
+        if (L.oo[t] < 27) wnode[cb[e] + L.onode[t]][L.kq] += v;
+      }
+    }
+  }
+}
+
+}  // namespace dw

@@ -11,6 +11,7 @@
 
 #include "dw_internal.h"
 #include "dw_kernels.h"
+#include "dw_scatter.h"
 
 namespace dw {
 
@@ -236,24 +237,8 @@ struct PView {
   int n, n_regions;
 };
 
-constexpr int P2G_L = 6;        // local node extent of a cell tile's stencils
-constexpr int P2G_NODES = 216;  // 6^3
-constexpr int P2G_DAT = 16;     // staged floats per particle: f(3), m, m v - A f dx (3), A dx (9)
-constexpr int P2G_UNIT = 64;    // particles per pass-C unit (16 MFMA steps)
-constexpr int P2G_MAX_UNITS = 64 + WORK_CHUNK / P2G_UNIT;  // bounds the sum over cells of ceil(count / unit)
-constexpr int P2G_THREADS = WORK_CHUNK;
-constexpr int P2G_WAVES = P2G_THREADS / 64;
+constexpr int P2G_THREADS = SC_THREADS;
 constexpr int P2G_PER_CU = 1024 / P2G_THREADS;  // resident workgroups per compute unit
-
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
-
-// Stencil weight polynomial of offset component oo: w = a + b f + c f^2,
-// w0 = (3/2 - f)^2 / 2, w1 = 3/4 - (f - 1)^2, w2 = (f - 1/2)^2 / 2.
-__device__ __forceinline__ void p2g_coef(int oo, float &a, float &b, float &c) {
-  if (oo == 0) { a = 1.125f; b = -1.5f; c = 0.5f; }
-  else if (oo == 1) { a = -0.25f; b = 2.0f; c = -1.0f; }
-  else { a = 0.125f; b = -0.5f; c = 0.5f; }
-}
 
 // One workgroup (8 waves) per work item -- a chunk of at most WORK_CHUNK
 // sorted particles of one cell tile, so a dense tile is spread over several
@@ -261,70 +246,33 @@ __device__ __forceinline__ void p2g_coef(int oo, float &a, float &b, float &c) {
 // items from a ticket counter until the list is done.  No float atomics in LDS:
 // Pass A1: thread j takes the item's particle j, finds its cell in the tile
 //   (LDS histogram) and issues the loads of the rest of its state.
-// Pass B: exclusive scan of the 64 cell counts; each cell is cut into units
-//   of at most P2G_UNIT particles.
+// Pass B: exclusive scan of the 64 cell counts; cells cut into units.
 // Pass A2: the thread computes the stress (the polar decomposition), the
 //   MLS affine matrix A and the momentum and stages, at its particle's slot
-//   in cell order, f, m, q = m v - A f dx and A dx (16 floats, structure of
-//   arrays in LDS).
-// Pass C: per unit, one wave forms on the matrix cores (fp32 MFMA 16x16x4)
-//   the product Feat (13 x n) W (n x 27): Feat holds m, q and A dx of the
-//   unit's particles, W their 27 stencil weights w_o(f); four particles per
-//   MFMA, offsets in two 16-column tiles.  For offset o = (ox, oy, oz) the
-//   node contribution (sum w m, sum w q + (sum w A dx) o) is a linear
-//   combination of the 13 sums; the rows are ordered so that the four rows a
-//   lane holds give one node value, (1, ox, oy, oz) . rows.  The 27 x 4
-//   results go to distinct entries of the wave's own 6^3 node block in LDS
-//   (plain adds).
+//   in cell order, f, m, q = m v - A f dx and A dx.
+// Pass C: the units on the matrix cores into per-wave node blocks (the tile
+//   scatter of dw_scatter.h).
 // Pass D: the thread owning node n of the 6^3 region adds the 8 wave blocks
 //   in a fixed order and adds the total into the global grid with a
 //   hardware float atomic (nodes that received mass only).
 template <bool DET>
-__global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_p2g(GridDev g, PView P, float dt, int material,
-                                                     const int32_t *__restrict__ perm,
-                                                     const int32_t *__restrict__ tile_start,
-                                                     const int32_t *__restrict__ item_tile,
-                                                     const int32_t *__restrict__ item_begin,
-                                                     const int32_t *__restrict__ n_items, float *__restrict__ gm,
-                                                     float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status,
-                                                     float *__restrict__ item_part) {
+__global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_p2g(
+    GridDev g, PView P, float dt, int material, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ tile_start, const int32_t *__restrict__ item_tile,
+    const int32_t *__restrict__ item_begin, const int32_t *__restrict__ n_items, float *__restrict__ gm,
+    float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status, float *__restrict__ item_part) {
   static_assert(WORK_CHUNK == P2G_THREADS, "one staged particle per thread");
-  // staged particles in cell order; rows padded by 4 floats so that the 13
-  // feature rows read by one MFMA operand fall into distinct LDS banks
-  __shared__ float s_dat[P2G_DAT][WORK_CHUNK + 4];
-  __shared__ __attribute__((aligned(16))) float s_node[P2G_WAVES][P2G_NODES][4];  // per-wave node sums
+  __shared__ float s_dat[SC_DAT][SC_PITCH];                       // staged particles in cell order
+  __shared__ __attribute__((aligned(16))) float s_node[SC_WAVES][SC_NODES][4];  // per-wave node sums
   __shared__ int s_cnt[64], s_off[64], s_cur[64];
-  __shared__ int s_udesc[P2G_MAX_UNITS];  // unit: first slot | count << 10 | node base << 17
+  __shared__ int s_udesc[SC_MAX_UNITS];
   __shared__ int s_nunits, s_next;
   __shared__ unsigned char s_cell[WORK_CHUNK];
   const int n = P.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const float kstress = dt * 4.0f * g.inv_dx * g.inv_dx;
   const float dx = g.dx;
-  // MFMA 16x16x4 roles: r16 = row of the feature operand / column (stencil
-  // offset within a 16-wide tile) of the weight operand, kq = particle slot
-  const int r16 = lane & 15, kq = lane >> 4;
-  // staged feature of operand row r16, grouped so that result rows 4 kq ..
-  // 4 kq + 3 (held by lane group kq) all feed node value kq:
-  //   rows 0-3: m, -, -, -;  rows 4 + 4d .. 7 + 4d: q_d, (A dx)_d0, (A dx)_d1, (A dx)_d2
-  const int feat = r16 == 0 ? 3 : (r16 < 4 ? -1 : ((r16 & 3) == 0 ? 3 + (r16 >> 2) : 7 + 3 * ((r16 >> 2) - 1) + (r16 & 3) - 1));
-  // the two stencil offsets of this lane (tiles 0 and 1) and their weights
-  int oo[2], onode[2];
-  float cfa[2][3], cfb[2][3], cfc[2][3], fo[2][3];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    int o = t * 16 + r16;
-    oo[t] = o;
-    int oc = o < 27 ? o : 0;
-    int ox = oc % 3, oy = (oc / 3) % 3, oz = oc / 9;
-    onode[t] = ox + P2G_L * (oy + P2G_L * oz);  // node offset in the 6^3 region
-    p2g_coef(ox, cfa[t][0], cfb[t][0], cfc[t][0]);
-    p2g_coef(oy, cfa[t][1], cfb[t][1], cfc[t][1]);
-    p2g_coef(oz, cfa[t][2], cfb[t][2], cfc[t][2]);
-    fo[t][0] = (float)ox;
-    fo[t][1] = (float)oy;
-    fo[t][2] = (float)oz;
-  }
+  const ScLane L = sc_lane(lane);
   float *s_node_flat = &s_node[0][0][0];
   const int ni = *n_items;
   // items are handed out by a ticket counter (header word 8, cleared by the
@@ -338,7 +286,7 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
     const int nb = min(WORK_CHUNK, tile_start[tile + 1] - b0);
     const int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
     if (tid < 64) s_cnt[tid] = 0;
-    for (int q = tid; q < P2G_WAVES * P2G_NODES; q += P2G_THREADS)
+    for (int q = tid; q < SC_WAVES * SC_NODES; q += P2G_THREADS)
       reinterpret_cast<float4 *>(s_node_flat)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     // pass A1: this thread's particle -> cell and histogram; the rest of its
@@ -378,33 +326,8 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
     }
     s_cell[j] = c;
     __syncthreads();
-    // pass B: cell offsets (exclusive scan) and units (wave 0)
-    if (wid == 0) {
-      const int v = s_cnt[lane];
-      int inc = v;
-#pragma unroll
-      for (int sh = 1; sh < 64; sh <<= 1) {
-        int t = __shfl_up(inc, sh, 64);
-        if (lane >= sh) inc += t;
-      }
-      s_off[lane] = inc - v;
-      s_cur[lane] = inc - v;
-      // cell `lane` cut into ceil(v / P2G_UNIT) units, numbered cell by cell
-      const int nu = (v + P2G_UNIT - 1) / P2G_UNIT;
-      int uinc = nu;
-#pragma unroll
-      for (int sh = 1; sh < 64; sh <<= 1) {
-        int t = __shfl_up(uinc, sh, 64);
-        if (lane >= sh) uinc += t;
-      }
-      const int u0 = uinc - nu;
-      const int nbase = (lane & 3) + P2G_L * (((lane >> 2) & 3) + P2G_L * (lane >> 4));
-      for (int q = 0; q < nu; ++q) {
-        const int first = inc - v + q * P2G_UNIT;
-        s_udesc[u0 + q] = first | (min(P2G_UNIT, v - q * P2G_UNIT) << 10) | (nbase << 17);
-      }
-      if (lane == 63) s_nunits = uinc;
-    }
+    // pass B: cell offsets and units
+    if (wid == 0) sc_scan_units(lane, s_cnt, s_off, s_cur, s_udesc, &s_nunits);
     __syncthreads();
     // pass A2: stress, APIC matrix and momentum, staged at the particle's
     // slot in cell order
@@ -421,109 +344,38 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
       float mu, lam, tau[9];
       lame(Er, nur, mu, lam);
       kirchhoff_shift(H, mu, lam, material, tau, status);
-      const float fx = X - (float)base_of(X), fy = Y - (float)base_of(Y), fz = Z - (float)base_of(Z);
+      const float f[3] = {X - (float)base_of(X), Y - (float)base_of(Y), Z - (float)base_of(Z)};
       float A[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) A[q] = (m * Cm[q] - kstress * V0 * tau[q]) * dx;
-      s_dat[0][slot] = fx;
-      s_dat[1][slot] = fy;
-      s_dat[2][slot] = fz;
-      s_dat[3][slot] = m;
-      s_dat[4][slot] = m * vx - (A[0] * fx + A[1] * fy + A[2] * fz);
-      s_dat[5][slot] = m * vy - (A[3] * fx + A[4] * fy + A[5] * fz);
-      s_dat[6][slot] = m * vz - (A[6] * fx + A[7] * fy + A[8] * fz);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) s_dat[7 + q][slot] = A[q];
+      const float qv[3] = {m * vx - (A[0] * f[0] + A[1] * f[1] + A[2] * f[2]),
+                           m * vy - (A[3] * f[0] + A[4] * f[1] + A[5] * f[2]),
+                           m * vz - (A[6] * f[0] + A[7] * f[1] + A[8] * f[2])};
+      sc_stage(s_dat, slot, f, m, qv, A);
     }
     __syncthreads();
-    // pass C: per unit, Feat (13 x n) W (n x 27) on the matrix cores, added
-    // into this wave's node block; a wave works on two units at once
-    {
-      const int nunits = s_nunits;
-      float(*wnode)[4] = s_node[wid];
-      for (int u = wid; u < nunits; u += 2 * P2G_WAVES) {
-        int k0[2], kn[2], cb[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int ue = u + e * P2G_WAVES;
-          const int d = ue < nunits ? s_udesc[ue] : 0;
-          k0[e] = d & 1023;
-          kn[e] = (d >> 10) & 127;
-          cb[e] = d >> 17;
-        }
-        floatx4_t acc[2][2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-#pragma unroll
-          for (int t = 0; t < 2; ++t) acc[e][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        const int len = max(kn[0], kn[1]);
-        for (int kk = 0; kk < len; kk += 8) {
-          // LDS reads of both units' next eight particles first
-          float f3[2][2][3], av[2][2];
-          bool live[2][2];
-#pragma unroll
-          for (int e = 0; e < 2; ++e)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int r = kk + 4 * h + kq;
-              live[e][h] = r < kn[e];
-              const int jj = k0[e] + (live[e][h] ? r : 0);
-              f3[e][h][0] = s_dat[0][jj];
-              f3[e][h][1] = s_dat[1][jj];
-              f3[e][h][2] = s_dat[2][jj];
-              av[e][h] = (live[e][h] && feat >= 0) ? s_dat[feat < 0 ? 0 : feat][jj] : 0.f;
-            }
-#pragma unroll
-          for (int e = 0; e < 2; ++e)
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-              for (int t = 0; t < 2; ++t) {
-                float w = 1.f;
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                  w *= cfa[t][d] + f3[e][h][d] * (cfb[t][d] + cfc[t][d] * f3[e][h][d]);
-                w = (live[e][h] && oo[t] < 27) ? w : 0.f;
-                acc[e][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e][h], w, acc[e][t], 0, 0, 0);
-              }
-        }
-        // lane (kq, r16) holds rows 4 kq + i of column r16 (offset o) of each
-        // tile: node value kq of node cell + o is row 4 kq + (1, ox, oy, oz).
-        // A unit's 27 offsets reach 27 distinct nodes and the four lane
-        // groups write the four values: plain adds (a wave's units are
-        // added one after the other).
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          if (kn[e] == 0) continue;
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const floatx4_t a4 = acc[e][t];
-            const float v = a4[0] + fo[t][0] * a4[1] + fo[t][1] * a4[2] + fo[t][2] * a4[3];
-            if (oo[t] < 27) wnode[cb[e] + onode[t]][kq] += v;
-          }
-        }
-      }
-    }
+    // pass C
+    sc_units_mfma(L, wid, s_dat, s_udesc, s_nunits, s_node[wid]);
     __syncthreads();
     // pass D: node owners add the wave blocks in a fixed order
     if (tid == 0) s_next = atomicAdd(ticket, 1);
-    if (tid < P2G_NODES) {
+    if (tid < SC_NODES) {
       float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
-      for (int w = 0; w < P2G_WAVES; ++w) {
+      for (int w = 0; w < SC_WAVES; ++w) {
         sm += s_node[w][tid][0];
         s0 += s_node[w][tid][1];
         s1 += s_node[w][tid][2];
         s2 += s_node[w][tid][3];
       }
       if (DET) {
-        float *dst = item_part + ((int64_t)it * P2G_NODES + tid) * 4;
+        float *dst = item_part + ((int64_t)it * SC_NODES + tid) * 4;
         dst[0] = sm;
         dst[1] = s0;
         dst[2] = s1;
         dst[3] = s2;
       } else if (sm != 0.f) {
-        const int nx_ = tid % P2G_L, ny_ = (tid / P2G_L) % P2G_L, nz_ = tid / (P2G_L * P2G_L);
+        const int nx_ = tid % SC_L, ny_ = (tid / SC_L) % SC_L, nz_ = tid / (SC_L * SC_L);
         const int64_t node = (4 * tx + nx_) + (int64_t)g.nx * ((4 * ty + ny_) + (int64_t)g.ny * (4 * tz + nz_));
         atomicAdd(&gm[node], sm);
         atomicAdd(&gmv[node], s0);
@@ -573,9 +425,9 @@ __global__ __launch_bounds__(256) void k_p2g_det_gather(GridDev g, const int32_t
           if (cx < 0 || ox > 5) continue;
           int ct = cx + g.tx * (cy + g.ty * cz);
           int nitem = (tile_count[ct] + WORK_CHUNK - 1) / WORK_CHUNK;
-          int li = ox + P2G_L * (oy + P2G_L * oz);
+          int li = ox + SC_L * (oy + SC_L * oz);
           for (int q = 0; q < nitem; ++q) {
-            const float *src = item_part + ((int64_t)(item_first[ct] + q) * P2G_NODES + li) * 4;
+            const float *src = item_part + ((int64_t)(item_first[ct] + q) * SC_NODES + li) * 4;
             sm += src[0];
             s0 += src[1];
             s1 += src[2];

@@ -2,9 +2,10 @@
 //
 // Reverse P2G is a gather per particle (each particle reads the grid adjoint
 // at its 27 stencil nodes); reverse G2P is a sorted scatter (particles
-// grouped by cell tile, grid adjoint accumulated in an LDS tile and added to
-// the global grid with float atomics); reverse grid update is pointwise over
-// the active node tiles.  All adjoint outputs accumulate (+=).
+// grouped by cell tile, the grid adjoint summed on the matrix cores into LDS
+// node blocks and added to the global grid with float atomics); reverse grid
+// update is pointwise over the active node tiles.  All adjoint outputs
+// accumulate (+=).
 //
 // Forward definitions differentiated here: Eq. P2G with the MLS-MPM stress
 // term A = m C - dt V0 (4/dx^2) tau(F), the explicit grid update of
@@ -16,6 +17,7 @@
 
 #include "dw_internal.h"
 #include "dw_kernels.h"
+#include "dw_scatter.h"
 
 namespace dw {
 
@@ -114,6 +116,11 @@ __device__ __forceinline__ void kirchhoff_vjp(const float *H, float mu, float la
   }
 }
 
+// three consecutive floats (the x-neighbours of a stencil row)
+struct AdjRow {
+  float v[3];
+};
+
 // sum over the 64 lanes of a wave
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -174,19 +181,25 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
       float vbar[3] = {0.f, 0.f, 0.f}, xbar[3] = {0.f, 0.f, 0.f};
       float Abar[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       const float dx = g.dx;
-#pragma unroll
-      for (int oz = 0; oz < 3; ++oz)
-#pragma unroll
-        for (int oy = 0; oy < 3; ++oy)
+      // rows of the stencil one at a time (bounded register use), the three
+      // x-neighbours of a row read with one 12-byte load per array
+#pragma unroll 1
+      for (int r9 = 0; r9 < 9; ++r9) {
+        const int oy = r9 % 3, oz = r9 / 3;
+        const int64_t row = bx + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+        AdjRow rm, r0, r1, r2;
+        __builtin_memcpy(&rm, mbar + row, sizeof(AdjRow));
+        __builtin_memcpy(&r0, mvbar + row, sizeof(AdjRow));
+        __builtin_memcpy(&r1, mvbar + N + row, sizeof(AdjRow));
+        __builtin_memcpy(&r2, mvbar + 2 * N + row, sizeof(AdjRow));
+        const float wyz = w[1][oy] * w[2][oz], dwy = dw[1][oy] * w[2][oz], dwz = w[1][oy] * dw[2][oz];
 #pragma unroll
           for (int ox = 0; ox < 3; ++ox) {
-            int64_t node = (bx + ox) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
-            float wt = w[0][ox] * w[1][oy] * w[2][oz];
-            float gw[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * g.inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * g.inv_dx,
-                           w[0][ox] * w[1][oy] * dw[2][oz] * g.inv_dx};
+            float wt = w[0][ox] * wyz;
+            float gw[3] = {dw[0][ox] * wyz * g.inv_dx, w[0][ox] * dwy * g.inv_dx, w[0][ox] * dwz * g.inv_dx};
             float d[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
-            float mb = mbar[node];
-            float gb[3] = {mvbar[node], mvbar[N + node], mvbar[2 * N + node]};
+            float mb = rm.v[ox];
+            float gb[3] = {r0.v[ox], r1.v[ox], r2.v[ox]};
             float c[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) c[a] = mom[a] + A[3 * a] * d[0] + A[3 * a + 1] * d[1] + A[3 * a + 2] * d[2];
@@ -200,6 +213,7 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
               for (int b = 0; b < 3; ++b) Abar[3 * a + b] += wt * gb[a] * d[b];
             }
           }
+      }
       if (P.vb) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) P.vb[a * n + p] += vbar[a];
@@ -228,14 +242,17 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
     }
   }
   if (P.Eb) {
-    // regions are usually uniform across a wave: reduce there, else per-lane atomics
-    int r0 = __shfl(r, 0, 64);
-    bool uniform = __all(!live || r == r0);
-    if (uniform) {
-      float s = wave_sum(live ? Ebar_p : 0.f);
-      if ((threadIdx.x & 63) == 0 && s != 0.f) atomicAdd(&P.Eb[r0], s);
-    } else if (live && Ebar_p != 0.f) {
-      atomicAdd(&P.Eb[r], Ebar_p);
+    // one atomic per (wave, region): a wave holds few regions, while
+    // per-lane atomics on a handful of addresses would serialise
+    unsigned long long pending = __ballot(live);
+    const int lane = threadIdx.x & 63;
+    while (pending) {
+      const int leader = __ffsll(pending) - 1;
+      const int rk = __shfl(r, leader, 64);
+      const bool mine = live && r == rk;
+      const float sum = wave_sum(mine ? Ebar_p : 0.f);
+      if (lane == leader && sum != 0.f) atomicAdd(&P.Eb[rk], sum);
+      pending &= ~__ballot(mine);
     }
   }
 }
@@ -285,35 +302,64 @@ __global__ __launch_bounds__(256) void k_grid_update_adj(GridDev g, float dt, fl
 }
 
 // ---------------------------------------------------------- reverse G2P
-constexpr int ADJ_L = 6;
-constexpr int ADJ_NODES = 216;
 
-__global__ __launch_bounds__(256) void k_g2p_adj(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
-                                                 const float *__restrict__ x, const float *__restrict__ F, int n,
-                                                 const float *__restrict__ xob, const float *__restrict__ vob,
-                                                 const float *__restrict__ Cob, const float *__restrict__ Fob,
-                                                 float *__restrict__ xb, float *__restrict__ Fb,
-                                                 float *__restrict__ gvb, const int32_t *__restrict__ perm,
-                                                 const int32_t *__restrict__ tile_start,
-                                                 const int32_t *__restrict__ cell_tiles,
-                                                 const int32_t *__restrict__ n_tiles) {
-  __shared__ float s_acc[3][ADJ_NODES];
-  int nt = *n_tiles;
+// Reverse G2P.  One workgroup per work item (a chunk of at most WORK_CHUNK
+// sorted particles of one cell tile), one particle per thread.  Each thread
+// redoes the forward gather of its particle (v_p and C_p), applies the
+// adjoints of the x, F and C updates and gathers x_bar; the scatter of the
+// grid-velocity adjoint, v_bar_i += w_ip (vbt_p + kc Cbt_p (o - f_p)), has
+// the P2G form w (q + A o) with q = vbt - kc Cbt f, A = kc Cbt and runs as
+// the tile scatter of dw_scatter.h; node owners add the result into the
+// global grid adjoint with float atomics.
+__global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_g2p_adj(
+    GridDev g, float dt, const float *__restrict__ gv, int64_t N, const float *__restrict__ x,
+    const float *__restrict__ F, int n, const float *__restrict__ xob, const float *__restrict__ vob,
+    const float *__restrict__ Cob, const float *__restrict__ Fob, float *__restrict__ xb, float *__restrict__ Fb,
+    float *__restrict__ gvb, const int32_t *__restrict__ perm, const int32_t *__restrict__ tile_start,
+    const int32_t *__restrict__ item_tile, const int32_t *__restrict__ item_begin,
+    const int32_t *__restrict__ n_items) {
+  __shared__ float s_dat[SC_DAT][SC_PITCH];
+  __shared__ __attribute__((aligned(16))) float s_node[SC_WAVES][SC_NODES][4];
+  __shared__ int s_cnt[64], s_off[64], s_cur[64];
+  __shared__ int s_udesc[SC_MAX_UNITS];
+  __shared__ int s_nunits;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const ScLane L = sc_lane(lane);
+  float *s_node_flat = &s_node[0][0][0];
+  const int ni = *n_items;
   const float kc = 4.0f * g.inv_dx;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
-    int tile = cell_tiles[it];
-    int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
-    for (int q = threadIdx.x; q < 3 * ADJ_NODES; q += blockDim.x) (&s_acc[0][0])[q] = 0.f;
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int tile = item_tile[it];
+    const int b0 = item_begin[it];
+    const int nb = min(WORK_CHUNK, tile_start[tile + 1] - b0);
+    const int tx = tile % g.tx, ty = (tile / g.tx) % g.ty, tz = tile / (g.tx * g.ty);
+    if (tid < 64) s_cnt[tid] = 0;
+    for (int q = tid; q < SC_WAVES * SC_NODES; q += SC_THREADS)
+      reinterpret_cast<float4 *>(s_node_flat)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    int beg = tile_start[tile], end = tile_start[tile + 1];
-    for (int j = beg + threadIdx.x; j < end; j += blockDim.x) {
-      int p = perm[j];
-      float X = grid_coord(x[p], g.ox, g.inv_dx);
-      float Y = grid_coord(x[n + p], g.oy, g.inv_dx);
-      float Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
-      int bx = base_of(X), by = base_of(Y), bz = base_of(Z);
-      int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
-      if ((unsigned)lx > 3u || (unsigned)ly > 3u || (unsigned)lz > 3u) continue;
+    // particle -> cell in the tile
+    const bool has = tid < nb;
+    const int p = has ? perm[b0 + tid] : 0;
+    float X = 0.f, Y = 0.f, Z = 0.f;
+    int bx = 0, by = 0, bz = 0, c = -1;
+    if (has) {
+      X = grid_coord(x[p], g.ox, g.inv_dx);
+      Y = grid_coord(x[n + p], g.oy, g.inv_dx);
+      Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
+      bx = base_of(X);
+      by = base_of(Y);
+      bz = base_of(Z);
+      const int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
+      if ((unsigned)lx <= 3u && (unsigned)ly <= 3u && (unsigned)lz <= 3u) {
+        c = lx + 4 * (ly + 4 * lz);
+        atomicAdd(&s_cnt[c], 1);
+      }
+    }
+    __syncthreads();
+    if (wid == 0) sc_scan_units(lane, s_cnt, s_off, s_cur, s_udesc, &s_nunits);
+    __syncthreads();
+    if (c >= 0) {
+      const int slot = atomicAdd(&s_cur[c], 1);
       float f[3] = {X - (float)bx, Y - (float)by, Z - (float)bz};
       float w[3][3], dw[3][3];
 #pragma unroll
@@ -324,23 +370,27 @@ __global__ __launch_bounds__(256) void k_g2p_adj(GridDev g, float dt, const floa
       // forward gather: v_p and C_p
       float vp[3] = {0.f, 0.f, 0.f};
       float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+      for (int r9 = 0; r9 < 9; ++r9) {
+        const int oy = r9 % 3, oz = r9 / 3;
+        const int64_t row = bx + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+        AdjRow r0, r1, r2;
+        __builtin_memcpy(&r0, gv + row, sizeof(AdjRow));
+        __builtin_memcpy(&r1, gv + N + row, sizeof(AdjRow));
+        __builtin_memcpy(&r2, gv + 2 * N + row, sizeof(AdjRow));
 #pragma unroll
-      for (int oz = 0; oz < 3; ++oz)
+        for (int ox = 0; ox < 3; ++ox) {
+          const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+          const float vi[3] = {r0.v[ox], r1.v[ox], r2.v[ox]};
+          const float o[3] = {(float)ox - f[0], (float)oy - f[1], (float)oz - f[2]};
 #pragma unroll
-        for (int oy = 0; oy < 3; ++oy)
+          for (int a = 0; a < 3; ++a) {
+            vp[a] += wt * vi[a];
 #pragma unroll
-          for (int ox = 0; ox < 3; ++ox) {
-            int64_t node = (bx + ox) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
-            float wt = w[0][ox] * w[1][oy] * w[2][oz];
-            float vi[3] = {gv[node], gv[N + node], gv[2 * N + node]};
-            float o[3] = {(float)ox - f[0], (float)oy - f[1], (float)oz - f[2]};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              vp[a] += wt * vi[a];
-#pragma unroll
-              for (int b = 0; b < 3; ++b) B[3 * a + b] += wt * vi[a] * o[b];
-            }
+            for (int b = 0; b < 3; ++b) B[3 * a + b] += wt * vi[a] * o[b];
           }
+        }
+      }
       float Cn[9], Fp[9], Fo[9], Cbt[9], vbt[3];
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -354,7 +404,9 @@ __global__ __launch_bounds__(256) void k_g2p_adj(GridDev g, float dt, const floa
         float G[9], GtFo[9], FoFt[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) G[q] = dt * Cn[q];
-        G[0] += 1.f; G[4] += 1.f; G[8] += 1.f;
+        G[0] += 1.f;
+        G[4] += 1.f;
+        G[8] += 1.f;
         matmul3_atb(G, Fo, GtFo);
         matmul3_abt(Fo, Fp, FoFt);
         if (Fb) {
@@ -366,52 +418,66 @@ __global__ __launch_bounds__(256) void k_g2p_adj(GridDev g, float dt, const floa
       }
       // x' = x + dt v_p
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float xo = xob ? xob[a * n + p] : 0.f;
-        vbt[a] = (vob ? vob[a * n + p] : 0.f) + dt * xo;
-      }
+      for (int a = 0; a < 3; ++a) vbt[a] = (vob ? vob[a * n + p] : 0.f) + dt * (xob ? xob[a * n + p] : 0.f);
+      // x_bar: gradient of the gather through the weights and the offsets
       float xbar[3] = {xob ? xob[p] : 0.f, xob ? xob[n + p] : 0.f, xob ? xob[2 * n + p] : 0.f};
+#pragma unroll 1
+      for (int r9 = 0; r9 < 9; ++r9) {
+        const int oy = r9 % 3, oz = r9 / 3;
+        const int64_t row = bx + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+        AdjRow r0, r1, r2;
+        __builtin_memcpy(&r0, gv + row, sizeof(AdjRow));
+        __builtin_memcpy(&r1, gv + N + row, sizeof(AdjRow));
+        __builtin_memcpy(&r2, gv + 2 * N + row, sizeof(AdjRow));
 #pragma unroll
-      for (int oz = 0; oz < 3; ++oz)
+        for (int ox = 0; ox < 3; ++ox) {
+          const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+          const float gw[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * g.inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * g.inv_dx,
+                               w[0][ox] * w[1][oy] * dw[2][oz] * g.inv_dx};
+          const float o[3] = {(float)ox - f[0], (float)oy - f[1], (float)oz - f[2]};
+          const float vi[3] = {r0.v[ox], r1.v[ox], r2.v[ox]};
+          float Co[3], CtV[3];
 #pragma unroll
-        for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-          for (int ox = 0; ox < 3; ++ox) {
-            int64_t node = (bx + ox) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
-            float wt = w[0][ox] * w[1][oy] * w[2][oz];
-            float gw[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * g.inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * g.inv_dx,
-                           w[0][ox] * w[1][oy] * dw[2][oz] * g.inv_dx};
-            float o[3] = {(float)ox - f[0], (float)oy - f[1], (float)oz - f[2]};
-            float vi[3] = {gv[node], gv[N + node], gv[2 * N + node]};
-            // C = kc sum w v o^T: v_i bar += w (vbt + kc Cbt o)
-            float Co[3], CtV[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              Co[a] = Cbt[3 * a] * o[0] + Cbt[3 * a + 1] * o[1] + Cbt[3 * a + 2] * o[2];
-              CtV[a] = Cbt[a] * vi[0] + Cbt[3 + a] * vi[1] + Cbt[6 + a] * vi[2];
-            }
-            float s = vi[0] * vbt[0] + vi[1] * vbt[1] + vi[2] * vbt[2] + kc * (vi[0] * Co[0] + vi[1] * Co[1] + vi[2] * Co[2]);
-            // d o / d x = -inv_dx I
-#pragma unroll
-            for (int a = 0; a < 3; ++a) xbar[a] += gw[a] * s - wt * kc * g.inv_dx * CtV[a];
-            int li = (lx + ox) + ADJ_L * ((ly + oy) + ADJ_L * (lz + oz));
-#pragma unroll
-            for (int a = 0; a < 3; ++a) atomicAdd(&s_acc[a][li], wt * (vbt[a] + kc * Co[a]));
+          for (int a = 0; a < 3; ++a) {
+            Co[a] = Cbt[3 * a] * o[0] + Cbt[3 * a + 1] * o[1] + Cbt[3 * a + 2] * o[2];
+            CtV[a] = Cbt[a] * vi[0] + Cbt[3 + a] * vi[1] + Cbt[6 + a] * vi[2];
           }
+          const float sdot =
+              vi[0] * vbt[0] + vi[1] * vbt[1] + vi[2] * vbt[2] + kc * (vi[0] * Co[0] + vi[1] * Co[1] + vi[2] * Co[2]);
+          // d o / d x = -inv_dx I
+#pragma unroll
+          for (int a = 0; a < 3; ++a) xbar[a] += gw[a] * sdot - wt * kc * g.inv_dx * CtV[a];
+        }
+      }
       if (xb) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) xb[a * n + p] += xbar[a];
       }
+      // scatter features: q = vbt - kc Cbt f, A = kc Cbt
+      float A[9], qv[3];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) A[q] = kc * Cbt[q];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) qv[a] = vbt[a] - (A[3 * a] * f[0] + A[3 * a + 1] * f[1] + A[3 * a + 2] * f[2]);
+      sc_stage(s_dat, slot, f, 0.f, qv, A);
     }
     __syncthreads();
-    for (int li = threadIdx.x; li < ADJ_NODES; li += blockDim.x) {
-      float a0 = s_acc[0][li], a1 = s_acc[1][li], a2 = s_acc[2][li];
-      if (a0 != 0.f || a1 != 0.f || a2 != 0.f) {
-        int ix = li % ADJ_L, iy = (li / ADJ_L) % ADJ_L, iz = li / (ADJ_L * ADJ_L);
-        int64_t node = (4 * tx + ix) + (int64_t)g.nx * ((4 * ty + iy) + (int64_t)g.ny * (4 * tz + iz));
-        atomicAdd(&gvb[node], a0);
-        atomicAdd(&gvb[N + node], a1);
-        atomicAdd(&gvb[2 * N + node], a2);
+    sc_units_mfma(L, wid, s_dat, s_udesc, s_nunits, s_node[wid]);
+    __syncthreads();
+    if (tid < SC_NODES) {
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int w = 0; w < SC_WAVES; ++w) {
+        s0 += s_node[w][tid][1];
+        s1 += s_node[w][tid][2];
+        s2 += s_node[w][tid][3];
+      }
+      if (s0 != 0.f || s1 != 0.f || s2 != 0.f) {
+        const int ix = tid % SC_L, iy = (tid / SC_L) % SC_L, iz = tid / (SC_L * SC_L);
+        const int64_t node = (4 * tx + ix) + (int64_t)g.nx * ((4 * ty + iy) + (int64_t)g.ny * (4 * tz + iz));
+        atomicAdd(&gvb[node], s0);
+        atomicAdd(&gvb[N + node], s1);
+        atomicAdd(&gvb[2 * N + node], s2);
       }
     }
     __syncthreads();
@@ -482,8 +548,8 @@ extern "C" int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, con
   if (rc) return rc;
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
-  hipLaunchKernelGGL(k_g2p_adj, dim3(2048), dim3(256), 0, (hipStream_t)stream, g, params->dt, grid_v, N, in->x,
-                     in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F, grid_v_bar,
-                     W.perm, W.tile_start, W.cell_tiles, W.n_cell_tiles);
+  hipLaunchKernelGGL(k_g2p_adj, dim3(2048), dim3(SC_THREADS), 0, (hipStream_t)stream, g, params->dt, grid_v, N,
+                     in->x, in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F,
+                     grid_v_bar, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items);
   return check_launch("mpm_g2p_adj");
 }
