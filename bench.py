@@ -51,6 +51,31 @@ def _args():
     return ap.parse_args()
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic_500k_grid128.md")
+TRAFFIC_SOURCES = ("csrc/mpm.hip", "csrc/dw_scatter.h", "csrc/dw_internal.h")
+
+
+def _measured_traffic(phase):
+    """HBM bytes per launch of `phase` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, if the kernel sources are the ones it was taken
+    with; else None."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic %s bytes=(\d+) sha256=([0-9a-f]{64})$" % phase, text, re.M)
+    if not m:
+        return None
+    pkg = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_09668_amd")
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(pkg, f), "rb") as fh:
+            h.update(fh.read())
+    return int(m.group(1)) if h.hexdigest() == m.group(2) else None
+
+
 def _graph_ms(fn, reps=5):
     """Average time of fn() captured in a HIP graph, by events on the stream."""
     import torch
@@ -365,7 +390,7 @@ def main():
         "phase_sum_ms": sum(ph_ms.values()),
         "status": status,
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant),
                      "algorithmic_bytes": bytes_per.get(dominant)},
     }
     if not a.no_surrogate:
