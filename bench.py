@@ -51,29 +51,29 @@ def _args():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic_500k_grid128.md")
+TRAFFIC_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 TRAFFIC_SOURCES = ("csrc/mpm.hip", "csrc/dw_scatter.h", "csrc/dw_internal.h")
 
 
-def _measured_traffic(phase):
-    """HBM bytes per launch of `phase` from the committed FETCH_SIZE /
-    WRITE_SIZE summary, if the kernel sources are the ones it was taken
-    with; else None."""
+def _measured_traffic(phase, n, res):
+    """HBM bytes per launch of `phase` on this workload (n particles, res^3
+    grid) from a committed FETCH_SIZE / WRITE_SIZE summary, if the kernel
+    sources are the ones it was taken with; else None."""
+    import glob
     import hashlib
     import re
-    try:
-        text = open(TRAFFIC_FILE).read()
-    except OSError:
-        return None
-    m = re.search(r"^traffic %s bytes=(\d+) sha256=([0-9a-f]{64})$" % phase, text, re.M)
-    if not m:
-        return None
     pkg = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_09668_amd")
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
-    return int(m.group(1)) if h.hexdigest() == m.group(2) else None
+    pat = re.compile(r"^traffic %s n=%d res=%d bytes=(\d+) sha256=([0-9a-f]{64})$" % (phase, n, res), re.M)
+    for path in sorted(glob.glob(os.path.join(TRAFFIC_DIR, "hbm_traffic_*.md"))):
+        with open(path) as fh:
+            m = pat.search(fh.read())
+        if m and m.group(2) == h.hexdigest():
+            return int(m.group(1))
+    return None
 
 
 def _graph_ms(fn, reps=5):
@@ -390,7 +390,7 @@ def main():
         "phase_sum_ms": sum(ph_ms.values()),
         "status": status,
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant),
+                     "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant, a.n, a.res),
                      "algorithmic_bytes": bytes_per.get(dominant)},
     }
     if not a.no_surrogate:

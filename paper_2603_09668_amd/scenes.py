@@ -60,13 +60,13 @@ def _sort_spatially(x, dx, origin):
 def _pin_boxes(grid, boxes):
     nx, ny, nz, dx = grid["nx"], grid["ny"], grid["nz"], grid["dx"]
     o = np.asarray(grid["origin"])
-    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    pos = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1) * dx + o
-    pin = np.zeros(nx * ny * nz, dtype=np.uint8)
+    # node positions per axis (i dx + origin); a box is a product of ranges
+    axes = [np.arange(m) * dx + o[a] for a, m in enumerate((nx, ny, nz))]
+    pin = np.zeros((nz, ny, nx), dtype=np.uint8)
     for lo, hi in boxes:
-        inside = np.all((pos >= np.asarray(lo)) & (pos <= np.asarray(hi)), axis=1)
-        pin[inside] = 1
-    return pin
+        ix, iy, iz = [np.nonzero((axes[a] >= lo[a]) & (axes[a] <= hi[a]))[0] for a in range(3)]
+        pin[np.ix_(iz, iy, ix)] = 1
+    return pin.reshape(-1)
 
 
 def _cfl_dt(E_max, nu, rho, dx, cfl=0.4):
