@@ -311,16 +311,20 @@ def main():
     torch.cuda.synchronize()
     if sim.status() != 0:
         print(f"[bench] status word {sim.status()} after warm-up", file=sys.stderr)
-    # the whole step as a HIP graph of two substeps, replayed
-    sim.capture(2)
+    # the whole step as a HIP graph of two substeps, replayed; the serial
+    # graph (one stream) is timed too, for reference
     steps = a.steps + (a.steps % 2)
-    sim.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps // 2):
+    timed = {}
+    for concurrent in (False, True):
+        sim.capture(2, concurrent=concurrent)
         sim.replay()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps // 2):
+            sim.replay()
+        torch.cuda.synchronize()
+        timed[concurrent] = time.perf_counter() - t0
+    elapsed = timed[True]
     a.steps = steps
     status = sim.status()
     active_nodes = sim.active_nodes()
@@ -375,6 +379,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": elapsed * 1e3 / a.steps,
+        "ms_per_step_one_stream": timed[False] * 1e3 / a.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -183,23 +183,35 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
                                                         float *__restrict__ fout, const uint8_t *__restrict__ solid,
                                                         float *__restrict__ rho_out, float *__restrict__ u_out) {
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  __shared__ int s_any[LBM_BLOCK / 64];
   const int x0 = blockIdx.x * LBM_BLOCK;
   const int i = x0 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
   if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
   const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
   float f[19];
+  // any solid flag in the staged rows?  Most blocks have none and take the
+  // plain pull (block-uniform branch).
+  bool any = false;
   if (SOLID) {
     uint32_t sv[SOL_PER_THREAD];
     load_solid_rows(P, solid, x0, j, k, sv);
     store_solid_rows(sv, s_sol);
+    uint32_t mine = 0;
+#pragma unroll
+    for (int u = 0; u < SOL_PER_THREAD; ++u) mine |= sv[u];
+    const bool wave_any = __ballot(mine != 0) != 0ull;
+    if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = wave_any;
     __syncthreads();
-    if (i >= P.nx) return;
+#pragma unroll
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) any = any || s_any[w] != 0;
+  }
+  if (i >= P.nx) return;
+  if (any) {
     if (!s_sol[4][i - x0 + 4]) pull_all<1>(P, fin, solid, s_sol, i, j, k, x0, node, f);
   } else {
-    if (i >= P.nx) return;
     pull_all<0>(P, fin, solid, s_sol, i, j, k, x0, node, f);
   }
-  if (SOLID && s_sol[4][i - x0 + 4]) {
+  if (any && s_sol[4][i - x0 + 4]) {
 #pragma unroll
     for (int q = 0; q < 19; ++q) fout[(int64_t)q * P.L + node] = 0.f;
     if (rho_out) rho_out[node] = 1.f;

@@ -124,44 +124,41 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *__res
   }
 }
 
-// single block: exclusive scan of the four block-sum rows, in place; writes totals
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int32_t *__restrict__ block_sums, int64_t NB,
-                                                         int32_t *__restrict__ totals /* [4] */) {
-  __shared__ int lds[128];
-  for (int r = 0; r < 4; ++r) {
-    int carry = 0;
-    for (int64_t b0 = 0; b0 < NB; b0 += SCAN_BLOCK) {
-      int64_t b = b0 + threadIdx.x;
-      int v = b < NB ? block_sums[r * NB + b] : 0;
-      int tot;
-      int ex = block_excl_scan(v, lds, &tot);
-      if (b < NB) block_sums[r * NB + b] = ex + carry;
-      carry += tot;
-    }
-    if (threadIdx.x == 0) totals[r] = carry;
-    __syncthreads();
-  }
-}
-
 // Final pass: tile offsets, the compacted active cell / node tile lists and
 // the work items (a cell tile cut into chunks of at most WORK_CHUNK sorted
-// particles: item = (tile, first particle)).
+// particles: item = (tile, first particle)).  Each block adds up the block
+// sums of the blocks before it itself (there are few: T / SCAN_BLOCK per
+// row), and block 0 writes the four totals.
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
     const int32_t *__restrict__ count, const int32_t *__restrict__ flag, int64_t T,
     const int32_t *__restrict__ block_sums, int64_t NB, int32_t *__restrict__ tile_start,
     int32_t *__restrict__ cell_tiles, int32_t *__restrict__ node_tiles, int32_t *__restrict__ item_tile,
-    int32_t *__restrict__ item_begin, int32_t *__restrict__ item_first) {
+    int32_t *__restrict__ item_begin, int32_t *__restrict__ item_first, int32_t *__restrict__ totals /* [4] */) {
   __shared__ int lds[128];
+  int pre[4];
+  for (int r = 0; r < 4; ++r) {
+    int before = 0, all = 0;
+    for (int64_t b = threadIdx.x; b < NB; b += SCAN_BLOCK) {
+      const int v = block_sums[r * NB + b];
+      all += v;
+      if (b < (int64_t)blockIdx.x) before += v;
+    }
+    int tb, ta;
+    block_excl_scan(before, lds, &tb);
+    block_excl_scan(all, lds, &ta);
+    pre[r] = tb;
+    if (blockIdx.x == 0 && threadIdx.x == 0) totals[r] = ta;
+  }
   int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
   int c = i < T ? count[i] : 0;
   int f = i < T ? (flag[i] != 0) : 0;
   int nz = c > 0;
   int ch = (c + WORK_CHUNK - 1) / WORK_CHUNK;
   int tc, tf, tn, th;
-  int ec = block_excl_scan(c, lds, &tc) + block_sums[blockIdx.x];
-  int ef = block_excl_scan(f, lds, &tf) + block_sums[NB + blockIdx.x];
-  int en = block_excl_scan(nz, lds, &tn) + block_sums[2 * NB + blockIdx.x];
-  int eh = block_excl_scan(ch, lds, &th) + block_sums[3 * NB + blockIdx.x];
+  int ec = block_excl_scan(c, lds, &tc) + pre[0];
+  int ef = block_excl_scan(f, lds, &tf) + pre[1];
+  int en = block_excl_scan(nz, lds, &tn) + pre[2];
+  int eh = block_excl_scan(ch, lds, &th) + pre[3];
   if (i < T) {
     tile_start[i] = ec;
     item_first[i] = eh;
@@ -275,12 +272,14 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
   const ScLane L = sc_lane(lane);
   float *s_node_flat = &s_node[0][0][0];
   const int ni = *n_items;
-  // items are handed out by a ticket counter (header word 8, cleared by the
-  // sort); the next ticket is drawn during the current item
+  // Workgroup b starts with item b (no stampede on the counter at launch);
+  // later items are handed out by a ticket counter (header word 8, cleared
+  // by the sort) as items gridDim.x + ticket.  The last wave, which owns no
+  // node in pass D, draws the next ticket there, so the atomic's round trip
+  // overlaps the node owners' work.
+  static_assert(P2G_THREADS - 64 >= SC_NODES, "the last wave owns no node");
   int32_t *ticket = status + 8;
-  if (tid == 0) s_next = atomicAdd(ticket, 1);
-  __syncthreads();
-  for (int it = s_next; it < ni; it = s_next) {
+  for (int it = blockIdx.x; it < ni; it = s_next) {
     const int tile = item_tile[it];
     const int b0 = item_begin[it];
     const int nb = min(WORK_CHUNK, tile_start[tile + 1] - b0);
@@ -358,7 +357,7 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
     sc_units_mfma(L, wid, s_dat, s_udesc, s_nunits, s_node[wid]);
     __syncthreads();
     // pass D: node owners add the wave blocks in a fixed order
-    if (tid == 0) s_next = atomicAdd(ticket, 1);
+    if (tid == P2G_THREADS - 1) s_next = (int)gridDim.x + atomicAdd(ticket, 1);
     if (tid < SC_NODES) {
       float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
@@ -555,6 +554,11 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
     a = 1.5f - fz; b = fz - 1.0f; c = fz - 0.5f;
     wz[0] = 0.5f * a * a; wz[1] = 0.75f - b * b; wz[2] = 0.5f * c * c;
   }
+  // Separable sums over the stencil, row by row (a row = the three
+  // x-neighbours at fixed oy, oz):
+  //   v = sum w u,   B = sum w u (o - f)^T = sum w u o^T - v f^T,
+  // with per row r0 = sum_ox wx u and r1 = sum_ox wx ox u, the row weight
+  // wy wz scaling r0 (v and the y, z columns of B) and r1 (the x column).
   float v0 = 0.f, v1 = 0.f, v2 = 0.f;
   float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -568,18 +572,29 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
       __builtin_memcpy(&ra, gv + row, sizeof(Float3));
       __builtin_memcpy(&rb, gv + N + row, sizeof(Float3));
       __builtin_memcpy(&rc, gv + 2 * N + row, sizeof(Float3));
-#pragma unroll
-      for (int ox = 0; ox < 3; ++ox) {
-        float w = wx[ox] * wy[oy] * wz[oz];
-        float a = ra.v[ox], b = rb.v[ox], c = rc.v[ox];
-        float dxo = (float)ox - fx, dyo = (float)oy - fy, dzo = (float)oz - fz;
-        v0 += w * a; v1 += w * b; v2 += w * c;
-        float wa = w * a, wb = w * b, wc = w * c;
-        B[0] += wa * dxo; B[1] += wa * dyo; B[2] += wa * dzo;
-        B[3] += wb * dxo; B[4] += wb * dyo; B[5] += wb * dzo;
-        B[6] += wc * dxo; B[7] += wc * dyo; B[8] += wc * dzo;
+      const float u0[3] = {ra.v[0] * wx[0] + ra.v[1] * wx[1] + ra.v[2] * wx[2],
+                           rb.v[0] * wx[0] + rb.v[1] * wx[1] + rb.v[2] * wx[2],
+                           rc.v[0] * wx[0] + rc.v[1] * wx[1] + rc.v[2] * wx[2]};
+      const float w2 = 2.0f * wx[2];
+      const float u1[3] = {ra.v[1] * wx[1] + ra.v[2] * w2, rb.v[1] * wx[1] + rb.v[2] * w2,
+                           rc.v[1] * wx[1] + rc.v[2] * w2};
+      const float wyz = wy[oy] * wz[oz];
+      v0 += wyz * u0[0]; v1 += wyz * u0[1]; v2 += wyz * u0[2];
+      B[0] += wyz * u1[0]; B[3] += wyz * u1[1]; B[6] += wyz * u1[2];
+      if (oy > 0) {
+        const float wy_ = wyz * (float)oy;
+        B[1] += wy_ * u0[0]; B[4] += wy_ * u0[1]; B[7] += wy_ * u0[2];
+      }
+      if (oz > 0) {
+        const float wz_ = wyz * (float)oz;
+        B[2] += wz_ * u0[0]; B[5] += wz_ * u0[1]; B[8] += wz_ * u0[2];
       }
     }
+  const float vv[3] = {v0, v1, v2}, ff[3] = {fx, fy, fz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) B[3 * a + b] -= vv[a] * ff[b];
   // C = (4/dx^2) sum w v d^T with d = (o - f) dx  ->  (4/dx) sum w v (o - f)^T
   float kc = 4.0f * g.inv_dx;
   float Cn[9];
@@ -649,10 +664,9 @@ int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, cons
                        W.node_flag, W.status);
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
                      W.block_sums, NB);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, W.block_sums, NB, W.status + 3);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
                      W.block_sums, NB, W.tile_start, W.cell_tiles, W.node_tiles, W.item_tile, W.item_begin,
-                     W.item_first);
+                     W.item_first, W.status + 3);
   if (n > 0) {
     int32_t *dst = deterministic ? W.perm_tmp : W.perm;
     hipLaunchKernelGGL(k_sort_scatter, dim3(grid_blocks(n, 256)), dim3(256), 0, s, W.key, n, W.tile_start,

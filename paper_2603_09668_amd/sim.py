@@ -7,8 +7,10 @@ One coupled step runs, on torch's current stream:
   4. mpm_p2g                   -- Eq. P2G with the MLS stress term
   5. mpm_grid_update           -- gravity, LBM drag wind (Sec. 3.4), walls, pins
   6. mpm_g2p                   -- Eq. G2P, APIC C, Eq. deformation_update (in place)
-All buffers are allocated once here; a step allocates nothing, and every
-launch has a data-independent shape (persistent kernels read their work
+Steps 1-2 (the wind branch) and 3-4 (the particle branch) are independent
+and can run side by side on two streams (`step(side)`, the default in a
+captured graph).  All buffers are allocated once here; a step allocates
+nothing, and every launch has a data-independent shape (persistent kernels read their work
 counts from device memory), so a pair of substeps can be captured once in a
 HIP graph and replayed: `capture()` / `replay()`.
 """
@@ -105,20 +107,43 @@ class CoupledSim:
 
     PHASES = ("voxelize", "lbm", "sort", "p2g", "grid_update", "g2p")
 
-    def step(self):
-        for ph in self.PHASES:
-            getattr(self, ph)()
+    def step(self, side=None):
+        """One coupled substep on the current stream.  With a `side` stream the
+        wind branch (voxelize, LBM) runs on it beside the particle branch
+        (sort, P2G): the two touch disjoint buffers and both read only the
+        positions the previous G2P wrote; the grid update waits for both."""
+        if side is None:
+            for ph in self.PHASES:
+                getattr(self, ph)()
+            return
+        main = torch.cuda.current_stream()
+        fork = torch.cuda.Event()
+        fork.record(main)
+        side.wait_event(fork)
+        with torch.cuda.stream(side):
+            self.voxelize()
+            self.lbm()
+        self.sort()
+        self.p2g()
+        join = torch.cuda.Event()
+        join.record(side)
+        main.wait_event(join)
+        self.grid_update()
+        self.g2p()
 
-    def capture(self, substeps: int = 2):
+    def capture(self, substeps: int = 2, concurrent: bool = True):
         """Record `substeps` coupled substeps (an even number of LBM steps, so
-        the ping-pong buffers return to their roles) in one HIP graph."""
+        the ping-pong buffers return to their roles) in one HIP graph; with
+        `concurrent` the wind and particle branches are parallel graph
+        branches."""
         if (substeps * self.R) % 2:
             raise ValueError("capture an even number of LBM steps")
         t_host = self.t
+        side = torch.cuda.Stream() if concurrent else None
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             for _ in range(substeps):
-                self.step()
+                self.step(side)
         self.t = t_host
         self.graph_substeps = substeps
 

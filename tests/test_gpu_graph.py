@@ -1,5 +1,6 @@
 """The coupled substep captured in a HIP graph gives the eager result on every
-replay, with eager work and synchronisations between replays."""
+replay, with eager work and synchronisations between replays, with the
+phases on one stream and with the wind branch on a second stream."""
 import pytest
 import torch
 
@@ -11,13 +12,16 @@ from gpu_util import rel, say
 pytestmark = pytest.mark.gpu
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_graph_replays_match_eager(concurrent):
+    """Serial graph and the graph with the wind and particle branches on two
+    streams."""
     sc = scenes.flag_and_leaves_scene(seed=4, n=20_000, res=32, n_clusters=4, lbm_dims=(32, 16, 16))
     eager = CoupledSim(sc)
     graphed = CoupledSim(sc)
-    graphed.capture(2)
+    graphed.capture(2, concurrent=concurrent)
     for r in range(4):
-        say(f"graph replay {r}")
+        say(f"graph replay {r} concurrent={concurrent}")
         eager.step()
         eager.step()
         graphed.replay()
