@@ -20,6 +20,9 @@ paper's equations (DiffWind, ICLR 2026) in float64:
 * ``oracle.lbm``   -- the lattice Boltzmann equation with BGK collision
   (Eq. lbe, Eq. lbm_sum_v2), D3Q19, and the particle-to-voxel solid rule
   (Eq. point2voxel).
+* ``oracle.home``  -- the moment-encoded HOME-LBM step (appendix "More
+  details on HOME-LBM Algorithm"): third-order Hermite reconstruction of the
+  populations from rho, u, S and the moment-space collision.
 * ``oracle.conv``  -- the 3-D convolutional wind surrogate, written with
   ``torch.nn.functional.conv3d`` in float64.
 

@@ -121,19 +121,21 @@ def inlet_velocity(lat: Lattice, p: LBMParams, t: int):
     return u0[:, None, None] * s[None]
 
 
-def stream(lat: Lattice, p: LBMParams, f_in, solid, t: int):
+def stream(lat: Lattice, p: LBMParams, f_in, solid, t: int, f_inlet=None):
     """Pull streaming with the boundary rules of the module docstring.
 
     f_in (19, nz, ny, nx); solid (nz, ny, nx) bool.  Returns the pulled
     populations f* (19, nz, ny, nx) for every node (solid ones are overwritten
-    later)."""
+    later).  f_inlet (19, nz, ny): the populations of the inlet ghost nodes,
+    by default the equilibrium at rho = 1, u_in(t)."""
     nx, ny, nz = lat.dims
     kz, jy, ix = torch.meshgrid(torch.arange(nz), torch.arange(ny), torch.arange(nx), indexing="ij")
     coords = [ix, jy, kz]
     dims = [nx, ny, nz]
     out = torch.empty_like(f_in)
-    u_inlet = inlet_velocity(lat, p, t)  # (3, nz, ny)
-    f_inlet = equilibrium(torch.ones(nz, ny, dtype=_DT), u_inlet)  # (19, nz, ny)
+    if f_inlet is None:
+        u_inlet = inlet_velocity(lat, p, t)  # (3, nz, ny)
+        f_inlet = equilibrium(torch.ones(nz, ny, dtype=_DT), u_inlet)  # (19, nz, ny)
     for i in range(Q):
         src = [coords[a] - int(C[i, a]) for a in range(3)]
         bounce = torch.zeros(nz, ny, nx, dtype=torch.bool)
