@@ -40,6 +40,7 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-substeps", type=int, default=12)
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-home", action="store_true", help="skip the HOME-LBM (moment-encoded) leg")
     ap.add_argument("--surrogate-only", action="store_true", help="run only the wind-surrogate leg (profiling)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -93,6 +94,50 @@ def _graph_ms(fn, reps=5):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def _home_leg(scene, sim, steps):
+    """The HOME-LBM (moment-encoded) form of the lattice step: the step alone
+    on the scene's lattice and solid mask, and the whole coupled substep with
+    it in place of the BGK step."""
+    import torch
+    from paper_2603_09668_amd import api
+    from paper_2603_09668_amd.sim import CoupledSim
+
+    L = sim.L
+    prm = api.make_lbm_params(**sim.lbm_kw, t=1)
+    ma = torch.empty(api.HOME_MOMENTS, L, device="cuda")
+    mb = torch.empty_like(ma)
+    api.lbm_home_equilibrium(sim.lat, prm, ma)
+    u = torch.empty(3, L, device="cuda")
+    state = [ma, mb]
+
+    def step():
+        api.lbm_home_step(sim.lat, prm, state[0], state[1], sim.solid, None, u)
+        state.reverse()
+
+    R = 10
+    ms = _graph_ms(lambda: [step() for _ in range(R)]) / R
+    bytes_node = 2 * 4 * api.HOME_MOMENTS + 1 + 12      # moments in and out, solid, u out
+    ach = bytes_node * L / (ms * 1e-3) / 1e9
+    del ma, mb, state
+    hs = CoupledSim(scene, lbm_model="home")
+    for _ in range(4):
+        hs.step()
+    hs.capture(2)
+    hs.replay()
+    torch.cuda.synchronize()
+    n2 = steps + (steps % 2)
+    t0 = time.perf_counter()
+    for _ in range(n2 // 2):
+        hs.replay()
+    torch.cuda.synchronize()
+    sub_ms = (time.perf_counter() - t0) * 1e3 / n2
+    return {"lbm_home_ms": ms, "lbm_home_mlups": L / (ms * 1e-3) / 1e6,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_node": bytes_node},
+            "coupled_ms_per_step": sub_ms, "coupled_value": scene.n / (sub_ms * 1e-3),
+            "status": hs.status()}
 
 
 def _surrogate_leg(n_rollouts, train_steps):
@@ -398,6 +443,8 @@ def main():
                      "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant, a.n, a.res),
                      "algorithmic_bytes": bytes_per.get(dominant)},
     }
+    if not a.no_home:
+        out["home_lbm"] = _home_leg(scene, sim, min(a.steps, 100))
     if not a.no_surrogate:
         del sim, scratch
         torch.cuda.empty_cache()

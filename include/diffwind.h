@@ -293,6 +293,31 @@ int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float
 int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const float *rho,
                     const float *u, float *f, void *stream);
 
+/* HOME-LBM step (appendix "More details on HOME-LBM Algorithm"): the
+ * moment-encoded form of the same lattice.  A node stores its post-collision
+ * moments m [10][L] = rho - 1, u (3), S (6: xx yy zz xy xz yz), with
+ * rho S_ab = sum_i (c_ia c_ib - delta_ab / 3) f_i.  For each direction the
+ * population of the source node is rebuilt from the source's moments by the
+ * third-order Hermite expansion (first equation of the appendix, over the
+ * six third-order classes D3Q19 carries, a3_aab = S_aa u_b + 2 S_ab u_a -
+ * 2 u_a^2 u_b), pulled with the boundary rules of lbm_step (an inlet ghost
+ * holds rho = 1, u = u_in(t), S = u_in u_in), and the moments of the pulled
+ * set are relaxed in moment space (second equation of the appendix): the
+ * deviatoric part of S relaxes with 1/tau towards that of u u (the printed
+ * diagonal update is read with its equilibrium term (u_a^2 - |u|^2/3)/tau),
+ * the trace is set to |u|^2, the force enters as Guo's source, and the
+ * stored u is u* + F / (2 rho).  rho_out [L] and u_out [3][L] (optional)
+ * receive the macroscopic rho* and u* = (sum c f* + F / 2) / rho*.  Solid
+ * nodes store the rest state and report u = 0, rho = 1.  m_in and m_out must
+ * not alias. */
+int lbm_home_step(const dw_lattice *lat, const dw_lbm_params *params, const float *m_in, float *m_out,
+                  const uint8_t *solid, float *rho_out, float *u_out, void *stream);
+
+/* Equilibrium moments (rho, u, S = u u) into m [10][L]: rho [L] (NULL = 1)
+ * and u [3][L] (NULL = the uniform params->u_in). */
+int lbm_home_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const float *rho,
+                         const float *u, float *m, void *stream);
+
 /* Eq. point2voxel: solid[floor((x_p - origin)/dx)] = 1 for every particle
  * inside the lattice.  accumulate = 0 clears solid [L] (uint8) first,
  * 1 ORs into it (static obstacles). */

@@ -30,7 +30,8 @@ STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED = 1, 2, 4
 SYMBOLS = [
     "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_reorder",
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
-    "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_solid_from_particles",
+    "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_home_step", "lbm_home_equilibrium",
+    "lbm_solid_from_particles",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
     "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats",
 ]
@@ -106,6 +107,8 @@ def lib():
         "lbm_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
+        "lbm_home_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
+        "lbm_home_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
         "conv_packed_weight_elems": ([c_int, c_int], c_size_t),
         "conv_pack_weights": ([P, c_int, c_int, c_int, P, P], c_int),
@@ -360,6 +363,22 @@ def lbm_step_adj(lat: Lattice, params: LBMParams, f_in, solid, f_out_bar, u_out_
 def lbm_equilibrium(lat: Lattice, params: LBMParams, f, rho=None, u=None):
     _check(lib().lbm_equilibrium(ctypes.byref(lat), ctypes.byref(params), _ptr(rho, name="rho"), _ptr(u, name="u"),
                                  _ptr(f, name="f"), _stream()), "lbm_equilibrium")
+
+
+HOME_MOMENTS = 10   # rho - 1, u (3), S (6: xx yy zz xy xz yz)
+
+
+def lbm_home_step(lat: Lattice, params: LBMParams, m_in, m_out, solid=None, rho_out=None, u_out=None):
+    """HOME-LBM step on moments m [10][L] (see the C header)."""
+    _check(lib().lbm_home_step(ctypes.byref(lat), ctypes.byref(params), _ptr(m_in, name="m_in"),
+                               _ptr(m_out, name="m_out"), _ptr(solid, torch.uint8, "solid"),
+                               _ptr(rho_out, name="rho_out"), _ptr(u_out, name="u_out"), _stream()),
+           "lbm_home_step")
+
+
+def lbm_home_equilibrium(lat: Lattice, params: LBMParams, m, rho=None, u=None):
+    _check(lib().lbm_home_equilibrium(ctypes.byref(lat), ctypes.byref(params), _ptr(rho, name="rho"),
+                                      _ptr(u, name="u"), _ptr(m, name="m"), _stream()), "lbm_home_equilibrium")
 
 
 def lbm_solid_from_particles(lat: Lattice, x, solid, accumulate=False):

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <utility>
 
 #include "dw_internal.h"
 
@@ -248,6 +249,275 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
   }
 }
 
+// ------------------------------------------------------------- HOME-LBM
+// Moment-encoded step (appendix on HOME-LBM): a node stores its
+// post-collision moments, [HM_N][L] = rho - 1, u (3), S (6: xx yy zz xy xz
+// yz) with rho S_ab = sum_i (c_a c_b - delta_ab / 3) f_i.  The step pulls,
+// for each direction q, the population f_q of the source node rebuilt from
+// the source's moments by the third-order Hermite expansion, accumulates the
+// moments of the pulled set on the fly (no population is stored), and
+// relaxes them in moment space.  40 bytes per node in and out instead of
+// the 76 + 76 of the population form.
+constexpr int HM_N = 10;
+
+struct Mom {
+  float drho, u[3], S[6];  // S: xx yy zz xy xz yz
+};
+
+__device__ __forceinline__ Mom load_mom(const float *__restrict__ m, int64_t L, int64_t node) {
+  Mom M;
+  M.drho = m[node];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) M.u[a] = m[(1 + a) * L + node];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) M.S[s] = m[(4 + s) * L + node];
+  return M;
+}
+
+// storage index of S_ab
+__host__ __device__ constexpr int sidx(int a, int b) {
+  return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
+}
+
+// a3_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b
+template <int A, int B>
+__device__ __forceinline__ float home_a3(const Mom &M) {
+  return M.S[sidx(A, A)] * M.u[B] + 2.f * M.S[sidx(A, B)] * M.u[A] - 2.f * M.u[A] * M.u[A] * M.u[B];
+}
+
+// f_q - w_q of the expansion
+//   f_q = w_q rho [1 + 3 c.u + 9/2 H2(c):S + 27/2 sum_(a,a,b) (c_a^2 - 1/3) c_b a3_aab]
+// terms with a zero velocity factor are dropped at compile time
+template <int Q>
+__device__ __forceinline__ float home_pop(const Mom &M) {
+  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
+  constexpr float h[3] = {c[0] * c[0] - 1.f / 3.f, c[1] * c[1] - 1.f / 3.f, c[2] * c[2] - 1.f / 3.f};
+  float s = 4.5f * (h[0] * M.S[0] + h[1] * M.S[1] + h[2] * M.S[2]);
+  if constexpr (c[0] != 0) s += 3.f * c[0] * M.u[0];
+  if constexpr (c[1] != 0) s += 3.f * c[1] * M.u[1];
+  if constexpr (c[2] != 0) s += 3.f * c[2] * M.u[2];
+  if constexpr (c[0] * c[1] != 0) s += 9.f * (c[0] * c[1]) * M.S[3];
+  if constexpr (c[0] * c[2] != 0) s += 9.f * (c[0] * c[2]) * M.S[4];
+  if constexpr (c[1] * c[2] != 0) s += 9.f * (c[1] * c[2]) * M.S[5];
+  float t = 0.f;
+  if constexpr (c[1] != 0) t += c[1] * (h[0] * home_a3<0, 1>(M) + h[2] * home_a3<2, 1>(M));
+  if constexpr (c[0] != 0) t += c[0] * (h[1] * home_a3<1, 0>(M) + h[2] * home_a3<2, 0>(M));
+  if constexpr (c[2] != 0) t += c[2] * (h[0] * home_a3<0, 2>(M) + h[1] * home_a3<1, 2>(M));
+  s += 13.5f * t;
+  return LW[Q] * (M.drho + (1.f + M.drho) * s);
+}
+
+// moments of the pulled set, accumulated direction by direction
+struct MomAcc {
+  float drho = 0.f, j[3] = {0.f, 0.f, 0.f}, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+};
+
+template <int Q>
+__device__ __forceinline__ void acc_pop(MomAcc &A, float g) {
+  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
+  A.drho += g;
+  if constexpr (c[0] != 0) A.j[0] += c[0] * g;
+  if constexpr (c[1] != 0) A.j[1] += c[1] * g;
+  if constexpr (c[2] != 0) A.j[2] += c[2] * g;
+  // sum H2_ab g (the weights' part sums to zero)
+  A.P[0] += (c[0] * c[0] - 1.f / 3.f) * g;
+  A.P[1] += (c[1] * c[1] - 1.f / 3.f) * g;
+  A.P[2] += (c[2] * c[2] - 1.f / 3.f) * g;
+  if constexpr (c[0] * c[1] != 0) A.P[3] += (c[0] * c[1]) * g;
+  if constexpr (c[0] * c[2] != 0) A.P[4] += (c[0] * c[2]) * g;
+  if constexpr (c[1] * c[2] != 0) A.P[5] += (c[1] * c[2]) * g;
+}
+
+// equilibrium moments of an inlet ghost node at inlet-plane (j, k)
+__device__ __forceinline__ Mom inlet_mom(const LbmDev &P, int j, int k) {
+  float sfac = 1.0f;
+  if (P.gust_amp != 0.f) {
+    int t = P.t_in ? *P.t_in : P.t;
+    float ph = 6.283185307179586f * ((float)t * P.gust_inv_period + P.gust_ky * (float)j / (float)P.ny +
+                                     P.gust_kz * (float)k / (float)P.nz) +
+               P.gust_phase;
+    sfac = 1.0f + P.gust_amp * sinf(ph);
+  }
+  Mom M;
+  M.drho = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) M.u[a] = P.uin[a] * sfac;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) M.S[a] = M.u[a] * M.u[a];
+  M.S[3] = M.u[0] * M.u[1];
+  M.S[4] = M.u[0] * M.u[2];
+  M.S[5] = M.u[1] * M.u[2];
+  return M;
+}
+
+template <int SOL, int Q>
+__device__ __forceinline__ void home_pull(const LbmDev &P, const float *__restrict__ min,
+                                          const uint8_t *__restrict__ solid, const uint8_t (*s_sol)[SOL_W],
+                                          int i, int j, int k, int x0, int64_t node, const Mom &own, MomAcc &A) {
+  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
+  const int si = i - c[0], sj = j - c[1], sk = k - c[2];
+  const bool inside = (unsigned)si < (unsigned)P.nx && (unsigned)sj < (unsigned)P.ny && (unsigned)sk < (unsigned)P.nz;
+  float g;
+  if (inside) {
+    const bool bb = SOL == 1 ? s_sol[(1 - c[1]) + 3 * (1 - c[2])][si - x0 + 4] != 0 : false;
+    if (bb) {
+      g = home_pop<LOPP[Q]>(own);
+    } else {
+      const int64_t src = node - (c[0] + c[1] * (int64_t)P.nx + c[2] * (int64_t)P.nx * P.ny);
+      g = home_pop<Q>(load_mom(min, P.L, src));
+    }
+  } else {
+    int64_t src = node;
+    int ssj = 0, ssk = 0;
+    const int kind = pull_source(P, solid, i, j, k, Q, src, ssj, ssk);
+    if (kind == SRC_NORMAL) g = home_pop<Q>(load_mom(min, P.L, src));
+    else if (kind == SRC_BOUNCE) g = home_pop<LOPP[Q]>(own);
+    else g = home_pop<Q>(inlet_mom(P, ssj, ssk));
+  }
+  acc_pop<Q>(A, g);
+}
+
+template <int SOL, int... Qs>
+__device__ __forceinline__ void home_pull_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
+                                              const float *__restrict__ min, const uint8_t *__restrict__ solid,
+                                              const uint8_t (*s_sol)[SOL_W], int i, int j, int k, int x0,
+                                              int64_t node, const Mom &own, MomAcc &A) {
+  (home_pull<SOL, Qs>(P, min, solid, s_sol, i, j, k, x0, node, own, A), ...);
+}
+
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so
+// consecutive block indices land on different XCDs.  The moment-encoded step
+// reads every node's moments from the 3 x 3 neighbouring rows; giving each
+// XCD a contiguous run of rows (in y, then z) keeps those rows in its L2.
+constexpr int N_XCD = 8;
+
+struct RowBlock {
+  int x0, j, k;
+  bool live;
+};
+
+__device__ __forceinline__ RowBlock xcd_row_block(const LbmDev &P) {
+  const int nbx = (P.nx + LBM_BLOCK - 1) / LBM_BLOCK;
+  const int64_t nblocks = (int64_t)nbx * P.ny * P.nz;
+  const int64_t per_xcd = (nblocks + N_XCD - 1) / N_XCD;
+  const int64_t b = blockIdx.x;
+  const int64_t logical = (b % N_XCD) * per_xcd + b / N_XCD;
+  RowBlock r;
+  r.live = logical < nblocks;
+  const int64_t row = logical / nbx;
+  r.x0 = (int)(logical % nbx) * LBM_BLOCK;
+  r.j = (int)(row % P.ny);
+  r.k = (int)(row / P.ny);
+  return r;
+}
+
+static dim3 xcd_lbm_grid(const LbmDev &P) {
+  const int64_t nbx = (P.nx + LBM_BLOCK - 1) / LBM_BLOCK;
+  const int64_t nblocks = nbx * P.ny * P.nz;
+  return dim3((unsigned)(((nblocks + N_XCD - 1) / N_XCD) * N_XCD));
+}
+
+template <bool SOLID>
+__global__ __launch_bounds__(LBM_BLOCK) void k_home_step(LbmDev P, const float *__restrict__ min,
+                                                         float *__restrict__ mout, const uint8_t *__restrict__ solid,
+                                                         float *__restrict__ rho_out, float *__restrict__ u_out) {
+  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  __shared__ int s_any[LBM_BLOCK / 64];
+  const RowBlock rb = xcd_row_block(P);
+  if (!rb.live) return;  // block-uniform: padding blocks of the last XCD
+  const int x0 = rb.x0;
+  const int i = x0 + threadIdx.x, j = rb.j, k = rb.k;
+  if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
+  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
+  bool any = false;
+  if (SOLID) {
+    uint32_t sv[SOL_PER_THREAD];
+    load_solid_rows(P, solid, x0, j, k, sv);
+    store_solid_rows(sv, s_sol);
+    uint32_t mine = 0;
+#pragma unroll
+    for (int u = 0; u < SOL_PER_THREAD; ++u) mine |= sv[u];
+    const bool wave_any = __ballot(mine != 0) != 0ull;
+    if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = wave_any;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) any = any || s_any[w] != 0;
+  }
+  if (i >= P.nx) return;
+  if (any && s_sol[4][i - x0 + 4]) {
+    // solid node: rest state
+#pragma unroll
+    for (int q = 0; q < HM_N; ++q) mout[(int64_t)q * P.L + node] = 0.f;
+    if (rho_out) rho_out[node] = 1.f;
+    if (u_out) {
+      u_out[node] = 0.f;
+      u_out[P.L + node] = 0.f;
+      u_out[2 * P.L + node] = 0.f;
+    }
+    return;
+  }
+  const Mom own = load_mom(min, P.L, node);
+  MomAcc A;
+  if (any) home_pull_all<1>(std::make_integer_sequence<int, 19>{}, P, min, solid, s_sol, i, j, k, x0, node, own, A);
+  else home_pull_all<0>(std::make_integer_sequence<int, 19>{}, P, min, solid, s_sol, i, j, k, x0, node, own, A);
+  // moments of the pulled set: u* carries half the force
+  const float rho = 1.f + A.drho, ir = 1.f / rho;
+  float u[3], Fu = 0.f, uu = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = (A.j[a] + 0.5f * P.F[a]) * ir;
+    Fu += P.F[a] * u[a];
+    uu += u[a] * u[a];
+  }
+  float S[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) S[s] = A.P[s] * ir;
+  // moment-space collision: deviatoric part relaxes with 1/tau towards
+  // dev(u u), the trace is set to |u|^2, Guo's source for the force
+  const float om = P.omega, keep = 1.f - om;
+  const float tr3 = (S[0] + S[1] + S[2]) * (1.f / 3.f), uu3 = uu * (1.f / 3.f);
+  float Sn[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    Sn[a] = keep * (S[a] - tr3) + om * (u[a] * u[a] - uu3) + uu3 +
+            (P.F[a] * u[a] + keep * (P.F[a] * u[a] - Fu * (1.f / 3.f))) * ir;
+  const float kf = (1.f - 0.5f * om) * ir;
+  Sn[3] = keep * S[3] + om * u[0] * u[1] + kf * (P.F[0] * u[1] + P.F[1] * u[0]);
+  Sn[4] = keep * S[4] + om * u[0] * u[2] + kf * (P.F[0] * u[2] + P.F[2] * u[0]);
+  Sn[5] = keep * S[5] + om * u[1] * u[2] + kf * (P.F[1] * u[2] + P.F[2] * u[1]);
+  mout[node] = A.drho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) mout[(1 + a) * P.L + node] = u[a] + 0.5f * P.F[a] * ir;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) mout[(4 + s) * P.L + node] = Sn[s];
+  if (rho_out) rho_out[node] = rho;
+  if (u_out) {
+    u_out[node] = u[0];
+    u_out[P.L + node] = u[1];
+    u_out[2 * P.L + node] = u[2];
+  }
+}
+
+// equilibrium moments (rho, u, S = u u) from rho [L] and u [3][L] (either
+// may be absent: rho = 1, u = the inflow velocity)
+__global__ __launch_bounds__(256) void k_home_equilibrium(LbmDev P, const float *__restrict__ rho_in,
+                                                          const float *__restrict__ u_in, float *__restrict__ m) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= P.L) return;
+  float u[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = u_in ? u_in[a * P.L + node] : P.uin[a];
+  m[node] = rho_in ? rho_in[node] - 1.f : 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m[(1 + a) * P.L + node] = u[a];
+    m[(4 + a) * P.L + node] = u[a] * u[a];
+  }
+  m[7 * P.L + node] = u[0] * u[1];
+  m[8 * P.L + node] = u[0] * u[2];
+  m[9 * P.L + node] = u[1] * u[2];
+}
+
 // Reverse of k_lbm_step: recompute the pulled populations and moments, form
 // the adjoint of the pulled populations through the BGK collision, and push
 // each one back to where it was pulled from (atomics: boundary rules can
@@ -434,6 +704,35 @@ extern "C" int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *param
   hipLaunchKernelGGL(k_lbm_equilibrium, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, rho,
                      u, f);
   return check_launch("lbm_equilibrium");
+}
+
+extern "C" int lbm_home_step(const dw_lattice *lat, const dw_lbm_params *params, const float *m_in, float *m_out,
+                             const uint8_t *solid, float *rho_out, float *u_out, void *stream) {
+  LbmDev P;
+  int rc = make_lbm(lat, params, &P);
+  if (rc) return rc;
+  DW_REQUIRE(m_in && m_out, DW_EINVAL, "lbm_home_step: m_in / m_out is NULL");
+  DW_REQUIRE(m_in != m_out, DW_EINVAL, "lbm_home_step: m_in and m_out must not alias");
+  if (solid)
+    hipLaunchKernelGGL(k_home_step<true>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, m_in, m_out,
+                       solid, rho_out, u_out);
+  else
+    hipLaunchKernelGGL(k_home_step<false>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, m_in, m_out,
+                       solid, rho_out, u_out);
+  return check_launch("lbm_home_step");
+}
+
+extern "C" int lbm_home_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const float *rho,
+                                    const float *u, float *m, void *stream) {
+  LbmDev P;
+  dw_lbm_params prm = *params;
+  if (prm.tau <= 0.5f) prm.tau = 1.0f;  // tau plays no role here
+  int rc = make_lbm(lat, &prm, &P);
+  if (rc) return rc;
+  DW_REQUIRE(m, DW_EINVAL, "lbm_home_equilibrium: m is NULL");
+  hipLaunchKernelGGL(k_home_equilibrium, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, rho,
+                     u, m);
+  return check_launch("lbm_home_equilibrium");
 }
 
 extern "C" int lbm_solid_from_particles(const dw_lattice *lat, const float *x, int n, uint8_t *solid,

@@ -3,6 +3,7 @@
 One coupled step runs, on torch's current stream:
   1. lbm_solid_from_particles  -- solid mask from the particles (Eq. point2voxel)
   2. lbm_step                  -- R fused stream-collide steps, velocity output
+                                 (or lbm_home_step, the moment-encoded form)
   3. mpm_sort                  -- cell-tile grouping of the particles
   4. mpm_p2g                   -- Eq. P2G with the MLS stress term
   5. mpm_grid_update           -- gravity, LBM drag wind (Sec. 3.4), walls, pins
@@ -23,7 +24,8 @@ from . import api
 
 
 class CoupledSim:
-    def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1, reorder: bool = True):
+    def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1, reorder: bool = True,
+                 lbm_model: str = "bgk"):
         self.scene = scene
         self.device = device
         self.R = int(lbm_steps_per_substep)
@@ -56,9 +58,16 @@ class CoupledSim:
         self.t_a = torch.zeros(1, dtype=torch.int32, device=device)
         self.t_b = torch.zeros(1, dtype=torch.int32, device=device)
         self.graph = None
-        self.fa = torch.empty(19, self.L, **f32)
-        self.fb = torch.empty(19, self.L, **f32)
-        api.lbm_equilibrium(self.lat, api.make_lbm_params(**self.lbm_kw), self.fa)
+        # lattice state, ping-ponged: 19 shifted populations (BGK) or the 10
+        # moments of the HOME-LBM form
+        if lbm_model not in ("bgk", "home"):
+            raise ValueError(f"unknown lbm_model {lbm_model!r}")
+        self.lbm_model = lbm_model
+        nstate = 19 if lbm_model == "bgk" else api.HOME_MOMENTS
+        self.fa = torch.empty(nstate, self.L, **f32)
+        self.fb = torch.empty(nstate, self.L, **f32)
+        init = api.lbm_equilibrium if lbm_model == "bgk" else api.lbm_home_equilibrium
+        init(self.lat, api.make_lbm_params(**self.lbm_kw), self.fa)
         self.solid = torch.zeros(self.L, dtype=torch.uint8, device=device)
         self.u = torch.zeros(3, self.L, **f32)
         self.wind = api.wind_lbm_drag(self.lat, self.u, scene.wind["vel_scale"], scene.wind["k_drag"])
@@ -87,7 +96,8 @@ class CoupledSim:
     def lbm(self):
         for _ in range(self.R):
             prm = api.make_lbm_params(**self.lbm_kw, t_in=self.t_a, t_out=self.t_b)
-            api.lbm_step(self.lat, prm, self.fa, self.fb, self.solid, None, self.u)
+            step = api.lbm_step if self.lbm_model == "bgk" else api.lbm_home_step
+            step(self.lat, prm, self.fa, self.fb, self.solid, None, self.u)
             self.fa, self.fb = self.fb, self.fa
             self.t_a, self.t_b = self.t_b, self.t_a
             self.t += 1
