@@ -135,20 +135,37 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
     int32_t *__restrict__ cell_tiles, int32_t *__restrict__ node_tiles, int32_t *__restrict__ item_tile,
     int32_t *__restrict__ item_begin, int32_t *__restrict__ item_first, int32_t *__restrict__ totals /* [4] */) {
   __shared__ int lds[128];
-  int pre[4];
-  for (int r = 0; r < 4; ++r) {
-    int before = 0, all = 0;
-    for (int64_t b = threadIdx.x; b < NB; b += SCAN_BLOCK) {
+  __shared__ int s_red[SCAN_BLOCK / 64][8];
+  __shared__ int s_sum[8];
+  // per row: the sum over the blocks before this one (0..3) and over all (4..7),
+  // one block-wide reduction of the eight values
+  int acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < NB; b += SCAN_BLOCK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
       const int v = block_sums[r * NB + b];
-      all += v;
-      if (b < (int64_t)blockIdx.x) before += v;
+      acc[4 + r] += v;
+      if (b < (int64_t)blockIdx.x) acc[r] += v;
     }
-    int tb, ta;
-    block_excl_scan(before, lds, &tb);
-    block_excl_scan(all, lds, &ta);
-    pre[r] = tb;
-    if (blockIdx.x == 0 && threadIdx.x == 0) totals[r] = ta;
   }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
+    if (lane == 0) s_red[wid][r] = acc[r];
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    int t = 0;
+    for (int w = 0; w < SCAN_BLOCK / 64; ++w) t += s_red[w][threadIdx.x];
+    s_sum[threadIdx.x] = t;
+  }
+  __syncthreads();
+  int pre[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) pre[r] = s_sum[r];
+  if (blockIdx.x == 0 && threadIdx.x < 4) totals[threadIdx.x] = s_sum[4 + threadIdx.x];
   int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
   int c = i < T ? count[i] : 0;
   int f = i < T ? (flag[i] != 0) : 0;
