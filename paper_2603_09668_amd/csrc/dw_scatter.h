@@ -5,8 +5,9 @@
 // base_p + o of the tile's 6^3 node region, with f_p the particle's position
 // in its base cell (in cells), w_o the quadratic B-spline weight, q_p a
 // 3-vector and A_p a 3x3 matrix (P2G also adds w_o m_p as a fourth value).
-// A workgroup stages its particles in LDS in cell order (16 floats each:
-// f, m, q, A row-major), cuts each cell into units of at most SC_UNIT
+// A workgroup stages its particles in LDS in cell order (f as one 16-byte
+// record per particle, read with one instruction; m, q, A row-major as 13
+// feature rows), cuts each cell into units of at most SC_UNIT
 // particles, and per unit forms Feat (13 x n) W (n x 27) with fp32 MFMA
 // 16x16x4 (four particles per step, offsets in two 16-column tiles), the
 // rows ordered so that the four result rows a lane holds give one node
@@ -21,7 +22,7 @@ namespace dw {
 
 constexpr int SC_L = 6;           // local node extent of a cell tile's stencils
 constexpr int SC_NODES = 216;     // 6^3
-constexpr int SC_DAT = 16;        // staged floats per particle: f(3), m, q(3), A(9)
+constexpr int SC_DAT = 13;        // staged feature rows per particle: m, q(3), A(9)
 constexpr int SC_UNIT = 64;       // particles per unit (16 MFMA steps)
 constexpr int SC_MAX_UNITS = 64 + WORK_CHUNK / SC_UNIT;  // bounds the sum over cells of ceil(count / unit)
 constexpr int SC_THREADS = WORK_CHUNK;
@@ -54,7 +55,7 @@ __device__ __forceinline__ ScLane sc_lane(int lane) {
   // staged feature of operand row r16, grouped so that result rows 4 kq ..
   // 4 kq + 3 (held by lane group kq) all feed node value kq:
   //   rows 0-3: m, -, -, -;  rows 4 + 4d .. 7 + 4d: q_d, A_d0, A_d1, A_d2
-  L.feat = r16 == 0 ? 3 : (r16 < 4 ? -1 : ((r16 & 3) == 0 ? 3 + (r16 >> 2) : 7 + 3 * ((r16 >> 2) - 1) + (r16 & 3) - 1));
+  L.feat = r16 == 0 ? 0 : (r16 < 4 ? -1 : ((r16 & 3) == 0 ? (r16 >> 2) : 4 + 3 * ((r16 >> 2) - 1) + (r16 & 3) - 1));
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int o = t * 16 + r16;
@@ -98,24 +99,22 @@ __device__ __forceinline__ void sc_scan_units(int lane, const int *s_cnt, int *s
   if (lane == 63) *s_nunits = uinc;
 }
 
-// Stage one particle at `slot`: f, m, q, A (A row-major).
-__device__ __forceinline__ void sc_stage(float (*s_dat)[SC_PITCH], int slot, const float f[3], float m, const float q[3],
-                                         const float A[9]) {
-  s_dat[0][slot] = f[0];
-  s_dat[1][slot] = f[1];
-  s_dat[2][slot] = f[2];
-  s_dat[3][slot] = m;
-  s_dat[4][slot] = q[0];
-  s_dat[5][slot] = q[1];
-  s_dat[6][slot] = q[2];
+// Stage one particle at `slot`: f, then m, q, A (A row-major).
+__device__ __forceinline__ void sc_stage(float (*s_dat)[SC_PITCH], float4 *s_f, int slot, const float f[3], float m,
+                                         const float q[3], const float A[9]) {
+  s_f[slot] = make_float4(f[0], f[1], f[2], 0.f);
+  s_dat[0][slot] = m;
+  s_dat[1][slot] = q[0];
+  s_dat[2][slot] = q[1];
+  s_dat[3][slot] = q[2];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) s_dat[7 + k][slot] = A[k];
+  for (int k = 0; k < 9; ++k) s_dat[4 + k][slot] = A[k];
 }
 
 // Pass over the units on the matrix cores; wave `wid` adds into wnode.
 // Two units per wave at a time.
 __device__ __forceinline__ void sc_units_mfma(const ScLane &L, int wid, const float (*s_dat)[SC_PITCH],
-                                              const int *s_udesc, int nunits, float (*wnode)[4]) {
+                                              const float4 *s_f, const int *s_udesc, int nunits, float (*wnode)[4]) {
   for (int u = wid; u < nunits; u += 2 * SC_WAVES) {
     int k0[2], kn[2], cb[2];
 #pragma unroll
@@ -143,9 +142,10 @@ __device__ __forceinline__ void sc_units_mfma(const ScLane &L, int wid, const fl
           const int r = kk + 4 * h + L.kq;
           live[e][h] = r < kn[e];
           const int jj = k0[e] + (live[e][h] ? r : 0);
-          f3[e][h][0] = s_dat[0][jj];
-          f3[e][h][1] = s_dat[1][jj];
-          f3[e][h][2] = s_dat[2][jj];
+          const float4 fv = s_f[jj];
+          f3[e][h][0] = fv.x;
+          f3[e][h][1] = fv.y;
+          f3[e][h][2] = fv.z;
           av[e][h] = (live[e][h] && L.feat >= 0) ? s_dat[L.feat < 0 ? 0 : L.feat][jj] : 0.f;
         }
 #pragma unroll

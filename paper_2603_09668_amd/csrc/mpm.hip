@@ -277,6 +277,7 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
     float *__restrict__ gmv, int64_t N, int32_t *__restrict__ status, float *__restrict__ item_part) {
   static_assert(WORK_CHUNK == P2G_THREADS, "one staged particle per thread");
   __shared__ float s_dat[SC_DAT][SC_PITCH];                       // staged particles in cell order
+  __shared__ float4 s_f[SC_PITCH];                                  // staged f per particle
   __shared__ __attribute__((aligned(16))) float s_node[SC_WAVES][SC_NODES][4];  // per-wave node sums
   __shared__ int s_cnt[64], s_off[64], s_cur[64];
   __shared__ int s_udesc[SC_MAX_UNITS];
@@ -367,11 +368,11 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
       const float qv[3] = {m * vx - (A[0] * f[0] + A[1] * f[1] + A[2] * f[2]),
                            m * vy - (A[3] * f[0] + A[4] * f[1] + A[5] * f[2]),
                            m * vz - (A[6] * f[0] + A[7] * f[1] + A[8] * f[2])};
-      sc_stage(s_dat, slot, f, m, qv, A);
+      sc_stage(s_dat, s_f, slot, f, m, qv, A);
     }
     __syncthreads();
     // pass C
-    sc_units_mfma(L, wid, s_dat, s_udesc, s_nunits, s_node[wid]);
+    sc_units_mfma(L, wid, s_dat, s_f, s_udesc, s_nunits, s_node[wid]);
     __syncthreads();
     // pass D: node owners add the wave blocks in a fixed order
     if (tid == P2G_THREADS - 1) s_next = (int)gridDim.x + atomicAdd(ticket, 1);

@@ -319,6 +319,7 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     const int32_t *__restrict__ item_tile, const int32_t *__restrict__ item_begin,
     const int32_t *__restrict__ n_items) {
   __shared__ float s_dat[SC_DAT][SC_PITCH];
+  __shared__ float4 s_f[SC_PITCH];                                  // staged f per particle
   __shared__ __attribute__((aligned(16))) float s_node[SC_WAVES][SC_NODES][4];
   __shared__ int s_cnt[64], s_off[64], s_cur[64];
   __shared__ int s_udesc[SC_MAX_UNITS];
@@ -459,10 +460,10 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
       for (int q = 0; q < 9; ++q) A[q] = kc * Cbt[q];
 #pragma unroll
       for (int a = 0; a < 3; ++a) qv[a] = vbt[a] - (A[3 * a] * f[0] + A[3 * a + 1] * f[1] + A[3 * a + 2] * f[2]);
-      sc_stage(s_dat, slot, f, 0.f, qv, A);
+      sc_stage(s_dat, s_f, slot, f, 0.f, qv, A);
     }
     __syncthreads();
-    sc_units_mfma(L, wid, s_dat, s_udesc, s_nunits, s_node[wid]);
+    sc_units_mfma(L, wid, s_dat, s_f, s_udesc, s_nunits, s_node[wid]);
     __syncthreads();
     if (tid < SC_NODES) {
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
