@@ -23,6 +23,8 @@ paper's equations (DiffWind, ICLR 2026) in float64:
 * ``oracle.home``  -- the moment-encoded HOME-LBM step (appendix "More
   details on HOME-LBM Algorithm"): third-order Hermite reconstruction of the
   populations from rho, u, S and the moment-space collision.
+* ``oracle.gauss`` -- the covariance of each Gaussian kernel after
+  deformation, Sigma(t) = F Sigma F^T (Sec. 3.2, "Interaction Modeling").
 * ``oracle.conv``  -- the 3-D convolutional wind surrogate, written with
   ``torch.nn.functional.conv3d`` in float64.
 
