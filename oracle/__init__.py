@@ -25,6 +25,9 @@ paper's equations (DiffWind, ICLR 2026) in float64:
   populations from rho, u, S and the moment-space collision.
 * ``oracle.gauss`` -- the covariance of each Gaussian kernel after
   deformation, Sigma(t) = F Sigma F^T (Sec. 3.2, "Interaction Modeling").
+* ``oracle.recon`` -- the physics-informed loss of Sec. 3.4, the LBM
+  direction guide at the wind-grid nodes, and the CosSim / NMSE metrics of
+  reconstructed force fields.
 * ``oracle.conv``  -- the 3-D convolutional wind surrogate, written with
   ``torch.nn.functional.conv3d`` in float64.
 
