@@ -443,6 +443,14 @@ def main():
                      "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant, a.n, a.res),
                      "algorithmic_bytes": bytes_per.get(dominant)},
     }
+    # covariance of the Gaussian kernels bound to the particles (Sec. 3.2)
+    sig0 = torch.zeros(6, sim.p.n, device="cuda")
+    sig0[:3] = (0.3 * scene.grid["dx"]) ** 2
+    sig = torch.empty_like(sig0)
+    cov_ms = _graph_ms(lambda: [api.gaussian_covariance(sim.p.F, sig0, sig) for _ in range(10)]) / 10
+    out["covariance"] = {"ms": cov_ms, "bytes_per_particle": 84,
+                         "achieved_GBps": 84 * sim.p.n / (cov_ms * 1e-3) / 1e9}
+    del sig0, sig
     if not a.no_home:
         out["home_lbm"] = _home_leg(scene, sim, min(a.steps, 100))
     if not a.no_surrogate:

@@ -267,6 +267,22 @@ int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, const float *g
 int wind_to_grid_adj(const dw_grid *grid, const dw_wind *wind, const float *acc_bar,
                      float *out_bar, void *stream);
 
+/* ----------------------------------------------------- Gaussian kernels */
+
+/* Covariance of each Gaussian kernel after deformation (Sec. 3.2,
+ * "Interaction Modeling"): sigma_p = F_p sigma0_p F_p^T for every particle.
+ * H [9][n]: F - I row-major (the MPM storage); sigma0, sigma [6][n]:
+ * symmetric matrices as (xx, yy, zz, xy, xz, yz); sigma must not alias
+ * sigma0.  n = 0 is a no-op. */
+int gaussian_covariance(int n, const float *H, const float *sigma0, float *sigma, void *stream);
+
+/* Reverse of gaussian_covariance: given sigma_bar [6][n], the gradient with
+ * respect to the six stored entries, ACCUMULATES H_bar [9][n] and
+ * sigma0_bar [6][n] (gradients with respect to the stored entries; either
+ * may be NULL). */
+int gaussian_covariance_adj(int n, const float *H, const float *sigma0, const float *sigma_bar, float *H_bar,
+                            float *sigma0_bar, void *stream);
+
 /* ------------------------------------------------------------------ LBM */
 
 /* One fused pull stream-collide step of Eq. lbe with BGK collision (D3Q19),

@@ -31,7 +31,7 @@ SYMBOLS = [
     "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_reorder",
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
     "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_home_step", "lbm_home_equilibrium",
-    "lbm_solid_from_particles",
+    "lbm_solid_from_particles", "gaussian_covariance", "gaussian_covariance_adj",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
     "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats",
 ]
@@ -110,6 +110,8 @@ def lib():
         "lbm_home_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_home_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
+        "gaussian_covariance": ([c_int, P, P, P, P], c_int),
+        "gaussian_covariance_adj": ([c_int, P, P, P, P, P, P], c_int),
         "conv_packed_weight_elems": ([c_int, c_int], c_size_t),
         "conv_pack_weights": ([P, c_int, c_int, c_int, P, P], c_int),
         "conv_prep_input": ([c_int, c_int, c_int, c_int, P, P, P, P], c_int),
@@ -154,6 +156,11 @@ def _ptr(t, dtype=torch.float32, name="tensor"):
     if not t.is_contiguous():
         raise ValueError(f"{name}: must be contiguous")
     return c_void_p(t.data_ptr())
+
+
+def _shape(t, shape, name):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
 
 
 # ----------------------------------------------------------------- structs
@@ -363,6 +370,30 @@ def lbm_step_adj(lat: Lattice, params: LBMParams, f_in, solid, f_out_bar, u_out_
 def lbm_equilibrium(lat: Lattice, params: LBMParams, f, rho=None, u=None):
     _check(lib().lbm_equilibrium(ctypes.byref(lat), ctypes.byref(params), _ptr(rho, name="rho"), _ptr(u, name="u"),
                                  _ptr(f, name="f"), _stream()), "lbm_equilibrium")
+
+
+def gaussian_covariance(H, sigma0, sigma):
+    """sigma = F sigma0 F^T per particle; H [9][n] = F - I, sigma0 / sigma [6][n]."""
+    n = H.shape[1]
+    _shape(H, (9, n), "H")
+    _shape(sigma0, (6, n), "sigma0")
+    _shape(sigma, (6, n), "sigma")
+    _check(lib().gaussian_covariance(n, _ptr(H, name="H"), _ptr(sigma0, name="sigma0"), _ptr(sigma, name="sigma"),
+                                     _stream()), "gaussian_covariance")
+
+
+def gaussian_covariance_adj(H, sigma0, sigma_bar, H_bar=None, sigma0_bar=None):
+    n = H.shape[1]
+    _shape(H, (9, n), "H")
+    _shape(sigma0, (6, n), "sigma0")
+    _shape(sigma_bar, (6, n), "sigma_bar")
+    if H_bar is not None:
+        _shape(H_bar, (9, n), "H_bar")
+    if sigma0_bar is not None:
+        _shape(sigma0_bar, (6, n), "sigma0_bar")
+    _check(lib().gaussian_covariance_adj(n, _ptr(H, name="H"), _ptr(sigma0, name="sigma0"),
+                                         _ptr(sigma_bar, name="sigma_bar"), _ptr(H_bar, name="H_bar"),
+                                         _ptr(sigma0_bar, name="sigma0_bar"), _stream()), "gaussian_covariance_adj")
 
 
 HOME_MOMENTS = 10   # rho - 1, u (3), S (6: xx yy zz xy xz yz)
