@@ -35,10 +35,12 @@ _DT = torch.float64
 
 
 def _unit(v):
-    """(3, n) -> unit vectors and a mask of the non-zero ones."""
-    nrm = torch.sqrt((v * v).sum(dim=0))
-    ok = nrm > 0
-    return v / torch.where(ok, nrm, torch.ones_like(nrm))[None], ok
+    """(3, n) -> unit vectors and a mask of the non-zero ones (zero vectors
+    map to zero with a zero derivative: their direction is undefined)."""
+    sq = (v * v).sum(dim=0)
+    ok = sq > 0
+    nrm = torch.sqrt(torch.where(ok, sq, torch.ones_like(sq)))
+    return torch.where(ok[None], v / nrm[None], torch.zeros_like(v)), ok
 
 
 def phys_loss(W, guide):

@@ -31,6 +31,10 @@ def test_phys_loss_closed_forms():
     W[:, 5] = 0.0
     ref = recon.phys_loss(torch.cat([W[:, :5], W[:, 6:]], 1), torch.cat([g[:, :5], g[:, 6:40]], 1))
     assert abs(recon.phys_loss(W, g[:, :40]) - ref) < 1e-12
+    # and such a node has a zero (finite) gradient
+    Wv = W.clone().requires_grad_(True)
+    recon.phys_loss(Wv, g[:, :40]).backward()
+    assert torch.isfinite(Wv.grad).all() and Wv.grad[:, 5].abs().max() == 0
 
 
 def test_phys_loss_gradient_matches_central_differences():
