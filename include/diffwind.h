@@ -283,6 +283,35 @@ int gaussian_covariance(int n, const float *H, const float *sigma0, float *sigma
 int gaussian_covariance_adj(int n, const float *H, const float *sigma0, const float *sigma_bar, float *H_bar,
                             float *sigma0_bar, void *stream);
 
+/* -------------------------------------------------------- reconstruction */
+
+/* Physics-informed loss of Sec. 3.4 over the n wind-grid nodes:
+ * L_phys = sum_i |d_i - (d_i . g_i) g_i|^2, d_i and g_i the unit directions
+ * of W [3][n] (reconstructed force field) and guide [3][n] (LBM velocity at
+ * the nodes, see wind_guide); nodes where either vector is zero contribute
+ * nothing.  ADDS weight * L_phys to *loss (if not NULL) and
+ * weight * dL_phys/dW to W_bar [3][n] (if not NULL).  Float atomics: the
+ * last bits of *loss depend on the order the blocks finish in. */
+int phys_loss(int n, const float *W, const float *guide, float weight, float *loss, float *W_bar, void *stream);
+
+/* Position loss sum_p |x_p - x*_p|^2 over n particles (the synthetic stand-in
+ * for the photometric loss of Sec. 3.3): ADDS it to *loss (if not NULL) and
+ * WRITES its gradient 2 (x - x*) to x_bar [3][n] (if not NULL). */
+int position_loss(int n, const float *x, const float *x_target, float *loss, float *x_bar, void *stream);
+
+/* Direction metrics of the appendix's evaluation of reconstructed wind force
+ * fields: with unit vectors a_i = F_ref_i / |F_ref_i| and b_i = F_i / |F_i|
+ * over the n locations where both are non-zero, ADDS (sum a.b, sum |a - b|^2,
+ * count) to out[0..2]; CosSim = out[0] / out[2], NMSE = out[1] / out[2]. */
+int direction_metrics(int n, const float *F_ref, const float *F, float *out, void *stream);
+
+/* The LBM direction guide: the lattice velocity u [3][L] sampled trilinearly
+ * at the nodes of a vertex-centred wind grid of nw[0] x nw[1] x nw[2] nodes
+ * spanning [lo, hi] (x fastest), into guide [3][nw^3]; nodes outside the
+ * lattice box get 0. */
+int wind_guide(const dw_lattice *lat, const float *u, const int nw[3], const float lo[3], const float hi[3],
+               float *guide, void *stream);
+
 /* ------------------------------------------------------------------ LBM */
 
 /* One fused pull stream-collide step of Eq. lbe with BGK collision (D3Q19),

@@ -32,6 +32,7 @@ SYMBOLS = [
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
     "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_home_step", "lbm_home_equilibrium",
     "lbm_solid_from_particles", "gaussian_covariance", "gaussian_covariance_adj",
+    "phys_loss", "position_loss", "direction_metrics", "wind_guide",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
     "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats",
 ]
@@ -112,6 +113,10 @@ def lib():
         "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
         "gaussian_covariance": ([c_int, P, P, P, P], c_int),
         "gaussian_covariance_adj": ([c_int, P, P, P, P, P, P], c_int),
+        "phys_loss": ([c_int, P, P, c_float, P, P, P], c_int),
+        "position_loss": ([c_int, P, P, P, P, P], c_int),
+        "direction_metrics": ([c_int, P, P, P, P], c_int),
+        "wind_guide": ([POINTER(Lattice), P, POINTER(c_int), POINTER(c_float), POINTER(c_float), P, P], c_int),
         "conv_packed_weight_elems": ([c_int, c_int], c_size_t),
         "conv_pack_weights": ([P, c_int, c_int, c_int, P, P], c_int),
         "conv_prep_input": ([c_int, c_int, c_int, c_int, P, P, P, P], c_int),
@@ -394,6 +399,49 @@ def gaussian_covariance_adj(H, sigma0, sigma_bar, H_bar=None, sigma0_bar=None):
     _check(lib().gaussian_covariance_adj(n, _ptr(H, name="H"), _ptr(sigma0, name="sigma0"),
                                          _ptr(sigma_bar, name="sigma_bar"), _ptr(H_bar, name="H_bar"),
                                          _ptr(sigma0_bar, name="sigma0_bar"), _stream()), "gaussian_covariance_adj")
+
+
+def phys_loss(W, guide, weight=1.0, loss=None, W_bar=None):
+    """Adds weight * L_phys to loss[0] and its gradient to W_bar; W, guide [3][n]."""
+    n = W.shape[1]
+    _shape(W, (3, n), "W")
+    _shape(guide, (3, n), "guide")
+    if loss is not None:
+        _shape(loss, (1,), "loss")
+    if W_bar is not None:
+        _shape(W_bar, (3, n), "W_bar")
+    _check(lib().phys_loss(n, _ptr(W, name="W"), _ptr(guide, name="guide"), float(weight), _ptr(loss, name="loss"),
+                           _ptr(W_bar, name="W_bar"), _stream()), "phys_loss")
+
+
+def position_loss(x, x_target, loss=None, x_bar=None):
+    n = x.shape[1]
+    _shape(x, (3, n), "x")
+    _shape(x_target, (3, n), "x_target")
+    if loss is not None:
+        _shape(loss, (1,), "loss")
+    if x_bar is not None:
+        _shape(x_bar, (3, n), "x_bar")
+    _check(lib().position_loss(n, _ptr(x, name="x"), _ptr(x_target, name="x_target"), _ptr(loss, name="loss"),
+                               _ptr(x_bar, name="x_bar"), _stream()), "position_loss")
+
+
+def direction_metrics(F_ref, F, out):
+    """Adds (sum cos, sum |a - b|^2, count) over non-zero locations to out[0..2]."""
+    n = F.shape[1]
+    _shape(F_ref, (3, n), "F_ref")
+    _shape(F, (3, n), "F")
+    _shape(out, (3,), "out")
+    _check(lib().direction_metrics(n, _ptr(F_ref, name="F_ref"), _ptr(F, name="F"), _ptr(out, name="out"),
+                                   _stream()), "direction_metrics")
+
+
+def wind_guide(lat: Lattice, u, nw, lo, hi, guide):
+    L = lat.nx * lat.ny * lat.nz
+    _shape(u, (3, L), "u")
+    _shape(guide, (3, nw[0] * nw[1] * nw[2]), "guide")
+    _check(lib().wind_guide(ctypes.byref(lat), _ptr(u, name="u"), (c_int * 3)(*nw), (c_float * 3)(*lo),
+                            (c_float * 3)(*hi), _ptr(guide, name="guide"), _stream()), "wind_guide")
 
 
 HOME_MOMENTS = 10   # rho - 1, u (3), S (6: xx yy zz xy xz yz)
