@@ -41,6 +41,8 @@ def _args():
     ap.add_argument("--cpu-substeps", type=int, default=12)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-home", action="store_true", help="skip the HOME-LBM (moment-encoded) leg")
+    ap.add_argument("--no-recon", action="store_true", help="skip the sequential reconstruction leg")
+    ap.add_argument("--recon-only", action="store_true", help="run only the reconstruction leg (profiling)")
     ap.add_argument("--surrogate-only", action="store_true", help="run only the wind-surrogate leg (profiling)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -138,6 +140,51 @@ def _home_leg(scene, sim, steps):
                          "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_node": bytes_node},
             "coupled_ms_per_step": sub_ms, "coupled_value": scene.n / (sub_ms * 1e-3),
             "status": hs.status()}
+
+
+def _recon_leg(n, res, frames, sub, iters):
+    """Sequential reconstruction (Sec. 3.3) of a drag-shaped force field along
+    the LBM wind of the scene's tunnel, from particle positions, with and
+    without the physics-informed loss: CosSim / NMSE of the force directions
+    per frame and the time of one optimisation iteration (forward, checkpointed
+    backward, losses, Adam)."""
+    import torch
+    from paper_2603_09668_amd import recon, scenes
+    sc = scenes.flag_and_leaves_scene(seed=3, n=n, res=res, lbm_dims=(res, res // 2, res // 2))
+    dev = "cuda"
+    nw, lo, hi = (16, 16, 16), (0.3, 0.2, 0.2), (0.95, 0.8, 0.8)
+    guide, _ = recon.lbm_guide(sc, nw, lo, hi, steps=300)
+    amp = 200.0
+    F_gt = recon.drag_field(guide, amp)
+    rc = recon.Reconstructor(sc, nw, lo, hi, substeps_per_frame=sub)
+    x0 = torch.tensor(sc.x.T.copy(), dtype=torch.float32, device=dev).contiguous()
+    z3, z9 = torch.zeros(3, sc.n, device=dev), torch.zeros(9, sc.n, device=dev)
+    state0 = (x0, z3, z9, z9.clone())
+    targets, st = [], state0
+    for _ in range(frames):
+        st = rc.advance(st, F_gt)
+        targets.append(st[0].clone())
+    out = {"config": {"workload": f"{n} particles, {res}^3 grid, 16^3 force grid, {frames} frames x {sub} substeps, "
+                                  f"{iters} Adam iterations per frame (lr {amp / 40:g}), drag-shaped target field "
+                                  f"along the LBM wind, largest force {amp:g}",
+                      "particles": n, "grid": res, "frames": frames, "substeps_per_frame": sub,
+                      "iterations": iters}}
+    for lam in (0.0, 1.0):
+        st = state0
+        per = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(frames):
+            r = rc.frame(st, targets[k], guide, lam=lam, iters=iters, lr=amp / 40)
+            c, m, cnt = recon.metrics(F_gt, r.W)
+            per.append({"cos_sim": c, "nmse": m, "nodes": cnt, "loss_first": r.loss[0], "loss_last": r.loss[-1]})
+            st = rc.advance(st, r.W)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        err = torch.sqrt(((st[0] - targets[-1]) ** 2).sum(dim=0)).max().item()
+        out[f"lambda_{lam:g}"] = {"frames": per, "ms_per_iteration": el * 1e3 / (frames * iters),
+                                  "final_max_position_error": err}
+    return out
 
 
 def _surrogate_leg(n_rollouts, train_steps):
@@ -340,6 +387,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.recon_only:
+        print(json.dumps({"metric": METRIC, "reconstruction": _recon_leg(256_000, 96, 3, 128, 20)}), flush=True)
+        return
     if a.adjoint_only:
         print(json.dumps({"metric": METRIC, "adjoint": _adjoint_leg(256_000, 96, 256, 16, a.fd)}), flush=True)
         return
@@ -461,6 +511,8 @@ def main():
         out["surrogate"] = sgo
     if not a.no_adjoint:
         out["adjoint"] = _adjoint_leg(256_000, 96, 256, 16, a.fd)
+    if not a.no_recon:
+        out["reconstruction"] = _recon_leg(256_000, 96, 3, 128, 20)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(scene, a.cpu_substeps)
     print(json.dumps(out), flush=True)
