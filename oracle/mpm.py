@@ -221,20 +221,27 @@ def p2g(grid: Grid, x, v, C, F, mass, vol0, mu_p, lam_p, dt: float, material: in
 
 
 def grid_update(grid: Grid, gm, gmv, dt: float, gravity=(0.0, 0.0, 0.0), acc=None, pin=None,
-                bound: int = 3):
+                bound: int = 3, drag_rel=None):
     """Grid momentum update (Eq. continuum_mechanics, explicit in time).
 
     For m_i > 0: v_i = mv_i / m_i + dt (g + a_i), where a_i is the wind force
     field (an acceleration) at node i; otherwise v_i = 0.  Separating-slip walls
     ``bound`` nodes deep: on axis a, if i_a < bound and v_a < 0, or
     i_a >= n_a - bound and v_a > 0, then v_a = 0.  Pinned nodes get v = 0.
+    ``drag_rel`` = (U (N, 3), inside (N,), k_drag) replaces ``acc`` by the
+    relative drag k_D |U - v*| (U - v*) with v* = mv / m (oracle.wind).
     """
+    from .wind import relative_drag
     g = torch.tensor(gravity, dtype=_DT)
     has_mass = gm > 0
     m_safe = torch.where(has_mass, gm, torch.ones_like(gm))
-    v = gmv / m_safe[:, None] + dt * g
+    vstar = gmv / m_safe[:, None]
+    v = vstar + dt * g
     if acc is not None:
         v = v + dt * acc
+    if drag_rel is not None:
+        U, inside, k_drag = drag_rel
+        v = v + dt * relative_drag(U, vstar, inside, k_drag)
     v = torch.where(has_mass[:, None], v, torch.zeros_like(v))
     n = torch.arange(grid.n_nodes)
     ijk = torch.stack([n % grid.nx, (n // grid.nx) % grid.ny, n // (grid.nx * grid.ny)], dim=1)

@@ -16,6 +16,12 @@ that per-node acceleration a_i are provided:
   one constant, and |u| = 0 gives a = 0.  MPM nodes outside the lattice box
   receive no wind.
 
+* relative LBM drag (a variant the paper leaves open: its drag relation
+  uses the wind velocity itself): the same interpolated wind velocity U_i,
+  taken relative to the node's own velocity v_i = mv_i / m_i from P2G,
+  a_i = k_D |U_i - v_i| (U_i - v_i), zero outside the lattice box and where
+  U_i = v_i.  It is evaluated inside the grid update (it needs mv, m).
+
 Trilinear interpolation along one axis at coordinate q in [0, n-1]:
 i0 = min(floor(q), n - 2), t = q - i0, value = (1 - t) f[i0] + t f[i0 + 1].
 
@@ -85,4 +91,28 @@ def lbm_drag_to_nodes(grid: Grid, lat_dims, lat_dx, lat_origin, u_lat, vel_scale
     speed = torch.where(moving, torch.sqrt(torch.where(moving, u2, torch.ones_like(u2))),
                         torch.zeros_like(u2))
     a = k_drag * speed[:, None] * u
+    return torch.where(inside[:, None], a, torch.zeros_like(a))
+
+
+def lbm_velocity_to_nodes(grid: Grid, lat_dims, lat_dx, lat_origin, u_lat, vel_scale):
+    """The wind velocity U_i = vel_scale * trilinear(u_lat) at the MPM nodes and
+    the mask of nodes inside the lattice box (U = 0 outside).  Returns
+    (U (N, 3), inside (N,))."""
+    pos = node_positions(grid)
+    q = (pos - torch.tensor(lat_origin, dtype=_DT)) / lat_dx
+    n_t = torch.tensor(lat_dims, dtype=_DT) - 1.0
+    inside = ((q >= 0) & (q <= n_t)).all(dim=1)
+    qc = torch.minimum(torch.maximum(q, torch.zeros(3, dtype=_DT)), n_t)
+    U = vel_scale * trilinear(u_lat, lat_dims, qc).T
+    return torch.where(inside[:, None], U, torch.zeros_like(U)), inside
+
+
+def relative_drag(U, v, inside, k_drag):
+    """a = k_D |U - v| (U - v) on nodes inside the lattice box, 0 elsewhere;
+    U, v (N, 3)."""
+    r = U - v
+    r2 = (r * r).sum(dim=1)
+    moving = r2 > 0
+    s = torch.sqrt(torch.where(moving, r2, torch.ones_like(r2)))
+    a = k_drag * torch.where(moving, s, torch.zeros_like(s))[:, None] * r
     return torch.where(inside[:, None], a, torch.zeros_like(a))

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from oracle import conv, wind
+from oracle import mpm as ompm
 from oracle.mpm import Grid, node_positions
 
 DT = torch.float64
@@ -76,6 +77,52 @@ def test_drag_uniform_flow_and_outside():
     a0 = wind.lbm_drag_to_nodes(grid, dims, 0.125, (0.25, 0.25, 0.25), u0, 20.0, 9.8)
     (g,) = torch.autograd.grad(a0.sum(), u0)
     assert torch.isfinite(g).all() and a0.abs().max() == 0
+
+
+def test_relative_drag():
+    """Relative drag: equals the absolute drag for a node at rest, vanishes
+    for a node moving with the wind, opposes the slip, and enters the grid
+    update as an acceleration evaluated at v* = mv / m."""
+    grid = Grid(8, 8, 8, 1.0 / 8)
+    dims = (4, 4, 4)
+    rng = np.random.default_rng(3)
+    u = torch.tensor(0.05 * rng.standard_normal((3, 64)))
+    args = (grid, dims, 0.125, (0.25, 0.25, 0.25), u, 20.0)
+    U, inside = wind.lbm_velocity_to_nodes(*args)
+    a_abs = wind.lbm_drag_to_nodes(*args, 9.8)
+    zero = torch.zeros_like(U)
+    assert (wind.relative_drag(U, zero, inside, 9.8) - a_abs).abs().max() < 1e-13
+    assert wind.relative_drag(U, U, inside, 9.8).abs().max() == 0
+    v = torch.tensor(rng.standard_normal(U.shape))
+    a = wind.relative_drag(U, v, inside, 9.8)
+    assert ((a * (U - v)).sum(1) >= 0).all()
+    assert a[~inside].abs().max() == 0
+    # one node by hand: |r| r with r = U - v
+    i = int(torch.nonzero(inside)[5])
+    r = U[i] - v[i]
+    assert (a[i] - 9.8 * r.norm() * r).abs().max() < 1e-14
+    # in the grid update
+    N = grid.n_nodes
+    m = torch.tensor(rng.uniform(0.5, 2.0, N))
+    mv = m[:, None] * v
+    dt = 1e-3
+    vo = ompm.grid_update(grid, m, mv, dt, (0.0, -9.8, 0.0), bound=0, drag_rel=(U, inside, 9.8))
+    ref = v + dt * (torch.tensor([0.0, -9.8, 0.0], dtype=DT) + a)
+    assert (vo - ref).abs().max() < 1e-14
+    # its derivative with respect to the momentum, against central differences
+    mvv = mv.clone().requires_grad_(True)
+    w = torch.tensor(rng.standard_normal((N, 3)))
+    (gmv,) = torch.autograd.grad((ompm.grid_update(grid, m, mvv, dt, bound=0, drag_rel=(U, inside, 9.8)) * w).sum(),
+                                 mvv)
+    h = 1e-6
+    for node in (i, int(torch.nonzero(inside)[20])):
+        for c in range(3):
+            p, q = mv.clone(), mv.clone()
+            p[node, c] += h
+            q[node, c] -= h
+            fp = (ompm.grid_update(grid, m, p, dt, bound=0, drag_rel=(U, inside, 9.8)) * w).sum()
+            fm = (ompm.grid_update(grid, m, q, dt, bound=0, drag_rel=(U, inside, 9.8)) * w).sum()
+            assert abs((fp - fm).item() / (2 * h) - gmv[node, c].item()) < 1e-6
 
 
 def test_conv_direct_matches_library():
