@@ -68,7 +68,7 @@ enum { DW_FIXED_COROTATED = 0, DW_NEO_HOOKEAN = 1 };
 enum { DW_BC_PERIODIC = 0, DW_BC_BOUNCEBACK = 1, DW_BC_INLET = 2, DW_BC_OUTLET = 3 };
 
 /* sources of the per-node wind acceleration */
-enum { DW_WIND_NONE = 0, DW_WIND_FORCE_GRID = 1, DW_WIND_LBM_DRAG = 2, DW_WIND_ACC = 3 };
+enum { DW_WIND_NONE = 0, DW_WIND_FORCE_GRID = 1, DW_WIND_LBM_DRAG = 2, DW_WIND_ACC = 3, DW_WIND_LBM_DRAG_REL = 4 };
 
 /* status bits */
 enum {
@@ -137,6 +137,10 @@ typedef struct {
    * u = [3][L] lattice velocity (zero on solid nodes); MPM nodes outside the
    * lattice box get no wind.  Drag relation of Sec. 3.4 with
    * k_drag = rho_w C_D / 2 times area over mass. */
+  /* DW_WIND_LBM_DRAG_REL (same fields): the drag of the wind relative to the
+   * node, a = k_drag |U - v*| (U - v*) with v* = mv / m, the node's velocity
+   * from P2G (zero outside the lattice box).  Only mpm_grid_update and its
+   * adjoint evaluate it (wind_to_grid has no node velocity and refuses it). */
   dw_lattice lat;
   const float *u;
   float vel_scale, k_drag;
@@ -245,7 +249,10 @@ int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, const dw_parti
 /* Reverse of mpm_grid_update on the active node tiles of `ws` (same sort as
  * the forward).  Recomputes the wall/pin masks from the forward inputs;
  * accumulates into grid_m_bar [N], grid_mv_bar [3][N] and acc_bar [3][N]
- * (d loss / d a_i; NULL to skip). */
+ * (d loss / d a_i; NULL to skip).  With DW_WIND_LBM_DRAG_REL the drag's
+ * dependence on v* = mv / m goes into grid_m_bar / grid_mv_bar here, and
+ * acc_bar receives d loss / d U_i, the adjoint of the interpolated wind
+ * velocity at the node, which wind_to_grid_adj carries back to the lattice. */
 int mpm_grid_update_adj(const dw_grid *grid, const dw_mpm_params *params, const float *grid_m,
                         const float *grid_mv, const dw_wind *wind, const uint8_t *pin,
                         const float *grid_v_bar, float *grid_m_bar, float *grid_mv_bar,
@@ -262,8 +269,9 @@ int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, const float *g
 
 /* Reverse of wind_to_grid / of the wind term of mpm_grid_update: given
  * acc_bar [3][N], accumulates W_bar [3][nw^3] (FORCE_GRID) or u_bar [3][L]
- * (LBM_DRAG; the lattice velocity adjoint) -- pass the matching pointer in
- * `out_bar`. */
+ * (LBM_DRAG and LBM_DRAG_REL; the lattice velocity adjoint) -- pass the
+ * matching pointer in `out_bar`.  For LBM_DRAG_REL acc_bar is the node wind
+ * velocity adjoint written by mpm_grid_update_adj. */
 int wind_to_grid_adj(const dw_grid *grid, const dw_wind *wind, const float *acc_bar,
                      float *out_bar, void *stream);
 

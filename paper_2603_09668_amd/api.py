@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libdiffwind.so")
 
 FIXED_COROTATED, NEO_HOOKEAN = 0, 1
 BC_PERIODIC, BC_BOUNCEBACK, BC_INLET, BC_OUTLET = 0, 1, 2, 3
-WIND_NONE, WIND_FORCE_GRID, WIND_LBM_DRAG, WIND_ACC = 0, 1, 2, 3
+WIND_NONE, WIND_FORCE_GRID, WIND_LBM_DRAG, WIND_ACC, WIND_LBM_DRAG_REL = 0, 1, 2, 3, 4
 STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED = 1, 2, 4
 
 # exported symbols, in the order of include/diffwind.h
@@ -206,8 +206,10 @@ def wind_force_grid(W_slot, nw, lo, hi) -> Wind:
     return w
 
 
-def wind_lbm_drag(lat: Lattice, u, vel_scale, k_drag) -> Wind:
-    w = Wind(mode=WIND_LBM_DRAG)
+def wind_lbm_drag(lat: Lattice, u, vel_scale, k_drag, relative: bool = False) -> Wind:
+    """LBM drag wind; relative=True takes the wind relative to the node
+    velocity (evaluated by mpm_grid_update only)."""
+    w = Wind(mode=WIND_LBM_DRAG_REL if relative else WIND_LBM_DRAG)
     w.lat = lat
     w.u = _ptr(u, name="u")
     w.vel_scale = float(vel_scale)

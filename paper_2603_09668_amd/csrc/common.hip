@@ -107,7 +107,8 @@ int make_wind(const dw_wind *w, const dw_grid *g, WindDev *o) {
       o->nw3 = (int64_t)w->nw[0] * w->nw[1] * w->nw[2];
       return DW_OK;
     case DW_WIND_LBM_DRAG:
-      DW_REQUIRE(w->u, DW_EINVAL, "wind: DW_WIND_LBM_DRAG needs u");
+    case DW_WIND_LBM_DRAG_REL:
+      DW_REQUIRE(w->u, DW_EINVAL, "wind: LBM drag needs u");
       DW_REQUIRE(w->lat.nx >= 2 && w->lat.ny >= 2 && w->lat.nz >= 2 && w->lat.dx > 0.f, DW_EINVAL,
                  "wind: lattice must be >= 2 nodes per axis with dx > 0");
       o->lnx = w->lat.nx;

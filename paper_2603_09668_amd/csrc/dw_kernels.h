@@ -66,9 +66,28 @@ __device__ __forceinline__ void trilinear3(const float *__restrict__ f, int nx, 
   }
 }
 
-// Wind acceleration at MPM node (i, j, k).
+// Interpolated wind velocity U at MPM node (i, j, k) in physical units, for
+// the LBM drag modes; false outside the lattice box (no wind there).
+__device__ __forceinline__ bool wind_velocity_at_node(const WindDev &w, const GridDev &g, int i, int j, int k,
+                                                      float &ux, float &uy, float &uz) {
+  float px = g.ox + g.dx * (float)i, py = g.oy + g.dx * (float)j, pz = g.oz + g.dx * (float)k;
+  float qx = (px - w.lox_l) * w.inv_ldx, qy = (py - w.loy_l) * w.inv_ldx, qz = (pz - w.loz_l) * w.inv_ldx;
+  ux = uy = uz = 0.f;
+  if (!(qx >= 0.f && qy >= 0.f && qz >= 0.f && qx <= (float)(w.lnx - 1) && qy <= (float)(w.lny - 1) &&
+        qz <= (float)(w.lnz - 1)))
+    return false;
+  trilinear3(w.u, w.lnx, w.lny, w.lnz, w.L, qx, qy, qz, ux, uy, uz);
+  ux *= w.vel_scale;
+  uy *= w.vel_scale;
+  uz *= w.vel_scale;
+  return true;
+}
+
+// Wind acceleration at MPM node (i, j, k); (vx, vy, vz) is the node's own
+// velocity mv / m, used by the relative drag only.
 __device__ __forceinline__ void wind_at_node(const WindDev &w, const GridDev &g, int i, int j, int k,
-                                             int64_t node, float &ax, float &ay, float &az) {
+                                             int64_t node, float vx, float vy, float vz, float &ax, float &ay,
+                                             float &az) {
   ax = ay = az = 0.f;
   if (w.mode == DW_WIND_NONE) return;
   if (w.mode == DW_WIND_ACC) {
@@ -85,16 +104,14 @@ __device__ __forceinline__ void wind_at_node(const WindDev &w, const GridDev &g,
     trilinear3(w.W, w.nwx, w.nwy, w.nwz, w.nw3, qx, qy, qz, ax, ay, az);
     return;
   }
-  // DW_WIND_LBM_DRAG
-  float qx = (px - w.lox_l) * w.inv_ldx, qy = (py - w.loy_l) * w.inv_ldx, qz = (pz - w.loz_l) * w.inv_ldx;
-  if (!(qx >= 0.f && qy >= 0.f && qz >= 0.f && qx <= (float)(w.lnx - 1) && qy <= (float)(w.lny - 1) &&
-        qz <= (float)(w.lnz - 1)))
-    return;
+  // DW_WIND_LBM_DRAG / DW_WIND_LBM_DRAG_REL
   float ux, uy, uz;
-  trilinear3(w.u, w.lnx, w.lny, w.lnz, w.L, qx, qy, qz, ux, uy, uz);
-  ux *= w.vel_scale;
-  uy *= w.vel_scale;
-  uz *= w.vel_scale;
+  if (!wind_velocity_at_node(w, g, i, j, k, ux, uy, uz)) return;
+  if (w.mode == DW_WIND_LBM_DRAG_REL) {
+    ux -= vx;
+    uy -= vy;
+    uz -= vz;
+  }
   float s = sqrtf(ux * ux + uy * uy + uz * uz);
   ax = w.k_drag * s * ux;
   ay = w.k_drag * s * uy;

@@ -509,12 +509,13 @@ __global__ __launch_bounds__(256) void k_grid_update(GridDev g, float dt, float 
     float m = gm[node];
     float vx = 0.f, vy = 0.f, vz = 0.f;
     if (m > 0.f) {
+      const float im = 1.0f / m;
+      const float sx = gmv[node] * im, sy = gmv[N + node] * im, sz = gmv[2 * N + node] * im;
       float ax = 0.f, ay = 0.f, az = 0.f;
-      wind_at_node(wind, g, i, j, k, node, ax, ay, az);
-      float im = 1.0f / m;
-      vx = gmv[node] * im + dt * (gx + ax);
-      vy = gmv[N + node] * im + dt * (gy + ay);
-      vz = gmv[2 * N + node] * im + dt * (gz + az);
+      wind_at_node(wind, g, i, j, k, node, sx, sy, sz, ax, ay, az);
+      vx = sx + dt * (gx + ax);
+      vy = sy + dt * (gy + ay);
+      vz = sz + dt * (gz + az);
       if ((i < bound && vx < 0.f) || (i >= g.nx - bound && vx > 0.f)) vx = 0.f;
       if ((j < bound && vy < 0.f) || (j >= g.ny - bound && vy > 0.f)) vy = 0.f;
       if ((k < bound && vz < 0.f) || (k >= g.nz - bound && vz > 0.f)) vz = 0.f;

@@ -278,25 +278,52 @@ __global__ __launch_bounds__(256) void k_grid_update_adj(GridDev g, float dt, fl
     float m = gm[node];
     if (!(m > 0.f)) continue;
     if (pin && pin[node]) continue;
-    float ax, ay, az;
-    wind_at_node(wind, g, i, j, k, node, ax, ay, az);
     float im = 1.0f / m;
     float mv[3] = {gmv[node], gmv[N + node], gmv[2 * N + node]};
-    float v[3] = {mv[0] * im + dt * (gx + ax), mv[1] * im + dt * (gy + ay), mv[2] * im + dt * (gz + az)};
+    const float vs[3] = {mv[0] * im, mv[1] * im, mv[2] * im};
+    float ax, ay, az;
+    wind_at_node(wind, g, i, j, k, node, vs[0], vs[1], vs[2], ax, ay, az);
+    float v[3] = {vs[0] + dt * (gx + ax), vs[1] + dt * (gy + ay), vs[2] + dt * (gz + az)};
     float vb[3] = {gvb[node], gvb[N + node], gvb[2 * N + node]};
     if ((i < bound && v[0] < 0.f) || (i >= g.nx - bound && v[0] > 0.f)) vb[0] = 0.f;
     if ((j < bound && v[1] < 0.f) || (j >= g.ny - bound && v[1] > 0.f)) vb[1] = 0.f;
     if ((k < bound && v[2] < 0.f) || (k >= g.nz - bound && v[2] > 0.f)) vb[2] = 0.f;
-    if (gmvb) {
-      gmvb[node] += vb[0] * im;
-      gmvb[N + node] += vb[1] * im;
-      gmvb[2 * N + node] += vb[2] * im;
+    // adjoint of the acceleration, and of the wind velocity U and of v* for
+    // the relative drag a = k |r| r, r = U - v*: with J = k (|r| I + r r^T / |r|)
+    // U_bar = J a_bar and v*_bar gets -J a_bar
+    float ab[3] = {dt * vb[0], dt * vb[1], dt * vb[2]};
+    float vsb[3] = {vb[0], vb[1], vb[2]};
+    if (wind.mode == DW_WIND_LBM_DRAG_REL) {
+      float U[3];
+      float r[3] = {0.f, 0.f, 0.f};
+      if (wind_velocity_at_node(wind, g, i, j, k, U[0], U[1], U[2])) {
+        r[0] = U[0] - vs[0];
+        r[1] = U[1] - vs[1];
+        r[2] = U[2] - vs[2];
+      }
+      const float sp = sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      float Jab[3] = {0.f, 0.f, 0.f};
+      if (sp > 0.f) {
+        const float rb = (r[0] * ab[0] + r[1] * ab[1] + r[2] * ab[2]) / sp;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Jab[a] = wind.k_drag * (sp * ab[a] + r[a] * rb);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        vsb[a] -= Jab[a];
+        ab[a] = Jab[a];
+      }
     }
-    if (gmb) gmb[node] += -(vb[0] * mv[0] + vb[1] * mv[1] + vb[2] * mv[2]) * im * im;
+    if (gmvb) {
+      gmvb[node] += vsb[0] * im;
+      gmvb[N + node] += vsb[1] * im;
+      gmvb[2 * N + node] += vsb[2] * im;
+    }
+    if (gmb) gmb[node] += -(vsb[0] * mv[0] + vsb[1] * mv[1] + vsb[2] * mv[2]) * im * im;
     if (accb) {
-      accb[node] += dt * vb[0];
-      accb[N + node] += dt * vb[1];
-      accb[2 * N + node] += dt * vb[2];
+      accb[node] += ab[0];
+      accb[N + node] += ab[1];
+      accb[2 * N + node] += ab[2];
     }
   }
 }

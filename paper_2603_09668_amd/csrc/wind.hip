@@ -17,7 +17,7 @@ __global__ __launch_bounds__(128) void k_wind_to_grid(GridDev g, WindDev w, floa
   if (i >= g.nx) return;
   const int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
   float ax, ay, az;
-  wind_at_node(w, g, i, j, k, node, ax, ay, az);
+  wind_at_node(w, g, i, j, k, node, 0.f, 0.f, 0.f, ax, ay, az);
   acc[node] = ax;
   acc[N + node] = ay;
   acc[2 * N + node] = az;
@@ -96,6 +96,11 @@ __global__ __launch_bounds__(128) void k_force_grid_adj_global(GridDev g, WindDe
 // Transpose of the drag mode: a = k |U| U, U = s * trilinear(u), so
 // dL/dU = k (|U| abar + U (U . abar) / |U|) and u_bar gets s times its
 // trilinear transpose.
+// JAC = true: transpose of the absolute drag a = k |U| U,
+// U = s * trilinear(u): dL/dU = k (|U| abar + U (U . abar) / |U|), then
+// u_bar += s trilinear^T(dL/dU).  JAC = false: abar already is dL/dU (the
+// relative drag, whose Jacobian the grid-update adjoint applies).
+template <bool JAC>
 __global__ __launch_bounds__(128) void k_drag_adj(GridDev g, WindDev w, const float *__restrict__ abar, int64_t N,
                                                   float *__restrict__ ubar) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
@@ -113,12 +118,19 @@ __global__ __launch_bounds__(128) void k_drag_adj(GridDev g, WindDev w, const fl
   ux *= w.vel_scale;
   uy *= w.vel_scale;
   uz *= w.vel_scale;
-  float sp = sqrtf(ux * ux + uy * uy + uz * uz);
-  if (!(sp > 0.f)) return;
-  float ub = (ux * bx + uy * by + uz * bz) / sp;
-  float Ux = w.k_drag * (sp * bx + ux * ub) * w.vel_scale;
-  float Uy = w.k_drag * (sp * by + uy * ub) * w.vel_scale;
-  float Uz = w.k_drag * (sp * bz + uz * ub) * w.vel_scale;
+  float Ux, Uy, Uz;
+  if (JAC) {
+    float sp = sqrtf(ux * ux + uy * uy + uz * uz);
+    if (!(sp > 0.f)) return;
+    float ub = (ux * bx + uy * by + uz * bz) / sp;
+    Ux = w.k_drag * (sp * bx + ux * ub) * w.vel_scale;
+    Uy = w.k_drag * (sp * by + uy * ub) * w.vel_scale;
+    Uz = w.k_drag * (sp * bz + uz * ub) * w.vel_scale;
+  } else {
+    Ux = bx * w.vel_scale;
+    Uy = by * w.vel_scale;
+    Uz = bz * w.vel_scale;
+  }
   int ix, iy, iz;
   float tx, ty, tz;
   lin_axis(qx, w.lnx, ix, tx);
@@ -147,6 +159,8 @@ extern "C" int wind_to_grid(const dw_grid *grid, const dw_wind *wind, float *acc
   rc = make_wind(wind, grid, &wd);
   if (rc) return rc;
   DW_REQUIRE(wd.mode != DW_WIND_ACC || wd.acc != acc, DW_EINVAL, "wind_to_grid: acc aliases the input");
+  DW_REQUIRE(wd.mode != DW_WIND_LBM_DRAG_REL, DW_EINVAL,
+             "wind_to_grid: the relative drag needs the node velocity (mpm_grid_update evaluates it)");
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
   hipLaunchKernelGGL(k_wind_to_grid, node_grid(g), dim3(WIND_BLOCK), 0, (hipStream_t)stream, g, wd, acc, N);
@@ -161,8 +175,8 @@ extern "C" int wind_to_grid_adj(const dw_grid *grid, const dw_wind *wind, const 
   WindDev wd;
   rc = make_wind(wind, grid, &wd);
   if (rc) return rc;
-  DW_REQUIRE(wd.mode == DW_WIND_FORCE_GRID || wd.mode == DW_WIND_LBM_DRAG, DW_EINVAL,
-             "wind_to_grid_adj: mode must be FORCE_GRID or LBM_DRAG");
+  DW_REQUIRE(wd.mode == DW_WIND_FORCE_GRID || wd.mode == DW_WIND_LBM_DRAG || wd.mode == DW_WIND_LBM_DRAG_REL,
+             DW_EINVAL, "wind_to_grid_adj: mode must be FORCE_GRID, LBM_DRAG or LBM_DRAG_REL");
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
   hipStream_t s = (hipStream_t)stream;
@@ -174,8 +188,10 @@ extern "C" int wind_to_grid_adj(const dw_grid *grid, const dw_wind *wind, const 
     } else {
       hipLaunchKernelGGL(k_force_grid_adj_global, node_grid(g), dim3(WIND_BLOCK), 0, s, g, wd, acc_bar, N, out_bar);
     }
+  } else if (wd.mode == DW_WIND_LBM_DRAG) {
+    hipLaunchKernelGGL(k_drag_adj<true>, node_grid(g), dim3(WIND_BLOCK), 0, s, g, wd, acc_bar, N, out_bar);
   } else {
-    hipLaunchKernelGGL(k_drag_adj, node_grid(g), dim3(WIND_BLOCK), 0, s, g, wd, acc_bar, N, out_bar);
+    hipLaunchKernelGGL(k_drag_adj<false>, node_grid(g), dim3(WIND_BLOCK), 0, s, g, wd, acc_bar, N, out_bar);
   }
   return check_launch("wind_to_grid_adj");
 }

@@ -25,7 +25,7 @@ from . import api
 
 class CoupledSim:
     def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1, reorder: bool = True,
-                 lbm_model: str = "bgk"):
+                 lbm_model: str = "bgk", relative_drag: bool = False):
         self.scene = scene
         self.device = device
         self.R = int(lbm_steps_per_substep)
@@ -70,7 +70,8 @@ class CoupledSim:
         init(self.lat, api.make_lbm_params(**self.lbm_kw), self.fa)
         self.solid = torch.zeros(self.L, dtype=torch.uint8, device=device)
         self.u = torch.zeros(3, self.L, **f32)
-        self.wind = api.wind_lbm_drag(self.lat, self.u, scene.wind["vel_scale"], scene.wind["k_drag"])
+        self.wind = api.wind_lbm_drag(self.lat, self.u, scene.wind["vel_scale"], scene.wind["k_drag"],
+                                      relative=relative_drag)
         # order[i] = scene index of particle i
         self.order = torch.arange(n, dtype=torch.int32, device=device)
         if reorder:

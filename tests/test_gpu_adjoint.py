@@ -201,3 +201,77 @@ def test_lbm_step_adj(forced):
                      ubar.reshape(3, L).float().to(DEV).contiguous(), fb)
     torch.cuda.synchronize()
     assert rel2(fb.cpu(), gf.reshape(19, L)) < TOL
+
+
+def _rel_drag_inputs(sc, og, seed):
+    """Grid mass/momentum from P2G of a seeded state and a lattice velocity,
+    rounded to float32 for both sides."""
+    st, dev = scene_state(sc, seed=seed)
+    mu, lam = ompm.particle_mu_lam(st["E"], st["nu"], st["region"])
+    m0, mv0 = ompm.p2g(og, st["x"], st["v"], st["C"], st["F"], st["mass"], st["vol0"], mu, lam, sc.dt,
+                       api.FIXED_COROTATED)
+    lat = sc.lattice
+    dims = (lat["nx"], lat["ny"], lat["nz"])
+    Lq = dims[0] * dims[1] * dims[2]
+    rng = np.random.default_rng(seed + 100)
+    u0 = f32(torch.tensor([0.08, 0.0, 0.0]).view(3, 1) + 0.03 * torch.tensor(rng.standard_normal((3, Lq))))
+    return st, dev, f32(m0), f32(mv0), lat, dims, u0
+
+
+def test_grid_update_relative_drag(scene):
+    """Forward and reverse of the grid update with the drag of the wind
+    relative to the node velocity v* = mv / m."""
+    sc = scene
+    og = oracle_grid(sc.grid)
+    g = api_grid(sc.grid)
+    N = og.n_nodes
+    st, dev, m0, mv0, lat, dims, u0 = _rel_drag_inputs(sc, og, 12)
+    vs, kd = 12.5, 9.8
+    alat = api.make_lattice(*dims, lat["dx"], lat["origin"])
+    wind = api.wind_lbm_drag(alat, u0.float().to(DEV).contiguous(), vs, kd, relative=True)
+    pin = torch.as_tensor(sc.pin)
+    ws = api.alloc_workspace(g, sc.n)
+    prm = api.make_mpm_params(sc.dt, gravity=sc.gravity, bound=3)
+    api.mpm_sort(g, prm, dev.x, ws)
+    say("mpm_grid_update relative drag")
+    gv = torch.zeros(3, N, device=DEV)
+    api.mpm_grid_update(g, prm, m0.float().to(DEV), mv0.T.contiguous().float().to(DEV), wind, pin.to(DEV), gv, ws)
+    torch.cuda.synchronize()
+    U, inside = owind.lbm_velocity_to_nodes(og, dims, lat["dx"], lat["origin"], u0, vs)
+    ov = ompm.grid_update(og, m0, mv0, sc.dt, sc.gravity, pin=pin, bound=3, drag_rel=(U, inside, kd))
+    assert (gv.cpu().T.double() - ov).abs().max().item() / ov.abs().max().item() < 1e-5
+    # the drag really is relative: it differs from the absolute one
+    gva = torch.zeros(3, N, device=DEV)
+    api.mpm_grid_update(g, prm, m0.float().to(DEV), mv0.T.contiguous().float().to(DEV),
+                        api.wind_lbm_drag(alat, u0.float().to(DEV).contiguous(), vs, kd), pin.to(DEV), gva, ws)
+    torch.cuda.synchronize()
+    assert (gva - gv).abs().max().item() > 1e-3 * gv.abs().max().item()
+    say("mpm_grid_update_adj relative drag")
+    rng = np.random.default_rng(13)
+    vbar = f32(rng.standard_normal((N, 3)))
+    m = m0.clone().requires_grad_(True)
+    mv = mv0.clone().requires_grad_(True)
+    Uv = U.clone().requires_grad_(True)
+    vo = ompm.grid_update(og, m, mv, sc.dt, sc.gravity, pin=pin, bound=3, drag_rel=(Uv, inside, kd))
+    gm, gmv, gU = torch.autograd.grad((vo * vbar).sum(), (m, mv, Uv))
+    mb = torch.zeros(N, device=DEV)
+    mvb = torch.zeros(3, N, device=DEV)
+    Ub = torch.zeros(3, N, device=DEV)
+    api.mpm_grid_update_adj(g, prm, m0.float().to(DEV), mv0.T.contiguous().float().to(DEV), wind, pin.to(DEV),
+                            vbar.T.contiguous().float().to(DEV), mb, mvb, Ub, ws)
+    torch.cuda.synchronize()
+    assert rel2(mb.cpu(), gm) < TOL
+    assert rel2(mvb.cpu().T, gmv) < TOL
+    assert rel2(Ub.cpu().T, gU) < TOL
+    say("wind_to_grid_adj relative drag (velocity transpose)")
+    uv = u0.clone().requires_grad_(True)
+    U2, _ = owind.lbm_velocity_to_nodes(og, dims, lat["dx"], lat["origin"], uv, vs)
+    Ubar = f32(rng.standard_normal((N, 3)))
+    (gu,) = torch.autograd.grad((U2 * Ubar).sum(), (uv,))
+    ub = torch.zeros(3, dims[0] * dims[1] * dims[2], device=DEV)
+    api.wind_to_grid_adj(g, wind, Ubar.T.contiguous().float().to(DEV), ub)
+    torch.cuda.synchronize()
+    assert rel2(ub.cpu(), gu) < TOL
+    # wind_to_grid has no node velocity and refuses the relative drag
+    with pytest.raises(api.DiffWindError):
+        api.wind_to_grid(g, wind, torch.empty(3, N, device=DEV))
