@@ -122,7 +122,11 @@ def _home_leg(scene, sim, steps):
     ms = _graph_ms(lambda: [step() for _ in range(R)]) / R
     bytes_node = 2 * 4 * api.HOME_MOMENTS + 1 + 12      # moments in and out, solid, u out
     ach = bytes_node * L / (ms * 1e-3) / 1e9
-    del ma, mb, state
+    # the reverse step (a push through the expansion, float atomics)
+    mbar = torch.ones(api.HOME_MOMENTS, L, device="cuda")
+    mib = torch.zeros_like(mbar)
+    adj_ms = _graph_ms(lambda: api.lbm_home_step_adj(sim.lat, prm, ma, sim.solid, mbar, None, mib))
+    del ma, mb, state, mbar, mib
     hs = CoupledSim(scene, lbm_model="home")
     for _ in range(4):
         hs.step()
@@ -135,7 +139,7 @@ def _home_leg(scene, sim, steps):
         hs.replay()
     torch.cuda.synchronize()
     sub_ms = (time.perf_counter() - t0) * 1e3 / n2
-    return {"lbm_home_ms": ms, "lbm_home_mlups": L / (ms * 1e-3) / 1e6,
+    return {"lbm_home_ms": ms, "lbm_home_mlups": L / (ms * 1e-3) / 1e6, "lbm_home_adj_ms": adj_ms,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_node": bytes_node},
             "coupled_ms_per_step": sub_ms, "coupled_value": scene.n / (sub_ms * 1e-3),

@@ -30,7 +30,7 @@ STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED = 1, 2, 4
 SYMBOLS = [
     "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_reorder",
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
-    "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_home_step", "lbm_home_equilibrium",
+    "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_home_step", "lbm_home_step_adj", "lbm_home_equilibrium",
     "lbm_solid_from_particles", "gaussian_covariance", "gaussian_covariance_adj",
     "phys_loss", "position_loss", "direction_metrics", "wind_guide",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
@@ -109,6 +109,7 @@ def lib():
         "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_home_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
+        "lbm_home_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_home_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
         "gaussian_covariance": ([c_int, P, P, P, P], c_int),
@@ -455,6 +456,21 @@ def lbm_home_step(lat: Lattice, params: LBMParams, m_in, m_out, solid=None, rho_
                                _ptr(m_out, name="m_out"), _ptr(solid, torch.uint8, "solid"),
                                _ptr(rho_out, name="rho_out"), _ptr(u_out, name="u_out"), _stream()),
            "lbm_home_step")
+
+
+def lbm_home_step_adj(lat: Lattice, params: LBMParams, m_in, solid, m_out_bar, u_out_bar, m_in_bar):
+    L = lat.nx * lat.ny * lat.nz
+    for t, shape, name in ((m_in, (HOME_MOMENTS, L), "m_in"), (m_out_bar, (HOME_MOMENTS, L), "m_out_bar"),
+                           (m_in_bar, (HOME_MOMENTS, L), "m_in_bar")):
+        _shape(t, shape, name)
+    if u_out_bar is not None:
+        _shape(u_out_bar, (3, L), "u_out_bar")
+    if solid is not None:
+        _shape(solid, (L,), "solid")
+    _check(lib().lbm_home_step_adj(ctypes.byref(lat), ctypes.byref(params), _ptr(m_in, name="m_in"),
+                                   _ptr(solid, torch.uint8, "solid"), _ptr(m_out_bar, name="m_out_bar"),
+                                   _ptr(u_out_bar, name="u_out_bar"), _ptr(m_in_bar, name="m_in_bar"), _stream()),
+           "lbm_home_step_adj")
 
 
 def lbm_home_equilibrium(lat: Lattice, params: LBMParams, m, rho=None, u=None):

@@ -288,8 +288,9 @@ __device__ __forceinline__ float home_a3(const Mom &M) {
 // f_q - w_q of the expansion
 //   f_q = w_q rho [1 + 3 c.u + 9/2 H2(c):S + 27/2 sum_(a,a,b) (c_a^2 - 1/3) c_b a3_aab]
 // terms with a zero velocity factor are dropped at compile time
+// the bracket s of f_q = w_q rho [1 + s]
 template <int Q>
-__device__ __forceinline__ float home_pop(const Mom &M) {
+__device__ __forceinline__ float home_series(const Mom &M) {
   constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
   constexpr float h[3] = {c[0] * c[0] - 1.f / 3.f, c[1] * c[1] - 1.f / 3.f, c[2] * c[2] - 1.f / 3.f};
   float s = 4.5f * (h[0] * M.S[0] + h[1] * M.S[1] + h[2] * M.S[2]);
@@ -304,7 +305,51 @@ __device__ __forceinline__ float home_pop(const Mom &M) {
   if constexpr (c[0] != 0) t += c[0] * (h[1] * home_a3<1, 0>(M) + h[2] * home_a3<2, 0>(M));
   if constexpr (c[2] != 0) t += c[2] * (h[0] * home_a3<0, 2>(M) + h[1] * home_a3<1, 2>(M));
   s += 13.5f * t;
-  return LW[Q] * (M.drho + (1.f + M.drho) * s);
+  return s;
+}
+
+template <int Q>
+__device__ __forceinline__ float home_pop(const Mom &M) {
+  return LW[Q] * (M.drho + (1.f + M.drho) * home_series<Q>(M));
+}
+
+// reverse of a3_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b, adjoint ab
+template <int A, int B>
+__device__ __forceinline__ void home_a3_adj(const Mom &M, float ab, Mom &Mb) {
+  Mb.S[sidx(A, A)] += ab * M.u[B];
+  Mb.S[sidx(A, B)] += 2.f * ab * M.u[A];
+  Mb.u[B] += ab * (M.S[sidx(A, A)] - 2.f * M.u[A] * M.u[A]);
+  Mb.u[A] += ab * (2.f * M.S[sidx(A, B)] - 4.f * M.u[A] * M.u[B]);
+}
+
+// reverse of home_pop<Q>: adds pb * d(f_q - w_q)/dM into Mb
+template <int Q>
+__device__ __forceinline__ void home_pop_adj(const Mom &M, float pb, Mom &Mb) {
+  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
+  constexpr float h[3] = {c[0] * c[0] - 1.f / 3.f, c[1] * c[1] - 1.f / 3.f, c[2] * c[2] - 1.f / 3.f};
+  Mb.drho += pb * LW[Q] * (1.f + home_series<Q>(M));
+  const float sb = pb * LW[Q] * (1.f + M.drho);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Mb.S[a] += 4.5f * h[a] * sb;
+  if constexpr (c[0] != 0) Mb.u[0] += 3.f * c[0] * sb;
+  if constexpr (c[1] != 0) Mb.u[1] += 3.f * c[1] * sb;
+  if constexpr (c[2] != 0) Mb.u[2] += 3.f * c[2] * sb;
+  if constexpr (c[0] * c[1] != 0) Mb.S[3] += 9.f * (c[0] * c[1]) * sb;
+  if constexpr (c[0] * c[2] != 0) Mb.S[4] += 9.f * (c[0] * c[2]) * sb;
+  if constexpr (c[1] * c[2] != 0) Mb.S[5] += 9.f * (c[1] * c[2]) * sb;
+  const float tb = 13.5f * sb;
+  if constexpr (c[1] != 0) {
+    home_a3_adj<0, 1>(M, tb * c[1] * h[0], Mb);
+    home_a3_adj<2, 1>(M, tb * c[1] * h[2], Mb);
+  }
+  if constexpr (c[0] != 0) {
+    home_a3_adj<1, 0>(M, tb * c[0] * h[1], Mb);
+    home_a3_adj<2, 0>(M, tb * c[0] * h[2], Mb);
+  }
+  if constexpr (c[2] != 0) {
+    home_a3_adj<0, 2>(M, tb * c[2] * h[0], Mb);
+    home_a3_adj<1, 2>(M, tb * c[2] * h[1], Mb);
+  }
 }
 
 // moments of the pulled set, accumulated direction by direction
@@ -359,13 +404,11 @@ __device__ __forceinline__ void home_pull(const LbmDev &P, const float *__restri
   const bool inside = (unsigned)si < (unsigned)P.nx && (unsigned)sj < (unsigned)P.ny && (unsigned)sk < (unsigned)P.nz;
   float g;
   if (inside) {
-    const bool bb = SOL == 1 ? s_sol[(1 - c[1]) + 3 * (1 - c[2])][si - x0 + 4] != 0 : false;
-    if (bb) {
-      g = home_pop<LOPP[Q]>(own);
-    } else {
-      const int64_t src = node - (c[0] + c[1] * (int64_t)P.nx + c[2] * (int64_t)P.nx * P.ny);
-      g = home_pop<Q>(load_mom(min, P.L, src));
-    }
+    const int64_t src = node - (c[0] + c[1] * (int64_t)P.nx + c[2] * (int64_t)P.nx * P.ny);
+    const bool bb = SOL == 1 ? s_sol[(1 - c[1]) + 3 * (1 - c[2])][si - x0 + 4] != 0
+                             : (SOL == 2 && solid[src] != 0);
+    if (bb) g = home_pop<LOPP[Q]>(own);
+    else g = home_pop<Q>(load_mom(min, P.L, src));
   } else {
     int64_t src = node;
     int ssj = 0, ssk = 0;
@@ -516,6 +559,138 @@ __global__ __launch_bounds__(256) void k_home_equilibrium(LbmDev P, const float 
   m[7 * P.L + node] = u[0] * u[1];
   m[8 * P.L + node] = u[0] * u[2];
   m[9 * P.L + node] = u[1] * u[2];
+}
+
+// ------------------------------------------------------- HOME-LBM reverse
+// Reverse of k_home_step: recompute the pulled set's moments, take the
+// adjoint of the stored moments (and of the reported u*) back through the
+// moment collision to the pulled populations, and push each population's
+// adjoint through the Hermite expansion into the moments it was rebuilt from
+// (atomics: boundary rules can make two destinations share one source).
+__device__ __forceinline__ void mom_atomic_add(float *__restrict__ mb, int64_t L, int64_t node, const Mom &M) {
+  atomicAdd(&mb[node], M.drho);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) atomicAdd(&mb[(1 + a) * L + node], M.u[a]);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) atomicAdd(&mb[(4 + s) * L + node], M.S[s]);
+}
+
+struct PopBar {
+  float drho, j[3], P[6];  // adjoints of the pulled set's moments
+};
+
+template <int Q>
+__device__ __forceinline__ void home_push(const LbmDev &P, const float *__restrict__ min,
+                                          const uint8_t *__restrict__ solid, int i, int j, int k, int64_t node,
+                                          const Mom &own, const PopBar &B, Mom &own_bar, float *__restrict__ mbar) {
+  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
+  // adjoint of the pulled population q
+  float gb = B.drho;
+  if constexpr (c[0] != 0) gb += c[0] * B.j[0];
+  if constexpr (c[1] != 0) gb += c[1] * B.j[1];
+  if constexpr (c[2] != 0) gb += c[2] * B.j[2];
+  gb += (c[0] * c[0] - 1.f / 3.f) * B.P[0] + (c[1] * c[1] - 1.f / 3.f) * B.P[1] + (c[2] * c[2] - 1.f / 3.f) * B.P[2];
+  if constexpr (c[0] * c[1] != 0) gb += (c[0] * c[1]) * B.P[3];
+  if constexpr (c[0] * c[2] != 0) gb += (c[0] * c[2]) * B.P[4];
+  if constexpr (c[1] * c[2] != 0) gb += (c[1] * c[2]) * B.P[5];
+  int64_t src = node;
+  int ssj = 0, ssk = 0;
+  const int kind = pull_source(P, solid, i, j, k, Q, src, ssj, ssk);
+  if (kind == SRC_NORMAL) {
+    Mom Mb{};
+    home_pop_adj<Q>(load_mom(min, P.L, src), gb, Mb);
+    mom_atomic_add(mbar, P.L, src, Mb);
+  } else if (kind == SRC_BOUNCE) {
+    home_pop_adj<LOPP[Q]>(own, gb, own_bar);
+  }
+}
+
+template <int... Qs>
+__device__ __forceinline__ void home_push_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
+                                              const float *__restrict__ min, const uint8_t *__restrict__ solid, int i,
+                                              int j, int k, int64_t node, const Mom &own, const PopBar &B,
+                                              Mom &own_bar, float *__restrict__ mbar) {
+  (home_push<Qs>(P, min, solid, i, j, k, node, own, B, own_bar, mbar), ...);
+}
+
+__global__ __launch_bounds__(LBM_BLOCK) void k_home_step_adj(LbmDev P, const float *__restrict__ min,
+                                                             const uint8_t *__restrict__ solid,
+                                                             const float *__restrict__ mout_bar,
+                                                             const float *__restrict__ ubar_out,
+                                                             float *__restrict__ mbar) {
+  const int i = blockIdx.x * LBM_BLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= P.nx) return;
+  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
+  if (solid && solid[node]) return;  // the stored rest state does not depend on the inputs
+  const Mom own = load_mom(min, P.L, node);
+  MomAcc A;
+  if (solid) home_pull_all<2>(std::make_integer_sequence<int, 19>{}, P, min, solid, nullptr, i, j, k, 0, node, own, A);
+  else home_pull_all<0>(std::make_integer_sequence<int, 19>{}, P, min, solid, nullptr, i, j, k, 0, node, own, A);
+  // forward moments and collision quantities
+  const float rho = 1.f + A.drho, ir = 1.f / rho;
+  float u[3], Fu = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = (A.j[a] + 0.5f * P.F[a]) * ir;
+    Fu += P.F[a] * u[a];
+  }
+  float S[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) S[s] = A.P[s] * ir;
+  const float om = P.omega, keep = 1.f - om, kf = 1.f - 0.5f * om;
+  // adjoints of the stored moments
+  float mb[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) mb[q] = mout_bar[(int64_t)q * P.L + node];
+  float Sb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ub[3] = {0.f, 0.f, 0.f}, irb = 0.f;
+  // diagonal S: keep (S_a - tr/3) + om (u_a^2 - |u|^2/3) + |u|^2/3
+  //             + (F_a u_a + keep (F_a u_a - F.u/3)) ir
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float sb = mb[4 + a];
+    Sb[a] += keep * sb;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      Sb[b] -= keep * sb * (1.f / 3.f);
+      ub[b] += sb * keep * 2.f * u[b] * (1.f / 3.f) - sb * keep * P.F[b] * (1.f / 3.f) * ir;
+    }
+    ub[a] += sb * (2.f * om * u[a] + (1.f + keep) * P.F[a] * ir);
+    irb += sb * (P.F[a] * u[a] + keep * (P.F[a] * u[a] - Fu * (1.f / 3.f)));
+  }
+  // off-diagonal S: keep S_ab + om u_a u_b + kf ir (F_a u_b + F_b u_a)
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a = pa[e], b = pb[e];
+    const float sb = mb[7 + e];
+    Sb[3 + e] += keep * sb;
+    ub[a] += sb * (om * u[b] + kf * ir * P.F[b]);
+    ub[b] += sb * (om * u[a] + kf * ir * P.F[a]);
+    irb += sb * kf * (P.F[a] * u[b] + P.F[b] * u[a]);
+  }
+  // stored u = u* + F / (2 rho), reported u*
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ub[a] += mb[1 + a];
+    irb += mb[1 + a] * 0.5f * P.F[a];
+    if (ubar_out) ub[a] += ubar_out[(int64_t)a * P.L + node];
+  }
+  // S = P ir, u = (j + F/2) ir, ir = 1 / (1 + drho)
+  PopBar B;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    B.P[s] = Sb[s] * ir;
+    irb += Sb[s] * A.P[s];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    B.j[a] = ub[a] * ir;
+    irb += ub[a] * (A.j[a] + 0.5f * P.F[a]);
+  }
+  B.drho = mb[0] - irb * ir * ir;
+  Mom own_bar{};
+  home_push_all(std::make_integer_sequence<int, 19>{}, P, min, solid, i, j, k, node, own, B, own_bar, mbar);
+  mom_atomic_add(mbar, P.L, node, own_bar);
 }
 
 // Reverse of k_lbm_step: recompute the pulled populations and moments, form
@@ -733,6 +908,19 @@ extern "C" int lbm_home_equilibrium(const dw_lattice *lat, const dw_lbm_params *
   hipLaunchKernelGGL(k_home_equilibrium, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, rho,
                      u, m);
   return check_launch("lbm_home_equilibrium");
+}
+
+extern "C" int lbm_home_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *m_in,
+                                 const uint8_t *solid, const float *m_out_bar, const float *u_out_bar,
+                                 float *m_in_bar, void *stream) {
+  LbmDev P;
+  int rc = make_lbm(lat, params, &P);
+  if (rc) return rc;
+  DW_REQUIRE(m_in && m_out_bar && m_in_bar, DW_EINVAL, "lbm_home_step_adj: m_in / m_out_bar / m_in_bar is NULL");
+  DW_REQUIRE(m_in_bar != m_in && m_in_bar != m_out_bar, DW_EINVAL, "lbm_home_step_adj: m_in_bar must not alias");
+  hipLaunchKernelGGL(k_home_step_adj, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, m_in, solid, m_out_bar,
+                     u_out_bar, m_in_bar);
+  return check_launch("lbm_home_step_adj");
 }
 
 extern "C" int lbm_solid_from_particles(const dw_lattice *lat, const float *x, int n, uint8_t *solid,

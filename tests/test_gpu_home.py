@@ -243,3 +243,41 @@ def test_coupled_simulation_with_home_lbm():
         assert graphed.status() == 0 and eager.status() == 0
     assert torch.isfinite(graphed.u).all()
     assert graphed.u[0].abs().max().item() > 0.0
+
+
+@pytest.mark.parametrize("case", ["tunnel", "periodic_forced", "channel"])
+def test_home_step_adj(case):
+    """The reverse of the HOME step against float64 autograd of the oracle
+    step: d/d(rho - 1, u, S) of <m_out_bar, moments out> + <u_bar, u*>."""
+    c = CASES[case]
+    nx, ny, nz = c["dims"]
+    say(f"lbm_home_step_adj {case}")
+    md, rho0, u0, S0 = _pack(*_random_state(c["dims"], 21))
+    solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
+    solid[nz // 3:nz // 3 + 2, ny // 3:ny // 3 + 2, nx // 2:nx // 2 + 5] = True
+    t = 9
+    op, ap = _params(tau=c["tau"], force=c["force"], bc=c["bc"], gust=c["gust"], t=t)
+    lat = olbm.Lattice(nx, ny, nz)
+    L = nx * ny * nz
+    rng = np.random.default_rng(22)
+    mbar = f32(torch.tensor(rng.standard_normal((10, L))))
+    ubar = f32(torch.tensor(rng.standard_normal((3, L))))
+    rho = rho0.clone().requires_grad_(True)
+    u = u0.clone().requires_grad_(True)
+    S = S0.clone().requires_grad_(True)
+    rn, un, Sn, _, ur = ohome.home_step(lat, op, rho, u, S, solid, t)
+    out = torch.cat([(rn - 1.0).reshape(1, L), un.reshape(3, L), Sn.reshape(6, L)])
+    gr, gu, gS = torch.autograd.grad((out * mbar).sum() + (ur.reshape(3, L) * ubar).sum(), (rho, u, S))
+    mb = torch.full((10, L), 0.5, device=DEV)     # accumulates onto what is there
+    api.lbm_home_step_adj(api.make_lattice(nx, ny, nz), ap, md, solid.reshape(-1).to(torch.uint8).to(DEV),
+                          mbar.float().to(DEV), ubar.float().to(DEV), mb)
+    torch.cuda.synchronize()
+    got = mb.cpu().double() - 0.5
+    ref = torch.cat([gr.reshape(1, L), gu.reshape(3, L), gS.reshape(6, L)])
+
+    def rel2(a, b):
+        return ((a - b).norm() / b.norm()).item()
+
+    assert rel2(got[0], ref[0]) < 1e-3
+    assert rel2(got[1:4], ref[1:4]) < 1e-3
+    assert rel2(got[4:], ref[4:]) < 1e-3
