@@ -529,6 +529,13 @@ __global__ __launch_bounds__(256) void k_grid_update(GridDev g, float dt, float 
 
 // ------------------------------------------------------------------ G2P
 
+// G2P stages the grid velocities of its block's stencils in LDS when their
+// bounding box holds at most G2P_BOX nodes (12^3, 20.7 KB): particles stored
+// in tile order keep a block's box small, and the 27-node gathers then come
+// from LDS instead of the vector memory pipeline, which they saturated.
+// Blocks with a larger box gather from global memory as before.
+constexpr int G2P_BOX = 1728;
+
 struct Float3 {
   float v[3];
 };
@@ -536,21 +543,65 @@ struct Float3 {
 __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
                                              const float *xin, const float *Fin, float *xout, float *vout,
                                              float *Cout, float *Fout, int n, int32_t *__restrict__ status) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  float px = xin[p], py = xin[n + p], pz = xin[2 * n + p];
+  __shared__ float s_v[3][G2P_BOX];
+  __shared__ int s_red[256 / 64][6];
+  __shared__ int s_box[6];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = p < n;
+  const int pp = live ? p : 0;
+  float px = xin[pp], py = xin[n + pp], pz = xin[2 * n + pp];
   float X = grid_coord(px, g.ox, g.inv_dx);
   float Y = grid_coord(py, g.oy, g.inv_dx);
   float Z = grid_coord(pz, g.oz, g.inv_dx);
   float F[9];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) F[q] = Fin[q * n + p];
+  for (int q = 0; q < 9; ++q) F[q] = Fin[q * n + pp];
   bool ok = isfinite(X) && isfinite(Y) && isfinite(Z) && fabsf(X) < 1e9f && fabsf(Y) < 1e9f && fabsf(Z) < 1e9f;
   int bx = 0, by = 0, bz = 0;
   if (ok) {
     bx = base_of(X); by = base_of(Y); bz = base_of(Z);
     ok = stencil_inside(g, bx, by, bz);
   }
+  // bounding box of the block's stencils; stage it in LDS when it is small
+  {
+    int r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+    if (live && ok) { r[0] = bx; r[1] = by; r[2] = bz; r[3] = bx; r[4] = by; r[5] = bz; }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        r[a] = min(r[a], __shfl_xor(r[a], o, 64));
+        r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], o, 64));
+      }
+    }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int a = 0; a < 6; ++a) s_red[threadIdx.x >> 6][a] = r[a];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      int v = s_red[0][threadIdx.x];
+      for (int w = 1; w < 256 / 64; ++w) v = threadIdx.x < 3 ? min(v, s_red[w][threadIdx.x]) : max(v, s_red[w][threadIdx.x]);
+      s_box[threadIdx.x] = v;
+    }
+    __syncthreads();
+  }
+  const int lo0 = s_box[0], lo1 = s_box[1], lo2 = s_box[2];
+  const bool any = s_box[3] >= lo0;
+  const int ex = any ? s_box[3] - lo0 + 3 : 0, ey = any ? s_box[4] - lo1 + 3 : 0, ez = any ? s_box[5] - lo2 + 3 : 0;
+  const bool staged = any && ex * ey * ez <= G2P_BOX;
+  if (staged) {
+    const int nb = ex * ey * ez;
+    for (int q = threadIdx.x; q < nb; q += 256) {
+      const int ix = q % ex, iy = (q / ex) % ey, iz = q / (ex * ey);
+      const int64_t node = (lo0 + ix) + (int64_t)g.nx * ((lo1 + iy) + (int64_t)g.ny * (lo2 + iz));
+      s_v[0][q] = gv[node];
+      s_v[1][q] = gv[N + node];
+      s_v[2][q] = gv[2 * N + node];
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+  const int lx = bx - lo0, ly = by - lo1, lz = bz - lo2;
   if (!ok) {
     if (status) atomicOr(status, DW_STATUS_OUT_OF_GRID);
     xout[p] = px; xout[n + p] = py; xout[2 * n + p] = pz;
@@ -588,9 +639,19 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
       // the three x-neighbours of a stencil row are contiguous: one 12-byte
       // load per velocity component
       Float3 ra, rb, rc;
-      __builtin_memcpy(&ra, gv + row, sizeof(Float3));
-      __builtin_memcpy(&rb, gv + N + row, sizeof(Float3));
-      __builtin_memcpy(&rc, gv + 2 * N + row, sizeof(Float3));
+      if (staged) {
+        const int li = lx + ex * ((ly + oy) + ey * (lz + oz));
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+          ra.v[ox] = s_v[0][li + ox];
+          rb.v[ox] = s_v[1][li + ox];
+          rc.v[ox] = s_v[2][li + ox];
+        }
+      } else {
+        __builtin_memcpy(&ra, gv + row, sizeof(Float3));
+        __builtin_memcpy(&rb, gv + N + row, sizeof(Float3));
+        __builtin_memcpy(&rc, gv + 2 * N + row, sizeof(Float3));
+      }
       const float u0[3] = {ra.v[0] * wx[0] + ra.v[1] * wx[1] + ra.v[2] * wx[2],
                            rb.v[0] * wx[0] + rb.v[1] * wx[1] + rb.v[2] * wx[2],
                            rc.v[0] * wx[0] + rc.v[1] * wx[1] + rc.v[2] * wx[2]};

@@ -13,8 +13,8 @@ from oracle import mpm as ompm
 from oracle import wind as owind
 from paper_2603_09668_amd import api, scenes
 
-from gpu_util import (DEV, EYE, api_grid, f32, mat_from_dev, oracle_grid, rel, say, scene_state, vec_from_dev,
-                      vec_to_dev)
+from gpu_util import (DEV, EYE, api_grid, device_particles, f32, mat_from_dev, oracle_grid, rel, say, scene_state,
+                      vec_from_dev, vec_to_dev)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -200,6 +200,23 @@ def test_g2p_parity(scene_name, request):
     sc = request.getfixturevalue(scene_name)
     say(f"mpm_g2p {sc.name}")
     st, dev = scene_state(sc, seed=11)
+    _g2p_check(sc, st, dev)
+
+
+def test_g2p_parity_unsorted_particles(leaves):
+    """Particles in random order: the blocks' stencil boxes are too large to
+    stage and G2P gathers from global memory."""
+    sc = leaves
+    say(f"mpm_g2p {sc.name} shuffled")
+    st, _ = scene_state(sc, seed=11)
+    perm = torch.as_tensor(np.random.default_rng(5).permutation(sc.n))
+    st = {k: (v[perm] if torch.is_tensor(v) and v.shape[:1] == (sc.n,) else v) for k, v in st.items()}
+    dev = device_particles(st["x"], st["v"], st["C"], st["F"], st["mass"], st["vol0"], st["region"], st["E"],
+                           st["nu"])
+    _g2p_check(sc, st, dev)
+
+
+def _g2p_check(sc, st, dev):
     og = oracle_grid(sc.grid)
     g = api_grid(sc.grid)
     rng = np.random.default_rng(12)
