@@ -85,7 +85,8 @@ typedef struct {
 } dw_grid;
 
 /* LBM lattice: nodes at origin + dx * (i, j, k).  Solid cells of Eq.
- * point2voxel are the cells [x_w, x_w + dx). */
+ * point2voxel are the cells [x_w, x_w + dx).  The LBM calls take lattices of
+ * fewer than 2^29 nodes (DW_ERANGE otherwise; node offsets are 32-bit). */
 typedef struct {
   int nx, ny, nz;
   float dx;

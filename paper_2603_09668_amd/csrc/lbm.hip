@@ -90,9 +90,10 @@ __device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, 
 
 // Solid flags of the 3 x 3 (y, z) rows around this block's row,
 // x0 - 4 .. x0 + LBM_BLOCK + 3, staged in LDS: row r = (dy + 1) + 3 (dz + 1).
-// Rows outside the lattice read as fluid (their sources take the boundary
-// rules, which look at the solid array themselves).  Whole 4-byte words are
-// loaded where the row is 4-byte aligned.
+// A periodic axis stages the wrapped row / positions, so every source that
+// is not a bounce-back or inlet source finds its flag here; rows beyond a
+// bounce-back face and positions beyond a non-periodic x face read as fluid.
+// Whole 4-byte words are loaded where the row is 4-byte aligned.
 constexpr int SOL_WORDS = 9 * (SOL_W / 4);
 constexpr int SOL_PER_THREAD = (SOL_WORDS + LBM_BLOCK - 1) / LBM_BLOCK;
 
@@ -100,22 +101,35 @@ __device__ __forceinline__ void load_solid_rows(const LbmDev &P, const uint8_t *
                                                 int k, uint32_t v[SOL_PER_THREAD]) {
   constexpr int WORDS = SOL_W / 4;
   const bool aligned = (P.nx & 3) == 0 && (((uintptr_t)solid) & 3) == 0;
+  const bool xper = P.bc[0] == DW_BC_PERIODIC;
 #pragma unroll
   for (int u = 0; u < SOL_PER_THREAD; ++u) {
     const int q = threadIdx.x + u * LBM_BLOCK;
     v[u] = 0;
     if (q >= SOL_WORDS) continue;
     const int r = q / WORDS, w = q % WORDS;
-    const int jj = j + r % 3 - 1, kk = k + r / 3 - 1;
+    int jj = j + r % 3 - 1, kk = k + r / 3 - 1;
+    if ((unsigned)jj >= (unsigned)P.ny) {
+      if (P.bc[2] != DW_BC_PERIODIC) continue;
+      jj = jj < 0 ? jj + P.ny : jj - P.ny;
+    }
+    if ((unsigned)kk >= (unsigned)P.nz) {
+      if (P.bc[4] != DW_BC_PERIODIC) continue;
+      kk = kk < 0 ? kk + P.nz : kk - P.nz;
+    }
     const int xs = x0 - 4 + 4 * w;
-    if ((unsigned)jj < (unsigned)P.ny && (unsigned)kk < (unsigned)P.nz) {
-      const int64_t row = (int64_t)P.nx * (jj + (int64_t)P.ny * kk);
-      if (aligned && xs >= 0 && xs + 3 < P.nx) {
-        v[u] = *reinterpret_cast<const uint32_t *>(solid + row + xs);
-      } else {
+    const int64_t row = (int64_t)P.nx * (jj + (int64_t)P.ny * kk);
+    if (aligned && xs >= 0 && xs + 3 < P.nx) {
+      v[u] = *reinterpret_cast<const uint32_t *>(solid + row + xs);
+    } else {
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (xs + b >= 0 && xs + b < P.nx) v[u] |= (uint32_t)solid[row + xs + b] << (8 * b);
+      for (int b = 0; b < 4; ++b) {
+        int x = xs + b;
+        if ((unsigned)x >= (unsigned)P.nx) {
+          if (!xper) continue;
+          x = ((x % P.nx) + P.nx) % P.nx;
+        }
+        v[u] |= (uint32_t)solid[row + x] << (8 * b);
       }
     }
   }
@@ -162,6 +176,147 @@ __device__ __forceinline__ void pull_all(const LbmDev &P, const float *__restric
   }
 }
 
+// ---- forward pull with 32-bit offsets and row-uniform boundary rules
+//
+// The y and z faces are periodic or bounce-back (inlet and outlet sit on the
+// x faces only), so the y/z part of every source is the same for a whole
+// block row and is resolved with scalar branches; only the two x-boundary
+// lanes of a row take the x rules, by selects.  Node indices are 32-bit
+// (a lattice has fewer than 2^29 nodes) and every population plane is a
+// scalar base plus a per-lane byte offset.
+
+__device__ __forceinline__ float ld_node(const float *__restrict__ plane, uint32_t node) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(plane) + (node << 2));
+}
+
+__device__ __forceinline__ void st_node(float *__restrict__ plane, uint32_t node, float v) {
+  *reinterpret_cast<float *>(reinterpret_cast<char *>(plane) + (node << 2)) = v;
+}
+
+// slot of the five directions with c_x = +1 (the ones an x-inlet feeds)
+__host__ __device__ constexpr int inlet_slot(int q) {
+  return q == 1 ? 0 : q == 7 ? 1 : q == 9 ? 2 : q == 13 ? 3 : q == 15 ? 4 : -1;
+}
+__device__ constexpr int INLET_Q[5] = {1, 7, 9, 13, 15};
+
+struct PullSrc {
+  uint32_t src;  // source node (always inside the lattice)
+  int kind;      // SRC_NORMAL / SRC_BOUNCE / SRC_INLET
+  int wx;        // x of the source in the staged solid rows (unwrapped; clamped at an outlet)
+};
+
+// y/z part of the source row of direction (cy, cz) for row (j, k): wraps a
+// periodic face, flags a bounce-back face; *sj, *sk stay inside the lattice.
+__device__ __forceinline__ void row_source(const LbmDev &P, int j, int k, int cy, int cz, int *sj, int *sk,
+                                           bool *bounce) {
+  int a = j - cy, b = k - cz;
+  *bounce = false;
+  if ((unsigned)a >= (unsigned)P.ny) {
+    if (P.bc[2] == DW_BC_PERIODIC) a += cy > 0 ? P.ny : -P.ny;
+    else { *bounce = true; a = j; }
+  }
+  if ((unsigned)b >= (unsigned)P.nz) {
+    if (P.bc[4] == DW_BC_PERIODIC) b += cz > 0 ? P.nz : -P.nz;
+    else { *bounce = true; b = k; }
+  }
+  *sj = a;
+  *sk = b;
+}
+
+template <int Q>
+__device__ __forceinline__ PullSrc pull_src(const LbmDev &P, int i, int j, int k) {
+  constexpr int CX = LC[Q][0], CY = LC[Q][1], CZ = LC[Q][2];
+  int sj = j, sk = k;
+  bool bounce = false;
+  if (CY != 0 || CZ != 0) row_source(P, j, k, CY, CZ, &sj, &sk, &bounce);
+  int si = i - CX, wx = i - CX;
+  bool inlet = false;
+  if (CX != 0) {
+    const bool xout = CX > 0 ? si < 0 : si >= P.nx;
+    const int rule = P.bc[CX > 0 ? 0 : 1];
+    if (rule == DW_BC_PERIODIC) {
+      si = xout ? si + (CX > 0 ? P.nx : -P.nx) : si;
+    } else {
+      si = xout ? (CX > 0 ? 0 : P.nx - 1) : si;
+      wx = xout ? i : wx;
+      bounce = bounce || (xout && rule == DW_BC_BOUNCEBACK);
+      inlet = CX > 0 && xout && rule == DW_BC_INLET;
+    }
+  }
+  PullSrc s;
+  s.src = (uint32_t)si + (uint32_t)P.nx * ((uint32_t)sj + (uint32_t)P.ny * (uint32_t)sk);
+  s.kind = bounce ? SRC_BOUNCE : (inlet ? SRC_INLET : SRC_NORMAL);
+  s.wx = wx;
+  return s;
+}
+
+// Does the source of a normal pull hold a solid node?  SOL: 0 = no solid flag
+// in the staged rows (so none on any source), 1 = look the flag up there.
+template <int Q, int SOL>
+__device__ __forceinline__ bool src_solid(const PullSrc &s, const uint8_t (*s_sol)[SOL_W], int x0) {
+  constexpr int CY = LC[Q][1], CZ = LC[Q][2];
+  if (SOL == 0) return false;
+  return s_sol[(1 - CY) + 3 * (1 - CZ)][s.wx - x0 + 4] != 0;
+}
+
+// the inlet population of the five c_x = +1 directions for block row (j, k),
+// staged by the block that holds x = 0 (threads 0..4)
+__device__ __forceinline__ void stage_inlet(const LbmDev &P, int j, int k, float *s_inl) {
+  if (threadIdx.x < 5) {
+    const int q = INLET_Q[threadIdx.x];
+    int sj, sk;
+    bool bounce;
+    row_source(P, j, k, LC[q][1], LC[q][2], &sj, &sk, &bounce);
+    s_inl[threadIdx.x] = inlet_feq_shift(P, q, sj, sk);
+  }
+}
+
+// Does the population of direction Q bounce back at this node (a bounce-back
+// face, or a source on a solid node)?
+template <int Q, int SOL>
+__device__ __forceinline__ bool pull_bounces(const PullSrc &s, const uint8_t (*s_sol)[SOL_W], int x0) {
+  const bool sf = src_solid<Q, SOL>(s, s_sol, x0);
+  return s.kind == SRC_BOUNCE || (s.kind == SRC_NORMAL && sf);
+}
+
+// The value a population takes comes from plane Q at the source node or, on
+// bounce-back, from plane LOPP[Q] at this node.  The two planes are adjacent
+// (LOPP pairs q with q +- 1), so one 32-bit offset from the lower of them
+// addresses either and the choice is a select: one load per population,
+// issued once the bounce flags are known, and no load waits on another.
+template <int Q>
+__device__ __forceinline__ constexpr int pair_lo() {
+  return Q < LOPP[Q] ? Q : LOPP[Q];
+}
+
+template <int Q, int SOL>
+__device__ __forceinline__ uint32_t pull_offset(const LbmDev &P, const uint8_t (*s_sol)[SOL_W], int i, int j, int k,
+                                                int x0, uint32_t node) {
+  const PullSrc s = pull_src<Q>(P, i, j, k);
+  const bool bb = pull_bounces<Q, SOL>(s, s_sol, x0);
+  const uint32_t L = (uint32_t)P.L;
+  return bb ? (uint32_t)(LOPP[Q] - pair_lo<Q>()) * L + node : (uint32_t)(Q - pair_lo<Q>()) * L + s.src;
+}
+
+// x-inlet lanes (x = 0 of an inlet row) take the staged inlet population
+template <int Q>
+__device__ __forceinline__ void pull_inlet(const LbmDev &P, const float *s_inl, int i, int j, int k, float &f) {
+  if constexpr (inlet_slot(Q) >= 0) {
+    if (pull_src<Q>(P, i, j, k).kind == SRC_INLET) f = s_inl[inlet_slot(Q)];
+  }
+}
+
+template <int SOL, int... Qs>
+__device__ __forceinline__ void pull_row(std::integer_sequence<int, Qs...>, const LbmDev &P,
+                                         const float *__restrict__ fin, const uint8_t (*s_sol)[SOL_W],
+                                         const float *s_inl, bool inlet_wave, int i, int j, int k, int x0,
+                                         uint32_t node, float f[19]) {
+  uint32_t off[19];
+  ((off[Qs] = pull_offset<Qs, SOL>(P, s_sol, i, j, k, x0, node)), ...);
+  ((f[Qs] = ld_node(fin + (size_t)pair_lo<Qs>() * P.L, off[Qs])), ...);
+  if (inlet_wave) (pull_inlet<Qs>(P, s_inl, i, j, k, f[Qs]), ...);
+}
+
 __device__ __forceinline__ void moments(const LbmDev &P, const float f[19], float &rho, float &ux, float &uy,
                                         float &uz) {
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -185,11 +340,15 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
                                                         float *__restrict__ rho_out, float *__restrict__ u_out) {
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
   __shared__ int s_any[LBM_BLOCK / 64];
+  __shared__ float s_inl[5];
   const int x0 = blockIdx.x * LBM_BLOCK;
   const int i = x0 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
   if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
-  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
+  const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
   float f[19];
+  // the row's x = 0 block stages the inlet populations (block-uniform)
+  const bool inlet_row = x0 == 0 && P.bc[0] == DW_BC_INLET;
+  if (inlet_row) stage_inlet(P, j, k, s_inl);
   // any solid flag in the staged rows?  Most blocks have none and take the
   // plain pull (block-uniform branch).
   bool any = false;
@@ -205,24 +364,18 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < LBM_BLOCK / 64; ++w) any = any || s_any[w] != 0;
+  } else if (inlet_row) {
+    __syncthreads();
   }
   if (i >= P.nx) return;
-  if (any) {
-    if (!s_sol[4][i - x0 + 4]) pull_all<1>(P, fin, solid, s_sol, i, j, k, x0, node, f);
-  } else {
-    pull_all<0>(P, fin, solid, s_sol, i, j, k, x0, node, f);
-  }
-  if (any && s_sol[4][i - x0 + 4]) {
-#pragma unroll
-    for (int q = 0; q < 19; ++q) fout[(int64_t)q * P.L + node] = 0.f;
-    if (rho_out) rho_out[node] = 1.f;
-    if (u_out) {
-      u_out[node] = 0.f;
-      u_out[P.L + node] = 0.f;
-      u_out[2 * P.L + node] = 0.f;
-    }
-    return;
-  }
+  // A solid node outputs the rest state (f = w, u = 0, rho = 1).  It runs
+  // the pull with its neighbours and only its stores are replaced, so the
+  // lanes of a wave write their cache lines together.
+  const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
+  // wave-uniform: the first wave of an inlet row's x = 0 block holds the inlet lane
+  const bool inlet_wave = inlet_row && threadIdx.x < 64;
+  if (any) pull_row<1>(std::make_integer_sequence<int, 19>{}, P, fin, s_sol, s_inl, inlet_wave, i, j, k, x0, node, f);
+  else pull_row<0>(std::make_integer_sequence<int, 19>{}, P, fin, s_sol, s_inl, inlet_wave, i, j, k, x0, node, f);
   float rho, ux, uy, uz;
   moments(P, f, rho, ux, uy, uz);
   float drho = rho - 1.0f;
@@ -239,13 +392,13 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
       float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
       g += kf * LW[q] * (3.f * (cF - uF) + 9.f * cu * cF);
     }
-    fout[(int64_t)q * P.L + node] = g;
+    st_node(fout + (size_t)q * P.L, node, solid_node ? 0.f : g);
   }
-  if (rho_out) rho_out[node] = rho;
+  if (rho_out) st_node(rho_out, node, solid_node ? 1.f : rho);
   if (u_out) {
-    u_out[node] = ux;
-    u_out[P.L + node] = uy;
-    u_out[2 * P.L + node] = uz;
+    st_node(u_out, node, solid_node ? 0.f : ux);
+    st_node(u_out + P.L, node, solid_node ? 0.f : uy);
+    st_node(u_out + 2 * P.L, node, solid_node ? 0.f : uz);
   }
 }
 
@@ -799,7 +952,7 @@ static int make_lbm(const dw_lattice *lat, const dw_lbm_params *prm, LbmDev *P) 
   DW_REQUIRE(lat && prm, DW_EINVAL, "lbm: lattice / params is NULL");
   DW_REQUIRE(lat->nx >= 1 && lat->ny >= 1 && lat->nz >= 1, DW_EINVAL, "lbm: lattice dims must be >= 1");
   int64_t L = (int64_t)lat->nx * lat->ny * lat->nz;
-  DW_REQUIRE(L * 19 < (int64_t)INT_MAX * 64, DW_ERANGE, "lbm: lattice too large");
+  DW_REQUIRE(L < ((int64_t)1 << 29), DW_ERANGE, "lbm: lattice too large (fewer than 2^29 nodes)");
   DW_REQUIRE(lat->ny <= 65535 && lat->nz <= 65535, DW_ERANGE, "lbm: ny, nz must be <= 65535");
   DW_REQUIRE(prm->tau > 0.5f, DW_EINVAL, "lbm: tau must be > 1/2 (got %g)", (double)prm->tau);
   for (int a = 0; a < 3; ++a) {

@@ -44,6 +44,12 @@ CASES = {
     "tunnel": dict(dims=(24, 20, 16), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 200.0, 1.0, 1.0, 0.3)),
     "periodic_forced": dict(dims=(12, 10, 8), bc=(0,) * 6, force=(1e-4, -2e-5, 3e-5), gust=(0.0, 1.0, 0, 0, 0)),
     "channel": dict(dims=(17, 9, 11), bc=(0, 0, 1, 1, 0, 0), force=(1e-5, 0.0, 0.0), gust=(0.0, 1.0, 0, 0, 0)),
+    # solids on the faces, so wrapped sources land on solid nodes
+    "periodic_face_solids": dict(dims=(16, 10, 9), bc=(0,) * 6, force=(0.0, 0.0, 0.0), gust=(0.0, 1.0, 0, 0, 0),
+                                 solid=(slice(0, 2), slice(8, 10), slice(14, 16))),
+    # rows longer than one workgroup (x0 > 0), solids in the second one
+    "wide_tunnel": dict(dims=(200, 7, 6), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 120.0, 1.0, 0.0, 0.7),
+                        solid=(slice(2, 4), slice(3, 5), slice(150, 190))),
 }
 
 
@@ -54,7 +60,7 @@ def test_lbm_step_parity(case):
     say(f"lbm_step {case} {c['dims']}")
     f, fs = _random_state(c["dims"], 1)
     solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
-    solid[nz // 3:nz // 3 + 4, ny // 3:ny // 3 + 3, nx // 2:nx // 2 + 5] = True
+    solid[c.get("solid", (slice(nz // 3, nz // 3 + 4), slice(ny // 3, ny // 3 + 3), slice(nx // 2, nx // 2 + 5)))] = True
     t = 17
     op, ap = _params(force=c["force"], bc=c["bc"], gust=c["gust"], t=t)
     lat = olbm.Lattice(nx, ny, nz)
