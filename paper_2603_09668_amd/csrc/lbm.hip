@@ -581,6 +581,64 @@ __device__ __forceinline__ void home_pull_all(std::integer_sequence<int, Qs...>,
   (home_pull<SOL, Qs>(P, min, solid, s_sol, i, j, k, x0, node, own, A), ...);
 }
 
+// Forward pull of the moment-encoded step with the row-uniform source rules
+// and 32-bit offsets of the population step: every bounce decision comes
+// from the staged flags first, then each source's ten moments are loaded
+// from scalar plane bases (one offset per source) and expanded.
+__device__ __forceinline__ Mom load_mom_at(const float *__restrict__ m, size_t L, uint32_t node) {
+  Mom M;
+  M.drho = ld_node(m, node);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) M.u[a] = ld_node(m + (1 + a) * L, node);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) M.S[s] = ld_node(m + (4 + s) * L, node);
+  return M;
+}
+
+// inlet population of direction INLET_Q[t] for block row (j, k)
+__device__ __forceinline__ float home_inlet_pop(const LbmDev &P, int t, int j, int k) {
+  const int q = INLET_Q[t];
+  int sj, sk;
+  bool bounce;
+  row_source(P, j, k, LC[q][1], LC[q][2], &sj, &sk, &bounce);
+  const Mom M = inlet_mom(P, sj, sk);
+  switch (t) {
+    case 0: return home_pop<1>(M);
+    case 1: return home_pop<7>(M);
+    case 2: return home_pop<9>(M);
+    case 3: return home_pop<13>(M);
+    default: return home_pop<15>(M);
+  }
+}
+
+template <int SOL, int Q>
+__device__ __forceinline__ void home_pull_row(const LbmDev &P, const float *__restrict__ min, const float *s_inl,
+                                              bool inlet_wave, int i, int j, int k, const Mom &own, bool bb,
+                                              MomAcc &A) {
+  float g;
+  if constexpr (Q == 0) {
+    g = home_pop<0>(own);
+  } else {
+    const PullSrc s = pull_src<Q>(P, i, j, k);
+    g = home_pop<Q>(load_mom_at(min, P.L, s.src));
+    if (bb) g = home_pop<LOPP[Q]>(own);
+    if constexpr (inlet_slot(Q) >= 0) {
+      if (inlet_wave && s.kind == SRC_INLET) g = s_inl[inlet_slot(Q)];
+    }
+  }
+  acc_pop<Q>(A, g);
+}
+
+template <int SOL, int... Qs>
+__device__ __forceinline__ void home_row_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
+                                             const float *__restrict__ min, const uint8_t (*s_sol)[SOL_W],
+                                             const float *s_inl, bool inlet_wave, int i, int j, int k, int x0,
+                                             const Mom &own, MomAcc &A) {
+  bool bb[19];
+  ((bb[Qs] = pull_bounces<Qs, SOL>(pull_src<Qs>(P, i, j, k), s_sol, x0)), ...);
+  (home_pull_row<SOL, Qs>(P, min, s_inl, inlet_wave, i, j, k, own, bb[Qs], A), ...);
+}
+
 // Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so
 // consecutive block indices land on different XCDs.  The moment-encoded step
 // reads every node's moments from the 3 x 3 neighbouring rows; giving each
@@ -619,12 +677,16 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_step(LbmDev P, const float *
                                                          float *__restrict__ rho_out, float *__restrict__ u_out) {
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
   __shared__ int s_any[LBM_BLOCK / 64];
+  __shared__ float s_inl[5];
   const RowBlock rb = xcd_row_block(P);
   if (!rb.live) return;  // block-uniform: padding blocks of the last XCD
   const int x0 = rb.x0;
   const int i = x0 + threadIdx.x, j = rb.j, k = rb.k;
   if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
-  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
+  const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
+  // the row's x = 0 block stages the inlet populations (block-uniform)
+  const bool inlet_row = x0 == 0 && P.bc[0] == DW_BC_INLET;
+  if (inlet_row && threadIdx.x < 5) s_inl[threadIdx.x] = home_inlet_pop(P, threadIdx.x, j, k);
   bool any = false;
   if (SOLID) {
     uint32_t sv[SOL_PER_THREAD];
@@ -638,24 +700,18 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_step(LbmDev P, const float *
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < LBM_BLOCK / 64; ++w) any = any || s_any[w] != 0;
+  } else if (inlet_row) {
+    __syncthreads();
   }
   if (i >= P.nx) return;
-  if (any && s_sol[4][i - x0 + 4]) {
-    // solid node: rest state
-#pragma unroll
-    for (int q = 0; q < HM_N; ++q) mout[(int64_t)q * P.L + node] = 0.f;
-    if (rho_out) rho_out[node] = 1.f;
-    if (u_out) {
-      u_out[node] = 0.f;
-      u_out[P.L + node] = 0.f;
-      u_out[2 * P.L + node] = 0.f;
-    }
-    return;
-  }
-  const Mom own = load_mom(min, P.L, node);
+  // a solid node outputs the rest state; it runs with its wave and only its
+  // stores are replaced, so the lanes of a wave write their lines together
+  const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
+  const bool inlet_wave = inlet_row && threadIdx.x < 64;  // wave-uniform
+  const Mom own = load_mom_at(min, P.L, node);
   MomAcc A;
-  if (any) home_pull_all<1>(std::make_integer_sequence<int, 19>{}, P, min, solid, s_sol, i, j, k, x0, node, own, A);
-  else home_pull_all<0>(std::make_integer_sequence<int, 19>{}, P, min, solid, s_sol, i, j, k, x0, node, own, A);
+  if (any) home_row_all<1>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
+  else home_row_all<0>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
   // moments of the pulled set: u* carries half the force
   const float rho = 1.f + A.drho, ir = 1.f / rho;
   float u[3], Fu = 0.f, uu = 0.f;
@@ -681,16 +737,15 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_step(LbmDev P, const float *
   Sn[3] = keep * S[3] + om * u[0] * u[1] + kf * (P.F[0] * u[1] + P.F[1] * u[0]);
   Sn[4] = keep * S[4] + om * u[0] * u[2] + kf * (P.F[0] * u[2] + P.F[2] * u[0]);
   Sn[5] = keep * S[5] + om * u[1] * u[2] + kf * (P.F[1] * u[2] + P.F[2] * u[1]);
-  mout[node] = A.drho;
+  st_node(mout, node, solid_node ? 0.f : A.drho);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) mout[(1 + a) * P.L + node] = u[a] + 0.5f * P.F[a] * ir;
+  for (int a = 0; a < 3; ++a) st_node(mout + (size_t)(1 + a) * P.L, node, solid_node ? 0.f : u[a] + 0.5f * P.F[a] * ir);
 #pragma unroll
-  for (int s = 0; s < 6; ++s) mout[(4 + s) * P.L + node] = Sn[s];
-  if (rho_out) rho_out[node] = rho;
+  for (int s = 0; s < 6; ++s) st_node(mout + (size_t)(4 + s) * P.L, node, solid_node ? 0.f : Sn[s]);
+  if (rho_out) st_node(rho_out, node, solid_node ? 1.f : rho);
   if (u_out) {
-    u_out[node] = u[0];
-    u_out[P.L + node] = u[1];
-    u_out[2 * P.L + node] = u[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) st_node(u_out + (size_t)a * P.L, node, solid_node ? 0.f : u[a]);
   }
 }
 
