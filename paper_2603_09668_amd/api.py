@@ -504,13 +504,13 @@ def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
 
     take("header", 64)
     take("tile_count", T)
-    take("tile_cursor", T)
     take("node_flag", T)
     take("tile_start", T + 1)
     take("cell_tiles", T)
     take("node_tiles", T)
     take("block_sums", 4 * NB)
     take("key", n)
+    take("rank", n)
     take("perm", n)
     take("perm_tmp", n)
     max_items = T + n // WORK_CHUNK + 1

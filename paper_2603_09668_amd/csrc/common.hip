@@ -40,20 +40,21 @@ size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base, 
     return (int32_t *)p;
   };
   int32_t *hdr = take(256);
-  // hdr[0] status; hdr[8..9] P2G work-item tickets; hdr[3..6] scan totals: sorted particles, active node
-  // tiles, active cell tiles, work items
+  // hdr[0] status; hdr[3..6] scan totals: sorted particles, active node tiles, active cell tiles, work
+  // items; hdr[8..9] P2G work-item tickets
   ws->status = hdr;
   ws->n_node_tiles = hdr ? hdr + 4 : nullptr;
   ws->n_cell_tiles = hdr ? hdr + 5 : nullptr;
   ws->n_items = hdr ? hdr + 6 : nullptr;
+  // header .. node_flag are cleared at the start of every sort
   ws->tile_count = take(sizeof(int32_t) * T);
-  ws->tile_cursor = take(sizeof(int32_t) * T);
   ws->node_flag = take(sizeof(int32_t) * T);
   ws->tile_start = take(sizeof(int32_t) * (T + 1));
   ws->cell_tiles = take(sizeof(int32_t) * T);
   ws->node_tiles = take(sizeof(int32_t) * T);
   ws->block_sums = take(sizeof(int32_t) * 4 * NB);
   ws->key = take(sizeof(int32_t) * (size_t)n_max);
+  ws->rank = take(sizeof(int32_t) * (size_t)n_max);
   ws->perm = take(sizeof(int32_t) * (size_t)n_max);
   ws->perm_tmp = take(sizeof(int32_t) * (size_t)n_max);
   int64_t max_items = T + (int64_t)n_max / WORK_CHUNK + 1;

@@ -40,28 +40,27 @@ inline GridDev make_grid(const dw_grid *g) {
 }
 
 // Workspace layout (bytes, all 256-aligned):
-//   [0, 256)          header: int32 status, n_cell_tiles, n_node_tiles, scratch
-//   tile_count  [T]   int32
-//   tile_start  [T+1] int32
-//   tile_cursor [T]   int32
-//   node_flag   [T]   int32
-//   cell_tiles  [T]   int32   active cell tiles (tile index)
-//   node_tiles  [T]   int32   active node tiles
-//   block_sums  [2*NB] int32  scan partials
-//   key         [n]   int32
-//   perm        [n]   int32
+//   [0, 256)            header: int32 status, scan totals, P2G tickets
+//   tile_count  [T]     int32   particles per cell tile
+//   node_flag   [T]     int32   node tile touched by a stencil
+//   tile_start  [T+1]   int32
+//   cell_tiles  [T]     int32   active cell tiles (tile index)
+//   node_tiles  [T]     int32   active node tiles
+//   block_sums  [4*NB]  int32   scan partials
+//   key, rank, perm, perm_tmp [n] int32
+//   item_tile, item_begin [max items], item_first [T], item_part (deterministic)
 struct Workspace {
   int32_t *status;
   int32_t *n_cell_tiles;
   int32_t *n_node_tiles;
   int32_t *tile_count;
   int32_t *tile_start;
-  int32_t *tile_cursor;
   int32_t *node_flag;
   int32_t *cell_tiles;
   int32_t *node_tiles;
   int32_t *block_sums;
   int32_t *key;
+  int32_t *rank;  // position of each particle inside its tile's range
   int32_t *perm;
   int32_t *perm_tmp;
   int32_t *n_items;     // work items: chunks of <= WORK_CHUNK particles of one cell tile

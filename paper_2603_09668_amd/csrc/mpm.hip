@@ -39,9 +39,11 @@ __device__ __forceinline__ int wave_keyed_add(int32_t *counters, int key, bool a
   return result;
 }
 
+// Key of every particle and its rank inside its tile (the tile count's value
+// before the particle's wave added to it), so the scatter needs no atomics.
 __global__ void k_sort_keys(GridDev g, const float *__restrict__ x, int n, int32_t *__restrict__ key,
-                            int32_t *__restrict__ tile_count, int32_t *__restrict__ node_flag,
-                            int32_t *__restrict__ status) {
+                            int32_t *__restrict__ rank, int32_t *__restrict__ tile_count,
+                            int32_t *__restrict__ node_flag, int32_t *__restrict__ status) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = p < n;
   int k = -1;
@@ -60,9 +62,12 @@ __global__ void k_sort_keys(GridDev g, const float *__restrict__ x, int n, int32
       if (stencil_inside(g, bx, by, bz)) k = (bx >> 2) + g.tx * ((by >> 2) + g.ty * (bz >> 2));
       else atomicOr(status, DW_STATUS_OUT_OF_GRID);
     }
-    key[p] = k;
   }
-  wave_keyed_add(tile_count, k, k >= 0);
+  const int r = wave_keyed_add(tile_count, k, k >= 0);
+  if (live) {
+    key[p] = k;
+    rank[p] = r;
+  }
   if (k >= 0) {
     int tx = bx >> 2, ty = by >> 2, tz = bz >> 2;
     int ux = (bx + 2) >> 2, uy = (by + 2) >> 2, uz = (bz + 2) >> 2;
@@ -189,12 +194,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
   }
 }
 
-__global__ void k_sort_scatter(const int32_t *__restrict__ key, int n, const int32_t *__restrict__ tile_start,
-                               int32_t *__restrict__ cursor, int32_t *__restrict__ perm) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  int k = p < n ? key[p] : -1;
-  int r = wave_keyed_add(cursor, k, k >= 0);
-  if (k >= 0) perm[tile_start[k] + r] = p;
+__global__ void k_sort_scatter(const int32_t *__restrict__ key, const int32_t *__restrict__ rank, int n,
+                               const int32_t *__restrict__ tile_start, int32_t *__restrict__ perm) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int k = key[p];
+  if (k >= 0) perm[tile_start[k] + rank[p]] = p;
 }
 
 // Deterministic mode: sort each tile's segment by particle index (rank by count).
@@ -736,12 +741,12 @@ int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, cons
              hipStream_t s) {
   GridDev g = make_grid(grid);
   int64_t T = W.n_tiles, NB = W.n_scan_blocks;
-  // header + tile_count + tile_cursor + node_flag are contiguous: clear them
+  // header + tile_count + node_flag are contiguous: clear them
   int64_t clear_words = (int64_t)((char *)W.tile_start - (char *)W.status) / 4;
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_blocks(clear_words, 256)), dim3(256), 0, s, W.status, clear_words, 0);
   if (n > 0)
-    hipLaunchKernelGGL(k_sort_keys, dim3(grid_blocks(n, 256)), dim3(256), 0, s, g, x, n, W.key, W.tile_count,
-                       W.node_flag, W.status);
+    hipLaunchKernelGGL(k_sort_keys, dim3(grid_blocks(n, 256)), dim3(256), 0, s, g, x, n, W.key, W.rank,
+                       W.tile_count, W.node_flag, W.status);
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
                      W.block_sums, NB);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
@@ -749,8 +754,8 @@ int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, cons
                      W.item_first, W.status + 3);
   if (n > 0) {
     int32_t *dst = deterministic ? W.perm_tmp : W.perm;
-    hipLaunchKernelGGL(k_sort_scatter, dim3(grid_blocks(n, 256)), dim3(256), 0, s, W.key, n, W.tile_start,
-                       W.tile_cursor, dst);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(grid_blocks(n, 256)), dim3(256), 0, s, W.key, W.rank, n, W.tile_start,
+                       dst);
     if (deterministic)
       hipLaunchKernelGGL(k_sort_segments, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, W.tile_start, W.cell_tiles,
                          W.n_cell_tiles, W.perm_tmp, W.perm);
