@@ -553,14 +553,14 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
   __shared__ int s_box[6];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < n;
-  const int pp = live ? p : 0;
-  float px = xin[pp], py = xin[n + pp], pz = xin[2 * n + pp];
+  const uint32_t pp = live ? (uint32_t)p : 0u;
+  float px = ld32(xin, pp), py = ld32(xin + n, pp), pz = ld32(xin + 2 * (size_t)n, pp);
   float X = grid_coord(px, g.ox, g.inv_dx);
   float Y = grid_coord(py, g.oy, g.inv_dx);
   float Z = grid_coord(pz, g.oz, g.inv_dx);
   float F[9];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) F[q] = Fin[q * n + pp];
+  for (int q = 0; q < 9; ++q) F[q] = ld32(Fin + (size_t)q * n, pp);
   bool ok = isfinite(X) && isfinite(Y) && isfinite(Z) && fabsf(X) < 1e9f && fabsf(Y) < 1e9f && fabsf(Z) < 1e9f;
   int bx = 0, by = 0, bz = 0;
   if (ok) {
@@ -685,12 +685,12 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
   float Cn[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) Cn[q] = kc * B[q];
-  xout[p] = px + dt * v0;
-  xout[n + p] = py + dt * v1;
-  xout[2 * n + p] = pz + dt * v2;
-  vout[p] = v0;
-  vout[n + p] = v1;
-  vout[2 * n + p] = v2;
+  st32(xout, pp, px + dt * v0);
+  st32(xout + n, pp, py + dt * v1);
+  st32(xout + 2 * (size_t)n, pp, pz + dt * v2);
+  st32(vout, pp, v0);
+  st32(vout + n, pp, v1);
+  st32(vout + 2 * (size_t)n, pp, v2);
   // F <- (I + dt C) F with F = I + H stored as H:  H <- H + dt C + dt C H
   float G[9], CH[9], Fn[9];
 #pragma unroll
@@ -700,8 +700,8 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
   for (int q = 0; q < 9; ++q) Fn[q] = F[q] + G[q] + CH[q];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    Cout[q * n + p] = Cn[q];
-    Fout[q * n + p] = Fn[q];
+    st32(Cout + (size_t)q * n, pp, Cn[q]);
+    st32(Fout + (size_t)q * n, pp, Fn[q]);
   }
 }
 
