@@ -28,18 +28,23 @@ namespace dw {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// float -> bf16, round to nearest even (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+// two floats -> packed bf16 pair (a in the low half), one instruction
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v{a, b}, bf16x2));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// logistic function with the hardware exponential and reciprocal (about
+// 1 ulp each, far below the bf16 rounding of every value it feeds)
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-  float sg = 1.0f / (1.0f + __expf(-z));
+  const float sg = sigmoid(z);
   return sg * (1.0f + z * (1.0f - sg));
 }
 
@@ -107,72 +112,82 @@ __device__ __forceinline__ void stage_patch(const ConvGeom &G, const uint16_t *_
   constexpr int VEC = CINP / 8;
   constexpr int NV = QVOX * VEC;
   constexpr int ITER = (NV + 255) / 256;
+  // each iteration moves a lane 256 chunks = D voxels on through the patch:
+  // its coordinates and field index advance by constant steps with carries
+  // (no divisions or 32-bit multiplies per chunk)
+  constexpr int D = 256 / VEC;
+  constexpr int DX = D % QX, DY = (D / QX) % QY, DZ = D / (QX * QY);
+  static_assert(256 % VEC == 0, "a lane keeps its channel chunk across iterations");
   const uint16_t *field = x + (int64_t)o.b * G.L * CINP;
   __amdgpu_buffer_rsrc_t rsrc =
       __builtin_amdgcn_make_buffer_rsrc((void *)field, (short)0, (int)(G.L * CINP * 2), 0x00020000);
   const int wid = threadIdx.x >> 6;
   int lane = threadIdx.x & 63;
   // recompute the per-lane patch coordinates for every tile rather than
-  // keeping ITER x 4 of them live across the tile loop
+  // keeping them live across the tile loop
   asm volatile("" : "+v"(lane));
+  const int ql = wid * 64 + lane;  // this lane's chunk in iteration 0
+  const int p = ql % VEC;
+  const int v = ql / VEC;
+  int xx = v % QX, yy = (v / QX) % QY;
+  int gx = o.x0 + xx - 1, gy = o.y0 + yy - 1, gz = o.z0 + v / (QX * QY) - 1;
+  const int sy = G.nx, sz = G.nx * G.ny;
+  int lin = gx + sy * gy + sz * gz;
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
-    int q0 = it * 256 + wid * 64;  // first chunk of this wave (uniform)
+    const int q0 = it * 256 + wid * 64;  // first chunk of this wave (uniform)
     if (q0 >= NV) break;
-    int q = q0 + lane;
-    int v = q / VEC, p = q % VEC;
-    int xx = v % QX, yy = (v / QX) % QY, zz = v / (QX * QY);
-    int c = VEC == 4 ? (p ^ swz(xx)) : p;  // channel chunk stored at position p
-    int gx = o.x0 + xx - 1, gy = o.y0 + yy - 1, gz = o.z0 + zz - 1;
-    bool in = q < NV && gx >= 0 && gy >= 0 && gz >= 0 && gx < G.nx && gy < G.ny && gz < G.nz;
-    unsigned off = in ? (unsigned)(((gx + G.nx * (gy + G.ny * gz)) * CINP + c * 8) * 2) : 0x80000000u;
+    const int q = q0 + lane;
+    const int c = VEC == 4 ? (p ^ swz(xx)) : p;  // channel chunk stored at position p
+    const bool in = q < NV && (unsigned)gx < (unsigned)G.nx && (unsigned)gy < (unsigned)G.ny &&
+                    (unsigned)gz < (unsigned)G.nz;
+    const unsigned off = in ? (unsigned)((lin * CINP + c * 8) * 2) : 0x80000000u;
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_ptr_t)(s_in + q0 * 8), 16, off, 0, 0, 0);
+    xx += DX; gx += DX; lin += DX;
+    if (xx >= QX) { xx -= QX; gx -= QX; yy += 1; gy += 1; lin += sy - QX; }
+    yy += DY; gy += DY; lin += DY * sy;
+    if (yy >= QY) { yy -= QY; gy -= QY; gz += 1; lin += sz - QY * sy; }
+    gz += DZ; lin += DZ * sz;
   }
 }
 
 // Epilogue of one output row: lane holds channels co0 .. co0 + 3 of voxel
-// x0 + r16 (acc = those 4 sums).
+// vi of field o.b (acc = those 4 sums); live = the voxel is inside the field
+// (ragged edge tiles).  Per-field bases plus 32-bit element offsets.
 template <int COUTP, int EPI>
-__device__ __forceinline__ void conv_epilogue(const ConvGeom &G, const TileOrigin &o, int gy, int gz, int r16,
+__device__ __forceinline__ void conv_epilogue(const ConvGeom &G, const TileOrigin &o, bool live, uint32_t vi,
                                               int co0, floatx4 acc, const float *s_bias, int cout,
                                               uint16_t *__restrict__ y, uint16_t *__restrict__ zpre,
                                               const uint16_t *__restrict__ zgate, const float *__restrict__ u,
                                               float sb, float *__restrict__ u_out) {
-  int gx = o.x0 + r16;
-  if (gx >= G.nx || gy >= G.ny || gz >= G.nz) return;  // ragged edge tile
-  int64_t vi = gx + (int64_t)G.nx * (gy + (int64_t)G.ny * gz);
-  int64_t gv = (int64_t)o.b * G.L + vi;
+  if (!live) return;
+  const uint32_t ei = vi * COUTP + co0;  // element offset in the field's activations
+  const size_t fb = (size_t)o.b * G.L * COUTP;
   if (EPI == DW_CONV_HIDDEN) {
-    uint16_t ob[4], zz[4];
+    float zv[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float zv = acc[j] + s_bias[co0 + j];
-      zz[j] = f2bf(zv);
-      ob[j] = f2bf(silu(zv));
-    }
-    *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) =
-        make_uint2(ob[0] | ((uint32_t)ob[1] << 16), ob[2] | ((uint32_t)ob[3] << 16));
-    if (zpre)
-      *reinterpret_cast<uint2 *>(zpre + gv * COUTP + co0) =
-          make_uint2(zz[0] | ((uint32_t)zz[1] << 16), zz[2] | ((uint32_t)zz[3] << 16));
+    for (int j = 0; j < 4; ++j) zv[j] = acc[j] + s_bias[co0 + j];
+    *reinterpret_cast<uint2 *>(y + fb + ei) = make_uint2(f2bf2(silu(zv[0]), silu(zv[1])), f2bf2(silu(zv[2]), silu(zv[3])));
+    if (zpre) *reinterpret_cast<uint2 *>(zpre + fb + ei) = make_uint2(f2bf2(zv[0], zv[1]), f2bf2(zv[2], zv[3]));
   } else if (EPI == DW_CONV_OUTPUT) {
+    const size_t ub = (size_t)o.b * cout * G.L;
+    const uint32_t L = (uint32_t)G.L;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int co = co0 + j;
+      const int co = co0 + j;
       if (co < cout) {
-        int64_t ui = ((int64_t)o.b * cout + co) * G.L + vi;
-        u_out[ui] = u[ui] + sb * (acc[j] + s_bias[co]);
+        const uint32_t ui = (uint32_t)co * L + vi;
+        u_out[ub + ui] = u[ub + ui] + sb * (acc[j] + s_bias[co]);
       }
     }
   } else {  // DW_CONV_DGRAD: gradient through the previous layer's silu
-    uint2 zg = *reinterpret_cast<const uint2 *>(zgate + gv * COUTP + co0);
-    float zf[4] = {bf2f((uint16_t)(zg.x & 0xffff)), bf2f((uint16_t)(zg.x >> 16)), bf2f((uint16_t)(zg.y & 0xffff)),
-                   bf2f((uint16_t)(zg.y >> 16))};
-    uint16_t ob[4];
+    const uint2 zg = *reinterpret_cast<const uint2 *>(zgate + fb + ei);
+    const float zf[4] = {bf2f((uint16_t)(zg.x & 0xffff)), bf2f((uint16_t)(zg.x >> 16)), bf2f((uint16_t)(zg.y & 0xffff)),
+                         bf2f((uint16_t)(zg.y >> 16))};
+    float ob[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) ob[j] = f2bf(acc[j] * silu_grad(zf[j]));
-    *reinterpret_cast<uint2 *>(y + gv * COUTP + co0) =
-        make_uint2(ob[0] | ((uint32_t)ob[1] << 16), ob[2] | ((uint32_t)ob[3] << 16));
+    for (int j = 0; j < 4; ++j) ob[j] = acc[j] * silu_grad(zf[j]);
+    *reinterpret_cast<uint2 *>(y + fb + ei) = make_uint2(f2bf2(ob[0], ob[1]), f2bf2(ob[2], ob[3]));
   }
 }
 
@@ -200,12 +215,32 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
 #pragma unroll
     for (int tap = 0; tap < 27; ++tap)
       wf[tap] = *reinterpret_cast<const bf16x8 *>(wk + ((tap * COUTP + mt * 16 + r16) * 32 + g * 8));
+    // the next tile's patch is copied while this tile's epilogue runs
+    if ((int)blockIdx.x < T.n) stage_patch<CINP>(G, x, fwd_tile(T, blockIdx.x), s_in);
     for (int t = blockIdx.x; t < T.n; t += gridDim.x) {
       const TileOrigin o = fwd_tile(T, t);
-      __syncthreads();  // the previous tile's reads of s_in are done
-      stage_patch<CINP>(G, x, o, s_in);
       __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies have landed
       __syncthreads();
+      // rows of this wave: voxel of row (yo, zo) = v00 + yo nx + zo nx ny
+      const int gx = o.x0 + r16;
+      const uint32_t sy = (uint32_t)G.nx, sz = (uint32_t)G.nx * (uint32_t)G.ny;
+      const uint32_t v00 = (uint32_t)gx + sy * (uint32_t)o.y0 + sz * (uint32_t)(o.z0 + zb);
+      // output layer: the input field's values at this wave's outputs are
+      // requested now and arrive during the MFMAs
+      float uin[RZ][FY][3];
+      if constexpr (EPI == DW_CONV_OUTPUT) {
+        const size_t ub = (size_t)o.b * cout * G.L;
+        const uint32_t L = (uint32_t)G.L;
+#pragma unroll
+        for (int zo = 0; zo < RZ; ++zo)
+#pragma unroll
+          for (int yo = 0; yo < FY; ++yo) {
+            const bool live = g == 0 && gx < G.nx && o.y0 + yo < G.ny && o.z0 + zb + zo < G.nz;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              uin[zo][yo][j] = (live && j < cout) ? u[ub + (uint32_t)j * L + v00 + yo * sy + zo * sz] : 0.f;
+          }
+      }
       floatx4 acc[RZ][FY];
 #pragma unroll
       for (int zo = 0; zo < RZ; ++zo)
@@ -222,9 +257,15 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
       for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
         for (int zi = 0; zi < RZ + 2; ++zi) {
+          // the row's six fragments are read together, so their LDS latency
+          // overlaps instead of stalling the matrix core per fragment
+          bf16x8 bfr[QY];
+#pragma unroll
+          for (int yi = 0; yi < QY; ++yi)
+            bfr[yi] = *reinterpret_cast<const bf16x8 *>(s_in + base[dx] + QX * (yi + QY * zi) * 32);
+          __builtin_amdgcn_sched_barrier(0);  // keep the six reads ahead of the MFMAs
 #pragma unroll
           for (int yi = 0; yi < QY; ++yi) {
-            bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(s_in + base[dx] + QX * (yi + QY * zi) * 32);
 #pragma unroll
             for (int dz = 0; dz < 3; ++dz) {
               const int zo = zi - dz;
@@ -233,20 +274,37 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
               for (int dy = 0; dy < 3; ++dy) {
                 const int yo = yi - dy;
                 if (yo < 0 || yo >= FY) continue;
-                acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[9 * dz + 3 * dy + dx], bfr, acc[zo][yo],
-                                                                      0, 0, 0);
+                acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[9 * dz + 3 * dy + dx], bfr[yi],
+                                                                      acc[zo][yo], 0, 0, 0);
               }
             }
           }
         }
       }
+      __syncthreads();  // every wave is done reading s_in
+      const int tn = t + (int)gridDim.x;
+      if (tn < T.n) stage_patch<CINP>(G, x, fwd_tile(T, tn), s_in);
       const float sb = EPI == DW_CONV_OUTPUT ? scale[o.b] : 0.f;
 #pragma unroll
       for (int zo = 0; zo < RZ; ++zo)
 #pragma unroll
-        for (int yo = 0; yo < FY; ++yo)
-          conv_epilogue<COUTP, EPI>(G, o, o.y0 + yo, o.z0 + zb + zo, r16, mt * 16 + 4 * g, acc[zo][yo], s_bias,
-                                    cout, y, zpre, zgate, u, sb, u_out);
+        for (int yo = 0; yo < FY; ++yo) {
+          const bool live = gx < G.nx && o.y0 + yo < G.ny && o.z0 + zb + zo < G.nz;
+          if constexpr (EPI == DW_CONV_OUTPUT) {
+            // u_{t+k} = u_t + s (acc + bias), channels 0 .. cout-1 held by the lanes of group 0
+            if (live && g == 0) {
+              const size_t ub = (size_t)o.b * cout * G.L;
+              const uint32_t L = (uint32_t)G.L;
+#pragma unroll
+              for (int j = 0; j < 3; ++j)
+                if (j < cout)
+                  u_out[ub + (uint32_t)j * L + v00 + yo * sy + zo * sz] = uin[zo][yo][j] + sb * (acc[zo][yo][j] + s_bias[j]);
+            }
+          } else {
+            conv_epilogue<COUTP, EPI>(G, o, live, v00 + yo * sy + zo * sz, mt * 16 + 4 * g, acc[zo][yo], s_bias, cout,
+                                      y, zpre, zgate, u, sb, u_out);
+          }
+        }
     }
   } else {
     // 8-channel input: chunk c covers taps 4c .. 4c + 3 (lane group g: tap 4c + g)
@@ -288,13 +346,18 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
               acc[i][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[c][m], bfr, acc[i][m], 0, 0, 0);
           }
         }
+        const int gx = o.x0 + r16;
+        const uint32_t sy = (uint32_t)G.nx, sz = (uint32_t)G.nx * (uint32_t)G.ny;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           const int row = wid * 8 + pr * 2 + i;
+          const int gy = o.y0 + row % FY, gz = o.z0 + row / FY;
+          const bool live = gx < G.nx && gy < G.ny && gz < G.nz;
+          const uint32_t vi = (uint32_t)gx + sy * (uint32_t)gy + sz * (uint32_t)gz;
 #pragma unroll
           for (int m = 0; m < MT; ++m)
-            conv_epilogue<COUTP, EPI>(G, o, o.y0 + row % FY, o.z0 + row / FY, r16, m * 16 + 4 * g, acc[i][m], s_bias,
-                                      cout, y, zpre, zgate, u, sb, u_out);
+            conv_epilogue<COUTP, EPI>(G, o, live, vi, m * 16 + 4 * g, acc[i][m], s_bias, cout, y, zpre, zgate, u, sb,
+                                      u_out);
         }
       }
     }
