@@ -9,12 +9,13 @@ over the substeps) and exposes them to torch as one autograd Function.
 
 Memory: the forward keeps the particle state every `ckpt` substeps only.  The
 backward walks the segments in reverse; for each it re-runs the segment from
-its checkpoint, keeping the per-substep particle states, then for every
-substep (last first) recomputes that substep's grid (sort, P2G, grid update)
-and applies the adjoints in reverse order: G2P adjoint (sorted scatter into
-the grid adjoint), grid-update adjoint, wind transpose into W_bar, P2G adjoint
-(per-particle gather, also giving E_bar).  Every step runs in the library's
-HIP kernels; torch provides device memory, zero-fills and the final loss.
+its checkpoint, keeping every substep's particle state, sort workspace and
+grid (m, mv, v: about 28 B per grid node and 20 B per particle per substep),
+then for every substep (last first) applies the adjoints in reverse order:
+G2P adjoint (sorted scatter into the grid adjoint), grid-update adjoint, wind
+transpose into W_bar, P2G adjoint (per-particle gather, also giving E_bar).
+Every step runs in the library's HIP kernels; torch provides device memory,
+zero-fills (one per buffer group) and the final loss.
 """
 from __future__ import annotations
 
@@ -37,14 +38,24 @@ class RolloutPlan:
         self.nw, self.box_lo, self.box_hi, self.K = tuple(nw), tuple(box_lo), tuple(box_hi), K
         self.n_sub, self.ckpt = n_sub, ckpt
         f = dict(dtype=torch.float32, device=device)
+        self.device = device
         self.ws = api.alloc_workspace(self.grid, n, device)
         self.gm = torch.zeros(self.N, **f)
         self.gmv = torch.zeros(3, self.N, **f)
         self.gv = torch.zeros(3, self.N, **f)
-        self.gvb = torch.zeros(3, self.N, **f)
-        self.gmb = torch.zeros(self.N, **f)
-        self.gmvb = torch.zeros(3, self.N, **f)
-        self.accb = torch.zeros(3, self.N, **f)
+        # grid adjoints in one buffer, cleared with one fill per substep
+        self._gbar = torch.zeros(10, self.N, **f)
+        self.gvb, self.gmb, self.gmvb, self.accb = (self._gbar[0:3], self._gbar[3], self._gbar[4:7],
+                                                    self._gbar[7:10])
+        self._seg = None  # per-substep workspaces and grids of a segment, made on first backward
+
+    def segment_buffers(self):
+        """Sort workspaces and grids (m, mv, v) for the substeps of one segment."""
+        if self._seg is None:
+            f = dict(dtype=torch.float32, device=self.device)
+            self._seg = [(api.alloc_workspace(self.grid, self.n, self.device), torch.empty(self.N, **f),
+                          torch.empty(3, self.N, **f), torch.empty(3, self.N, **f)) for _ in range(self.ckpt)]
+        return self._seg
 
     def slot(self, s: int) -> int:
         return s * self.K // self.n_sub
@@ -56,32 +67,37 @@ class RolloutPlan:
         return api.wind_force_grid(W[self.slot(s)], self.nw, self.box_lo, self.box_hi)
 
     # --------------------------------------------------------------- forward
-    def substep(self, p: api.ParticleArrays, W, s: int, out=None):
-        """One substep; in place unless `out` = (x, v, C, H) buffers are given."""
-        api.mpm_sort(self.grid, self.prm, p.x, self.ws)
-        api.mpm_p2g(self.grid, self.prm, p, self.gm, self.gmv, self.ws)
-        api.mpm_grid_update(self.grid, self.prm, self.gm, self.gmv, self.wind(W, s), self.pin, self.gv, self.ws)
+    def substep(self, p: api.ParticleArrays, W, s: int, out=None, bufs=None, g2p: bool = True):
+        """One substep; in place unless `out` = (x, v, C, H) buffers are given.
+        `bufs` = (workspace, m, mv, v) keeps this substep's sort and grid."""
+        ws, gm, gmv, gv = bufs if bufs is not None else (self.ws, self.gm, self.gmv, self.gv)
+        api.mpm_sort(self.grid, self.prm, p.x, ws)
+        api.mpm_p2g(self.grid, self.prm, p, gm, gmv, ws)
+        api.mpm_grid_update(self.grid, self.prm, gm, gmv, self.wind(W, s), self.pin, gv, ws)
+        if not g2p:
+            return None
         if out is None:
-            api.mpm_g2p(self.grid, self.prm, self.gv, p, p.x, p.v, p.C, p.F)
+            api.mpm_g2p(self.grid, self.prm, gv, p, p.x, p.v, p.C, p.F)
             return p
-        api.mpm_g2p(self.grid, self.prm, self.gv, p, *out)
+        api.mpm_g2p(self.grid, self.prm, gv, p, *out)
         return self.particles(*out, p.E)
 
     # -------------------------------------------------------------- backward
-    def substep_adjoint(self, p: api.ParticleArrays, W, s: int, bar_out, bar_in, W_bar, E_bar):
+    def substep_adjoint(self, p: api.ParticleArrays, W, s: int, bar_out, bar_in, W_bar, E_bar, bufs=None):
         """Adjoint of substep s at input state p: adds into bar_in = (x, v, C, H)
-        adjoints of the inputs, W_bar and E_bar, given bar_out of the outputs."""
+        adjoints of the inputs, W_bar and E_bar, given bar_out of the outputs.
+        `bufs` = the substep's kept (workspace, m, mv, v); without it the
+        substep's grid is recomputed first."""
         g, prm = self.grid, self.prm
         wind = self.wind(W, s)
-        api.mpm_sort(g, prm, p.x, self.ws)
-        api.mpm_p2g(g, prm, p, self.gm, self.gmv, self.ws)
-        api.mpm_grid_update(g, prm, self.gm, self.gmv, wind, self.pin, self.gv, self.ws)
-        for t in (self.gvb, self.gmb, self.gmvb, self.accb):
-            t.zero_()
+        if bufs is None:
+            self.substep(p, W, s, g2p=False)
+            bufs = (self.ws, self.gm, self.gmv, self.gv)
+        ws, gm, gmv, gv = bufs
+        self._gbar.zero_()
         xb, vb, Cb, Hb = bar_in
-        api.mpm_g2p_adj(g, prm, self.gv, p, *bar_out, x_bar=xb, F_bar=Hb, grid_v_bar=self.gvb, ws=self.ws)
-        api.mpm_grid_update_adj(g, prm, self.gm, self.gmv, wind, self.pin, self.gvb, self.gmb, self.gmvb,
-                                self.accb, self.ws)
+        api.mpm_g2p_adj(g, prm, gv, p, *bar_out, x_bar=xb, F_bar=Hb, grid_v_bar=self.gvb, ws=ws)
+        api.mpm_grid_update_adj(g, prm, gm, gmv, wind, self.pin, self.gvb, self.gmb, self.gmvb, self.accb, ws)
         api.wind_to_grid_adj(g, wind, self.accb, W_bar[self.slot(s)])
         api.mpm_p2g_adj(g, prm, p, self.gmb, self.gmvb, xb, vb, Cb, Hb, E_bar)
 
@@ -110,20 +126,36 @@ class _RolloutFn(torch.autograd.Function):
                for b, t in zip((xb, vb, Cb, Hb), ctx.ckpts[0])]
         W_bar = torch.zeros_like(W)
         E_bar = torch.zeros_like(E)
+        seg_bufs = plan.segment_buffers()
+        # particle-state adjoints: two groups of (x, v, C, H) views, one fill each
+        shapes = [t.shape for t in ctx.ckpts[0]]
+        sizes = [t.numel() for t in ctx.ckpts[0]]
+        pair = torch.empty(2, sum(sizes), dtype=torch.float32, device=W.device)
+        groups = [list(t.view(sh) for t, sh in zip(torch.split(pair[k], sizes), shapes)) for k in range(2)]
+        cur = 0
+        for dst, b in zip(groups[cur], bar):
+            dst.copy_(b)
+        bar = groups[cur]
         for seg in reversed(range(len(ctx.ckpts))):
             s0 = seg * plan.ckpt
             s1 = min(s0 + plan.ckpt, plan.n_sub)
+            # re-run the segment, keeping each substep's state, sort and grid
             states = [[t.clone() for t in ctx.ckpts[seg]]]
-            for s in range(s0, s1 - 1):
-                nxt = [torch.empty_like(t) for t in states[-1]]
-                plan.substep(plan.particles(*states[-1], E), W, s, out=nxt)
-                states.append(nxt)
+            for s in range(s0, s1):
+                last = s == s1 - 1
+                nxt = None if last else [torch.empty_like(t) for t in states[-1]]
+                plan.substep(plan.particles(*states[-1], E), W, s, out=nxt, bufs=seg_bufs[s - s0], g2p=not last)
+                if not last:
+                    states.append(nxt)
             for s in reversed(range(s0, s1)):
                 st = states[s - s0]
-                bar_in = [torch.zeros_like(t) for t in st]
-                plan.substep_adjoint(plan.particles(*st, E), W, s, bar, bar_in, W_bar, E_bar)
-                bar = bar_in
-        return (None, W_bar, E_bar, *bar)
+                nxt_group = groups[1 - cur]
+                pair[1 - cur].zero_()
+                plan.substep_adjoint(plan.particles(*st, E), W, s, bar, nxt_group, W_bar, E_bar,
+                                     bufs=seg_bufs[s - s0])
+                bar = nxt_group
+                cur = 1 - cur
+        return (None, W_bar, E_bar, *[b.clone() for b in bar])
 
 
 def rollout(plan: RolloutPlan, W, E, x0, v0, C0, H0):
