@@ -351,6 +351,7 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
   __shared__ int s_cnt[64], s_off[64], s_cur[64];
   __shared__ int s_udesc[SC_MAX_UNITS];
   __shared__ int s_nunits;
+  __shared__ float s_gv[3][SC_NODES];  // grid velocities of the item's 6^3 node region
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const ScLane L = sc_lane(lane);
   float *s_node_flat = &s_node[0][0][0];
@@ -364,6 +365,21 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     if (tid < 64) s_cnt[tid] = 0;
     for (int q = tid; q < SC_WAVES * SC_NODES; q += SC_THREADS)
       reinterpret_cast<float4 *>(s_node_flat)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // every stencil of the item lies in the tile's 6^3 node region: stage its
+    // grid velocities once, for both gathers below
+    if (tid < SC_NODES) {
+      const int gx = 4 * tx + tid % SC_L, gy = 4 * ty + (tid / SC_L) % SC_L, gz = 4 * tz + tid / (SC_L * SC_L);
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      if (gx < g.nx && gy < g.ny && gz < g.nz) {
+        const int64_t node = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+        a0 = gv[node];
+        a1 = gv[N + node];
+        a2 = gv[2 * N + node];
+      }
+      s_gv[0][tid] = a0;
+      s_gv[1][tid] = a1;
+      s_gv[2][tid] = a2;
+    }
     __syncthreads();
     // particle -> cell in the tile
     const bool has = tid < nb;
@@ -401,11 +417,14 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll 1
       for (int r9 = 0; r9 < 9; ++r9) {
         const int oy = r9 % 3, oz = r9 / 3;
-        const int64_t row = bx + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+        const int li = (bx - 4 * tx) + SC_L * ((by - 4 * ty + oy) + SC_L * (bz - 4 * tz + oz));
         AdjRow r0, r1, r2;
-        __builtin_memcpy(&r0, gv + row, sizeof(AdjRow));
-        __builtin_memcpy(&r1, gv + N + row, sizeof(AdjRow));
-        __builtin_memcpy(&r2, gv + 2 * N + row, sizeof(AdjRow));
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+          r0.v[ox] = s_gv[0][li + ox];
+          r1.v[ox] = s_gv[1][li + ox];
+          r2.v[ox] = s_gv[2][li + ox];
+        }
 #pragma unroll
         for (int ox = 0; ox < 3; ++ox) {
           const float wt = w[0][ox] * w[1][oy] * w[2][oz];
@@ -452,11 +471,14 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll 1
       for (int r9 = 0; r9 < 9; ++r9) {
         const int oy = r9 % 3, oz = r9 / 3;
-        const int64_t row = bx + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+        const int li = (bx - 4 * tx) + SC_L * ((by - 4 * ty + oy) + SC_L * (bz - 4 * tz + oz));
         AdjRow r0, r1, r2;
-        __builtin_memcpy(&r0, gv + row, sizeof(AdjRow));
-        __builtin_memcpy(&r1, gv + N + row, sizeof(AdjRow));
-        __builtin_memcpy(&r2, gv + 2 * N + row, sizeof(AdjRow));
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+          r0.v[ox] = s_gv[0][li + ox];
+          r1.v[ox] = s_gv[1][li + ox];
+          r2.v[ox] = s_gv[2][li + ox];
+        }
 #pragma unroll
         for (int ox = 0; ox < 3; ++ox) {
           const float wt = w[0][ox] * w[1][oy] * w[2][oz];
