@@ -88,44 +88,68 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-// block-wide exclusive scan of a 1024-thread block; returns the block total in *total
-__device__ __forceinline__ int block_excl_scan(int v, int *lds, int *total) {
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int inc = wave_incl_scan(v);
-  if (lane == 63) lds[wid] = inc;
+// Block-wide exclusive scans of the four tile rows at once (1024-thread
+// block, two barriers in all): ex[r] = sum of v[r] over the threads before
+// this one, tot[r] = the block's total.
+constexpr int SCAN_WAVES = SCAN_BLOCK / 64;
+
+__device__ __forceinline__ void block_excl_scan4(const int v[4], int ex[4], int tot[4],
+                                                 int (*lds)[4] /* [2 * SCAN_WAVES + 1][4] */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int inc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) inc[r] = wave_incl_scan(v[r]);
+  if (lane == 63)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lds[wid][r] = inc[r];
   __syncthreads();
   if (wid == 0) {
-    int s = lane < (int)(blockDim.x >> 6) ? lds[lane] : 0;
-    int si = wave_incl_scan(s);
-    if (lane < (int)(blockDim.x >> 6)) lds[32 + lane] = si - s;
-    if (lane == (int)(blockDim.x >> 6) - 1) lds[31] = si;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = lane < SCAN_WAVES ? lds[lane][r] : 0;
+      const int ti = wave_incl_scan(t);
+      if (lane < SCAN_WAVES) lds[SCAN_WAVES + lane][r] = ti - t;
+      if (lane == SCAN_WAVES - 1) lds[2 * SCAN_WAVES][r] = ti;
+    }
   }
   __syncthreads();
-  int res = inc - v + lds[32 + wid];
-  *total = lds[31];
-  __syncthreads();
-  return res;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    ex[r] = inc[r] - v[r] + lds[SCAN_WAVES + wid][r];
+    tot[r] = lds[2 * SCAN_WAVES][r];
+  }
 }
 
+// the four rows of tile i: particle count, node-tile flag, occupied, work items
+__device__ __forceinline__ void tile_rows(const int32_t *__restrict__ count, const int32_t *__restrict__ flag,
+                                          int64_t T, int64_t i, int v[4]) {
+  const int c = i < T ? count[i] : 0;
+  v[0] = c;
+  v[1] = i < T ? (flag[i] != 0) : 0;
+  v[2] = c > 0;
+  v[3] = (c + WORK_CHUNK - 1) / WORK_CHUNK;
+}
+
+// per block: the sums of the four rows (one block-wide reduction)
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *__restrict__ count,
                                                             const int32_t *__restrict__ flag, int64_t T,
                                                             int32_t *__restrict__ block_sums, int64_t NB) {
-  __shared__ int lds[128];
-  int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
-  int c = i < T ? count[i] : 0;
-  int f = i < T ? (flag[i] != 0) : 0;
-  int nz = c > 0;
-  int ch = (c + WORK_CHUNK - 1) / WORK_CHUNK;
-  int tc, tf, tn, th;
-  block_excl_scan(c, lds, &tc);
-  block_excl_scan(f, lds, &tf);
-  block_excl_scan(nz, lds, &tn);
-  block_excl_scan(ch, lds, &th);
-  if (threadIdx.x == 0) {
-    block_sums[blockIdx.x] = tc;
-    block_sums[NB + blockIdx.x] = tf;
-    block_sums[2 * NB + blockIdx.x] = tn;
-    block_sums[3 * NB + blockIdx.x] = th;
+  __shared__ int s_red[SCAN_WAVES][4];
+  const int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+  int v[4];
+  tile_rows(count, flag, T, i, v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[r] += __shfl_xor(v[r], o, 64);
+    if (lane == 0) s_red[wid][r] = v[r];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    int t = 0;
+    for (int w = 0; w < SCAN_WAVES; ++w) t += s_red[w][threadIdx.x];
+    block_sums[threadIdx.x * NB + blockIdx.x] = t;
   }
 }
 
@@ -139,8 +163,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
     const int32_t *__restrict__ block_sums, int64_t NB, int32_t *__restrict__ tile_start,
     int32_t *__restrict__ cell_tiles, int32_t *__restrict__ node_tiles, int32_t *__restrict__ item_tile,
     int32_t *__restrict__ item_begin, int32_t *__restrict__ item_first, int32_t *__restrict__ totals /* [4] */) {
-  __shared__ int lds[128];
-  __shared__ int s_red[SCAN_BLOCK / 64][8];
+  __shared__ int lds[2 * SCAN_WAVES + 1][4];
+  __shared__ int s_red[SCAN_WAVES][8];
   __shared__ int s_sum[8];
   // per row: the sum over the blocks before this one (0..3) and over all (4..7),
   // one block-wide reduction of the eight values
@@ -160,32 +184,25 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(
     for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
     if (lane == 0) s_red[wid][r] = acc[r];
   }
-  __syncthreads();
+  // the block's own rows are scanned while the reduction above settles
+  const int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+  int v[4], ex[4], tot[4];
+  tile_rows(count, flag, T, i, v);
+  block_excl_scan4(v, ex, tot, lds);  // its barriers also publish s_red
   if (threadIdx.x < 8) {
     int t = 0;
-    for (int w = 0; w < SCAN_BLOCK / 64; ++w) t += s_red[w][threadIdx.x];
+    for (int w = 0; w < SCAN_WAVES; ++w) t += s_red[w][threadIdx.x];
     s_sum[threadIdx.x] = t;
   }
   __syncthreads();
-  int pre[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) pre[r] = s_sum[r];
   if (blockIdx.x == 0 && threadIdx.x < 4) totals[threadIdx.x] = s_sum[4 + threadIdx.x];
-  int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
-  int c = i < T ? count[i] : 0;
-  int f = i < T ? (flag[i] != 0) : 0;
-  int nz = c > 0;
-  int ch = (c + WORK_CHUNK - 1) / WORK_CHUNK;
-  int tc, tf, tn, th;
-  int ec = block_excl_scan(c, lds, &tc) + pre[0];
-  int ef = block_excl_scan(f, lds, &tf) + pre[1];
-  int en = block_excl_scan(nz, lds, &tn) + pre[2];
-  int eh = block_excl_scan(ch, lds, &th) + pre[3];
   if (i < T) {
+    const int ec = ex[0] + s_sum[0], ef = ex[1] + s_sum[1], en = ex[2] + s_sum[2], eh = ex[3] + s_sum[3];
+    const int c = v[0], ch = v[3];
     tile_start[i] = ec;
     item_first[i] = eh;
-    if (nz) cell_tiles[en] = (int)i;
-    if (f) node_tiles[ef] = (int)i;
+    if (v[2]) cell_tiles[en] = (int)i;
+    if (v[1]) node_tiles[ef] = (int)i;
     for (int q = 0; q < ch; ++q) {
       item_tile[eh + q] = (int)i;
       item_begin[eh + q] = ec + q * WORK_CHUNK;
