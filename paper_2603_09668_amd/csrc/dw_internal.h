@@ -84,9 +84,17 @@ int bind_workspace(const dw_grid *g, int n, const void *ws, size_t ws_bytes, Wor
 
 // fill kernels (a kernel rather than hipMemsetAsync, so the calls stay
 // capturable in HIP graphs); static: every translation unit launches its own
+// k_fill_i32 writes 16 bytes per store over the 16-byte aligned body of the
+// range and single words at its ends (launch it for count / 4 + 1 threads)
 static __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = value;
+  const int64_t head = min((int64_t)(((16 - ((uintptr_t)p & 15)) & 15) / 4), count);
+  const int64_t body = (count - head) / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  int4 *q = reinterpret_cast<int4 *>(p + head);
+  for (int64_t i = t; i < body; i += stride) q[i] = make_int4(value, value, value, value);
+  const int64_t tail0 = head + body * 4;
+  if (t < head) p[t] = value;
+  if (t < count - tail0) p[tail0 + t] = value;
 }
 
 static __global__ void k_fill_f32(float *p, int64_t count, float value) {

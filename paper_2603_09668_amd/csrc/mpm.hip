@@ -760,7 +760,7 @@ int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, cons
   int64_t T = W.n_tiles, NB = W.n_scan_blocks;
   // header + tile_count + node_flag are contiguous: clear them
   int64_t clear_words = (int64_t)((char *)W.tile_start - (char *)W.status) / 4;
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_blocks(clear_words, 256)), dim3(256), 0, s, W.status, clear_words, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_blocks(clear_words / 4 + 4, 256)), dim3(256), 0, s, W.status, clear_words, 0);
   if (n > 0)
     hipLaunchKernelGGL(k_sort_keys, dim3(grid_blocks(n, 256)), dim3(256), 0, s, g, x, n, W.key, W.rank,
                        W.tile_count, W.node_flag, W.status);

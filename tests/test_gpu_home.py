@@ -71,6 +71,12 @@ CASES = {
     "channel": dict(dims=(17, 9, 11), bc=(0, 0, 1, 1, 0, 0), force=(1e-5, 0.0, 0.0), gust=(0.0, 1.0, 0, 0, 0),
                     tau=0.55),
     "ragged_row": dict(dims=(130, 3, 2), bc=None, force=(0.0, 0.0, 0.0), gust=(0.0, 1.0, 0, 0, 0), tau=1.2),
+    # solids on the faces of a periodic box: wrapped sources land on solid nodes
+    "periodic_face_solids": dict(dims=(14, 9, 8), bc=(0,) * 6, force=(2e-5, 0.0, -1e-5), gust=(0.0, 1.0, 0, 0, 0),
+                                 tau=0.7, solid=(slice(0, 2), slice(7, 9), slice(12, 14))),
+    # rows wider than a workgroup with solids in the second one, gusty inlet
+    "wide_tunnel": dict(dims=(200, 6, 5), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 90.0, 1.0, 0.0, 0.4), tau=0.6,
+                        solid=(slice(1, 3), slice(2, 4), slice(140, 180))),
 }
 
 
@@ -81,7 +87,7 @@ def test_home_step_parity(case):
     say(f"lbm_home_step {case} {c['dims']}")
     md, rho, u, S = _pack(*_random_state(c["dims"], 1))
     solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
-    solid[nz // 3:nz // 3 + 2, ny // 3:ny // 3 + 2, nx // 2:nx // 2 + 5] = True
+    solid[c.get("solid", (slice(nz // 3, nz // 3 + 2), slice(ny // 3, ny // 3 + 2), slice(nx // 2, nx // 2 + 5)))] = True
     t = 17
     op, ap = _params(tau=c["tau"], force=c["force"], bc=c["bc"], gust=c["gust"], t=t)
     lat = olbm.Lattice(nx, ny, nz)
