@@ -122,11 +122,12 @@ def _home_leg(scene, sim, steps):
     ms = _graph_ms(lambda: [step() for _ in range(R)]) / R
     bytes_node = 2 * 4 * api.HOME_MOMENTS + 1 + 12      # moments in and out, solid, u out
     ach = bytes_node * L / (ms * 1e-3) / 1e9
-    # the reverse step (a push through the expansion, float atomics)
+    # the reverse step (per-population adjoints, then the transposed gather)
     mbar = torch.ones(api.HOME_MOMENTS, L, device="cuda")
     mib = torch.zeros_like(mbar)
-    adj_ms = _graph_ms(lambda: api.lbm_home_step_adj(sim.lat, prm, ma, sim.solid, mbar, None, mib))
-    del ma, mb, state, mbar, mib
+    work = torch.empty(19, L, device="cuda")
+    adj_ms = _graph_ms(lambda: api.lbm_home_step_adj(sim.lat, prm, ma, sim.solid, mbar, None, mib, work=work))
+    del ma, mb, state, mbar, mib, work
     hs = CoupledSim(scene, lbm_model="home")
     for _ in range(4):
         hs.step()

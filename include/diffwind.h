@@ -367,13 +367,20 @@ int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const fl
 int lbm_home_step(const dw_lattice *lat, const dw_lbm_params *params, const float *m_in, float *m_out,
                   const uint8_t *solid, float *rho_out, float *u_out, void *stream);
 
-/* Reverse of lbm_home_step (a push through the Hermite expansion): given
- * m_out_bar [10][L] and u_out_bar [3][L] (the reported velocity's adjoint;
- * NULL = zero), ACCUMULATES m_in_bar [10][L].  Solid nodes pass nothing
- * back.  Float atomics: the last bits depend on the order of the pushes. */
+/* Reverse of lbm_home_step: given m_out_bar [10][L] and u_out_bar [3][L]
+ * (the reported velocity's adjoint; NULL = zero), ACCUMULATES m_in_bar
+ * [10][L].  Two passes: the first recomputes every node's pulled set and
+ * writes the adjoints of its 19 pulled populations to work [19][L] (device
+ * scratch of 76 bytes per node, owned by the caller, contents on return
+ * unspecified); the second gathers, for every node, the adjoints of the
+ * populations rebuilt from its moments (the streaming transposed under the
+ * same boundary rules, bounced pulls included) and takes them back through
+ * the Hermite expansion.  Solid nodes pass nothing back.  No atomics: the
+ * result does not depend on scheduling.  m_in_bar must alias neither m_in
+ * nor m_out_bar; work aliases no other argument. */
 int lbm_home_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *m_in,
                       const uint8_t *solid, const float *m_out_bar, const float *u_out_bar, float *m_in_bar,
-                      void *stream);
+                      float *work, void *stream);
 
 /* Equilibrium moments (rho, u, S = u u) into m [10][L]: rho [L] (NULL = 1)
  * and u [3][L] (NULL = the uniform params->u_in). */

@@ -109,7 +109,7 @@ def lib():
         "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_home_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
-        "lbm_home_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
+        "lbm_home_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P, P], c_int),
         "lbm_home_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
         "gaussian_covariance": ([c_int, P, P, P, P], c_int),
@@ -458,8 +458,12 @@ def lbm_home_step(lat: Lattice, params: LBMParams, m_in, m_out, solid=None, rho_
            "lbm_home_step")
 
 
-def lbm_home_step_adj(lat: Lattice, params: LBMParams, m_in, solid, m_out_bar, u_out_bar, m_in_bar):
+def lbm_home_step_adj(lat: Lattice, params: LBMParams, m_in, solid, m_out_bar, u_out_bar, m_in_bar, work=None):
+    """`work`: float32 scratch of (19, L) on the device (allocated here when None)."""
     L = lat.nx * lat.ny * lat.nz
+    if work is None:
+        work = torch.empty(19, L, dtype=torch.float32, device=m_in.device)
+    _shape(work, (19, L), "work")
     for t, shape, name in ((m_in, (HOME_MOMENTS, L), "m_in"), (m_out_bar, (HOME_MOMENTS, L), "m_out_bar"),
                            (m_in_bar, (HOME_MOMENTS, L), "m_in_bar")):
         _shape(t, shape, name)
@@ -469,7 +473,8 @@ def lbm_home_step_adj(lat: Lattice, params: LBMParams, m_in, solid, m_out_bar, u
         _shape(solid, (L,), "solid")
     _check(lib().lbm_home_step_adj(ctypes.byref(lat), ctypes.byref(params), _ptr(m_in, name="m_in"),
                                    _ptr(solid, torch.uint8, "solid"), _ptr(m_out_bar, name="m_out_bar"),
-                                   _ptr(u_out_bar, name="u_out_bar"), _ptr(m_in_bar, name="m_in_bar"), _stream()),
+                                   _ptr(u_out_bar, name="u_out_bar"), _ptr(m_in_bar, name="m_in_bar"),
+                                   _ptr(work, name="work"), _stream()),
            "lbm_home_step_adj")
 
 

@@ -417,16 +417,6 @@ struct Mom {
   float drho, u[3], S[6];  // S: xx yy zz xy xz yz
 };
 
-__device__ __forceinline__ Mom load_mom(const float *__restrict__ m, int64_t L, int64_t node) {
-  Mom M;
-  M.drho = m[node];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) M.u[a] = m[(1 + a) * L + node];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) M.S[s] = m[(4 + s) * L + node];
-  return M;
-}
-
 // storage index of S_ab
 __host__ __device__ constexpr int sidx(int a, int b) {
   return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
@@ -546,39 +536,6 @@ __device__ __forceinline__ Mom inlet_mom(const LbmDev &P, int j, int k) {
   M.S[4] = M.u[0] * M.u[2];
   M.S[5] = M.u[1] * M.u[2];
   return M;
-}
-
-template <int SOL, int Q>
-__device__ __forceinline__ void home_pull(const LbmDev &P, const float *__restrict__ min,
-                                          const uint8_t *__restrict__ solid, const uint8_t (*s_sol)[SOL_W],
-                                          int i, int j, int k, int x0, int64_t node, const Mom &own, MomAcc &A) {
-  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
-  const int si = i - c[0], sj = j - c[1], sk = k - c[2];
-  const bool inside = (unsigned)si < (unsigned)P.nx && (unsigned)sj < (unsigned)P.ny && (unsigned)sk < (unsigned)P.nz;
-  float g;
-  if (inside) {
-    const int64_t src = node - (c[0] + c[1] * (int64_t)P.nx + c[2] * (int64_t)P.nx * P.ny);
-    const bool bb = SOL == 1 ? s_sol[(1 - c[1]) + 3 * (1 - c[2])][si - x0 + 4] != 0
-                             : (SOL == 2 && solid[src] != 0);
-    if (bb) g = home_pop<LOPP[Q]>(own);
-    else g = home_pop<Q>(load_mom(min, P.L, src));
-  } else {
-    int64_t src = node;
-    int ssj = 0, ssk = 0;
-    const int kind = pull_source(P, solid, i, j, k, Q, src, ssj, ssk);
-    if (kind == SRC_NORMAL) g = home_pop<Q>(load_mom(min, P.L, src));
-    else if (kind == SRC_BOUNCE) g = home_pop<LOPP[Q]>(own);
-    else g = home_pop<Q>(inlet_mom(P, ssj, ssk));
-  }
-  acc_pop<Q>(A, g);
-}
-
-template <int SOL, int... Qs>
-__device__ __forceinline__ void home_pull_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
-                                              const float *__restrict__ min, const uint8_t *__restrict__ solid,
-                                              const uint8_t (*s_sol)[SOL_W], int i, int j, int k, int x0,
-                                              int64_t node, const Mom &own, MomAcc &A) {
-  (home_pull<SOL, Qs>(P, min, solid, s_sol, i, j, k, x0, node, own, A), ...);
 }
 
 // Forward pull of the moment-encoded step with the row-uniform source rules
@@ -770,71 +727,27 @@ __global__ __launch_bounds__(256) void k_home_equilibrium(LbmDev P, const float 
 }
 
 // ------------------------------------------------------- HOME-LBM reverse
-// Reverse of k_home_step: recompute the pulled set's moments, take the
-// adjoint of the stored moments (and of the reported u*) back through the
-// moment collision to the pulled populations, and push each population's
-// adjoint through the Hermite expansion into the moments it was rebuilt from
-// (atomics: boundary rules can make two destinations share one source).
-__device__ __forceinline__ void mom_atomic_add(float *__restrict__ mb, int64_t L, int64_t node, const Mom &M) {
-  atomicAdd(&mb[node], M.drho);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) atomicAdd(&mb[(1 + a) * L + node], M.u[a]);
-#pragma unroll
-  for (int s = 0; s < 6; ++s) atomicAdd(&mb[(4 + s) * L + node], M.S[s]);
-}
+// Reverse of k_home_step in two passes, neither with atomics.
+//  1. k_home_adj_pull, per node: recompute the pulled set's moments, take
+//     the adjoints of the stored moments (and of the reported u*) back
+//     through the moment collision, and write the adjoint of each of the 19
+//     pulled populations to gbar [19][L] (zeros at a solid node: its stored
+//     rest state does not depend on the inputs).
+//  2. k_home_adj_gather, per node s: population p rebuilt from the moments
+//     of s was pulled either by the node at s + c_p (the transposed
+//     streaming, same boundary rules) or, where the pull of opp(p) at s
+//     bounced back, by s itself.  T_p gathers gbar_p of the first or
+//     gbar_opp(p) of s, and sum_p T_p df_p/dM(s) is added into m_in_bar.
+// Every node's m_in_bar is written by one thread, in a fixed order.
 
 struct PopBar {
   float drho, j[3], P[6];  // adjoints of the pulled set's moments
 };
 
-template <int Q>
-__device__ __forceinline__ void home_push(const LbmDev &P, const float *__restrict__ min,
-                                          const uint8_t *__restrict__ solid, int i, int j, int k, int64_t node,
-                                          const Mom &own, const PopBar &B, Mom &own_bar, float *__restrict__ mbar) {
-  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
-  // adjoint of the pulled population q
-  float gb = B.drho;
-  if constexpr (c[0] != 0) gb += c[0] * B.j[0];
-  if constexpr (c[1] != 0) gb += c[1] * B.j[1];
-  if constexpr (c[2] != 0) gb += c[2] * B.j[2];
-  gb += (c[0] * c[0] - 1.f / 3.f) * B.P[0] + (c[1] * c[1] - 1.f / 3.f) * B.P[1] + (c[2] * c[2] - 1.f / 3.f) * B.P[2];
-  if constexpr (c[0] * c[1] != 0) gb += (c[0] * c[1]) * B.P[3];
-  if constexpr (c[0] * c[2] != 0) gb += (c[0] * c[2]) * B.P[4];
-  if constexpr (c[1] * c[2] != 0) gb += (c[1] * c[2]) * B.P[5];
-  int64_t src = node;
-  int ssj = 0, ssk = 0;
-  const int kind = pull_source(P, solid, i, j, k, Q, src, ssj, ssk);
-  if (kind == SRC_NORMAL) {
-    Mom Mb{};
-    home_pop_adj<Q>(load_mom(min, P.L, src), gb, Mb);
-    mom_atomic_add(mbar, P.L, src, Mb);
-  } else if (kind == SRC_BOUNCE) {
-    home_pop_adj<LOPP[Q]>(own, gb, own_bar);
-  }
-}
-
-template <int... Qs>
-__device__ __forceinline__ void home_push_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
-                                              const float *__restrict__ min, const uint8_t *__restrict__ solid, int i,
-                                              int j, int k, int64_t node, const Mom &own, const PopBar &B,
-                                              Mom &own_bar, float *__restrict__ mbar) {
-  (home_push<Qs>(P, min, solid, i, j, k, node, own, B, own_bar, mbar), ...);
-}
-
-__global__ __launch_bounds__(LBM_BLOCK) void k_home_step_adj(LbmDev P, const float *__restrict__ min,
-                                                             const uint8_t *__restrict__ solid,
-                                                             const float *__restrict__ mout_bar,
-                                                             const float *__restrict__ ubar_out,
-                                                             float *__restrict__ mbar) {
-  const int i = blockIdx.x * LBM_BLOCK + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-  if (i >= P.nx) return;
-  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
-  if (solid && solid[node]) return;  // the stored rest state does not depend on the inputs
-  const Mom own = load_mom(min, P.L, node);
-  MomAcc A;
-  if (solid) home_pull_all<2>(std::make_integer_sequence<int, 19>{}, P, min, solid, nullptr, i, j, k, 0, node, own, A);
-  else home_pull_all<0>(std::make_integer_sequence<int, 19>{}, P, min, solid, nullptr, i, j, k, 0, node, own, A);
-  // forward moments and collision quantities
+// adjoints of the pulled set's moments from those of the stored moments
+// (mb) and of the reported u* (ubo), through the collision of k_home_step
+__device__ __forceinline__ PopBar home_collision_adj(const LbmDev &P, const MomAcc &A, const float mb[HM_N],
+                                                     const float ubo[3]) {
   const float rho = 1.f + A.drho, ir = 1.f / rho;
   float u[3], Fu = 0.f;
 #pragma unroll
@@ -842,14 +755,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_step_adj(LbmDev P, const flo
     u[a] = (A.j[a] + 0.5f * P.F[a]) * ir;
     Fu += P.F[a] * u[a];
   }
-  float S[6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) S[s] = A.P[s] * ir;
   const float om = P.omega, keep = 1.f - om, kf = 1.f - 0.5f * om;
-  // adjoints of the stored moments
-  float mb[10];
-#pragma unroll
-  for (int q = 0; q < 10; ++q) mb[q] = mout_bar[(int64_t)q * P.L + node];
   float Sb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ub[3] = {0.f, 0.f, 0.f}, irb = 0.f;
   // diagonal S: keep (S_a - tr/3) + om (u_a^2 - |u|^2/3) + |u|^2/3
   //             + (F_a u_a + keep (F_a u_a - F.u/3)) ir
@@ -879,9 +785,8 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_step_adj(LbmDev P, const flo
   // stored u = u* + F / (2 rho), reported u*
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    ub[a] += mb[1 + a];
+    ub[a] += mb[1 + a] + ubo[a];
     irb += mb[1 + a] * 0.5f * P.F[a];
-    if (ubar_out) ub[a] += ubar_out[(int64_t)a * P.L + node];
   }
   // S = P ir, u = (j + F/2) ir, ir = 1 / (1 + drho)
   PopBar B;
@@ -896,9 +801,163 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_step_adj(LbmDev P, const flo
     irb += ub[a] * (A.j[a] + 0.5f * P.F[a]);
   }
   B.drho = mb[0] - irb * ir * ir;
-  Mom own_bar{};
-  home_push_all(std::make_integer_sequence<int, 19>{}, P, min, solid, i, j, k, node, own, B, own_bar, mbar);
-  mom_atomic_add(mbar, P.L, node, own_bar);
+  return B;
+}
+
+// adjoint of pulled population Q: the pulled set's moments are linear in it
+template <int Q>
+__device__ __forceinline__ float pop_bar(const PopBar &B) {
+  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
+  float gb = B.drho;
+  if constexpr (c[0] != 0) gb += c[0] * B.j[0];
+  if constexpr (c[1] != 0) gb += c[1] * B.j[1];
+  if constexpr (c[2] != 0) gb += c[2] * B.j[2];
+  gb += (c[0] * c[0] - 1.f / 3.f) * B.P[0] + (c[1] * c[1] - 1.f / 3.f) * B.P[1] + (c[2] * c[2] - 1.f / 3.f) * B.P[2];
+  if constexpr (c[0] * c[1] != 0) gb += (c[0] * c[1]) * B.P[3];
+  if constexpr (c[0] * c[2] != 0) gb += (c[0] * c[2]) * B.P[4];
+  if constexpr (c[1] * c[2] != 0) gb += (c[1] * c[2]) * B.P[5];
+  return gb;
+}
+
+template <int... Qs>
+__device__ __forceinline__ void store_pop_bars(std::integer_sequence<int, Qs...>, const LbmDev &P,
+                                               float *__restrict__ gbar, uint32_t node, const PopBar &B, bool zero) {
+  (st_node(gbar + (size_t)Qs * P.L, node, zero ? 0.f : pop_bar<Qs>(B)), ...);
+}
+
+// Solid flags of the 3 x 3 rows around the block's row into LDS; true if any
+// is set (block-uniform; has a barrier).
+__device__ __forceinline__ bool stage_solid(const LbmDev &P, const uint8_t *__restrict__ solid, int x0, int j, int k,
+                                            uint8_t (*s_sol)[SOL_W], int *s_any) {
+  uint32_t sv[SOL_PER_THREAD];
+  load_solid_rows(P, solid, x0, j, k, sv);
+  store_solid_rows(sv, s_sol);
+  uint32_t mine = 0;
+#pragma unroll
+  for (int u = 0; u < SOL_PER_THREAD; ++u) mine |= sv[u];
+  const bool wave_any = __ballot(mine != 0) != 0ull;
+  if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = wave_any;
+  __syncthreads();
+  bool any = false;
+#pragma unroll
+  for (int w = 0; w < LBM_BLOCK / 64; ++w) any = any || s_any[w] != 0;
+  return any;
+}
+
+template <bool SOLID>
+__global__ __launch_bounds__(LBM_BLOCK) void k_home_adj_pull(LbmDev P, const float *__restrict__ min,
+                                                             const uint8_t *__restrict__ solid,
+                                                             const float *__restrict__ mout_bar,
+                                                             const float *__restrict__ ubar_out,
+                                                             float *__restrict__ gbar) {
+  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  __shared__ int s_any[LBM_BLOCK / 64];
+  __shared__ float s_inl[5];
+  const RowBlock rb = xcd_row_block(P);
+  if (!rb.live) return;  // block-uniform
+  const int x0 = rb.x0;
+  const int i = x0 + threadIdx.x, j = rb.j, k = rb.k;
+  const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
+  const bool inlet_row = x0 == 0 && P.bc[0] == DW_BC_INLET;
+  if (inlet_row && threadIdx.x < 5) s_inl[threadIdx.x] = home_inlet_pop(P, threadIdx.x, j, k);
+  bool any = false;
+  if (SOLID) any = stage_solid(P, solid, x0, j, k, s_sol, s_any);
+  else if (inlet_row) __syncthreads();
+  if (i >= P.nx) return;
+  const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
+  const bool inlet_wave = inlet_row && threadIdx.x < 64;  // wave-uniform
+  const Mom own = load_mom_at(min, P.L, node);
+  MomAcc A;
+  if (any) home_row_all<1>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
+  else home_row_all<0>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
+  float mb[HM_N], ubo[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < HM_N; ++q) mb[q] = ld_node(mout_bar + (size_t)q * P.L, node);
+  if (ubar_out) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ubo[a] = ld_node(ubar_out + (size_t)a * P.L, node);
+  }
+  store_pop_bars(std::make_integer_sequence<int, 19>{}, P, gbar, node, home_collision_adj(P, A, mb, ubo), solid_node);
+}
+
+// Where T_Q of this node comes from: the node at +c_Q pulled population Q
+// from here (the source rules of pull_src<opp(Q)> find it), unless the pull
+// of opp(Q) here bounced (then gbar_opp(Q) of this node) or came from an
+// inlet ghost or an outlet clamp (no node at +c_Q: T_Q = 0).  Planes Q and
+// opp(Q) are adjacent, so one offset from the lower addresses either.
+template <int Q, int SOL>
+__device__ __forceinline__ uint32_t push_offset(const LbmDev &P, const uint8_t (*s_sol)[SOL_W], int i, int j, int k,
+                                                int x0, uint32_t node, bool &live) {
+  constexpr int R = LOPP[Q];
+  const PullSrc s = pull_src<R>(P, i, j, k);
+  const bool bb = pull_bounces<R, SOL>(s, s_sol, x0);
+  const bool clamped = LC[Q][0] > 0 && i == P.nx - 1 && P.bc[1] == DW_BC_OUTLET;
+  live = bb || (s.kind == SRC_NORMAL && !clamped);
+  const uint32_t L = (uint32_t)P.L;
+  return bb ? (uint32_t)(R - pair_lo<Q>()) * L + node : (uint32_t)(Q - pair_lo<Q>()) * L + s.src;
+}
+
+// At the last x of an outlet the pull of each c_x = -1 direction Q by node
+// (nx - 1, j + c_Q.y, k + c_Q.z) was clamped onto this node.
+template <int Q>
+__device__ __forceinline__ void outlet_extra(const LbmDev &P, const float *__restrict__ gbar, int j, int k,
+                                             float &T) {
+  if constexpr (LC[Q][0] < 0) {
+    int sj, sk;
+    bool bounce;
+    row_source(P, j, k, -LC[Q][1], -LC[Q][2], &sj, &sk, &bounce);
+    if (!bounce)
+      T += ld_node(gbar + (size_t)Q * P.L,
+                   (uint32_t)(P.nx - 1) + (uint32_t)P.nx * ((uint32_t)sj + (uint32_t)P.ny * (uint32_t)sk));
+  }
+}
+
+template <int SOL, int... Qs>
+__device__ __forceinline__ void gather_row(std::integer_sequence<int, Qs...>, const LbmDev &P,
+                                           const float *__restrict__ gbar, const uint8_t (*s_sol)[SOL_W], int i,
+                                           int j, int k, int x0, uint32_t node, float T[19]) {
+  uint32_t off[19];
+  bool live[19];
+  ((off[Qs] = push_offset<Qs, SOL>(P, s_sol, i, j, k, x0, node, live[Qs])), ...);
+  ((T[Qs] = ld_node(gbar + (size_t)pair_lo<Qs>() * P.L, off[Qs])), ...);
+  ((T[Qs] = live[Qs] ? T[Qs] : 0.f), ...);
+  if (i == P.nx - 1 && P.bc[1] == DW_BC_OUTLET) (outlet_extra<Qs>(P, gbar, j, k, T[Qs]), ...);
+}
+
+template <int... Qs>
+__device__ __forceinline__ void pops_adj(std::integer_sequence<int, Qs...>, const Mom &M, const float T[19],
+                                         Mom &Mb) {
+  (home_pop_adj<Qs>(M, T[Qs], Mb), ...);
+}
+
+template <bool SOLID>
+__global__ __launch_bounds__(LBM_BLOCK) void k_home_adj_gather(LbmDev P, const float *__restrict__ min,
+                                                               const uint8_t *__restrict__ solid,
+                                                               const float *__restrict__ gbar,
+                                                               float *__restrict__ mbar) {
+  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  __shared__ int s_any[LBM_BLOCK / 64];
+  const RowBlock rb = xcd_row_block(P);
+  if (!rb.live) return;  // block-uniform
+  const int x0 = rb.x0;
+  const int i = x0 + threadIdx.x, j = rb.j, k = rb.k;
+  const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
+  const bool any = SOLID && stage_solid(P, solid, x0, j, k, s_sol, s_any);
+  if (i >= P.nx) return;
+  // a solid node's moments feed no population (every pull from it bounced)
+  const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
+  const Mom own = load_mom_at(min, P.L, node);
+  float T[19];
+  if (any) gather_row<1>(std::make_integer_sequence<int, 19>{}, P, gbar, s_sol, i, j, k, x0, node, T);
+  else gather_row<0>(std::make_integer_sequence<int, 19>{}, P, gbar, s_sol, i, j, k, x0, node, T);
+  Mom Mb{};
+  pops_adj(std::make_integer_sequence<int, 19>{}, own, T, Mb);
+  float v[HM_N] = {Mb.drho, Mb.u[0], Mb.u[1], Mb.u[2], Mb.S[0], Mb.S[1], Mb.S[2], Mb.S[3], Mb.S[4], Mb.S[5]};
+#pragma unroll
+  for (int q = 0; q < HM_N; ++q) {
+    float *plane = mbar + (size_t)q * P.L;
+    st_node(plane, node, ld_node(plane, node) + (solid_node ? 0.f : v[q]));
+  }
 }
 
 // Reverse of k_lbm_step: recompute the pulled populations and moments, form
@@ -1128,14 +1187,27 @@ extern "C" int lbm_home_equilibrium(const dw_lattice *lat, const dw_lbm_params *
 
 extern "C" int lbm_home_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *m_in,
                                  const uint8_t *solid, const float *m_out_bar, const float *u_out_bar,
-                                 float *m_in_bar, void *stream) {
+                                 float *m_in_bar, float *work, void *stream) {
   LbmDev P;
   int rc = make_lbm(lat, params, &P);
   if (rc) return rc;
-  DW_REQUIRE(m_in && m_out_bar && m_in_bar, DW_EINVAL, "lbm_home_step_adj: m_in / m_out_bar / m_in_bar is NULL");
+  DW_REQUIRE(m_in && m_out_bar && m_in_bar && work, DW_EINVAL,
+             "lbm_home_step_adj: m_in / m_out_bar / m_in_bar / work is NULL");
   DW_REQUIRE(m_in_bar != m_in && m_in_bar != m_out_bar, DW_EINVAL, "lbm_home_step_adj: m_in_bar must not alias");
-  hipLaunchKernelGGL(k_home_step_adj, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, m_in, solid, m_out_bar,
-                     u_out_bar, m_in_bar);
+  DW_REQUIRE(work != m_in && work != m_out_bar && work != m_in_bar && work != u_out_bar, DW_EINVAL,
+             "lbm_home_step_adj: work must not alias another argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (solid) {
+    hipLaunchKernelGGL(k_home_adj_pull<true>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, m_out_bar,
+                       u_out_bar, work);
+    hipLaunchKernelGGL(k_home_adj_gather<true>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
+                       m_in_bar);
+  } else {
+    hipLaunchKernelGGL(k_home_adj_pull<false>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, m_out_bar,
+                       u_out_bar, work);
+    hipLaunchKernelGGL(k_home_adj_gather<false>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
+                       m_in_bar);
+  }
   return check_launch("lbm_home_step_adj");
 }
 
