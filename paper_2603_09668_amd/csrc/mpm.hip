@@ -551,18 +551,77 @@ __global__ __launch_bounds__(256) void k_grid_update(GridDev g, float dt, float 
 
 // ------------------------------------------------------------------ G2P
 
-// G2P stages the grid velocities of its block's stencils in LDS when their
-// bounding box holds at most G2P_BOX nodes (12^3, 20.7 KB): particles stored
-// in tile order keep a block's box small, and the 27-node gathers then come
-// from LDS instead of the vector memory pipeline, which they saturated.
-// Blocks with a larger box gather from global memory as before.
+// G2P, one particle per thread.  A workgroup stages the grid velocities of
+// its stencils in LDS when their bounding box holds at most G2P_BOX nodes
+// (12^3, 20.7 KB): particles stored in tile order keep the box small, and the
+// 27-node gathers then come from LDS instead of the vector memory pipeline,
+// which they saturated (a workgroup with a larger box gathers from global
+// memory).  One batch per workgroup: on this ISA a wave's stores count
+// against the same counter as its loads, so a workgroup that went on to a
+// next batch would wait for its previous stores at the next staging wait.
 constexpr int G2P_BOX = 1728;
 
 struct Float3 {
   float v[3];
 };
 
-__global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
+// v = sum w u and B = sum w u o^T over the stencil, row by row (a row = the
+// three x-neighbours at fixed oy, oz): per row r0 = sum_ox wx u and
+// r1 = sum_ox wx ox u, the row weight wy wz scaling r0 (v and the y, z
+// columns of B) and r1 (the x column).  LDS: the box's node li0 + ox + ex oy
+// + exy oz; else the grid row at (bx, by + oy, bz + oz).
+template <bool LDS>
+__device__ __forceinline__ void g2p_gather(const GridDev &g, const float *__restrict__ gv, int64_t N,
+                                           const float (*s_v)[G2P_BOX], int li0, int ex, int exy, int bx, int by,
+                                           int bz, const float wx[3], const float wy[3], const float wz[3],
+                                           float vv[3], float B[9]) {
+#pragma unroll
+  for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) {
+      Float3 ra, rb, rc;
+      if constexpr (LDS) {
+        const int li = li0 + oy * ex + oz * exy;
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+          ra.v[ox] = s_v[0][li + ox];
+          rb.v[ox] = s_v[1][li + ox];
+          rc.v[ox] = s_v[2][li + ox];
+        }
+      } else {
+        // the three x-neighbours are contiguous: one 12-byte load per component
+        const int64_t row = bx + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
+        __builtin_memcpy(&ra, gv + row, sizeof(Float3));
+        __builtin_memcpy(&rb, gv + N + row, sizeof(Float3));
+        __builtin_memcpy(&rc, gv + 2 * N + row, sizeof(Float3));
+      }
+      const float u0[3] = {ra.v[0] * wx[0] + ra.v[1] * wx[1] + ra.v[2] * wx[2],
+                           rb.v[0] * wx[0] + rb.v[1] * wx[1] + rb.v[2] * wx[2],
+                           rc.v[0] * wx[0] + rc.v[1] * wx[1] + rc.v[2] * wx[2]};
+      const float w2 = 2.0f * wx[2];
+      const float u1[3] = {ra.v[1] * wx[1] + ra.v[2] * w2, rb.v[1] * wx[1] + rb.v[2] * w2,
+                           rc.v[1] * wx[1] + rc.v[2] * w2};
+      const float wyz = wy[oy] * wz[oz];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        vv[a] += wyz * u0[a];
+        B[3 * a] += wyz * u1[a];
+      }
+      if (oy > 0) {
+        const float wy_ = wyz * (float)oy;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) B[3 * a + 1] += wy_ * u0[a];
+      }
+      if (oz > 0) {
+        const float wz_ = wyz * (float)oz;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) B[3 * a + 2] += wz_ * u0[a];
+      }
+    }
+}
+
+// at most 72 VGPRs: 7 workgroups per CU, the count the LDS box allows
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_g2p(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
                                              const float *xin, const float *Fin, float *xout, float *vout,
                                              float *Cout, float *Fout, int n, int32_t *__restrict__ status) {
   __shared__ float s_v[3][G2P_BOX];
@@ -571,10 +630,10 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < n;
   const uint32_t pp = live ? (uint32_t)p : 0u;
-  float px = ld32(xin, pp), py = ld32(xin + n, pp), pz = ld32(xin + 2 * (size_t)n, pp);
-  float X = grid_coord(px, g.ox, g.inv_dx);
-  float Y = grid_coord(py, g.oy, g.inv_dx);
-  float Z = grid_coord(pz, g.oz, g.inv_dx);
+  const float px = ld32(xin, pp), py = ld32(xin + n, pp), pz = ld32(xin + 2 * (size_t)n, pp);
+  const float X = grid_coord(px, g.ox, g.inv_dx);
+  const float Y = grid_coord(py, g.oy, g.inv_dx);
+  const float Z = grid_coord(pz, g.oz, g.inv_dx);
   float F[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) F[q] = ld32(Fin + (size_t)q * n, pp);
@@ -584,7 +643,7 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
     bx = base_of(X); by = base_of(Y); bz = base_of(Z);
     ok = stencil_inside(g, bx, by, bz);
   }
-  // bounding box of the block's stencils; stage it in LDS when it is small
+  // bounding box of the workgroup's stencils
   {
     int r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
     if (live && ok) { r[0] = bx; r[1] = by; r[2] = bz; r[3] = bx; r[4] = by; r[5] = bz; }
@@ -602,7 +661,8 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
     __syncthreads();
     if (threadIdx.x < 6) {
       int v = s_red[0][threadIdx.x];
-      for (int w = 1; w < 256 / 64; ++w) v = threadIdx.x < 3 ? min(v, s_red[w][threadIdx.x]) : max(v, s_red[w][threadIdx.x]);
+      for (int w = 1; w < 256 / 64; ++w)
+        v = threadIdx.x < 3 ? min(v, s_red[w][threadIdx.x]) : max(v, s_red[w][threadIdx.x]);
       s_box[threadIdx.x] = v;
     }
     __syncthreads();
@@ -612,31 +672,47 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
   const int ex = any ? s_box[3] - lo0 + 3 : 0, ey = any ? s_box[4] - lo1 + 3 : 0, ez = any ? s_box[5] - lo2 + 3 : 0;
   const bool staged = any && ex * ey * ez <= G2P_BOX;
   if (staged) {
+    // every load of the box first, then the LDS writes
     const int nb = ex * ey * ez;
-    for (int q = threadIdx.x; q < nb; q += 256) {
-      const int ix = q % ex, iy = (q / ex) % ey, iz = q / (ex * ey);
-      const int64_t node = (lo0 + ix) + (int64_t)g.nx * ((lo1 + iy) + (int64_t)g.ny * (lo2 + iz));
-      s_v[0][q] = gv[node];
-      s_v[1][q] = gv[N + node];
-      s_v[2][q] = gv[2 * N + node];
+    constexpr int PER = (G2P_BOX + 255) / 256;
+    float sv[PER][3];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      if (256 * r < nb) {
+        const int q = min((int)threadIdx.x + 256 * r, nb - 1);
+        const int ix = q % ex, iy = (q / ex) % ey, iz = q / (ex * ey);
+        const uint32_t node = (uint32_t)(lo0 + ix) +
+                              (uint32_t)g.nx * ((uint32_t)(lo1 + iy) + (uint32_t)g.ny * (uint32_t)(lo2 + iz));
+        sv[r][0] = ld32(gv, node);
+        sv[r][1] = ld32(gv + N, node);
+        sv[r][2] = ld32(gv + 2 * N, node);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int q = (int)threadIdx.x + 256 * r;
+      if (256 * r < nb && q < nb) {
+        s_v[0][q] = sv[r][0];
+        s_v[1][q] = sv[r][1];
+        s_v[2][q] = sv[r][2];
+      }
     }
     __syncthreads();
   }
   if (!live) return;
-  const int lx = bx - lo0, ly = by - lo1, lz = bz - lo2;
   if (!ok) {
     if (status) atomicOr(status, DW_STATUS_OUT_OF_GRID);
-    xout[p] = px; xout[n + p] = py; xout[2 * n + p] = pz;
+    st32(xout, pp, px); st32(xout + n, pp, py); st32(xout + 2 * (size_t)n, pp, pz);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) vout[q * n + p] = 0.f;
+    for (int q = 0; q < 3; ++q) st32(vout + (size_t)q * n, pp, 0.f);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      Cout[q * n + p] = 0.f;
-      Fout[q * n + p] = F[q];
+      st32(Cout + (size_t)q * n, pp, 0.f);
+      st32(Fout + (size_t)q * n, pp, F[q]);
     }
     return;
   }
-  float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
+  const float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
   float wx[3], wy[3], wz[3];
   {
     float a = 1.5f - fx, b = fx - 1.0f, c = fx - 0.5f;
@@ -646,79 +722,38 @@ __global__ __launch_bounds__(256) void k_g2p(GridDev g, float dt, const float *_
     a = 1.5f - fz; b = fz - 1.0f; c = fz - 0.5f;
     wz[0] = 0.5f * a * a; wz[1] = 0.75f - b * b; wz[2] = 0.5f * c * c;
   }
-  // Separable sums over the stencil, row by row (a row = the three
-  // x-neighbours at fixed oy, oz):
-  //   v = sum w u,   B = sum w u (o - f)^T = sum w u o^T - v f^T,
-  // with per row r0 = sum_ox wx u and r1 = sum_ox wx ox u, the row weight
-  // wy wz scaling r0 (v and the y, z columns of B) and r1 (the x column).
-  float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+  float vv[3] = {0.f, 0.f, 0.f};
   float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int oz = 0; oz < 3; ++oz)
-#pragma unroll
-    for (int oy = 0; oy < 3; ++oy) {
-      int64_t row = (bx) + (int64_t)g.nx * ((by + oy) + (int64_t)g.ny * (bz + oz));
-      // the three x-neighbours of a stencil row are contiguous: one 12-byte
-      // load per velocity component
-      Float3 ra, rb, rc;
-      if (staged) {
-        const int li = lx + ex * ((ly + oy) + ey * (lz + oz));
-#pragma unroll
-        for (int ox = 0; ox < 3; ++ox) {
-          ra.v[ox] = s_v[0][li + ox];
-          rb.v[ox] = s_v[1][li + ox];
-          rc.v[ox] = s_v[2][li + ox];
-        }
-      } else {
-        __builtin_memcpy(&ra, gv + row, sizeof(Float3));
-        __builtin_memcpy(&rb, gv + N + row, sizeof(Float3));
-        __builtin_memcpy(&rc, gv + 2 * N + row, sizeof(Float3));
-      }
-      const float u0[3] = {ra.v[0] * wx[0] + ra.v[1] * wx[1] + ra.v[2] * wx[2],
-                           rb.v[0] * wx[0] + rb.v[1] * wx[1] + rb.v[2] * wx[2],
-                           rc.v[0] * wx[0] + rc.v[1] * wx[1] + rc.v[2] * wx[2]};
-      const float w2 = 2.0f * wx[2];
-      const float u1[3] = {ra.v[1] * wx[1] + ra.v[2] * w2, rb.v[1] * wx[1] + rb.v[2] * w2,
-                           rc.v[1] * wx[1] + rc.v[2] * w2};
-      const float wyz = wy[oy] * wz[oz];
-      v0 += wyz * u0[0]; v1 += wyz * u0[1]; v2 += wyz * u0[2];
-      B[0] += wyz * u1[0]; B[3] += wyz * u1[1]; B[6] += wyz * u1[2];
-      if (oy > 0) {
-        const float wy_ = wyz * (float)oy;
-        B[1] += wy_ * u0[0]; B[4] += wy_ * u0[1]; B[7] += wy_ * u0[2];
-      }
-      if (oz > 0) {
-        const float wz_ = wyz * (float)oz;
-        B[2] += wz_ * u0[0]; B[5] += wz_ * u0[1]; B[8] += wz_ * u0[2];
-      }
-    }
-  const float vv[3] = {v0, v1, v2}, ff[3] = {fx, fy, fz};
+  if (staged)
+    g2p_gather<true>(g, gv, N, s_v, (bx - lo0) + ex * ((by - lo1) + ey * (bz - lo2)), ex, ex * ey, bx, by, bz, wx,
+                     wy, wz, vv, B);
+  else
+    g2p_gather<false>(g, gv, N, s_v, 0, 0, 0, bx, by, bz, wx, wy, wz, vv, B);
+  const float ff[3] = {fx, fy, fz};
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) B[3 * a + b] -= vv[a] * ff[b];
+    for (int c = 0; c < 3; ++c) B[3 * a + c] -= vv[a] * ff[c];
   // C = (4/dx^2) sum w v d^T with d = (o - f) dx  ->  (4/dx) sum w v (o - f)^T
-  float kc = 4.0f * g.inv_dx;
+  const float kc = 4.0f * g.inv_dx;
   float Cn[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) Cn[q] = kc * B[q];
-  st32(xout, pp, px + dt * v0);
-  st32(xout + n, pp, py + dt * v1);
-  st32(xout + 2 * (size_t)n, pp, pz + dt * v2);
-  st32(vout, pp, v0);
-  st32(vout + n, pp, v1);
-  st32(vout + 2 * (size_t)n, pp, v2);
+  st32(xout, pp, px + dt * vv[0]);
+  st32(xout + n, pp, py + dt * vv[1]);
+  st32(xout + 2 * (size_t)n, pp, pz + dt * vv[2]);
+  st32(vout, pp, vv[0]);
+  st32(vout + n, pp, vv[1]);
+  st32(vout + 2 * (size_t)n, pp, vv[2]);
   // F <- (I + dt C) F with F = I + H stored as H:  H <- H + dt C + dt C H
-  float G[9], CH[9], Fn[9];
+  float G[9], CH[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) G[q] = dt * Cn[q];
   matmul3(G, F, CH);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) Fn[q] = F[q] + G[q] + CH[q];
-#pragma unroll
   for (int q = 0; q < 9; ++q) {
     st32(Cout + (size_t)q * n, pp, Cn[q]);
-    st32(Fout + (size_t)q * n, pp, Fn[q]);
+    st32(Fout + (size_t)q * n, pp, F[q] + G[q] + CH[q]);
   }
 }
 
@@ -730,19 +765,22 @@ namespace dw {
 
 constexpr int PERSISTENT_BLOCKS = 2048;
 
-// P2G grid: the workgroups that fit at once (two per compute unit), which
-// then draw work items from the ticket counter
-static unsigned p2g_blocks() {
+// compute units of the current device (cached per device)
+static int cu_count() {
   static int cus[64] = {0};
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 512;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
   if (cus[dev] == 0) {
     int c = 0;
     if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
     cus[dev] = c;
   }
-  return (unsigned)(P2G_PER_CU * cus[dev]);
+  return cus[dev];
 }
+
+// P2G grid: the workgroups that fit at once (two per compute unit), which
+// then draw work items from the ticket counter
+static unsigned p2g_blocks() { return (unsigned)(P2G_PER_CU * cu_count()); }
 
 static PView make_pview(const dw_particles *p) {
   PView v;
