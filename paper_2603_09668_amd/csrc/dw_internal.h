@@ -297,10 +297,6 @@ __device__ __forceinline__ void kirchhoff_shift(const float *H, float mu, float 
   }
 }
 
-// Grid coordinate X = (x - origin) / dx of a particle and its stencil base
-// floor(X - 1/2).  Contraction is disabled so that every kernel rounds the
-// same way and a particle lands in the same cell tile in the sort, the
-// transfers and the adjoints.
 // Element i of an array whose byte offsets fit in 32 bits (i < 2^30): a
 // scalar base plus a 32-bit lane offset, which the load / store encodes
 // directly (no 64-bit address arithmetic per lane).
@@ -311,6 +307,10 @@ __device__ __forceinline__ void st32(float *base, uint32_t i, float v) {
   *reinterpret_cast<float *>(reinterpret_cast<char *>(base) + (i << 2)) = v;
 }
 
+// Grid coordinate X = (x - origin) / dx of a particle and its stencil base
+// floor(X - 1/2).  Contraction is disabled so that every kernel rounds the
+// same way and a particle lands in the same cell tile in the sort, the
+// transfers and the adjoints.
 __device__ __forceinline__ float grid_coord(float x, float o, float inv_dx) {
 #pragma clang fp contract(off)
   return (x - o) * inv_dx;

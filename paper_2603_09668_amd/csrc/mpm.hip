@@ -551,16 +551,101 @@ __global__ __launch_bounds__(256) void k_grid_update(GridDev g, float dt, float 
 
 // ------------------------------------------------------------------ G2P
 
-// G2P, one particle per thread.  A workgroup stages the grid velocities of
-// its stencils in LDS when their bounding box holds at most G2P_BOX nodes
-// (12^3, 20.7 KB): particles stored in tile order keep the box small, and the
-// 27-node gathers then come from LDS instead of the vector memory pipeline,
-// which they saturated (a workgroup with a larger box gathers from global
-// memory).  One batch per workgroup: on this ISA a wave's stores count
-// against the same counter as its loads, so a workgroup that went on to a
-// next batch would wait for its previous stores at the next staging wait.
-constexpr int G2P_BOX = 1728;
+// ------------------------------------------------ stencil box staged in LDS
+// The 256 particles of a workgroup, stored in tile order, touch few grid
+// nodes: the bounding box of their 3 x 3 x 3 stencils.  When it holds at most
+// STENCIL_BOX nodes (12^3) a kernel stages the grid arrays it gathers over
+// the box in LDS once, and the 27-node gathers read LDS instead of keeping
+// the vector memory pipeline busy (they mostly hit L1/L2, but issue 27 loads
+// per particle and array).
+constexpr int STENCIL_BOX = 1728;
 
+struct StencilBox {
+  int lo[3];    // lowest node of the box
+  int ex, ey;   // extents in x and y (nodes)
+  int nb;       // nodes in the box, 0 if no thread takes part
+  bool staged;  // 0 < nb <= STENCIL_BOX
+};
+
+// Box of the stencil bases (bx, by, bz) of the threads with `have` set, for a
+// 256-thread workgroup; block-uniform.  Two barriers; s_red [4][6] and
+// s_box [6] are LDS scratch.
+__device__ __forceinline__ StencilBox block_box(bool have, int bx, int by, int bz, int (*s_red)[6], int *s_box) {
+  int r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  if (have) {
+    r[0] = bx; r[1] = by; r[2] = bz;
+    r[3] = bx; r[4] = by; r[5] = bz;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r[a] = min(r[a], __shfl_xor(r[a], o, 64));
+      r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], o, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) s_red[threadIdx.x >> 6][a] = r[a];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    int v = s_red[0][threadIdx.x];
+    for (int w = 1; w < 4; ++w) v = threadIdx.x < 3 ? min(v, s_red[w][threadIdx.x]) : max(v, s_red[w][threadIdx.x]);
+    s_box[threadIdx.x] = v;
+  }
+  __syncthreads();
+  StencilBox B;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) B.lo[a] = s_box[a];
+  const bool any = s_box[3] >= B.lo[0];
+  B.ex = any ? s_box[3] - B.lo[0] + 3 : 0;
+  B.ey = any ? s_box[4] - B.lo[1] + 3 : 0;
+  B.nb = any ? B.ex * B.ey * (s_box[5] - B.lo[2] + 3) : 0;
+  B.staged = any && B.nb <= STENCIL_BOX;
+  return B;
+}
+
+// LDS index of the box node (i, j, k)
+__device__ __forceinline__ int box_index(const StencilBox &B, int i, int j, int k) {
+  return (i - B.lo[0]) + B.ex * ((j - B.lo[1]) + B.ey * (k - B.lo[2]));
+}
+
+// s[a][q] = src[a][node q of the box] for the NV arrays (grid node indices
+// below 2^30): every load first, then the LDS writes, then a barrier.  For a
+// staged box, called by the whole workgroup.
+template <int NV>
+__device__ __forceinline__ void stage_box(const GridDev &g, const StencilBox &B, const float *const (&src)[NV],
+                                          float (*s)[STENCIL_BOX]) {
+  constexpr int PER = (STENCIL_BOX + 255) / 256;
+  float sv[PER][NV];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    if (256 * r < B.nb) {
+      const int q = min((int)threadIdx.x + 256 * r, B.nb - 1);
+      const int ix = q % B.ex, iy = (q / B.ex) % B.ey, iz = q / (B.ex * B.ey);
+      const uint32_t node = (uint32_t)(B.lo[0] + ix) +
+                            (uint32_t)g.nx * ((uint32_t)(B.lo[1] + iy) + (uint32_t)g.ny * (uint32_t)(B.lo[2] + iz));
+#pragma unroll
+      for (int a = 0; a < NV; ++a) sv[r][a] = ld32(src[a], node);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int q = (int)threadIdx.x + 256 * r;
+    if (256 * r < B.nb && q < B.nb) {
+#pragma unroll
+      for (int a = 0; a < NV; ++a) s[a][q] = sv[r][a];
+    }
+  }
+  __syncthreads();
+}
+
+
+// G2P, one particle per thread, the 27-node gathers from the workgroup's
+// stencil box in LDS when it is staged, else from global memory.  One batch
+// per workgroup: on this ISA a wave's stores count against the same counter
+// as its loads, so a workgroup that went on to a next batch would wait for
+// its previous stores at the next staging wait.
 struct Float3 {
   float v[3];
 };
@@ -572,7 +657,7 @@ struct Float3 {
 // + exy oz; else the grid row at (bx, by + oy, bz + oz).
 template <bool LDS>
 __device__ __forceinline__ void g2p_gather(const GridDev &g, const float *__restrict__ gv, int64_t N,
-                                           const float (*s_v)[G2P_BOX], int li0, int ex, int exy, int bx, int by,
+                                           const float (*s_v)[STENCIL_BOX], int li0, int ex, int exy, int bx, int by,
                                            int bz, const float wx[3], const float wy[3], const float wz[3],
                                            float vv[3], float B[9]) {
 #pragma unroll
@@ -624,8 +709,8 @@ __device__ __forceinline__ void g2p_gather(const GridDev &g, const float *__rest
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_g2p(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
                                              const float *xin, const float *Fin, float *xout, float *vout,
                                              float *Cout, float *Fout, int n, int32_t *__restrict__ status) {
-  __shared__ float s_v[3][G2P_BOX];
-  __shared__ int s_red[256 / 64][6];
+  __shared__ float s_v[3][STENCIL_BOX];
+  __shared__ int s_red[4][6];
   __shared__ int s_box[6];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < n;
@@ -643,61 +728,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     bx = base_of(X); by = base_of(Y); bz = base_of(Z);
     ok = stencil_inside(g, bx, by, bz);
   }
-  // bounding box of the workgroup's stencils
-  {
-    int r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
-    if (live && ok) { r[0] = bx; r[1] = by; r[2] = bz; r[3] = bx; r[4] = by; r[5] = bz; }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        r[a] = min(r[a], __shfl_xor(r[a], o, 64));
-        r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], o, 64));
-      }
-    }
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-      for (int a = 0; a < 6; ++a) s_red[threadIdx.x >> 6][a] = r[a];
-    __syncthreads();
-    if (threadIdx.x < 6) {
-      int v = s_red[0][threadIdx.x];
-      for (int w = 1; w < 256 / 64; ++w)
-        v = threadIdx.x < 3 ? min(v, s_red[w][threadIdx.x]) : max(v, s_red[w][threadIdx.x]);
-      s_box[threadIdx.x] = v;
-    }
-    __syncthreads();
-  }
-  const int lo0 = s_box[0], lo1 = s_box[1], lo2 = s_box[2];
-  const bool any = s_box[3] >= lo0;
-  const int ex = any ? s_box[3] - lo0 + 3 : 0, ey = any ? s_box[4] - lo1 + 3 : 0, ez = any ? s_box[5] - lo2 + 3 : 0;
-  const bool staged = any && ex * ey * ez <= G2P_BOX;
-  if (staged) {
-    // every load of the box first, then the LDS writes
-    const int nb = ex * ey * ez;
-    constexpr int PER = (G2P_BOX + 255) / 256;
-    float sv[PER][3];
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      if (256 * r < nb) {
-        const int q = min((int)threadIdx.x + 256 * r, nb - 1);
-        const int ix = q % ex, iy = (q / ex) % ey, iz = q / (ex * ey);
-        const uint32_t node = (uint32_t)(lo0 + ix) +
-                              (uint32_t)g.nx * ((uint32_t)(lo1 + iy) + (uint32_t)g.ny * (uint32_t)(lo2 + iz));
-        sv[r][0] = ld32(gv, node);
-        sv[r][1] = ld32(gv + N, node);
-        sv[r][2] = ld32(gv + 2 * N, node);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int q = (int)threadIdx.x + 256 * r;
-      if (256 * r < nb && q < nb) {
-        s_v[0][q] = sv[r][0];
-        s_v[1][q] = sv[r][1];
-        s_v[2][q] = sv[r][2];
-      }
-    }
-    __syncthreads();
+  const StencilBox box = block_box(live && ok, bx, by, bz, s_red, s_box);
+  if (box.staged) {
+    const float *const src[3] = {gv, gv + N, gv + 2 * N};
+    stage_box<3>(g, box, src, s_v);
   }
   if (!live) return;
   if (!ok) {
@@ -724,9 +758,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   }
   float vv[3] = {0.f, 0.f, 0.f};
   float B[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (staged)
-    g2p_gather<true>(g, gv, N, s_v, (bx - lo0) + ex * ((by - lo1) + ey * (bz - lo2)), ex, ex * ey, bx, by, bz, wx,
-                     wy, wz, vv, B);
+  if (box.staged)
+    g2p_gather<true>(g, gv, N, s_v, box_index(box, bx, by, bz), box.ex, box.ex * box.ey, bx, by, bz, wx, wy, wz, vv,
+                     B);
   else
     g2p_gather<false>(g, gv, N, s_v, 0, 0, 0, bx, by, bz, wx, wy, wz, vv, B);
   const float ff[3] = {fx, fy, fz};
