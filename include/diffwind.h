@@ -335,11 +335,19 @@ int wind_guide(const dw_lattice *lat, const float *u, const int nw[3], const flo
 int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in, float *f_out,
              const uint8_t *solid, float *rho_out, float *u_out, void *stream);
 
-/* Reverse of lbm_step (a push of the adjoint populations): given f_out_bar
- * [19][L] and u_out_bar [3][L] (NULL = zero), accumulates f_in_bar [19][L]. */
+/* Reverse of lbm_step: given f_out_bar [19][L] and u_out_bar [3][L] (NULL =
+ * zero), ACCUMULATES f_in_bar [19][L].  Two passes: the first recomputes
+ * every node's pulled populations and writes their adjoints through the BGK
+ * collision to work [19][L] (device scratch of 76 bytes per node, owned by
+ * the caller, contents on return unspecified); the second adds to every
+ * f_in_bar entry the adjoint of the pull that read it (the streaming
+ * transposed under the same boundary rules, bounced pulls included).  Solid
+ * nodes pass nothing back.  No atomics: the result does not depend on
+ * scheduling.  f_in_bar must alias neither f_in nor f_out_bar; work aliases
+ * no other argument. */
 int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
                  const uint8_t *solid, const float *f_out_bar, const float *u_out_bar,
-                 float *f_in_bar, void *stream);
+                 float *f_in_bar, float *work, void *stream);
 
 /* Shifted equilibrium populations f^eq(rho, u) - w: rho [L] (NULL = 1) and
  * u [3][L] (NULL = the uniform params->u_in).  Used to initialise a lattice

@@ -106,7 +106,7 @@ def lib():
                          POINTER(ParticlesBar), P, P, c_size_t, P], c_int),
         "wind_to_grid_adj": ([POINTER(Grid), POINTER(Wind), P, P, P], c_int),
         "lbm_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
-        "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
+        "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P, P], c_int),
         "lbm_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_home_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_home_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P, P], c_int),
@@ -368,10 +368,22 @@ def lbm_step(lat: Lattice, params: LBMParams, f_in, f_out, solid=None, rho_out=N
                           _ptr(rho_out, name="rho_out"), _ptr(u_out, name="u_out"), _stream()), "lbm_step")
 
 
-def lbm_step_adj(lat: Lattice, params: LBMParams, f_in, solid, f_out_bar, u_out_bar, f_in_bar):
+def lbm_step_adj(lat: Lattice, params: LBMParams, f_in, solid, f_out_bar, u_out_bar, f_in_bar, work=None):
+    """`work`: float32 scratch of (19, L) on the device (allocated here when None)."""
+    L = lat.nx * lat.ny * lat.nz
+    for t, name in ((f_in, "f_in"), (f_out_bar, "f_out_bar"), (f_in_bar, "f_in_bar")):
+        _shape(t, (19, L), name)
+    if u_out_bar is not None:
+        _shape(u_out_bar, (3, L), "u_out_bar")
+    if solid is not None:
+        _shape(solid, (L,), "solid")
+    if work is None:
+        work = torch.empty(19, L, dtype=torch.float32, device=f_in.device)
+    _shape(work, (19, L), "work")
     _check(lib().lbm_step_adj(ctypes.byref(lat), ctypes.byref(params), _ptr(f_in, name="f_in"),
                               _ptr(solid, torch.uint8, "solid"), _ptr(f_out_bar, name="f_out_bar"),
-                              _ptr(u_out_bar, name="u_out_bar"), _ptr(f_in_bar, name="f_in_bar"), _stream()),
+                              _ptr(u_out_bar, name="u_out_bar"), _ptr(f_in_bar, name="f_in_bar"),
+                              _ptr(work, name="work"), _stream()),
            "lbm_step_adj")
 
 

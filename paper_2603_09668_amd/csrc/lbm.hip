@@ -40,37 +40,9 @@ struct LbmDev {
 constexpr int LBM_BLOCK = 128;
 constexpr int SOL_W = LBM_BLOCK + 8;  // staged solid bytes per row: x0 - 4 .. x0 + LBM_BLOCK + 3
 
-// Where the population arriving at (i, j, k) in direction q comes from.
+// Where a pulled population comes from: the source node, this node's
+// opposite population (bounce-back), or the inlet ghost.
 enum { SRC_NORMAL = 0, SRC_BOUNCE = 1, SRC_INLET = 2 };
-
-__device__ __forceinline__ int pull_source(const LbmDev &P, const uint8_t *__restrict__ solid, int i, int j,
-                                           int k, int q, int64_t &src, int &sj, int &sk) {
-  int s[3] = {i - LC[q][0], j - LC[q][1], k - LC[q][2]};
-  const int n[3] = {P.nx, P.ny, P.nz};
-  bool bounce = false, inlet = false;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    int lo = P.bc[2 * a], hi = P.bc[2 * a + 1];
-    if (s[a] < 0) {
-      if (lo == DW_BC_PERIODIC) s[a] += n[a];
-      else if (lo == DW_BC_BOUNCEBACK) bounce = true;
-      else if (lo == DW_BC_INLET) inlet = true;
-    } else if (s[a] >= n[a]) {
-      if (hi == DW_BC_PERIODIC) s[a] -= n[a];
-      else if (hi == DW_BC_BOUNCEBACK) bounce = true;
-      else if (hi == DW_BC_OUTLET) s[a] = n[a] - 1;
-    }
-  }
-  if (bounce) return SRC_BOUNCE;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) s[a] = min(max(s[a], 0), n[a] - 1);
-  src = s[0] + (int64_t)P.nx * (s[1] + (int64_t)P.ny * s[2]);
-  sj = s[1];
-  sk = s[2];
-  if (inlet) return SRC_INLET;
-  if (solid && solid[src]) return SRC_BOUNCE;
-  return SRC_NORMAL;
-}
 
 // inlet equilibrium population (shifted) in direction q at inlet-plane (j, k)
 __device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, int k) {
@@ -140,39 +112,6 @@ __device__ __forceinline__ void store_solid_rows(const uint32_t v[SOL_PER_THREAD
   for (int u = 0; u < SOL_PER_THREAD; ++u) {
     const int q = threadIdx.x + u * LBM_BLOCK;
     if (q < SOL_WORDS) reinterpret_cast<uint32_t *>(&s_sol[0][0])[q] = v[u];
-  }
-}
-
-// Pull the 19 shifted populations of fluid node (i, j, k).  A source inside
-// the lattice is read unconditionally and replaced by the bounce-back value
-// when the staged solid flag says so; the boundary rules run only for the
-// few lanes whose source leaves the lattice (the inlet and outlet columns
-// sit in every x-row, so the general rule must not be taken per node).
-// SOL: 0 = no solid nodes, 1 = flags staged in s_sol, 2 = flags read from `solid`
-template <int SOL>
-__device__ __forceinline__ void pull_all(const LbmDev &P, const float *__restrict__ fin,
-                                         const uint8_t *__restrict__ solid, const uint8_t (*s_sol)[SOL_W], int i,
-                                         int j, int k, int x0, int64_t node, float f[19]) {
-  const int64_t sy = P.nx, sz = (int64_t)P.nx * P.ny;
-#pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    int si = i - LC[q][0], sj = j - LC[q][1], sk = k - LC[q][2];
-    bool inside = (unsigned)si < (unsigned)P.nx && (unsigned)sj < (unsigned)P.ny && (unsigned)sk < (unsigned)P.nz;
-    if (inside) {
-      int64_t src = node - (LC[q][0] + LC[q][1] * sy + LC[q][2] * sz);
-      float v = fin[(int64_t)q * P.L + src];
-      const bool bb = SOL == 1 ? s_sol[(1 - LC[q][1]) + 3 * (1 - LC[q][2])][si - x0 + 4] != 0
-                              : (SOL == 2 && solid[src] != 0);
-      if (bb) v = fin[(int64_t)LOPP[q] * P.L + node];
-      f[q] = v;
-    } else {
-      int64_t src = node;
-      int ssj = 0, ssk = 0;
-      int kind = pull_source(P, solid, i, j, k, q, src, ssj, ssk);
-      if (kind == SRC_NORMAL) f[q] = fin[(int64_t)q * P.L + src];
-      else if (kind == SRC_BOUNCE) f[q] = fin[(int64_t)LOPP[q] * P.L + node];
-      else f[q] = inlet_feq_shift(P, q, ssj, ssk);
-    }
   }
 }
 
@@ -733,7 +672,7 @@ __global__ __launch_bounds__(256) void k_home_equilibrium(LbmDev P, const float 
 //     through the moment collision, and write the adjoint of each of the 19
 //     pulled populations to gbar [19][L] (zeros at a solid node: its stored
 //     rest state does not depend on the inputs).
-//  2. k_home_adj_gather, per node s: population p rebuilt from the moments
+//  2. k_adj_gather, per node s: population p rebuilt from the moments
 //     of s was pulled either by the node at s + c_p (the transposed
 //     streaming, same boundary rules) or, where the pull of opp(p) at s
 //     bounced back, by s itself.  T_p gathers gbar_p of the first or
@@ -930,11 +869,14 @@ __device__ __forceinline__ void pops_adj(std::integer_sequence<int, Qs...>, cons
   (home_pop_adj<Qs>(M, T[Qs], Mb), ...);
 }
 
-template <bool SOLID>
-__global__ __launch_bounds__(LBM_BLOCK) void k_home_adj_gather(LbmDev P, const float *__restrict__ min,
-                                                               const uint8_t *__restrict__ solid,
-                                                               const float *__restrict__ gbar,
-                                                               float *__restrict__ mbar) {
+// Pass 2 of both reverse steps, per node: T_p gathered as above, then for
+// HOME (bar = m_in_bar [10][L]) sum_p T_p df_p/dM taken through the Hermite
+// expansion of this node's moments, for BGK (bar = f_in_bar [19][L]) T_p
+// itself.  A solid node's state feeds no population: it adds nothing.
+template <bool SOLID, bool HOME>
+__global__ __launch_bounds__(LBM_BLOCK) void k_adj_gather(LbmDev P, const float *__restrict__ min,
+                                                          const uint8_t *__restrict__ solid,
+                                                          const float *__restrict__ gbar, float *__restrict__ bar) {
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
   __shared__ int s_any[LBM_BLOCK / 64];
   const RowBlock rb = xcd_row_block(P);
@@ -944,78 +886,92 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_adj_gather(LbmDev P, const f
   const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
   const bool any = SOLID && stage_solid(P, solid, x0, j, k, s_sol, s_any);
   if (i >= P.nx) return;
-  // a solid node's moments feed no population (every pull from it bounced)
   const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
-  const Mom own = load_mom_at(min, P.L, node);
   float T[19];
   if (any) gather_row<1>(std::make_integer_sequence<int, 19>{}, P, gbar, s_sol, i, j, k, x0, node, T);
   else gather_row<0>(std::make_integer_sequence<int, 19>{}, P, gbar, s_sol, i, j, k, x0, node, T);
-  Mom Mb{};
-  pops_adj(std::make_integer_sequence<int, 19>{}, own, T, Mb);
-  float v[HM_N] = {Mb.drho, Mb.u[0], Mb.u[1], Mb.u[2], Mb.S[0], Mb.S[1], Mb.S[2], Mb.S[3], Mb.S[4], Mb.S[5]};
+  if constexpr (HOME) {
+    const Mom own = load_mom_at(min, P.L, node);
+    Mom Mb{};
+    pops_adj(std::make_integer_sequence<int, 19>{}, own, T, Mb);
+    const float v[HM_N] = {Mb.drho, Mb.u[0], Mb.u[1], Mb.u[2], Mb.S[0], Mb.S[1], Mb.S[2], Mb.S[3], Mb.S[4], Mb.S[5]};
 #pragma unroll
-  for (int q = 0; q < HM_N; ++q) {
-    float *plane = mbar + (size_t)q * P.L;
-    st_node(plane, node, ld_node(plane, node) + (solid_node ? 0.f : v[q]));
+    for (int q = 0; q < HM_N; ++q) {
+      float *plane = bar + (size_t)q * P.L;
+      st_node(plane, node, ld_node(plane, node) + (solid_node ? 0.f : v[q]));
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      float *plane = bar + (size_t)q * P.L;
+      st_node(plane, node, ld_node(plane, node) + (solid_node ? 0.f : T[q]));
+    }
   }
 }
 
-// Reverse of k_lbm_step: recompute the pulled populations and moments, form
-// the adjoint of the pulled populations through the BGK collision, and push
-// each one back to where it was pulled from (atomics: boundary rules can
-// make two destinations share one source).
-__global__ __launch_bounds__(128) void k_lbm_step_adj(LbmDev P, const float *__restrict__ fin,
-                                                      const uint8_t *__restrict__ solid,
-                                                      const float *__restrict__ gout,
-                                                      const float *__restrict__ ubar_out,
-                                                      float *__restrict__ fin_bar) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+// Reverse of k_lbm_step, pass 1 (pass 2 is k_adj_gather): per node,
+// recompute the pulled populations and moments and write the adjoint of each
+// pulled population through the BGK collision to fbar [19][L] (zeros at a
+// solid node, whose stored rest state does not depend on the inputs).
+template <bool SOLID>
+__global__ __launch_bounds__(LBM_BLOCK) void k_lbm_adj_pull(LbmDev P, const float *__restrict__ fin,
+                                                            const uint8_t *__restrict__ solid,
+                                                            const float *__restrict__ gout,
+                                                            const float *__restrict__ ubar_out,
+                                                            float *__restrict__ fbar) {
+  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  __shared__ int s_any[LBM_BLOCK / 64];
+  __shared__ float s_inl[5];
+  const int x0 = blockIdx.x * LBM_BLOCK;
+  const int i = x0 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
+  const bool inlet_row = x0 == 0 && P.bc[0] == DW_BC_INLET;
+  if (inlet_row) stage_inlet(P, j, k, s_inl);
+  bool any = false;
+  if (SOLID) any = stage_solid(P, solid, x0, j, k, s_sol, s_any);
+  else if (inlet_row) __syncthreads();
   if (i >= P.nx) return;
-  const int64_t node = i + (int64_t)P.nx * (j + (int64_t)P.ny * k);
-  if (solid && solid[node]) return;
+  const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
+  const bool inlet_wave = inlet_row && threadIdx.x < 64;  // wave-uniform
   float f[19];
-  pull_all<2>(P, fin, solid, nullptr, i, j, k, 0, node, f);
+  if (any) pull_row<1>(std::make_integer_sequence<int, 19>{}, P, fin, s_sol, s_inl, inlet_wave, i, j, k, x0, node, f);
+  else pull_row<0>(std::make_integer_sequence<int, 19>{}, P, fin, s_sol, s_inl, inlet_wave, i, j, k, x0, node, f);
   float rho, ux, uy, uz;
   moments(P, f, rho, ux, uy, uz);
-  float uu = ux * ux + uy * uy + uz * uz;
-  float om = P.omega;
-  float kf = 1.0f - 0.5f * om;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float om = P.omega, kf = 1.0f - 0.5f * om;
   float g[19];
   float rbar = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
-    g[q] = gout[(int64_t)q * P.L + node];
-    float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+    g[q] = ld_node(gout + (size_t)q * P.L, node);
+    const float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
     // d feq_q / d rho at fixed u = feq_q / rho
     rbar += om * g[q] * LW[q] * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
     // d feq_q / d u = w rho (3 c + 9 (c.u) c - 3 u)
-    float s = om * g[q] * LW[q] * rho;
+    const float s = om * g[q] * LW[q] * rho;
     bx += s * (3.f * LC[q][0] + 9.f * cu * LC[q][0] - 3.f * ux);
     by += s * (3.f * LC[q][1] + 9.f * cu * LC[q][1] - 3.f * uy);
     bz += s * (3.f * LC[q][2] + 9.f * cu * LC[q][2] - 3.f * uz);
     if (P.forced) {
-      float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
-      float t = kf * g[q] * LW[q];
+      const float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
+      const float t = kf * g[q] * LW[q];
       bx += t * (9.f * cF * LC[q][0] - 3.f * P.F[0]);
       by += t * (9.f * cF * LC[q][1] - 3.f * P.F[1]);
       bz += t * (9.f * cF * LC[q][2] - 3.f * P.F[2]);
     }
   }
   if (ubar_out) {
-    bx += ubar_out[node];
-    by += ubar_out[P.L + node];
-    bz += ubar_out[2 * P.L + node];
+    bx += ld_node(ubar_out, node);
+    by += ld_node(ubar_out + P.L, node);
+    bz += ld_node(ubar_out + 2 * P.L, node);
   }
-  float ir = 1.0f / rho;
-  float bu = bx * ux + by * uy + bz * uz;
+  const float ir = 1.0f / rho;
+  const float bu = bx * ux + by * uy + bz * uz;
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
-    float fb = (1.f - om) * g[q] + rbar + (bx * LC[q][0] + by * LC[q][1] + bz * LC[q][2] - bu) * ir;
-    int64_t src = node;
-    int ssj, ssk;
-    int kind = pull_source(P, solid, i, j, k, q, src, ssj, ssk);
-    if (kind == SRC_NORMAL) atomicAdd(&fin_bar[(int64_t)q * P.L + src], fb);
-    else if (kind == SRC_BOUNCE) atomicAdd(&fin_bar[(int64_t)LOPP[q] * P.L + node], fb);
+    const float fb = (1.f - om) * g[q] + rbar + (bx * LC[q][0] + by * LC[q][1] + bz * LC[q][2] - bu) * ir;
+    st_node(fbar + (size_t)q * P.L, node, solid_node ? 0.f : fb);
   }
 }
 
@@ -1133,13 +1089,27 @@ extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, cons
 
 extern "C" int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
                             const uint8_t *solid, const float *f_out_bar, const float *u_out_bar, float *f_in_bar,
-                            void *stream) {
+                            float *work, void *stream) {
   LbmDev P;
   int rc = make_lbm(lat, params, &P);
   if (rc) return rc;
-  DW_REQUIRE(f_in && f_out_bar && f_in_bar, DW_EINVAL, "lbm_step_adj: f_in / f_out_bar / f_in_bar is NULL");
-  hipLaunchKernelGGL(k_lbm_step_adj, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, solid,
-                     f_out_bar, u_out_bar, f_in_bar);
+  DW_REQUIRE(f_in && f_out_bar && f_in_bar && work, DW_EINVAL,
+             "lbm_step_adj: f_in / f_out_bar / f_in_bar / work is NULL");
+  DW_REQUIRE(f_in_bar != f_in && f_in_bar != f_out_bar, DW_EINVAL, "lbm_step_adj: f_in_bar must not alias");
+  DW_REQUIRE(work != f_in && work != f_out_bar && work != f_in_bar && work != u_out_bar, DW_EINVAL,
+             "lbm_step_adj: work must not alias another argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (solid) {
+    hipLaunchKernelGGL(k_lbm_adj_pull<true>, lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, f_out_bar, u_out_bar,
+                       work);
+    hipLaunchKernelGGL((k_adj_gather<true, false>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, work,
+                       f_in_bar);
+  } else {
+    hipLaunchKernelGGL(k_lbm_adj_pull<false>, lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, f_out_bar,
+                       u_out_bar, work);
+    hipLaunchKernelGGL((k_adj_gather<false, false>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, work,
+                       f_in_bar);
+  }
   return check_launch("lbm_step_adj");
 }
 
@@ -1200,12 +1170,12 @@ extern "C" int lbm_home_step_adj(const dw_lattice *lat, const dw_lbm_params *par
   if (solid) {
     hipLaunchKernelGGL(k_home_adj_pull<true>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, m_out_bar,
                        u_out_bar, work);
-    hipLaunchKernelGGL(k_home_adj_gather<true>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
+    hipLaunchKernelGGL((k_adj_gather<true, true>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
                        m_in_bar);
   } else {
     hipLaunchKernelGGL(k_home_adj_pull<false>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, m_out_bar,
                        u_out_bar, work);
-    hipLaunchKernelGGL(k_home_adj_gather<false>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
+    hipLaunchKernelGGL((k_adj_gather<false, true>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
                        m_in_bar);
   }
   return check_launch("lbm_home_step_adj");

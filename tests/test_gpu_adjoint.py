@@ -172,19 +172,42 @@ def test_wind_to_grid_adj(scene):
     assert rel2(ub.cpu(), gu) < TOL
 
 
+LBM_ADJ_CASES = {
+    # inlet / outlet in x, bounce-back y, periodic z, gusty inflow
+    "tunnel": dict(dims=(18, 12, 10), bc=(olbm.INLET, olbm.OUTLET, olbm.BOUNCEBACK, olbm.BOUNCEBACK,
+                                          olbm.PERIODIC, olbm.PERIODIC), solid=(slice(3, 6), slice(4, 8), slice(7, 10))),
+    # solids on the faces of a periodic box: wrapped pulls from solid nodes
+    "periodic_face_solids": dict(dims=(14, 9, 8), bc=(olbm.PERIODIC,) * 6,
+                                 solid=(slice(0, 2), slice(7, 9), slice(12, 14))),
+    # solids against the outlet: clamped outlet pulls that land on solid nodes
+    "outlet_solids": dict(dims=(20, 7, 6), bc=(olbm.INLET, olbm.OUTLET) + (olbm.BOUNCEBACK,) * 4,
+                          solid=(slice(1, 4), slice(2, 5), slice(17, 20))),
+    # bounce-back on all six faces
+    "closed_box": dict(dims=(9, 8, 7), bc=(olbm.BOUNCEBACK,) * 6, solid=(slice(2, 4), slice(3, 5), slice(3, 6))),
+    # rows wider than a workgroup, outlet clamps onto periodic y rows
+    "wide_row": dict(dims=(200, 5, 4), bc=(olbm.INLET, olbm.OUTLET, olbm.PERIODIC, olbm.PERIODIC, olbm.BOUNCEBACK,
+                                           olbm.BOUNCEBACK), solid=(slice(1, 3), slice(1, 3), slice(140, 180))),
+}
+
+
 @pytest.mark.parametrize("forced", [False, True])
-def test_lbm_step_adj(forced):
-    say(f"lbm_step_adj forced={forced}")
-    nx, ny, nz = 18, 12, 10
+@pytest.mark.parametrize("case", list(LBM_ADJ_CASES))
+def test_lbm_step_adj(case, forced):
+    """The reverse BGK step against float64 autograd of the oracle step:
+    d/d f_in of <f_out_bar, f_out> + <u_bar, u_out>; bit-identical between
+    calls (no atomics)."""
+    c = LBM_ADJ_CASES[case]
+    nx, ny, nz = c["dims"]
+    say(f"lbm_step_adj {case} forced={forced}")
     rng = np.random.default_rng(11)
     rho = 1.0 + 0.01 * torch.tensor(rng.standard_normal((nz, ny, nx)))
     u = torch.tensor([0.05, 0.0, 0.0]).view(3, 1, 1, 1) + 0.02 * torch.tensor(rng.standard_normal((3, nz, ny, nx)))
     WQ = olbm.W.view(19, 1, 1, 1)
     fs = f32(olbm.equilibrium(rho.double(), u.double()) - WQ)
     solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
-    solid[3:6, 4:8, 7:10] = True
+    solid[c["solid"]] = True
     force = (2e-5, 1e-5, 0.0) if forced else (0.0, 0.0, 0.0)
-    bc = (olbm.INLET, olbm.OUTLET, olbm.BOUNCEBACK, olbm.BOUNCEBACK, olbm.PERIODIC, olbm.PERIODIC)
+    bc = c["bc"]
     op = olbm.LBMParams(tau=0.62, u_in=(0.05, 0, 0), force=force, bc=bc, gust_amp=0.05, gust_period=80.0,
                         gust_ky=1.0)
     ap = api.make_lbm_params(0.62, (0.05, 0, 0), force, bc, 0.05, 80.0, 1.0, 0.0, 0.0, t=5)
@@ -195,12 +218,19 @@ def test_lbm_step_adj(forced):
     f = (fs + WQ).clone().requires_grad_(True)
     fo, rho_o, uo = olbm.lbm_step(lat, op, f, solid, 5)
     (gf,) = torch.autograd.grad((fo * gbar).sum() + (uo * ubar).sum(), (f,))
-    fb = torch.zeros(19, L, device=DEV)
-    api.lbm_step_adj(api.make_lattice(nx, ny, nz), ap, fs.reshape(19, L).float().to(DEV).contiguous(),
-                     solid.reshape(-1).to(torch.uint8).to(DEV), gbar.reshape(19, L).float().to(DEV).contiguous(),
-                     ubar.reshape(3, L).float().to(DEV).contiguous(), fb)
+    alat = api.make_lattice(nx, ny, nz)
+    args = (fs.reshape(19, L).float().to(DEV).contiguous(), solid.reshape(-1).to(torch.uint8).to(DEV),
+            gbar.reshape(19, L).float().to(DEV).contiguous(), ubar.reshape(3, L).float().to(DEV).contiguous())
+    fb = torch.full((19, L), 0.25, device=DEV)        # accumulates onto what is there
+    work = torch.full((19, L), float("nan"), device=DEV)   # scratch: every entry is written before it is read
+    api.lbm_step_adj(alat, ap, *args, fb, work=work)
+    fb2 = torch.full((19, L), 0.25, device=DEV)
+    api.lbm_step_adj(alat, ap, *args, fb2)
     torch.cuda.synchronize()
-    assert rel2(fb.cpu(), gf.reshape(19, L)) < TOL
+    assert torch.equal(fb, fb2)
+    err = rel2(fb.cpu() - 0.25, gf.reshape(19, L))
+    say(f"  rel error {err:.2e}")
+    assert err < TOL
 
 
 def _rel_drag_inputs(sc, og, seed):

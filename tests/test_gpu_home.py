@@ -302,4 +302,4 @@ def test_home_step_adj(case):
 
     errs = (rel2(got[0], ref[0]), rel2(got[1:4], ref[1:4]), rel2(got[4:], ref[4:]))
     say(f"  rel errors (rho, u, S): {errs[0]:.2e} {errs[1]:.2e} {errs[2]:.2e}")
-    assert max(errs) < 1e-3
+    assert max(errs) < 1e-5      # measured about 1.6e-7 on every lattice
