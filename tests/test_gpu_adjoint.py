@@ -230,7 +230,7 @@ def test_lbm_step_adj(case, forced):
     assert torch.equal(fb, fb2)
     err = rel2(fb.cpu() - 0.25, gf.reshape(19, L))
     say(f"  rel error {err:.2e}")
-    assert err < TOL
+    assert err < 1e-5      # measured about 9e-8 on every lattice
 
 
 def _rel_drag_inputs(sc, og, seed):
