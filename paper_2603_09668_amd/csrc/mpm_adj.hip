@@ -178,9 +178,22 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
 #pragma unroll
       for (int q = 0; q < 9; ++q) A[q] = m * Cm[q] - ks * V0 * tau[q];
       float mom[3] = {m * P.v[p], m * P.v[n + p], m * P.v[2 * n + p]};
-      float vbar[3] = {0.f, 0.f, 0.f}, xbar[3] = {0.f, 0.f, 0.f};
-      float Abar[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       const float dx = g.dx;
+      // Per node n (offset o, weight w_n, gradient gw_n, d_n = (o - f) dx):
+      //   v_bar += m w gb,  A_bar += w gb d^T,
+      //   x_bar += gw s - w A^T gb  with s = m mb + gb . (mom + A d).
+      // Sums that factor are taken once: G = sum w gb (v_bar = m G, and the
+      // A^T term is A^T G), O = sum w gb o^T (A_bar = dx (O - G f^T)), and
+      // mom + A d = c0 + dx A o with c0 = mom - dx A f, whose y/z part is
+      // constant along a stencil row.
+      float c0[3], Ax[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        c0[a] = mom[a] - dx * (A[3 * a] * f[0] + A[3 * a + 1] * f[1] + A[3 * a + 2] * f[2]);
+        Ax[a] = dx * A[3 * a];
+      }
+      float G[3] = {0.f, 0.f, 0.f}, X[3] = {0.f, 0.f, 0.f};
+      float O[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       // rows of the stencil one at a time (bounded register use), the three
       // x-neighbours of a row read with one 12-byte load per array
 #pragma unroll 1
@@ -192,27 +205,45 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
         __builtin_memcpy(&r0, mvbar + row, sizeof(AdjRow));
         __builtin_memcpy(&r1, mvbar + N + row, sizeof(AdjRow));
         __builtin_memcpy(&r2, mvbar + 2 * N + row, sizeof(AdjRow));
-        const float wyz = w[1][oy] * w[2][oz], dwy = dw[1][oy] * w[2][oz], dwz = w[1][oy] * dw[2][oz];
+        const float wyz = w[1][oy] * w[2][oz];
+        const float gwx = wyz * g.inv_dx, gwy = dw[1][oy] * w[2][oz] * g.inv_dx,
+                    gwz = w[1][oy] * dw[2][oz] * g.inv_dx;
+        float cy[3];
 #pragma unroll
-          for (int ox = 0; ox < 3; ++ox) {
-            float wt = w[0][ox] * wyz;
-            float gw[3] = {dw[0][ox] * wyz * g.inv_dx, w[0][ox] * dwy * g.inv_dx, w[0][ox] * dwz * g.inv_dx};
-            float d[3] = {((float)ox - f[0]) * dx, ((float)oy - f[1]) * dx, ((float)oz - f[2]) * dx};
-            float mb = rm.v[ox];
-            float gb[3] = {r0.v[ox], r1.v[ox], r2.v[ox]};
-            float c[3];
+        for (int a = 0; a < 3; ++a) cy[a] = c0[a] + dx * (A[3 * a + 1] * (float)oy + A[3 * a + 2] * (float)oz);
+        float RG[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-            for (int a = 0; a < 3; ++a) c[a] = mom[a] + A[3 * a] * d[0] + A[3 * a + 1] * d[1] + A[3 * a + 2] * d[2];
-            float s = m * mb + gb[0] * c[0] + gb[1] * c[1] + gb[2] * c[2];
+        for (int ox = 0; ox < 3; ++ox) {
+          const float wt = w[0][ox] * wyz;
+          const float gb[3] = {r0.v[ox], r1.v[ox], r2.v[ox]};
+          float s = m * rm.v[ox];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              vbar[a] += wt * m * gb[a];
-              // d (A d) / d x = -A   ->   -w A^T gb
-              xbar[a] += gw[a] * s - wt * (A[a] * gb[0] + A[3 + a] * gb[1] + A[6 + a] * gb[2]);
+          for (int a = 0; a < 3; ++a) s += gb[a] * (cy[a] + Ax[a] * (float)ox);
+          X[0] += dw[0][ox] * gwx * s;
+          X[1] += w[0][ox] * gwy * s;
+          X[2] += w[0][ox] * gwz * s;
 #pragma unroll
-              for (int b = 0; b < 3; ++b) Abar[3 * a + b] += wt * gb[a] * d[b];
-            }
+          for (int a = 0; a < 3; ++a) {
+            const float t = wt * gb[a];
+            RG[a] += t;
+            O[3 * a] += (float)ox * t;
           }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          G[a] += RG[a];
+          O[3 * a + 1] += (float)oy * RG[a];
+          O[3 * a + 2] += (float)oz * RG[a];
+        }
+      }
+      float vbar[3], xbar[3], Abar[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        vbar[a] = m * G[a];
+        // d (A d) / d x = -A   ->   -A^T G
+        xbar[a] = X[a] - (A[a] * G[0] + A[3 + a] * G[1] + A[6 + a] * G[2]);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Abar[3 * a + b] = dx * (O[3 * a + b] - G[a] * f[b]);
       }
       if (P.vb) {
 #pragma unroll
