@@ -510,7 +510,7 @@ def workspace_views(grid: Grid, n: int, ws: torch.Tensor) -> dict:
     keys and the permutation.  For inspection and tests."""
     tile = 4
     T = (-(-grid.nx // tile)) * (-(-grid.ny // tile)) * (-(-grid.nz // tile))
-    NB = -(-T // 1024)
+    NB = -(-T // 512)
     off = 0
     views = {}
 

@@ -73,7 +73,7 @@ struct Workspace {
   size_t bytes;
 };
 
-constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_BLOCK = 512;
 constexpr int WORK_CHUNK = 512;  // particles per scatter work item
 
 size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base, int deterministic = 0);

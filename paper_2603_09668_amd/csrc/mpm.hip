@@ -88,7 +88,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-// Block-wide exclusive scans of the four tile rows at once (1024-thread
+// Block-wide exclusive scans of the four tile rows at once (SCAN_BLOCK-thread
 // block, two barriers in all): ex[r] = sum of v[r] over the threads before
 // this one, tot[r] = the block's total.
 constexpr int SCAN_WAVES = SCAN_BLOCK / 64;
