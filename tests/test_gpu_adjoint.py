@@ -305,3 +305,33 @@ def test_grid_update_relative_drag(scene):
     # wind_to_grid has no node velocity and refuses the relative drag
     with pytest.raises(api.DiffWindError):
         api.wind_to_grid(g, wind, torch.empty(3, N, device=DEV))
+
+
+def test_lbm_reverse_work_checks():
+    """The reverse LBM steps reject aliased outputs and work buffers of the
+    wrong shape before launching anything; valid calls on the same buffers
+    run."""
+    nx, ny, nz = 8, 6, 5
+    L = nx * ny * nz
+    lat = api.make_lattice(nx, ny, nz)
+    ap = api.make_lbm_params(0.7, (0.05, 0.0, 0.0), (0.0, 0.0, 0.0), (olbm.PERIODIC,) * 6, 0.0, 1.0, 0.0, 0.0, 0.0)
+    f = torch.zeros(19, L, device=DEV)
+    gb = torch.zeros_like(f)
+    fb = torch.zeros_like(f)
+    with pytest.raises(api.DiffWindError):
+        api.lbm_step_adj(lat, ap, f, None, gb, None, fb, work=fb)
+    with pytest.raises(ValueError):
+        api.lbm_step_adj(lat, ap, f, None, gb, None, fb, work=torch.zeros(10, L, device=DEV))
+    m = torch.zeros(10, L, device=DEV)
+    mbar = torch.zeros_like(m)
+    mib = torch.zeros_like(m)
+    work = torch.zeros(19, L, device=DEV)
+    with pytest.raises(api.DiffWindError):
+        api.lbm_home_step_adj(lat, ap, m, None, mbar, None, m, work=work)   # m_in_bar aliases m_in
+    with pytest.raises(ValueError):
+        api.lbm_home_step_adj(lat, ap, m, None, mbar, None, mib, work=torch.zeros(10, L, device=DEV))
+    # a valid call on the same buffers runs (zero adjoints stay zero)
+    api.lbm_home_step_adj(lat, ap, m, None, mbar, None, mib, work=work)
+    api.lbm_step_adj(lat, ap, f, None, gb, None, fb, work=work)
+    torch.cuda.synchronize()
+    assert mib.abs().max().item() == 0.0 and fb.abs().max().item() == 0.0
