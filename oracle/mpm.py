@@ -32,7 +32,13 @@ particles, P(R) = 0 for rotations, P against a central finite difference of
 psi, tau symmetric, exact mass / linear / angular momentum conservation in
 P2G and G2P, affine-field reproduction in G2P, rest-state invariance
 (bit-exact), free flight and uniform translation, and autograd against
-central finite differences.
+central finite differences.  The elastic force is pinned separately
+(tests/test_oracle_stress_pins.py): the stress part of P2G's momentum equals
+minus the gradient, by central differences, of the total energy
+sum_p V0_p psi after a G2P deformation update driven by the grid velocities
+(sign, 4/dx^2, V0, dt and tau = P F^T); the small-strain limit
+P(I + e) = 2 mu sym(e) + lam tr(e) I of both models; and uniaxial stress
+E e under the strain (e, -nu e, -nu e), which is what E and nu mean.
 """
 from __future__ import annotations
 
