@@ -162,9 +162,7 @@ def _recon_leg(n, res, frames, sub, iters):
     amp = 200.0
     F_gt = recon.drag_field(guide, amp)
     rc = recon.Reconstructor(sc, nw, lo, hi, substeps_per_frame=sub)
-    x0 = torch.tensor(sc.x.T.copy(), dtype=torch.float32, device=dev).contiguous()
-    z3, z9 = torch.zeros(3, sc.n, device=dev), torch.zeros(9, sc.n, device=dev)
-    state0 = (x0, z3, z9, z9.clone())
+    state0 = rc.initial_state()  # positions as displacements from the scene's positions
     targets, st = [], state0
     for _ in range(frames):
         st = rc.advance(st, F_gt)
@@ -282,12 +280,14 @@ def _adjoint_leg(n, res, n_sub, ckpt, n_fd):
     K, nw = 8, 16
     plan = RolloutPlan(sc.grid, sc.n, mass, vol0, region, nu, pin, sc.dt, sc.gravity, sc.material, sc.bound,
                        (nw,) * 3, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), K, n_sub, ckpt, device=dev)
-    # particles in the sort's order (memory layout only)
+    # particles in the sort's order (memory layout only); positions as
+    # displacements from the scene's positions
     api.mpm_sort(plan.grid, plan.prm, x0, plan.ws)
-    pa = api.mpm_reorder(plan.grid, api.ParticleArrays(x0, torch.zeros(3, sc.n, **f32), torch.zeros(9, sc.n, **f32),
-                                                       torch.zeros(9, sc.n, **f32), mass, vol0, region, E0, nu),
+    pa = api.mpm_reorder(plan.grid, api.ParticleArrays(torch.zeros(3, sc.n, **f32), torch.zeros(3, sc.n, **f32),
+                                                       torch.zeros(9, sc.n, **f32), torch.zeros(9, sc.n, **f32),
+                                                       mass, vol0, region, E0, nu, xref=x0),
                          plan.ws)
-    plan.mass, plan.vol0, plan.region = pa.mass, pa.vol0, pa.region
+    plan.mass, plan.vol0, plan.region, plan.xref = pa.mass, pa.vol0, pa.region, pa.xref
     x0 = pa.x
     z3, z9 = torch.zeros(3, sc.n, **f32), torch.zeros(9, sc.n, **f32)
     amp = 200.0

@@ -29,6 +29,16 @@
  *    holds H = F - I (rest state all zeros), so float32 keeps its relative
  *    resolution on small strains; stresses are evaluated from H without
  *    forming differences of numbers close to one.
+ *  - Positions are absolute (dw_particles.xref == NULL: x holds them) or
+ *    relative to a fixed per-particle reference (xref != NULL: the position
+ *    is xref + x, and x holds the displacement from xref, zero at the start
+ *    of a run).  The reference keeps float32 resolution on the motion
+ *    itself: an absolute float32 position near 0.5 resolves 6e-8 while a
+ *    substep moves it ~1e-6, so over 100 substeps the rounding of stored
+ *    absolute positions reaches ~1 % of the displacement; a displacement is
+ *    rounded relative to its own size.  Kernels form the grid coordinate as
+ *    (xref - origin)/dx + x/dx with each part rounded once, G2P writes the
+ *    new displacement x + dt v and never writes xref.
  *  - LBM populations are stored shifted by their lattice weight, f_i - w_i
  *    (rest fluid is all zeros); this keeps float32 resolution on the small
  *    deviations from rest.  Direction order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
@@ -110,12 +120,14 @@ typedef struct {
  * and Poisson ratio nu (Lame parameters by Eq. young_poisson). */
 typedef struct {
   int n;
-  float *x, *v, *C, *F;   /* [3][n], [3][n], [9][n], [9][n]; F holds F - I */
+  float *x, *v, *C, *F;   /* [3][n], [3][n], [9][n], [9][n]; F holds F - I;
+                             x holds the displacement from xref when xref is set */
   const float *mass;      /* [n] */
   const float *vol0;      /* [n] */
   const int32_t *region;  /* [n], values in [0, n_regions) */
   const float *E, *nu;    /* [n_regions] */
   int n_regions;
+  const float *xref;      /* [3][n] position reference, or NULL (x absolute) */
 } dw_particles;
 
 /* Adjoint particle state: same layout as dw_particles' x, v, C, F. */
@@ -188,8 +200,9 @@ size_t mpm_workspace_bytes(const dw_grid *grid, int n_max, int deterministic);
  * grouping particles by tile (order inside a tile unspecified unless
  * params->deterministic), per-tile ranges, the active cell tiles, and the
  * active node tiles (4x4x4 node blocks holding a node of some particle's
- * stencil).  Clears the status word.  x: [3][n]. */
-int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const float *x, int n,
+ * stencil).  Clears the status word.  x: [3][n]; xref: [3][n] position
+ * reference (positions xref + x) or NULL (x absolute). */
+int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const float *x, const float *xref, int n,
              void *ws, size_t ws_bytes, void *stream);
 
 /* P2G, Eq. P2G with the MLS-MPM stress term:
@@ -218,14 +231,17 @@ int mpm_grid_update(const dw_grid *grid, const dw_mpm_params *params, const floa
  *   v_p = sum_i w_ip v_i,  C_p = (4/dx^2) sum_i w_ip v_i (x_i - x_p)^T,
  *   x_p += dt v_p,  F_p <- (I + dt C_p) F_p   (weights at the old x_p;
  *   stored as H <- H + dt C (I + H)).
- * Reads in->x, in->F; writes out->x, v, C, F.  `in` and `out` may alias. */
+ * Reads in->x, in->F (and in->xref: with a reference, in->x and out->x are
+ * displacements from it; out->xref is not used); writes out->x, v, C, F.
+ * `in` and `out` may alias. */
 int mpm_g2p(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
             const dw_particles *in, dw_particles *out, void *stream);
 
 /* Memory layout, not physics: writes the particles in the order of the
  * permutation that the last mpm_sort() left in `ws` (grouped by 4x4x4 cell
  * tile), out->a[i] = in->a[perm[i]] for x, v, C, F, mass, vol0 and region
- * (in->n entries; E and nu are per region and not touched).  Keeping the
+ * (in->n entries; E and nu are per region and not touched; xref too when
+ * in->xref is set, into out->xref, which must then be set).  Keeping the
  * arrays in this order lets P2G and G2P read particles of a tile from
  * neighbouring memory; particles move little per substep, so a reorder now
  * and then keeps it so.  perm_out [n] (NULL to skip) receives perm, i.e. the
@@ -242,7 +258,8 @@ int wind_to_grid(const dw_grid *grid, const dw_wind *wind, float *acc, void *str
 
 /* Reverse of mpm_p2g, a gather per particle: given m_bar [N] and mv_bar [3][N]
  * (read at stencil nodes), accumulates into bar->x, v, C, F and E_bar
- * [n_regions] (NULL to skip).  Mass and volume are constants. */
+ * [n_regions] (NULL to skip).  Mass and volume are constants; so is p->xref
+ * (bar->x is the adjoint of the position, i.e. of the displacement x). */
 int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p,
                 const float *grid_m_bar, const float *grid_mv_bar, dw_particles_bar *bar,
                 float *E_bar, void *stream);
@@ -260,7 +277,7 @@ int mpm_grid_update_adj(const dw_grid *grid, const dw_mpm_params *params, const 
                         float *acc_bar, const void *ws, size_t ws_bytes, void *stream);
 
 /* Reverse of mpm_g2p, a sorted scatter: reads the forward inputs in->x,
- * in->F and grid_v, the output adjoints out_bar (x, v, C, F; any may be
+ * in->xref, in->F and grid_v, the output adjoints out_bar (x, v, C, F; any may be
  * NULL = zero); accumulates into in_bar->x, in_bar->F and grid_v_bar [3][N].
  * Uses the sort in `ws`, which must come from mpm_sort on the same in->x. */
 int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
@@ -397,8 +414,10 @@ int lbm_home_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, con
 
 /* Eq. point2voxel: solid[floor((x_p - origin)/dx)] = 1 for every particle
  * inside the lattice.  accumulate = 0 clears solid [L] (uint8) first,
- * 1 ORs into it (static obstacles). */
-int lbm_solid_from_particles(const dw_lattice *lat, const float *x, int n, uint8_t *solid,
+ * 1 ORs into it (static obstacles).  x [3][n]; xref [3][n] or NULL as in
+ * mpm_sort (with a reference the index is floor((xref - origin)/dx + x/dx),
+ * each part rounded once). */
+int lbm_solid_from_particles(const dw_lattice *lat, const float *x, const float *xref, int n, uint8_t *solid,
                              int accumulate, void *stream);
 
 /* ------------------------------------------------------ wind surrogate */

@@ -206,16 +206,23 @@ def lbm_step(lat: Lattice, p: LBMParams, f_in, solid=None, t: int = 0):
     return f_out, rho, u
 
 
-def voxelize(lat: Lattice, x):
+def voxelize(lat: Lattice, x, x_ref=None):
     """Eq. point2voxel: node x_w is solid iff some particle satisfies
     0 <= x_p,d - x_w,d < dx on every axis, i.e. sits in the cell
     [x_w, x_w + dx); index floor((x_p - origin) / dx), ignored off-lattice.
     The index is computed in the precision of ``x`` (float32 input gives the
-    float32 decision)."""
+    float32 decision).  With ``x_ref`` the position is x_ref + x (x the
+    displacement) and the cell coordinate is taken in two parts,
+    (x_ref - origin) / dx + x / dx, each rounded in that precision."""
     nx, ny, nz = lat.dims
     solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
     o = torch.tensor(lat.origin, dtype=x.dtype)
-    idx = torch.floor((x - o) / torch.tensor(lat.dx, dtype=x.dtype)).to(torch.int64)
+    h = torch.tensor(lat.dx, dtype=x.dtype)
+    if x_ref is None:
+        q = (x - o) / h
+    else:
+        q = (x_ref.to(x.dtype) - o) / h + x / h
+    idx = torch.floor(q).to(torch.int64)
     ok = ((idx >= 0) & (idx < torch.tensor([nx, ny, nz]))).all(dim=1)
     idx = idx[ok]
     solid[idx[:, 2], idx[:, 1], idx[:, 0]] = True

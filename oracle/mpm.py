@@ -302,15 +302,20 @@ def substep(grid: Grid, state: dict, mass, vol0, mu_p, lam_p, dt: float, materia
 TILE = 4
 
 
-def stencil_base_f32(x32, grid: Grid):
+def stencil_base_f32(x32, grid: Grid, xref32=None):
     """Stencil base cell decided in float32 the way a float32 implementation
     decides it: X = (x - origin) * fl32(1/dx), base = floor(X - 1/2), each
-    operation rounded to float32.  Used where the integer decision has to be
-    taken in the kernel's precision."""
+    operation rounded to float32.  With a position reference (the position
+    is xref + x, x the displacement) the coordinate is taken in two parts,
+    X = fl32((xref - origin) * inv) + fl32(x * inv), rounded once more.  Used
+    where the integer decision has to be taken in the kernel's precision."""
     x32 = x32.to(torch.float32)
     o = torch.tensor(grid.origin, dtype=torch.float32)
     inv = torch.tensor(1.0 / grid.dx, dtype=torch.float32)
-    X = (x32 - o) * inv
+    if xref32 is None:
+        X = (x32 - o) * inv
+    else:
+        X = (xref32.to(torch.float32) - o) * inv + x32 * inv
     return torch.floor(X - torch.tensor(0.5, dtype=torch.float32)).to(torch.int64)
 
 

@@ -55,7 +55,7 @@ class MPMParams(ctypes.Structure):
 class Particles(ctypes.Structure):
     _fields_ = [("n", c_int), ("x", c_void_p), ("v", c_void_p), ("C", c_void_p), ("F", c_void_p),
                 ("mass", c_void_p), ("vol0", c_void_p), ("region", c_void_p), ("E", c_void_p),
-                ("nu", c_void_p), ("n_regions", c_int)]
+                ("nu", c_void_p), ("n_regions", c_int), ("xref", c_void_p)]
 
 
 class ParticlesBar(ctypes.Structure):
@@ -91,7 +91,7 @@ def lib():
     sig = {
         "dw_last_error": ([], ctypes.c_char_p),
         "mpm_workspace_bytes": ([POINTER(Grid), c_int, c_int], c_size_t),
-        "mpm_sort": ([POINTER(Grid), POINTER(MPMParams), P, c_int, P, c_size_t, P], c_int),
+        "mpm_sort": ([POINTER(Grid), POINTER(MPMParams), P, P, c_int, P, c_size_t, P], c_int),
         "mpm_p2g": ([POINTER(Grid), POINTER(MPMParams), POINTER(Particles), P, P, P, c_size_t, P], c_int),
         "mpm_grid_update": ([POINTER(Grid), POINTER(MPMParams), P, P, POINTER(Wind), P, P, P, c_size_t, P],
                             c_int),
@@ -111,7 +111,7 @@ def lib():
         "lbm_home_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_home_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P, P], c_int),
         "lbm_home_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
-        "lbm_solid_from_particles": ([POINTER(Lattice), P, c_int, P, c_int, P], c_int),
+        "lbm_solid_from_particles": ([POINTER(Lattice), P, P, c_int, P, c_int, P], c_int),
         "gaussian_covariance": ([c_int, P, P, P, P], c_int),
         "gaussian_covariance_adj": ([c_int, P, P, P, P, P, P], c_int),
         "phys_loss": ([c_int, P, P, c_float, P, P, P], c_int),
@@ -228,7 +228,8 @@ def wind_acc(acc) -> Wind:
 
 @dataclass
 class ParticleArrays:
-    """Device particle state in the header's layout."""
+    """Device particle state in the header's layout.  With `xref` set the
+    positions are xref + x and `x` holds the displacement from xref."""
 
     x: torch.Tensor      # (3, n)
     v: torch.Tensor      # (3, n)
@@ -239,19 +240,26 @@ class ParticleArrays:
     region: torch.Tensor  # (n,) int32
     E: torch.Tensor      # (R,)
     nu: torch.Tensor     # (R,)
+    xref: torch.Tensor | None = None  # (3, n) position reference, or None
 
     @property
     def n(self):
         return self.x.shape[1]
 
+    def positions(self):
+        """Absolute positions (3, n) as float64 (xref + x is exact there)."""
+        if self.xref is None:
+            return self.x.double()
+        return self.xref.double() + self.x.double()
+
     def struct(self) -> Particles:
         return Particles(self.n, _ptr(self.x, name="x"), _ptr(self.v, name="v"), _ptr(self.C, name="C"),
                          _ptr(self.F, name="F"), _ptr(self.mass, name="mass"), _ptr(self.vol0, name="vol0"),
                          _ptr(self.region, torch.int32, "region"), _ptr(self.E, name="E"),
-                         _ptr(self.nu, name="nu"), int(self.E.numel()))
+                         _ptr(self.nu, name="nu"), int(self.E.numel()), _ptr(self.xref, name="xref"))
 
     def with_state(self, x, v, C, F) -> "ParticleArrays":
-        return ParticleArrays(x, v, C, F, self.mass, self.vol0, self.region, self.E, self.nu)
+        return ParticleArrays(x, v, C, F, self.mass, self.vol0, self.region, self.E, self.nu, self.xref)
 
 
 def _bar_struct(n, x=None, v=None, C=None, F=None) -> ParticlesBar:
@@ -282,15 +290,19 @@ def read_status(ws: torch.Tensor) -> int:
     return int(ws[:4].view(torch.int32).item())
 
 
-def mpm_sort(grid: Grid, params: MPMParams, x, ws):
-    _check(lib().mpm_sort(ctypes.byref(grid), ctypes.byref(params), _ptr(x, name="x"), int(x.shape[1]),
-                          _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()), "mpm_sort")
+def mpm_sort(grid: Grid, params: MPMParams, x, ws, xref=None):
+    """x (3, n): positions, or displacements from xref (3, n) when given."""
+    if xref is not None:
+        _shape(xref, tuple(x.shape), "xref")
+    _check(lib().mpm_sort(ctypes.byref(grid), ctypes.byref(params), _ptr(x, name="x"), _ptr(xref, name="xref"),
+                          int(x.shape[1]), _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()), "mpm_sort")
 
 
 def mpm_reorder(grid: Grid, p: ParticleArrays, ws, perm_out=None) -> ParticleArrays:
     """New particle arrays in the order of the last mpm_sort (see the header)."""
     out = ParticleArrays(torch.empty_like(p.x), torch.empty_like(p.v), torch.empty_like(p.C), torch.empty_like(p.F),
-                         torch.empty_like(p.mass), torch.empty_like(p.vol0), torch.empty_like(p.region), p.E, p.nu)
+                         torch.empty_like(p.mass), torch.empty_like(p.vol0), torch.empty_like(p.region), p.E, p.nu,
+                         None if p.xref is None else torch.empty_like(p.xref))
     pi, po = p.struct(), out.struct()
     _check(lib().mpm_reorder(ctypes.byref(grid), ctypes.byref(pi), ctypes.byref(po),
                              _ptr(perm_out, torch.int32, "perm_out"), _ptr(ws, torch.uint8, "ws"), ws.numel(),
@@ -314,7 +326,8 @@ def mpm_grid_update(grid: Grid, params: MPMParams, grid_m, grid_mv, wind: Wind |
 
 def mpm_g2p(grid: Grid, params: MPMParams, grid_v, p_in: ParticleArrays, x_out, v_out, C_out, F_out):
     n = p_in.n
-    pin = Particles(n, _ptr(p_in.x, name="x"), None, None, _ptr(p_in.F, name="F"), None, None, None, None, None, 0)
+    pin = Particles(n, _ptr(p_in.x, name="x"), None, None, _ptr(p_in.F, name="F"), None, None, None, None, None, 0,
+                    _ptr(p_in.xref, name="xref"))
     pout = Particles(n, _ptr(x_out, name="x_out"), _ptr(v_out, name="v_out"), _ptr(C_out, name="C_out"),
                      _ptr(F_out, name="F_out"), None, None, None, None, None, 0)
     _check(lib().mpm_g2p(ctypes.byref(grid), ctypes.byref(params), _ptr(grid_v, name="grid_v"), ctypes.byref(pin),
@@ -348,7 +361,8 @@ def mpm_grid_update_adj(grid: Grid, params: MPMParams, grid_m, grid_mv, wind: Wi
 def mpm_g2p_adj(grid: Grid, params: MPMParams, grid_v, p_in: ParticleArrays, x_out_bar=None, v_out_bar=None,
                 C_out_bar=None, F_out_bar=None, x_bar=None, F_bar=None, grid_v_bar=None, ws=None):
     n = p_in.n
-    pin = Particles(n, _ptr(p_in.x, name="x"), None, None, _ptr(p_in.F, name="F"), None, None, None, None, None, 0)
+    pin = Particles(n, _ptr(p_in.x, name="x"), None, None, _ptr(p_in.F, name="F"), None, None, None, None, None, 0,
+                    _ptr(p_in.xref, name="xref"))
     ob = _bar_struct(n, x_out_bar, v_out_bar, C_out_bar, F_out_bar)
     ib = _bar_struct(n, x_bar, None, None, F_bar)
     _check(lib().mpm_g2p_adj(ctypes.byref(grid), ctypes.byref(params), _ptr(grid_v, name="grid_v"),
@@ -495,10 +509,13 @@ def lbm_home_equilibrium(lat: Lattice, params: LBMParams, m, rho=None, u=None):
                                       _ptr(u, name="u"), _ptr(m, name="m"), _stream()), "lbm_home_equilibrium")
 
 
-def lbm_solid_from_particles(lat: Lattice, x, solid, accumulate=False):
-    _check(lib().lbm_solid_from_particles(ctypes.byref(lat), _ptr(x, name="x"), int(x.shape[1]),
-                                          _ptr(solid, torch.uint8, "solid"), int(bool(accumulate)), _stream()),
-           "lbm_solid_from_particles")
+def lbm_solid_from_particles(lat: Lattice, x, solid, accumulate=False, xref=None):
+    """x (3, n): positions, or displacements from xref (3, n) when given."""
+    if xref is not None:
+        _shape(xref, tuple(x.shape), "xref")
+    _check(lib().lbm_solid_from_particles(ctypes.byref(lat), _ptr(x, name="x"), _ptr(xref, name="xref"),
+                                          int(x.shape[1]), _ptr(solid, torch.uint8, "solid"),
+                                          int(bool(accumulate)), _stream()), "lbm_solid_from_particles")
 
 
 WORK_CHUNK = 512  # particles per scatter work item (the library's constant)

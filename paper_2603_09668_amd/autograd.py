@@ -16,6 +16,16 @@ G2P adjoint (sorted scatter into the grid adjoint), grid-update adjoint, wind
 transpose into W_bar, P2G adjoint (per-particle gather, also giving E_bar).
 Every step runs in the library's HIP kernels; torch provides device memory,
 zero-fills (one per buffer group) and the final loss.
+
+With `xref` the positions are xref + x: the rollout's x input and output are
+displacements from that fixed reference (see the header), which keeps their
+float32 resolution on the motion.
+
+A particle whose stencil leaves the grid is skipped by the kernels and
+flagged in the workspace status word (as are non-finite positions); the
+status of every forward and recomputed substep is OR-ed on the device and
+checked once per forward and once per backward, and a flagged rollout
+raises instead of returning a truncated gradient.
 """
 from __future__ import annotations
 
@@ -28,12 +38,14 @@ class RolloutPlan:
     """Device buffers and constants for rollouts of one particle set on one grid."""
 
     def __init__(self, grid: dict, n: int, mass, vol0, region, nu, pin, dt: float, gravity, material: int,
-                 bound: int, nw, box_lo, box_hi, K: int, n_sub: int, ckpt: int = 16, device="cuda"):
+                 bound: int, nw, box_lo, box_hi, K: int, n_sub: int, ckpt: int = 16, device="cuda",
+                 xref=None):
         self.grid = api.make_grid(grid["nx"], grid["ny"], grid["nz"], grid["dx"], grid["origin"])
         self.N = grid["nx"] * grid["ny"] * grid["nz"]
         self.n = n
         self.mass, self.vol0, self.region, self.nu = mass, vol0, region, nu
         self.pin = pin
+        self.xref = xref
         self.prm = api.make_mpm_params(dt, gravity, bound, material)
         self.nw, self.box_lo, self.box_hi, self.K = tuple(nw), tuple(box_lo), tuple(box_hi), K
         self.n_sub, self.ckpt = n_sub, ckpt
@@ -48,6 +60,7 @@ class RolloutPlan:
         self.gvb, self.gmb, self.gmvb, self.accb = (self._gbar[0:3], self._gbar[3], self._gbar[4:7],
                                                     self._gbar[7:10])
         self._seg = None  # per-substep workspaces and grids of a segment, made on first backward
+        self._status = torch.zeros(1, dtype=torch.int32, device=device)  # OR of the substeps' status words
 
     def segment_buffers(self):
         """Sort workspaces and grids (m, mv, v) for the substeps of one segment."""
@@ -61,7 +74,17 @@ class RolloutPlan:
         return s * self.K // self.n_sub
 
     def particles(self, x, v, C, H, E):
-        return api.ParticleArrays(x, v, C, H, self.mass, self.vol0, self.region, E, self.nu)
+        return api.ParticleArrays(x, v, C, H, self.mass, self.vol0, self.region, E, self.nu, self.xref)
+
+    def check_status(self, what: str):
+        """Raise if a substep since the last check met a particle outside the
+        grid or a non-finite position (one host synchronisation)."""
+        st = int(self._status.item())
+        self._status.zero_()
+        bad = st & (api.STATUS_OUT_OF_GRID | api.STATUS_NONFINITE)
+        if bad:
+            raise api.DiffWindError(f"rollout {what}: status {st:#x} (a particle left the grid or is not finite); "
+                                    "the kernels skipped it, so the result would be truncated")
 
     def wind(self, W, s):
         return api.wind_force_grid(W[self.slot(s)], self.nw, self.box_lo, self.box_hi)
@@ -71,8 +94,9 @@ class RolloutPlan:
         """One substep; in place unless `out` = (x, v, C, H) buffers are given.
         `bufs` = (workspace, m, mv, v) keeps this substep's sort and grid."""
         ws, gm, gmv, gv = bufs if bufs is not None else (self.ws, self.gm, self.gmv, self.gv)
-        api.mpm_sort(self.grid, self.prm, p.x, ws)
+        api.mpm_sort(self.grid, self.prm, p.x, ws, xref=self.xref)
         api.mpm_p2g(self.grid, self.prm, p, gm, gmv, ws)
+        self._status.bitwise_or_(ws[:4].view(torch.int32))
         api.mpm_grid_update(self.grid, self.prm, gm, gmv, self.wind(W, s), self.pin, gv, ws)
         if not g2p:
             return None
@@ -113,6 +137,7 @@ class _RolloutFn(torch.autograd.Function):
             if s % plan.ckpt == 0:
                 ckpts.append([t.clone() for t in state])
             plan.substep(plan.particles(*state, E), W, s)
+        plan.check_status("forward")
         ctx.plan = plan
         ctx.ckpts = ckpts
         ctx.save_for_backward(W, E)
@@ -155,10 +180,13 @@ class _RolloutFn(torch.autograd.Function):
                                      bufs=seg_bufs[s - s0])
                 bar = nxt_group
                 cur = 1 - cur
+        plan.check_status("backward")
         return (None, W_bar, E_bar, *[b.clone() for b in bar])
 
 
 def rollout(plan: RolloutPlan, W, E, x0, v0, C0, H0):
     """Differentiable n-substep rollout: returns the final (x, v, C, H), with
-    gradients flowing to W (K, 3, nw^3), E (n_regions,) and the initial state."""
+    gradients flowing to W (K, 3, nw^3), E (n_regions,) and the initial state.
+    With plan.xref set, x0 and the returned x are displacements from it.
+    Raises DiffWindError if a particle left the grid."""
     return _RolloutFn.apply(plan, W, E, x0, v0, C0, H0)

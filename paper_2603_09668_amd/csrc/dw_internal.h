@@ -321,6 +321,46 @@ __device__ __forceinline__ int base_of(float X) {
   return (int)floorf(X - 0.5f);
 }
 
+// Grid coordinate of a particle on one axis, kept as two parts A + B.
+// Absolute positions (no reference array): A = (x - o) / dx, B = 0.
+// Positions relative to a per-particle reference xr (the position is
+// xr + x): A = (xr - o) / dx and B = x / dx, the displacement scaled on its
+// own so that it keeps its float32 resolution.  Each difference and product
+// is rounded once (contraction off), the same way in every kernel.  The
+// stencil base is base_of(A + B); the fractional position (A - base) + B,
+// where A - base is exact.  With B = 0 both reduce to the absolute forms.
+struct Coord {
+  float A, B;
+};
+
+__device__ __forceinline__ Coord make_coord(bool ref, float xr, float x, float o, float inv_dx) {
+#pragma clang fp contract(off)
+  Coord c;
+  if (ref) {
+    c.A = (xr - o) * inv_dx;
+    c.B = x * inv_dx;
+  } else {
+    c.A = (x - o) * inv_dx;
+    c.B = 0.f;
+  }
+  return c;
+}
+
+// element idx of the position arrays (xr may be NULL: absolute positions)
+__device__ __forceinline__ Coord load_coord(const float *xr, const float *x, size_t idx, float o, float inv_dx) {
+  return make_coord(xr != nullptr, xr ? xr[idx] : 0.f, x[idx], o, inv_dx);
+}
+
+__device__ __forceinline__ float coord_sum(Coord c) {
+#pragma clang fp contract(off)
+  return c.A + c.B;
+}
+
+__device__ __forceinline__ float coord_frac(Coord c, int base) {
+#pragma clang fp contract(off)
+  return (c.A - (float)base) + c.B;
+}
+
 // Quadratic B-spline weights of nodes base + 0, 1, 2 at fractional position
 // f = X - base in [1/2, 3/2), and their derivatives d w / d f.
 __device__ __forceinline__ void bspline_w(float f, float w[3]) {

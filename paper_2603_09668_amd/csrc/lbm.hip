@@ -992,17 +992,22 @@ __global__ __launch_bounds__(256) void k_lbm_equilibrium(LbmDev P, const float *
   }
 }
 
+// lattice cell coordinate (x - o) / dx, or (xr - o) / dx + x / dx with a
+// position reference, each part rounded once
+__device__ __forceinline__ float voxel_coord(const float *xr, const float *x, size_t i, float o, float dx) {
+#pragma clang fp contract(off)
+  if (xr) return (xr[i] - o) / dx + x[i] / dx;
+  return (x[i] - o) / dx;
+}
+
 __global__ void k_voxelize(int nx, int ny, int nz, float ox, float oy, float oz, float dx,
-                           const float *__restrict__ x, int n, uint8_t *__restrict__ solid) {
+                           const float *__restrict__ x, const float *__restrict__ xr, int n,
+                           uint8_t *__restrict__ solid) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  float qx, qy, qz;
-  {
-#pragma clang fp contract(off)
-    qx = floorf((x[p] - ox) / dx);
-    qy = floorf((x[n + p] - oy) / dx);
-    qz = floorf((x[2 * n + p] - oz) / dx);
-  }
+  const float qx = floorf(voxel_coord(xr, x, p, ox, dx));
+  const float qy = floorf(voxel_coord(xr, x, (size_t)n + p, oy, dx));
+  const float qz = floorf(voxel_coord(xr, x, 2 * (size_t)n + p, oz, dx));
   // NaN fails every comparison and is dropped here
   if (!(qx >= 0.f && qy >= 0.f && qz >= 0.f && qx < (float)nx && qy < (float)ny && qz < (float)nz)) return;
   int64_t idx = (int64_t)qx + (int64_t)nx * ((int64_t)qy + (int64_t)ny * (int64_t)qz);
@@ -1181,8 +1186,8 @@ extern "C" int lbm_home_step_adj(const dw_lattice *lat, const dw_lbm_params *par
   return check_launch("lbm_home_step_adj");
 }
 
-extern "C" int lbm_solid_from_particles(const dw_lattice *lat, const float *x, int n, uint8_t *solid,
-                                        int accumulate, void *stream) {
+extern "C" int lbm_solid_from_particles(const dw_lattice *lat, const float *x, const float *xref, int n,
+                                        uint8_t *solid, int accumulate, void *stream) {
   DW_REQUIRE(lat && solid, DW_EINVAL, "lbm_solid_from_particles: lattice / solid is NULL");
   DW_REQUIRE(lat->nx >= 1 && lat->ny >= 1 && lat->nz >= 1 && lat->dx > 0.f, DW_EINVAL,
              "lbm_solid_from_particles: bad lattice");
@@ -1192,6 +1197,6 @@ extern "C" int lbm_solid_from_particles(const dw_lattice *lat, const float *x, i
   if (!accumulate) hipLaunchKernelGGL(k_fill_u8, dim3(grid_blocks(L / 16 + 16, 256)), dim3(256), 0, s, solid, L);
   if (n > 0)
     hipLaunchKernelGGL(k_voxelize, dim3(grid_blocks(n, 256)), dim3(256), 0, s, lat->nx, lat->ny, lat->nz,
-                       lat->origin[0], lat->origin[1], lat->origin[2], lat->dx, x, n, solid);
+                       lat->origin[0], lat->origin[1], lat->origin[2], lat->dx, x, xref, n, solid);
   return check_launch("lbm_solid_from_particles");
 }

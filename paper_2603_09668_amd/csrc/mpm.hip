@@ -41,7 +41,8 @@ __device__ __forceinline__ int wave_keyed_add(int32_t *counters, int key, bool a
 
 // Key of every particle and its rank inside its tile (the tile count's value
 // before the particle's wave added to it), so the scatter needs no atomics.
-__global__ void k_sort_keys(GridDev g, const float *__restrict__ x, int n, int32_t *__restrict__ key,
+__global__ void k_sort_keys(GridDev g, const float *__restrict__ x, const float *__restrict__ xr, int n,
+                            int32_t *__restrict__ key,
                             int32_t *__restrict__ rank, int32_t *__restrict__ tile_count,
                             int32_t *__restrict__ node_flag, int32_t *__restrict__ status) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,9 +50,9 @@ __global__ void k_sort_keys(GridDev g, const float *__restrict__ x, int n, int32
   int k = -1;
   int bx = 0, by = 0, bz = 0;
   if (live) {
-    float X = grid_coord(x[p], g.ox, g.inv_dx);
-    float Y = grid_coord(x[n + p], g.oy, g.inv_dx);
-    float Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
+    const float X = coord_sum(load_coord(xr, x, p, g.ox, g.inv_dx));
+    const float Y = coord_sum(load_coord(xr, x, (size_t)n + p, g.oy, g.inv_dx));
+    const float Z = coord_sum(load_coord(xr, x, 2 * (size_t)n + p, g.oz, g.inv_dx));
     const float lim = 1.0e9f;  // guard the float -> int conversion
     if (!(isfinite(X) && isfinite(Y) && isfinite(Z))) {
       atomicOr(status, DW_STATUS_NONFINITE);
@@ -269,6 +270,7 @@ __global__ __launch_bounds__(256) void k_grid_clear(GridDev g, const int32_t *__
 
 struct PView {
   const float *x, *v, *C, *F, *mass, *vol0, *E, *nu;
+  const float *xr;  // position reference or NULL
   const int32_t *region;
   int n, n_regions;
 };
@@ -333,15 +335,15 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
     const int j = tid;
     const bool has = j < nb;
     const int p = has ? perm[b0 + j] : 0;
-    float X = 0.f, Y = 0.f, Z = 0.f, H[9], Cm[9], m = 0.f, V0 = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, Er = 0.f,
+    float fx = 0.f, fy = 0.f, fz = 0.f, H[9], Cm[9], m = 0.f, V0 = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, Er = 0.f,
           nur = 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) H[q] = Cm[q] = 0.f;
     unsigned char c = 255;
     if (has) {
-      X = grid_coord(P.x[p], g.ox, g.inv_dx);
-      Y = grid_coord(P.x[n + p], g.oy, g.inv_dx);
-      Z = grid_coord(P.x[2 * n + p], g.oz, g.inv_dx);
+      const Coord cx = load_coord(P.xr, P.x, p, g.ox, g.inv_dx);
+      const Coord cy = load_coord(P.xr, P.x, (size_t)n + p, g.oy, g.inv_dx);
+      const Coord cz = load_coord(P.xr, P.x, 2 * (size_t)n + p, g.oz, g.inv_dx);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         H[q] = P.F[q * n + p];
@@ -355,7 +357,11 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
       const int r = P.region[p];
       Er = P.E[r];
       nur = P.nu[r];
-      const int lx = base_of(X) - 4 * tx, ly = base_of(Y) - 4 * ty, lz = base_of(Z) - 4 * tz;
+      const int bx = base_of(coord_sum(cx)), by = base_of(coord_sum(cy)), bz = base_of(coord_sum(cz));
+      fx = coord_frac(cx, bx);
+      fy = coord_frac(cy, by);
+      fz = coord_frac(cz, bz);
+      const int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
       if ((unsigned)lx <= 3u && (unsigned)ly <= 3u && (unsigned)lz <= 3u) {
         c = (unsigned char)(lx + 4 * (ly + 4 * lz));
         atomicAdd(&s_cnt[c], 1);
@@ -383,7 +389,7 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
       float mu, lam, tau[9];
       lame(Er, nur, mu, lam);
       kirchhoff_shift(H, mu, lam, material, tau, status);
-      const float f[3] = {X - (float)base_of(X), Y - (float)base_of(Y), Z - (float)base_of(Z)};
+      const float f[3] = {fx, fy, fz};
       float A[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) A[q] = (m * Cm[q] - kstress * V0 * tau[q]) * dx;
@@ -486,7 +492,8 @@ __global__ __launch_bounds__(256) void k_p2g_det_gather(GridDev g, const int32_t
 // ---------------------------------------------------------------- reorder
 
 // out[i] = in[perm[i]] for every per-particle array (SoA, n entries each)
-__global__ __launch_bounds__(256) void k_reorder(PView in, float *__restrict__ x, float *__restrict__ v,
+__global__ __launch_bounds__(256) void k_reorder(PView in, float *__restrict__ x, float *__restrict__ xr,
+                                                 float *__restrict__ v,
                                                  float *__restrict__ C, float *__restrict__ F,
                                                  float *__restrict__ mass, float *__restrict__ vol0,
                                                  int32_t *__restrict__ region, const int32_t *__restrict__ perm,
@@ -499,6 +506,7 @@ __global__ __launch_bounds__(256) void k_reorder(PView in, float *__restrict__ x
   for (int d = 0; d < 3; ++d) {
     x[d * n + i] = in.x[d * n + p];
     v[d * n + i] = in.v[d * n + p];
+    if (xr) xr[d * n + i] = in.xr[d * n + p];
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -707,8 +715,9 @@ __device__ __forceinline__ void g2p_gather(const GridDev &g, const float *__rest
 
 // at most 72 VGPRs: 7 workgroups per CU, the count the LDS box allows
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_g2p(GridDev g, float dt, const float *__restrict__ gv, int64_t N,
-                                             const float *xin, const float *Fin, float *xout, float *vout,
-                                             float *Cout, float *Fout, int n, int32_t *__restrict__ status) {
+                                             const float *xin, const float *xref, const float *Fin, float *xout,
+                                             float *vout, float *Cout, float *Fout, int n,
+                                             int32_t *__restrict__ status) {
   __shared__ float s_v[3][STENCIL_BOX];
   __shared__ int s_red[4][6];
   __shared__ int s_box[6];
@@ -716,9 +725,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   const bool live = p < n;
   const uint32_t pp = live ? (uint32_t)p : 0u;
   const float px = ld32(xin, pp), py = ld32(xin + n, pp), pz = ld32(xin + 2 * (size_t)n, pp);
-  const float X = grid_coord(px, g.ox, g.inv_dx);
-  const float Y = grid_coord(py, g.oy, g.inv_dx);
-  const float Z = grid_coord(pz, g.oz, g.inv_dx);
+  const bool ref = xref != nullptr;
+  const Coord cx = make_coord(ref, ref ? ld32(xref, pp) : 0.f, px, g.ox, g.inv_dx);
+  const Coord cy = make_coord(ref, ref ? ld32(xref + n, pp) : 0.f, py, g.oy, g.inv_dx);
+  const Coord cz = make_coord(ref, ref ? ld32(xref + 2 * (size_t)n, pp) : 0.f, pz, g.oz, g.inv_dx);
+  const float X = coord_sum(cx), Y = coord_sum(cy), Z = coord_sum(cz);
   float F[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) F[q] = ld32(Fin + (size_t)q * n, pp);
@@ -746,7 +757,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     }
     return;
   }
-  const float fx = X - (float)bx, fy = Y - (float)by, fz = Z - (float)bz;
+  const float fx = coord_frac(cx, bx), fy = coord_frac(cy, by), fz = coord_frac(cz, bz);
   float wx[3], wy[3], wz[3];
   {
     float a = 1.5f - fx, b = fx - 1.0f, c = fx - 0.5f;
@@ -821,20 +832,21 @@ static PView make_pview(const dw_particles *p) {
   v.x = p->x; v.v = p->v; v.C = p->C; v.F = p->F;
   v.mass = p->mass; v.vol0 = p->vol0; v.E = p->E; v.nu = p->nu;
   v.region = p->region;
+  v.xr = p->xref;
   v.n = p->n;
   v.n_regions = p->n_regions;
   return v;
 }
 
-int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, const Workspace &W,
-             hipStream_t s) {
+int run_sort(const dw_grid *grid, int deterministic, const float *x, const float *xref, int n,
+             const Workspace &W, hipStream_t s) {
   GridDev g = make_grid(grid);
   int64_t T = W.n_tiles, NB = W.n_scan_blocks;
   // header + tile_count + node_flag are contiguous: clear them
   int64_t clear_words = (int64_t)((char *)W.tile_start - (char *)W.status) / 4;
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_blocks(clear_words / 4 + 4, 256)), dim3(256), 0, s, W.status, clear_words, 0);
   if (n > 0)
-    hipLaunchKernelGGL(k_sort_keys, dim3(grid_blocks(n, 256)), dim3(256), 0, s, g, x, n, W.key, W.rank,
+    hipLaunchKernelGGL(k_sort_keys, dim3(grid_blocks(n, 256)), dim3(256), 0, s, g, x, xref, n, W.key, W.rank,
                        W.tile_count, W.node_flag, W.status);
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)NB), dim3(SCAN_BLOCK), 0, s, W.tile_count, W.node_flag, T,
                      W.block_sums, NB);
@@ -856,8 +868,8 @@ int run_sort(const dw_grid *grid, int deterministic, const float *x, int n, cons
 
 using namespace dw;
 
-extern "C" int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const float *x, int n, void *ws,
-                        size_t ws_bytes, void *stream) {
+extern "C" int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const float *x, const float *xref,
+                        int n, void *ws, size_t ws_bytes, void *stream) {
   int rc = check_grid(grid);
   if (rc) return rc;
   DW_REQUIRE(n >= 0, DW_EINVAL, "mpm_sort: n must be >= 0");
@@ -865,7 +877,7 @@ extern "C" int mpm_sort(const dw_grid *grid, const dw_mpm_params *params, const 
   Workspace W;
   rc = bind_workspace(grid, n, ws, ws_bytes, &W);
   if (rc) return rc;
-  return run_sort(grid, params ? params->deterministic : 0, x, n, W, (hipStream_t)stream);
+  return run_sort(grid, params ? params->deterministic : 0, x, xref, n, W, (hipStream_t)stream);
 }
 
 extern "C" int mpm_reorder(const dw_grid *grid, const dw_particles *in, dw_particles *out, int32_t *perm_out,
@@ -880,12 +892,15 @@ extern "C" int mpm_reorder(const dw_grid *grid, const dw_particles *in, dw_parti
   DW_REQUIRE(out->x != in->x && out->v != in->v && out->C != in->C && out->F != in->F && out->mass != in->mass &&
                  out->vol0 != in->vol0 && out->region != in->region,
              DW_EINVAL, "mpm_reorder: in and out must not share arrays");
+  DW_REQUIRE(!in->xref || (out->xref && out->xref != in->xref), DW_EINVAL,
+             "mpm_reorder: with in->xref set, out->xref must be a separate array");
   Workspace W;
   rc = bind_workspace(grid, in->n, ws, ws_bytes, &W, 0);
   if (rc) return rc;
   if (in->n > 0)
     hipLaunchKernelGGL(k_reorder, dim3(grid_blocks(in->n, 256)), dim3(256), 0, (hipStream_t)stream,
-                       make_pview(in), out->x, out->v, out->C, out->F, const_cast<float *>(out->mass),
+                       make_pview(in), out->x, in->xref ? const_cast<float *>(out->xref) : (float *)nullptr,
+                       out->v, out->C, out->F, const_cast<float *>(out->mass),
                        const_cast<float *>(out->vol0), const_cast<int32_t *>(out->region), W.perm,
                        perm_out);
   return check_launch("mpm_reorder");
@@ -961,6 +976,7 @@ extern "C" int mpm_g2p(const dw_grid *grid, const dw_mpm_params *params, const f
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
   hipLaunchKernelGGL(k_g2p, dim3(grid_blocks(in->n, 256)), dim3(256), 0, (hipStream_t)stream, g, params->dt,
-                     grid_v, N, in->x, in->F, out->x, out->v, out->C, out->F, in->n, (int32_t *)nullptr);
+                     grid_v, N, in->x, in->xref, in->F, out->x, out->v, out->C, out->F, in->n,
+                     (int32_t *)nullptr);
   return check_launch("mpm_g2p");
 }

@@ -130,6 +130,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 struct PAdj {
   const float *x, *v, *C, *F, *mass, *vol0, *E, *nu;
+  const float *xr;  // position reference or NULL
   const int32_t *region;
   int n;
   float *xb, *vb, *Cb, *Fb, *Eb;
@@ -145,9 +146,10 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
   float Ebar_p = 0.f;
   int r = 0;
   if (live) {
-    float X = grid_coord(P.x[p], g.ox, g.inv_dx);
-    float Y = grid_coord(P.x[n + p], g.oy, g.inv_dx);
-    float Z = grid_coord(P.x[2 * n + p], g.oz, g.inv_dx);
+    const Coord cx = load_coord(P.xr, P.x, p, g.ox, g.inv_dx);
+    const Coord cy = load_coord(P.xr, P.x, (size_t)n + p, g.oy, g.inv_dx);
+    const Coord cz = load_coord(P.xr, P.x, 2 * (size_t)n + p, g.oz, g.inv_dx);
+    const float X = coord_sum(cx), Y = coord_sum(cy), Z = coord_sum(cz);
     bool ok = isfinite(X) && isfinite(Y) && isfinite(Z) && fabsf(X) < 1e9f && fabsf(Y) < 1e9f && fabsf(Z) < 1e9f;
     int bx = 0, by = 0, bz = 0;
     if (ok) {
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
       ok = stencil_inside(g, bx, by, bz);
     }
     if (ok) {
-      float f[3] = {X - (float)bx, Y - (float)by, Z - (float)bz};
+      float f[3] = {coord_frac(cx, bx), coord_frac(cy, by), coord_frac(cz, bz)};
       float w[3][3], dw[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_grid_update_adj(GridDev g, float dt, fl
 // global grid adjoint with float atomics.
 __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_g2p_adj(
     GridDev g, float dt, const float *__restrict__ gv, int64_t N, const float *__restrict__ x,
-    const float *__restrict__ F, int n, const float *__restrict__ xob, const float *__restrict__ vob,
+    const float *__restrict__ xr, const float *__restrict__ F, int n, const float *__restrict__ xob, const float *__restrict__ vob,
     const float *__restrict__ Cob, const float *__restrict__ Fob, float *__restrict__ xb, float *__restrict__ Fb,
     float *__restrict__ gvb, const int32_t *__restrict__ perm, const int32_t *__restrict__ tile_start,
     const int32_t *__restrict__ item_tile, const int32_t *__restrict__ item_begin,
@@ -415,15 +417,15 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     // particle -> cell in the tile
     const bool has = tid < nb;
     const int p = has ? perm[b0 + tid] : 0;
-    float X = 0.f, Y = 0.f, Z = 0.f;
+    Coord cx = {0.f, 0.f}, cy = {0.f, 0.f}, cz = {0.f, 0.f};
     int bx = 0, by = 0, bz = 0, c = -1;
     if (has) {
-      X = grid_coord(x[p], g.ox, g.inv_dx);
-      Y = grid_coord(x[n + p], g.oy, g.inv_dx);
-      Z = grid_coord(x[2 * n + p], g.oz, g.inv_dx);
-      bx = base_of(X);
-      by = base_of(Y);
-      bz = base_of(Z);
+      cx = load_coord(xr, x, p, g.ox, g.inv_dx);
+      cy = load_coord(xr, x, (size_t)n + p, g.oy, g.inv_dx);
+      cz = load_coord(xr, x, 2 * (size_t)n + p, g.oz, g.inv_dx);
+      bx = base_of(coord_sum(cx));
+      by = base_of(coord_sum(cy));
+      bz = base_of(coord_sum(cz));
       const int lx = bx - 4 * tx, ly = by - 4 * ty, lz = bz - 4 * tz;
       if ((unsigned)lx <= 3u && (unsigned)ly <= 3u && (unsigned)lz <= 3u) {
         c = lx + 4 * (ly + 4 * lz);
@@ -435,7 +437,7 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     __syncthreads();
     if (c >= 0) {
       const int slot = atomicAdd(&s_cur[c], 1);
-      float f[3] = {X - (float)bx, Y - (float)by, Z - (float)bz};
+      float f[3] = {coord_frac(cx, bx), coord_frac(cy, by), coord_frac(cz, bz)};
       float w[3][3], dw[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -584,7 +586,7 @@ extern "C" int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, con
   if (p->n == 0) return DW_OK;
   PAdj P;
   P.x = p->x; P.v = p->v; P.C = p->C; P.F = p->F; P.mass = p->mass; P.vol0 = p->vol0;
-  P.E = p->E; P.nu = p->nu; P.region = p->region; P.n = p->n;
+  P.E = p->E; P.nu = p->nu; P.region = p->region; P.n = p->n; P.xr = p->xref;
   P.xb = bar->x; P.vb = bar->v; P.Cb = bar->C; P.Fb = bar->F; P.Eb = E_bar;
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
@@ -630,7 +632,7 @@ extern "C" int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, con
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
   hipLaunchKernelGGL(k_g2p_adj, dim3(2048), dim3(SC_THREADS), 0, (hipStream_t)stream, g, params->dt, grid_v, N,
-                     in->x, in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F,
+                     in->x, in->xref, in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F,
                      grid_v_bar, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items);
   return check_launch("mpm_g2p_adj");
 }

@@ -30,7 +30,11 @@ class FrameResult:
 
 
 class Reconstructor:
-    """Frame-by-frame reconstruction of a force-grid wind for one particle set."""
+    """Frame-by-frame reconstruction of a force-grid wind for one particle set.
+
+    Positions are displacements from the scene's positions (the rollout's
+    position reference); `initial_state()` gives the scene at rest in that
+    form, and the targets of `frame` are displacements too."""
 
     def __init__(self, scene, nw, box_lo, box_hi, substeps_per_frame: int, ckpt: int = 16, device="cuda"):
         f32 = dict(dtype=torch.float32, device=device)
@@ -44,9 +48,17 @@ class Reconstructor:
         nu = torch.tensor(scene.nu, **f32)
         pin = torch.tensor(scene.pin, dtype=torch.uint8, device=device)
         self.E = torch.tensor(scene.E, **f32)
+        self.xref = torch.tensor(scene.x.T.copy(), **f32).contiguous()
         self.plan = RolloutPlan(scene.grid, n, mass, vol0, region, nu, pin, scene.dt, scene.gravity, scene.material,
                                 scene.bound, nw, box_lo, box_hi, K=1, n_sub=substeps_per_frame, ckpt=ckpt,
-                                device=device)
+                                device=device, xref=self.xref)
+
+    def initial_state(self):
+        """(x, v, C, H) of the scene at rest: zero displacement, v = C = 0, F = I."""
+        n = self.xref.shape[1]
+        z3 = torch.zeros(3, n, device=self.device)
+        z9 = torch.zeros(9, n, device=self.device)
+        return (z3, z3.clone(), z9, z9.clone())
 
     def advance(self, state, W):
         """One frame forward with force field W (3, nw^3); returns the new state."""

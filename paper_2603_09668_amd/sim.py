@@ -8,6 +8,9 @@ One coupled step runs, on torch's current stream:
   4. mpm_p2g                   -- Eq. P2G with the MLS stress term
   5. mpm_grid_update           -- gravity, LBM drag wind (Sec. 3.4), walls, pins
   6. mpm_g2p                   -- Eq. G2P, APIC C, Eq. deformation_update (in place)
+Particle positions are stored as a fixed reference (the scene's positions)
+plus a float32 displacement (`p.xref`, `p.x`; see the header), unless
+`position_reference=False` keeps absolute positions in `p.x`.
 Steps 1-2 (the wind branch) and 3-4 (the particle branch) are independent
 and can run side by side on two streams (`step(side)`, the default in a
 captured graph).  All buffers are allocated once here; a step allocates
@@ -25,7 +28,7 @@ from . import api
 
 class CoupledSim:
     def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1, reorder: bool = True,
-                 lbm_model: str = "bgk", relative_drag: bool = False):
+                 lbm_model: str = "bgk", relative_drag: bool = False, position_reference: bool = True):
         self.scene = scene
         self.device = device
         self.R = int(lbm_steps_per_substep)
@@ -34,12 +37,14 @@ class CoupledSim:
         self.N = g["nx"] * g["ny"] * g["nz"]
         n = scene.n
         f32 = dict(dtype=torch.float32, device=device)
+        x0 = torch.tensor(np.ascontiguousarray(scene.x.T), **f32)
         self.p = api.ParticleArrays(
-            x=torch.tensor(np.ascontiguousarray(scene.x.T), **f32),
+            x=torch.zeros(3, n, **f32) if position_reference else x0,
             v=torch.zeros(3, n, **f32), C=torch.zeros(9, n, **f32), F=torch.zeros(9, n, **f32),
             mass=torch.tensor(scene.mass, **f32), vol0=torch.tensor(scene.vol0, **f32),
             region=torch.tensor(scene.region, dtype=torch.int32, device=device),
-            E=torch.tensor(scene.E, **f32), nu=torch.tensor(scene.nu, **f32))
+            E=torch.tensor(scene.E, **f32), nu=torch.tensor(scene.nu, **f32),
+            xref=x0 if position_reference else None)
         self.ws = api.alloc_workspace(self.grid, n, device)
         self.gm = torch.zeros(self.N, **f32)
         self.gmv = torch.zeros(3, self.N, **f32)
@@ -91,8 +96,12 @@ class CoupledSim:
         self.order = self.order[perm.long()]
 
     # -------------------------------------------------------------- phases
+    def positions(self):
+        """Absolute particle positions (3, n), float64."""
+        return self.p.positions()
+
     def voxelize(self):
-        api.lbm_solid_from_particles(self.lat, self.p.x, self.solid)
+        api.lbm_solid_from_particles(self.lat, self.p.x, self.solid, xref=self.p.xref)
 
     def lbm(self):
         for _ in range(self.R):
@@ -104,7 +113,7 @@ class CoupledSim:
             self.t += 1
 
     def sort(self):
-        api.mpm_sort(self.grid, self.prm, self.p.x, self.ws)
+        api.mpm_sort(self.grid, self.prm, self.p.x, self.ws, xref=self.p.xref)
 
     def p2g(self):
         api.mpm_p2g(self.grid, self.prm, self.p, self.gm, self.gmv, self.ws)

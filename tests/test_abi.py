@@ -44,7 +44,7 @@ def test_struct_layout_matches_header():
 int main(void) {
   P(dw_grid) P(dw_lattice) P(dw_mpm_params) P(dw_particles) P(dw_particles_bar) P(dw_wind) P(dw_lbm_params)
   O(dw_wind, W) O(dw_wind, lat) O(dw_wind, u) O(dw_wind, acc) O(dw_particles, n_regions) O(dw_lbm_params, t)
-  O(dw_lbm_params, bc) O(dw_mpm_params, deterministic)
+  O(dw_lbm_params, bc) O(dw_mpm_params, deterministic) O(dw_particles, xref)
   return 0;
 }
 """
@@ -65,6 +65,7 @@ int main(void) {
     assert int(got["dw_wind.u"]) == api.Wind.u.offset
     assert int(got["dw_wind.acc"]) == api.Wind.acc.offset
     assert int(got["dw_particles.n_regions"]) == api.Particles.n_regions.offset
+    assert int(got["dw_particles.xref"]) == api.Particles.xref.offset
     assert int(got["dw_lbm_params.t"]) == api.LBMParams.t.offset
     assert int(got["dw_lbm_params.bc"]) == api.LBMParams.bc.offset
     assert int(got["dw_mpm_params.deterministic"]) == api.MPMParams.deterministic.offset
@@ -84,13 +85,15 @@ def test_argument_errors_are_codes():
     g = api.make_grid(16, 16, 16, 1 / 16)
     prm = api.make_mpm_params(1e-4)
     # null workspace
-    rc = L.mpm_sort(ctypes.byref(g), ctypes.byref(prm), ctypes.c_void_p(16), 10, None, 0, None)
+    rc = L.mpm_sort(ctypes.byref(g), ctypes.byref(prm), ctypes.c_void_p(16), None, 10, None, 0, None)
     assert rc == -1 and "workspace" in api.dw_last_error()
     # workspace too small (aligned fake pointer, never dereferenced)
-    rc = L.mpm_sort(ctypes.byref(g), ctypes.byref(prm), ctypes.c_void_p(256), 10, ctypes.c_void_p(256), 8, None)
+    rc = L.mpm_sort(ctypes.byref(g), ctypes.byref(prm), ctypes.c_void_p(256), None, 10, ctypes.c_void_p(256), 8,
+                    None)
     assert rc == -4
     bad = api.make_grid(16, 0, 16, 1 / 16)
-    assert L.mpm_sort(ctypes.byref(bad), ctypes.byref(prm), None, 0, ctypes.c_void_p(256), 1 << 20, None) == -1
+    assert L.mpm_sort(ctypes.byref(bad), ctypes.byref(prm), None, None, 0, ctypes.c_void_p(256), 1 << 20,
+                      None) == -1
     lat = api.make_lattice(8, 8, 8)
     lp = api.make_lbm_params(0.5)  # tau must exceed 1/2
     assert L.lbm_step(ctypes.byref(lat), ctypes.byref(lp), ctypes.c_void_p(256), ctypes.c_void_p(512), None, None,

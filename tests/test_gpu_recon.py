@@ -90,9 +90,7 @@ def test_sequential_reconstruction_with_phys_loss():
     F_gt = recon.drag_field(guide, 20.0)
     assert recon.metrics(F_gt, guide)[0] > 0.999999
     rc = recon.Reconstructor(sc, nw, lo, hi, substeps_per_frame=16)
-    n = sc.n
-    x0 = torch.tensor(sc.x.T.copy(), dtype=torch.float32, device=DEV).contiguous()
-    state0 = (x0, torch.zeros(3, n, device=DEV), torch.zeros(9, n, device=DEV), torch.zeros(9, n, device=DEV))
+    state0 = rc.initial_state()  # positions as displacements from the scene's positions
     frames = 2
     targets, st = [], state0
     for _ in range(frames):

@@ -46,32 +46,38 @@ def _oracle_loss(grid, x0, region, mass, vol0, E, nu, W, target, cfg):
     return ((st["x"] - target) ** 2).sum()
 
 
-def _gpu_grad(grid, x0, region, mass, vol0, E, nu, W, target, cfg):
+def _gpu_grad(grid, x0, region, mass, vol0, E, nu, W, target, cfg, ref=False):
+    """Loss and gradients through the library; ref=True keeps the positions
+    as x0 (reference) plus a displacement."""
     n = x0.shape[0]
+    xd = x0.T.contiguous().float().to(DEV)
     plan = RolloutPlan(grid, n, mass.float().to(DEV), vol0.float().to(DEV), region.to(torch.int32).to(DEV),
                        nu.float().to(DEV), None, cfg["dt"], cfg["gravity"], cfg["material"], cfg["bound"],
-                       cfg["nw"], (0, 0, 0), (1, 1, 1), cfg["K"], cfg["n_sub"], cfg["ckpt"])
+                       cfg["nw"], (0, 0, 0), (1, 1, 1), cfg["K"], cfg["n_sub"], cfg["ckpt"],
+                       xref=xd if ref else None)
     Wd = W.float().to(DEV).contiguous().requires_grad_(True)
     Ed = E.float().to(DEV).requires_grad_(True)
-    x = x0.T.contiguous().float().to(DEV)
+    x = torch.zeros_like(xd) if ref else xd
     z3 = torch.zeros(3, n, device=DEV)
     z9 = torch.zeros(9, n, device=DEV)
     xT, vT, CT, HT = rollout(plan, Wd, Ed, x, z3, z9, z9.clone())
-    L = ((xT.double() - target.T.to(DEV)) ** 2).sum()
+    pos = xT.double() + (xd.double() if ref else 0.0)
+    L = ((pos - target.T.to(DEV)) ** 2).sum()
     gW, gE = torch.autograd.grad(L, (Wd, Ed))
     return L.item(), gW.double().cpu(), gE.double().cpu()
 
 
+@pytest.mark.parametrize("ref", [False, True])
 @pytest.mark.parametrize("material", [api.FIXED_COROTATED, api.NEO_HOOKEAN])
-def test_rollout_gradient_matches_oracle(material):
-    say(f"rollout gradient material={material}")
+def test_rollout_gradient_matches_oracle(material, ref):
+    say(f"rollout gradient material={material} ref={ref}")
     args = _setup(material)
     grid, x0, region, mass, vol0, E, nu, W, target, cfg = args
     Wo = W.clone().requires_grad_(True)
     Eo = E.clone().requires_grad_(True)
     Lo = _oracle_loss(grid, x0, region, mass, vol0, Eo, nu, Wo, target, cfg)
     gWo, gEo = torch.autograd.grad(Lo, (Wo, Eo))
-    L, gW, gE = _gpu_grad(*args)
+    L, gW, gE = _gpu_grad(*args, ref=ref)
     say(f"  loss gpu {L:.6e} oracle {Lo.item():.6e}")
     assert abs(L - Lo.item()) / Lo.item() < 1e-4
     eW = ((gW - gWo).norm() / gWo.norm()).item()

@@ -147,3 +147,17 @@ def test_inlet_gust_profile():
     expect = 0.08 * (1 + 0.05 * math.sin(2 * math.pi * (17 / 200 + j / 8) + 0.3))
     assert abs(u[0, 2, j].item() - expect) < 1e-16
     assert u[1].abs().max() == 0
+
+
+def test_two_part_voxel_decision():
+    """The voxel index from a reference plus a displacement reduces to the
+    one-part rule for a zero displacement and equals the exact cell away
+    from cell faces."""
+    lat = lbm.Lattice(16, 12, 10, 1.0 / 16, (0.0, 0.1, 0.2))
+    rng = np.random.default_rng(42)
+    xr = torch.tensor(rng.uniform(0.1, 0.7, (3000, 3))).float()
+    d = torch.tensor(1e-2 * rng.standard_normal((3000, 3))).float()
+    assert torch.equal(lbm.voxelize(lat, torch.zeros_like(xr), x_ref=xr), lbm.voxelize(lat, xr))
+    q = (xr.double() + d.double() - torch.tensor(lat.origin, dtype=torch.float64)) / lat.dx
+    far = ((q - torch.round(q)).abs() > 1e-5).all(dim=1)
+    assert torch.equal(lbm.voxelize(lat, d[far], x_ref=xr[far]), lbm.voxelize(lat, (xr.double() + d.double())[far]))

@@ -293,3 +293,20 @@ def test_autograd_matches_finite_differences():
         Em[r] -= hE
         fd = (loss_fn(W, Ep) - loss_fn(W, Em)) / (2 * hE)
         assert abs(fd - gE[r]) <= 1e-6 * max(abs(gE[r].item()), 1e-6)
+
+
+def test_two_part_stencil_decision():
+    """With a position reference the float32 base decision is taken from the
+    two parts; it reduces to the one-part decision for a zero displacement
+    and equals the exact floor away from cell boundaries."""
+    grid = Grid(32, 32, 32, 1.0 / 32)
+    rng = np.random.default_rng(41)
+    xr = torch.tensor(rng.uniform(0.2, 0.8, (4000, 3))).float()
+    d = torch.tensor(1e-2 * rng.standard_normal((4000, 3))).float()
+    assert torch.equal(mpm.stencil_base_f32(torch.zeros_like(xr), grid, xref32=xr), mpm.stencil_base_f32(xr, grid))
+    got = mpm.stencil_base_f32(d, grid, xref32=xr)
+    X = (xr.double() + d.double()) / grid.dx - 0.5
+    exact = torch.floor(X).long()
+    far = ((X - torch.round(X)).abs() > 1e-5).all(dim=1)
+    assert far.sum() > 3900
+    assert torch.equal(got[far], exact[far])
