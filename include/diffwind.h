@@ -366,6 +366,24 @@ int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float
                  const uint8_t *solid, const float *f_out_bar, const float *u_out_bar,
                  float *f_in_bar, float *work, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_step_adj with its
+ * work buffer in a static device array of the library instead of a
+ * caller-provided one.  Same arguments, result and error behaviour as
+ * lbm_step_adj, without `work`; lattices of at most DW_STATIC_ADJ_MAX_NODES
+ * nodes (the 128 x 64 x 64 tunnel; larger ones return DW_ERANGE with a
+ * message, before any launch).  The array (19 x DW_STATIC_ADJ_MAX_NODES
+ * floats, 38 MiB) exists once per device for the life of the process; its
+ * device address is looked up on the first call on each device.  No call
+ * allocates or frees memory.  Every call on one device uses the same array,
+ * so calls that overlap on one device (two streams, two host threads) race
+ * and must be serialised by the caller; the array keeps the last call's
+ * contents, which no later call reads before writing. */
+enum { DW_STATIC_ADJ_MAX_NODES = 1 << 19 };
+int lbm_step_adj_static(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
+                        const uint8_t *solid, const float *f_out_bar, const float *u_out_bar, float *f_in_bar,
+                        void *stream);
+
 /* Shifted equilibrium populations f^eq(rho, u) - w: rho [L] (NULL = 1) and
  * u [3][L] (NULL = the uniform params->u_in).  Used to initialise a lattice
  * and to re-initialise it from macroscopic fields. */

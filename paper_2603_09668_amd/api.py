@@ -30,7 +30,7 @@ STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED = 1, 2, 4
 SYMBOLS = [
     "dw_last_error", "mpm_workspace_bytes", "mpm_sort", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_reorder",
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
-    "lbm_step", "lbm_step_adj", "lbm_equilibrium", "lbm_home_step", "lbm_home_step_adj", "lbm_home_equilibrium",
+    "lbm_step", "lbm_step_adj", "lbm_step_adj_static", "lbm_equilibrium", "lbm_home_step", "lbm_home_step_adj", "lbm_home_equilibrium",
     "lbm_solid_from_particles", "gaussian_covariance", "gaussian_covariance_adj",
     "phys_loss", "position_loss", "direction_metrics", "wind_guide",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
@@ -107,6 +107,7 @@ def lib():
         "wind_to_grid_adj": ([POINTER(Grid), POINTER(Wind), P, P, P], c_int),
         "lbm_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P, P], c_int),
+        "lbm_step_adj_static": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_equilibrium": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P], c_int),
         "lbm_home_step": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P], c_int),
         "lbm_home_step_adj": ([POINTER(Lattice), POINTER(LBMParams), P, P, P, P, P, P, P], c_int),
@@ -399,6 +400,26 @@ def lbm_step_adj(lat: Lattice, params: LBMParams, f_in, solid, f_out_bar, u_out_
                               _ptr(u_out_bar, name="u_out_bar"), _ptr(f_in_bar, name="f_in_bar"),
                               _ptr(work, name="work"), _stream()),
            "lbm_step_adj")
+
+
+STATIC_ADJ_MAX_NODES = 1 << 19  # DW_STATIC_ADJ_MAX_NODES
+
+
+def lbm_step_adj_static(lat: Lattice, params: LBMParams, f_in, solid, f_out_bar, u_out_bar, f_in_bar):
+    """lbm_step_adj with the library's static work buffer (no allocation;
+    lattices of at most STATIC_ADJ_MAX_NODES nodes; calls on one device must
+    not overlap)."""
+    L = lat.nx * lat.ny * lat.nz
+    for t, name in ((f_in, "f_in"), (f_out_bar, "f_out_bar"), (f_in_bar, "f_in_bar")):
+        _shape(t, (19, L), name)
+    if u_out_bar is not None:
+        _shape(u_out_bar, (3, L), "u_out_bar")
+    if solid is not None:
+        _shape(solid, (L,), "solid")
+    _check(lib().lbm_step_adj_static(ctypes.byref(lat), ctypes.byref(params), _ptr(f_in, name="f_in"),
+                                     _ptr(solid, torch.uint8, "solid"), _ptr(f_out_bar, name="f_out_bar"),
+                                     _ptr(u_out_bar, name="u_out_bar"), _ptr(f_in_bar, name="f_in_bar"), _stream()),
+           "lbm_step_adj_static")
 
 
 def lbm_equilibrium(lat: Lattice, params: LBMParams, f, rho=None, u=None):

@@ -6,6 +6,8 @@
 // keeps its resolution on the deviation from rest.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <climits>
 #include <utility>
 
@@ -1092,18 +1094,21 @@ extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, cons
   return check_launch("lbm_step");
 }
 
-extern "C" int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
+namespace dw {
+
+// The reverse BGK step: pull pass into `work`, then the transposed-streaming
+// gather into f_in_bar (shared by lbm_step_adj and lbm_step_adj_static).
+static int run_lbm_step_adj(const char *name, const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
                             const uint8_t *solid, const float *f_out_bar, const float *u_out_bar, float *f_in_bar,
-                            float *work, void *stream) {
+                            float *work, hipStream_t s) {
   LbmDev P;
   int rc = make_lbm(lat, params, &P);
   if (rc) return rc;
-  DW_REQUIRE(f_in && f_out_bar && f_in_bar && work, DW_EINVAL,
-             "lbm_step_adj: f_in / f_out_bar / f_in_bar / work is NULL");
-  DW_REQUIRE(f_in_bar != f_in && f_in_bar != f_out_bar, DW_EINVAL, "lbm_step_adj: f_in_bar must not alias");
+  DW_REQUIRE(f_in && f_out_bar && f_in_bar && work, DW_EINVAL, "%s: f_in / f_out_bar / f_in_bar / work is NULL",
+             name);
+  DW_REQUIRE(f_in_bar != f_in && f_in_bar != f_out_bar, DW_EINVAL, "%s: f_in_bar must not alias", name);
   DW_REQUIRE(work != f_in && work != f_out_bar && work != f_in_bar && work != u_out_bar, DW_EINVAL,
-             "lbm_step_adj: work must not alias another argument");
-  hipStream_t s = (hipStream_t)stream;
+             "%s: work must not alias another argument", name);
   if (solid) {
     hipLaunchKernelGGL(k_lbm_adj_pull<true>, lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, f_out_bar, u_out_bar,
                        work);
@@ -1115,7 +1120,59 @@ extern "C" int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, 
     hipLaunchKernelGGL((k_adj_gather<false, false>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, work,
                        f_in_bar);
   }
-  return check_launch("lbm_step_adj");
+  return check_launch(name);
+}
+
+// Work buffer of lbm_step_adj_static: [19][L] floats for lattices of at most
+// DW_STATIC_ADJ_MAX_NODES nodes, a file-scope device array (one copy per
+// device, held for the life of the process).  Host code never uses the
+// symbol itself as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) float scratch[(size_t)19 * DW_STATIC_ADJ_MAX_NODES];
+
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[64] = {nullptr};
+
+static int static_scratch(const char *name, float **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  DW_REQUIRE(e == hipSuccess, DW_ELAUNCH, "%s: hipGetDevice failed: %s", name, hipGetErrorString(e));
+  DW_REQUIRE(dev >= 0 && dev < 64, DW_ERANGE, "%s: device index %d not supported", name, dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    DW_REQUIRE(e == hipSuccess && ptr, DW_ELAUNCH, "%s: hipGetSymbolAddress(scratch) failed on device %d: %s", name,
+               dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<float *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return DW_OK;
+}
+
+}  // namespace dw
+
+extern "C" int lbm_step_adj(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
+                            const uint8_t *solid, const float *f_out_bar, const float *u_out_bar, float *f_in_bar,
+                            float *work, void *stream) {
+  return run_lbm_step_adj("lbm_step_adj", lat, params, f_in, solid, f_out_bar, u_out_bar, f_in_bar, work,
+                          (hipStream_t)stream);
+}
+
+extern "C" int lbm_step_adj_static(const dw_lattice *lat, const dw_lbm_params *params, const float *f_in,
+                                   const uint8_t *solid, const float *f_out_bar, const float *u_out_bar,
+                                   float *f_in_bar, void *stream) {
+  DW_REQUIRE(lat, DW_EINVAL, "lbm_step_adj_static: lattice is NULL");
+  const int64_t L = (int64_t)lat->nx * lat->ny * lat->nz;
+  DW_REQUIRE(L <= DW_STATIC_ADJ_MAX_NODES, DW_ERANGE,
+             "lbm_step_adj_static: lattice of %lld nodes exceeds the static work buffer (%d nodes); "
+             "use lbm_step_adj with a caller-provided work buffer",
+             (long long)L, (int)DW_STATIC_ADJ_MAX_NODES);
+  float *work = nullptr;
+  int rc = static_scratch("lbm_step_adj_static", &work);
+  if (rc) return rc;
+  return run_lbm_step_adj("lbm_step_adj_static", lat, params, f_in, solid, f_out_bar, u_out_bar, f_in_bar, work,
+                          (hipStream_t)stream);
 }
 
 extern "C" int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *params, const float *rho,

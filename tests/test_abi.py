@@ -107,3 +107,9 @@ def test_argument_errors_are_codes():
                       None, None) == -1
     w = api.Wind(mode=7)
     assert L.wind_to_grid(ctypes.byref(g), ctypes.byref(w), ctypes.c_void_p(256), None) == -1
+    # the allocation-free reverse step refuses lattices beyond its static buffer before any HIP call
+    big = api.make_lattice(128, 64, 65)
+    lp = api.make_lbm_params(0.6)
+    assert L.lbm_step_adj_static(ctypes.byref(big), ctypes.byref(lp), ctypes.c_void_p(256), None,
+                                 ctypes.c_void_p(512), None, ctypes.c_void_p(768), None) == -2
+    assert "static work buffer" in api.dw_last_error()
