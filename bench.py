@@ -9,8 +9,11 @@ and a 128x64x64 D3Q19 lattice with inflow 0.08 and a 5 % seeded gust.
 
 Prints one JSON line: particle-substeps/s for the whole step, the LBM MLUPS
 of a standalone stream-collide loop, per-phase times from HIP events on the
-launch stream, the roofline of the dominant kernel and the float64 CPU
-oracle timed on a bounded sample of the same workload.  The wind-surrogate
+launch stream, the roofline of the dominant kernel (and of every phase), a
+measured device-copy bandwidth beside the 8 TB/s peak, the reverse LBM step,
+the same coupled substep at the largest single-GPU size (4M particles, 256^3
+grid, 256x128x128 lattice) and the float64 CPU oracle timed on a bounded
+sample of the same workload (all host threads, one thread, the LBM alone).  The wind-surrogate
 leg trains the BF16 conv net on 2000 LBM pairs of 64^3 wind tunnels (1800
 train / 200 held out), then reports its held-out wind error against the LBM
 and the speedup of one batched call over the 8 LBM steps it replaces.  The
@@ -49,6 +52,7 @@ def _args():
     ap.add_argument("--sg-rollouts", type=int, default=250)
     ap.add_argument("--sg-steps", type=int, default=1000)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-largest", action="store_true", help="skip the 4M-particle / 256^3 leg")
     ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint leg (profiling)")
     ap.add_argument("--fd", type=int, default=20, help="finite-difference coordinates in the adjoint leg")
     return ap.parse_args()
@@ -96,6 +100,123 @@ def _graph_ms(fn, reps=5):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def _phase_times(sim, R=10, reps=5):
+    """Average launch time (ms) of every phase of a coupled substep: each
+    phase alone, R launches in one HIP graph, timed with HIP events on the
+    stream the kernels are launched on.  G2P runs out of place so that the
+    state does not drift."""
+    import torch
+    from paper_2603_09668_amd import api
+    scratch = [torch.empty_like(t) for t in (sim.p.x, sim.p.v, sim.p.C, sim.p.F)]
+
+    def g2p_out_of_place():
+        api.mpm_g2p(sim.grid, sim.prm, sim.gv, sim.p, *scratch)
+
+    out = {}
+    for ph in sim.PHASES:
+        fn = g2p_out_of_place if ph == "g2p" else getattr(sim, ph)
+        out[ph] = _graph_ms(lambda: [fn() for _ in range(R)], reps=reps) / R
+    return out
+
+
+def _phase_bytes(sim, active_nodes):
+    """Algorithmic bytes per launch of each phase (what the step must move).
+    Positions are a reference plus a displacement (24 bytes per particle)."""
+    n, L = sim.p.n, sim.L
+    pos = 24 if sim.p.xref is not None else 12
+    return {
+        "p2g": (pos + 96) * n + 16 * active_nodes,        # read x (+xref) v C F m V0 region; write m, mv
+        "g2p": (pos + 36 + 96) * n + 12 * active_nodes,   # read x (+xref) F, write x v C F; read grid v
+        "lbm": 153 * L + 12 * L,                          # 19 pops in + out, solid, u out
+        "grid_update": 29 * active_nodes,                 # read m mv pin, write v
+        "voxelize": pos * n + L,
+        "sort": pos * n,
+    }
+
+
+def _rooflines(ph_ms, bytes_per):
+    """Achieved algorithmic GB/s of every phase against the HBM peak."""
+    out = {}
+    for ph, ms in ph_ms.items():
+        b = bytes_per.get(ph)
+        if b and ms > 0:
+            ach = b / (ms * 1e-3) / 1e9
+            out[ph] = {"ms": ms, "algorithmic_bytes": b, "achieved_GBps": ach, "frac": ach / HBM_PEAK_GBS}
+    return out
+
+
+def _copy_bandwidth(mib=1024):
+    """Device-to-device copy of `mib` MiB (torch copy_), GB/s of bytes read plus written."""
+    import torch
+    src = torch.ones(mib << 18, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _graph_ms(lambda: dst.copy_(src), reps=10)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": 2 * (mib << 20) / (ms * 1e-3) / 1e9, "mib": mib, "ms": ms,
+            "frac_of_peak": 2 * (mib << 20) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def _largest_leg(steps=20):
+    """The largest single-GPU workload: 4M particles on a 256^3 grid with a
+    256x128x128 lattice, the same coupled substep as the main line (HIP graph
+    of two substeps, one stream), its phases and their rooflines."""
+    import torch
+    from paper_2603_09668_amd import scenes
+    from paper_2603_09668_amd.sim import CoupledSim
+    t0 = time.perf_counter()
+    scene = scenes.flag_and_leaves_scene(seed=0, n=4_000_000, res=256, lbm_dims=(256, 128, 128))
+    sim = CoupledSim(scene)
+    t_setup = time.perf_counter() - t0
+    for _ in range(4):
+        sim.step()
+    sim.capture(2, concurrent=False)
+    sim.replay()
+    torch.cuda.synchronize()
+    steps += steps % 2
+    t0 = time.perf_counter()
+    for _ in range(steps // 2):
+        sim.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    active = sim.active_nodes()
+    ph = _phase_times(sim, R=4, reps=3)
+    rl = _rooflines(ph, _phase_bytes(sim, active))
+    for k in rl:
+        rl[k]["traffic"] = _measured_traffic(k, scene.n, 256)
+    ms = el * 1e3 / steps
+    out = {"config": {"workload": "coupled MPM+LBM substep: 4000000 particles (flag sheet + 40 leaf clusters), "
+                                  "256^3 MPM grid, 256x128x128 D3Q19 BGK lattice, LBM drag wind",
+                      "particles": scene.n, "mpm_grid": 256, "lattice": [256, 128, 128], "dt": scene.dt,
+                      "active_nodes": active},
+           "ms_per_step": ms, "value": scene.n / (ms * 1e-3), "unit": "particle-substeps/s", "steps": steps,
+           "lbm_mlups": sim.L / (ph["lbm"] * 1e-3) / 1e6, "phase_ms": ph, "rooflines": rl,
+           "status": sim.status(), "setup_s": t_setup}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def _lbm_adj_leg(sim):
+    """The reverse BGK step (lbm_step_adj) on the scene's lattice and solids:
+    228 algorithmic bytes per node (f_in and the output adjoint read, the
+    input adjoint read and written; the work buffer's 76 B written and read
+    again is overhead)."""
+    import torch
+    from paper_2603_09668_amd import api
+    L = sim.L
+    prm = api.make_lbm_params(**sim.lbm_kw, t=3)
+    gb = torch.ones(19, L, device="cuda")
+    fib = torch.zeros(19, L, device="cuda")
+    work = torch.empty(19, L, device="cuda")
+    ms = _graph_ms(lambda: api.lbm_step_adj(sim.lat, prm, sim.fa, sim.solid, gb, None, fib, work=work))
+    b = (228 + 1) * L
+    ach = b / (ms * 1e-3) / 1e9
+    del gb, fib, work
+    return {"ms": ms, "mlups": L / (ms * 1e-3) / 1e6, "algorithmic_bytes_per_node": 229, "achieved_GBps": ach,
+            "frac": ach / HBM_PEAK_GBS}
 
 
 def _home_leg(scene, sim, steps):
@@ -247,15 +368,127 @@ def _surrogate_leg(n_rollouts, train_steps):
     t_lbm = _graph_ms(lbm_block)
     flops = 120_960 * L * B
     tfl = flops / (t_sur * 1e-3) / 1e12
-    return {"speedup": t_lbm / t_sur, "wind_error_mean": e.mean().item(), "wind_error_max": e.max().item(),
+    step = _surrogate_step_timing(net)
+    return {"speedup": step["speedup"], "wind_error_mean": e.mean().item(), "wind_error_max": e.max().item(),
             "persistence_error_mean": e_id.mean().item(), "persistence_error_max": e_id.max().item(),
-            "accepted_by_checks": ok.float().mean().item(), "ms_surrogate_b16": t_sur, "ms_lbm_8steps_b16": t_lbm,
+            "accepted_by_checks": ok.float().mean().item(), "step_256x128x128": step,
+            "forward_only_b16": {"ms_surrogate": t_sur, "ms_lbm_8steps": t_lbm, "ratio": t_lbm / t_sur},
             "roofline": {"bound": "mfma", "achieved": tfl, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": tfl / BF16_PEAK_TFLOPS, "flop_per_voxel": 120_960},
+            "_net": net,
             "config": {"workload": "64^3 wind tunnels with 1-4 obstacle boxes, inflow 0.02-0.1, tau 0.6; "
                                    "pairs (u_t, u_t+8), t in [200, 1000]; inference batch 16",
                        "pairs": int(U0.shape[0]), "train_pairs": n_train, "train_steps": train_steps,
                        "train_s": t_train, "data_s": t_data}}
+
+
+def _surrogate_step_timing(net, dims3=(256, 128, 128), warm=800):
+    """The whole surrogate step against the 8 LBM steps it replaces, on one
+    lattice of the same node count as the largest workload's: prediction,
+    divergence and energy checks, the device-side decision, the LBM fallback
+    branch (switched off by the decision) and the output selection, captured
+    in one HIP graph; the 8 BGK steps in another.  The flow is a developed
+    tunnel flow around obstacle boxes (`warm` steps: the 256-long tunnel
+    takes about four times the 64^3 tunnels' warm-up of 200 steps)."""
+    import torch
+    from paper_2603_09668_amd import api, scenes
+    from paper_2603_09668_amd import surrogate as sg
+    nx, ny, nz = dims3
+    L = nx * ny * nz
+    spd, solid_np, bc = scenes.wind_tunnel_obstacles(5, dims3)
+    lat = api.make_lattice(nx, ny, nz)
+    solid = torch.tensor(solid_np.reshape(-1), dtype=torch.uint8, device="cuda")
+    kw = dict(tau=0.6, u_in=(spd, 0.0, 0.0), bc=bc)
+    fa = torch.empty(19, L, device="cuda")
+    fb = torch.empty_like(fa)
+    u = torch.empty(1, 3, L, device="cuda")
+    api.lbm_equilibrium(lat, api.make_lbm_params(**kw), fa)
+    for t in range(1, warm + 1):
+        api.lbm_step(lat, api.make_lbm_params(**kw, t=t), fa, fb, solid, None, u[0])
+        fa, fb = fb, fa
+    prms = [api.make_lbm_params(**kw, t=warm + j + 1) for j in range(8)]
+    u8 = torch.empty(3, L, device="cuda")
+
+    def lbm8():
+        a, b = fa, fb
+        for j in range(8):
+            api.lbm_step(lat, prms[j], a, b, solid, None, u8 if j == 7 else None)
+            a, b = b, a
+
+    t_lbm = _graph_ms(lbm8, reps=10)
+    sw = sg.SurrogateWind(net, lat, kw, solid, k=8, batch=1)
+    scale = torch.tensor([spd], device="cuda")
+    uo = torch.empty_like(u)
+    t_step = _graph_ms(lambda: sw.advance_device(u, scale, uo, t0=warm), reps=10)
+    t_fwd = _graph_ms(lambda: net.forward(u, scale, sw.u_pred, sw.dims), reps=10)
+    accepted = int(sw.accept.item())
+    err = sg.rel_error(uo, u8.view(1, 3, L), solid.view(1, -1)).item()
+    err_id = sg.rel_error(u, u8.view(1, 3, L), solid.view(1, -1)).item()
+    flops = 120_960 * L
+    del fa, fb, u, uo, u8, sw
+    torch.cuda.empty_cache()
+    return {"lattice": list(dims3), "ms_surrogate_step": t_step, "ms_net_forward": t_fwd, "ms_lbm_8steps": t_lbm,
+            "speedup": t_lbm / t_step, "accepted": accepted, "wind_error_vs_lbm": err,
+            "persistence_error_vs_lbm": err_id,
+            "roofline_net": {"bound": "mfma", "achieved": flops / (t_fwd * 1e-3) / 1e12, "peak": BF16_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": flops / (t_fwd * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}}
+
+
+def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
+    """The largest workload driven three ways for `substeps` coupled substeps
+    from the same developed flow (`warm` LBM steps around the particles at
+    rest): the LBM every substep (the reference), the surrogate replacing
+    every block of 8 LBM steps (with its device-side checks and LBM
+    fallback), and a frozen wind.  Reports each run's time per substep and,
+    against the LBM-driven run, the final wind error over fluid nodes and the
+    error of the particle displacements."""
+    import torch
+    from paper_2603_09668_amd import scenes
+    from paper_2603_09668_amd.sim import CoupledSim
+    scene = scenes.flag_and_leaves_scene(seed=0, n=n, res=res, lbm_dims=(res, res // 2, res // 2))
+    res_ = {}
+    for model in ("lbm", "surrogate", "frozen"):
+        sim = CoupledSim(scene, wind=model, surrogate=net if model == "surrogate" else None)
+        sim.warm_wind(warm)
+        acc = torch.zeros(1, dtype=torch.int32, device="cuda")
+        calls = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(substeps):
+            if model == "surrogate" and sim.t % sim.k == 0:
+                calls += 1
+                sim.step()
+                acc += sim.sw.accept
+            else:
+                sim.step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res_[model] = {"ms_per_substep": el * 1e3 / substeps, "status": sim.status(),
+                       "u": sim.u.clone(), "solid": sim.solid.clone(),
+                       "disp": sim.in_scene_order(sim.p.x).clone()}
+        if model == "surrogate":
+            res_[model]["surrogate_calls"] = calls
+            res_[model]["accepted_calls"] = int(acc.item())
+        del sim
+        torch.cuda.empty_cache()
+    ref = res_["lbm"]
+    fluid = (ref["solid"] == 0).float()[None]
+    un = torch.sqrt(((ref["u"] ** 2) * fluid).sum()).item()
+    dn = torch.linalg.vector_norm(ref["disp"]).item()
+    out = {"config": {"workload": f"coupled substep, {n} particles, {res}^3 grid, {res}x{res // 2}x{res // 2} "
+                                  f"lattice, {substeps} substeps from {warm} LBM warm-up steps",
+                      "substeps": substeps, "warm_lbm_steps": warm}}
+    for model in ("lbm", "surrogate", "frozen"):
+        r = res_[model]
+        e = {"ms_per_substep": r["ms_per_substep"], "status": r["status"]}
+        if model != "lbm":
+            e["wind_error_vs_lbm"] = torch.sqrt((((r["u"] - ref["u"]) ** 2) * fluid).sum()).item() / un
+            e["displacement_error_vs_lbm"] = torch.linalg.vector_norm(r["disp"] - ref["disp"]).item() / dn
+        for k in ("surrogate_calls", "accepted_calls"):
+            if k in r:
+                e[k] = r[k]
+        out[model] = e
+    return out
 
 
 def _adjoint_leg(n, res, n_sub, ckpt, n_fd):
@@ -329,8 +562,14 @@ def _adjoint_leg(n, res, n_sub, ckpt, n_fd):
             fd = (loss_of(Wp.reshape(W0.shape), E0) - loss_of(Wm.reshape(W0.shape), E0)).item() / (2 * h)
             errs.append(abs(fd - flat[c].item()) / max(abs(fd), 1e-30))
     errs = np.array(errs) if errs else np.zeros(1)
+    # reverse substep: the segment recompute (sort 24, P2G 120, G2P 156 B per
+    # particle) plus the adjoints (G2P 252, P2G 312 B per particle)
+    b_rev = 864 * sc.n
+    ach = b_rev / (t_bwd * 1e-3 / n_sub) / 1e9
     return {"ms_forward": t_fwd, "ms_backward": t_bwd, "us_per_substep_forward": 1e3 * t_fwd / n_sub,
             "us_per_substep_backward": 1e3 * t_bwd / n_sub, "loss": L.item(),
+            "roofline_backward": {"bound": "hbm", "algorithmic_bytes_per_particle": 864, "achieved_GBps": ach,
+                                  "frac": ach / HBM_PEAK_GBS},
             "fd_check": {"coordinates": int(n_fd), "rel_err_median": float(np.median(errs)),
                          "rel_err_max": float(errs.max()), "step": "0.05 x field amplitude, float32 forward"},
             "config": {"workload": f"reconstruction gradient: {sc.n} particles, {res}^3 grid, {n_sub} substeps, "
@@ -338,9 +577,31 @@ def _adjoint_leg(n, res, n_sub, ckpt, n_fd):
                        "particles": sc.n, "grid": res, "substeps": n_sub, "checkpoint_every": ckpt}}
 
 
-def _cpu_baseline(scene, substeps):
-    """The float64 oracle on the host: `substeps` coupled substeps (LBM step,
-    drag wind, MPM substep) of the full scene."""
+def _cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _cpu_baseline(scene, substeps, substeps_1t=1, lbm_steps=4):
+    """The float64 oracle on the host: `substeps` coupled substeps (voxelize,
+    LBM step, drag wind, MPM substep) of the full scene with torch's threads,
+    the same with one thread for `substeps_1t` substeps, and the LBM step
+    alone on the scene's lattice (`lbm_steps` steps)."""
     import torch
     from oracle import lbm as olbm
     from oracle import mpm as ompm
@@ -349,8 +610,6 @@ def _cpu_baseline(scene, substeps):
     og = ompm.Grid(g["nx"], g["ny"], g["nz"], g["dx"], tuple(g["origin"]))
     n = scene.n
     d = torch.float64
-    st = {"x": torch.tensor(scene.x), "v": torch.zeros(n, 3, dtype=d), "C": torch.zeros(n, 3, 3, dtype=d),
-          "F": torch.eye(3, dtype=d).repeat(n, 1, 1)}
     mu, lam = ompm.particle_mu_lam(torch.tensor(scene.E), torch.tensor(scene.nu), torch.tensor(scene.region).long())
     lat = scene.lattice
     ol = olbm.Lattice(lat["nx"], lat["ny"], lat["nz"], lat["dx"], tuple(lat["origin"]))
@@ -359,21 +618,44 @@ def _cpu_baseline(scene, substeps):
                         gust_period=lb["gust_period"], gust_ky=lb["gust_ky"], gust_kz=lb["gust_kz"],
                         gust_phase=lb["gust_phase"])
     u0 = torch.tensor(lb["u_in"], dtype=d).view(3, 1, 1, 1).expand(3, ol.nz, ol.ny, ol.nx)
-    f = olbm.equilibrium(torch.ones(ol.nz, ol.ny, ol.nx, dtype=d), u0)
     mass, vol0, pin = torch.tensor(scene.mass), torch.tensor(scene.vol0), torch.tensor(scene.pin)
+
+    def run(k):
+        st = {"x": torch.tensor(scene.x), "v": torch.zeros(n, 3, dtype=d), "C": torch.zeros(n, 3, 3, dtype=d),
+              "F": torch.eye(3, dtype=d).repeat(n, 1, 1)}
+        f = olbm.equilibrium(torch.ones(ol.nz, ol.ny, ol.nx, dtype=d), u0)
+        t0 = time.perf_counter()
+        for s in range(k):
+            solid = olbm.voxelize(ol, st["x"])
+            f, rho, u = olbm.lbm_step(ol, op, f, solid, s)
+            acc = owind.lbm_drag_to_nodes(og, ol.dims, ol.dx, ol.origin, u.reshape(3, -1), scene.wind["vel_scale"],
+                                          scene.wind["k_drag"])
+            st, _ = ompm.substep(og, st, mass, vol0, mu, lam, scene.dt, scene.material, gravity=scene.gravity,
+                                 acc=acc, pin=pin, bound=scene.bound)
+        return time.perf_counter() - t0
+
+    threads = torch.get_num_threads()
+    el = run(substeps)
+    torch.set_num_threads(1)
+    try:
+        el1 = run(substeps_1t)
+    finally:
+        torch.set_num_threads(threads)
+    f = olbm.equilibrium(torch.ones(ol.nz, ol.ny, ol.nx, dtype=d), u0)
+    solid = torch.zeros(ol.nz, ol.ny, ol.nx, dtype=torch.bool)
     t0 = time.perf_counter()
-    for s in range(substeps):
-        solid = olbm.voxelize(ol, st["x"])
-        f, rho, u = olbm.lbm_step(ol, op, f, solid, s)
-        acc = owind.lbm_drag_to_nodes(og, ol.dims, ol.dx, ol.origin, u.reshape(3, -1), scene.wind["vel_scale"],
-                                      scene.wind["k_drag"])
-        st, _ = ompm.substep(og, st, mass, vol0, mu, lam, scene.dt, scene.material, gravity=scene.gravity, acc=acc,
-                             pin=pin, bound=scene.bound)
-    el = time.perf_counter() - t0
-    return {"value": n * substeps / el, "unit": "particle-substeps/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+    for s in range(lbm_steps):
+        f, _, _ = olbm.lbm_step(ol, op, f, solid, s)
+    el_l = time.perf_counter() - t0
+    return {"value": n * substeps / el, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
             "sample": f"{substeps} coupled substeps (voxelize, LBM step, drag wind, MPM substep) of the full "
-                      f"{n}-particle scene, float64, {el:.1f} s"}
+                      f"{n}-particle scene, float64, {el:.1f} s on {threads} threads",
+            "one_thread": {"value": n * substeps_1t / el1, "unit": "particle-substeps/s",
+                           "sample": f"{substeps_1t} coupled substeps, {el1:.1f} s"},
+            "lbm_mlups": ol.n_nodes * lbm_steps / el_l / 1e6,
+            "lbm_sample": f"{lbm_steps} BGK steps of the {ol.nx}x{ol.ny}x{ol.nz} lattice, {el_l:.1f} s",
+            "os_cpu_count": os.cpu_count(), "cpu_model": _cpu_model(),
+            "note": "CPU float64 oracle: a baseline, not the target"}
 
 
 def main():
@@ -399,7 +681,11 @@ def main():
         print(json.dumps({"metric": METRIC, "adjoint": _adjoint_leg(256_000, 96, 256, 16, a.fd)}), flush=True)
         return
     if a.surrogate_only:
-        print(json.dumps({"metric": METRIC, "surrogate": _surrogate_leg(a.sg_rollouts, a.sg_steps)}), flush=True)
+        sgo = _surrogate_leg(a.sg_rollouts, a.sg_steps)
+        net = sgo.pop("_net")
+        if not a.no_largest:
+            sgo["coupled_largest"] = _surrogate_coupled_leg(net)
+        print(json.dumps({"metric": METRIC, "surrogate": sgo}), flush=True)
         return
 
     scene = scenes.flag_and_leaves_scene(seed=0, n=a.n, res=a.res, lbm_dims=(a.res, a.res // 2, a.res // 2))
@@ -434,43 +720,14 @@ def main():
     # per-phase launch times: each phase alone, R launches in one graph, timed
     # with HIP events on the stream the kernels are launched on
     phases = CoupledSim.PHASES
-    scratch = [torch.empty_like(t) for t in (sim.p.x, sim.p.v, sim.p.C, sim.p.F)]
-
-    def g2p_out_of_place():
-        api.mpm_g2p(sim.grid, sim.prm, sim.gv, sim.p, *scratch)
-
-    R = 10
-    ph_ms = {}
-    for ph in phases:
-        fn = g2p_out_of_place if ph == "g2p" else getattr(sim, ph)
-        gph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(gph):
-            for _ in range(R):
-                fn()
-        gph.replay()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 5
-        e0.record()
-        for _ in range(reps):
-            gph.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        ph_ms[ph] = e0.elapsed_time(e1) / (reps * R)
+    ph_ms = _phase_times(sim)
     lbm_ms = ph_ms["lbm"]
     mlups = sim.L / (lbm_ms * 1e-3) / 1e6
 
     n = scene.n
     value = n * a.steps / elapsed
     # algorithmic bytes per launch
-    bytes_per = {
-        "p2g": 108 * n + 16 * active_nodes,          # read x v C F m V0 region; write m, mv
-        "g2p": 144 * n + 12 * active_nodes,          # read x F, write x v C F; read grid v
-        "lbm": 153 * sim.L + 12 * sim.L,             # 19 pops in + out, solid, u out
-        "grid_update": 29 * active_nodes,            # read m mv pin, write v
-        "voxelize": 12 * n + sim.L,
-        "sort": 12 * n,
-    }
+    bytes_per = _phase_bytes(sim, active_nodes)
     dominant = max(phases, key=lambda ph: ph_ms[ph])
     ach = bytes_per.get(dominant, 0) / (ph_ms[dominant] * 1e-3) / 1e9
     out = {
@@ -501,7 +758,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant, a.n, a.res),
                      "algorithmic_bytes": bytes_per.get(dominant)},
+        "rooflines": _rooflines(ph_ms, bytes_per),
     }
+    out["lbm_adjoint"] = _lbm_adj_leg(sim)
+    out["copy_bandwidth"] = _copy_bandwidth()
     # covariance of the Gaussian kernels bound to the particles (Sec. 3.2)
     sig0 = torch.zeros(6, sim.p.n, device="cuda")
     sig0[:3] = (0.3 * scene.grid["dx"]) ** 2
@@ -512,12 +772,18 @@ def main():
     del sig0, sig
     if not a.no_home:
         out["home_lbm"] = _home_leg(scene, sim, min(a.steps, 100))
+    if not a.no_largest:
+        out["largest"] = _largest_leg()
     if not a.no_surrogate:
-        del sim, scratch
+        del sim
         torch.cuda.empty_cache()
         sgo = _surrogate_leg(a.sg_rollouts, a.sg_steps)
+        net = sgo.pop("_net")
         out["surrogate_speedup"] = sgo["speedup"]
         out["surrogate"] = sgo
+        if not a.no_largest:
+            out["surrogate"]["coupled_largest"] = _surrogate_coupled_leg(net)
+        del net
     if not a.no_adjoint:
         out["adjoint"] = _adjoint_leg(256_000, 96, 256, 16, a.fd)
     if not a.no_recon:

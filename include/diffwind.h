@@ -159,6 +159,10 @@ typedef struct {
   float vel_scale, k_drag;
   /* DW_WIND_ACC: precomputed acceleration [3][N] (e.g. from wind_to_grid) */
   const float *acc;
+  /* 1: wind_to_grid_adj sums its transpose in a fixed order (every wind-grid
+   * or lattice node gathers the MPM nodes it feeds; no atomics, bit
+   * reproducible, slower); 0: float atomics */
+  int deterministic;
 } dw_wind;
 
 typedef struct {
@@ -176,6 +180,11 @@ typedef struct {
    * alias t_in -- swap the two like the population buffers). */
   const int32_t *t_in;
   int32_t *t_out;
+  /* Optional device flag read by lbm_step and lbm_equilibrium: if skip is not
+   * NULL and *skip != 0 the call does nothing (no output, no step counter).
+   * Lets a captured HIP graph hold a branch that a device-side decision
+   * switches off, e.g. the LBM fallback of an accepted surrogate step. */
+  const int32_t *skip;
 } dw_lbm_params;
 
 /* ---------------------------------------------------------------- errors */
@@ -259,10 +268,13 @@ int wind_to_grid(const dw_grid *grid, const dw_wind *wind, float *acc, void *str
 /* Reverse of mpm_p2g, a gather per particle: given m_bar [N] and mv_bar [3][N]
  * (read at stencil nodes), accumulates into bar->x, v, C, F and E_bar
  * [n_regions] (NULL to skip).  Mass and volume are constants; so is p->xref
- * (bar->x is the adjoint of the position, i.e. of the displacement x). */
+ * (bar->x is the adjoint of the position, i.e. of the displacement x).
+ * E_bar is summed over particles with float atomics, or, with
+ * params->deterministic, in a fixed order through the scratch of a
+ * deterministic workspace `ws` (then required; else ws may be NULL). */
 int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p,
                 const float *grid_m_bar, const float *grid_mv_bar, dw_particles_bar *bar,
-                float *E_bar, void *stream);
+                float *E_bar, void *ws, size_t ws_bytes, void *stream);
 
 /* Reverse of mpm_grid_update on the active node tiles of `ws` (same sort as
  * the forward).  Recomputes the wall/pin masks from the forward inputs;
@@ -279,7 +291,10 @@ int mpm_grid_update_adj(const dw_grid *grid, const dw_mpm_params *params, const 
 /* Reverse of mpm_g2p, a sorted scatter: reads the forward inputs in->x,
  * in->xref, in->F and grid_v, the output adjoints out_bar (x, v, C, F; any may be
  * NULL = zero); accumulates into in_bar->x, in_bar->F and grid_v_bar [3][N].
- * Uses the sort in `ws`, which must come from mpm_sort on the same in->x. */
+ * Uses the sort in `ws`, which must come from mpm_sort on the same in->x.
+ * With params->deterministic (and a deterministic workspace and sort) the
+ * grid_v_bar scatter sums in a fixed order without atomics, as the
+ * deterministic mpm_p2g does. */
 int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, const float *grid_v,
                 const dw_particles *in, const dw_particles_bar *out_bar,
                 dw_particles_bar *in_bar, float *grid_v_bar, const void *ws, size_t ws_bytes,
@@ -316,8 +331,8 @@ int gaussian_covariance_adj(int n, const float *H, const float *sigma0, const fl
  * of W [3][n] (reconstructed force field) and guide [3][n] (LBM velocity at
  * the nodes, see wind_guide); nodes where either vector is zero contribute
  * nothing.  ADDS weight * L_phys to *loss (if not NULL) and
- * weight * dL_phys/dW to W_bar [3][n] (if not NULL).  Float atomics: the
- * last bits of *loss depend on the order the blocks finish in. */
+ * weight * dL_phys/dW to W_bar [3][n] (if not NULL).  One workgroup sums
+ * the loss in a fixed node order, so both outputs are bit-reproducible. */
 int phys_loss(int n, const float *W, const float *guide, float weight, float *loss, float *W_bar, void *stream);
 
 /* Position loss sum_p |x_p - x*_p|^2 over n particles (the synthetic stand-in
@@ -509,6 +524,24 @@ int adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr,
  * mask per field, nonzero = solid) or NULL.  out is added to (zero it first);
  * the order of the float additions is not fixed. */
 int field_stats(int B, int nx, int ny, int nz, const float *u, const uint8_t *solid, float *out, void *stream);
+
+/* Device-side acceptance of surrogate predictions (no host
+ * synchronisation, capturable in a HIP graph).  stats_prev and stats_pred
+ * [B][3] are field_stats of the input fields and of the predictions;
+ * accept[b] = 1 iff the prediction's RMS central-difference divergence is at
+ * most div_factor times the input's and its kinetic energy lies in
+ * [ke_lo, ke_hi] times the input's (a non-finite prediction fails both);
+ * else 0.  reject [B] (nullable) receives 1 - accept: as the `skip` flag of
+ * dw_lbm_params, accept switches the LBM fallback off and reject switches a
+ * branch on only for rejected fields. */
+int field_accept(int B, const float *stats_prev, const float *stats_pred, float div_factor, float ke_lo, float ke_hi,
+                 int32_t *accept, int32_t *reject, void *stream);
+
+/* u_out [B][3][L] = accept[b] ? u_pred with zero velocity on solid nodes
+ * (solid [B][L] nullable, as lbm_step reports solids) : u_alt.  u_out may
+ * alias either input. */
+int field_select(int B, int nx, int ny, int nz, const int32_t *accept, const float *u_pred, const float *u_alt,
+                 const uint8_t *solid, float *u_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ SYMBOLS = [
     "lbm_solid_from_particles", "gaussian_covariance", "gaussian_covariance_adj",
     "phys_loss", "position_loss", "direction_metrics", "wind_guide",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
-    "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats",
+    "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats", "field_accept", "field_select",
 ]
 CONV_HIDDEN, CONV_OUTPUT, CONV_DGRAD = 0, 1, 2
 
@@ -65,14 +65,14 @@ class ParticlesBar(ctypes.Structure):
 class Wind(ctypes.Structure):
     _fields_ = [("mode", c_int), ("nw", c_int * 3), ("lo", c_float * 3), ("hi", c_float * 3),
                 ("W", c_void_p), ("lat", Lattice), ("u", c_void_p), ("vel_scale", c_float),
-                ("k_drag", c_float), ("acc", c_void_p)]
+                ("k_drag", c_float), ("acc", c_void_p), ("deterministic", c_int)]
 
 
 class LBMParams(ctypes.Structure):
     _fields_ = [("tau", c_float), ("u_in", c_float * 3), ("force", c_float * 3), ("bc", c_int * 6),
                 ("gust_amp", c_float), ("gust_period", c_float), ("gust_ky", c_float),
                 ("gust_kz", c_float), ("gust_phase", c_float), ("t", c_int), ("t_in", c_void_p),
-                ("t_out", c_void_p)]
+                ("t_out", c_void_p), ("skip", c_void_p)]
 
 
 _lib = None
@@ -99,7 +99,7 @@ def lib():
         "mpm_reorder": ([POINTER(Grid), POINTER(Particles), POINTER(Particles), P, P, c_size_t, P], c_int),
         "wind_to_grid": ([POINTER(Grid), POINTER(Wind), P, P], c_int),
         "mpm_p2g_adj": ([POINTER(Grid), POINTER(MPMParams), POINTER(Particles), P, P, POINTER(ParticlesBar), P,
-                         P], c_int),
+                         P, c_size_t, P], c_int),
         "mpm_grid_update_adj": ([POINTER(Grid), POINTER(MPMParams), P, P, POINTER(Wind), P, P, P, P, P, P,
                                  c_size_t, P], c_int),
         "mpm_g2p_adj": ([POINTER(Grid), POINTER(MPMParams), P, POINTER(Particles), POINTER(ParticlesBar),
@@ -128,6 +128,8 @@ def lib():
         "conv_mse_grad": ([c_int, c_int, c_int, c_int, P, P, P, P, P, P], c_int),
         "adam_step": ([P, P, P, P, ctypes.c_int64, c_float, c_float, c_float, c_float, c_int, P], c_int),
         "field_stats": ([c_int, c_int, c_int, c_int, P, P, P, P], c_int),
+        "field_accept": ([c_int, P, P, c_float, c_float, c_float, P, P, P], c_int),
+        "field_select": ([c_int, c_int, c_int, c_int, P, P, P, P, P, P], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -186,20 +188,23 @@ def make_mpm_params(dt, gravity=(0.0, 0.0, 0.0), bound=3, material=FIXED_COROTAT
 
 def make_lbm_params(tau, u_in=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0), bc=(BC_PERIODIC,) * 6, gust_amp=0.0,
                     gust_period=1.0, gust_ky=0.0, gust_kz=0.0, gust_phase=0.0, t=0, t_in=None,
-                    t_out=None) -> LBMParams:
-    """t_in / t_out: optional device int32 step counters (see the header)."""
+                    t_out=None, skip=None) -> LBMParams:
+    """t_in / t_out: optional device int32 step counters; skip: optional
+    device int32 flag that switches the call off (see the header)."""
     return LBMParams(float(tau), (c_float * 3)(*u_in), (c_float * 3)(*force), (c_int * 6)(*bc),
                      float(gust_amp), float(gust_period), float(gust_ky), float(gust_kz), float(gust_phase),
-                     int(t), _ptr(t_in, torch.int32, "t_in"), _ptr(t_out, torch.int32, "t_out"))
+                     int(t), _ptr(t_in, torch.int32, "t_in"), _ptr(t_out, torch.int32, "t_out"),
+                     _ptr(skip, torch.int32, "skip"))
 
 
 def wind_none() -> Wind:
     return Wind(mode=WIND_NONE)
 
 
-def wind_force_grid(W_slot, nw, lo, hi) -> Wind:
-    """W_slot: (3, nw_z*nw_y*nw_x) device float32 (one time slot)."""
-    w = Wind(mode=WIND_FORCE_GRID)
+def wind_force_grid(W_slot, nw, lo, hi, deterministic: bool = False) -> Wind:
+    """W_slot: (3, nw_z*nw_y*nw_x) device float32 (one time slot);
+    deterministic: fixed-order transpose in wind_to_grid_adj."""
+    w = Wind(mode=WIND_FORCE_GRID, deterministic=int(bool(deterministic)))
     w.nw = (c_int * 3)(*nw)
     w.lo = (c_float * 3)(*lo)
     w.hi = (c_float * 3)(*hi)
@@ -208,10 +213,11 @@ def wind_force_grid(W_slot, nw, lo, hi) -> Wind:
     return w
 
 
-def wind_lbm_drag(lat: Lattice, u, vel_scale, k_drag, relative: bool = False) -> Wind:
+def wind_lbm_drag(lat: Lattice, u, vel_scale, k_drag, relative: bool = False, deterministic: bool = False) -> Wind:
     """LBM drag wind; relative=True takes the wind relative to the node
-    velocity (evaluated by mpm_grid_update only)."""
-    w = Wind(mode=WIND_LBM_DRAG_REL if relative else WIND_LBM_DRAG)
+    velocity (evaluated by mpm_grid_update only); deterministic: fixed-order
+    transpose in wind_to_grid_adj."""
+    w = Wind(mode=WIND_LBM_DRAG_REL if relative else WIND_LBM_DRAG, deterministic=int(bool(deterministic)))
     w.lat = lat
     w.u = _ptr(u, name="u")
     w.vel_scale = float(vel_scale)
@@ -341,12 +347,15 @@ def wind_to_grid(grid: Grid, wind: Wind, acc):
 
 
 def mpm_p2g_adj(grid: Grid, params: MPMParams, p: ParticleArrays, grid_m_bar, grid_mv_bar, x_bar=None, v_bar=None,
-                C_bar=None, F_bar=None, E_bar=None):
+                C_bar=None, F_bar=None, E_bar=None, ws=None):
+    """ws: a deterministic workspace, needed for the fixed-order E_bar of
+    params.deterministic."""
     ps = p.struct()
     bar = _bar_struct(p.n, x_bar, v_bar, C_bar, F_bar)
     _check(lib().mpm_p2g_adj(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(ps),
                              _ptr(grid_m_bar, name="grid_m_bar"), _ptr(grid_mv_bar, name="grid_mv_bar"),
-                             ctypes.byref(bar), _ptr(E_bar, name="E_bar"), _stream()), "mpm_p2g_adj")
+                             ctypes.byref(bar), _ptr(E_bar, name="E_bar"), _ptr(ws, torch.uint8, "ws"),
+                             0 if ws is None else ws.numel(), _stream()), "mpm_p2g_adj")
 
 
 def mpm_grid_update_adj(grid: Grid, params: MPMParams, grid_m, grid_mv, wind: Wind | None, pin, grid_v_bar,
@@ -640,3 +649,22 @@ def field_stats(dims, u, solid, out):
     B, nx, ny, nz = dims
     _check(lib().field_stats(B, nx, ny, nz, _ptr(u, name="u"), _ptr(solid, torch.uint8, "solid"),
                              _ptr(out, name="out"), _stream()), "field_stats")
+
+
+def field_accept(stats_prev, stats_pred, accept, reject=None, div_factor=2.0, ke_band=(0.9, 1.1)):
+    """accept[b] (int32) = the prediction passes the divergence and energy
+    checks; reject = 1 - accept (see the header)."""
+    B = accept.shape[0]
+    _shape(stats_prev, (B, 3), "stats_prev")
+    _shape(stats_pred, (B, 3), "stats_pred")
+    _check(lib().field_accept(B, _ptr(stats_prev, name="stats_prev"), _ptr(stats_pred, name="stats_pred"),
+                              float(div_factor), float(ke_band[0]), float(ke_band[1]),
+                              _ptr(accept, torch.int32, "accept"), _ptr(reject, torch.int32, "reject"), _stream()),
+           "field_accept")
+
+
+def field_select(dims, accept, u_pred, u_alt, solid, u_out):
+    B, nx, ny, nz = dims
+    _check(lib().field_select(B, nx, ny, nz, _ptr(accept, torch.int32, "accept"), _ptr(u_pred, name="u_pred"),
+                              _ptr(u_alt, name="u_alt"), _ptr(solid, torch.uint8, "solid"), _ptr(u_out, name="u_out"),
+                              _stream()), "field_select")

@@ -17,6 +17,10 @@ transpose into W_bar, P2G adjoint (per-particle gather, also giving E_bar).
 Every step runs in the library's HIP kernels; torch provides device memory,
 zero-fills (one per buffer group) and the final loss.
 
+With `deterministic` every reduction of the forward and reverse substeps
+runs in a fixed order (sort, P2G, the reverse G2P's grid scatter, the E and
+force-grid adjoints), so a rollout's gradients are bit-identical run to run.
+
 With `xref` the positions are xref + x: the rollout's x input and output are
 displacements from that fixed reference (see the header), which keeps their
 float32 resolution on the motion.
@@ -39,19 +43,20 @@ class RolloutPlan:
 
     def __init__(self, grid: dict, n: int, mass, vol0, region, nu, pin, dt: float, gravity, material: int,
                  bound: int, nw, box_lo, box_hi, K: int, n_sub: int, ckpt: int = 16, device="cuda",
-                 xref=None):
+                 xref=None, deterministic: bool = False):
         self.grid = api.make_grid(grid["nx"], grid["ny"], grid["nz"], grid["dx"], grid["origin"])
         self.N = grid["nx"] * grid["ny"] * grid["nz"]
         self.n = n
         self.mass, self.vol0, self.region, self.nu = mass, vol0, region, nu
         self.pin = pin
         self.xref = xref
-        self.prm = api.make_mpm_params(dt, gravity, bound, material)
+        self.deterministic = bool(deterministic)
+        self.prm = api.make_mpm_params(dt, gravity, bound, material, deterministic=self.deterministic)
         self.nw, self.box_lo, self.box_hi, self.K = tuple(nw), tuple(box_lo), tuple(box_hi), K
         self.n_sub, self.ckpt = n_sub, ckpt
         f = dict(dtype=torch.float32, device=device)
         self.device = device
-        self.ws = api.alloc_workspace(self.grid, n, device)
+        self.ws = api.alloc_workspace(self.grid, n, device, deterministic=self.deterministic)
         self.gm = torch.zeros(self.N, **f)
         self.gmv = torch.zeros(3, self.N, **f)
         self.gv = torch.zeros(3, self.N, **f)
@@ -66,7 +71,8 @@ class RolloutPlan:
         """Sort workspaces and grids (m, mv, v) for the substeps of one segment."""
         if self._seg is None:
             f = dict(dtype=torch.float32, device=self.device)
-            self._seg = [(api.alloc_workspace(self.grid, self.n, self.device), torch.empty(self.N, **f),
+            self._seg = [(api.alloc_workspace(self.grid, self.n, self.device, deterministic=self.deterministic),
+                          torch.empty(self.N, **f),
                           torch.empty(3, self.N, **f), torch.empty(3, self.N, **f)) for _ in range(self.ckpt)]
         return self._seg
 
@@ -87,7 +93,8 @@ class RolloutPlan:
                                     "the kernels skipped it, so the result would be truncated")
 
     def wind(self, W, s):
-        return api.wind_force_grid(W[self.slot(s)], self.nw, self.box_lo, self.box_hi)
+        return api.wind_force_grid(W[self.slot(s)], self.nw, self.box_lo, self.box_hi,
+                                   deterministic=self.deterministic)
 
     # --------------------------------------------------------------- forward
     def substep(self, p: api.ParticleArrays, W, s: int, out=None, bufs=None, g2p: bool = True):
@@ -123,7 +130,7 @@ class RolloutPlan:
         api.mpm_g2p_adj(g, prm, gv, p, *bar_out, x_bar=xb, F_bar=Hb, grid_v_bar=self.gvb, ws=ws)
         api.mpm_grid_update_adj(g, prm, gm, gmv, wind, self.pin, self.gvb, self.gmb, self.gmvb, self.accb, ws)
         api.wind_to_grid_adj(g, wind, self.accb, W_bar[self.slot(s)])
-        api.mpm_p2g_adj(g, prm, p, self.gmb, self.gmvb, xb, vb, Cb, Hb, E_bar)
+        api.mpm_p2g_adj(g, prm, p, self.gmb, self.gmvb, xb, vb, Cb, Hb, E_bar, ws=ws)
 
 
 class _RolloutFn(torch.autograd.Function):

@@ -63,6 +63,7 @@ size_t workspace_layout(const dw_grid *g, int n_max, Workspace *ws, void *base, 
   ws->item_first = take(sizeof(int32_t) * T);
   // the deterministic scratch ends the layout, so the two sizes share a prefix
   ws->item_part = deterministic ? (float *)take(sizeof(float) * 4 * 216 * (size_t)max_items) : nullptr;
+  ws->item_part_floats = deterministic ? 4 * 216 * max_items : 0;
   ws->n_tiles = T;
   ws->n_scan_blocks = NB;
   ws->bytes = off;

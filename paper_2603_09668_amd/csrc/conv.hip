@@ -634,6 +634,42 @@ __global__ __launch_bounds__(256) void k_field_stats(ConvGeom G, const float *__
   }
 }
 
+// Acceptance of surrogate fields on the device (no host synchronisation):
+// from field_stats of the input fields (prev) and of the predictions (new),
+// accept[b] = 1 iff the prediction's RMS divergence is at most div_factor
+// times the input's and its kinetic energy is within [ke_lo, ke_hi] times
+// the input's; a non-finite prediction makes its sums non-finite and fails
+// both comparisons.  reject[b] = 1 - accept[b] (the skip flag of the
+// fallback branch is the acceptance, its run flag the rejection).
+__global__ void k_field_accept(int B, const float *__restrict__ prev, const float *__restrict__ pred,
+                               float div_factor, float ke_lo, float ke_hi, int32_t *__restrict__ accept,
+                               int32_t *__restrict__ reject) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const float rms0 = sqrtf(prev[3 * b] / fmaxf(prev[3 * b + 1], 1.f));
+  const float rms1 = sqrtf(pred[3 * b] / fmaxf(pred[3 * b + 1], 1.f));
+  const float ratio = pred[3 * b + 2] / fmaxf(prev[3 * b + 2], 1e-30f);
+  const bool ok = (rms1 <= div_factor * rms0 + 1e-12f) && (ratio >= ke_lo) && (ratio <= ke_hi);
+  accept[b] = ok ? 1 : 0;
+  if (reject) reject[b] = ok ? 0 : 1;
+}
+
+// u_out[b] = accept[b] ? u_pred[b] with zero velocity on solid nodes : u_alt[b]
+__global__ void k_field_select(int B, int64_t L, const int32_t *__restrict__ accept, const float *__restrict__ u_pred,
+                               const float *__restrict__ u_alt, const uint8_t *__restrict__ solid,
+                               float *__restrict__ u_out) {
+  const int b = blockIdx.y;
+  const bool ok = accept[b] != 0;
+  const float *src = (ok ? u_pred : u_alt) + (int64_t)b * 3 * L;
+  const uint8_t *sb = solid ? solid + (int64_t)b * L : nullptr;
+  float *dst = u_out + (int64_t)b * 3 * L;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < L; v += (int64_t)gridDim.x * blockDim.x) {
+    const bool zero = ok && sb && sb[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c * L + v] = zero ? 0.f : src[c * L + v];
+  }
+}
+
 static int make_geom(int B, int nx, int ny, int nz, ConvGeom *G) {
   DW_REQUIRE(B >= 1 && nx >= 1 && ny >= 1 && nz >= 1, DW_EINVAL, "conv: bad field size");
   DW_REQUIRE(nx <= (1 << 20) && ny <= (1 << 20) && nz <= (1 << 20), DW_ERANGE, "conv: field too large");
@@ -806,4 +842,25 @@ extern "C" int field_stats(int B, int nx, int ny, int nz, const float *u, const 
   if (bx > 256) bx = 256;
   hipLaunchKernelGGL(k_field_stats, dim3(bx, B), dim3(256), 0, (hipStream_t)stream, G, u, solid, out);
   return check_launch("field_stats");
+}
+
+extern "C" int field_accept(int B, const float *stats_prev, const float *stats_pred, float div_factor, float ke_lo,
+                            float ke_hi, int32_t *accept, int32_t *reject, void *stream) {
+  DW_REQUIRE(B >= 1 && stats_prev && stats_pred && accept, DW_EINVAL, "field_accept: bad arguments");
+  DW_REQUIRE(reject != accept, DW_EINVAL, "field_accept: reject must not alias accept");
+  hipLaunchKernelGGL(k_field_accept, dim3(grid_blocks(B, 64)), dim3(64), 0, (hipStream_t)stream, B, stats_prev,
+                     stats_pred, div_factor, ke_lo, ke_hi, accept, reject);
+  return check_launch("field_accept");
+}
+
+extern "C" int field_select(int B, int nx, int ny, int nz, const int32_t *accept, const float *u_pred,
+                            const float *u_alt, const uint8_t *solid, float *u_out, void *stream) {
+  DW_REQUIRE(B >= 1 && B <= 65535 && nx >= 1 && ny >= 1 && nz >= 1, DW_EINVAL, "field_select: bad size");
+  DW_REQUIRE(accept && u_pred && u_alt && u_out, DW_EINVAL, "field_select: NULL pointer");
+  const int64_t L = (int64_t)nx * ny * nz;
+  unsigned bx = grid_blocks(L, 256);
+  if (bx > 2048) bx = 2048;
+  hipLaunchKernelGGL(k_field_select, dim3(bx, B), dim3(256), 0, (hipStream_t)stream, B, L, accept, u_pred, u_alt,
+                     solid, u_out);
+  return check_launch("field_select");
 }

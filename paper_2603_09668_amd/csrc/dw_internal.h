@@ -68,6 +68,7 @@ struct Workspace {
   int32_t *item_begin;
   int32_t *item_first;  // first work item of each cell tile
   float *item_part;     // deterministic mode: 6^3 x 4 partial node block per work item
+  int64_t item_part_floats;
   int64_t n_tiles;
   int64_t n_scan_blocks;
   size_t bytes;
@@ -295,6 +296,67 @@ __device__ __forceinline__ void kirchhoff_shift(const float *H, float mu, float 
     tau[4] += l;
     tau[8] += l;
   }
+}
+
+// Kirchhoff stress for the forward P2G.  Fixed-corotated through the left
+// stretch: with F = V R, (F - R) F^T = F F^T - V, so
+//   tau = 2 mu (B - V) + lam (J - 1) J I,  B = F F^T = I + E,  V = sqrt(B),
+// E = H + H^T + H H^T symmetric.  For |E|_F < 0.05 the binomial series
+//   B - V = E - (sqrt(I + E) - I) = E/2 + E^2/8 - E^3/16 + 5 E^4/128 - 7 E^5/256 + ...
+// (powers of one symmetric matrix commute, so every product stays
+// symmetric: six entries) is truncated after E^5; the first dropped term is
+// 21/1024 |E|^6, below 2e-8 of E/2 there, under float32 round-off.  Larger
+// strains take the polar decomposition of kirchhoff_shift.  Neo-Hookean is
+// kirchhoff_shift's closed form.
+// symmetric 3x3 as (xx, yy, zz, xy, xz, yz)
+__device__ __forceinline__ void sym_mul(const float *a, const float *b, float *c) {
+  c[0] = a[0] * b[0] + a[3] * b[3] + a[4] * b[4];
+  c[1] = a[3] * b[3] + a[1] * b[1] + a[5] * b[5];
+  c[2] = a[4] * b[4] + a[5] * b[5] + a[2] * b[2];
+  c[3] = a[0] * b[3] + a[3] * b[1] + a[4] * b[5];
+  c[4] = a[0] * b[4] + a[3] * b[5] + a[4] * b[2];
+  c[5] = a[3] * b[4] + a[1] * b[5] + a[5] * b[2];
+}
+
+__device__ __forceinline__ void kirchhoff_shift_p2g(const float *H, float mu, float lam, int material, float *tau,
+                                                    int32_t *status) {
+  if (material == DW_FIXED_COROTATED) {
+    // E = H + H^T + H H^T
+    float E[6];
+    E[0] = 2.f * H[0] + H[0] * H[0] + H[1] * H[1] + H[2] * H[2];
+    E[1] = 2.f * H[4] + H[3] * H[3] + H[4] * H[4] + H[5] * H[5];
+    E[2] = 2.f * H[8] + H[6] * H[6] + H[7] * H[7] + H[8] * H[8];
+    E[3] = H[1] + H[3] + H[0] * H[3] + H[1] * H[4] + H[2] * H[5];
+    E[4] = H[2] + H[6] + H[0] * H[6] + H[1] * H[7] + H[2] * H[8];
+    E[5] = H[5] + H[7] + H[3] * H[6] + H[4] * H[7] + H[5] * H[8];
+    const float e2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + 2.f * (E[3] * E[3] + E[4] * E[4] + E[5] * E[5]);
+    if (e2 < 0.0025f) {
+      const float Jm1 = det_shift(H);
+      if (!(Jm1 > -1.f) && status) atomicOr(status, DW_STATUS_INVERTED);
+      // Horner: T = c1 I + E (c2 I + E (c3 I + E (c4 I + c5 E))), B - V = E T
+      float T[6], U[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) T[i] = (-7.f / 256.f) * E[i];
+      T[0] += 5.f / 128.f; T[1] += 5.f / 128.f; T[2] += 5.f / 128.f;
+      sym_mul(E, T, U);
+      U[0] -= 1.f / 16.f; U[1] -= 1.f / 16.f; U[2] -= 1.f / 16.f;
+      sym_mul(E, U, T);
+      T[0] += 1.f / 8.f; T[1] += 1.f / 8.f; T[2] += 1.f / 8.f;
+      sym_mul(E, T, U);
+      U[0] += 0.5f; U[1] += 0.5f; U[2] += 0.5f;
+      sym_mul(E, U, T);  // T = B - V
+      const float l = lam * Jm1 * (1.0f + Jm1);
+      const float m2 = 2.0f * mu;
+      tau[0] = m2 * T[0] + l;
+      tau[4] = m2 * T[1] + l;
+      tau[8] = m2 * T[2] + l;
+      tau[1] = tau[3] = m2 * T[3];
+      tau[2] = tau[6] = m2 * T[4];
+      tau[5] = tau[7] = m2 * T[5];
+      return;
+    }
+  }
+  kirchhoff_shift(H, mu, lam, material, tau, status);
 }
 
 // Element i of an array whose byte offsets fit in 32 bits (i < 2^30): a

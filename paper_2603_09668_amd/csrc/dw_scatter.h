@@ -177,4 +177,63 @@ __device__ __forceinline__ void sc_units_mfma(const ScLane &L, int wid, const fl
   }
 }
 
+// Deterministic mode, second pass of the tile scatter: every node of an
+// active node tile sums, in a fixed order (cell tile z, y, x, then work
+// item), the partial node blocks (item_part, 6^3 x 4 values per work item)
+// of the work items whose 6^3 region covers it.  ADJ = false (P2G):
+// overwrites gm with value 0 and gmv with values 1-3.  ADJ = true (reverse
+// G2P): adds values 1-3 into gmv, the grid-velocity adjoint.
+// Bit-reproducible given a deterministic particle order.
+template <bool ADJ>
+static __global__ __launch_bounds__(256) void k_det_gather(GridDev g, const int32_t *__restrict__ node_tiles,
+                                                        const int32_t *__restrict__ n_tiles,
+                                                        const int32_t *__restrict__ tile_count,
+                                                        const int32_t *__restrict__ item_first,
+                                                        const float *__restrict__ item_part, float *__restrict__ gm,
+                                                        float *__restrict__ gmv, int64_t N) {
+  int nt = *n_tiles;
+  int sub = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int it = blockIdx.x * 4 + sub; it < nt; it += gridDim.x * 4) {
+    int t = node_tiles[it];
+    int tx = t % g.tx, ty = (t / g.tx) % g.ty, tz = t / (g.tx * g.ty);
+    int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    int i = tx * 4 + lx, j = ty * 4 + ly, k = tz * 4 + lz;
+    if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
+    float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int dz = 1; dz >= 0; --dz) {
+      int cz = tz - dz, oz = lz + 4 * dz;
+      if (cz < 0 || oz > 5) continue;
+      for (int dy = 1; dy >= 0; --dy) {
+        int cy = ty - dy, oy = ly + 4 * dy;
+        if (cy < 0 || oy > 5) continue;
+        for (int dxx = 1; dxx >= 0; --dxx) {
+          int cx = tx - dxx, ox = lx + 4 * dxx;
+          if (cx < 0 || ox > 5) continue;
+          int ct = cx + g.tx * (cy + g.ty * cz);
+          int nitem = (tile_count[ct] + WORK_CHUNK - 1) / WORK_CHUNK;
+          int li = ox + SC_L * (oy + SC_L * oz);
+          for (int q = 0; q < nitem; ++q) {
+            const float *src = item_part + ((int64_t)(item_first[ct] + q) * SC_NODES + li) * 4;
+            sm += src[0];
+            s0 += src[1];
+            s1 += src[2];
+            s2 += src[3];
+          }
+        }
+      }
+    }
+    int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    if (ADJ) {
+      gmv[node] += s0;
+      gmv[N + node] += s1;
+      gmv[2 * N + node] += s2;
+    } else {
+      gm[node] = sm;
+      gmv[node] = s0;
+      gmv[N + node] = s1;
+      gmv[2 * N + node] = s2;
+    }
+  }
+}
+
 }  // namespace dw

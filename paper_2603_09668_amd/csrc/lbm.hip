@@ -35,6 +35,7 @@ struct LbmDev {
   int t;
   const int32_t *t_in;
   int32_t *t_out;
+  const int32_t *skip;  // device flag: non-zero makes the launch do nothing
   bool forced;
 };
 
@@ -282,6 +283,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
   __shared__ int s_any[LBM_BLOCK / 64];
   __shared__ float s_inl[5];
+  if (P.skip && *P.skip) return;  // block-uniform: a switched-off graph branch
   const int x0 = blockIdx.x * LBM_BLOCK;
   const int i = x0 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
   if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
@@ -979,6 +981,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_adj_pull(LbmDev P, const floa
 
 __global__ __launch_bounds__(256) void k_lbm_equilibrium(LbmDev P, const float *__restrict__ rho_in,
                                                          const float *__restrict__ u_in, float *__restrict__ f) {
+  if (P.skip && *P.skip) return;
   int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= P.L) return;
   float rho = rho_in ? rho_in[node] : 1.f;
@@ -1069,6 +1072,7 @@ static int make_lbm(const dw_lattice *lat, const dw_lbm_params *prm, LbmDev *P) 
   P->t = prm->t;
   P->t_in = prm->t_in;
   P->t_out = prm->t_out;
+  P->skip = prm->skip;
   DW_REQUIRE(!prm->t_out || (const int32_t *)prm->t_out != prm->t_in, DW_EINVAL, "lbm: t_out must not alias t_in");
   P->forced = prm->force[0] != 0.f || prm->force[1] != 0.f || prm->force[2] != 0.f;
   return DW_OK;

@@ -388,7 +388,7 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
       }
       float mu, lam, tau[9];
       lame(Er, nur, mu, lam);
-      kirchhoff_shift(H, mu, lam, material, tau, status);
+      kirchhoff_shift_p2g(H, mu, lam, material, tau, status);
       const float f[3] = {fx, fy, fz};
       float A[9];
 #pragma unroll
@@ -437,55 +437,6 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
       atomicExch(ticket, 0);
       atomicExch(ticket + 1, 0);
     }
-  }
-}
-
-// Deterministic mode, second pass: every node of an active node tile sums,
-// in a fixed order (cell tile z, y, x, then work item), the partial node
-// blocks of the work items whose 6^3 region covers it, and overwrites the
-// grid.  Bit-reproducible given a deterministic particle order.
-__global__ __launch_bounds__(256) void k_p2g_det_gather(GridDev g, const int32_t *__restrict__ node_tiles,
-                                                        const int32_t *__restrict__ n_tiles,
-                                                        const int32_t *__restrict__ tile_count,
-                                                        const int32_t *__restrict__ item_first,
-                                                        const float *__restrict__ item_part, float *__restrict__ gm,
-                                                        float *__restrict__ gmv, int64_t N) {
-  int nt = *n_tiles;
-  int sub = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int it = blockIdx.x * 4 + sub; it < nt; it += gridDim.x * 4) {
-    int t = node_tiles[it];
-    int tx = t % g.tx, ty = (t / g.tx) % g.ty, tz = t / (g.tx * g.ty);
-    int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
-    int i = tx * 4 + lx, j = ty * 4 + ly, k = tz * 4 + lz;
-    if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
-    float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    for (int dz = 1; dz >= 0; --dz) {
-      int cz = tz - dz, oz = lz + 4 * dz;
-      if (cz < 0 || oz > 5) continue;
-      for (int dy = 1; dy >= 0; --dy) {
-        int cy = ty - dy, oy = ly + 4 * dy;
-        if (cy < 0 || oy > 5) continue;
-        for (int dxx = 1; dxx >= 0; --dxx) {
-          int cx = tx - dxx, ox = lx + 4 * dxx;
-          if (cx < 0 || ox > 5) continue;
-          int ct = cx + g.tx * (cy + g.ty * cz);
-          int nitem = (tile_count[ct] + WORK_CHUNK - 1) / WORK_CHUNK;
-          int li = ox + SC_L * (oy + SC_L * oz);
-          for (int q = 0; q < nitem; ++q) {
-            const float *src = item_part + ((int64_t)(item_first[ct] + q) * SC_NODES + li) * 4;
-            sm += src[0];
-            s0 += src[1];
-            s1 += src[2];
-            s2 += src[3];
-          }
-        }
-      }
-    }
-    int64_t node = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-    gm[node] = sm;
-    gmv[node] = s0;
-    gmv[N + node] = s1;
-    gmv[2 * N + node] = s2;
   }
 }
 
@@ -928,7 +879,7 @@ extern "C" int mpm_p2g(const dw_grid *grid, const dw_mpm_params *params, const d
       hipLaunchKernelGGL(k_p2g<true>, dim3(p2g_blocks()), dim3(P2G_THREADS), 0, s, g, make_pview(p), params->dt,
                          params->material, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, grid_m,
                          grid_mv, N, W.status, W.item_part);
-    hipLaunchKernelGGL(k_p2g_det_gather, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
+    hipLaunchKernelGGL(k_det_gather<false>, dim3(PERSISTENT_BLOCKS), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
                        W.tile_count, W.item_first, W.item_part, grid_m, grid_mv, N);
     return check_launch("mpm_p2g");
   }

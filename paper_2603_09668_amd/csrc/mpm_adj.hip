@@ -132,11 +132,16 @@ struct PAdj {
   const float *x, *v, *C, *F, *mass, *vol0, *E, *nu;
   const float *xr;  // position reference or NULL
   const int32_t *region;
-  int n;
+  int n, n_regions;
   float *xb, *vb, *Cb, *Fb, *Eb;
+  float *Epart;     // deterministic mode: per-wave region sums [waves][n_regions]
 };
 
 // ---------------------------------------------------------- reverse P2G
+// DET: the E adjoint is not added with atomics; every wave writes its
+// per-region sums (fixed-order wave reductions) to P.Epart and
+// k_ebar_reduce adds the waves in index order.
+template <bool DET>
 __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, int material,
                                                  const float *__restrict__ mbar, const float *__restrict__ mvbar,
                                                  int64_t N) {
@@ -274,7 +279,24 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
       }
     }
   }
-  if (P.Eb) {
+  if (P.Eb && DET) {
+    // lane l of the wave keeps the sum of region r0 + l; one store per entry
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    for (int r0 = 0; r0 < P.n_regions; r0 += 64) {
+      float mine_sum = 0.f;
+      unsigned long long pending = __ballot(live && r >= r0 && r < r0 + 64);
+      while (pending) {
+        const int leader = __ffsll(pending) - 1;
+        const int rk = __shfl(r, leader, 64);
+        const bool mine = live && r == rk;
+        const float sum = wave_sum(mine ? Ebar_p : 0.f);
+        if (lane == rk - r0) mine_sum = sum;
+        pending &= ~__ballot(mine);
+      }
+      if (r0 + lane < P.n_regions) P.Epart[wave * P.n_regions + r0 + lane] = mine_sum;
+    }
+  } else if (P.Eb) {
     // one atomic per (wave, region): a wave holds few regions, while
     // per-lane atomics on a handful of addresses would serialise
     unsigned long long pending = __ballot(live);
@@ -288,6 +310,17 @@ __global__ __launch_bounds__(256) void k_p2g_adj(GridDev g, PAdj P, float dt, in
       pending &= ~__ballot(mine);
     }
   }
+}
+
+// E adjoint of the deterministic reverse P2G: region r adds the per-wave sums
+// in wave order.
+__global__ __launch_bounds__(64) void k_ebar_reduce(const float *__restrict__ part, int64_t waves, int R,
+                                                    float *__restrict__ Eb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  float s = 0.f;
+  for (int64_t w = 0; w < waves; ++w) s += part[w * R + r];
+  Eb[r] += s;
 }
 
 // --------------------------------------------------- reverse grid update
@@ -370,15 +403,20 @@ __global__ __launch_bounds__(256) void k_grid_update_adj(GridDev g, float dt, fl
 // grid-velocity adjoint, v_bar_i += w_ip (vbt_p + kc Cbt_p (o - f_p)), has
 // the P2G form w (q + A o) with q = vbt - kc Cbt f, A = kc Cbt and runs as
 // the tile scatter of dw_scatter.h; node owners add the result into the
-// global grid adjoint with float atomics.
+// global grid adjoint with float atomics.  DET: the particles of a cell take
+// their slots in index order and the node owners write the item's 6^3 block
+// to item_part instead, which k_det_gather<true> then adds to the grid
+// adjoint in a fixed order (bit-reproducible with a deterministic sort).
+template <bool DET>
 __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_g2p_adj(
     GridDev g, float dt, const float *__restrict__ gv, int64_t N, const float *__restrict__ x,
     const float *__restrict__ xr, const float *__restrict__ F, int n, const float *__restrict__ xob, const float *__restrict__ vob,
     const float *__restrict__ Cob, const float *__restrict__ Fob, float *__restrict__ xb, float *__restrict__ Fb,
     float *__restrict__ gvb, const int32_t *__restrict__ perm, const int32_t *__restrict__ tile_start,
     const int32_t *__restrict__ item_tile, const int32_t *__restrict__ item_begin,
-    const int32_t *__restrict__ n_items) {
+    const int32_t *__restrict__ n_items, float *__restrict__ item_part) {
   __shared__ float s_dat[SC_DAT][SC_PITCH];
+  __shared__ unsigned char s_cell[WORK_CHUNK];
   __shared__ float4 s_f[SC_PITCH];                                  // staged f per particle
   __shared__ __attribute__((aligned(16))) float s_node[SC_WAVES][SC_NODES][4];
   __shared__ int s_cnt[64], s_off[64], s_cur[64];
@@ -432,11 +470,20 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
         atomicAdd(&s_cnt[c], 1);
       }
     }
+    if (DET) s_cell[tid] = (unsigned char)(c >= 0 ? c : 255);
     __syncthreads();
     if (wid == 0) sc_scan_units(lane, s_cnt, s_off, s_cur, s_udesc, &s_nunits);
     __syncthreads();
     if (c >= 0) {
-      const int slot = atomicAdd(&s_cur[c], 1);
+      int slot;
+      if (DET) {
+        // fixed order: rank among the item's earlier particles of the same cell
+        int rank = 0;
+        for (int q = 0; q < tid; ++q) rank += s_cell[q] == c;
+        slot = s_off[c] + rank;
+      } else {
+        slot = atomicAdd(&s_cur[c], 1);
+      }
       float f[3] = {coord_frac(cx, bx), coord_frac(cy, by), coord_frac(cz, bz)};
       float w[3][3], dw[3][3];
 #pragma unroll
@@ -555,7 +602,13 @@ __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
         s1 += s_node[w][tid][2];
         s2 += s_node[w][tid][3];
       }
-      if (s0 != 0.f || s1 != 0.f || s2 != 0.f) {
+      if (DET) {
+        float *dst = item_part + ((int64_t)it * SC_NODES + tid) * 4;
+        dst[0] = 0.f;
+        dst[1] = s0;
+        dst[2] = s1;
+        dst[3] = s2;
+      } else if (s0 != 0.f || s1 != 0.f || s2 != 0.f) {
         const int ix = tid % SC_L, iy = (tid / SC_L) % SC_L, iz = tid / (SC_L * SC_L);
         const int64_t node = (4 * tx + ix) + (int64_t)g.nx * ((4 * ty + iy) + (int64_t)g.ny * (4 * tz + iz));
         atomicAdd(&gvb[node], s0);
@@ -573,7 +626,7 @@ using namespace dw;
 
 extern "C" int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, const dw_particles *p,
                            const float *grid_m_bar, const float *grid_mv_bar, dw_particles_bar *bar, float *E_bar,
-                           void *stream) {
+                           void *ws, size_t ws_bytes, void *stream) {
   int rc = check_grid(grid);
   if (rc) return rc;
   DW_REQUIRE(params, DW_EINVAL, "mpm_p2g_adj: params is NULL");
@@ -588,10 +641,28 @@ extern "C" int mpm_p2g_adj(const dw_grid *grid, const dw_mpm_params *params, con
   P.x = p->x; P.v = p->v; P.C = p->C; P.F = p->F; P.mass = p->mass; P.vol0 = p->vol0;
   P.E = p->E; P.nu = p->nu; P.region = p->region; P.n = p->n; P.xr = p->xref;
   P.xb = bar->x; P.vb = bar->v; P.Cb = bar->C; P.Fb = bar->F; P.Eb = E_bar;
+  P.n_regions = p->n_regions;
+  P.Epart = nullptr;
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
-  hipLaunchKernelGGL(k_p2g_adj, dim3(grid_blocks(p->n, 256)), dim3(256), 0, (hipStream_t)stream, g, P, params->dt,
-                     params->material, grid_m_bar, grid_mv_bar, N);
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned blocks = grid_blocks(p->n, 256);
+  if (params->deterministic && E_bar) {
+    Workspace W;
+    rc = bind_workspace(grid, p->n, ws, ws_bytes, &W, 1);
+    if (rc) return rc;
+    const int64_t waves = (int64_t)blocks * 4;
+    DW_REQUIRE(waves * p->n_regions <= W.item_part_floats, DW_EWORKSPACE,
+               "mpm_p2g_adj: %d regions need more deterministic scratch than the workspace holds", p->n_regions);
+    P.Epart = W.item_part;
+    hipLaunchKernelGGL(k_p2g_adj<true>, dim3(blocks), dim3(256), 0, s, g, P, params->dt, params->material,
+                       grid_m_bar, grid_mv_bar, N);
+    hipLaunchKernelGGL(k_ebar_reduce, dim3(grid_blocks(p->n_regions, 64)), dim3(64), 0, s, W.item_part, waves,
+                       p->n_regions, E_bar);
+  } else {
+    hipLaunchKernelGGL(k_p2g_adj<false>, dim3(blocks), dim3(256), 0, s, g, P, params->dt, params->material,
+                       grid_m_bar, grid_mv_bar, N);
+  }
   return check_launch("mpm_p2g_adj");
 }
 
@@ -627,12 +698,22 @@ extern "C" int mpm_g2p_adj(const dw_grid *grid, const dw_mpm_params *params, con
   if (in->n == 0) return DW_OK;
   DW_REQUIRE(in->x && in->F, DW_EINVAL, "mpm_g2p_adj: in->x / in->F is NULL");
   Workspace W;
-  rc = bind_workspace(grid, in->n, ws, ws_bytes, &W);
+  const int det = params->deterministic ? 1 : 0;
+  rc = bind_workspace(grid, in->n, ws, ws_bytes, &W, det);
   if (rc) return rc;
   GridDev g = make_grid(grid);
   int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
-  hipLaunchKernelGGL(k_g2p_adj, dim3(2048), dim3(SC_THREADS), 0, (hipStream_t)stream, g, params->dt, grid_v, N,
-                     in->x, in->xref, in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F,
-                     grid_v_bar, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items);
+  hipStream_t s = (hipStream_t)stream;
+  if (det) {
+    hipLaunchKernelGGL(k_g2p_adj<true>, dim3(2048), dim3(SC_THREADS), 0, s, g, params->dt, grid_v, N, in->x,
+                       in->xref, in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F,
+                       grid_v_bar, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, W.item_part);
+    hipLaunchKernelGGL(k_det_gather<true>, dim3(2048), dim3(256), 0, s, g, W.node_tiles, W.n_node_tiles,
+                       W.tile_count, W.item_first, W.item_part, (float *)nullptr, grid_v_bar, N);
+  } else {
+    hipLaunchKernelGGL(k_g2p_adj<false>, dim3(2048), dim3(SC_THREADS), 0, s, g, params->dt, grid_v, N, in->x,
+                       in->xref, in->F, in->n, out_bar->x, out_bar->v, out_bar->C, out_bar->F, in_bar->x, in_bar->F,
+                       grid_v_bar, W.perm, W.tile_start, W.item_tile, W.item_begin, W.n_items, (float *)nullptr);
+  }
   return check_launch("mpm_g2p_adj");
 }

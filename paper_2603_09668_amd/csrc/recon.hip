@@ -8,8 +8,10 @@
 //    photometric loss on synthetic targets, and its gradient;
 //  * CosSim and NMSE of unit force directions;
 //  * the guide: the lattice velocity sampled at the wind-grid nodes.
-// Sums are reduced per block and added with one float atomic per block, so
-// their last bits depend on the order the blocks finish in.
+// The physics-informed loss runs as one workgroup (the wind grid is small), so
+// its sum has a fixed order; the other sums are reduced per block and added
+// with one float atomic per block, so their last bits depend on the order the
+// blocks finish in.
 #include <hip/hip_runtime.h>
 
 #include "dw_internal.h"
@@ -39,12 +41,12 @@ __device__ __forceinline__ void block_add(float (&v)[K], float *out) {
   }
 }
 
+// one workgroup: thread t takes nodes t, t + RC_BLOCK, ... (fixed order)
 __global__ __launch_bounds__(RC_BLOCK) void k_phys_loss(int n, const float *__restrict__ W,
                                                         const float *__restrict__ G, float weight,
                                                         float *__restrict__ loss, float *__restrict__ Wb) {
-  const int i = blockIdx.x * RC_BLOCK + threadIdx.x;
   float part[1] = {0.f};
-  if (i < n) {
+  for (int i = threadIdx.x; i < n; i += RC_BLOCK) {
     const float w[3] = {W[i], W[n + i], W[2 * n + i]};
     const float g[3] = {G[i], G[n + i], G[2 * n + i]};
     const float wn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(RC_BLOCK) void k_phys_loss(int n, const float *__re
 #pragma unroll
       for (int a = 0; a < 3; ++a) perp[a] = d[a] - c * e[a];
       const float li = perp[0] * perp[0] + perp[1] * perp[1] + perp[2] * perp[2];
-      part[0] = weight * li;
+      part[0] += weight * li;
       // d L_i / d w = 2 (perp - (perp . d) d) / |w|
       if (Wb) {
         const float pd = perp[0] * d[0] + perp[1] * d[1] + perp[2] * d[2];
@@ -145,7 +147,7 @@ extern "C" int phys_loss(int n, const float *W, const float *guide, float weight
   if (n == 0) return DW_OK;
   DW_REQUIRE(W && guide, DW_EINVAL, "phys_loss: W / guide is NULL");
   DW_REQUIRE(loss || W_bar, DW_EINVAL, "phys_loss: nothing to compute");
-  hipLaunchKernelGGL(k_phys_loss, dim3(grid_blocks(n, RC_BLOCK)), dim3(RC_BLOCK), 0, (hipStream_t)stream, n, W,
+  hipLaunchKernelGGL(k_phys_loss, dim3(1), dim3(RC_BLOCK), 0, (hipStream_t)stream, n, W,
                      guide, weight, loss, W_bar);
   return check_launch("phys_loss");
 }

@@ -8,6 +8,13 @@ One coupled step runs, on torch's current stream:
   4. mpm_p2g                   -- Eq. P2G with the MLS stress term
   5. mpm_grid_update           -- gravity, LBM drag wind (Sec. 3.4), walls, pins
   6. mpm_g2p                   -- Eq. G2P, APIC C, Eq. deformation_update (in place)
+Wind models (`wind`): "lbm" steps the lattice every substep; "surrogate"
+replaces each block of k LBM steps by one call of the learned surrogate
+(u_{t+k} from u_t, decided and, on a failed check, replaced by k plain LBM
+steps on the device), the drag then using u_{t+k} for the k substeps of the
+block; "frozen" keeps the wind field fixed (the method without a wind
+update, the floor the surrogate must beat).
+
 Particle positions are stored as a fixed reference (the scene's positions)
 plus a float32 displacement (`p.xref`, `p.x`; see the header), unless
 `position_reference=False` keeps absolute positions in `p.x`.
@@ -28,7 +35,8 @@ from . import api
 
 class CoupledSim:
     def __init__(self, scene, device="cuda", lbm_steps_per_substep: int = 1, reorder: bool = True,
-                 lbm_model: str = "bgk", relative_drag: bool = False, position_reference: bool = True):
+                 lbm_model: str = "bgk", relative_drag: bool = False, position_reference: bool = True,
+                 wind: str = "lbm", surrogate=None, k: int = 8):
         self.scene = scene
         self.device = device
         self.R = int(lbm_steps_per_substep)
@@ -77,6 +85,17 @@ class CoupledSim:
         self.u = torch.zeros(3, self.L, **f32)
         self.wind = api.wind_lbm_drag(self.lat, self.u, scene.wind["vel_scale"], scene.wind["k_drag"],
                                       relative=relative_drag)
+        if wind not in ("lbm", "surrogate", "frozen"):
+            raise ValueError(f"unknown wind model {wind!r}")
+        self.wind_model = wind
+        self.sw = None
+        if wind == "surrogate":
+            if surrogate is None or lbm_model != "bgk" or self.R != 1:
+                raise ValueError("the surrogate wind needs a trained net, the BGK lattice and one LBM step per substep")
+            from .surrogate import SurrogateWind
+            self.k = int(k)
+            self.sw = SurrogateWind(surrogate, self.lat, self.lbm_kw, self.solid, k=self.k, batch=1)
+            self.scale = torch.tensor([float(np.linalg.norm(lb["u_in"]))], **f32)
         # order[i] = scene index of particle i
         self.order = torch.arange(n, dtype=torch.int32, device=device)
         if reorder:
@@ -104,6 +123,16 @@ class CoupledSim:
         api.lbm_solid_from_particles(self.lat, self.p.x, self.solid, xref=self.p.xref)
 
     def lbm(self):
+        if self.wind_model == "frozen":
+            self.t += self.R
+            return
+        if self.wind_model == "surrogate":
+            # one surrogate call per block of k steps, at the block's start
+            if self.t % self.k == 0:
+                u = self.u.view(1, 3, self.L)
+                self.sw.advance_device(u, self.scale, u, t0=self.t)
+            self.t += 1
+            return
         for _ in range(self.R):
             prm = api.make_lbm_params(**self.lbm_kw, t_in=self.t_a, t_out=self.t_b)
             step = api.lbm_step if self.lbm_model == "bgk" else api.lbm_home_step
@@ -151,6 +180,17 @@ class CoupledSim:
         self.grid_update()
         self.g2p()
 
+    def warm_wind(self, steps: int):
+        """`steps` LBM steps around the particles at rest (solid mask from their
+        positions), e.g. to start from a developed flow; the step index of
+        the gust continues from there."""
+        self.voxelize()
+        model = self.wind_model
+        self.wind_model = "lbm"
+        for _ in range(steps):
+            self.lbm()
+        self.wind_model = model
+
     def capture(self, substeps: int = 2, concurrent: bool = True):
         """Record `substeps` coupled substeps (an even number of LBM steps, so
         the ping-pong buffers return to their roles) in one HIP graph; with
@@ -158,6 +198,8 @@ class CoupledSim:
         branches."""
         if (substeps * self.R) % 2:
             raise ValueError("capture an even number of LBM steps")
+        if self.wind_model != "lbm":
+            raise ValueError("graph capture takes the LBM wind model (the others branch on the host step index)")
         t_host = self.t
         side = torch.cuda.Stream() if concurrent else None
         self.graph = torch.cuda.CUDAGraph()

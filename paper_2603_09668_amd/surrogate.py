@@ -232,39 +232,76 @@ def train(net: Surrogate, U0, U1, S, dims, steps: int, batch: int = 16, lr: floa
 
 class SurrogateWind:
     """Advances the wind of one lattice k LBM steps per call with the surrogate,
-    judged by check_fields; a rejected field is re-initialised at equilibrium
-    (rho = 1, the current u) and advanced k plain LBM steps instead."""
+    judged by the divergence and kinetic-energy checks; a rejected field is
+    re-initialised at equilibrium (rho = 1, the current u) and advanced k plain
+    LBM steps instead.  The decision is taken on the device: the checks write
+    an acceptance flag that switches the LBM fallback branch off (the `skip`
+    flag of its launches) and selects the output, so a call needs no host
+    synchronisation and can be captured in a HIP graph."""
 
-    def __init__(self, net: Surrogate, lat, lbm_kw: dict, solid, k: int = 8, batch: int = 1):
+    def __init__(self, net: Surrogate, lat, lbm_kw: dict, solid, k: int = 8, batch: int = 1,
+                 div_factor: float = 2.0, ke_band=(0.9, 1.1)):
         self.net, self.lat, self.kw, self.solid, self.k = net, lat, dict(lbm_kw), solid, k
+        self.div_factor, self.ke_band = float(div_factor), tuple(ke_band)
         nx, ny, nz = lat.nx, lat.ny, lat.nz
         self.dims = (batch, nx, ny, nz)
         L = nx * ny * nz
-        self.fa = torch.empty(19, L, device=net.device)
+        dev = net.device
+        self.fa = torch.empty(19, L, device=dev)
         self.fb = torch.empty_like(self.fa)
-        self.u_tmp = torch.empty(3, L, device=net.device)
-        self.solid_b = solid.reshape(1, -1).expand(batch, -1).contiguous() if solid is not None else None
+        self.u_tmp = torch.empty(3, L, device=dev)
+        self.u_pred = torch.empty(batch, 3, L, device=dev)
+        self.u_lbm = torch.empty(batch, 3, L, device=dev)
+        self.stats = torch.zeros(2, batch, 3, device=dev)
+        self.accept = torch.zeros(batch, dtype=torch.int32, device=dev)
+        self.reject = torch.zeros(batch, dtype=torch.int32, device=dev)
+        self.solid_b = None
+        self.set_solid(solid)
         self.fallbacks = 0
 
-    def lbm_block(self, u, t0: int, u_out):
-        """k LBM steps from the equilibrium at (rho = 1, u); writes u_out (3, L)."""
-        api.lbm_equilibrium(self.lat, api.make_lbm_params(**self.kw), self.fa, None, u)
+    def set_solid(self, solid):
+        """The solid mask (L,) of the lattice (read at every call, so a mask
+        updated in place is seen)."""
+        self.solid = solid
+        B = self.dims[0]
+        if solid is None:
+            self.solid_b = None
+        elif B == 1:
+            self.solid_b = solid.reshape(1, -1)
+        else:
+            self.solid_b = solid.reshape(1, -1).expand(B, -1).contiguous()
+
+    def lbm_block(self, u, t0: int, u_out, skip=None):
+        """k LBM steps from the equilibrium at (rho = 1, u); writes u_out (3, L).
+        skip: optional device int32 flag that switches the whole block off."""
+        api.lbm_equilibrium(self.lat, api.make_lbm_params(**self.kw, skip=skip), self.fa, None, u)
         fa, fb = self.fa, self.fb
         for j in range(self.k):
-            api.lbm_step(self.lat, api.make_lbm_params(**self.kw, t=t0 + j + 1), fa, fb, self.solid, None, u_out)
+            api.lbm_step(self.lat, api.make_lbm_params(**self.kw, t=t0 + j + 1, skip=skip), fa, fb, self.solid, None,
+                         u_out if j == self.k - 1 else None)
             fa, fb = fb, fa
 
-    def advance(self, u, scale, u_out, t0: int = 0, override=None):
-        """u, u_out: (B, 3, L); scale (B,).  `override(u_out)` may alter the
-        prediction before the checks (fault-injection hook).  Returns the
-        per-field bool tensor of accepted predictions."""
-        self.net.forward(u, scale, u_out, self.dims)
+    def advance_device(self, u, scale, u_out, t0: int = 0, override=None):
+        """u, u_out: (B, 3, L); scale (B,).  Prediction, checks, decision and
+        fallback all on the device; returns the device int32 acceptance
+        flags (B,).  `override(u_pred)` may alter the prediction before the
+        checks (fault-injection hook).  u_out may be u itself."""
+        dims = self.dims
+        self.net.forward(u, scale, self.u_pred, dims)
         if override is not None:
-            override(u_out)
-        ok = check_fields(u, u_out, self.dims, self.solid_b)
-        bad = (~ok).nonzero().flatten().tolist()
-        for b in bad:
-            self.lbm_block(u[b], t0, self.u_tmp)
-            u_out[b].copy_(self.u_tmp)
-        self.fallbacks += len(bad)
+            override(self.u_pred)
+        self.stats.zero_()
+        api.field_stats(dims, u, self.solid_b, self.stats[0])
+        api.field_stats(dims, self.u_pred, self.solid_b, self.stats[1])
+        api.field_accept(self.stats[0], self.stats[1], self.accept, self.reject, self.div_factor, self.ke_band)
+        for b in range(dims[0]):
+            self.lbm_block(u[b], t0, self.u_lbm[b], skip=self.accept[b:b + 1])
+        api.field_select(dims, self.accept, self.u_pred, self.u_lbm, self.solid_b, u_out)
+        return self.accept
+
+    def advance(self, u, scale, u_out, t0: int = 0, override=None):
+        """advance_device, then the per-field bool tensor of accepted
+        predictions (this reads the flags on the host)."""
+        ok = self.advance_device(u, scale, u_out, t0, override).bool()
+        self.fallbacks += int((~ok).sum().item())
         return ok

@@ -44,7 +44,8 @@ def test_struct_layout_matches_header():
 int main(void) {
   P(dw_grid) P(dw_lattice) P(dw_mpm_params) P(dw_particles) P(dw_particles_bar) P(dw_wind) P(dw_lbm_params)
   O(dw_wind, W) O(dw_wind, lat) O(dw_wind, u) O(dw_wind, acc) O(dw_particles, n_regions) O(dw_lbm_params, t)
-  O(dw_lbm_params, bc) O(dw_mpm_params, deterministic) O(dw_particles, xref)
+  O(dw_lbm_params, bc) O(dw_mpm_params, deterministic) O(dw_particles, xref) O(dw_lbm_params, skip)
+  O(dw_wind, deterministic)
   return 0;
 }
 """
@@ -66,6 +67,8 @@ int main(void) {
     assert int(got["dw_wind.acc"]) == api.Wind.acc.offset
     assert int(got["dw_particles.n_regions"]) == api.Particles.n_regions.offset
     assert int(got["dw_particles.xref"]) == api.Particles.xref.offset
+    assert int(got["dw_lbm_params.skip"]) == api.LBMParams.skip.offset
+    assert int(got["dw_wind.deterministic"]) == api.Wind.deterministic.offset
     assert int(got["dw_lbm_params.t"]) == api.LBMParams.t.offset
     assert int(got["dw_lbm_params.bc"]) == api.LBMParams.bc.offset
     assert int(got["dw_mpm_params.deterministic"]) == api.MPMParams.deterministic.offset

@@ -32,9 +32,11 @@ def scene():
                                         n_regions=3, E_range=(1e3, 1e4))
 
 
+@pytest.mark.parametrize("det", [False, True])
 @pytest.mark.parametrize("material", [api.FIXED_COROTATED, api.NEO_HOOKEAN])
-def test_p2g_adj(scene, material):
-    say(f"mpm_p2g_adj material={material}")
+def test_p2g_adj(scene, material, det):
+    """det: the E adjoint summed in a fixed order (bit-identical on a second call)."""
+    say(f"mpm_p2g_adj material={material} deterministic={det}")
     sc = scene
     st, dev = scene_state(sc, seed=3, scale_f=0.05)
     og = oracle_grid(sc.grid)
@@ -58,8 +60,15 @@ def test_p2g_adj(scene, material):
     Cb = torch.zeros_like(dev.C)
     Fb = torch.zeros_like(dev.F)
     Eb = torch.zeros_like(dev.E)
-    api.mpm_p2g_adj(g, api.make_mpm_params(dt, material=material), dev, mbar.float().to(DEV),
-                    mvbar.T.contiguous().float().to(DEV), xb, vb, Cb, Fb, Eb)
+    prm = api.make_mpm_params(dt, material=material, deterministic=det)
+    ws = api.alloc_workspace(g, sc.n, deterministic=True) if det else None
+    args = (mbar.float().to(DEV), mvbar.T.contiguous().float().to(DEV))
+    api.mpm_p2g_adj(g, prm, dev, *args, xb, vb, Cb, Fb, Eb, ws=ws)
+    if det:
+        Eb2 = torch.zeros_like(dev.E)
+        api.mpm_p2g_adj(g, prm, dev, *args, E_bar=Eb2, ws=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(Eb, Eb2)
     torch.cuda.synchronize()
     errs = dict(x=rel2(vec_from_dev(xb), gx), v=rel2(vec_from_dev(vb), gv), C=rel2(mat_from_dev(Cb), gC),
                 F=rel2(mat_from_dev(Fb), gF), E=rel2(Eb.cpu(), gE))
@@ -103,7 +112,10 @@ def test_grid_update_adj(scene):
     assert rel2(ab.cpu().T, ga) < TOL
 
 
-def test_g2p_adj(scene):
+@pytest.mark.parametrize("det", [False, True])
+def test_g2p_adj(scene, det):
+    """det: deterministic sort and a fixed-order grid-velocity scatter
+    (bit-identical on a second call)."""
     sc = scene
     st, dev = scene_state(sc, seed=7)
     og = oracle_grid(sc.grid)
@@ -115,21 +127,26 @@ def test_g2p_adj(scene):
     xob, vob = f32(rng.standard_normal((n, 3))), f32(rng.standard_normal((n, 3)))
     Cob, Fob = f32(rng.standard_normal((n, 3, 3))), f32(rng.standard_normal((n, 3, 3)))
     dt = 1e-3
-    say("mpm_g2p_adj")
+    say(f"mpm_g2p_adj deterministic={det}")
     gvt = gv0.clone().requires_grad_(True)
     x = st["x"].clone().requires_grad_(True)
     F = st["F"].clone().requires_grad_(True)
     x1, v1, C1, F1 = ompm.g2p(og, gvt, x, F, dt)
     L = (x1 * xob).sum() + (v1 * vob).sum() + (C1 * Cob).sum() + (F1 * Fob).sum()
     ggv, gx, gF = torch.autograd.grad(L, (gvt, x, F))
-    ws = api.alloc_workspace(g, n)
-    prm = api.make_mpm_params(dt)
+    ws = api.alloc_workspace(g, n, deterministic=det)
+    prm = api.make_mpm_params(dt, deterministic=det)
     api.mpm_sort(g, prm, dev.x, ws)
     xb = torch.zeros_like(dev.x)
     Fb = torch.zeros_like(dev.F)
     gvb = torch.zeros(3, N, device=DEV)
-    api.mpm_g2p_adj(g, prm, gv0.T.contiguous().float().to(DEV), dev, vec_to_dev(xob), vec_to_dev(vob),
-                    mat_to_dev(Cob), mat_to_dev(Fob), xb, Fb, gvb, ws)
+    cot = (vec_to_dev(xob), vec_to_dev(vob), mat_to_dev(Cob), mat_to_dev(Fob))
+    api.mpm_g2p_adj(g, prm, gv0.T.contiguous().float().to(DEV), dev, *cot, xb, Fb, gvb, ws)
+    if det:
+        gvb2 = torch.zeros(3, N, device=DEV)
+        api.mpm_g2p_adj(g, prm, gv0.T.contiguous().float().to(DEV), dev, *cot, None, None, gvb2, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(gvb2, gvb)
     torch.cuda.synchronize()
     errs = dict(gv=rel2(gvb.cpu().T, ggv), x=rel2(vec_from_dev(xb), gx), F=rel2(mat_from_dev(Fb), gF))
     say("  " + " ".join(f"{k}={e:.2e}" for k, e in errs.items()))
@@ -137,7 +154,9 @@ def test_g2p_adj(scene):
         assert e < TOL, k
 
 
-def test_wind_to_grid_adj(scene):
+@pytest.mark.parametrize("det", [False, True])
+def test_wind_to_grid_adj(scene, det):
+    """det: the transposes as fixed-order gathers (bit-identical on a second call)."""
     sc = scene
     og = oracle_grid(sc.grid)
     g = api_grid(sc.grid)
@@ -152,8 +171,13 @@ def test_wind_to_grid_adj(scene):
     a = owind.force_grid_to_nodes(og, W, nw, (0, 0, 0), (1, 1, 1))
     (gW,) = torch.autograd.grad((a * abar).sum(), (W,))
     Wb = torch.zeros(3, 16 ** 3, device=DEV)
-    api.wind_to_grid_adj(g, api.wind_force_grid(W0.float().to(DEV).contiguous(), nw, (0, 0, 0), (1, 1, 1)),
-                         abar.T.contiguous().float().to(DEV), Wb)
+    wf = api.wind_force_grid(W0.float().to(DEV).contiguous(), nw, (0, 0, 0), (1, 1, 1), deterministic=det)
+    api.wind_to_grid_adj(g, wf, abar.T.contiguous().float().to(DEV), Wb)
+    if det:
+        Wb2 = torch.zeros(3, 16 ** 3, device=DEV)
+        api.wind_to_grid_adj(g, wf, abar.T.contiguous().float().to(DEV), Wb2)
+        torch.cuda.synchronize()
+        assert torch.equal(Wb, Wb2)
     torch.cuda.synchronize()
     assert rel2(Wb.cpu(), gW) < TOL
     say("wind_to_grid_adj drag")
@@ -166,8 +190,13 @@ def test_wind_to_grid_adj(scene):
     (gu,) = torch.autograd.grad((a * abar).sum(), (u,))
     ub = torch.zeros(3, Lq, device=DEV)
     alat = api.make_lattice(*dims, lat["dx"], lat["origin"])
-    api.wind_to_grid_adj(g, api.wind_lbm_drag(alat, u0.float().to(DEV).contiguous(), 12.5, 9.8),
-                         abar.T.contiguous().float().to(DEV), ub)
+    wd = api.wind_lbm_drag(alat, u0.float().to(DEV).contiguous(), 12.5, 9.8, deterministic=det)
+    api.wind_to_grid_adj(g, wd, abar.T.contiguous().float().to(DEV), ub)
+    if det:
+        ub2 = torch.zeros(3, Lq, device=DEV)
+        api.wind_to_grid_adj(g, wd, abar.T.contiguous().float().to(DEV), ub2)
+        torch.cuda.synchronize()
+        assert torch.equal(ub, ub2)
     torch.cuda.synchronize()
     assert rel2(ub.cpu(), gu) < TOL
 

@@ -46,7 +46,7 @@ def _oracle_loss(grid, x0, region, mass, vol0, E, nu, W, target, cfg):
     return ((st["x"] - target) ** 2).sum()
 
 
-def _gpu_grad(grid, x0, region, mass, vol0, E, nu, W, target, cfg, ref=False):
+def _gpu_grad(grid, x0, region, mass, vol0, E, nu, W, target, cfg, ref=False, deterministic=False):
     """Loss and gradients through the library; ref=True keeps the positions
     as x0 (reference) plus a displacement."""
     n = x0.shape[0]
@@ -54,7 +54,7 @@ def _gpu_grad(grid, x0, region, mass, vol0, E, nu, W, target, cfg, ref=False):
     plan = RolloutPlan(grid, n, mass.float().to(DEV), vol0.float().to(DEV), region.to(torch.int32).to(DEV),
                        nu.float().to(DEV), None, cfg["dt"], cfg["gravity"], cfg["material"], cfg["bound"],
                        cfg["nw"], (0, 0, 0), (1, 1, 1), cfg["K"], cfg["n_sub"], cfg["ckpt"],
-                       xref=xd if ref else None)
+                       xref=xd if ref else None, deterministic=deterministic)
     Wd = W.float().to(DEV).contiguous().requires_grad_(True)
     Ed = E.float().to(DEV).requires_grad_(True)
     x = torch.zeros_like(xd) if ref else xd
@@ -108,3 +108,23 @@ def test_rollout_checkpoint_invariance():
     L5, gW5, gE5 = _gpu_grad(grid, x0, region, mass, vol0, E, nu, W, target, cfg)
     assert abs(L1 - L5) <= 1e-6 * abs(L1)
     assert ((gW1 - gW5).norm() / gW1.norm()).item() < 1e-5
+
+
+def test_rollout_deterministic_gradient_is_bit_reproducible():
+    """In the deterministic mode every reduction of the forward and reverse
+    substeps has a fixed order: two runs give bit-identical gradients, which
+    still match the oracle's reverse mode."""
+    say("rollout gradient deterministic x2")
+    args = _setup(api.FIXED_COROTATED)
+    La, gWa, gEa = _gpu_grad(*args, ref=True, deterministic=True)
+    Lb, gWb, gEb = _gpu_grad(*args, ref=True, deterministic=True)
+    assert La == Lb and torch.equal(gWa, gWb) and torch.equal(gEa, gEb)
+    grid, x0, region, mass, vol0, E, nu, W, target, cfg = args
+    Wo = W.clone().requires_grad_(True)
+    Eo = E.clone().requires_grad_(True)
+    Lo = _oracle_loss(grid, x0, region, mass, vol0, Eo, nu, Wo, target, cfg)
+    gWo, gEo = torch.autograd.grad(Lo, (Wo, Eo))
+    eW = ((gWa - gWo).norm() / gWo.norm()).item()
+    eE = ((gEa - gEo).norm() / gEo.norm()).item()
+    say(f"  rel err dL/dW {eW:.2e} dL/dE {eE:.2e}")
+    assert eW < 1e-3 and eE < 1e-3
