@@ -159,15 +159,26 @@ def _copy_bandwidth(mib=1024):
             "frac_of_peak": 2 * (mib << 20) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+_SCENES = {}
+
+
+def _scene(n, res):
+    """The flag-and-leaves scene of n particles on a res^3 grid (built once)."""
+    from paper_2603_09668_amd import scenes
+    key = (n, res)
+    if key not in _SCENES:
+        _SCENES[key] = scenes.flag_and_leaves_scene(seed=0, n=n, res=res, lbm_dims=(res, res // 2, res // 2))
+    return _SCENES[key]
+
+
 def _largest_leg(steps=20):
     """The largest single-GPU workload: 4M particles on a 256^3 grid with a
     256x128x128 lattice, the same coupled substep as the main line (HIP graph
     of two substeps, one stream), its phases and their rooflines."""
     import torch
-    from paper_2603_09668_amd import scenes
     from paper_2603_09668_amd.sim import CoupledSim
     t0 = time.perf_counter()
-    scene = scenes.flag_and_leaves_scene(seed=0, n=4_000_000, res=256, lbm_dims=(256, 128, 128))
+    scene = _scene(4_000_000, 256)
     sim = CoupledSim(scene)
     t_setup = time.perf_counter() - t0
     for _ in range(4):
@@ -443,9 +454,8 @@ def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
     against the LBM-driven run, the final wind error over fluid nodes and the
     error of the particle displacements."""
     import torch
-    from paper_2603_09668_amd import scenes
     from paper_2603_09668_amd.sim import CoupledSim
-    scene = scenes.flag_and_leaves_scene(seed=0, n=n, res=res, lbm_dims=(res, res // 2, res // 2))
+    scene = _scene(n, res)
     res_ = {}
     for model in ("lbm", "surrogate", "frozen"):
         sim = CoupledSim(scene, wind=model, surrogate=net if model == "surrogate" else None)
