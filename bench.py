@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 METRIC = "particle-substeps/s, LBM MLUPS; surrogate-vs-LBM speedup at \u22642% wind error"
@@ -55,6 +57,8 @@ def _args():
     ap.add_argument("--no-largest", action="store_true", help="skip the 4M-particle / 256^3 leg")
     ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint leg (profiling)")
     ap.add_argument("--fd", type=int, default=20, help="finite-difference coordinates in the adjoint leg")
+    ap.add_argument("--no-render", action="store_true", help="skip the 3DGS rendering leg")
+    ap.add_argument("--render-only", action="store_true", help="run only the rendering leg (profiling)")
     return ap.parse_args()
 
 
@@ -587,6 +591,52 @@ def _adjoint_leg(n, res, n_sub, ckpt, n_fd):
                        "particles": sc.n, "grid": res, "substeps": n_sub, "checkpoint_every": ckpt}}
 
 
+def _render_leg(reps=5):
+    """Differentiable rendering of the particles as Gaussian kernels (Sec. 3.3,
+    Eq. rendering and L_render): the splat workload of the paper's timing
+    table in shape (500k object kernels on the flag-and-leaves particles,
+    500k background kernels around them, one 1024 x 1024 view, the usual
+    truncations alpha_min = 1/255 and t_min = 1e-4).  Times the forward
+    render and the loss plus reverse pass, each as a HIP graph."""
+    import torch
+    from paper_2603_09668_amd import api, scenes
+    g = scenes.splat_scene(seed=0)
+    c = g.camera
+    cam = api.make_camera(c["width"], c["height"], c["fx"], c["fy"], c["cx"], c["cy"], R=np.asarray(c["R"]).tolist(),
+                          t=np.asarray(c["t"]).tolist(), near_plane=c["near"], alpha_min=1.0 / 255.0, t_min=1e-4)
+    f = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda").contiguous()
+    mu, sig, col, op = f(g.mu), f(g.sigma), f(g.color), f(g.opacity)
+    n = mu.shape[1]
+    ws = api.RenderWorkspace(n, cam, 24 * n)
+    img = torch.empty(3, c["height"], c["width"], device="cuda")
+    tgt = torch.empty_like(img)
+    # target: the same kernels displaced by a small uniform shift
+    pairs_t = api.gs_render(cam, mu + 0.002, sig, col, op, tgt, ws)
+    pairs = api.gs_render(cam, mu, sig, col, op, img, ws)
+    fwd_ms = _graph_ms(lambda: api.gs_render(cam, mu, sig, col, op, img, ws, check=False), reps)
+    lws = api.render_loss_workspace(3, c["height"], c["width"])
+    L = torch.zeros(1, device="cuda")
+    ib = torch.zeros_like(img)
+    bars = [torch.zeros(3, n, device="cuda"), torch.zeros(6, n, device="cuda"), torch.zeros(3, n, device="cuda"),
+            torch.zeros(n, device="cuda")]
+
+    def back():
+        L.zero_()
+        ib.zero_()
+        api.render_loss(img, tgt, lws, 0.1, L, ib)
+        api.gs_render_adj(cam, mu, sig, col, op, img, ib, ws, *bars)
+    back()
+    torch.cuda.synchronize()
+    loss = float(L.item())
+    bwd_ms = _graph_ms(back, reps)
+    st, _ = ws.status()
+    return {"config": {"workload": "3DGS render of 500000 object kernels (flag-and-leaves particles) and 500000 "
+                                   "background kernels, one 1024x1024 view, alpha_min 1/255, t_min 1e-4",
+                       "kernels": n, "width": c["width"], "height": c["height"]},
+            "pairs": pairs, "pairs_target": pairs_t, "ms_forward": fwd_ms, "ms_loss_and_reverse": bwd_ms,
+            "loss": loss, "status": st, "kernels_per_s_forward": n / (fwd_ms * 1e-3)}
+
+
 def _cpu_model():
     """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
     import subprocess
@@ -690,6 +740,9 @@ def main():
     if a.adjoint_only:
         print(json.dumps({"metric": METRIC, "adjoint": _adjoint_leg(256_000, 96, 256, 16, a.fd)}), flush=True)
         return
+    if a.render_only:
+        print(json.dumps({"metric": METRIC, "render": _render_leg()}), flush=True)
+        return
     if a.surrogate_only:
         sgo = _surrogate_leg(a.sg_rollouts, a.sg_steps)
         net = sgo.pop("_net")
@@ -784,6 +837,8 @@ def main():
         out["home_lbm"] = _home_leg(scene, sim, min(a.steps, 100))
     if not a.no_largest:
         out["largest"] = _largest_leg()
+    if not a.no_render:
+        out["render"] = _render_leg()
     if not a.no_surrogate:
         del sim
         torch.cuda.empty_cache()

@@ -84,7 +84,8 @@ enum { DW_WIND_NONE = 0, DW_WIND_FORCE_GRID = 1, DW_WIND_LBM_DRAG = 2, DW_WIND_A
 enum {
   DW_STATUS_OUT_OF_GRID = 1, /* a particle's 27-node stencil left the grid; it was skipped */
   DW_STATUS_NONFINITE = 2,   /* a NaN/Inf particle position was met */
-  DW_STATUS_INVERTED = 4     /* det F <= 0 met in the stress evaluation */
+  DW_STATUS_INVERTED = 4,    /* det F <= 0 met in the stress evaluation */
+  DW_STATUS_RENDER_OVERFLOW = 8 /* gs_render: more (kernel, tile) pairs than max_pairs; nothing drawn */
 };
 
 /* MPM background grid: nodes at origin + dx * (i, j, k); nx, ny, nz >= 3. */
@@ -323,6 +324,73 @@ int gaussian_covariance(int n, const float *H, const float *sigma0, float *sigma
  * may be NULL). */
 int gaussian_covariance_adj(int n, const float *H, const float *sigma0, const float *sigma_bar, float *H_bar,
                             float *sigma0_bar, void *stream);
+
+/* ------------------------------------------------------------ rendering */
+
+/* A view (Sec. 3.3, Eq. rendering): world-to-camera rotation R (row-major)
+ * and translation t, pinhole intrinsics fx, fy, cx, cy in pixels; pixel
+ * (i, j) has its centre at (i + 1/2, j + 1/2).  Kernels with camera depth
+ * <= near_plane are not drawn.  bg: background colour.  alpha_min: a kernel
+ * whose alpha at a pixel is below it is not blended there (0 blends every
+ * kernel at every pixel, the plain sum of Eq. rendering); t_min: a pixel
+ * stops blending once its transmittance falls below it (0: never). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float near_plane;
+  float bg[3];
+  float alpha_min;
+  float t_min;
+} dw_camera;
+
+/* Workspace of gs_render / gs_render_adj for n kernels, this camera's image
+ * size and at most max_pairs (kernel, 16 x 16 pixel tile) pairs. */
+size_t gs_render_workspace_bytes(int n, const dw_camera *cam, int64_t max_pairs);
+
+/* Image of n 3-D Gaussian kernels (Eq. rendering; appendix "3D Gaussian
+ * Representation"): kernel g has centre mu [3][n] (world), covariance
+ * sigma [6][n] (xx, yy, zz, xy, xz, yz; the gaussian_covariance output),
+ * colour [3][n] and opacity [n] in [0, 1).  Its projection has centre
+ * (fx p_x / p_z + cx, fy p_y / p_z + cy), p = R mu + t, and 2-D covariance
+ * J R Sigma R^T J^T (J the Jacobian of the projection at p); at a pixel
+ * centre x, alpha = o exp(-(x - m)^T Sigma'^-1 (x - m) / 2), and the kernels
+ * are blended front to back by p_z (equal depths in index order):
+ * C = sum_i T_i alpha_i c_i + T bg, T_i = prod_{j<i} (1 - alpha_j).
+ * Kernels with a singular 2-D covariance are not drawn.  Writes image
+ * [3][height][width].  When the kernels cover more than max_pairs (kernel,
+ * tile) pairs, status bit DW_STATUS_RENDER_OVERFLOW is set in the workspace
+ * (gs_render_status) and the image is not written.  The workspace keeps the
+ * sorted lists that gs_render_adj reads. */
+int gs_render(const dw_camera *cam, int n, const float *mu, const float *sigma, const float *color,
+              const float *opacity, float *image, int64_t max_pairs, void *ws, size_t ws_bytes, void *stream);
+
+/* Reverse of gs_render with the same arguments and the workspace it left:
+ * given image (its output) and image_bar [3][H][W], ACCUMULATES mu_bar
+ * [3][n], sigma_bar [6][n] (gradients with respect to the stored entries),
+ * color_bar [3][n] and opacity_bar [n] (any may be NULL).  Per-kernel sums
+ * use float atomics (not bit-reproducible). */
+int gs_render_adj(const dw_camera *cam, int n, const float *mu, const float *sigma, const float *color,
+                  const float *opacity, const float *image, const float *image_bar, float *mu_bar, float *sigma_bar,
+                  float *color_bar, float *opacity_bar, int64_t max_pairs, void *ws, size_t ws_bytes, void *stream);
+
+/* Copies the render workspace's status word and its pair count (two int32)
+ * to status_out (device memory), stream-ordered. */
+int gs_render_status(const void *ws, int32_t *status_out, void *stream);
+
+/* Workspace of render_loss for a C x H x W image. */
+size_t render_loss_workspace_bytes(int C, int H, int W);
+
+/* Photometric loss of Sec. 3.3 for one view: L = (1 - lambda) L1 +
+ * lambda (1 - SSIM) with L1 the mean of |image - target| over channels and
+ * pixels and SSIM the mean structural similarity (per channel, 11 x 11
+ * Gaussian window of sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, windows zero
+ * outside the image).  ADDS L to *loss (if not NULL; the block partial sums
+ * are reduced in a fixed order) and dL/dimage to image_bar (if not NULL).
+ * image, target [C][H][W]. */
+int render_loss(int C, int H, int W, const float *image, const float *target, float lambda, float *loss,
+                float *image_bar, void *ws, size_t ws_bytes, void *stream);
 
 /* -------------------------------------------------------- reconstruction */
 

@@ -26,8 +26,13 @@ Follows Sec. 3.3 (Eq. rendering and the loss L_render) and the appendix
 Readings: the projected centre is the perspective projection of W mu (the
 printed mu' = J W mu is the affine approximation's linear part); pixel
 (i, j) (column i, row j) has its centre at (i + 1/2, j + 1/2); kernels with
-camera depth below `near` are not drawn; no low-pass dilation is added to
-Sigma' (the equations have none).
+camera depth at or below `near` are not drawn; no low-pass dilation is
+added to Sigma' (the equations have none); colours are per-kernel RGB
+(view-independent).  Two optional truncations of the sum, both off by
+default (the plain sum of the equation): alpha below `alpha_min` is not
+blended, and a pixel stops blending once its transmittance has fallen below
+`t_min` (the kernel that takes it below still counts).  Equal depths keep
+the input order.
 
 Parity pins: tests/test_oracle_render.py.
 """
@@ -52,6 +57,8 @@ class Camera:
     t: tuple = (0.0, 0.0, 0.0)
     near: float = 0.01
     bg: tuple = (0.0, 0.0, 0.0)
+    alpha_min: float = 0.0
+    t_min: float = 0.0
 
 
 def project(mu, Sigma, cam: Camera):
@@ -75,23 +82,31 @@ def pixel_centres(cam: Camera):
     return torch.stack([i.reshape(-1) + 0.5, j.reshape(-1) + 0.5], dim=1)
 
 
-def render(mu, Sigma, color, opacity, cam: Camera):
+def render(mu, Sigma, color, opacity, cam: Camera, pixels=None):
     """The image (3, H, W) of Eq. rendering by alpha blending, every kernel
-    against every pixel (brute force)."""
+    against every pixel (brute force); with `pixels` ((P, 2) pixel centres)
+    the colours (3, P) of those pixels only."""
     mu2, S2, z = project(mu, Sigma, cam)
     keep = z > cam.near
     order = torch.argsort(z[keep], stable=True)
     mu2, S2, col, op = mu2[keep][order], S2[keep][order], color[keep][order], opacity[keep][order]
-    X = pixel_centres(cam)
+    X = pixel_centres(cam) if pixels is None else pixels
     d = X[None, :, :] - mu2[:, None, :]                       # (n, P, 2)
     Sinv = torch.linalg.inv(S2)                              # (n, 2, 2)
     q = torch.einsum("npa,nab,npb->np", d, Sinv, d)
     alpha = op[:, None] * torch.exp(-0.5 * q)                # (n, P)
-    one_minus = 1.0 - alpha
-    T = torch.cumprod(torch.cat([torch.ones(1, X.shape[0], dtype=_DT), one_minus], dim=0), dim=0)  # (n + 1, P)
+    if cam.alpha_min > 0.0:
+        alpha = alpha * (alpha.detach() >= cam.alpha_min)
+    ones = torch.ones(1, X.shape[0], dtype=_DT)
+    if cam.t_min > 0.0:
+        # transmittance in front of each kernel before truncation: a kernel is
+        # blended while it is at least t_min
+        T_raw = torch.cumprod(torch.cat([ones, 1.0 - alpha.detach()], dim=0), dim=0)[:-1]
+        alpha = alpha * (T_raw >= cam.t_min)
+    T = torch.cumprod(torch.cat([ones, 1.0 - alpha], dim=0), dim=0)  # (n + 1, P)
     C = (T[:-1, :, None] * alpha[:, :, None] * col[:, None, :]).sum(dim=0)               # (P, 3)
     C = C + T[-1][:, None] * torch.tensor(cam.bg, dtype=_DT)[None, :]
-    return C.T.reshape(3, cam.height, cam.width)
+    return C.T if pixels is not None else C.T.reshape(3, cam.height, cam.width)
 
 
 def gaussian_window(size: int = 11, sigma: float = 1.5):

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libdiffwind.so")
 FIXED_COROTATED, NEO_HOOKEAN = 0, 1
 BC_PERIODIC, BC_BOUNCEBACK, BC_INLET, BC_OUTLET = 0, 1, 2, 3
 WIND_NONE, WIND_FORCE_GRID, WIND_LBM_DRAG, WIND_ACC, WIND_LBM_DRAG_REL = 0, 1, 2, 3, 4
-STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED = 1, 2, 4
+STATUS_OUT_OF_GRID, STATUS_NONFINITE, STATUS_INVERTED, STATUS_RENDER_OVERFLOW = 1, 2, 4, 8
 
 # exported symbols, in the order of include/diffwind.h
 SYMBOLS = [
@@ -32,6 +32,8 @@ SYMBOLS = [
     "wind_to_grid", "mpm_p2g_adj", "mpm_grid_update_adj", "mpm_g2p_adj", "wind_to_grid_adj",
     "lbm_step", "lbm_step_adj", "lbm_step_adj_static", "lbm_equilibrium", "lbm_home_step", "lbm_home_step_adj", "lbm_home_equilibrium",
     "lbm_solid_from_particles", "gaussian_covariance", "gaussian_covariance_adj",
+    "gs_render_workspace_bytes", "gs_render", "gs_render_adj", "gs_render_status", "render_loss_workspace_bytes",
+    "render_loss",
     "phys_loss", "position_loss", "direction_metrics", "wind_guide",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
     "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats", "field_accept", "field_select",
@@ -75,6 +77,12 @@ class LBMParams(ctypes.Structure):
                 ("t_out", c_void_p), ("skip", c_void_p)]
 
 
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("R", c_float * 9), ("t", c_float * 3), ("near_plane", c_float),
+                ("bg", c_float * 3), ("alpha_min", c_float), ("t_min", c_float)]
+
+
 _lib = None
 
 
@@ -115,6 +123,13 @@ def lib():
         "lbm_solid_from_particles": ([POINTER(Lattice), P, P, c_int, P, c_int, P], c_int),
         "gaussian_covariance": ([c_int, P, P, P, P], c_int),
         "gaussian_covariance_adj": ([c_int, P, P, P, P, P, P], c_int),
+        "gs_render_workspace_bytes": ([c_int, POINTER(Camera), ctypes.c_int64], c_size_t),
+        "gs_render": ([POINTER(Camera), c_int, P, P, P, P, P, ctypes.c_int64, P, c_size_t, P], c_int),
+        "gs_render_adj": ([POINTER(Camera), c_int, P, P, P, P, P, P, P, P, P, P, ctypes.c_int64, P, c_size_t, P],
+                          c_int),
+        "gs_render_status": ([P, P, P], c_int),
+        "render_loss_workspace_bytes": ([c_int, c_int, c_int], c_size_t),
+        "render_loss": ([c_int, c_int, c_int, P, P, c_float, P, P, P, c_size_t, P], c_int),
         "phys_loss": ([c_int, P, P, c_float, P, P, P], c_int),
         "position_loss": ([c_int, P, P, P, P, P], c_int),
         "direction_metrics": ([c_int, P, P, P, P], c_int),
@@ -458,6 +473,98 @@ def gaussian_covariance_adj(H, sigma0, sigma_bar, H_bar=None, sigma0_bar=None):
     _check(lib().gaussian_covariance_adj(n, _ptr(H, name="H"), _ptr(sigma0, name="sigma0"),
                                          _ptr(sigma_bar, name="sigma_bar"), _ptr(H_bar, name="H_bar"),
                                          _ptr(sigma0_bar, name="sigma0_bar"), _stream()), "gaussian_covariance_adj")
+
+
+def make_camera(width, height, fx, fy, cx, cy, R=((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)),
+                t=(0.0, 0.0, 0.0), near_plane=0.01, bg=(0.0, 0.0, 0.0), alpha_min=0.0, t_min=0.0) -> Camera:
+    """A view: world-to-camera R (3x3, row-major) and t, pinhole intrinsics in pixels."""
+    Rf = [float(v) for row in R for v in row]
+    return Camera(int(width), int(height), float(fx), float(fy), float(cx), float(cy), (c_float * 9)(*Rf),
+                  (c_float * 3)(*t), float(near_plane), (c_float * 3)(*bg), float(alpha_min), float(t_min))
+
+
+class RenderWorkspace:
+    """Device workspace of gs_render / gs_render_adj for n kernels, one
+    camera size and at most max_pairs (kernel, tile) pairs."""
+
+    def __init__(self, n: int, cam: Camera, max_pairs: int, device="cuda"):
+        nbytes = lib().gs_render_workspace_bytes(int(n), ctypes.byref(cam), int(max_pairs))
+        if nbytes == 0:
+            raise DiffWindError("gs_render_workspace_bytes: invalid sizes")
+        self.n, self.max_pairs, self.size = int(n), int(max_pairs), (cam.width, cam.height)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.status_buf = torch.zeros(2, dtype=torch.int32, device=device)
+
+    def status(self):
+        """(status bits, pair count) of the last gs_render on this workspace (synchronises)."""
+        _check(lib().gs_render_status(_ptr(self.buf, torch.uint8, "ws"), _ptr(self.status_buf, torch.int32, "status"),
+                                      _stream()), "gs_render_status")
+        s = self.status_buf.tolist()
+        return int(s[0]), int(s[1])
+
+
+def _render_args(cam: Camera, mu, sigma, color, opacity, ws: RenderWorkspace):
+    n = mu.shape[1]
+    _shape(mu, (3, n), "mu")
+    _shape(sigma, (6, n), "sigma")
+    _shape(color, (3, n), "color")
+    _shape(opacity, (n,), "opacity")
+    if ws.n != n or ws.size != (cam.width, cam.height):
+        raise DiffWindError("render workspace was sized for another kernel count or image size")
+    return n
+
+
+def gs_render(cam: Camera, mu, sigma, color, opacity, image, ws: RenderWorkspace, check: bool = True):
+    """Writes image [3][H][W]; with check, raises if the pairs overflowed the workspace (synchronises)."""
+    n = _render_args(cam, mu, sigma, color, opacity, ws)
+    _shape(image, (3, cam.height, cam.width), "image")
+    _check(lib().gs_render(ctypes.byref(cam), n, _ptr(mu, name="mu"), _ptr(sigma, name="sigma"),
+                           _ptr(color, name="color"), _ptr(opacity, name="opacity"), _ptr(image, name="image"),
+                           ws.max_pairs, _ptr(ws.buf, torch.uint8, "ws"), ws.buf.numel(), _stream()), "gs_render")
+    if check:
+        st, pairs = ws.status()
+        if st & STATUS_RENDER_OVERFLOW:
+            raise DiffWindError(f"gs_render: more than max_pairs={ws.max_pairs} (kernel, tile) pairs")
+        return pairs
+    return None
+
+
+def gs_render_adj(cam: Camera, mu, sigma, color, opacity, image, image_bar, ws: RenderWorkspace, mu_bar=None,
+                  sigma_bar=None, color_bar=None, opacity_bar=None):
+    """Accumulates the gradients of gs_render (same arguments, same workspace) into the given outputs."""
+    n = _render_args(cam, mu, sigma, color, opacity, ws)
+    _shape(image, (3, cam.height, cam.width), "image")
+    _shape(image_bar, (3, cam.height, cam.width), "image_bar")
+    for t, shp, nm in ((mu_bar, (3, n), "mu_bar"), (sigma_bar, (6, n), "sigma_bar"), (color_bar, (3, n), "color_bar"),
+                       (opacity_bar, (n,), "opacity_bar")):
+        if t is not None:
+            _shape(t, shp, nm)
+    _check(lib().gs_render_adj(ctypes.byref(cam), n, _ptr(mu, name="mu"), _ptr(sigma, name="sigma"),
+                               _ptr(color, name="color"), _ptr(opacity, name="opacity"), _ptr(image, name="image"),
+                               _ptr(image_bar, name="image_bar"), _ptr(mu_bar, name="mu_bar"),
+                               _ptr(sigma_bar, name="sigma_bar"), _ptr(color_bar, name="color_bar"),
+                               _ptr(opacity_bar, name="opacity_bar"), ws.max_pairs, _ptr(ws.buf, torch.uint8, "ws"),
+                               ws.buf.numel(), _stream()), "gs_render_adj")
+
+
+def render_loss_workspace(C, H, W, device="cuda") -> torch.Tensor:
+    nbytes = lib().render_loss_workspace_bytes(int(C), int(H), int(W))
+    if nbytes == 0:
+        raise DiffWindError("render_loss_workspace_bytes: invalid sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def render_loss(image, target, ws, lam=0.1, loss=None, image_bar=None):
+    """Adds (1 - lam) L1 + lam (1 - SSIM) to loss[0] and its gradient to image_bar; image, target [C][H][W]."""
+    C, H, W = image.shape
+    _shape(target, (C, H, W), "target")
+    if loss is not None:
+        _shape(loss, (1,), "loss")
+    if image_bar is not None:
+        _shape(image_bar, (C, H, W), "image_bar")
+    _check(lib().render_loss(C, H, W, _ptr(image, name="image"), _ptr(target, name="target"), float(lam),
+                             _ptr(loss, name="loss"), _ptr(image_bar, name="image_bar"),
+                             _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()), "render_loss")
 
 
 def phys_loss(W, guide, weight=1.0, loss=None, W_bar=None):

@@ -131,36 +131,31 @@ __device__ __forceinline__ void sc_units_mfma(const ScLane &L, int wid, const fl
 #pragma unroll
       for (int t = 0; t < 2; ++t) acc[e][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     const int len = max(kn[0], kn[1]);
-    for (int kk = 0; kk < len; kk += 8) {
-      // LDS reads of both units' next eight particles first
-      float f3[2][2][3], av[2][2];
-      bool live[2][2];
+    for (int kk = 0; kk < len; kk += 4) {
+      // LDS reads of both units' next four particles first
+      float f3[2][3], av[2];
+      bool live[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int r = kk + L.kq;
+        live[e] = r < kn[e];
+        const int jj = k0[e] + (live[e] ? r : 0);
+        const float4 fv = s_f[jj];
+        f3[e][0] = fv.x;
+        f3[e][1] = fv.y;
+        f3[e][2] = fv.z;
+        av[e] = (live[e] && L.feat >= 0) ? s_dat[L.feat < 0 ? 0 : L.feat][jj] : 0.f;
+      }
 #pragma unroll
       for (int e = 0; e < 2; ++e)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int r = kk + 4 * h + L.kq;
-          live[e][h] = r < kn[e];
-          const int jj = k0[e] + (live[e][h] ? r : 0);
-          const float4 fv = s_f[jj];
-          f3[e][h][0] = fv.x;
-          f3[e][h][1] = fv.y;
-          f3[e][h][2] = fv.z;
-          av[e][h] = (live[e][h] && L.feat >= 0) ? s_dat[L.feat < 0 ? 0 : L.feat][jj] : 0.f;
+        for (int t = 0; t < 2; ++t) {
+          float w = 1.f;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) w *= L.cfa[t][d] + f3[e][d] * (L.cfb[t][d] + L.cfc[t][d] * f3[e][d]);
+          w = (live[e] && L.oo[t] < 27) ? w : 0.f;
+          acc[e][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], w, acc[e][t], 0, 0, 0);
         }
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            float w = 1.f;
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-              w *= L.cfa[t][d] + f3[e][h][d] * (L.cfb[t][d] + L.cfc[t][d] * f3[e][h][d]);
-            w = (live[e][h] && L.oo[t] < 27) ? w : 0.f;
-            acc[e][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e][h], w, acc[e][t], 0, 0, 0);
-          }
     }
     // lane (kq, r16) holds rows 4 kq + i of column r16 (offset o) of each
     // tile: node value kq of node cell + o is row 4 kq + (1, ox, oy, oz).

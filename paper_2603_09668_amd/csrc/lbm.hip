@@ -276,7 +276,57 @@ __device__ __forceinline__ void moments(const LbmDev &P, const float f[19], floa
   uz = (jz + 0.5f * P.F[2]) * ir;
 }
 
-template <bool SOLID>
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so
+// consecutive block indices land on different XCDs.  The pull reads every
+// node's populations from the 3 x 3 neighbouring rows; giving each XCD a
+// contiguous run of rows (in y, then z) keeps those rows in its L2.
+constexpr int N_XCD = 8;
+
+struct RowBlock {
+  int x0, j, k;
+  bool live;
+};
+
+__device__ __forceinline__ RowBlock xcd_row_block(const LbmDev &P) {
+  const int nbx = (P.nx + LBM_BLOCK - 1) / LBM_BLOCK;
+  const int64_t nblocks = (int64_t)nbx * P.ny * P.nz;
+  const int64_t per_xcd = (nblocks + N_XCD - 1) / N_XCD;
+  const int64_t b = blockIdx.x;
+  const int64_t logical = (b % N_XCD) * per_xcd + b / N_XCD;
+  RowBlock r;
+  r.live = logical < nblocks;
+  const int64_t row = logical / nbx;
+  r.x0 = (int)(logical % nbx) * LBM_BLOCK;
+  r.j = (int)(row % P.ny);
+  r.k = (int)(row / P.ny);
+  return r;
+}
+
+static dim3 xcd_lbm_grid(const LbmDev &P) {
+  const int64_t nbx = (P.nx + LBM_BLOCK - 1) / LBM_BLOCK;
+  const int64_t nblocks = nbx * P.ny * P.nz;
+  return dim3((unsigned)(((nblocks + N_XCD - 1) / N_XCD) * N_XCD));
+}
+
+// Lattices whose two population arrays exceed the 256 MB last-level cache
+// (MALL) stream their output with nontemporal stores, which keep the next
+// step's reads from being evicted; smaller lattices keep the output cached,
+// since the next step reads it back from there.
+constexpr double LBM_CACHE_BYTES = 256.0 * 1024 * 1024;
+
+static bool lbm_streams(const LbmDev &P) { return 2.0 * 76.0 * (double)P.L > LBM_CACHE_BYTES; }
+
+template <bool NT>
+__device__ __forceinline__ void st_out(float *__restrict__ plane, uint32_t node, float v) {
+  float *a = reinterpret_cast<float *>(reinterpret_cast<char *>(plane) + (node << 2));
+  if constexpr (NT) __builtin_nontemporal_store(v, a);
+  else *a = v;
+}
+
+// BIG: a lattice larger than the last-level cache (lbm_streams): a 3-D grid
+// of row blocks and nontemporal output stores; otherwise rows are handed to
+// the XCDs in contiguous runs (xcd_row_block) and the output stays cached.
+template <bool SOLID, bool BIG>
 __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *__restrict__ fin,
                                                         float *__restrict__ fout, const uint8_t *__restrict__ solid,
                                                         float *__restrict__ rho_out, float *__restrict__ u_out) {
@@ -284,8 +334,19 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
   __shared__ int s_any[LBM_BLOCK / 64];
   __shared__ float s_inl[5];
   if (P.skip && *P.skip) return;  // block-uniform: a switched-off graph branch
-  const int x0 = blockIdx.x * LBM_BLOCK;
-  const int i = x0 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  int x0, j, k;
+  if (BIG) {
+    x0 = blockIdx.x * LBM_BLOCK;
+    j = blockIdx.y;
+    k = blockIdx.z;
+  } else {
+    const RowBlock rb = xcd_row_block(P);
+    if (!rb.live) return;  // block-uniform
+    x0 = rb.x0;
+    j = rb.j;
+    k = rb.k;
+  }
+  const int i = x0 + threadIdx.x;
   if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
   const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
   float f[19];
@@ -335,13 +396,13 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
       float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
       g += kf * LW[q] * (3.f * (cF - uF) + 9.f * cu * cF);
     }
-    st_node(fout + (size_t)q * P.L, node, solid_node ? 0.f : g);
+    st_out<BIG>(fout + (size_t)q * P.L, node, solid_node ? 0.f : g);
   }
-  if (rho_out) st_node(rho_out, node, solid_node ? 1.f : rho);
+  if (rho_out) st_out<BIG>(rho_out, node, solid_node ? 1.f : rho);
   if (u_out) {
-    st_node(u_out, node, solid_node ? 0.f : ux);
-    st_node(u_out + P.L, node, solid_node ? 0.f : uy);
-    st_node(u_out + 2 * P.L, node, solid_node ? 0.f : uz);
+    st_out<BIG>(u_out, node, solid_node ? 0.f : ux);
+    st_out<BIG>(u_out + P.L, node, solid_node ? 0.f : uy);
+    st_out<BIG>(u_out + 2 * P.L, node, solid_node ? 0.f : uz);
   }
 }
 
@@ -537,38 +598,6 @@ __device__ __forceinline__ void home_row_all(std::integer_sequence<int, Qs...>, 
   bool bb[19];
   ((bb[Qs] = pull_bounces<Qs, SOL>(pull_src<Qs>(P, i, j, k), s_sol, x0)), ...);
   (home_pull_row<SOL, Qs>(P, min, s_inl, inlet_wave, i, j, k, own, bb[Qs], A), ...);
-}
-
-// Workgroups are handed to the 8 XCDs (each with its own L2) in turn, so
-// consecutive block indices land on different XCDs.  The moment-encoded step
-// reads every node's moments from the 3 x 3 neighbouring rows; giving each
-// XCD a contiguous run of rows (in y, then z) keeps those rows in its L2.
-constexpr int N_XCD = 8;
-
-struct RowBlock {
-  int x0, j, k;
-  bool live;
-};
-
-__device__ __forceinline__ RowBlock xcd_row_block(const LbmDev &P) {
-  const int nbx = (P.nx + LBM_BLOCK - 1) / LBM_BLOCK;
-  const int64_t nblocks = (int64_t)nbx * P.ny * P.nz;
-  const int64_t per_xcd = (nblocks + N_XCD - 1) / N_XCD;
-  const int64_t b = blockIdx.x;
-  const int64_t logical = (b % N_XCD) * per_xcd + b / N_XCD;
-  RowBlock r;
-  r.live = logical < nblocks;
-  const int64_t row = logical / nbx;
-  r.x0 = (int)(logical % nbx) * LBM_BLOCK;
-  r.j = (int)(row % P.ny);
-  r.k = (int)(row / P.ny);
-  return r;
-}
-
-static dim3 xcd_lbm_grid(const LbmDev &P) {
-  const int64_t nbx = (P.nx + LBM_BLOCK - 1) / LBM_BLOCK;
-  const int64_t nblocks = nbx * P.ny * P.nz;
-  return dim3((unsigned)(((nblocks + N_XCD - 1) / N_XCD) * N_XCD));
 }
 
 template <bool SOLID>
@@ -1089,12 +1118,22 @@ extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, cons
   if (rc) return rc;
   DW_REQUIRE(f_in && f_out, DW_EINVAL, "lbm_step: f_in / f_out is NULL");
   DW_REQUIRE(f_in != f_out, DW_EINVAL, "lbm_step: f_in and f_out must not alias");
-  if (solid)
-    hipLaunchKernelGGL(k_lbm_step<true>, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, f_out, solid,
-                       rho_out, u_out);
-  else
-    hipLaunchKernelGGL(k_lbm_step<false>, lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, f_in, f_out,
-                       solid, rho_out, u_out);
+  hipStream_t s = (hipStream_t)stream;
+  if (lbm_streams(P)) {
+    if (solid)
+      hipLaunchKernelGGL((k_lbm_step<true, true>), lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid, rho_out,
+                         u_out);
+    else
+      hipLaunchKernelGGL((k_lbm_step<false, true>), lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid,
+                         rho_out, u_out);
+  } else {
+    if (solid)
+      hipLaunchKernelGGL((k_lbm_step<true, false>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid,
+                         rho_out, u_out);
+    else
+      hipLaunchKernelGGL((k_lbm_step<false, false>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid,
+                         rho_out, u_out);
+  }
   return check_launch("lbm_step");
 }
 

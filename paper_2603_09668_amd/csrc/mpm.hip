@@ -316,10 +316,7 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
   const int ni = *n_items;
   // Workgroup b starts with item b (no stampede on the counter at launch);
   // later items are handed out by a ticket counter (header word 8, cleared
-  // by the sort) as items gridDim.x + ticket.  The last wave, which owns no
-  // node in pass D, draws the next ticket there, so the atomic's round trip
-  // overlaps the node owners' work.
-  static_assert(P2G_THREADS - 64 >= SC_NODES, "the last wave owns no node");
+  // by the sort) as items gridDim.x + ticket.
   int32_t *ticket = status + 8;
   for (int it = blockIdx.x; it < ni; it = s_next) {
     const int tile = item_tile[it];
@@ -399,11 +396,14 @@ __global__ __launch_bounds__(P2G_THREADS) __attribute__((amdgpu_waves_per_eu(4))
       sc_stage(s_dat, s_f, slot, f, m, qv, A);
     }
     __syncthreads();
-    // pass C
+    // pass C; the next ticket is drawn before it and stored after it, so the
+    // atomic's round trip overlaps the matrix work
+    int tk = 0;
+    if (tid == P2G_THREADS - 1) tk = atomicAdd(ticket, 1);
     sc_units_mfma(L, wid, s_dat, s_f, s_udesc, s_nunits, s_node[wid]);
+    if (tid == P2G_THREADS - 1) s_next = (int)gridDim.x + tk;
     __syncthreads();
     // pass D: node owners add the wave blocks in a fixed order
-    if (tid == P2G_THREADS - 1) s_next = (int)gridDim.x + atomicAdd(ticket, 1);
     if (tid < SC_NODES) {
       float sm = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll

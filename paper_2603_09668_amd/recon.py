@@ -5,13 +5,15 @@ The paper optimises, one time step after another, the force field that
 drives the object from the previous optimised state to the observed next
 state (initialised from zero each time), with a photometric loss plus the
 physics-informed loss that aligns the force directions with the LBM wind
-velocity.  Without images, the observed states here are particle positions
-of a reference rollout and the photometric loss becomes the position loss
-sum_p |x_p - x*_p|^2 (normalised by its value at W = 0).  Every step runs in
-the library's kernels: the differentiable rollout (forward, checkpointed
-recompute, adjoints), `position_loss`, `phys_loss`, `adam_step`,
-`wind_guide` and `direction_metrics`; torch holds the buffers and calls the
-rollout's backward.
+velocity.  Two observation models: `frame` compares particle positions with
+those of a reference rollout (the position loss sum_p |x_p - x*_p|^2);
+`frame_render` compares rendered images with target images (L_render of
+Sec. 3.3: every particle is a Gaussian kernel whose covariance follows its
+deformation gradient, Sigma(t) = F Sigma0 F^T, rendered by `gs_render`;
+the gradient runs back through `render_loss`, `gs_render_adj`,
+`gaussian_covariance_adj` and the rollout).  Both losses are normalised by
+their value at W = 0.  Every step runs in the library's kernels; torch holds
+the buffers and calls the rollout's backward.
 """
 from __future__ import annotations
 
@@ -21,6 +23,51 @@ import torch
 
 from . import api
 from .autograd import RolloutPlan, rollout
+
+
+@dataclass
+class View:
+    """One camera with its target image and its device workspaces."""
+    cam: api.Camera
+    target: torch.Tensor          # (3, H, W)
+    ws: api.RenderWorkspace
+    loss_ws: torch.Tensor
+    image: torch.Tensor           # (3, H, W) scratch for the rendered image
+
+
+def make_view(cam: api.Camera, target, n: int, max_pairs: int, device="cuda") -> View:
+    return View(cam, target, api.RenderWorkspace(n, cam, max_pairs, device=device),
+                api.render_loss_workspace(3, cam.height, cam.width, device=device),
+                torch.empty(3, cam.height, cam.width, device=device))
+
+
+def render_image(view: View, mu, H, sigma0, color, opacity):
+    """The image of kernels at mu (3, n) with covariances F sigma0 F^T (H = F - I)."""
+    sig = torch.empty_like(sigma0)
+    api.gaussian_covariance(H, sigma0, sig)
+    img = torch.empty_like(view.image)
+    api.gs_render(view.cam, mu, sig, color, opacity, img, view.ws)
+    return img
+
+
+def render_loss_grad(views, mu, H, sigma0, color, opacity, lam: float = 0.1):
+    """L_render = sum over views of (1 - lam) L1 + lam (1 - SSIM) of the
+    rendered kernels against the views' targets, and its gradients with
+    respect to the centres mu (3, n) and H (9, n) (through Sigma = F sigma0 F^T)."""
+    n = mu.shape[1]
+    sig = torch.empty_like(sigma0)
+    api.gaussian_covariance(H, sigma0, sig)
+    L = torch.zeros(1, device=mu.device)
+    mu_bar = torch.zeros_like(mu)
+    sig_bar = torch.zeros_like(sigma0)
+    for v in views:
+        api.gs_render(v.cam, mu, sig, color, opacity, v.image, v.ws)
+        ib = torch.zeros_like(v.image)
+        api.render_loss(v.image, v.target, v.loss_ws, lam, L, ib)
+        api.gs_render_adj(v.cam, mu, sig, color, opacity, v.image, ib, v.ws, mu_bar=mu_bar, sigma_bar=sig_bar)
+    H_bar = torch.zeros(9, n, device=mu.device)
+    api.gaussian_covariance_adj(H, sigma0, sig_bar, H_bar=H_bar)
+    return L, mu_bar, H_bar
 
 
 @dataclass
@@ -89,6 +136,41 @@ class Reconstructor:
             W.grad = None
             torch.autograd.backward(xT, grad_tensors=xb / scale)
             total = float(lp.item()) / scale
+            if n_guided is not None:
+                lph = torch.zeros(1, device=dev)
+                api.phys_loss(W.detach()[0], guide, lam / n_guided, lph, W.grad[0])
+                total += float(lph.item())
+            res.loss.append(total)
+            api.adam_step(W.data, W.grad, m, v, lr, 0.9, 0.999, 1e-8, it + 1)
+        res.W = W.detach()[0].clone()
+        return res
+
+
+    def frame_render(self, state, views, sigma0, color, opacity, guide=None, lam: float = 0.0, iters: int = 30,
+                     lr: float = 0.5) -> FrameResult:
+        """Optimise the force field of one frame from zero against target
+        images: Adam on L_render / L_render(W = 0) + lam * L_phys / (nodes
+        with a guide).  sigma0 (6, n), color (3, n), opacity (n,) describe
+        the particles' Gaussian kernels at rest."""
+        dev = self.device
+        W = torch.zeros(1, 3, self.n_nodes, device=dev, requires_grad=True)
+        m = torch.zeros_like(W)
+        v = torch.zeros_like(W)
+        res = FrameResult(W=None)
+        scale = None
+        n_guided = None
+        if guide is not None and lam > 0:
+            cnt = torch.zeros(3, device=dev)
+            api.direction_metrics(guide, guide, cnt)
+            n_guided = max(float(cnt[2].item()), 1.0)
+        for it in range(iters):
+            xT, _, _, HT = rollout(self.plan, W, self.E, *state)
+            L, xb, Hb = render_loss_grad(views, self.xref + xT.detach(), HT.detach(), sigma0, color, opacity)
+            if scale is None:
+                scale = max(float(L.item()), 1e-30)
+            W.grad = None
+            torch.autograd.backward([xT, HT], grad_tensors=[xb / scale, Hb / scale])
+            total = float(L.item()) / scale
             if n_guided is not None:
                 lph = torch.zeros(1, device=dev)
                 api.phys_loss(W.detach()[0], guide, lam / n_guided, lph, W.grad[0])

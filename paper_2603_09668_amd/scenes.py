@@ -241,3 +241,89 @@ def wind_tunnel_obstacles(seed: int, dims=(64, 64, 64)):
         solid[o[2]:o[2] + s[2], o[1]:o[1] + s[1], o[0]:o[0] + s[0]] = True
     bc = (BC_INLET, BC_OUTLET, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK, BC_BOUNCEBACK)
     return u, solid, bc
+
+
+@dataclass
+class GaussianCloud:
+    """Inputs of the renderer: n kernels in the [3][n] / [6][n] layouts of
+    the C header (float64 here) and one view."""
+    mu: np.ndarray        # (3, n)
+    sigma: np.ndarray     # (6, n): xx, yy, zz, xy, xz, yz
+    color: np.ndarray     # (3, n)
+    opacity: np.ndarray   # (n,)
+    camera: dict          # width, height, fx, fy, cx, cy, R (3x3), t (3), near
+
+
+def _look_at(eye, target):
+    """World-to-camera rotation whose camera z axis points from eye to target
+    (camera y down, x right) and the matching translation."""
+    eye, target = np.asarray(eye, float), np.asarray(target, float)
+    z = target - eye
+    z /= np.linalg.norm(z)
+    up = np.array([0.0, 0.0, 1.0]) if abs(z[2]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    x = np.cross(z, -up)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    R = np.stack([x, y, z])
+    return R, -R @ eye
+
+
+def random_gaussians(seed: int, n: int, width: int = 40, height: int = 36, depth=(1.5, 3.5), scale=0.05,
+                     opacity=(0.2, 0.9), min_depth_gap: float = 1e-5) -> GaussianCloud:
+    """n kernels spread over the view of a camera at the origin looking along
+    +z (depths in `depth`, anisotropic covariances of size ~scale, random RGB
+    and opacity).  Depths are stratified (one per slot of width
+    (hi - lo) / n, jittered within the middle 60 % of the slot, in random
+    order), so any two differ by at least 0.4 (hi - lo) / n and the
+    front-to-back order does not depend on rounding."""
+    rng = np.random.default_rng(seed)
+    f = 1.2 * width
+    lo, hi = depth
+    z = lo + (hi - lo) * (np.arange(n) + 0.2 + 0.6 * rng.uniform(0, 1, n)) / max(n, 1)
+    z = z[rng.permutation(n)]
+    assert n < 2 or np.min(np.diff(np.sort(z))) >= min(min_depth_gap, 0.4 * (hi - lo) / n)
+    u = rng.uniform(-0.1 * width, 1.1 * width, n)
+    v = rng.uniform(-0.1 * height, 1.1 * height, n)
+    x = (u - width / 2) * z / f
+    y = (v - height / 2) * z / f
+    A = rng.standard_normal((n, 3, 3)) * scale
+    S = A @ A.transpose(0, 2, 1) + (0.1 * scale) ** 2 * np.eye(3)
+    sigma = np.stack([S[:, 0, 0], S[:, 1, 1], S[:, 2, 2], S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]])
+    cam = dict(width=width, height=height, fx=f, fy=1.05 * f, cx=width / 2, cy=height / 2, R=np.eye(3),
+               t=np.zeros(3), near=0.1)
+    return GaussianCloud(np.stack([x, y, z]), sigma, rng.uniform(0, 1, (3, n)), rng.uniform(*opacity, n), cam)
+
+
+def splat_scene(seed: int = 0, n_object: int = 500_000, n_background: int = 500_000, res: int = 128,
+                width: int = 1024, height: int = 1024) -> GaussianCloud:
+    """A splat scene shaped like the paper's captured ones (Tab. sim_time: an
+    object of 52k-146k kernels inside 0.5-4.5M background kernels): the
+    object kernels sit on the flag-and-leaves particles (isotropic, half the
+    particle spacing), the background kernels on a thick shell around the
+    simulation box (radii 1.2-2.0, larger, flattened along the shell
+    normal); one camera outside the shell looking at the box centre."""
+    rng = np.random.default_rng(seed + 101)
+    sc = flag_and_leaves_scene(seed=seed, n=n_object, res=res, lbm_dims=(res, res // 2, res // 2))
+    dx = sc.grid["dx"]
+    centre = np.array(sc.grid["origin"]) + 0.5 * dx * np.array([sc.grid["nx"], sc.grid["ny"], sc.grid["nz"]])
+    spacing = (sc.vol0.mean()) ** (1.0 / 3.0)
+    mu_o = sc.x.T
+    s_o = (0.5 * spacing) ** 2
+    sig_o = np.zeros((6, n_object))
+    sig_o[:3] = s_o
+    d = rng.standard_normal((n_background, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = rng.uniform(1.2, 2.0, n_background)
+    mu_b = (centre + d * r[:, None]).T
+    a = rng.uniform(0.01, 0.04, n_background)
+    # covariance a^2 (I - 0.9 d d^T): flattened along the shell normal
+    S = a[:, None, None] ** 2 * (np.eye(3)[None] - 0.9 * d[:, :, None] * d[:, None, :])
+    sig_b = np.stack([S[:, 0, 0], S[:, 1, 1], S[:, 2, 2], S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]])
+    eye_dir = np.array([-0.45, -0.8, 0.25])
+    eye = centre + 2.3 * eye_dir / np.linalg.norm(eye_dir)  # outside the shell
+    R, t = _look_at(eye, centre)
+    f = 1.1 * width
+    cam = dict(width=width, height=height, fx=f, fy=f, cx=width / 2, cy=height / 2, R=R, t=t, near=0.05)
+    col = np.concatenate([rng.uniform(0.2, 0.9, (3, n_object)), rng.uniform(0, 1, (3, n_background))], axis=1)
+    op = np.concatenate([rng.uniform(0.5, 0.95, n_object), rng.uniform(0.1, 0.9, n_background)])
+    return GaussianCloud(np.concatenate([mu_o, mu_b], axis=1), np.concatenate([sig_o, sig_b], axis=1), col, op, cam)

@@ -1,0 +1,247 @@
+"""GPU parity of the renderer and the photometric loss (gs_render,
+gs_render_adj, render_loss) against the float64 oracle (oracle/render.py)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import render as orender
+from paper_2603_09668_amd import api, scenes
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+
+def _cams(cam: dict, alpha_min=0.0, t_min=0.0, bg=(0.1, 0.2, 0.3)):
+    R = np.asarray(cam["R"], dtype=np.float64)
+    oc = orender.Camera(width=cam["width"], height=cam["height"], fx=cam["fx"], fy=cam["fy"], cx=cam["cx"],
+                        cy=cam["cy"], R=tuple(map(tuple, R.tolist())), t=tuple(np.asarray(cam["t"]).tolist()),
+                        near=cam["near"], bg=bg, alpha_min=alpha_min, t_min=t_min)
+    gc = api.make_camera(cam["width"], cam["height"], cam["fx"], cam["fy"], cam["cx"], cam["cy"], R=R.tolist(),
+                         t=np.asarray(cam["t"]).tolist(), near_plane=cam["near"], bg=bg, alpha_min=alpha_min,
+                         t_min=t_min)
+    return oc, gc
+
+
+def _dev(g: scenes.GaussianCloud):
+    f = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda").contiguous()
+    return f(g.mu), f(g.sigma), f(g.color), f(g.opacity)
+
+
+def _oracle_inputs(dev):
+    """float64 copies of the float32 device inputs, oracle layouts."""
+    mu, sig, col, op = (t.double().cpu() for t in dev)
+    S = torch.zeros(mu.shape[1], 3, 3, dtype=DT)
+    for e, (a, b) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        S[:, a, b] = sig[e]
+        S[:, b, a] = sig[e]
+    return mu.T.contiguous(), S, col.T.contiguous(), op
+
+
+def _render_gpu(gc, dev, max_pairs=None):
+    mu = dev[0]
+    n = mu.shape[1]
+    T = ((gc.width + 15) // 16) * ((gc.height + 15) // 16)
+    ws = api.RenderWorkspace(n, gc, max_pairs if max_pairs is not None else max(n * T, 1))
+    img = torch.full((3, gc.height, gc.width), -1.0, device="cuda")
+    pairs = api.gs_render(gc, *dev, img, ws)
+    torch.cuda.synchronize()
+    return img, ws, pairs
+
+
+@pytest.mark.parametrize("size", [(40, 36), (16, 16), (53, 7)])
+def test_render_matches_oracle_exact_sum(size):
+    """alpha_min = t_min = 0: every kernel at every pixel, the plain sum of
+    Eq. rendering; several tiles with ragged edges; rotated camera."""
+    W, H = size
+    g = scenes.random_gaussians(11, 300, width=W, height=H)
+    ang = 0.15
+    Rz = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1.0]])
+    g.camera["R"] = Rz
+    g.camera["t"] = np.array([0.02, -0.03, 0.1])
+    oc, gc = _cams(g.camera)
+    dev = _dev(g)
+    img, ws, pairs = _render_gpu(gc, dev)
+    ref = orender.render(*_oracle_inputs(dev), oc)
+    err = (img.double().cpu() - ref).abs().max().item()
+    assert err < 2e-5, err
+    assert pairs == 300 * ((W + 15) // 16) * ((H + 15) // 16)
+
+
+def test_render_truncated_matches_oracle():
+    """alpha_min = 1/255 and t_min = 1e-3 on both sides: the same function;
+    a float32 alpha straddling alpha_min may flip one term (at most
+    alpha_min), so all pixels are held to alpha_min and 99.9 % to 2e-5."""
+    g = scenes.random_gaussians(12, 3000, width=96, height=80, opacity=(0.3, 0.95))
+    oc, gc = _cams(g.camera, alpha_min=1.0 / 255.0, t_min=1e-3)
+    dev = _dev(g)
+    img, ws, pairs = _render_gpu(gc, dev)
+    assert 0 < pairs < 3000 * 30
+    ref = orender.render(*_oracle_inputs(dev), oc)
+    err = (img.double().cpu() - ref).abs()
+    assert err.max().item() < 1.0 / 255.0
+    assert torch.quantile(err.flatten(), 0.999).item() < 2e-5
+
+
+def test_render_gradients_match_oracle_autograd():
+    """gs_render_adj(render_loss gradient) against oracle autograd of
+    L_render = 0.9 L1 + 0.1 (1 - SSIM) for centres, covariances (stored
+    entries), colours and opacities: <= 1e-3 of each gradient's largest
+    entry."""
+    g = scenes.random_gaussians(13, 80, width=32, height=24, scale=0.08)
+    oc, gc = _cams(g.camera)
+    dev = _dev(g)
+    img, ws, _ = _render_gpu(gc, dev)
+    rng = np.random.default_rng(5)
+    target = torch.tensor(rng.uniform(0, 1, (3, 24, 32)), dtype=torch.float32, device="cuda")
+    lws = api.render_loss_workspace(3, 24, 32)
+    loss = torch.zeros(1, device="cuda")
+    ibar = torch.zeros_like(img)
+    api.render_loss(img, target, lws, 0.1, loss, ibar)
+    n = 80
+    bars = [torch.zeros(3, n, device="cuda"), torch.zeros(6, n, device="cuda"), torch.zeros(3, n, device="cuda"),
+            torch.zeros(n, device="cuda")]
+    api.gs_render_adj(gc, *dev, img, ibar, ws, *bars)
+    torch.cuda.synchronize()
+    mu, S, col, op = (t.clone().requires_grad_(True) for t in _oracle_inputs(dev))
+    L = orender.render_loss([orender.render(mu, S, col, op, oc)], [target.double().cpu()])
+    gmu, gS, gcol, gop = torch.autograd.grad(L, [mu, S, col, op])
+    assert abs(loss.item() - L.item()) < 1e-5 * max(1.0, abs(L.item()))
+    gS6 = torch.stack([gS[:, 0, 0], gS[:, 1, 1], gS[:, 2, 2], gS[:, 0, 1] + gS[:, 1, 0], gS[:, 0, 2] + gS[:, 2, 0],
+                       gS[:, 1, 2] + gS[:, 2, 1]])
+    for name, got, want in (("mu", bars[0], gmu.T), ("sigma", bars[1], gS6), ("color", bars[2], gcol.T),
+                            ("opacity", bars[3], gop)):
+        got = got.double().cpu()
+        scale = want.abs().max().item()
+        err = (got - want).abs().max().item()
+        assert err <= 1e-3 * scale, (name, err, scale)
+
+
+@pytest.mark.parametrize("shape", [(3, 37, 45), (1, 16, 16), (3, 5, 70)])
+def test_render_loss_matches_oracle(shape):
+    """L1 + D-SSIM value and image gradient against the oracle (zero-padded
+    windows at the border, images smaller than the window included)."""
+    rng = np.random.default_rng(sum(shape))
+    a = torch.tensor(rng.uniform(0, 1, shape), dtype=torch.float32, device="cuda")
+    b = torch.tensor(rng.uniform(0, 1, shape), dtype=torch.float32, device="cuda")
+    ws = api.render_loss_workspace(*shape)
+    loss = torch.full((1,), 0.25, device="cuda")
+    abar = torch.zeros_like(a)
+    api.render_loss(a, b, ws, 0.1, loss, abar)
+    torch.cuda.synchronize()
+    A = a.double().cpu().requires_grad_(True)
+    L = orender.render_loss([A], [b.double().cpu()], lam=0.1)
+    (gA,) = torch.autograd.grad(L, [A])
+    assert abs(loss.item() - 0.25 - L.item()) < 2e-6
+    err = (abar.double().cpu() - gA).abs().max().item()
+    assert err <= 1e-4 * gA.abs().max().item(), err
+
+
+def test_render_edge_cases():
+    """No kernels, every kernel behind the near plane, and a pair count over
+    the capacity (status bit, error, image left untouched)."""
+    g = scenes.random_gaussians(14, 50, width=20, height=20)
+    oc, gc = _cams(g.camera)
+    bg = torch.tensor([0.1, 0.2, 0.3], device="cuda").view(3, 1, 1)
+    empty = tuple(torch.zeros(r, 0, device="cuda") for r in (3, 6, 3)) + (torch.zeros(0, device="cuda"),)
+    img, _, pairs = _render_gpu(gc, empty)
+    assert pairs == 0 and torch.equal(img, bg.expand_as(img))
+    dev = list(_dev(g))
+    dev[0] = dev[0].clone()
+    dev[0][2] = -dev[0][2]
+    img, _, pairs = _render_gpu(gc, tuple(dev))
+    assert pairs == 0 and torch.equal(img, bg.expand_as(img))
+    dev = _dev(g)
+    with pytest.raises(api.DiffWindError, match="max_pairs"):
+        _render_gpu(gc, dev, max_pairs=10)
+    ws = api.RenderWorkspace(50, gc, 10)
+    img = torch.full((3, 20, 20), -1.0, device="cuda")
+    api.gs_render(gc, *dev, img, ws, check=False)
+    st, _ = ws.status()
+    assert st & api.STATUS_RENDER_OVERFLOW
+    assert torch.equal(img, torch.full_like(img, -1.0))
+
+
+def test_rollout_render_loss_gradient_matches_oracle():
+    """The photometric reconstruction gradient end to end: a 12-substep
+    rollout driven by a force grid, every particle a Gaussian kernel with
+    Sigma = F Sigma0 F^T, L_render of one view against a target image; dL/dW
+    through render_loss, gs_render_adj, gaussian_covariance_adj and the
+    rollout adjoints against oracle autograd (norm-wise <= 1e-3)."""
+    from oracle import gauss as ogauss
+    from oracle import mpm as ompm
+    from oracle import wind as owind
+    from paper_2603_09668_amd import recon
+    from paper_2603_09668_amd.autograd import RolloutPlan, rollout
+    from test_gpu_rollout import _setup
+
+    grid, x0, region, mass, vol0, E, nu, W, _, cfg = _setup(api.FIXED_COROTATED, n=400)
+    n = x0.shape[0]
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((n, 3, 3)) * 0.004
+    S0 = A @ A.transpose(0, 2, 1) + (0.004 ** 2) * np.eye(3)
+    sig0 = torch.tensor(np.stack([S0[:, a, b] for a, b in ogauss.PAIRS]), dtype=DT)       # (6, n)
+    col = torch.tensor(rng.uniform(0.1, 0.9, (3, n)), dtype=DT)
+    op = torch.tensor(rng.uniform(0.3, 0.8, n), dtype=DT)
+    cam = dict(width=40, height=32, fx=90.0, fy=90.0, cx=20.0, cy=16.0, R=np.eye(3),
+               t=np.array([-0.5, -0.5, 0.9]), near=0.05)
+    oc, gc = _cams(cam)
+    target = torch.tensor(rng.uniform(0.0, 1.0, (3, 32, 40)), dtype=DT)
+    # oracle
+    og = ompm.Grid(grid["nx"], grid["ny"], grid["nz"], grid["dx"])
+    mu_l, lam_l = ompm.particle_mu_lam(E, nu, region)
+    Wo = W.clone().requires_grad_(True)
+    st = {"x": x0, "v": torch.zeros(n, 3, dtype=DT), "C": torch.zeros(n, 3, 3, dtype=DT),
+          "F": torch.eye(3, dtype=DT).repeat(n, 1, 1)}
+    for s in range(cfg["n_sub"]):
+        k = s * cfg["K"] // cfg["n_sub"]
+        acc = owind.force_grid_to_nodes(og, Wo[k], cfg["nw"], (0, 0, 0), (1, 1, 1))
+        st, _ = ompm.substep(og, st, mass, vol0, mu_l, lam_l, cfg["dt"], cfg["material"], gravity=cfg["gravity"],
+                             acc=acc, bound=cfg["bound"])
+    Sig = ogauss.unpack(ogauss.covariance(st["F"], sig0.T))
+    Lo = orender.render_loss([orender.render(st["x"], Sig, col.T, op, oc)], [target])
+    (gWo,) = torch.autograd.grad(Lo, [Wo])
+    # library
+    dev = "cuda"
+    xd = x0.T.contiguous().float().to(dev)
+    plan = RolloutPlan(grid, n, mass.float().to(dev), vol0.float().to(dev), region.to(torch.int32).to(dev),
+                       nu.float().to(dev), None, cfg["dt"], cfg["gravity"], cfg["material"], cfg["bound"], cfg["nw"],
+                       (0, 0, 0), (1, 1, 1), cfg["K"], cfg["n_sub"], cfg["ckpt"], xref=xd)
+    Wd = W.float().to(dev).contiguous().requires_grad_(True)
+    z3, z9 = torch.zeros(3, n, device=dev), torch.zeros(9, n, device=dev)
+    xT, _, _, HT = rollout(plan, Wd, E.float().to(dev), torch.zeros_like(xd), z3, z9, z9.clone())
+    T = ((40 + 15) // 16) * ((32 + 15) // 16)
+    view = recon.make_view(gc, target.float().to(dev), n, n * T)
+    f = lambda t: t.float().to(dev).contiguous()
+    L, xb, Hb = recon.render_loss_grad([view], xd + xT.detach(), HT.detach(), f(sig0), f(col), f(op))
+    torch.autograd.backward([xT, HT], grad_tensors=[xb, Hb])
+    torch.cuda.synchronize()
+    assert abs(L.item() - Lo.item()) < 1e-5 * abs(Lo.item())
+    rel = (Wd.grad.double().cpu() - gWo).norm().item() / gWo.norm().item()
+    assert rel < 1e-3, rel
+
+
+def test_render_full_size_sampled():
+    """The splat workload the benchmark times (500k object kernels on the
+    flag-and-leaves particles, 500k background kernels, 1024 x 1024, the
+    usual truncations alpha_min = 1/255, t_min = 1e-4): 48 seeded pixels
+    against the oracle evaluated at those pixels over all kernels with the
+    same truncations (a float32 alpha straddling alpha_min may flip one
+    term: the largest error is held to alpha_min, the others to 5e-5)."""
+    g = scenes.splat_scene(seed=0)
+    oc, gc = _cams(g.camera, alpha_min=1.0 / 255.0, t_min=1e-4, bg=(0.0, 0.0, 0.0))
+    dev = _dev(g)
+    n = dev[0].shape[1]
+    img, ws, pairs = _render_gpu(gc, dev, max_pairs=24 * n)
+    assert pairs > n
+    rng = np.random.default_rng(3)
+    ij = np.stack([rng.integers(0, gc.width, 48), rng.integers(0, gc.height, 48)], axis=1)
+    mu, S, col, op = _oracle_inputs(dev)
+    errs = []
+    for c0 in range(0, 48, 8):
+        pix = torch.tensor(ij[c0:c0 + 8] + 0.5, dtype=DT)
+        ref = orender.render(mu, S, col, op, oc, pixels=pix)
+        got = img[:, ij[c0:c0 + 8, 1], ij[c0:c0 + 8, 0]].double().cpu()
+        errs.append((got - ref).abs().amax(dim=0))
+    e = torch.cat(errs).sort().values
+    assert e[-1].item() < 1.0 / 255.0, e[-3:]
+    assert e[-2].item() < 5e-5, e[-3:]

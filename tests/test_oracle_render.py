@@ -180,3 +180,31 @@ def test_render_gradients_match_finite_differences():
                 fd = (vals[0] - vals[1]) / (2 * h)
                 an = g[idx].item()
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (k, idx, fd, an)
+
+
+def test_truncations_and_pixel_subset():
+    """alpha_min drops a kernel whose alpha stays below it (the image equals
+    the render without that kernel); t_min stops a pixel after the kernel
+    that takes its transmittance below it; a pixel subset gives the same
+    colours as the full image."""
+    cam = orender.Camera(width=16, height=16, fx=20.0, fy=20.0, cx=8.0, cy=8.0, bg=(0.2, 0.3, 0.4))
+    def on_ray(z):
+        return [(8.5 - 8.0) * z / 20.0, (8.5 - 8.0) * z / 20.0, z]
+    S = 0.01 * torch.eye(3, dtype=DT)[None].repeat(3, 1, 1)
+    c = torch.tensor([[1.0, 0.0, 0.0], [0.0, 1.0, 0.5], [0.3, 0.3, 0.3]], dtype=DT)
+    mu = torch.tensor([on_ray(1.0), on_ray(2.0), on_ray(3.0)], dtype=DT)
+    o = torch.tensor([0.6, 0.8, 1e-3], dtype=DT)
+    full = orender.render(mu, S, c, o, cam)
+    cam_a = orender.Camera(**{**cam.__dict__, "alpha_min": 2e-3})
+    bg = torch.tensor(cam.bg, dtype=DT)
+    two = o[0] * c[0] + (1 - o[0]) * o[1] * c[1] + (1 - o[0]) * (1 - o[1]) * bg
+    assert (orender.render(mu, S, c, o, cam_a)[:, 8, 8] - two).abs().max() < 1e-15
+    assert (full[:, 8, 8] - two).abs().max() > 5e-6
+    cam_t = orender.Camera(**{**cam.__dict__, "t_min": 0.5})
+    px = orender.render(mu, S, c, o, cam_t)[:, 8, 8]
+    want = o[0] * c[0] + (1 - o[0]) * torch.tensor(cam.bg, dtype=DT)
+    assert (px - want).abs().max() < 1e-15
+    pix = torch.tensor([[8.5, 8.5], [0.5, 15.5], [3.5, 7.5]], dtype=DT)
+    sub = orender.render(mu, S, c, o, cam, pixels=pix)
+    for k, (x, y) in enumerate(pix.tolist()):
+        assert (sub[:, k] - full[:, int(y), int(x)]).abs().max() < 1e-15
