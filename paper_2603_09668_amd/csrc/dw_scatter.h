@@ -73,26 +73,38 @@ __device__ __forceinline__ ScLane sc_lane(int lane) {
   return L;
 }
 
+// DPP source v shifted by CTRL within the enabled rows (ROWS mask), zero
+// where the source lane lies outside the row or the row is not enabled
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int sc_dpp(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+
+// Inclusive scan over the 64 lanes of a fully active wave without LDS round
+// trips: Hillis-Steele inside each 16-lane row (row shifts by 1, 2, 4, 8),
+// then row 0's total broadcast into row 1 and row 2's into row 3 (row
+// broadcast of lane 15), then the total of rows 0-1 into rows 2 and 3 (row
+// broadcast of lane 31).
+__device__ __forceinline__ int sc_wave_scan(int v) {
+  v += sc_dpp<0x111>(v);
+  v += sc_dpp<0x112>(v);
+  v += sc_dpp<0x114>(v);
+  v += sc_dpp<0x118>(v);
+  v += sc_dpp<0x142, 0xA>(v);
+  v += sc_dpp<0x143, 0xC>(v);
+  return v;
+}
+
 // Wave 0: exclusive scan of the 64 cell counts into s_off / s_cur and the
 // unit descriptors (first slot | count << 10 | node base << 17).
 __device__ __forceinline__ void sc_scan_units(int lane, const int *s_cnt, int *s_off, int *s_cur, int *s_udesc,
                                               int *s_nunits) {
   const int v = s_cnt[lane];
-  int inc = v;
-#pragma unroll
-  for (int sh = 1; sh < 64; sh <<= 1) {
-    int t = __shfl_up(inc, sh, 64);
-    if (lane >= sh) inc += t;
-  }
+  const int inc = sc_wave_scan(v);
   s_off[lane] = inc - v;
   s_cur[lane] = inc - v;
   const int nu = (v + SC_UNIT - 1) / SC_UNIT;
-  int uinc = nu;
-#pragma unroll
-  for (int sh = 1; sh < 64; sh <<= 1) {
-    int t = __shfl_up(uinc, sh, 64);
-    if (lane >= sh) uinc += t;
-  }
+  const int uinc = sc_wave_scan(nu);
   const int u0 = uinc - nu;
   const int nbase = (lane & 3) + SC_L * (((lane >> 2) & 3) + SC_L * (lane >> 4));
   for (int q = 0; q < nu; ++q) s_udesc[u0 + q] = (inc - v + q * SC_UNIT) | (min(SC_UNIT, v - q * SC_UNIT) << 10) | (nbase << 17);

@@ -21,9 +21,10 @@
 // Reverse (gs_render_adj): the same traversal per pixel, front to back,
 // recomputing alpha and T; dC/dalpha_i = T_i c_i - (C - A_i) / (1 - alpha_i)
 // with A_i the colour blended up to and including i (C includes the
-// background term).  Per-kernel adjoints of the centre, conic, opacity and
-// colour are summed over a wave with butterfly shuffles, over the
-// workgroup in LDS, and added to global memory with one atomic per value;
+// background term).  The reverse pass runs one wave per tile with four
+// pixels per lane: per-kernel adjoints of the centre, conic, opacity and
+// colour are summed over the lane's pixels, then over the wave with DPP
+// row operations, and added to global memory with one atomic per value;
 // k_gs_project_adj then takes the centre and conic adjoints back to mu and
 // Sigma through the projection.
 // Loss (render_loss): L1 and SSIM with an 11 x 11 Gaussian window
@@ -48,6 +49,12 @@ constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_PER;
 constexpr int SCAN_TOP_THREADS = 1024;
 constexpr int SCAN_TOP_MAX = SCAN_TOP_THREADS * 16;  // block sums the top level scans
 
+// workspace header: [0] status, [1] pair count, [GS_CNT0 ...] 64 partial
+// 64-bit pair totals (one per block residue, to spread the atomics)
+constexpr int GS_HDR_INTS = 256;
+constexpr int GS_CNT0 = 64;
+constexpr int GS_NCNT = 64;
+
 struct CamDev {
   int W, H, tw, th;
   float fx, fy, cx, cy;
@@ -57,7 +64,7 @@ struct CamDev {
 };
 
 // Workspace of gs_render / gs_render_adj (all sections 256-aligned):
-//   header [64] int32: status, pair count
+//   header [256] int32: status, pair count, 64 partial pair totals (u64)
 //   rec [n] 3 float4: (mx, my, A, B), (C, o, c0, c1), (c2, -, -, -)
 //   rect [n] int4 tile box (tx0, tx1, ty0, ty1); cnt [n] int32
 //   key_a, key_b [n] u32, id_a, id_b [n] int32   (depth sort)
@@ -97,7 +104,7 @@ static GsWs gs_layout(char *base, int64_t n, int64_t P, int W, int H) {
     o += al256(bytes);
     return p;
   };
-  w.hdr = (int32_t *)take(256);
+  w.hdr = (int32_t *)take(GS_HDR_INTS * 4);
   w.rec = (float4 *)take((size_t)n * 3 * sizeof(float4));
   w.rect = (int4 *)take((size_t)n * sizeof(int4));
   w.cnt = (int32_t *)take((size_t)n * 4);
@@ -227,11 +234,18 @@ __global__ __launch_bounds__(256) void k_gs_project(CamDev K, int n, const float
     w.key_a[g] = key;
     w.id_a[g] = g;
   }
-  // 64-bit pair total (the int32 scan below is only trusted when it fits)
-  int sw = c;
+  // 64-bit pair total (the int32 scan below is only trusted when it fits):
+  // a block sum added to one of 64 partial counters
+  __shared__ unsigned long long s_c[256 / 64];
+  unsigned long long sw = (unsigned long long)c;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) sw += __shfl_xor(sw, m, 64);
-  if ((threadIdx.x & 63) == 0 && sw) atomicAdd(reinterpret_cast<unsigned long long *>(w.hdr + 2), (unsigned long long)sw);
+  if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = sw;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long b = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    if (b) atomicAdd(reinterpret_cast<unsigned long long *>(w.hdr + GS_CNT0) + (blockIdx.x % GS_NCNT), b);
+  }
 }
 
 // ------------------------------------------------------------ scan (int32)
@@ -456,7 +470,10 @@ __global__ __launch_bounds__(256) void k_gs_cnt_by_rank(int n, const int32_t *__
 // DW_STATUS_RENDER_OVERFLOW and the pair count hdr[1] to 0: nothing is
 // emitted, sorted or drawn.
 __global__ void k_gs_check(int64_t cap, int32_t *hdr) {
-  if (threadIdx.x == 0 && *reinterpret_cast<const unsigned long long *>(hdr + 2) > (unsigned long long)cap) {
+  if (threadIdx.x != 0) return;
+  unsigned long long t = 0;
+  for (int q = 0; q < GS_NCNT; ++q) t += reinterpret_cast<const unsigned long long *>(hdr + GS_CNT0)[q];
+  if (t > (unsigned long long)cap) {
     hdr[0] |= DW_STATUS_RENDER_OVERFLOW;
     hdr[1] = 0;
   }
@@ -468,21 +485,89 @@ __global__ void k_gs_status(const int32_t *hdr, int32_t *out) {
 
 __device__ __forceinline__ bool gs_failed(const int32_t *hdr) { return (hdr[0] & DW_STATUS_RENDER_OVERFLOW) != 0; }
 
+// Pairs in depth order.  Block b writes pairs [b E, (b + 1) E) of the list
+// (E = GS_EMIT): two threads find by binary search the depth ranks that own
+// its first and last pair (off is the exclusive scan of the tile counts in
+// depth order; every drawn kernel owns at least one pair and the kernels
+// that are not drawn sort last, so at most E ranks are involved); their
+// offsets and ids are staged in LDS; thread t fills pairs t*16 .. t*16 + 15
+// into an LDS copy of the block's slice, walking its kernels' tile boxes
+// incrementally from one binary search; the slice is then stored with
+// contiguous writes.  The work per block is fixed whatever the kernels'
+// sizes, so a kernel covering thousands of tiles does not hold up a wave.
+constexpr int GS_EMIT = 4096;
+constexpr int GS_EMIT_PER = GS_EMIT / 256;
+
 __global__ __launch_bounds__(256) void k_gs_emit(int n, CamDev K, const int32_t *__restrict__ id,
                                                  const int32_t *__restrict__ off, const int4 *__restrict__ rect,
                                                  const int32_t *hdr, uint32_t *__restrict__ pk,
                                                  int32_t *__restrict__ pv) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gs_failed(hdr) || r >= n) return;
-  const int g = id[r];
-  const int4 b = rect[g];
-  int64_t o = off[r];
-  for (int ty = b.z; ty <= b.w; ++ty)
-    for (int tx = b.x; tx <= b.y; ++tx) {
-      pk[o] = (uint32_t)(tx + K.tw * ty);
-      pv[o] = g;
-      ++o;
+  __shared__ int s_off[GS_EMIT], s_g[GS_EMIT];
+  __shared__ uint32_t s_pk[GS_EMIT];
+  __shared__ int32_t s_pv[GS_EMIT];
+  __shared__ int s_r[2];
+  if (gs_failed(hdr)) return;  // grid-uniform
+  const int64_t total = hdr[1];
+  const int64_t P0 = (int64_t)blockIdx.x * GS_EMIT;
+  if (P0 >= total) return;  // block-uniform
+  const int m_pairs = (int)min((int64_t)GS_EMIT, total - P0);
+  if (threadIdx.x < 2) {
+    // last rank whose first pair is at or before the target pair
+    const int64_t tgt = threadIdx.x == 0 ? P0 : P0 + m_pairs - 1;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= tgt) lo = mid;
+      else hi = mid - 1;
     }
+    s_r[threadIdx.x] = lo;
+  }
+  __syncthreads();
+  const int r_lo = s_r[0], m_ranks = s_r[1] - s_r[0] + 1;  // <= GS_EMIT
+  for (int k = threadIdx.x; k < m_ranks; k += 256) {
+    s_off[k] = (int)(off[r_lo + k] - P0);
+    s_g[k] = id[r_lo + k];
+  }
+  __syncthreads();
+  const int j0 = threadIdx.x * GS_EMIT_PER;
+  if (j0 < m_pairs) {
+    int lo = 0, hi = m_ranks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= j0) lo = mid;
+      else hi = mid - 1;
+    }
+    int k = lo;
+    int g = s_g[k];
+    int4 b = rect[g];
+    int w = b.y - b.x + 1;
+    const int q0 = j0 - s_off[k];
+    int tx = q0 % w, ty = q0 / w;
+    int rows = b.w - b.z + 1;
+    const int j1 = min(j0 + GS_EMIT_PER, m_pairs);
+    for (int j = j0; j < j1; ++j) {
+      if (ty == rows) {  // next kernel (at least one pair each)
+        ++k;
+        g = s_g[k];
+        b = rect[g];
+        w = b.y - b.x + 1;
+        rows = b.w - b.z + 1;
+        tx = 0;
+        ty = 0;
+      }
+      s_pk[j] = (uint32_t)(b.x + tx + K.tw * (b.z + ty));
+      s_pv[j] = g;
+      if (++tx == w) {
+        tx = 0;
+        ++ty;
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < m_pairs; j += 256) {
+    pk[P0 + j] = s_pk[j];
+    pv[P0 + j] = s_pv[j];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gs_ranges(const uint32_t *__restrict__ pk, const int32_t *__restrict__ hdr,
@@ -573,110 +658,129 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wave whose lanes are all active: four DPP
+// steps give every lane its 16-lane row total (quad_perm [1,0,3,2] and
+// [2,3,0,1], then row rotations by 4 and 8), four lane reads add the rows.
+// The result is wave-uniform.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+  v = dpp_add<0xB1>(v);
+  v = dpp_add<0x4E>(v);
+  v = dpp_add<0x124>(v);
+  v = dpp_add<0x128>(v);
+  const int b = __float_as_int(v);
+  return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) + __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(b, 32)) + __int_as_float(__builtin_amdgcn_readlane(b, 48)));
+}
+
 // per-kernel adjoints in LDS for one batch: centre (2), conic (3), opacity,
 // colour (3)
 constexpr int GS_NB = 9;
 
-__global__ __launch_bounds__(GS_THREADS) void k_gs_raster_adj(
+// One wave per tile, four pixels per lane (lane l: column l % 16, rows
+// 4 (l / 16) .. 4 (l / 16) + 3), so each list entry's per-kernel adjoints
+// are summed over the lane's pixels in registers and then over the wave
+// once (DPP), and lane 0 adds them to global memory.
+constexpr int GS_ADJ_PX = 4;
+
+__global__ __launch_bounds__(64) void k_gs_raster_adj(
     CamDev K, const int32_t *__restrict__ hdr, const int2 *__restrict__ range,
     const int32_t *__restrict__ pv, const float4 *__restrict__ rec, const int32_t *__restrict__ last,
     const float *__restrict__ image, const float *__restrict__ image_bar, int n, float *__restrict__ gbar,
     float *__restrict__ color_bar, float *__restrict__ opacity_bar) {
-  __shared__ GsRec s_r[GS_THREADS];
-  __shared__ int s_g[GS_THREADS];
-  __shared__ float s_acc[GS_THREADS][GS_NB];
+  __shared__ GsRec s_r[64];
+  __shared__ int s_g[64];
   if (gs_failed(hdr)) return;
   const int tile = blockIdx.x;
   const int tx = tile % K.tw, ty = tile / K.tw;
-  const int i = tx * GS_TILE + (threadIdx.x % GS_TILE), j = ty * GS_TILE + (threadIdx.x / GS_TILE);
-  const bool inside = i < K.W && j < K.H;
-  const float x = i + 0.5f, y = j + 0.5f;
+  const int lane = threadIdx.x;
+  const int i = tx * GS_TILE + (lane % GS_TILE);
+  const int jb = ty * GS_TILE + GS_ADJ_PX * (lane / GS_TILE);
   const int2 rg = range[tile];
-  const int64_t pix = i + (int64_t)K.W * j, HW = (int64_t)K.W * K.H;
-  float G[3] = {0.f, 0.f, 0.f}, Ct[3] = {0.f, 0.f, 0.f};
-  int used = 0;
-  if (inside) {
-    used = last[pix];
+  const int64_t HW = (int64_t)K.W * K.H;
+  const float x = i + 0.5f;
+  float G[GS_ADJ_PX][3], Ct[GS_ADJ_PX][3], T[GS_ADJ_PX], Acc[GS_ADJ_PX][3];
+  int used[GS_ADJ_PX];
+  int maxused = 0;
+#pragma unroll
+  for (int k = 0; k < GS_ADJ_PX; ++k) {
+    const int j = jb + k;
+    const bool inside = i < K.W && j < K.H;
+    const int64_t pix = i + (int64_t)K.W * j;
+    used[k] = inside ? last[pix] : 0;
+    T[k] = 1.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      G[c] = image_bar[c * HW + pix];
-      Ct[c] = image[c * HW + pix];
+      G[k][c] = inside ? image_bar[c * HW + pix] : 0.f;
+      Ct[k][c] = inside ? image[c * HW + pix] : 0.f;
+      Acc[k][c] = 0.f;
     }
+    maxused = max(maxused, used[k]);
   }
-  float T = 1.f, Acc[3] = {0.f, 0.f, 0.f};
-  const int lane = threadIdx.x & 63;
-  int maxused = used;
-  {
-    // the tile's furthest pixel bounds the traversal
-    __shared__ int s_max;
-    if (threadIdx.x == 0) s_max = 0;
-    __syncthreads();
-    atomicMax(&s_max, used);
-    __syncthreads();
-    maxused = s_max;
-  }
-  for (int b = 0; b < maxused; b += GS_THREADS) {
-    const int nbatch = min(GS_THREADS, maxused - b);
-    __syncthreads();
-    if ((int)threadIdx.x < nbatch) {
-      const int g = pv[rg.x + b + threadIdx.x];
-      s_g[threadIdx.x] = g;
-      s_r[threadIdx.x] = load_rec(rec, g);
-    }
+  // the tile's furthest pixel bounds the traversal (wave maximum)
 #pragma unroll
-    for (int v = 0; v < GS_NB; ++v) s_acc[threadIdx.x][v] = 0.f;
+  for (int m = 32; m >= 1; m >>= 1) maxused = max(maxused, __shfl_xor(maxused, m, 64));
+  for (int b = 0; b < maxused; b += 64) {
+    const int nbatch = min(64, maxused - b);
+    __syncthreads();
+    if (lane < nbatch) {
+      const int g = pv[rg.x + b + lane];
+      s_g[lane] = g;
+      s_r[lane] = load_rec(rec, g);
+    }
     __syncthreads();
     for (int q = 0; q < nbatch; ++q) {
       const GsRec r = s_r[q];
-      float dx, dy, e;
-      const float al = gs_alpha(r, x, y, dx, dy, e);
-      const bool live = (b + q < used) && al >= K.amin;
+      const float cc[3] = {r.c0, r.c1, r.c2};
       float d[GS_NB];
 #pragma unroll
       for (int v = 0; v < GS_NB; ++v) d[v] = 0.f;
-      if (live) {
-        const float wgt = T * al;
-        const float cc[3] = {r.c0, r.c1, r.c2};
-        float dal = 0.f;
-        const float inv1m = 1.0f / (1.0f - al);
+      bool any = false;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          Acc[c] += wgt * cc[c];
-          d[6 + c] = wgt * G[c];                           // colour
-          dal += G[c] * (T * cc[c] - (Ct[c] - Acc[c]) * inv1m);
-        }
-        T *= 1.0f - al;
-        d[5] = dal * e;                                    // opacity
-        const float dq = -0.5f * al * dal;                 // alpha = o exp(-q/2)
-        d[0] = -2.0f * dq * (r.A * dx + r.B * dy);         // centre x (dq/dmx = -2 (A dx + B dy))
-        d[1] = -2.0f * dq * (r.B * dx + r.C * dy);         // centre y
-        d[2] = dq * dx * dx;                               // conic A
-        d[3] = dq * 2.0f * dx * dy;                        // conic B (q has 2 B dx dy)
-        d[4] = dq * dy * dy;                               // conic C
-      }
-      if (__ballot(live) != 0ull) {
+      for (int k = 0; k < GS_ADJ_PX; ++k) {
+        float dx, dy, e;
+        const float al = gs_alpha(r, x, (float)(jb + k) + 0.5f, dx, dy, e);
+        if ((b + q < used[k]) && al >= K.amin) {
+          any = true;
+          const float wgt = T[k] * al;
+          float dal = 0.f;
+          const float inv1m = 1.0f / (1.0f - al);
 #pragma unroll
-        for (int v = 0; v < GS_NB; ++v) d[v] = wave_sum(d[v]);
-        if (lane == 0) {
-#pragma unroll
-          for (int v = 0; v < GS_NB; ++v) atomicAdd(&s_acc[q][v], d[v]);
+          for (int c = 0; c < 3; ++c) {
+            Acc[k][c] += wgt * cc[c];
+            d[6 + c] += wgt * G[k][c];                                 // colour
+            dal += G[k][c] * (T[k] * cc[c] - (Ct[k][c] - Acc[k][c]) * inv1m);
+          }
+          T[k] *= 1.0f - al;
+          d[5] += dal * e;                                             // opacity
+          const float dq = -0.5f * al * dal;                           // alpha = o exp(-q/2)
+          d[0] += -2.0f * dq * (r.A * dx + r.B * dy);                  // centre x
+          d[1] += -2.0f * dq * (r.B * dx + r.C * dy);                  // centre y
+          d[2] += dq * dx * dx;                                        // conic A
+          d[3] += dq * 2.0f * dx * dy;                                 // conic B (q has 2 B dx dy)
+          d[4] += dq * dy * dy;                                        // conic C
         }
       }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nbatch) {
-      const int g = s_g[threadIdx.x];
-      const float *a = s_acc[threadIdx.x];
-      if (a[0] != 0.f) atomicAdd(&gbar[g], a[0]);
-      if (a[1] != 0.f) atomicAdd(&gbar[(int64_t)n + g], a[1]);
-      if (a[2] != 0.f) atomicAdd(&gbar[2 * (int64_t)n + g], a[2]);
-      if (a[3] != 0.f) atomicAdd(&gbar[3 * (int64_t)n + g], a[3]);
-      if (a[4] != 0.f) atomicAdd(&gbar[4 * (int64_t)n + g], a[4]);
-      if (opacity_bar && a[5] != 0.f) atomicAdd(&opacity_bar[g], a[5]);
-      if (color_bar) {
+      if (__ballot(any) == 0ull) continue;  // wave-uniform
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          if (a[6 + c] != 0.f) atomicAdd(&color_bar[c * (int64_t)n + g], a[6 + c]);
+      for (int v = 0; v < GS_NB; ++v) d[v] = wave_total(d[v]);
+      if (lane == 0) {
+        const int g = s_g[q];
+        if (d[0] != 0.f) atomicAdd(&gbar[g], d[0]);
+        if (d[1] != 0.f) atomicAdd(&gbar[(int64_t)n + g], d[1]);
+        if (d[2] != 0.f) atomicAdd(&gbar[2 * (int64_t)n + g], d[2]);
+        if (d[3] != 0.f) atomicAdd(&gbar[3 * (int64_t)n + g], d[3]);
+        if (d[4] != 0.f) atomicAdd(&gbar[4 * (int64_t)n + g], d[4]);
+        if (opacity_bar && d[5] != 0.f) atomicAdd(&opacity_bar[g], d[5]);
+        if (color_bar) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (d[6 + c] != 0.f) atomicAdd(&color_bar[c * (int64_t)n + g], d[6 + c]);
+        }
       }
     }
   }
@@ -1011,7 +1115,7 @@ extern "C" int gs_render(const dw_camera *cam, int n, const float *mu, const flo
   DW_REQUIRE(image, DW_EINVAL, "gs_render: image is NULL");
   hipStream_t s = (hipStream_t)stream;
   const int64_t T = (int64_t)K.tw * K.th;
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, w.hdr, (int64_t)64, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, w.hdr, (int64_t)GS_HDR_INTS, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_blocks(2 * T, 256 * 4)), dim3(256), 0, s, (int32_t *)w.range, 2 * T, 0);
   if (n > 0) {
     hipLaunchKernelGGL(k_gs_project, dim3(grid_blocks(n, 256)), dim3(256), 0, s, K, n, mu, sigma, color, opacity, w);
@@ -1022,8 +1126,8 @@ extern "C" int gs_render(const dw_camera *cam, int n, const float *mu, const flo
     scan_excl(w.off, w.off, n, nullptr, w.bsum, w.hdr + 1, s);
     hipLaunchKernelGGL(k_gs_check, dim3(1), dim3(64), 0, s, max_pairs, w.hdr);
     if (max_pairs > 0) {
-      hipLaunchKernelGGL(k_gs_emit, dim3(grid_blocks(n, 256)), dim3(256), 0, s, n, K, va, w.off, w.rect, w.hdr, w.pk_a,
-                         w.pv_a);
+      hipLaunchKernelGGL(k_gs_emit, dim3(grid_blocks(max_pairs, GS_EMIT)), dim3(256), 0, s, n, K, va, w.off, w.rect,
+                         w.hdr, w.pk_a, w.pv_a);
       uint32_t *pa = w.pk_a, *pb = w.pk_b;
       int32_t *qa = w.pv_a, *qb = w.pv_b;
       radix_sort(&pa, &qa, &pb, &qb, max_pairs, w.hdr + 1, pair_bits(T), w.hist, w.bsum, s);
@@ -1051,7 +1155,7 @@ extern "C" int gs_render_adj(const dw_camera *cam, int n, const float *mu, const
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_blocks(5 * (int64_t)n, 256 * 8)), dim3(256), 0, s, w.gbar, 5 * (int64_t)n,
                      0.f);
   const int32_t *ids = pairs_in_b(T) ? w.pv_b : w.pv_a;
-  hipLaunchKernelGGL(k_gs_raster_adj, dim3((unsigned)T), dim3(GS_THREADS), 0, s, K, w.hdr, w.range, ids, w.rec,
+  hipLaunchKernelGGL(k_gs_raster_adj, dim3((unsigned)T), dim3(64), 0, s, K, w.hdr, w.range, ids, w.rec,
                      w.last, image, image_bar, n, w.gbar, color_bar, opacity_bar);
   hipLaunchKernelGGL(k_gs_project_adj, dim3(grid_blocks(n, 256)), dim3(256), 0, s, K, n, mu, sigma, opacity, w.gbar,
                      mu_bar, sigma_bar);
