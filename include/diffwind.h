@@ -525,9 +525,11 @@ int lbm_solid_from_particles(const dw_lattice *lat, const float *x, const float 
 
 /* A learned stand-in for k LBM steps (the paper has no learned wind model;
  * the lattice Boltzmann step of Eq. lbe is its fallback and judge):
- *   u_{t+k} = u_t + s * net(u_t / s),
+ *   u_{t+k} = u_t + g s net(u_t / s),
  *   net = conv(32->3) o silu o conv(32->32) o silu o conv(32->32) o silu o conv(3->32),
- * 3x3x3 kernels with zero padding, s the per-field inflow speed.  Fields are
+ * 3x3x3 kernels with zero padding, s the per-field inflow speed, g a fixed
+ * output gain (the binding uses 0.01; conv3d_bf16's output epilogue takes
+ * g s as its per-field scale).  Fields are
  * batches of B lattices of nx * ny * nz voxels (any sizes; multiples of 16 in
  * x and 4 in y, z fill every tile).  Velocities are float [B][3][L] (as lbm_step writes u); activations
  * are BF16 (uint16 storage) channels-last [B][L][C] with C = 8 for

@@ -1,19 +1,20 @@
 // BF16 MFMA 3x3x3 convolutions of the wind surrogate (gfx950), FP32 accumulation.
 //
 // The surrogate advances a wind velocity field k LBM steps at once:
-//   u_{t+k} = u_t + s * net(u_t / s),  net = conv(32->3) o silu o conv(32->32)
+//   u_{t+k} = u_t + g s net(u_t / s),  net = conv(32->3) o silu o conv(32->32)
 //   o silu o conv(32->32) o silu o conv(3->32),  3x3x3 kernels, zero padding,
-// s the per-field inflow speed.  It is judged against the lattice Boltzmann
+// s the per-field inflow speed, g a fixed output gain (the caller's scale of
+// the output layer's residual).  It is judged against the lattice Boltzmann
 // step of Eq. lbe.
 //
 // Implicit GEMM per layer: M = output channels (tiles of 16), N = a row of 16
 // voxels along x, K = (tap, input channel).  Activations are channels-last
 // BF16 [B][nz][ny][nx][C] with C padded to 8 (3-channel fields) or 32.  One
 // v_mfma_f32_16x16x32_bf16 consumes K = 32: one tap of 32 channels, or four
-// taps of 8 (padded) channels.  A workgroup (4 waves) stages a zero-padded
-// input patch of 16 x 4 x 4 output voxels (18 x 6 x 6 input voxels) in LDS;
-// the weight fragments of the whole layer stay in registers for the life of
-// the persistent workgroup.  Lane layout of the 16x16x32 MFMA: lane l holds
+// taps of 8 (padded) channels.  A workgroup (4 waves) stages the zero-padded
+// input patch of a tile of 16 x 4 x 8 output voxels (18 x 6 x 10 input
+// voxels) in LDS; for 32-channel inputs a wave's m-tile weight fragments stay
+// in registers for the life of the persistent workgroup.  Lane layout of the 16x16x32 MFMA: lane l holds
 // A[l % 16][8 (l / 16) .. +8], B[8 (l / 16) .. +8][l % 16] and
 // D[4 (l / 16) .. +4][l % 16].
 #include <hip/hip_runtime.h>

@@ -570,14 +570,16 @@ __global__ __launch_bounds__(256) void k_gs_emit(int n, CamDev K, const int32_t 
   }
 }
 
+// grid-stride over the pairs actually present (the grid is sized for a
+// typical count, not for the capacity)
 __global__ __launch_bounds__(256) void k_gs_ranges(const uint32_t *__restrict__ pk, const int32_t *__restrict__ hdr,
                                                    int2 *__restrict__ range) {
   const int64_t m = hdr[1];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const uint32_t t = pk[i];
-  if (i == 0 || pk[i - 1] != t) range[t].x = (int)i;
-  if (i == m - 1 || pk[i + 1] != t) range[t].y = (int)(i + 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = pk[i];
+    if (i == 0 || pk[i - 1] != t) range[t].x = (int)i;
+    if (i == m - 1 || pk[i + 1] != t) range[t].y = (int)(i + 1);
+  }
 }
 
 // ------------------------------------------------------------- raster
@@ -1131,7 +1133,8 @@ extern "C" int gs_render(const dw_camera *cam, int n, const float *mu, const flo
       uint32_t *pa = w.pk_a, *pb = w.pk_b;
       int32_t *qa = w.pv_a, *qb = w.pv_b;
       radix_sort(&pa, &qa, &pb, &qb, max_pairs, w.hdr + 1, pair_bits(T), w.hist, w.bsum, s);
-      hipLaunchKernelGGL(k_gs_ranges, dim3(grid_blocks(max_pairs, 256)), dim3(256), 0, s, pa, w.hdr, w.range);
+      hipLaunchKernelGGL(k_gs_ranges, dim3(grid_blocks(max_pairs < 8 * (int64_t)n ? max_pairs : 8 * (int64_t)n, 256)),
+                         dim3(256), 0, s, pa, w.hdr, w.range);
     }
   }
   const int32_t *ids = pairs_in_b(T) ? w.pv_b : w.pv_a;
