@@ -126,18 +126,46 @@ def _phase_times(sim, R=10, reps=5):
 
 
 def _phase_bytes(sim, active_nodes):
-    """Algorithmic bytes per launch of each phase (what the step must move).
-    Positions are a reference plus a displacement (24 bytes per particle)."""
+    """Algorithmic bytes per launch of each phase: what the method must move
+    per unit of work (particle-substep 108 B read by P2G + 96 B written by
+    G2P, 56 B per active grid node; LBM node 152 B + 1 B solid + 12 B u).
+    The sort, the voxelisation, the position reference (12 B per particle
+    wherever positions are read) and G2P's re-read of x and F are overheads
+    of this implementation, counted in `_overhead_bytes`, not here."""
     n, L = sim.p.n, sim.L
-    pos = 24 if sim.p.xref is not None else 12
     return {
-        "p2g": (pos + 96) * n + 16 * active_nodes,        # read x (+xref) v C F m V0 region; write m, mv
-        "g2p": (pos + 36 + 96) * n + 12 * active_nodes,   # read x (+xref) F, write x v C F; read grid v
+        "p2g": 108 * n + 16 * active_nodes,               # read x v C F m V0 region; write m, mv
+        "g2p": 96 * n + 12 * active_nodes,                # write x v C F; read grid v
         "lbm": 153 * L + 12 * L,                          # 19 pops in + out, solid, u out
         "grid_update": 29 * active_nodes,                 # read m mv pin, write v
-        "voxelize": pos * n + L,
-        "sort": pos * n,
     }
+
+
+def _overhead_bytes(sim):
+    """Bytes per launch beyond the algorithmic ones that each phase of this
+    implementation necessarily moves (not counted in the rooflines)."""
+    n, L = sim.p.n, sim.L
+    ref = 12 * n if sim.p.xref is not None else 0
+    return {
+        "p2g": ref,                       # position reference
+        "g2p": ref + 12 * n + 36 * n,     # position reference, displacement and F read back
+        "sort": 2 * ref + 12 * n,         # positions read, key and rank written
+        "voxelize": 2 * ref + L,          # positions read, solid flags written
+    }
+
+
+def _substep_rooflines(sim, active_nodes, ph_ms, ms_per_step):
+    """The whole substep against its algorithmic bytes: the MPM part (204 B
+    per particle + 56 B per active node) over the MPM phases' time (sort,
+    P2G, grid update, G2P), and the coupled substep (+ the LBM node update)
+    over the measured time per substep."""
+    n, L = sim.p.n, sim.L
+    mpm_b = 204 * n + 56 * active_nodes
+    mpm_ms = sum(ph_ms[k] for k in ("sort", "p2g", "grid_update", "g2p"))
+    cpl_b = mpm_b + 165 * L
+    f = lambda b, ms: {"algorithmic_bytes": b, "ms": ms, "achieved_GBps": b / (ms * 1e-3) / 1e9,
+                       "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return {"mpm": f(mpm_b, mpm_ms), "coupled": f(cpl_b, ms_per_step)}
 
 
 def _rooflines(ph_ms, bytes_per):
@@ -208,6 +236,7 @@ def _largest_leg(steps=20):
                       "active_nodes": active},
            "ms_per_step": ms, "value": scene.n / (ms * 1e-3), "unit": "particle-substeps/s", "steps": steps,
            "lbm_mlups": sim.L / (ph["lbm"] * 1e-3) / 1e6, "phase_ms": ph, "rooflines": rl,
+           "overhead_bytes": _overhead_bytes(sim), "substep_rooflines": _substep_rooflines(sim, active, ph, ms),
            "status": sim.status(), "setup_s": t_setup}
     del sim
     torch.cuda.empty_cache()
@@ -822,6 +851,8 @@ def main():
                      "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant, a.n, a.res),
                      "algorithmic_bytes": bytes_per.get(dominant)},
         "rooflines": _rooflines(ph_ms, bytes_per),
+        "overhead_bytes": _overhead_bytes(sim),
+        "substep_rooflines": _substep_rooflines(sim, active_nodes, ph_ms, elapsed * 1e3 / a.steps),
     }
     out["lbm_adjoint"] = _lbm_adj_leg(sim)
     out["copy_bandwidth"] = _copy_bandwidth()
