@@ -63,7 +63,7 @@ def _args():
 
 
 TRAFFIC_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
-TRAFFIC_SOURCES = ("csrc/mpm.hip", "csrc/dw_scatter.h", "csrc/dw_internal.h")
+TRAFFIC_SOURCES = ("csrc/mpm.hip", "csrc/dw_scatter.h", "csrc/dw_internal.h", "csrc/dw_kernels.h", "csrc/lbm.hip")
 
 
 def _measured_traffic(phase, n, res):
@@ -850,7 +850,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": _measured_traffic(dominant, a.n, a.res),
                      "algorithmic_bytes": bytes_per.get(dominant)},
-        "rooflines": _rooflines(ph_ms, bytes_per),
+        "rooflines": {k: dict(v, traffic=_measured_traffic(k, a.n, a.res))
+                      for k, v in _rooflines(ph_ms, bytes_per).items()},
         "overhead_bytes": _overhead_bytes(sim),
         "substep_rooflines": _substep_rooflines(sim, active_nodes, ph_ms, elapsed * 1e3 / a.steps),
     }
