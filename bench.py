@@ -352,7 +352,48 @@ def _recon_leg(n, res, frames, sub, iters):
         err = torch.sqrt(((st[0] - targets[-1]) ** 2).sum(dim=0)).max().item()
         out[f"lambda_{lam:g}"] = {"frames": per, "ms_per_iteration": el * 1e3 / (frames * iters),
                                   "final_max_position_error": err}
+    out["photometric"] = _recon_render(rc, sc, state0, F_gt, guide, frames, iters, amp)
     return out
+
+
+def _recon_render(rc, sc, state0, F_gt, guide, frames, iters, amp):
+    """The same reconstruction from rendered images (L_render of Sec. 3.3):
+    the particles as Gaussian kernels (rest covariance of half the particle
+    spacing, a colour per region, opacity 0.8) seen by two 512 x 512 views;
+    the target images rendered from the reference rollout's states; L_render
+    plus L_phys (lambda 1) per frame."""
+    import torch
+    from paper_2603_09668_amd import api, recon, scenes
+    dev = "cuda"
+    n = sc.n
+    f = lambda a: torch.tensor(a, dtype=torch.float32, device=dev).contiguous()
+    s0, col, op = (f(a) for a in scenes.particle_splats(sc))
+    centre = np.array([0.6, 0.5, 0.5])
+    cams = [scenes.look_at_camera(centre + np.array(d), centre, 512, 512, 700.0) for d in
+            ((-0.3, -1.4, 0.3), (0.2, -0.6, -1.3))]
+    cams = [api.make_camera(c["width"], c["height"], c["fx"], c["fy"], c["cx"], c["cy"], R=c["R"].tolist(),
+                            t=c["t"].tolist(), near_plane=c["near"], bg=(1.0, 1.0, 1.0), alpha_min=1.0 / 255.0,
+                            t_min=1e-4) for c in cams]
+    views = [recon.make_view(c, torch.empty(3, 512, 512, device=dev), n, 32 * n) for c in cams]
+    st, targets = state0, []
+    for _ in range(frames):
+        st = rc.advance(st, F_gt)
+        targets.append([recon.render_image(v, rc.xref + st[0], st[3], s0, col, op) for v in views])
+    st = state0
+    per = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(frames):
+        for v, img in zip(views, targets[k]):
+            v.target = img
+        r = rc.frame_render(st, views, s0, col, op, guide, lam=1.0, iters=iters, lr=amp / 40)
+        c, m, cnt = recon.metrics(F_gt, r.W)
+        per.append({"cos_sim": c, "nmse": m, "nodes": cnt, "loss_first": r.loss[0], "loss_last": r.loss[-1]})
+        st = rc.advance(st, r.W)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"views": 2, "image": [512, 512], "lambda": 1.0, "frames": per,
+            "ms_per_iteration": el * 1e3 / (frames * iters)}
 
 
 def _surrogate_leg(n_rollouts, train_steps):

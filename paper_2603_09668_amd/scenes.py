@@ -268,6 +268,26 @@ def _look_at(eye, target):
     return R, -R @ eye
 
 
+def look_at_camera(eye, target, width: int, height: int, focal: float, near: float = 0.05) -> dict:
+    """A camera dict (the GaussianCloud.camera form) at `eye` looking at `target`."""
+    R, t = _look_at(eye, target)
+    return dict(width=width, height=height, fx=focal, fy=focal, cx=width / 2, cy=height / 2, R=R, t=t, near=near)
+
+
+def particle_splats(sc: Scene, seed: int = 0):
+    """Gaussian kernels for the particles of a scene: isotropic rest
+    covariances of half the particle spacing (6, n), a colour per region
+    with a little per-particle variation (3, n), opacity 0.8 (n,)."""
+    rng = np.random.default_rng(seed + 7)
+    n = sc.n
+    s2 = (0.5 * float(sc.vol0.mean()) ** (1.0 / 3.0)) ** 2
+    sigma0 = np.zeros((6, n))
+    sigma0[:3] = s2
+    base = rng.uniform(0.15, 0.95, (3, int(sc.region.max()) + 1))
+    color = np.clip(base[:, sc.region] + rng.normal(0.0, 0.05, (3, n)), 0.0, 1.0)
+    return sigma0, color, np.full(n, 0.8)
+
+
 def random_gaussians(seed: int, n: int, width: int = 40, height: int = 36, depth=(1.5, 3.5), scale=0.05,
                      opacity=(0.2, 0.9), min_depth_gap: float = 1e-5) -> GaussianCloud:
     """n kernels spread over the view of a camera at the origin looking along
