@@ -245,3 +245,54 @@ def test_render_full_size_sampled():
     e = torch.cat(errs).sort().values
     assert e[-1].item() < 1.0 / 255.0, e[-3:]
     assert e[-2].item() < 5e-5, e[-3:]
+
+
+def test_render_forward_and_reverse_replay_in_a_graph():
+    """gs_render, render_loss and gs_render_adj captured in one HIP graph
+    (status read-back off): every replay, with eager work in between, gives
+    the eager image, loss and gradients (the per-kernel sums use atomics, so
+    gradients are compared to 1e-5 of their largest entry, the image and
+    the loss exactly)."""
+    g = scenes.random_gaussians(15, 500, width=48, height=40, opacity=(0.3, 0.9))
+    oc, gc = _cams(g.camera, alpha_min=1.0 / 255.0, t_min=1e-4)
+    gc_dev = _dev(g)
+    n = 500
+    ws = api.RenderWorkspace(n, gc, 500 * 12)
+    rng = np.random.default_rng(9)
+    target = torch.tensor(rng.uniform(0, 1, (3, 40, 48)), dtype=torch.float32, device="cuda")
+    lws = api.render_loss_workspace(3, 40, 48)
+    img = torch.empty(3, 40, 48, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    ibar = torch.zeros_like(img)
+    bars = [torch.zeros(3, n, device="cuda"), torch.zeros(6, n, device="cuda"), torch.zeros(3, n, device="cuda"),
+            torch.zeros(n, device="cuda")]
+
+    def step():
+        loss.zero_()
+        ibar.zero_()
+        for b in bars:
+            b.zero_()
+        api.gs_render(gc, *gc_dev, img, ws, check=False)
+        api.render_loss(img, target, lws, 0.1, loss, ibar)
+        api.gs_render_adj(gc, *gc_dev, img, ibar, ws, *bars)
+
+    step()
+    torch.cuda.synchronize()
+    assert ws.status()[0] == 0
+    ref = [t.clone() for t in (img, loss, *bars)]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        img.fill_(-1.0)
+        for b in bars:
+            b.fill_(123.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref[0]), rep
+        assert torch.equal(loss, ref[1]), rep
+        for got, want in zip(bars, ref[2:]):
+            assert (got - want).abs().max().item() <= 1e-5 * max(want.abs().max().item(), 1e-30), rep
+        step()  # eager work between replays
+        torch.cuda.synchronize()
