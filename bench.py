@@ -519,6 +519,48 @@ def _surrogate_step_timing(net, dims3=(256, 128, 128), warm=800):
                              "unit": "TFLOP/s", "frac": flops / (t_fwd * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}}
 
 
+def _tune_surrogate(net, n, res, warm, pairs=100, steps=300):
+    """A copy of the net fine-tuned on the tunnel of the largest workload
+    built from another seed (other particles, another gust): pairs
+    (u_t, u_t+8) of its LBM flow around the particles at rest, t from
+    `warm` on, `steps` Adam steps at batch 1, lr 2e-4.  Returns the net and
+    the time the data and the training took."""
+    import torch
+    from paper_2603_09668_amd import surrogate as sg
+    from paper_2603_09668_amd.sim import CoupledSim
+    t0 = time.perf_counter()
+    sc = scenes_mod().flag_and_leaves_scene(seed=1, n=n, res=res, lbm_dims=(res, res // 2, res // 2))
+    sim = CoupledSim(sc, wind="lbm")
+    sim.warm_wind(warm)
+    U0 = torch.empty(pairs, 3, sim.L, device="cuda")
+    U1 = torch.empty_like(U0)
+    for i in range(pairs):
+        U0[i].copy_(sim.u)
+        sim.warm_wind(8)
+        U1[i].copy_(sim.u)
+    s = float(np.linalg.norm(sc.lbm["u_in"]))
+    S = torch.full((pairs,), s, device="cuda")
+    dims = (1, res, res // 2, res // 2)
+    del sim
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    tuned = sg.Surrogate(seed=0)
+    tuned.load_state_dict(net.state_dict())
+    t0 = time.perf_counter()
+    sg.train(tuned, U0, U1, S, dims, steps=steps, batch=1, lr=2e-4, seed=2)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del U0, U1
+    torch.cuda.empty_cache()
+    return tuned, {"pairs": pairs, "steps": steps, "data_s": t_data, "train_s": t_train,
+                   "source": "tunnel of the seed-1 scene, LBM from the particles at rest"}
+
+
+def scenes_mod():
+    from paper_2603_09668_amd import scenes
+    return scenes
+
+
 def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
     """The largest workload driven three ways for `substeps` coupled substeps
     from the same developed flow (`warm` LBM steps around the particles at
@@ -530,16 +572,19 @@ def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
     import torch
     from paper_2603_09668_amd.sim import CoupledSim
     scene = _scene(n, res)
+    tuned, tune_info = _tune_surrogate(net, n, res, warm)
+    nets = {"surrogate": net, "surrogate_tuned": tuned}
     res_ = {}
-    for model in ("lbm", "surrogate", "frozen"):
-        sim = CoupledSim(scene, wind=model, surrogate=net if model == "surrogate" else None)
+    for model in ("lbm", "surrogate", "surrogate_tuned", "frozen"):
+        kind = "surrogate" if model.startswith("surrogate") else model
+        sim = CoupledSim(scene, wind=kind, surrogate=nets.get(model))
         sim.warm_wind(warm)
         acc = torch.zeros(1, dtype=torch.int32, device="cuda")
         calls = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(substeps):
-            if model == "surrogate" and sim.t % sim.k == 0:
+            if kind == "surrogate" and sim.t % sim.k == 0:
                 calls += 1
                 sim.step()
                 acc += sim.sw.accept
@@ -550,7 +595,7 @@ def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
         res_[model] = {"ms_per_substep": el * 1e3 / substeps, "status": sim.status(),
                        "u": sim.u.clone(), "solid": sim.solid.clone(),
                        "disp": sim.in_scene_order(sim.p.x).clone()}
-        if model == "surrogate":
+        if kind == "surrogate":
             res_[model]["surrogate_calls"] = calls
             res_[model]["accepted_calls"] = int(acc.item())
         del sim
@@ -561,8 +606,9 @@ def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
     dn = torch.linalg.vector_norm(ref["disp"]).item()
     out = {"config": {"workload": f"coupled substep, {n} particles, {res}^3 grid, {res}x{res // 2}x{res // 2} "
                                   f"lattice, {substeps} substeps from {warm} LBM warm-up steps",
-                      "substeps": substeps, "warm_lbm_steps": warm}}
-    for model in ("lbm", "surrogate", "frozen"):
+                      "substeps": substeps, "warm_lbm_steps": warm},
+           "tuning": tune_info}
+    for model in ("lbm", "surrogate", "surrogate_tuned", "frozen"):
         r = res_[model]
         e = {"ms_per_substep": r["ms_per_substep"], "status": r["status"]}
         if model != "lbm":
