@@ -600,6 +600,25 @@ def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
             res_[model]["accepted_calls"] = int(acc.item())
         del sim
         torch.cuda.empty_cache()
+    # one surrogate application on this tunnel (t = warm .. warm + 8) against
+    # the 8 LBM steps it replaces, for both nets, and persistence
+    from paper_2603_09668_amd import surrogate as sg
+    sim = CoupledSim(scene, wind="lbm")
+    sim.warm_wind(warm)
+    u0 = sim.u.clone().view(1, 3, -1)
+    sim.warm_wind(8)
+    u8 = sim.u.clone().view(1, 3, -1)
+    sol = sim.solid.view(1, -1)
+    lat = sim.lat
+    scale = torch.tensor([float(np.linalg.norm(scene.lbm["u_in"]))], device="cuda")
+    dims = (1, lat.nx, lat.ny, lat.nz)
+    one_step = {"persistence": sg.rel_error(u0, u8, sol).item()}
+    for name, nt in nets.items():
+        out = torch.empty_like(u0)
+        nt.forward(u0, scale, out, dims)
+        one_step[name] = sg.rel_error(out, u8, sol).item()
+    del sim
+    torch.cuda.empty_cache()
     ref = res_["lbm"]
     fluid = (ref["solid"] == 0).float()[None]
     un = torch.sqrt(((ref["u"] ** 2) * fluid).sum()).item()
@@ -607,7 +626,7 @@ def _surrogate_coupled_leg(net, n=4_000_000, res=256, substeps=500, warm=300):
     out = {"config": {"workload": f"coupled substep, {n} particles, {res}^3 grid, {res}x{res // 2}x{res // 2} "
                                   f"lattice, {substeps} substeps from {warm} LBM warm-up steps",
                       "substeps": substeps, "warm_lbm_steps": warm},
-           "tuning": tune_info}
+           "tuning": tune_info, "one_step_wind_error": one_step}
     for model in ("lbm", "surrogate", "surrogate_tuned", "frozen"):
         r = res_[model]
         e = {"ms_per_substep": r["ms_per_substep"], "status": r["status"]}
