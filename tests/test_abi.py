@@ -45,7 +45,8 @@ int main(void) {
   P(dw_grid) P(dw_lattice) P(dw_mpm_params) P(dw_particles) P(dw_particles_bar) P(dw_wind) P(dw_lbm_params)
   O(dw_wind, W) O(dw_wind, lat) O(dw_wind, u) O(dw_wind, acc) O(dw_particles, n_regions) O(dw_lbm_params, t)
   O(dw_lbm_params, bc) O(dw_mpm_params, deterministic) O(dw_particles, xref) O(dw_lbm_params, skip)
-  O(dw_wind, deterministic)
+  O(dw_wind, deterministic) P(dw_camera) O(dw_camera, R) O(dw_camera, near_plane) O(dw_camera, alpha_min)
+  O(dw_camera, t_min)
   return 0;
 }
 """
@@ -58,7 +59,7 @@ int main(void) {
     got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     mirror = {"dw_grid": api.Grid, "dw_lattice": api.Lattice, "dw_mpm_params": api.MPMParams,
               "dw_particles": api.Particles, "dw_particles_bar": api.ParticlesBar, "dw_wind": api.Wind,
-              "dw_lbm_params": api.LBMParams}
+              "dw_lbm_params": api.LBMParams, "dw_camera": api.Camera}
     for name, cls in mirror.items():
         assert int(got[name]) == ctypes.sizeof(cls), name
     assert int(got["dw_wind.W"]) == api.Wind.W.offset
@@ -72,6 +73,34 @@ int main(void) {
     assert int(got["dw_lbm_params.t"]) == api.LBMParams.t.offset
     assert int(got["dw_lbm_params.bc"]) == api.LBMParams.bc.offset
     assert int(got["dw_mpm_params.deterministic"]) == api.MPMParams.deterministic.offset
+    for f in ("R", "near_plane", "alpha_min", "t_min"):
+        assert int(got["dw_camera." + f]) == getattr(api.Camera, f).offset, f
+
+
+def test_render_argument_errors_are_codes():
+    """Camera, capacity and workspace checks of the renderer and the loss
+    happen on the host before any launch (fake pointers, never read)."""
+    L = api.lib()
+    cam = api.make_camera(64, 48, 50.0, 50.0, 32.0, 24.0)
+    nb = L.gs_render_workspace_bytes(100, ctypes.byref(cam), 1000)
+    assert nb > 0 and L.gs_render_workspace_bytes(100, ctypes.byref(cam), 4000) > nb
+    P = ctypes.c_void_p
+    args = lambda c, n, pairs, ws_bytes: (ctypes.byref(c), n, P(256), P(512), P(768), P(1024), P(1280), pairs,
+                                          P(4096), ws_bytes, None)
+    assert L.gs_render(*args(cam, 100, 1000, nb - 1)) == -4
+    assert "workspace too small" in api.dw_last_error()
+    assert L.gs_render(*args(cam, -1, 1000, nb)) == -1
+    bad = api.make_camera(0, 48, 50.0, 50.0, 32.0, 24.0)
+    assert L.gs_render(*args(bad, 100, 1000, nb)) == -2
+    bad = api.make_camera(64, 48, 50.0, 50.0, 32.0, 24.0, alpha_min=1.0)
+    assert L.gs_render(*args(bad, 100, 1000, nb)) == -1 and "alpha_min" in api.dw_last_error()
+    bad = api.make_camera(64, 48, 50.0, 50.0, 32.0, 24.0, t_min=-0.1)
+    assert L.gs_render(*args(bad, 100, 1000, nb)) == -1
+    assert L.gs_render(*args(cam, 100, 1 << 31, nb)) == -2
+    lb = L.render_loss_workspace_bytes(3, 48, 64)
+    assert lb > 0 and L.render_loss_workspace_bytes(0, 48, 64) == 0
+    assert L.render_loss(3, 48, 64, P(256), P(512), ctypes.c_float(0.1), None, None, P(1024), lb - 1, None) == -4
+    assert L.render_loss(3, 48, 64, P(256), P(512), ctypes.c_float(1.5), None, None, P(1024), lb, None) == -1
 
 
 def test_workspace_size_is_host_only_and_grows_with_n():
