@@ -184,7 +184,11 @@ typedef struct {
   /* Optional device flag read by lbm_step and lbm_equilibrium: if skip is not
    * NULL and *skip != 0 the call does nothing (no output, no step counter).
    * Lets a captured HIP graph hold a branch that a device-side decision
-   * switches off, e.g. the LBM fallback of an accepted surrogate step. */
+   * switches off, e.g. the LBM fallback of an accepted surrogate step.  With
+   * a switch the calls launch a bounded grid that strides over the lattice,
+   * so a switched-off call costs a few thousand workgroups that return at
+   * once; the results of a switched-on call are the same bits as without
+   * the switch. */
   const int32_t *skip;
 } dw_lbm_params;
 

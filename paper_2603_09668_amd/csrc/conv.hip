@@ -598,40 +598,58 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 // central-difference divergence over interior fluid nodes, their count, and
 // the kinetic energy 1/2 sum |u|^2 over fluid nodes.  out [B][3] is added to
 // (the caller zeroes it).  solid [B][L] (nullable): one mask per field.
+// Per field: sums of the squared central-difference divergence over
+// interior fluid nodes, their count, and the kinetic energy over fluid
+// nodes.  Workgroups stride over the (y, z) rows of the field and the
+// threads over x, so node coordinates need no 64-bit divisions; block sums
+// are added to out [B][3] with one atomic per value.
 __global__ __launch_bounds__(256) void k_field_stats(ConvGeom G, const float *__restrict__ u,
                                                      const uint8_t *__restrict__ solid, float *__restrict__ out) {
-  __shared__ float r0[256], r1[256], r2[256];
-  int b = blockIdx.y;
+  __shared__ float r0[256 / 64], r1[256 / 64], r2[256 / 64];
+  const int b = blockIdx.y;
   float dsum = 0.f, dcnt = 0.f, ke = 0.f;
   const float *ux = u + (int64_t)b * 3 * G.L, *uy = ux + G.L, *uz = uy + G.L;
   const uint8_t *sb = solid ? solid + (int64_t)b * G.L : nullptr;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < G.L; v += (int64_t)gridDim.x * blockDim.x) {
-    if (sb && sb[v]) continue;
-    ke += 0.5f * (ux[v] * ux[v] + uy[v] * uy[v] + uz[v] * uz[v]);
-    int i = (int)(v % G.nx), j = (int)((v / G.nx) % G.ny), k = (int)(v / ((int64_t)G.nx * G.ny));
-    if (i > 0 && j > 0 && k > 0 && i < G.nx - 1 && j < G.ny - 1 && k < G.nz - 1) {
-      int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
-      float d = 0.5f * (ux[v + 1] - ux[v - 1] + uy[v + sy] - uy[v - sy] + uz[v + sz] - uz[v - sz]);
-      dsum += d * d;
-      dcnt += 1.f;
+  const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
+  const int rows = G.ny * G.nz;
+  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int j = r % G.ny, k = r / G.ny;
+    const bool inner_row = j > 0 && k > 0 && j < G.ny - 1 && k < G.nz - 1;
+    const int64_t row0 = (int64_t)r * G.nx;
+    for (int i = threadIdx.x; i < G.nx; i += blockDim.x) {
+      const int64_t v = row0 + i;
+      if (sb && sb[v]) continue;
+      ke += 0.5f * (ux[v] * ux[v] + uy[v] * uy[v] + uz[v] * uz[v]);
+      if (inner_row && i > 0 && i < G.nx - 1) {
+        const float d = 0.5f * (ux[v + 1] - ux[v - 1] + uy[v + sy] - uy[v - sy] + uz[v + sz] - uz[v - sz]);
+        dsum += d * d;
+        dcnt += 1.f;
+      }
     }
   }
-  r0[threadIdx.x] = dsum;
-  r1[threadIdx.x] = dcnt;
-  r2[threadIdx.x] = ke;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dsum += __shfl_xor(dsum, o, 64);
+    dcnt += __shfl_xor(dcnt, o, 64);
+    ke += __shfl_xor(ke, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    r0[threadIdx.x >> 6] = dsum;
+    r1[threadIdx.x >> 6] = dcnt;
+    r2[threadIdx.x >> 6] = ke;
+  }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      r0[threadIdx.x] += r0[threadIdx.x + o];
-      r1[threadIdx.x] += r1[threadIdx.x + o];
-      r2[threadIdx.x] += r2[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    atomicAdd(&out[b * 3 + 0], r0[0]);
-    atomicAdd(&out[b * 3 + 1], r1[0]);
-    atomicAdd(&out[b * 3 + 2], r2[0]);
+    float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+#pragma unroll
+    for (int w = 0; w < 256 / 64; ++w) {
+      t0 += r0[w];
+      t1 += r1[w];
+      t2 += r2[w];
+    }
+    atomicAdd(&out[b * 3 + 0], t0);
+    atomicAdd(&out[b * 3 + 1], t1);
+    atomicAdd(&out[b * 3 + 2], t2);
   }
 }
 
@@ -839,8 +857,9 @@ extern "C" int field_stats(int B, int nx, int ny, int nz, const float *u, const 
   G.ny = ny;
   G.nz = nz;
   G.L = (int64_t)nx * ny * nz;
-  unsigned bx = grid_blocks(G.L, 256);
-  if (bx > 256) bx = 256;
+  DW_REQUIRE((int64_t)ny * nz < (1LL << 31), DW_ERANGE, "field_stats: too many rows");
+  const int rows = ny * nz;
+  const unsigned bx = (unsigned)(rows < 2048 ? rows : 2048);
   hipLaunchKernelGGL(k_field_stats, dim3(bx, B), dim3(256), 0, (hipStream_t)stream, G, u, solid, out);
   return check_launch("field_stats");
 }

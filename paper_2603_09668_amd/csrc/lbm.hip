@@ -323,29 +323,15 @@ __device__ __forceinline__ void st_out(float *__restrict__ plane, uint32_t node,
   else *a = v;
 }
 
-// BIG: a lattice larger than the last-level cache (lbm_streams): a 3-D grid
-// of row blocks and nontemporal output stores; otherwise rows are handed to
-// the XCDs in contiguous runs (xcd_row_block) and the output stays cached.
+// One row block of the step: LBM_BLOCK nodes along x from x0 in row (j, k).
+// BIG: a lattice larger than the last-level cache (lbm_streams): the output
+// is stored with nontemporal stores.  Lanes past the lattice's x end return
+// after the block's staging barrier.
 template <bool SOLID, bool BIG>
-__global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *__restrict__ fin,
-                                                        float *__restrict__ fout, const uint8_t *__restrict__ solid,
-                                                        float *__restrict__ rho_out, float *__restrict__ u_out) {
-  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
-  __shared__ int s_any[LBM_BLOCK / 64];
-  __shared__ float s_inl[5];
-  if (P.skip && *P.skip) return;  // block-uniform: a switched-off graph branch
-  int x0, j, k;
-  if (BIG) {
-    x0 = blockIdx.x * LBM_BLOCK;
-    j = blockIdx.y;
-    k = blockIdx.z;
-  } else {
-    const RowBlock rb = xcd_row_block(P);
-    if (!rb.live) return;  // block-uniform
-    x0 = rb.x0;
-    j = rb.j;
-    k = rb.k;
-  }
+__device__ __forceinline__ void lbm_row_block(const LbmDev &P, const float *__restrict__ fin,
+                                              float *__restrict__ fout, const uint8_t *__restrict__ solid,
+                                              float *__restrict__ rho_out, float *__restrict__ u_out, int x0, int j,
+                                              int k, uint8_t (*s_sol)[SOL_W], int *s_any, float *s_inl) {
   const int i = x0 + threadIdx.x;
   if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
   const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
@@ -403,6 +389,56 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *_
     st_out<BIG>(u_out, node, solid_node ? 0.f : ux);
     st_out<BIG>(u_out + P.L, node, solid_node ? 0.f : uy);
     st_out<BIG>(u_out + 2 * P.L, node, solid_node ? 0.f : uz);
+  }
+}
+
+// One workgroup per row block.  Large lattices (BIG): a 3-D grid of row
+// blocks; otherwise rows are handed to the XCDs in contiguous runs
+// (xcd_row_block) and the output stays cached.
+template <bool SOLID, bool BIG>
+__global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *__restrict__ fin,
+                                                        float *__restrict__ fout, const uint8_t *__restrict__ solid,
+                                                        float *__restrict__ rho_out, float *__restrict__ u_out) {
+  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  __shared__ int s_any[LBM_BLOCK / 64];
+  __shared__ float s_inl[5];
+  int x0, j, k;
+  if (BIG) {
+    x0 = blockIdx.x * LBM_BLOCK;
+    j = blockIdx.y;
+    k = blockIdx.z;
+  } else {
+    const RowBlock rb = xcd_row_block(P);
+    if (!rb.live) return;  // block-uniform
+    x0 = rb.x0;
+    j = rb.j;
+    k = rb.k;
+  }
+  lbm_row_block<SOLID, BIG>(P, fin, fout, solid, rho_out, u_out, x0, j, k, s_sol, s_any, s_inl);
+}
+
+// The step behind a device switch (dw_lbm_params.skip, e.g. a fallback
+// branch of a captured graph): a bounded grid whose workgroups stride over
+// the row blocks, so a switched-off step costs a few thousand workgroups
+// that return at once instead of one per row block.
+constexpr unsigned LBM_GATED_BLOCKS = 2048;
+
+template <bool SOLID, bool BIG>
+__global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step_gated(LbmDev P, const float *__restrict__ fin,
+                                                              float *__restrict__ fout,
+                                                              const uint8_t *__restrict__ solid,
+                                                              float *__restrict__ rho_out, float *__restrict__ u_out) {
+  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
+  __shared__ int s_any[LBM_BLOCK / 64];
+  __shared__ float s_inl[5];
+  if (*P.skip) return;  // grid-uniform
+  const int nbx = (P.nx + LBM_BLOCK - 1) / LBM_BLOCK;
+  const int64_t nblocks = (int64_t)nbx * P.ny * P.nz;
+  for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const int64_t row = b / nbx;
+    lbm_row_block<SOLID, BIG>(P, fin, fout, solid, rho_out, u_out, (int)(b % nbx) * LBM_BLOCK, (int)(row % P.ny),
+                              (int)(row / P.ny), s_sol, s_any, s_inl);
+    __syncthreads();  // the next row block restages the shared rows
   }
 }
 
@@ -1010,19 +1046,22 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_adj_pull(LbmDev P, const floa
 
 __global__ __launch_bounds__(256) void k_lbm_equilibrium(LbmDev P, const float *__restrict__ rho_in,
                                                          const float *__restrict__ u_in, float *__restrict__ f) {
-  if (P.skip && *P.skip) return;
-  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= P.L) return;
-  float rho = rho_in ? rho_in[node] : 1.f;
-  float ux = u_in ? u_in[node] : P.uin[0];
-  float uy = u_in ? u_in[P.L + node] : P.uin[1];
-  float uz = u_in ? u_in[2 * P.L + node] : P.uin[2];
-  float uu = ux * ux + uy * uy + uz * uz;
-  float drho = rho - 1.f;
+  if (P.skip && *P.skip) return;  // grid-uniform
+  // grid-stride over the nodes (the grid is bounded, so a switched-off call
+  // returns from a few thousand workgroups)
+  for (int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; node < P.L;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    float rho = rho_in ? rho_in[node] : 1.f;
+    float ux = u_in ? u_in[node] : P.uin[0];
+    float uy = u_in ? u_in[P.L + node] : P.uin[1];
+    float uz = u_in ? u_in[2 * P.L + node] : P.uin[2];
+    float uu = ux * ux + uy * uy + uz * uz;
+    float drho = rho - 1.f;
 #pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
-    f[(int64_t)q * P.L + node] = LW[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+    for (int q = 0; q < 19; ++q) {
+      float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+      f[(int64_t)q * P.L + node] = LW[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+    }
   }
 }
 
@@ -1119,7 +1158,23 @@ extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, cons
   DW_REQUIRE(f_in && f_out, DW_EINVAL, "lbm_step: f_in / f_out is NULL");
   DW_REQUIRE(f_in != f_out, DW_EINVAL, "lbm_step: f_in and f_out must not alias");
   hipStream_t s = (hipStream_t)stream;
-  if (lbm_streams(P)) {
+  if (P.skip) {
+    const int64_t nblocks = (int64_t)((P.nx + LBM_BLOCK - 1) / LBM_BLOCK) * P.ny * P.nz;
+    const dim3 grid((unsigned)(nblocks < (int64_t)LBM_GATED_BLOCKS ? nblocks : LBM_GATED_BLOCKS));
+    const bool big = lbm_streams(P);
+    if (solid && big)
+      hipLaunchKernelGGL((k_lbm_step_gated<true, true>), grid, dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid, rho_out,
+                         u_out);
+    else if (solid)
+      hipLaunchKernelGGL((k_lbm_step_gated<true, false>), grid, dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid, rho_out,
+                         u_out);
+    else if (big)
+      hipLaunchKernelGGL((k_lbm_step_gated<false, true>), grid, dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid,
+                         rho_out, u_out);
+    else
+      hipLaunchKernelGGL((k_lbm_step_gated<false, false>), grid, dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid,
+                         rho_out, u_out);
+  } else if (lbm_streams(P)) {
     if (solid)
       hipLaunchKernelGGL((k_lbm_step<true, true>), lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid, rho_out,
                          u_out);
@@ -1226,7 +1281,8 @@ extern "C" int lbm_equilibrium(const dw_lattice *lat, const dw_lbm_params *param
   int rc = make_lbm(lat, &prm, &P);
   if (rc) return rc;
   DW_REQUIRE(f, DW_EINVAL, "lbm_equilibrium: f is NULL");
-  hipLaunchKernelGGL(k_lbm_equilibrium, dim3(grid_blocks(P.L, 256)), dim3(256), 0, (hipStream_t)stream, P, rho,
+  const unsigned eg = grid_blocks(P.L, 256);
+  hipLaunchKernelGGL(k_lbm_equilibrium, dim3(eg < 4096u ? eg : 4096u), dim3(256), 0, (hipStream_t)stream, P, rho,
                      u, f);
   return check_launch("lbm_equilibrium");
 }

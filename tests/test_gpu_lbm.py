@@ -179,3 +179,43 @@ def test_voxelize_bit_exact():
     expect = ref.reshape(-1).clone()
     expect[:10] = True
     assert torch.equal(extra.cpu().bool(), expect)
+
+
+@pytest.mark.parametrize("dims", [(24, 20, 16), (200, 7, 6), (256, 96, 80)])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_switched_step_equals_plain_step(dims, periodic):
+    """lbm_step and lbm_equilibrium behind a device switch (the bounded-grid
+    form a captured fallback branch uses): with the switch off (0) the step
+    is bit-identical to the plain call, with solids, the inlet/outlet or
+    periodic faces, and on a lattice past the last-level cache (256 x 96 x
+    80 takes the nontemporal-store form); with the switch on (1) nothing is
+    written."""
+    say(f"switched step dims={dims} periodic={periodic}")
+    nx, ny, nz = dims
+    L = nx * ny * nz
+    lat = api.make_lattice(nx, ny, nz)
+    bc = (api.BC_PERIODIC,) * 6 if periodic else (api.BC_INLET, api.BC_OUTLET) + (api.BC_BOUNCEBACK,) * 4
+    kw = dict(tau=0.6, u_in=(0.05, 0.0, 0.0), bc=bc, gust_amp=0.05, gust_period=150.0, gust_ky=1.0, gust_kz=0.0,
+              gust_phase=0.2, t=7)
+    rng = np.random.default_rng(L % 1000)
+    solid = torch.tensor(rng.random(L) < 0.03, dtype=torch.uint8, device=DEV)
+    u0 = torch.tensor(0.05 * (1 + 0.1 * rng.standard_normal((3, L))), dtype=torch.float32, device=DEV)
+    f = torch.empty(19, L, device=DEV)
+    api.lbm_equilibrium(lat, api.make_lbm_params(**kw), f, u=u0)
+    plain_out, plain_u = torch.empty_like(f), torch.empty(3, L, device=DEV)
+    api.lbm_step(lat, api.make_lbm_params(**kw), f, plain_out, solid, None, plain_u)
+    off = torch.zeros(1, dtype=torch.int32, device=DEV)
+    on = torch.ones(1, dtype=torch.int32, device=DEV)
+    g = torch.empty_like(f)
+    api.lbm_equilibrium(lat, api.make_lbm_params(**kw, skip=off), g, u=u0)
+    assert torch.equal(g, f)
+    out, uo = torch.full_like(f, 7.0), torch.full((3, L), 7.0, device=DEV)
+    api.lbm_step(lat, api.make_lbm_params(**kw, skip=off), g, out, solid, None, uo)
+    torch.cuda.synchronize()
+    assert torch.equal(out, plain_out) and torch.equal(uo, plain_u)
+    out.fill_(7.0)
+    uo.fill_(7.0)
+    api.lbm_step(lat, api.make_lbm_params(**kw, skip=on), g, out, solid, None, uo)
+    api.lbm_equilibrium(lat, api.make_lbm_params(**kw, skip=on), out, u=u0)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all()) and bool((uo == 7.0).all())
