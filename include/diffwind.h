@@ -592,12 +592,17 @@ int conv_mse_grad(int B, int nx, int ny, int nz, const float *u_out, const float
 int adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
               int step, void *stream);
 
-/* Checks of velocity fields u [B][3][L]: out[b][0..2] += (sum of squared
+/* Checks of velocity fields u [B][3][L]: out[b][0..2] = (sum of squared
  * central-difference divergence over interior fluid nodes, number of such
  * nodes, kinetic energy 1/2 sum |u|^2 over fluid nodes); solid [B][L] (one
- * mask per field, nonzero = solid) or NULL.  out is added to (zero it first);
- * the order of the float additions is not fixed. */
-int field_stats(int B, int nx, int ny, int nz, const float *u, const uint8_t *solid, float *out, void *stream);
+ * mask per field, nonzero = solid) or NULL.  out [B][3] is overwritten.
+ * ws (device, ws_bytes >= field_stats_workspace_bytes, else DW_EWORKSPACE)
+ * receives per-workgroup partial sums, which a second kernel adds in a
+ * fixed order in double: the result is the same on every call.  Rows
+ * ny * nz must be below 2^31 (DW_ERANGE). */
+size_t field_stats_workspace_bytes(int B, int nx, int ny, int nz);
+int field_stats(int B, int nx, int ny, int nz, const float *u, const uint8_t *solid, float *out, void *ws,
+                size_t ws_bytes, void *stream);
 
 /* Device-side acceptance of surrogate predictions (no host
  * synchronisation, capturable in a HIP graph).  stats_prev and stats_pred

@@ -36,7 +36,7 @@ SYMBOLS = [
     "render_loss",
     "phys_loss", "position_loss", "direction_metrics", "wind_guide",
     "conv_packed_weight_elems", "conv_pack_weights", "conv_prep_input", "conv3d_bf16", "conv_wgrad_scratch_floats",
-    "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats", "field_accept", "field_select",
+    "conv3d_bf16_wgrad", "conv_mse_grad", "adam_step", "field_stats_workspace_bytes", "field_stats", "field_accept", "field_select",
 ]
 CONV_HIDDEN, CONV_OUTPUT, CONV_DGRAD = 0, 1, 2
 
@@ -142,7 +142,8 @@ def lib():
         "conv3d_bf16_wgrad": ([c_int, c_int, c_int, c_int, c_int, c_int, P, P, P, P, c_int, P, P], c_int),
         "conv_mse_grad": ([c_int, c_int, c_int, c_int, P, P, P, P, P, P], c_int),
         "adam_step": ([P, P, P, P, ctypes.c_int64, c_float, c_float, c_float, c_float, c_int, P], c_int),
-        "field_stats": ([c_int, c_int, c_int, c_int, P, P, P, P], c_int),
+        "field_stats_workspace_bytes": ([c_int, c_int, c_int, c_int], c_size_t),
+        "field_stats": ([c_int, c_int, c_int, c_int, P, P, P, P, c_size_t, P], c_int),
         "field_accept": ([c_int, P, P, c_float, c_float, c_float, P, P, P], c_int),
         "field_select": ([c_int, c_int, c_int, c_int, P, P, P, P, P, P], c_int),
     }
@@ -752,10 +753,24 @@ def adam_step(p, g, m, v, lr, b1, b2, eps, step):
                            float(lr), float(b1), float(b2), float(eps), int(step), _stream()), "adam_step")
 
 
-def field_stats(dims, u, solid, out):
+def field_stats_workspace(dims, device="cuda") -> torch.Tensor:
+    """Device workspace of field_stats for fields of these dims (B, nx, ny, nz)."""
+    nbytes = lib().field_stats_workspace_bytes(*map(int, dims))
+    if nbytes == 0:
+        raise DiffWindError("field_stats_workspace_bytes: invalid sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def field_stats(dims, u, solid, out, ws=None):
+    """out (B, 3) = the divergence and energy sums of the fields u (see the
+    header); ws from field_stats_workspace (allocated here when None)."""
     B, nx, ny, nz = dims
+    _shape(out, (B, 3), "out")
+    if ws is None:
+        ws = field_stats_workspace(dims, u.device)
     _check(lib().field_stats(B, nx, ny, nz, _ptr(u, name="u"), _ptr(solid, torch.uint8, "solid"),
-                             _ptr(out, name="out"), _stream()), "field_stats")
+                             _ptr(out, name="out"), _ptr(ws, torch.uint8, "ws"), ws.numel(), _stream()),
+           "field_stats")
 
 
 def field_accept(stats_prev, stats_pred, accept, reject=None, div_factor=2.0, ke_band=(0.9, 1.1)):

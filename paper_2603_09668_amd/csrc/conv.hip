@@ -594,17 +594,27 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// Per-field checks of a velocity field u [B][3][L]: sum of squared
-// central-difference divergence over interior fluid nodes, their count, and
-// the kinetic energy 1/2 sum |u|^2 over fluid nodes.  out [B][3] is added to
-// (the caller zeroes it).  solid [B][L] (nullable): one mask per field.
-// Per field: sums of the squared central-difference divergence over
-// interior fluid nodes, their count, and the kinetic energy over fluid
-// nodes.  Workgroups stride over the (y, z) rows of the field and the
-// threads over x, so node coordinates need no 64-bit divisions; block sums
-// are added to out [B][3] with one atomic per value.
+// Per-field checks of a velocity field u [B][3][L] (solid [B][L] nullable,
+// one mask per field): the sum of the squared central-difference divergence
+// over interior fluid nodes, their count, and the kinetic energy 1/2 |u|^2
+// summed over fluid nodes.  Pass 1: a workgroup takes rpi = 256 / nx rows
+// of x per iteration (one row when nx >= 256), strides over the (y, z) rows
+// of its field, and writes its three sums to part [B][nblk][3]; no node
+// coordinate needs a 64-bit division and no two workgroups add to one
+// address.  Pass 2 (k_field_stats_reduce) sums a field's partials in a
+// fixed order in double, so the result does not depend on scheduling.
+constexpr int FS_MAX_BLOCKS = 2048;
+
+__host__ __device__ inline int fs_lanes_per_row(int nx) { return nx >= 256 ? 256 : nx; }
+
+inline int fs_blocks(int nx, int ny, int nz) {
+  const int64_t rpi = 256 / fs_lanes_per_row(nx);
+  const int64_t need = ((int64_t)ny * nz + rpi - 1) / rpi;
+  return (int)(need < FS_MAX_BLOCKS ? need : FS_MAX_BLOCKS);
+}
+
 __global__ __launch_bounds__(256) void k_field_stats(ConvGeom G, const float *__restrict__ u,
-                                                     const uint8_t *__restrict__ solid, float *__restrict__ out) {
+                                                     const uint8_t *__restrict__ solid, float *__restrict__ part) {
   __shared__ float r0[256 / 64], r1[256 / 64], r2[256 / 64];
   const int b = blockIdx.y;
   float dsum = 0.f, dcnt = 0.f, ke = 0.f;
@@ -612,18 +622,22 @@ __global__ __launch_bounds__(256) void k_field_stats(ConvGeom G, const float *__
   const uint8_t *sb = solid ? solid + (int64_t)b * G.L : nullptr;
   const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
   const int rows = G.ny * G.nz;
-  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
-    const int j = r % G.ny, k = r / G.ny;
-    const bool inner_row = j > 0 && k > 0 && j < G.ny - 1 && k < G.nz - 1;
-    const int64_t row0 = (int64_t)r * G.nx;
-    for (int i = threadIdx.x; i < G.nx; i += blockDim.x) {
-      const int64_t v = row0 + i;
-      if (sb && sb[v]) continue;
-      ke += 0.5f * (ux[v] * ux[v] + uy[v] * uy[v] + uz[v] * uz[v]);
-      if (inner_row && i > 0 && i < G.nx - 1) {
-        const float d = 0.5f * (ux[v + 1] - ux[v - 1] + uy[v + sy] - uy[v - sy] + uz[v + sz] - uz[v - sz]);
-        dsum += d * d;
-        dcnt += 1.f;
+  const int lpr = fs_lanes_per_row(G.nx), rpi = 256 / lpr;
+  const int sub = threadIdx.x / lpr, i0 = threadIdx.x - sub * lpr;
+  if (sub < rpi) {
+    for (int r = blockIdx.x * rpi + sub; r < rows; r += gridDim.x * rpi) {
+      const int j = r % G.ny, k = r / G.ny;
+      const bool inner_row = j > 0 && k > 0 && j < G.ny - 1 && k < G.nz - 1;
+      const int64_t row0 = (int64_t)r * G.nx;
+      for (int i = i0; i < G.nx; i += lpr) {
+        const int64_t v = row0 + i;
+        if (sb && sb[v]) continue;
+        ke += 0.5f * (ux[v] * ux[v] + uy[v] * uy[v] + uz[v] * uz[v]);
+        if (inner_row && i > 0 && i < G.nx - 1) {
+          const float d = 0.5f * (ux[v + 1] - ux[v - 1] + uy[v + sy] - uy[v - sy] + uz[v + sz] - uz[v - sz]);
+          dsum += d * d;
+          dcnt += 1.f;
+        }
       }
     }
   }
@@ -639,18 +653,41 @@ __global__ __launch_bounds__(256) void k_field_stats(ConvGeom G, const float *__
     r2[threadIdx.x >> 6] = ke;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+  if (threadIdx.x < 3) {
+    const float *rr = threadIdx.x == 0 ? r0 : threadIdx.x == 1 ? r1 : r2;
+    float t = 0.f;
 #pragma unroll
-    for (int w = 0; w < 256 / 64; ++w) {
-      t0 += r0[w];
-      t1 += r1[w];
-      t2 += r2[w];
-    }
-    atomicAdd(&out[b * 3 + 0], t0);
-    atomicAdd(&out[b * 3 + 1], t1);
-    atomicAdd(&out[b * 3 + 2], t2);
+    for (int w = 0; w < 256 / 64; ++w) t += rr[w];
+    part[((int64_t)b * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = t;
   }
+}
+
+// out[b][c] = sum over the nblk partials of field b (one workgroup per
+// field; fixed summation order, double accumulation).
+__global__ __launch_bounds__(256) void k_field_stats_reduce(int nblk, const float *__restrict__ part,
+                                                            float *__restrict__ out) {
+  __shared__ double s[3][256];
+  const int b = blockIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += 256) {
+    const float *pq = part + ((int64_t)b * nblk + q) * 3;
+    a0 += pq[0];
+    a1 += pq[1];
+    a2 += pq[2];
+  }
+  s[0][threadIdx.x] = a0;
+  s[1][threadIdx.x] = a1;
+  s[2][threadIdx.x] = a2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + h];
+      s[1][threadIdx.x] += s[1][threadIdx.x + h];
+      s[2][threadIdx.x] += s[2][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) out[b * 3 + threadIdx.x] = (float)s[threadIdx.x][0];
 }
 
 // Acceptance of surrogate fields on the device (no host synchronisation):
@@ -847,21 +884,30 @@ extern "C" int adam_step(float *p, const float *g, float *m, float *v, int64_t n
   return check_launch("adam_step");
 }
 
-extern "C" int field_stats(int B, int nx, int ny, int nz, const float *u, const uint8_t *solid, float *out,
-                           void *stream) {
+extern "C" size_t field_stats_workspace_bytes(int B, int nx, int ny, int nz) {
+  if (B < 1 || B > 65535 || nx < 1 || ny < 1 || nz < 1 || (int64_t)ny * nz >= (1LL << 31)) return 0;
+  return (size_t)B * fs_blocks(nx, ny, nz) * 3 * sizeof(float);
+}
+
+extern "C" int field_stats(int B, int nx, int ny, int nz, const float *u, const uint8_t *solid, float *out, void *ws,
+                           size_t ws_bytes, void *stream) {
   DW_REQUIRE(B >= 1 && nx >= 1 && ny >= 1 && nz >= 1 && B <= 65535, DW_EINVAL, "field_stats: bad size");
-  DW_REQUIRE(u && out, DW_EINVAL, "field_stats: NULL pointer");
+  DW_REQUIRE(u && out && ws, DW_EINVAL, "field_stats: NULL pointer");
+  DW_REQUIRE((int64_t)ny * nz < (1LL << 31), DW_ERANGE, "field_stats: too many rows");
+  const int nblk = fs_blocks(nx, ny, nz);
+  DW_REQUIRE(ws_bytes >= (size_t)B * nblk * 3 * sizeof(float), DW_EWORKSPACE, "field_stats: workspace too small");
   ConvGeom G{};
   G.B = B;
   G.nx = nx;
   G.ny = ny;
   G.nz = nz;
   G.L = (int64_t)nx * ny * nz;
-  DW_REQUIRE((int64_t)ny * nz < (1LL << 31), DW_ERANGE, "field_stats: too many rows");
-  const int rows = ny * nz;
-  const unsigned bx = (unsigned)(rows < 2048 ? rows : 2048);
-  hipLaunchKernelGGL(k_field_stats, dim3(bx, B), dim3(256), 0, (hipStream_t)stream, G, u, solid, out);
-  return check_launch("field_stats");
+  float *part = static_cast<float *>(ws);
+  hipLaunchKernelGGL(k_field_stats, dim3(nblk, B), dim3(256), 0, (hipStream_t)stream, G, u, solid, part);
+  int rc = check_launch("field_stats");
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_field_stats_reduce, dim3(B), dim3(256), 0, (hipStream_t)stream, nblk, part, out);
+  return check_launch("field_stats_reduce");
 }
 
 extern "C" int field_accept(int B, const float *stats_prev, const float *stats_pred, float div_factor, float ke_lo,

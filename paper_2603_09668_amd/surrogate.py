@@ -200,9 +200,10 @@ def check_fields(u_prev, u_new, dims, solid=None, div_factor=2.0, ke_band=(0.9, 
     divergence at most div_factor times the input's, kinetic energy within
     ke_band of the input's.  Returns a bool tensor (B,)."""
     B = dims[0]
-    st = torch.zeros(2, B, 3, dtype=torch.float32, device=u_new.device)
-    api.field_stats(dims, u_prev, solid, st[0])
-    api.field_stats(dims, u_new, solid, st[1])
+    st = torch.empty(2, B, 3, dtype=torch.float32, device=u_new.device)
+    ws = api.field_stats_workspace(dims, u_new.device)
+    api.field_stats(dims, u_prev, solid, st[0], ws)
+    api.field_stats(dims, u_new, solid, st[1], ws)
     finite = torch.isfinite(u_new).flatten(1).all(dim=1)
     rms = torch.sqrt(st[:, :, 0] / st[:, :, 1].clamp(min=1.0))
     ke = st[:, :, 2]
@@ -253,6 +254,7 @@ class SurrogateWind:
         self.u_pred = torch.empty(batch, 3, L, device=dev)
         self.u_lbm = torch.empty(batch, 3, L, device=dev)
         self.stats = torch.zeros(2, batch, 3, device=dev)
+        self.stats_ws = api.field_stats_workspace(self.dims, dev)
         self.accept = torch.zeros(batch, dtype=torch.int32, device=dev)
         self.reject = torch.zeros(batch, dtype=torch.int32, device=dev)
         self.solid_b = None
@@ -290,9 +292,8 @@ class SurrogateWind:
         self.net.forward(u, scale, self.u_pred, dims)
         if override is not None:
             override(self.u_pred)
-        self.stats.zero_()
-        api.field_stats(dims, u, self.solid_b, self.stats[0])
-        api.field_stats(dims, self.u_pred, self.solid_b, self.stats[1])
+        api.field_stats(dims, u, self.solid_b, self.stats[0], self.stats_ws)
+        api.field_stats(dims, self.u_pred, self.solid_b, self.stats[1], self.stats_ws)
         api.field_accept(self.stats[0], self.stats[1], self.accept, self.reject, self.div_factor, self.ke_band)
         for b in range(dims[0]):
             self.lbm_block(u[b], t0, self.u_lbm[b], skip=self.accept[b:b + 1])

@@ -103,6 +103,23 @@ def test_render_argument_errors_are_codes():
     assert L.render_loss(3, 48, 64, P(256), P(512), ctypes.c_float(1.5), None, None, P(1024), lb, None) == -1
 
 
+def test_field_stats_workspace_is_checked_on_the_host():
+    """One partial triple per workgroup and field (at most 2048 workgroups,
+    256 / nx rows each when nx < 256); a short workspace or a bad size is an
+    error code before any launch (fake pointers, never read)."""
+    L = api.lib()
+    assert L.field_stats_workspace_bytes(1, 256, 128, 128) == 2048 * 12
+    assert L.field_stats_workspace_bytes(2, 64, 8, 8) == 2 * 16 * 12      # 4 rows of 64 per workgroup
+    assert L.field_stats_workspace_bytes(1, 100, 3, 3) == 5 * 12          # 2 rows of 100 per workgroup
+    assert L.field_stats_workspace_bytes(0, 8, 8, 8) == 0
+    nb = L.field_stats_workspace_bytes(3, 12, 10, 9)
+    P = ctypes.c_void_p
+    assert L.field_stats(3, 12, 10, 9, P(256), None, P(512), P(1024), nb - 1, None) == -4
+    assert "workspace too small" in api.dw_last_error()
+    assert L.field_stats(3, 12, 10, 9, P(256), None, P(512), None, nb, None) == -1
+    assert L.field_stats(3, 0, 10, 9, P(256), None, P(512), P(1024), nb, None) == -1
+
+
 def test_workspace_size_is_host_only_and_grows_with_n():
     g = api.make_grid(32, 32, 32, 1 / 32)
     a = api.mpm_workspace_bytes(g, 0)

@@ -212,16 +212,24 @@ def test_adam_step():
     assert (md.double().cpu() - m64).abs().max().item() < 1e-6
 
 
-def test_field_stats():
-    say("field stats")
+@pytest.mark.parametrize("dims", [(2, 12, 10, 9), (1, 300, 5, 4), (3, 64, 9, 7), (1, 100, 7, 6), (1, 256, 80, 40)])
+def test_field_stats(dims):
+    """Sums of the divergence and energy checks against the oracle, over row
+    shapes that give one row per workgroup (nx >= 256), several rows per
+    workgroup with idle lanes (nx = 100), and a grid capped at 2048
+    workgroups; a repeated call gives the same bits."""
+    say(f"field stats {dims}")
     rng = np.random.default_rng(5)
-    dims = (2, 12, 10, 9)
     B, nx, ny, nz = dims
     L = nx * ny * nz
     u = torch.tensor(rng.standard_normal((B, 3, L)), dtype=torch.float32)
     solid = torch.tensor(rng.random((B, L)) < 0.2, dtype=torch.uint8)
-    out = torch.zeros(B, 3, device=DEV)
-    api.field_stats(dims, u.to(DEV), solid.to(DEV), out)
+    out = torch.full((B, 3), float("nan"), device=DEV)
+    ud, sd = u.to(DEV), solid.to(DEV)
+    api.field_stats(dims, ud, sd, out)
+    again = torch.empty_like(out)
+    api.field_stats(dims, ud, sd, again, api.field_stats_workspace(dims))
+    assert torch.equal(out, again)
     for b in range(B):
         uf = u[b].double().view(3, nz, ny, nx)
         fl = (solid[b] == 0).view(nz, ny, nx)
