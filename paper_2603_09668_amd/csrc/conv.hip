@@ -11,10 +11,10 @@
 // voxels along x, K = (tap, input channel).  Activations are channels-last
 // BF16 [B][nz][ny][nx][C] with C padded to 8 (3-channel fields) or 32.  One
 // v_mfma_f32_16x16x32_bf16 consumes K = 32: one tap of 32 channels, or four
-// taps of 8 (padded) channels.  A workgroup (4 waves) stages the zero-padded
-// input patch of a tile of 16 x 4 x 8 output voxels (18 x 6 x 10 input
-// voxels) in LDS; for 32-channel inputs a wave's m-tile weight fragments stay
-// in registers for the life of the persistent workgroup.  Lane layout of the 16x16x32 MFMA: lane l holds
+// taps of 8 (padded) channels.  A workgroup (4 waves) stages zero-padded
+// input patches of its output tiles in LDS; for 32-channel inputs a wave's
+// m-tile weight fragments stay in registers for the life of the persistent
+// workgroup.  Lane layout of the 16x16x32 MFMA: lane l holds
 // A[l % 16][8 (l / 16) .. +8], B[8 (l / 16) .. +8][l % 16] and
 // D[4 (l / 16) .. +4][l % 16].
 #include <hip/hip_runtime.h>
@@ -62,16 +62,20 @@ struct ConvGeom {
 // ----------------------------------------------------------------- forward
 //
 // Forward / data-gradient layer.  A workgroup (4 waves, 2 resident per CU)
-// owns output tiles of FX x FY x FZ voxels; per tile it copies the
-// zero-padded input patch (FX+2) x (FY+2) x (FZ+2) into LDS with
-// buffer_load ... lds (channels-last, 16-byte chunks of 8 channels), then:
-//  * 32-channel inputs: wave w computes a 4 (y) x RZ (z) block of output
-//    rows for one 16-channel m-tile, holding that m-tile's 27 weight
-//    fragments in registers for the life of the kernel.  For each x-shift
-//    it walks the (RZ+2) x 6 input rows; every fragment read from LDS feeds
-//    up to 9 MFMAs (all (dz, dy) taps that map it onto an output row).
-//  * 8-channel inputs (3 channels padded): K = 32 spans 4 taps; each wave
-//    computes 8 whole rows, all m-tiles, two rows at a time.
+// copies zero-padded input patches into LDS with buffer_load ... lds
+// (channels-last, 16-byte chunks of 8 channels), then:
+//  * 32-channel inputs: tiles of FX x FY x CZ = 16 x 4 x 4 outputs; a
+//    workgroup walks a column of tiles along z, the patch planes in a ring
+//    of RING slots, and copies the next tile's CZ new planes into the slots
+//    the current tile does not read while its MFMAs run.  Wave w computes a
+//    4 (y) x RZ (z) block of output rows for one 16-channel m-tile, holding
+//    that m-tile's 27 weight fragments in registers for the life of the
+//    kernel.  For each x-shift it walks the (RZ+2) x 6 input rows; every
+//    fragment read from LDS feeds up to 3 RZ MFMAs (all (dz, dy) taps that
+//    map it onto an output row).
+//  * 8-channel inputs (3 channels padded): tiles of FX x FY x FZ = 16 x 4 x 8
+//    outputs, one patch per tile; K = 32 spans 4 taps; each wave computes 8
+//    whole rows, all m-tiles, two rows at a time.
 // The 4 chunks of a voxel's 32 channels are stored permuted by swz(x) so the
 // 16 lanes of a fragment read (16 consecutive x) spread over the LDS banks.
 
@@ -79,8 +83,17 @@ constexpr int FX = 16, FY = 4, FZ = 8;                 // output tile
 constexpr int QX = FX + 2, QY = FY + 2, QZ = FZ + 2;   // input patch
 constexpr int QVOX = QX * QY * QZ;
 
+// 32-channel inputs: tiles of FX x FY x CZ outputs, walked along z; the
+// patch planes live in a ring of RING slots of CPLANE elements in LDS
+constexpr int CZ = 4, CQZ = CZ + 2, RING = QZ;
+constexpr int CPLANE = QX * QY * 32;
+static_assert(RING >= CQZ + CZ, "the next tile's new planes need slots of their own");
+
 struct FwdTiles {
   int tx, ty, tz, n;  // tiles per axis, total over the batch
+  // 32-channel inputs: work items are (column, z segment) pairs; a column is
+  // the tzc tiles (CZ planes each) of one (x, y) tile position of one field
+  int tzc, ncol, zlen, nitems;
 };
 
 struct TileOrigin {
@@ -97,8 +110,11 @@ __device__ __forceinline__ TileOrigin fwd_tile(const FwdTiles &T, int t) {
   return o;
 }
 
-// chunk c of a patch voxel with x index xx is stored at position c ^ swz(xx)
-__device__ __forceinline__ int swz(int xx) { return ((xx >> 2) & 1) | (xx & 2); }
+// chunk c of a patch voxel with x index xx is stored at position c ^ swz(xx).
+// A 16-byte LDS read is served 16 lanes (256 bytes) at a time; the 16 lanes
+// of a fragment read take 16 consecutive x, whose voxels lie 64 bytes apart,
+// so x and x + 4, x + 8, x + 12 would share banks without the permutation.
+__device__ __forceinline__ int swz(int xx) { return (xx >> 2) & 3; }
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
@@ -150,6 +166,61 @@ __device__ __forceinline__ void stage_patch(const ConvGeom &G, const uint16_t *_
     if (yy >= QY) { yy -= QY; gy -= QY; gz += 1; lin += sz - QY * sy; }
     gz += DZ; lin += DZ * sz;
   }
+}
+
+// Copy planes zi0 .. zi0 + np - 1 of the zero-padded input patch of tile o
+// (patch-relative z) into LDS at dst (np consecutive plane slots of
+// QX * QY voxels).  Lanes past the range issue no copy, so the slots after
+// the range are left as they are.
+template <int CINP>
+__device__ __forceinline__ void stage_planes(const ConvGeom &G, const uint16_t *__restrict__ x, const TileOrigin &o,
+                                             uint16_t *dst, int zi0, int np) {
+  constexpr int VEC = CINP / 8;
+  constexpr int D = 256 / VEC;
+  constexpr int DX = D % QX, DY = (D / QX) % QY, DZ = D / (QX * QY);
+  static_assert(256 % VEC == 0, "a lane keeps its channel chunk across iterations");
+  const int nch = np * QX * QY * VEC;
+  const uint16_t *field = x + (int64_t)o.b * G.L * CINP;
+  __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)field, (short)0, (int)(G.L * CINP * 2), 0x00020000);
+  const int wid = threadIdx.x >> 6;
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  const int ql = wid * 64 + lane;
+  const int p = ql % VEC;
+  const int v = ql / VEC;
+  int xx = v % QX, yy = (v / QX) % QY;
+  int gx = o.x0 + xx - 1, gy = o.y0 + yy - 1, gz = o.z0 + zi0 + v / (QX * QY) - 1;
+  const int sy = G.nx, sz = G.nx * G.ny;
+  int lin = gx + sy * gy + sz * gz;
+  for (int q0 = wid * 64; q0 < nch; q0 += 256) {
+    const int q = q0 + lane;
+    const int c = VEC == 4 ? (p ^ swz(xx)) : p;
+    const bool in = (unsigned)gx < (unsigned)G.nx && (unsigned)gy < (unsigned)G.ny && (unsigned)gz < (unsigned)G.nz;
+    const unsigned off = in ? (unsigned)((lin * CINP + c * 8) * 2) : 0x80000000u;
+    if (q < nch) __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_ptr_t)(dst + q0 * 8), 16, off, 0, 0, 0);
+    xx += DX; gx += DX; lin += DX;
+    if (xx >= QX) { xx -= QX; gx -= QX; yy += 1; gy += 1; lin += sy - QX; }
+    yy += DY; gy += DY; lin += DY * sy;
+    if (yy >= QY) { yy -= QY; gy -= QY; gz += 1; lin += sz - QY * sy; }
+    gz += DZ; lin += DZ * sz;
+  }
+}
+
+// Work item v of the column plan: column v % ncol, z segment v / ncol.
+struct ColItem {
+  int b, x0, y0, zt0, zt1;  // field, tile origin in x and y, z tiles [zt0, zt1)
+};
+__device__ __forceinline__ ColItem col_item(const FwdTiles &T, int v) {
+  ColItem c;
+  const int col = v % T.ncol, seg = v / T.ncol;
+  c.x0 = (col % T.tx) * FX;
+  const int r = col / T.tx;
+  c.y0 = (r % T.ty) * FY;
+  c.b = r / T.ty;
+  c.zt0 = seg * T.zlen;
+  c.zt1 = min(T.tzc, c.zt0 + T.zlen);
+  return c;
 }
 
 // Epilogue of one output row: lane holds channels co0 .. co0 + 3 of voxel
@@ -208,28 +279,88 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
   if (threadIdx.x < 32) s_bias[threadIdx.x] = (bias && (int)threadIdx.x < cout) ? bias[threadIdx.x] : 0.f;
 
   if constexpr (CINP == 32) {
-    // wave -> (m-tile, z block)
-    constexpr int RZ = MT == 2 ? 4 : 2;
+    // wave -> (m-tile, z rows of the 16 x 4 x 4 tile)
+    constexpr int RZ = MT == 2 ? 2 : 1;
     const int mt = MT == 2 ? (wid & 1) : 0;
-    const int zb = MT == 2 ? (wid >> 1) * 4 : wid * 2;
+    const int zb = MT == 2 ? (wid >> 1) * 2 : wid;
     bf16x8 wf[27];
 #pragma unroll
     for (int tap = 0; tap < 27; ++tap)
       wf[tap] = *reinterpret_cast<const bf16x8 *>(wk + ((tap * COUTP + mt * 16 + r16) * 32 + g * 8));
-    // the next tile's patch is copied while this tile's epilogue runs
-    if ((int)blockIdx.x < T.n) stage_patch<CINP>(G, x, fwd_tile(T, blockIdx.x), s_in);
-    for (int t = blockIdx.x; t < T.n; t += gridDim.x) {
-      const TileOrigin o = fwd_tile(T, t);
-      __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies have landed
-      __syncthreads();
-      // rows of this wave: voxel of row (yo, zo) = v00 + yo nx + zo nx ny
-      const int gx = o.x0 + r16;
+    // Work items in an order that gives the workgroups of one XCD (dispatch
+    // is round-robin over the 8 XCDs) neighbouring columns, so the x and y
+    // halos of concurrent tiles meet in one L2.  A column is walked along z
+    // with its patch planes in a ring of RING slots: a tile reads CQZ slots,
+    // and the CZ new planes of the column's next tile are copied into the
+    // other CZ slots while this tile's MFMAs run.
+    const int nb = (int)gridDim.x;
+    int v = (nb & 7) ? (int)blockIdx.x : ((int)blockIdx.x & 7) * (nb >> 3) + ((int)blockIdx.x >> 3);
+    ColItem ci{};
+    int zt = 0, rot = 0;
+    bool fresh = true;
+    if (v < T.nitems) {
+      ci = col_item(T, v);
+      zt = ci.zt0;
+    }
+    floatx4 acc[RZ][FY];
+    float uin[RZ][FY][3];
+    TileOrigin op{};
+    bool have_prev = false;
+    auto epilogue = [&](const TileOrigin &oe) {
+      const int gx = oe.x0 + r16;
       const uint32_t sy = (uint32_t)G.nx, sz = (uint32_t)G.nx * (uint32_t)G.ny;
-      const uint32_t v00 = (uint32_t)gx + sy * (uint32_t)o.y0 + sz * (uint32_t)(o.z0 + zb);
+      const uint32_t v00 = (uint32_t)gx + sy * (uint32_t)oe.y0 + sz * (uint32_t)(oe.z0 + zb);
+      const float sb = EPI == DW_CONV_OUTPUT ? scale[oe.b] : 0.f;
+#pragma unroll
+      for (int zo = 0; zo < RZ; ++zo)
+#pragma unroll
+        for (int yo = 0; yo < FY; ++yo) {
+          const bool live = gx < G.nx && oe.y0 + yo < G.ny && oe.z0 + zb + zo < G.nz;
+          if constexpr (EPI == DW_CONV_OUTPUT) {
+            // u_{t+k} = u_t + s (acc + bias), channels 0 .. cout-1 held by the lanes of group 0
+            if (live && g == 0) {
+              const size_t ub = (size_t)oe.b * cout * G.L;
+              const uint32_t L = (uint32_t)G.L;
+#pragma unroll
+              for (int j = 0; j < 3; ++j)
+                if (j < cout)
+                  u_out[ub + (uint32_t)j * L + v00 + yo * sy + zo * sz] = uin[zo][yo][j] + sb * (acc[zo][yo][j] + s_bias[j]);
+            }
+          } else {
+            conv_epilogue<COUTP, EPI>(G, oe, live, v00 + yo * sy + zo * sz, mt * 16 + 4 * g, acc[zo][yo], s_bias,
+                                      cout, y, zpre, zgate, u, sb, u_out);
+          }
+        }
+    };
+    while (v < T.nitems) {
+      const TileOrigin o{ci.b, ci.x0, ci.y0, zt * CZ};
+      if (fresh) {
+        __syncthreads();  // every wave is done with the previous tile's planes
+        stage_planes<CINP>(G, x, o, s_in, 0, CQZ);
+        rot = 0;
+        fresh = false;
+      }
+      __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's copies have landed
+      __syncthreads();  // every wave's have, and every wave is done with the previous tile
+      const bool more = zt + 1 < ci.zt1;
+      if (more) {
+        // planes 2 .. CQZ-1 of the next tile into slots rot + CQZ .. rot + RING - 1
+        const TileOrigin on{ci.b, ci.x0, ci.y0, (zt + 1) * CZ};
+        const int s0 = rot + CQZ >= RING ? rot + CQZ - RING : rot + CQZ;
+        const int n1 = RING - s0 < CZ ? RING - s0 : CZ;
+        stage_planes<CINP>(G, x, on, s_in + s0 * CPLANE, 2, n1);
+        if (n1 < CZ) stage_planes<CINP>(G, x, on, s_in, 2 + n1, CZ - n1);
+      }
+      // epilogue of the previous tile: its stores are issued before this
+      // tile's MFMAs and complete while they run, so the next barrier does
+      // not wait for them
+      if (have_prev) epilogue(op);
       // output layer: the input field's values at this wave's outputs are
       // requested now and arrive during the MFMAs
-      float uin[RZ][FY][3];
       if constexpr (EPI == DW_CONV_OUTPUT) {
+        const int gx = o.x0 + r16;
+        const uint32_t sy = (uint32_t)G.nx, sz = (uint32_t)G.nx * (uint32_t)G.ny;
+        const uint32_t v00 = (uint32_t)gx + sy * (uint32_t)o.y0 + sz * (uint32_t)(o.z0 + zb);
         const size_t ub = (size_t)o.b * cout * G.L;
         const uint32_t L = (uint32_t)G.L;
 #pragma unroll
@@ -242,7 +373,6 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
               uin[zo][yo][j] = (live && j < cout) ? u[ub + (uint32_t)j * L + v00 + yo * sy + zo * sz] : 0.f;
           }
       }
-      floatx4 acc[RZ][FY];
 #pragma unroll
       for (int zo = 0; zo < RZ; ++zo)
 #pragma unroll
@@ -252,8 +382,15 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
       // addresses out of the tile loop (which costs 108 registers).
       int base[3];
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) base[dx] = (r16 + dx + QX * QY * zb) * 32 + (g ^ swz(r16 + dx)) * 8;
+      for (int dx = 0; dx < 3; ++dx) base[dx] = (r16 + dx) * 32 + (g ^ swz(r16 + dx)) * 8;
       asm volatile("" : "+v"(base[0]), "+v"(base[1]), "+v"(base[2]));
+      // LDS offset of the slot that holds patch plane zb + zi
+      int poff[RZ + 2];
+#pragma unroll
+      for (int zi = 0; zi < RZ + 2; ++zi) {
+        const int sl = rot + zb + zi;
+        poff[zi] = (sl >= RING ? sl - RING : sl) * CPLANE;
+      }
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
@@ -263,7 +400,7 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
           bf16x8 bfr[QY];
 #pragma unroll
           for (int yi = 0; yi < QY; ++yi)
-            bfr[yi] = *reinterpret_cast<const bf16x8 *>(s_in + base[dx] + QX * (yi + QY * zi) * 32);
+            bfr[yi] = *reinterpret_cast<const bf16x8 *>(s_in + base[dx] + poff[zi] + QX * yi * 32);
           __builtin_amdgcn_sched_barrier(0);  // keep the six reads ahead of the MFMAs
 #pragma unroll
           for (int yi = 0; yi < QY; ++yi) {
@@ -282,31 +419,21 @@ __global__ __launch_bounds__(256, 2) void k_conv(ConvGeom G, FwdTiles T, const u
           }
         }
       }
-      __syncthreads();  // every wave is done reading s_in
-      const int tn = t + (int)gridDim.x;
-      if (tn < T.n) stage_patch<CINP>(G, x, fwd_tile(T, tn), s_in);
-      const float sb = EPI == DW_CONV_OUTPUT ? scale[o.b] : 0.f;
-#pragma unroll
-      for (int zo = 0; zo < RZ; ++zo)
-#pragma unroll
-        for (int yo = 0; yo < FY; ++yo) {
-          const bool live = gx < G.nx && o.y0 + yo < G.ny && o.z0 + zb + zo < G.nz;
-          if constexpr (EPI == DW_CONV_OUTPUT) {
-            // u_{t+k} = u_t + s (acc + bias), channels 0 .. cout-1 held by the lanes of group 0
-            if (live && g == 0) {
-              const size_t ub = (size_t)o.b * cout * G.L;
-              const uint32_t L = (uint32_t)G.L;
-#pragma unroll
-              for (int j = 0; j < 3; ++j)
-                if (j < cout)
-                  u_out[ub + (uint32_t)j * L + v00 + yo * sy + zo * sz] = uin[zo][yo][j] + sb * (acc[zo][yo][j] + s_bias[j]);
-            }
-          } else {
-            conv_epilogue<COUTP, EPI>(G, o, live, v00 + yo * sy + zo * sz, mt * 16 + 4 * g, acc[zo][yo], s_bias, cout,
-                                      y, zpre, zgate, u, sb, u_out);
-          }
+      op = o;
+      have_prev = true;
+      if (more) {
+        ++zt;
+        rot = rot + CZ >= RING ? rot + CZ - RING : rot + CZ;
+      } else {
+        v += nb;
+        if (v < T.nitems) {
+          ci = col_item(T, v);
+          zt = ci.zt0;
+          fresh = true;
         }
+      }
     }
+    if (have_prev) epilogue(op);
   } else {
     // 8-channel input: chunk c covers taps 4c .. 4c + 3 (lane group g: tap 4c + g)
     bf16x8 wf[7][MT];
@@ -750,11 +877,20 @@ static FwdTiles fwd_tiles(const ConvGeom &G) {
   T.ty = (G.ny + FY - 1) / FY;
   T.tz = (G.nz + FZ - 1) / FZ;
   T.n = T.tx * T.ty * T.tz * G.B;
+  // columns, split into z segments when there are fewer columns than the
+  // 512 resident workgroups
+  T.tzc = (G.nz + CZ - 1) / CZ;
+  T.ncol = T.tx * T.ty * G.B;
+  int segs = T.ncol >= 512 ? 1 : (512 + T.ncol - 1) / T.ncol;
+  segs = segs < T.tzc ? segs : T.tzc;
+  T.zlen = (T.tzc + segs - 1) / segs;
+  T.nitems = T.ncol * ((T.tzc + T.zlen - 1) / T.zlen);
   return T;
 }
 
 // persistent grid: two workgroups per CU
 static unsigned fwd_blocks(const FwdTiles &T) { return (unsigned)(T.n < 512 ? T.n : 512); }
+static unsigned col_blocks(const FwdTiles &T) { return (unsigned)(T.nitems < 512 ? T.nitems : 512); }
 
 }  // namespace dw
 
@@ -799,19 +935,19 @@ extern "C" int conv3d_bf16(int B, int nx, int ny, int nz, int cin, int cout, int
   DW_REQUIRE((cin == 3 || cin == 32) && (cout == 3 || cout == 32), DW_EINVAL, "conv3d_bf16: channels 3 or 32");
   hipStream_t s = (hipStream_t)stream;
   const FwdTiles T = fwd_tiles(G);
-  const unsigned nb = fwd_blocks(T);
+  const unsigned nb = fwd_blocks(T), nb32 = col_blocks(T);
   if (epilogue == DW_CONV_HIDDEN) {
     DW_REQUIRE(cout == 32 && bias && y, DW_EINVAL, "conv3d_bf16: hidden layer needs cout 32, bias, y");
     if (cin == 3)
       hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, T, x, wk, bias, cout, y, zpre,
                          nullptr, nullptr, nullptr, nullptr);
     else
-      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_HIDDEN>), dim3(nb), dim3(256), 0, s, G, T, x, wk, bias, cout, y,
+      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_HIDDEN>), dim3(nb32), dim3(256), 0, s, G, T, x, wk, bias, cout, y,
                          zpre, nullptr, nullptr, nullptr, nullptr);
   } else if (epilogue == DW_CONV_OUTPUT) {
     DW_REQUIRE(cin == 32 && cout == 3 && bias && u && scale && u_out, DW_EINVAL,
                "conv3d_bf16: output layer needs 32 -> 3, bias, u, scale, u_out");
-    hipLaunchKernelGGL((k_conv<32, 16, DW_CONV_OUTPUT>), dim3(nb), dim3(256), 0, s, G, T, x, wk, bias, cout, nullptr,
+    hipLaunchKernelGGL((k_conv<32, 16, DW_CONV_OUTPUT>), dim3(nb32), dim3(256), 0, s, G, T, x, wk, bias, cout, nullptr,
                        nullptr, nullptr, u, scale, u_out);
   } else if (epilogue == DW_CONV_DGRAD) {
     // transposed convolution of the gradient: input channels = the layer's cout
@@ -820,7 +956,7 @@ extern "C" int conv3d_bf16(int B, int nx, int ny, int nz, int cin, int cout, int
       hipLaunchKernelGGL((k_conv<8, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, T, x, wk, nullptr, 32, y,
                          nullptr, zgate, nullptr, nullptr, nullptr);
     else
-      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_DGRAD>), dim3(nb), dim3(256), 0, s, G, T, x, wk, nullptr, 32, y,
+      hipLaunchKernelGGL((k_conv<32, 32, DW_CONV_DGRAD>), dim3(nb32), dim3(256), 0, s, G, T, x, wk, nullptr, 32, y,
                          nullptr, zgate, nullptr, nullptr, nullptr);
   } else {
     return set_error(DW_EINVAL, "conv3d_bf16: unknown epilogue %d", epilogue);

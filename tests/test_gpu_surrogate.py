@@ -314,6 +314,80 @@ def test_full_size_layers_sampled():
         assert e <= ACC * ab
 
 
+def _walk_samples(rng, dims, n=1536):
+    """Sampled voxels of dims, with extra samples on the z planes where one
+    8-plane tile ends and the next begins, on the last x and z planes, and on
+    the y tile seams."""
+    B, nx, ny, nz = dims
+    zs = [z for z in range(7, nz, 8)] + [z for z in range(8, nz, 8)] + [nz - 1]
+    k = 16 * len(zs)
+    bb = torch.tensor(rng.integers(0, B, n + k))
+    zz = torch.tensor(np.r_[rng.integers(0, nz, n), np.repeat(zs, 16)])
+    yy = torch.tensor(np.r_[rng.integers(0, ny, n), rng.choice([3, 4, ny - 1], k)])
+    xx = torch.tensor(np.r_[rng.integers(0, nx, n - 64), np.full(64, nx - 1), rng.integers(0, nx, k)])
+    return bb, zz, yy, xx
+
+
+def test_column_walk_layers_sampled():
+    """Fields on which every workgroup walks a column of five z tiles, so the
+    patch planes the tiles share go round the whole plane ring (ragged x and
+    z edges): sampled outputs of the hidden, output and data-gradient layers
+    against float64 sums over the gathered neighbourhoods."""
+    dims = (16, 20, 64, 36)
+    B, nx, ny, nz = dims
+    L = nx * ny * nz
+    say(f"column walk sampled {dims}")
+    rng = np.random.default_rng(8)
+    bb, zz, yy, xx = _walk_samples(rng, dims)
+    idx = (bb.to(DEV), zz.to(DEV), yy.to(DEV), xx.to(DEV))
+    # hidden layer 32 -> 32
+    x = _rand_act(rng, dims, 32)
+    w, w64 = _rand_w(rng, 32, 32)
+    bias = torch.tensor(0.1 * rng.standard_normal(32), dtype=torch.float32)
+    y = torch.empty(B * L * 32, dtype=torch.bfloat16, device=DEV)
+    zp = torch.empty_like(y)
+    xd = _to_dev_act(x, 32)
+    api.conv3d_bf16(dims, 32, 32, api.CONV_HIDDEN, xd, _pack(w, 32, 32, 0), bias=bias.to(DEV), y=y, zpre=zp)
+    xh = xd.view(B, nz, ny, nx, 32).cpu().double()
+    P = _gather_patch(xh, bb, zz, yy, xx)                                   # (n, 27, ci)
+    W = w64.reshape(32, 32, 27)
+    ref = torch.einsum("ntc,oct->no", P, W) + bias.double()
+    a = torch.einsum("ntc,oct->no", P.abs(), W.abs()) + bias.double().abs()
+    _check("zpre", zp.view(B, nz, ny, nx, 32)[idx].double().cpu(), ref, U_BF * ref.abs() + 2 * ACC * a)
+    s_ref = oconv.silu(ref)
+    _check("silu", y.view(B, nz, ny, nx, 32)[idx].double().cpu(), s_ref, U_BF * s_ref.abs() + 3 * ACC * a + 1e-6)
+    # output layer 32 -> 3 on the same input
+    w3, w364 = _rand_w(rng, 32, 3)
+    b3 = torch.tensor(0.1 * rng.standard_normal(3), dtype=torch.float32)
+    u = torch.tensor(0.05 * rng.standard_normal((B, 3, L)), dtype=torch.float32)
+    sc = torch.tensor(rng.uniform(0.02, 0.1, B), dtype=torch.float32)
+    uo = torch.empty(B, 3, L, device=DEV)
+    api.conv3d_bf16(dims, 32, 3, api.CONV_OUTPUT, xd, _pack(w3, 32, 3, 0), bias=b3.to(DEV), u=u.to(DEV),
+                    scale=sc.to(DEV), u_out=uo)
+    z3 = torch.einsum("ntc,oct->no", P, w364.reshape(3, 32, 27)) + b3.double()
+    a3 = torch.einsum("ntc,oct->no", P.abs(), w364.reshape(3, 32, 27).abs()) + b3.double().abs()
+    vox = xx + nx * (yy + ny * zz)
+    sv = sc.double()[bb][:, None]
+    ref3 = u.double()[bb, :, vox] + sv * z3
+    got3 = uo.view(B, 3, L).cpu().double()[bb, :, vox]
+    _check("u_out", got3, ref3, 2 * ACC * sv * a3 + 1e-6 * ref3.abs())
+    # data gradient of a 32 -> 32 layer: conv^T of g, times silu'(zgate)
+    gr = _rand_act(rng, dims, 32, 1e-3)
+    zg = _rand_act(rng, dims, 32, 2.0)
+    gd, zgd = _to_dev_act(gr, 32), _to_dev_act(zg, 32)
+    yd = torch.empty_like(y)
+    api.conv3d_bf16(dims, 32, 32, api.CONV_DGRAD, gd, _pack(w, 32, 32, 1), y=yd, zgate=zgd)
+    Pg = _gather_patch(gd.view(B, nz, ny, nx, 32).cpu().double(), bb, zz, yy, xx)   # (n, 27, co)
+    Wf = W.flip(2)                                   # conv^T: the tap at -d is tap 26 - t
+    dx = torch.einsum("ntc,cot->no", Pg, Wf)
+    da = torch.einsum("ntc,cot->no", Pg.abs(), Wf.abs())
+    zgs = zgd.view(B, nz, ny, nx, 32)[idx].double().cpu()
+    sig = torch.sigmoid(zgs)
+    gate = sig * (1 + zgs * (1 - sig))
+    refd = dx * gate
+    _check("dgrad", yd.view(B, nz, ny, nx, 32)[idx].double().cpu(), refd, U_BF * refd.abs() + 2 * ACC * da * gate.abs())
+
+
 # --------------------------------------------------------------- whole network
 
 def _oracle_net(net):
