@@ -23,7 +23,7 @@ namespace dw {
 constexpr int SC_L = 6;           // local node extent of a cell tile's stencils
 constexpr int SC_NODES = 216;     // 6^3
 constexpr int SC_DAT = 13;        // staged feature rows per particle: m, q(3), A(9)
-constexpr int SC_UNIT = 64;       // particles per unit (16 MFMA steps)
+constexpr int SC_UNIT = 16;       // particles per unit (4 MFMA steps): a dense cell spreads over waves
 constexpr int SC_MAX_UNITS = 64 + WORK_CHUNK / SC_UNIT;  // bounds the sum over cells of ceil(count / unit)
 constexpr int SC_THREADS = WORK_CHUNK;
 constexpr int SC_WAVES = SC_THREADS / 64;
