@@ -394,11 +394,13 @@ __device__ __forceinline__ void lbm_row_block(const LbmDev &P, const float *__re
 
 // One workgroup per row block.  Large lattices (BIG): a 3-D grid of row
 // blocks; otherwise rows are handed to the XCDs in contiguous runs
-// (xcd_row_block) and the output stays cached.
+// (xcd_row_block) and the output stays cached.  Eight waves per SIMD: the
+// plane bases it would otherwise keep in scalar registers limit it to seven
+// (some spill to vector-register lanes instead).
 template <bool SOLID, bool BIG>
-__global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step(LbmDev P, const float *__restrict__ fin,
-                                                        float *__restrict__ fout, const uint8_t *__restrict__ solid,
-                                                        float *__restrict__ rho_out, float *__restrict__ u_out) {
+__global__ __launch_bounds__(LBM_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_lbm_step(
+    LbmDev P, const float *__restrict__ fin, float *__restrict__ fout, const uint8_t *__restrict__ solid,
+    float *__restrict__ rho_out, float *__restrict__ u_out) {
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
   __shared__ int s_any[LBM_BLOCK / 64];
   __shared__ float s_inl[5];
