@@ -47,16 +47,22 @@ constexpr int SOL_W = LBM_BLOCK + 8;  // staged solid bytes per row: x0 - 4 .. x
 // opposite population (bounce-back), or the inlet ghost.
 enum { SRC_NORMAL = 0, SRC_BOUNCE = 1, SRC_INLET = 2 };
 
+// Inflow factor of the gust at inlet-plane (j, k): 1 + a sin(2 pi (t / T +
+// ky j / ny + kz k / nz) + phase).  The phase is taken in turns and reduced
+// to [0, 1) for the hardware sine of turns (a few instructions instead of a
+// library sine; its error is far below float rounding of the inflow).
+__device__ __forceinline__ float gust_factor(const LbmDev &P, int j, int k) {
+  if (P.gust_amp == 0.f) return 1.0f;
+  const int t = P.t_in ? *P.t_in : P.t;
+  float rev = (float)t * P.gust_inv_period + P.gust_ky * (float)j / (float)P.ny +
+              P.gust_kz * (float)k / (float)P.nz + P.gust_phase * 0.15915494309189535f;
+  rev -= floorf(rev);
+  return 1.0f + P.gust_amp * __builtin_amdgcn_sinf(rev);
+}
+
 // inlet equilibrium population (shifted) in direction q at inlet-plane (j, k)
 __device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, int k) {
-  float sfac = 1.0f;
-  if (P.gust_amp != 0.f) {
-    int t = P.t_in ? *P.t_in : P.t;
-    float ph = 6.283185307179586f * ((float)t * P.gust_inv_period + P.gust_ky * (float)j / (float)P.ny +
-                                     P.gust_kz * (float)k / (float)P.nz) +
-               P.gust_phase;
-    sfac = 1.0f + P.gust_amp * sinf(ph);
-  }
+  const float sfac = gust_factor(P, j, k);
   float ux = P.uin[0] * sfac, uy = P.uin[1] * sfac, uz = P.uin[2] * sfac;
   float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
   float uu = ux * ux + uy * uy + uz * uz;
@@ -368,22 +374,38 @@ __device__ __forceinline__ void lbm_row_block(const LbmDev &P, const float *__re
   else pull_row<0>(std::make_integer_sequence<int, 19>{}, P, fin, s_sol, s_inl, inlet_wave, i, j, k, x0, node, f);
   float rho, ux, uy, uz;
   moments(P, f, rho, ux, uy, uz);
-  float drho = rho - 1.0f;
-  float uu = ux * ux + uy * uy + uz * uz;
-  float om = P.omega;
-  float kf = 1.0f - 0.5f * om;
-  float uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
+  const float drho = rho - 1.0f;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float om = P.omega;
+  // BGK against the shifted equilibrium W (drho + rho (3 cu + 4.5 cu^2 -
+  // 1.5 u.u)), a direction and its opposite together: they share the even
+  // part W (c0 + 4.5 rho cu^2) and differ in the sign of the odd part
+  // 3 W rho cu.
+  const float c0 = drho - 1.5f * rho * uu;
+  const float r45 = 4.5f * rho, r3 = 3.0f * rho;
+  float g[19];
+  g[0] = f[0] + om * (LW[0] * c0 - f[0]);
 #pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
-    float feq = LW[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-    float g = f[q] - om * (f[q] - feq);
-    if (P.forced) {
-      float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
-      g += kf * LW[q] * (3.f * (cF - uF) + 9.f * cu * cF);
-    }
-    st_out<BIG>(fout + (size_t)q * P.L, node, solid_node ? 0.f : g);
+  for (int q = 1; q < 19; q += 2) {
+    const float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+    const float ev = LW[q] * fmaf(r45 * cu, cu, c0);
+    const float od = (LW[q] * r3) * cu;
+    g[q] = f[q] + om * ((ev + od) - f[q]);
+    g[q + 1] = f[q + 1] + om * ((ev - od) - f[q + 1]);
   }
+  if (P.forced) {
+    const float kf = 1.0f - 0.5f * om;
+    const float uF = ux * P.F[0] + uy * P.F[1] + uz * P.F[2];
+#pragma unroll
+    for (int q = 1; q < 19; ++q) {
+      const float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
+      const float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
+      g[q] += kf * LW[q] * (3.f * (cF - uF) + 9.f * cu * cF);
+    }
+    g[0] += kf * LW[0] * (-3.f * uF);
+  }
+#pragma unroll
+  for (int q = 0; q < 19; ++q) st_out<BIG>(fout + (size_t)q * P.L, node, solid_node ? 0.f : g[q]);
   if (rho_out) st_out<BIG>(rho_out, node, solid_node ? 1.f : rho);
   if (u_out) {
     st_out<BIG>(u_out, node, solid_node ? 0.f : ux);
@@ -560,14 +582,7 @@ __device__ __forceinline__ void acc_pop(MomAcc &A, float g) {
 
 // equilibrium moments of an inlet ghost node at inlet-plane (j, k)
 __device__ __forceinline__ Mom inlet_mom(const LbmDev &P, int j, int k) {
-  float sfac = 1.0f;
-  if (P.gust_amp != 0.f) {
-    int t = P.t_in ? *P.t_in : P.t;
-    float ph = 6.283185307179586f * ((float)t * P.gust_inv_period + P.gust_ky * (float)j / (float)P.ny +
-                                     P.gust_kz * (float)k / (float)P.nz) +
-               P.gust_phase;
-    sfac = 1.0f + P.gust_amp * sinf(ph);
-  }
+  const float sfac = gust_factor(P, j, k);
   Mom M;
   M.drho = 0.f;
 #pragma unroll

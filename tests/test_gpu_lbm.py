@@ -50,6 +50,24 @@ CASES = {
     # rows longer than one workgroup (x0 > 0), solids in the second one
     "wide_tunnel": dict(dims=(200, 7, 6), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 120.0, 1.0, 0.0, 0.7),
                         solid=(slice(2, 4), slice(3, 5), slice(150, 190))),
+    # rows of whole 64-node waves (the bounce decisions taken as lane masks):
+    # solids on the inlet and outlet lanes, across the seam between two waves
+    # and between two workgroups, and wrapped across the lattice ends
+    "tunnel_waves": dict(dims=(128, 7, 6), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 90.0, 1.0, 1.0, 0.2),
+                         solid=[(slice(1, 4), slice(2, 5), slice(0, 3)), (slice(2, 5), slice(1, 4), slice(125, 128)),
+                                (slice(0, 3), slice(3, 6), slice(61, 67)), (slice(4, 6), slice(0, 2), slice(30, 33))]),
+    "wide_waves": dict(dims=(256, 5, 4), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 150.0, 0.0, 1.0, 0.5),
+                       solid=[(slice(1, 3), slice(1, 4), slice(125, 131)), (slice(0, 2), slice(2, 5), slice(190, 194)),
+                              (slice(2, 4), slice(0, 2), slice(253, 256))]),
+    "periodic_waves": dict(dims=(64, 6, 5), bc=(0,) * 6, force=(2e-5, 0.0, 1e-5), gust=(0.0, 1.0, 0, 0, 0),
+                           solid=[(slice(0, 2), slice(4, 6), slice(62, 64)), (slice(3, 5), slice(0, 2), slice(0, 2)),
+                                  (slice(1, 4), slice(2, 4), slice(30, 34))]),
+    "x_bounce_waves": dict(dims=(64, 6, 5), bc=(1, 1, 0, 0, 1, 1), force=(0.0, 1e-5, 0.0), gust=(0.0, 1.0, 0, 0, 0),
+                           solid=[(slice(0, 3), slice(0, 2), slice(0, 2)), (slice(2, 5), slice(4, 6), slice(61, 64))]),
+    "bb_outlet_waves": dict(dims=(64, 6, 5), bc=(1, 3, 1, 1, 0, 0), force=(0.0, 0.0, 0.0), gust=(0.0, 1.0, 0, 0, 0),
+                            solid=[(slice(0, 5), slice(1, 3), slice(0, 2)), (slice(1, 4), slice(3, 5), slice(62, 64))]),
+    "inlet_bb_waves": dict(dims=(64, 6, 5), bc=(2, 1, 0, 0, 1, 1), force=(0.0, 0.0, 0.0), gust=(0.05, 60.0, 1.0, 0.0, 0.0),
+                           solid=[(slice(0, 5), slice(1, 3), slice(0, 2)), (slice(1, 4), slice(3, 5), slice(62, 64))]),
 }
 
 
@@ -60,7 +78,9 @@ def test_lbm_step_parity(case):
     say(f"lbm_step {case} {c['dims']}")
     f, fs = _random_state(c["dims"], 1)
     solid = torch.zeros(nz, ny, nx, dtype=torch.bool)
-    solid[c.get("solid", (slice(nz // 3, nz // 3 + 4), slice(ny // 3, ny // 3 + 3), slice(nx // 2, nx // 2 + 5)))] = True
+    regions = c.get("solid", (slice(nz // 3, nz // 3 + 4), slice(ny // 3, ny // 3 + 3), slice(nx // 2, nx // 2 + 5)))
+    for reg in (regions if isinstance(regions, list) else [regions]):
+        solid[reg] = True
     t = 17
     op, ap = _params(force=c["force"], bc=c["bc"], gust=c["gust"], t=t)
     lat = olbm.Lattice(nx, ny, nz)
