@@ -20,23 +20,30 @@ namespace dw {
 // Wave-aggregated keyed atomicAdd: lanes holding equal keys share one
 // global atomic (particles are spatially coherent, so a wave usually holds one
 // or two keys).  Returns base + rank of the lane among the lanes with its key
-// (lane order).  Every lane of the wave must call it.
+// (lane order).  The distinct keys are found first with ballots, then their
+// leaders issue their atomics together, so a wave waits for one round trip
+// however many keys it holds.  Every lane of the wave must call it.
 __device__ __forceinline__ int wave_keyed_add(int32_t *counters, int key, bool active) {
   unsigned long long pending = __ballot(active);
   const int lane = threadIdx.x & 63;
-  int result = 0;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int my_leader = 0, my_rank = 0, count = 0;
   while (pending) {
-    int leader = __ffsll((unsigned long long)pending) - 1;
-    int k = __shfl(key, leader, 64);
-    bool mine = active && key == k;
-    unsigned long long same = __ballot(mine);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counters[k], (int)__popcll(same));
-    base = __shfl(base, leader, 64);
-    if (mine) result = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int k = __shfl(key, leader, 64);
+    const bool mine = active && key == k;
+    const unsigned long long same = __ballot(mine);
+    if (mine) {
+      my_leader = leader;
+      my_rank = (int)__popcll(same & below);
+    }
+    if (lane == leader) count = (int)__popcll(same);
     pending &= ~same;
   }
-  return result;
+  int base = 0;
+  if (count > 0) base = atomicAdd(&counters[key], count);
+  base = __shfl(base, my_leader, 64);
+  return active ? base + my_rank : 0;
 }
 
 // Key of every particle and its rank inside its tile (the tile count's value
