@@ -528,7 +528,7 @@ int lbm_solid_from_particles(const dw_lattice *lat, const float *x, const float 
 /* ------------------------------------------------------ wind surrogate */
 
 /* A learned stand-in for k LBM steps (the paper has no learned wind model;
- * the lattice Boltzmann step of Eq. lbe is its fallback and judge):
+ * the lattice Boltzmann step of Eq. lbe is its fallback and its reference):
  *   u_{t+k} = u_t + g s net(u_t / s),
  *   net = conv(32->3) o silu o conv(32->32) o silu o conv(32->32) o silu o conv(3->32),
  * 3x3x3 kernels with zero padding, s the per-field inflow speed, g a fixed

@@ -1,8 +1,8 @@
 """FP64 oracle: 3-D convolutional wind surrogate and its field checks (test infrastructure only).
 
 The paper has no learned wind model; the surrogate advances the LBM wind
-velocity field by k lattice steps in one call and is judged against the LBM
-of Eq. lbe.  Network (fixed by the workload definition): four 3x3x3
+velocity field by k lattice steps in one call and its error is measured
+against the LBM of Eq. lbe.  Network (fixed by the workload definition): four 3x3x3
 convolutions with zero "same" padding, channels 3 -> 32 -> 32 -> 32 -> 3,
 SiLU after the first three, residual output scaled by the per-sample inflow
 speed s and a fixed output gain g:

@@ -4,8 +4,8 @@
 //   u_{t+k} = u_t + g s net(u_t / s),  net = conv(32->3) o silu o conv(32->32)
 //   o silu o conv(32->32) o silu o conv(3->32),  3x3x3 kernels, zero padding,
 // s the per-field inflow speed, g a fixed output gain (the caller's scale of
-// the output layer's residual).  It is judged against the lattice Boltzmann
-// step of Eq. lbe.
+// the output layer's residual).  Its error is measured against the lattice
+// Boltzmann step of Eq. lbe.
 //
 // Implicit GEMM per layer: M = output channels (tiles of 16), N = a row of 16
 // voxels along x, K = (tap, input channel).  Activations are channels-last

@@ -3,7 +3,7 @@ velocity field k lattice steps per call, trained on rollouts of the library's
 own lbm_step, with a divergence / kinetic-energy check and plain-LBM fallback.
 
 The paper's wind is the lattice Boltzmann solution of Eq. lbe; this net is a
-faster stand-in that the LBM judges and replaces whenever a check fails:
+faster stand-in, measured against the LBM, which replaces it whenever a check fails:
 
     u_{t+k} = u_t + g s * net(u_t / s),  s = the field's inflow speed,
     net = conv(32->3) . silu . conv(32->32) . silu . conv(32->32) . silu . conv(3->32).
@@ -233,7 +233,7 @@ def train(net: Surrogate, U0, U1, S, dims, steps: int, batch: int = 16, lr: floa
 
 class SurrogateWind:
     """Advances the wind of one lattice k LBM steps per call with the surrogate,
-    judged by the divergence and kinetic-energy checks; a rejected field is
+    checked by the divergence and kinetic-energy tests; a rejected field is
     re-initialised at equilibrium (rho = 1, the current u) and advanced k plain
     LBM steps instead.  The decision is taken on the device: the checks write
     an acceptance flag that switches the LBM fallback branch off (the `skip`
