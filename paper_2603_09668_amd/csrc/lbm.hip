@@ -99,9 +99,11 @@ __device__ __forceinline__ void load_solid_rows(const LbmDev &P, const uint8_t *
       kk = kk < 0 ? kk + P.nz : kk - P.nz;
     }
     const int xs = x0 - 4 + 4 * w;
-    const int64_t row = (int64_t)P.nx * (jj + (int64_t)P.ny * kk);
+    const uint32_t row = (uint32_t)P.nx * ((uint32_t)jj + (uint32_t)P.ny * (uint32_t)kk);
     if (aligned && xs >= 0 && xs + 3 < P.nx) {
       v[u] = *reinterpret_cast<const uint32_t *>(solid + row + xs);
+    } else if (!xper && (xs + 3 < 0 || xs >= P.nx)) {
+      // wholly beyond a non-periodic x face: fluid
     } else {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
