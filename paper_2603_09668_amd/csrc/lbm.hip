@@ -473,8 +473,8 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step_gated(LbmDev P, const fl
 // post-collision moments, [HM_N][L] = rho - 1, u (3), S (6: xx yy zz xy xz
 // yz) with rho S_ab = sum_i (c_a c_b - delta_ab / 3) f_i.  The step pulls,
 // for each direction q, the population f_q of the source node rebuilt from
-// the source's moments by the third-order Hermite expansion, accumulates the
-// moments of the pulled set on the fly (no population is stored), and
+// the source's moments by the third-order Hermite expansion, takes the
+// moments of the pulled set (no population is stored in memory), and
 // relaxes them in moment space.  40 bytes per node in and out instead of
 // the 76 + 76 of the population form.
 constexpr int HM_N = 10;
@@ -561,26 +561,10 @@ __device__ __forceinline__ void home_pop_adj(const Mom &M, float pb, Mom &Mb) {
   }
 }
 
-// moments of the pulled set, accumulated direction by direction
+// moments of the pulled set
 struct MomAcc {
   float drho = 0.f, j[3] = {0.f, 0.f, 0.f}, P[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 };
-
-template <int Q>
-__device__ __forceinline__ void acc_pop(MomAcc &A, float g) {
-  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
-  A.drho += g;
-  if constexpr (c[0] != 0) A.j[0] += c[0] * g;
-  if constexpr (c[1] != 0) A.j[1] += c[1] * g;
-  if constexpr (c[2] != 0) A.j[2] += c[2] * g;
-  // sum H2_ab g (the weights' part sums to zero)
-  A.P[0] += (c[0] * c[0] - 1.f / 3.f) * g;
-  A.P[1] += (c[1] * c[1] - 1.f / 3.f) * g;
-  A.P[2] += (c[2] * c[2] - 1.f / 3.f) * g;
-  if constexpr (c[0] * c[1] != 0) A.P[3] += (c[0] * c[1]) * g;
-  if constexpr (c[0] * c[2] != 0) A.P[4] += (c[0] * c[2]) * g;
-  if constexpr (c[1] * c[2] != 0) A.P[5] += (c[1] * c[2]) * g;
-}
 
 // equilibrium moments of an inlet ghost node at inlet-plane (j, k)
 __device__ __forceinline__ Mom inlet_mom(const LbmDev &P, int j, int k) {
@@ -597,10 +581,7 @@ __device__ __forceinline__ Mom inlet_mom(const LbmDev &P, int j, int k) {
   return M;
 }
 
-// Forward pull of the moment-encoded step with the row-uniform source rules
-// and 32-bit offsets of the population step: every bounce decision comes
-// from the staged flags first, then each source's ten moments are loaded
-// from scalar plane bases (one offset per source) and expanded.
+// the ten moments of a node (planes of L floats)
 __device__ __forceinline__ Mom load_mom_at(const float *__restrict__ m, size_t L, uint32_t node) {
   Mom M;
   M.drho = ld_node(m, node);
@@ -627,75 +608,11 @@ __device__ __forceinline__ float home_inlet_pop(const LbmDev &P, int t, int j, i
   }
 }
 
-template <int SOL, int Q>
-__device__ __forceinline__ void home_pull_row(const LbmDev &P, const float *__restrict__ min, const float *s_inl,
-                                              bool inlet_wave, int i, int j, int k, const Mom &own, bool bb,
-                                              MomAcc &A) {
-  float g;
-  if constexpr (Q == 0) {
-    g = home_pop<0>(own);
-  } else {
-    const PullSrc s = pull_src<Q>(P, i, j, k);
-    g = home_pop<Q>(load_mom_at(min, P.L, s.src));
-    if (bb) g = home_pop<LOPP[Q]>(own);
-    if constexpr (inlet_slot(Q) >= 0) {
-      if (inlet_wave && s.kind == SRC_INLET) g = s_inl[inlet_slot(Q)];
-    }
-  }
-  acc_pop<Q>(A, g);
-}
-
-template <int SOL, int... Qs>
-__device__ __forceinline__ void home_row_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
-                                             const float *__restrict__ min, const uint8_t (*s_sol)[SOL_W],
-                                             const float *s_inl, bool inlet_wave, int i, int j, int k, int x0,
-                                             const Mom &own, MomAcc &A) {
-  bool bb[19];
-  ((bb[Qs] = pull_bounces<Qs, SOL>(pull_src<Qs>(P, i, j, k), s_sol, x0)), ...);
-  (home_pull_row<SOL, Qs>(P, min, s_inl, inlet_wave, i, j, k, own, bb[Qs], A), ...);
-}
-
-template <bool SOLID>
-__global__ __launch_bounds__(LBM_BLOCK) void k_home_step(LbmDev P, const float *__restrict__ min,
-                                                         float *__restrict__ mout, const uint8_t *__restrict__ solid,
-                                                         float *__restrict__ rho_out, float *__restrict__ u_out) {
-  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
-  __shared__ int s_any[LBM_BLOCK / 64];
-  __shared__ float s_inl[5];
-  const RowBlock rb = xcd_row_block(P);
-  if (!rb.live) return;  // block-uniform: padding blocks of the last XCD
-  const int x0 = rb.x0;
-  const int i = x0 + threadIdx.x, j = rb.j, k = rb.k;
-  if (i == 0 && j == 0 && k == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
-  const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
-  // the row's x = 0 block stages the inlet populations (block-uniform)
-  const bool inlet_row = x0 == 0 && P.bc[0] == DW_BC_INLET;
-  if (inlet_row && threadIdx.x < 5) s_inl[threadIdx.x] = home_inlet_pop(P, threadIdx.x, j, k);
-  bool any = false;
-  if (SOLID) {
-    uint32_t sv[SOL_PER_THREAD];
-    load_solid_rows(P, solid, x0, j, k, sv);
-    store_solid_rows(sv, s_sol);
-    uint32_t mine = 0;
-#pragma unroll
-    for (int u = 0; u < SOL_PER_THREAD; ++u) mine |= sv[u];
-    const bool wave_any = __ballot(mine != 0) != 0ull;
-    if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = wave_any;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < LBM_BLOCK / 64; ++w) any = any || s_any[w] != 0;
-  } else if (inlet_row) {
-    __syncthreads();
-  }
-  if (i >= P.nx) return;
-  // a solid node outputs the rest state; it runs with its wave and only its
-  // stores are replaced, so the lanes of a wave write their lines together
-  const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
-  const bool inlet_wave = inlet_row && threadIdx.x < 64;  // wave-uniform
-  const Mom own = load_mom_at(min, P.L, node);
-  MomAcc A;
-  if (any) home_row_all<1>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
-  else home_row_all<0>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
+// Collision of the pulled set's moments and the stores of one node (a solid
+// node stores the rest state).
+__device__ __forceinline__ void home_collide_store(const LbmDev &P, const MomAcc &A, float *__restrict__ mout,
+                                                   float *__restrict__ rho_out, float *__restrict__ u_out,
+                                                   uint32_t node, bool solid_node) {
   // moments of the pulled set: u* carries half the force
   const float rho = 1.f + A.drho, ir = 1.f / rho;
   float u[3], Fu = 0.f, uu = 0.f;
@@ -733,6 +650,440 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_home_step(LbmDev P, const float *
   }
 }
 
+// ------------------------------------------------------ HOME-LBM tile step
+// The moment-encoded step on tiles of HT_X x HT_Y x HT_Z nodes (x fastest),
+// one thread per node.  Most terms of the expansion of a node's moments into
+// its 19 populations are shared between directions (the third-order
+// coefficients a3_aab, the even and odd parts of each axis and of each axis
+// pair), so every node evaluates all of its populations at once and pushes
+// each into the LDS slot of the node that pulls it; nodes of the one-node
+// halo around the tile evaluate only the populations that point into it.
+// Every slot has one writer: the source node of the pull, or, where the
+// zero-gradient outlet clamps the source, the outlet-face node of the source
+// row.  After a barrier each node takes its populations from its slots,
+// except where the pull bounces back (its own population of the opposite
+// direction, still in registers) or comes from the inlet (staged per row).
+constexpr int HT_X = 32, HT_Y = 4, HT_Z = 4, HT_N = HT_X * HT_Y * HT_Z;
+constexpr int HT_SX = HT_X + 2, HT_SY = HT_Y + 2, HT_SZ = HT_Z + 2;
+
+struct HomeTile {
+  int x0, y0, z0;  // lattice coordinates of the tile's first node
+  int wx, wy, wz;  // extents of the tile inside the lattice
+  bool live;
+};
+
+// Tiles in x, then y, then z; each XCD takes a contiguous run of them, so
+// the halo a tile shares with its neighbours stays in one L2.
+__device__ __forceinline__ HomeTile home_tile(const LbmDev &P) {
+  const int ntx = (P.nx + HT_X - 1) / HT_X, nty = (P.ny + HT_Y - 1) / HT_Y, ntz = (P.nz + HT_Z - 1) / HT_Z;
+  const int64_t nt = (int64_t)ntx * nty * ntz;
+  const int64_t per_xcd = (nt + N_XCD - 1) / N_XCD;
+  const int64_t b = blockIdx.x;
+  const int64_t v = (b % N_XCD) * per_xcd + b / N_XCD;
+  HomeTile T;
+  T.live = v < nt;
+  const int64_t r = v / ntx;
+  T.x0 = (int)(v % ntx) * HT_X;
+  T.y0 = (int)(r % nty) * HT_Y;
+  T.z0 = (int)(r / nty) * HT_Z;
+  T.wx = min(HT_X, P.nx - T.x0);
+  T.wy = min(HT_Y, P.ny - T.y0);
+  T.wz = min(HT_Z, P.nz - T.z0);
+  return T;
+}
+
+static dim3 home_tile_grid(const LbmDev &P) {
+  const int64_t nt = (int64_t)((P.nx + HT_X - 1) / HT_X) * ((P.ny + HT_Y - 1) / HT_Y) * ((P.nz + HT_Z - 1) / HT_Z);
+  return dim3((unsigned)(((nt + N_XCD - 1) / N_XCD) * N_XCD));
+}
+
+// Shared terms of f_q - w_q = w_q (drho + (1 + drho) s_q):
+//   c = +-e_a:                 s = E_a +- O_a
+//   c = sa e_a + sb e_b:       s = K + sa sb C + sa A + sb B   (pair ab, d the third axis)
+//   c = 0:                     s = -3/2 tr S
+// with a3_AB = u_B (S_AA - 2 u_A^2) + 2 S_AB u_A,
+//   E_a = 3 S_aa - 3/2 (S_bb + S_dd),
+//   O_a = 3 u_a - 9/2 [u_a (S_bb + S_dd - 2 u_b^2 - 2 u_d^2) + 2 (S_ab u_b + S_ad u_d)],
+//   K = 3 (S_aa + S_bb) - 3/2 S_dd,  C = 9 S_ab,
+//   A = 3 u_a + 9 a3_ba - 9/2 a3_da,  B = 3 u_b + 9 a3_ab - 9/2 a3_db;
+// the pairs keep K + C, K - C, A + B and A - B for their four sign cases.
+struct HomeTerms {
+  float s0;
+  float E[3], O[3];                    // axes x, y, z
+  float P1[3], P2[3], ApB[3], AmB[3];  // pairs xy, xz, yz
+  float wr[3], wd[3];                  // w (1 + drho), w drho for |c|^2 = 0, 1, 2
+};
+
+__device__ __forceinline__ HomeTerms home_terms(const Mom &M) {
+  const float *u = M.u, *S = M.S;
+  float uu[3], D[3], p[3][3], a3[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uu[a] = u[a] * u[a];
+    D[a] = S[a] - 2.f * uu[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (a == b) continue;
+      p[a][b] = S[sidx(a, b)] * u[a];
+      a3[a][b] = fmaf(u[b], D[a], 2.f * p[a][b]);
+    }
+  HomeTerms H;
+  H.s0 = -1.5f * (S[0] + S[1] + S[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, d = (a + 2) % 3;
+    const float T = S[b] + S[d];
+    const float X = T - 2.f * (uu[b] + uu[d]);
+    const float Z = fmaf(u[a], X, 2.f * (p[b][a] + p[d][a]));
+    H.E[a] = 3.f * S[a] - 1.5f * T;
+    H.O[a] = 3.f * u[a] - 4.5f * Z;
+  }
+  constexpr int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2}, PD[3] = {2, 1, 0};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a = PA[e], b = PB[e], d = PD[e];
+    const float K = 3.f * (S[a] + S[b]) - 1.5f * S[d];
+    const float C = 9.f * S[sidx(a, b)];
+    const float A = 3.f * u[a] + (9.f * a3[b][a] - 4.5f * a3[d][a]);
+    const float B = 3.f * u[b] + (9.f * a3[a][b] - 4.5f * a3[d][b]);
+    H.P1[e] = K + C;
+    H.P2[e] = K - C;
+    H.ApB[e] = A + B;
+    H.AmB[e] = A - B;
+  }
+  const float r = 1.f + M.drho;
+  constexpr float W[3] = {1.f / 3.f, 1.f / 18.f, 1.f / 36.f};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    H.wr[c] = W[c] * r;
+    H.wd[c] = W[c] * M.drho;
+  }
+  return H;
+}
+
+// f_Q - w_Q from the shared terms
+template <int Q>
+__device__ __forceinline__ float home_pop_t(const HomeTerms &H) {
+  constexpr int c0 = LC[Q][0], c1 = LC[Q][1], c2 = LC[Q][2];
+  constexpr int n = (c0 != 0) + (c1 != 0) + (c2 != 0);
+  float s;
+  if constexpr (n == 0) {
+    s = H.s0;
+  } else if constexpr (n == 1) {
+    constexpr int a = c0 != 0 ? 0 : (c1 != 0 ? 1 : 2);
+    s = LC[Q][a] > 0 ? H.E[a] + H.O[a] : H.E[a] - H.O[a];
+  } else {
+    constexpr int e = c2 == 0 ? 0 : (c1 == 0 ? 1 : 2);
+    constexpr int a = e == 2 ? 1 : 0, b = e == 0 ? 1 : 2;
+    constexpr int sa = LC[Q][a], sb = LC[Q][b];
+    if constexpr (sa == sb) s = sa > 0 ? H.P1[e] + H.ApB[e] : H.P1[e] - H.ApB[e];
+    else s = sa > 0 ? H.P2[e] + H.AmB[e] : H.P2[e] - H.AmB[e];
+  }
+  return fmaf(H.wr[n], s, H.wd[n]);
+}
+
+// Population Q of a tile node into the slot of the node at +c_Q when that is
+// in the tile (ok: the three per-axis tests, taken once per node); an
+// outlet-face node (outx) also fills, for c_x < 0, the slot of the
+// outlet-face node at +(0, c_y, c_z), whose pull the outlet clamps to here.
+template <int Q>
+__device__ __forceinline__ void home_push_in(float (*s_pop)[HT_N], int l, const bool okx[3], const bool oky[3],
+                                             const bool okz[3], bool outx, float v) {
+  constexpr int cx = LC[Q][0], cy = LC[Q][1], cz = LC[Q][2];
+  constexpr int off = cx + HT_X * (cy + HT_Y * cz);
+  const bool yz = oky[cy + 1] && okz[cz + 1];
+  if (yz && okx[cx + 1]) s_pop[Q - 1][l + off] = v;
+  if constexpr (cx < 0) {
+    if (outx && yz) s_pop[Q - 1][l + off - cx] = v;
+  }
+}
+
+// The same for a halo node at tile position (sx, sy, sz)
+template <int Q>
+__device__ __forceinline__ void home_push_halo(float (*s_pop)[HT_N], const HomeTile &T, int sx, int sy, int sz,
+                                               bool outx, const HomeTerms &H) {
+  constexpr int cx = LC[Q][0], cy = LC[Q][1], cz = LC[Q][2];
+  const int dx = sx + cx, dy = sy + cy, dz = sz + cz;
+  const bool yz = (unsigned)dy < (unsigned)T.wy && (unsigned)dz < (unsigned)T.wz;
+  const int dl = dx + HT_X * (dy + HT_Y * dz);
+  const float v = home_pop_t<Q>(H);
+  if (yz && (unsigned)dx < (unsigned)T.wx) s_pop[Q - 1][dl] = v;
+  if constexpr (cx < 0) {
+    if (outx && yz && (unsigned)sx < (unsigned)T.wx) s_pop[Q - 1][dl - cx] = v;
+  }
+}
+
+template <int... Qs>
+__device__ __forceinline__ void home_push_halo_set(float (*s_pop)[HT_N], const HomeTile &T, int sx, int sy, int sz,
+                                                   bool outx, const Mom &M) {
+  const HomeTerms H = home_terms(M);  // only the terms these directions use survive
+  (home_push_halo<Qs>(s_pop, T, sx, sy, sz, outx, H), ...);
+}
+
+// Lattice coordinate of tile offset o on an axis of n nodes: wrapped on a
+// periodic axis, false where there is no node.
+__device__ __forceinline__ bool home_wrap(int &x, int n, bool periodic) {
+  if (periodic) x = x < 0 ? x + n : (x >= n ? x - n : x);
+  return (unsigned)x < (unsigned)n;
+}
+
+// One halo node (h-th of the tile's list: the y faces, z faces, x faces,
+// then the yz, xy and xz edges; an edge node feeds one population).  FULL:
+// the tile lies wholly inside the lattice, so its extents are the constants.
+template <bool SOL, bool FULL>
+__device__ __forceinline__ void home_halo_node(const LbmDev &P, const HomeTile &T, const float *__restrict__ min,
+                                               const uint8_t (*s_sol)[HT_SY][HT_SX], bool any, float (*s_pop)[HT_N],
+                                               int h) {
+  const int wx = FULL ? HT_X : T.wx, wy = FULL ? HT_Y : T.wy, wz = FULL ? HT_Z : T.wz;
+  const int nA = wz * wx, nB = wy * wx, nC = wz * wy;
+  int e = h, hx, hy, hz, kind;
+  if (e < 2 * nA) {
+    const int side = e >= nA;
+    e -= side * nA;
+    hx = e % wx, hz = e / wx, hy = side ? wy : -1, kind = side;
+  } else if ((e -= 2 * nA) < 2 * nB) {
+    const int side = e >= nB;
+    e -= side * nB;
+    hx = e % wx, hy = e / wx, hz = side ? wz : -1, kind = 2 + side;
+  } else if ((e -= 2 * nB) < 2 * nC) {
+    const int side = e >= nC;
+    e -= side * nC;
+    hy = e % wy, hz = e / wy, hx = side ? wx : -1, kind = 4 + side;
+  } else if ((e -= 2 * nC) < 4 * wx) {
+    const int c = e / wx;
+    hx = e % wx, hy = (c & 1) ? wy : -1, hz = (c & 2) ? wz : -1, kind = 6 + c;
+  } else if ((e -= 4 * wx) < 4 * wz) {
+    const int c = e / wz;
+    hz = e % wz, hx = (c & 1) ? wx : -1, hy = (c & 2) ? wy : -1, kind = 10 + c;
+  } else {
+    e -= 4 * wz;
+    const int c = e / wy;
+    hy = e % wy, hx = (c & 1) ? wx : -1, hz = (c & 2) ? wz : -1, kind = 14 + c;
+  }
+  int x = T.x0 + hx, y = T.y0 + hy, z = T.z0 + hz;
+  if (!home_wrap(x, P.nx, P.bc[0] == DW_BC_PERIODIC) || !home_wrap(y, P.ny, P.bc[2] == DW_BC_PERIODIC) ||
+      !home_wrap(z, P.nz, P.bc[4] == DW_BC_PERIODIC))
+    return;  // no node there: the face rules of the pull decide
+  if (SOL && any && s_sol[hz + 1][hy + 1][hx + 1] != 0) return;  // pulls from a solid node bounce
+  const uint32_t node = (uint32_t)x + (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
+  const Mom M = load_mom_at(min, P.L, node);
+  const bool outx = x == P.nx - 1 && P.bc[1] == DW_BC_OUTLET;
+  switch (kind) {
+    case 0: home_push_halo_set<3, 7, 11, 14, 17>(s_pop, T, hx, hy, hz, outx, M); break;   // y- face: c_y = +1
+    case 1: home_push_halo_set<4, 8, 12, 13, 18>(s_pop, T, hx, hy, hz, outx, M); break;   // y+ face: c_y = -1
+    case 2: home_push_halo_set<5, 9, 11, 16, 18>(s_pop, T, hx, hy, hz, outx, M); break;   // z- face: c_z = +1
+    case 3: home_push_halo_set<6, 10, 12, 15, 17>(s_pop, T, hx, hy, hz, outx, M); break;  // z+ face: c_z = -1
+    case 4: home_push_halo_set<1, 7, 9, 13, 15>(s_pop, T, hx, hy, hz, outx, M); break;    // x- face: c_x = +1
+    case 5: home_push_halo_set<2, 8, 10, 14, 16>(s_pop, T, hx, hy, hz, outx, M); break;   // x+ face: c_x = -1
+    case 6: home_push_halo_set<11>(s_pop, T, hx, hy, hz, outx, M); break;                 // yz edges
+    case 7: home_push_halo_set<18>(s_pop, T, hx, hy, hz, outx, M); break;
+    case 8: home_push_halo_set<17>(s_pop, T, hx, hy, hz, outx, M); break;
+    case 9: home_push_halo_set<12>(s_pop, T, hx, hy, hz, outx, M); break;
+    case 10: home_push_halo_set<7>(s_pop, T, hx, hy, hz, outx, M); break;                 // xy edges
+    case 11: home_push_halo_set<14>(s_pop, T, hx, hy, hz, outx, M); break;
+    case 12: home_push_halo_set<13>(s_pop, T, hx, hy, hz, outx, M); break;
+    case 13: home_push_halo_set<8>(s_pop, T, hx, hy, hz, outx, M); break;
+    case 14: home_push_halo_set<9>(s_pop, T, hx, hy, hz, outx, M); break;                 // xz edges
+    case 15: home_push_halo_set<16>(s_pop, T, hx, hy, hz, outx, M); break;
+    case 16: home_push_halo_set<15>(s_pop, T, hx, hy, hz, outx, M); break;
+    default: home_push_halo_set<10>(s_pop, T, hx, hy, hz, outx, M); break;
+  }
+}
+
+// Where the pulls of a node leave the lattice: the node sits on a
+// non-periodic face (lo: the source is beyond the low face of the axis).
+struct HomeFaces {
+  bool lo[3], hi[3];
+};
+
+// Population Q pulled by the tile node at (tx, ty, tz): from its slot, or its
+// own population opp(Q) on bounce-back, or the staged inlet population.  The
+// source rules are those of the population step: a y / z face of the node
+// that the pull crosses bounces it; an x face bounces it, feeds the inlet,
+// or (outlet) clamps its source onto the outlet face of the source row.
+template <int Q, bool SOL>
+__device__ __forceinline__ float home_take(const LbmDev &P, const float (*s_pop)[HT_N],
+                                           const uint8_t (*s_sol)[HT_SY][HT_SX], const float (*s_inl)[5],
+                                           bool inlet_tile, const HomeFaces &F, int l, int tx, int ty, int tz,
+                                           const float f[19]) {
+  if constexpr (Q == 0) {
+    return f[0];
+  } else {
+    constexpr int R = LOPP[Q], CX = LC[Q][0], CY = LC[Q][1], CZ = LC[Q][2];
+    bool yz = false;
+    if constexpr (CY != 0) yz = CY > 0 ? F.lo[1] : F.hi[1];
+    if constexpr (CZ != 0) yz = yz || (CZ > 0 ? F.lo[2] : F.hi[2]);
+    bool xo = false;
+    if constexpr (CX != 0) xo = CX > 0 ? F.lo[0] : F.hi[0];
+    const int xrule = P.bc[CX > 0 ? 0 : 1];
+    float g = s_pop[Q - 1][l];
+    // an opaque register value: otherwise the selects below become one load
+    // from a selected address, which sends f to private memory
+    asm("" : "+v"(g));
+    bool bb = yz || (xo && xrule == DW_BC_BOUNCEBACK);
+    if constexpr (SOL) {
+      const int sx = xo ? tx : tx - CX;  // an outlet clamps the source onto the face
+      bb = bb || s_sol[tz + 1 - CZ][ty + 1 - CY][sx + 1] != 0;
+    }
+    g = bb ? f[R] : g;
+    if constexpr (inlet_slot(Q) >= 0) {
+      if (inlet_tile) g = (xo && !yz && xrule == DW_BC_INLET) ? s_inl[ty + HT_Y * tz][inlet_slot(Q)] : g;
+    }
+    return g;
+  }
+}
+
+template <bool SOL, int... Qs>
+__device__ __forceinline__ void home_take_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
+                                              const float (*s_pop)[HT_N], const uint8_t (*s_sol)[HT_SY][HT_SX],
+                                              const float (*s_inl)[5], bool inlet_tile, const HomeFaces &F, int l,
+                                              int tx, int ty, int tz, const float f[19], float g[19]) {
+  ((g[Qs] = home_take<Qs, SOL>(P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty, tz, f)), ...);
+}
+
+// Moments of the pulled set from the sums and differences of opposite
+// populations (pairs q, q + 1 for odd q).
+__device__ __forceinline__ MomAcc home_pulled_moments(const float g[19]) {
+  float sp[19], dp[19];
+#pragma unroll
+  for (int q = 1; q < 19; q += 2) {
+    sp[q] = g[q] + g[q + 1];
+    dp[q] = g[q] - g[q + 1];
+  }
+  MomAcc A;
+  A.drho = g[0] + sp[1] + sp[3] + sp[5] + sp[7] + sp[9] + sp[11] + sp[13] + sp[15] + sp[17];
+  A.j[0] = dp[1] + dp[7] + dp[9] + dp[13] + dp[15];
+  A.j[1] = dp[3] + dp[7] + dp[11] - dp[13] + dp[17];
+  A.j[2] = dp[5] + dp[9] + dp[11] - dp[15] - dp[17];
+  const float d3 = A.drho * (1.f / 3.f);
+  A.P[0] = (sp[1] + sp[7] + sp[9] + sp[13] + sp[15]) - d3;
+  A.P[1] = (sp[3] + sp[7] + sp[11] + sp[13] + sp[17]) - d3;
+  A.P[2] = (sp[5] + sp[9] + sp[11] + sp[15] + sp[17]) - d3;
+  A.P[3] = sp[7] - sp[13];
+  A.P[4] = sp[9] - sp[15];
+  A.P[5] = sp[11] - sp[17];
+  return A;
+}
+
+template <int... Qs>
+__device__ __forceinline__ void home_push_all(std::integer_sequence<int, Qs...>, float (*s_pop)[HT_N], int l,
+                                              const bool okx[3], const bool oky[3], const bool okz[3], bool outx,
+                                              const float f[19]) {
+  (home_push_in<Qs + 1>(s_pop, l, okx, oky, okz, outx, f[Qs + 1]), ...);
+}
+
+template <int... Qs>
+__device__ __forceinline__ void home_pops_all(std::integer_sequence<int, Qs...>, const HomeTerms &H, float f[19]) {
+  ((f[Qs] = home_pop_t<Qs>(H)), ...);
+}
+
+// The pulled set's moments of the tile node of this thread (false for a
+// thread outside the lattice, which has nothing more to do); every thread of
+// the workgroup calls it (it has barriers).
+template <bool SOLID>
+__device__ __forceinline__ bool home_tile_pulled(const LbmDev &P, const HomeTile &T, const float *__restrict__ min,
+                                                 const uint8_t *__restrict__ solid, float (*s_pop)[HT_N],
+                                                 uint8_t (*s_sol)[HT_SY][HT_SX], float (*s_inl)[5], MomAcc &A,
+                                                 uint32_t &node, bool &solid_node) {
+  const int tid = threadIdx.x;
+  const int tx = tid % HT_X, ty = (tid / HT_X) % HT_Y, tz = tid / (HT_X * HT_Y);
+  const bool active = tx < T.wx && ty < T.wy && tz < T.wz;
+  const int i = T.x0 + tx, j = T.y0 + ty, k = T.z0 + tz;
+  node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
+  // this node's moments first: their loads overlap the staging and the halo
+  Mom M;
+  if (active) M = load_mom_at(min, P.L, node);
+  // the inlet populations of the tile's rows (tiles at x = 0 of an inlet lattice)
+  const bool inlet_tile = T.x0 == 0 && P.bc[0] == DW_BC_INLET;
+  if (inlet_tile && tid < 5 * HT_Y * HT_Z) {
+    const int row = tid / 5, ry = row % HT_Y, rz = row / HT_Y;
+    if (ry < T.wy && rz < T.wz) s_inl[row][tid % 5] = home_inlet_pop(P, tid % 5, T.y0 + ry, T.z0 + rz);
+  }
+  // solid flags of the tile and its halo, one staged row of HT_SX bytes per
+  // wave and pass (wrapped; 0 where there is no node)
+  bool any = false;
+  if (SOLID) {
+    const int lane = tid & 63;
+    int mine = 0;
+    for (int r = __builtin_amdgcn_readfirstlane(tid >> 6); r < HT_SY * HT_SZ; r += HT_N / 64) {
+      const int ly = r % HT_SY, lz = r / HT_SY;
+      int y = T.y0 + ly - 1, z = T.z0 + lz - 1;
+      const bool row_ok = ly <= T.wy + 1 && lz <= T.wz + 1 && home_wrap(y, P.ny, P.bc[2] == DW_BC_PERIODIC) &&
+                          home_wrap(z, P.nz, P.bc[4] == DW_BC_PERIODIC);
+      if (lane < HT_SX) {
+        int x = T.x0 + lane - 1;
+        uint8_t v = 0;
+        if (row_ok && lane <= T.wx + 1 && home_wrap(x, P.nx, P.bc[0] == DW_BC_PERIODIC))
+          v = solid[(uint32_t)x + (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z)];
+        s_sol[lz][ly][lane] = v;
+        mine |= v;
+      }
+    }
+    any = __syncthreads_or(mine) != 0;
+  }
+  // halo populations that stream into the tile
+  const bool full = T.wx == HT_X && T.wy == HT_Y && T.wz == HT_Z;  // block-uniform
+  const int nh = 2 * (T.wz * T.wx + T.wy * T.wx + T.wz * T.wy) + 4 * (T.wx + T.wy + T.wz);
+  if (full)
+    for (int h = tid; h < nh; h += HT_N) home_halo_node<SOLID, true>(P, T, min, s_sol, any, s_pop, h);
+  else
+    for (int h = tid; h < nh; h += HT_N) home_halo_node<SOLID, false>(P, T, min, s_sol, any, s_pop, h);
+  // this node's populations, pushed to the nodes that pull them
+  const int l = tid;
+  float f[19];
+  solid_node = false;
+  if (active) {
+    home_pops_all(std::make_integer_sequence<int, 19>{}, home_terms(M), f);
+    solid_node = SOLID && any && s_sol[tz + 1][ty + 1][tx + 1] != 0;
+    if (!solid_node) {
+      const bool okx[3] = {tx >= 1, true, tx + 1 < T.wx}, oky[3] = {ty >= 1, true, ty + 1 < T.wy},
+                 okz[3] = {tz >= 1, true, tz + 1 < T.wz};
+      const bool outx = i == P.nx - 1 && P.bc[1] == DW_BC_OUTLET;
+      home_push_all(std::make_integer_sequence<int, 18>{}, s_pop, l, okx, oky, okz, outx, f);
+    }
+  }
+  __syncthreads();
+  if (!active) return false;
+  HomeFaces F;
+  F.lo[0] = i == 0 && P.bc[0] != DW_BC_PERIODIC;
+  F.hi[0] = i == P.nx - 1 && P.bc[1] != DW_BC_PERIODIC;
+  F.lo[1] = j == 0 && P.bc[2] != DW_BC_PERIODIC;
+  F.hi[1] = j == P.ny - 1 && P.bc[3] != DW_BC_PERIODIC;
+  F.lo[2] = k == 0 && P.bc[4] != DW_BC_PERIODIC;
+  F.hi[2] = k == P.nz - 1 && P.bc[5] != DW_BC_PERIODIC;
+  float g[19];
+  if (any)
+    home_take_all<true>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty, tz,
+                        f, g);
+  else
+    home_take_all<false>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty,
+                         tz, f, g);
+  A = home_pulled_moments(g);
+  return true;
+}
+
+// 8 waves per SIMD (some scalar registers spill to vector lanes): four
+// tiles per CU, the 128 x 64 x 64 lattice's 1024 tiles in one round.
+template <bool SOLID>
+__global__ __launch_bounds__(HT_N) __attribute__((amdgpu_waves_per_eu(8))) void k_home_tile(
+    LbmDev P, const float *__restrict__ min, float *__restrict__ mout, const uint8_t *__restrict__ solid,
+    float *__restrict__ rho_out, float *__restrict__ u_out) {
+  __shared__ float s_pop[18][HT_N];
+  __shared__ uint8_t s_sol[HT_SZ][HT_SY][HT_SX];
+  __shared__ float s_inl[HT_Y * HT_Z][5];
+  const HomeTile T = home_tile(P);
+  if (!T.live) return;  // block-uniform: padding blocks of the last XCD
+  if (threadIdx.x == 0 && T.x0 == 0 && T.y0 == 0 && T.z0 == 0 && P.t_out) *P.t_out = (P.t_in ? *P.t_in : P.t) + 1;
+  MomAcc A;
+  uint32_t node;
+  bool solid_node;
+  if (!home_tile_pulled<SOLID>(P, T, min, solid, s_pop, s_sol, s_inl, A, node, solid_node)) return;
+  home_collide_store(P, A, mout, rho_out, u_out, node, solid_node);
+}
+
 // equilibrium moments (rho, u, S = u u) from rho [L] and u [3][L] (either
 // may be absent: rho = 1, u = the inflow velocity)
 __global__ __launch_bounds__(256) void k_home_equilibrium(LbmDev P, const float *__restrict__ rho_in,
@@ -754,8 +1105,8 @@ __global__ __launch_bounds__(256) void k_home_equilibrium(LbmDev P, const float 
 }
 
 // ------------------------------------------------------- HOME-LBM reverse
-// Reverse of k_home_step in two passes, neither with atomics.
-//  1. k_home_adj_pull, per node: recompute the pulled set's moments, take
+// Reverse of k_home_tile in two passes, neither with atomics.
+//  1. k_home_tile_adj, per node: recompute the pulled set's moments, take
 //     the adjoints of the stored moments (and of the reported u*) back
 //     through the moment collision, and write the adjoint of each of the 19
 //     pulled populations to gbar [19][L] (zeros at a solid node: its stored
@@ -772,7 +1123,7 @@ struct PopBar {
 };
 
 // adjoints of the pulled set's moments from those of the stored moments
-// (mb) and of the reported u* (ubo), through the collision of k_home_step
+// (mb) and of the reported u* (ubo), through the collision of k_home_tile
 __device__ __forceinline__ PopBar home_collision_adj(const LbmDev &P, const MomAcc &A, const float mb[HM_N],
                                                      const float ubo[3]) {
   const float rho = 1.f + A.drho, ir = 1.f / rho;
@@ -872,31 +1223,18 @@ __device__ __forceinline__ bool stage_solid(const LbmDev &P, const uint8_t *__re
 }
 
 template <bool SOLID>
-__global__ __launch_bounds__(LBM_BLOCK) void k_home_adj_pull(LbmDev P, const float *__restrict__ min,
-                                                             const uint8_t *__restrict__ solid,
-                                                             const float *__restrict__ mout_bar,
-                                                             const float *__restrict__ ubar_out,
-                                                             float *__restrict__ gbar) {
-  __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
-  __shared__ int s_any[LBM_BLOCK / 64];
-  __shared__ float s_inl[5];
-  const RowBlock rb = xcd_row_block(P);
-  if (!rb.live) return;  // block-uniform
-  const int x0 = rb.x0;
-  const int i = x0 + threadIdx.x, j = rb.j, k = rb.k;
-  const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
-  const bool inlet_row = x0 == 0 && P.bc[0] == DW_BC_INLET;
-  if (inlet_row && threadIdx.x < 5) s_inl[threadIdx.x] = home_inlet_pop(P, threadIdx.x, j, k);
-  bool any = false;
-  if (SOLID) any = stage_solid(P, solid, x0, j, k, s_sol, s_any);
-  else if (inlet_row) __syncthreads();
-  if (i >= P.nx) return;
-  const bool solid_node = any && s_sol[4][i - x0 + 4] != 0;
-  const bool inlet_wave = inlet_row && threadIdx.x < 64;  // wave-uniform
-  const Mom own = load_mom_at(min, P.L, node);
+__global__ __launch_bounds__(HT_N) __attribute__((amdgpu_waves_per_eu(8))) void k_home_tile_adj(
+    LbmDev P, const float *__restrict__ min, const uint8_t *__restrict__ solid, const float *__restrict__ mout_bar,
+    const float *__restrict__ ubar_out, float *__restrict__ gbar) {
+  __shared__ float s_pop[18][HT_N];
+  __shared__ uint8_t s_sol[HT_SZ][HT_SY][HT_SX];
+  __shared__ float s_inl[HT_Y * HT_Z][5];
+  const HomeTile T = home_tile(P);
+  if (!T.live) return;  // block-uniform: padding blocks of the last XCD
   MomAcc A;
-  if (any) home_row_all<1>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
-  else home_row_all<0>(std::make_integer_sequence<int, 19>{}, P, min, s_sol, s_inl, inlet_wave, i, j, k, x0, own, A);
+  uint32_t node;
+  bool solid_node;
+  if (!home_tile_pulled<SOLID>(P, T, min, solid, s_pop, s_sol, s_inl, A, node, solid_node)) return;
   float mb[HM_N], ubo[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int q = 0; q < HM_N; ++q) mb[q] = ld_node(mout_bar + (size_t)q * P.L, node);
@@ -1314,10 +1652,10 @@ extern "C" int lbm_home_step(const dw_lattice *lat, const dw_lbm_params *params,
   DW_REQUIRE(m_in && m_out, DW_EINVAL, "lbm_home_step: m_in / m_out is NULL");
   DW_REQUIRE(m_in != m_out, DW_EINVAL, "lbm_home_step: m_in and m_out must not alias");
   if (solid)
-    hipLaunchKernelGGL(k_home_step<true>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, m_in, m_out,
+    hipLaunchKernelGGL(k_home_tile<true>, home_tile_grid(P), dim3(HT_N), 0, (hipStream_t)stream, P, m_in, m_out,
                        solid, rho_out, u_out);
   else
-    hipLaunchKernelGGL(k_home_step<false>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, (hipStream_t)stream, P, m_in, m_out,
+    hipLaunchKernelGGL(k_home_tile<false>, home_tile_grid(P), dim3(HT_N), 0, (hipStream_t)stream, P, m_in, m_out,
                        solid, rho_out, u_out);
   return check_launch("lbm_home_step");
 }
@@ -1348,12 +1686,12 @@ extern "C" int lbm_home_step_adj(const dw_lattice *lat, const dw_lbm_params *par
              "lbm_home_step_adj: work must not alias another argument");
   hipStream_t s = (hipStream_t)stream;
   if (solid) {
-    hipLaunchKernelGGL(k_home_adj_pull<true>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, m_out_bar,
+    hipLaunchKernelGGL(k_home_tile_adj<true>, home_tile_grid(P), dim3(HT_N), 0, s, P, m_in, solid, m_out_bar,
                        u_out_bar, work);
     hipLaunchKernelGGL((k_adj_gather<true, true>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
                        m_in_bar);
   } else {
-    hipLaunchKernelGGL(k_home_adj_pull<false>, xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, m_out_bar,
+    hipLaunchKernelGGL(k_home_tile_adj<false>, home_tile_grid(P), dim3(HT_N), 0, s, P, m_in, solid, m_out_bar,
                        u_out_bar, work);
     hipLaunchKernelGGL((k_adj_gather<false, true>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, m_in, solid, work,
                        m_in_bar);
