@@ -663,7 +663,7 @@ __device__ __forceinline__ void home_collide_store(const LbmDev &P, const MomAcc
 // row.  After a barrier each node takes its populations from its slots,
 // except where the pull bounces back (its own population of the opposite
 // direction, still in registers) or comes from the inlet (staged per row).
-constexpr int HT_X = 32, HT_Y = 4, HT_Z = 4, HT_N = HT_X * HT_Y * HT_Z;
+constexpr int HT_X = 32, HT_Y = 8, HT_Z = 4, HT_N = HT_X * HT_Y * HT_Z;
 constexpr int HT_SX = HT_X + 2, HT_SY = HT_Y + 2, HT_SZ = HT_Z + 2;
 
 struct HomeTile {
@@ -830,48 +830,67 @@ __device__ __forceinline__ bool home_wrap(int &x, int n, bool periodic) {
   return (unsigned)x < (unsigned)n;
 }
 
-// One halo node (h-th of the tile's list: the y faces, z faces, x faces,
-// then the yz, xy and xz edges; an edge node feeds one population).  FULL:
-// the tile lies wholly inside the lattice, so its extents are the constants.
-template <bool SOL, bool FULL>
-__device__ __forceinline__ void home_halo_node(const LbmDev &P, const HomeTile &T, const float *__restrict__ min,
-                                               const uint8_t (*s_sol)[HT_SY][HT_SX], bool any, float (*s_pop)[HT_N],
-                                               int h) {
+// The halo of a tile: the y faces, z faces, x faces, then the yz, xy and xz
+// edges (an edge node feeds one population); at most one node per thread.
+constexpr int HT_HALO = 2 * (HT_Z * HT_X + HT_Y * HT_X + HT_Z * HT_Y) + 4 * (HT_X + HT_Y + HT_Z);
+static_assert(HT_HALO <= HT_N, "the halo is taken in one pass of the workgroup");
+
+struct HaloNode {
+  int hx, hy, hz, kind;  // tile position and which populations it feeds
+  int x;                 // lattice x (wrapped)
+  uint32_t node;
+  bool live;             // a node exists there (wrapped on a periodic axis)
+};
+
+// The h-th halo node.  FULL: the tile lies wholly inside the lattice, so its
+// extents are the constants.
+template <bool FULL>
+__device__ __forceinline__ HaloNode home_halo_at(const LbmDev &P, const HomeTile &T, int h) {
   const int wx = FULL ? HT_X : T.wx, wy = FULL ? HT_Y : T.wy, wz = FULL ? HT_Z : T.wz;
   const int nA = wz * wx, nB = wy * wx, nC = wz * wy;
-  int e = h, hx, hy, hz, kind;
+  int e = h;
+  HaloNode H;
   if (e < 2 * nA) {
     const int side = e >= nA;
     e -= side * nA;
-    hx = e % wx, hz = e / wx, hy = side ? wy : -1, kind = side;
+    H.hx = e % wx, H.hz = e / wx, H.hy = side ? wy : -1, H.kind = side;
   } else if ((e -= 2 * nA) < 2 * nB) {
     const int side = e >= nB;
     e -= side * nB;
-    hx = e % wx, hy = e / wx, hz = side ? wz : -1, kind = 2 + side;
+    H.hx = e % wx, H.hy = e / wx, H.hz = side ? wz : -1, H.kind = 2 + side;
   } else if ((e -= 2 * nB) < 2 * nC) {
     const int side = e >= nC;
     e -= side * nC;
-    hy = e % wy, hz = e / wy, hx = side ? wx : -1, kind = 4 + side;
+    H.hy = e % wy, H.hz = e / wy, H.hx = side ? wx : -1, H.kind = 4 + side;
   } else if ((e -= 2 * nC) < 4 * wx) {
     const int c = e / wx;
-    hx = e % wx, hy = (c & 1) ? wy : -1, hz = (c & 2) ? wz : -1, kind = 6 + c;
+    H.hx = e % wx, H.hy = (c & 1) ? wy : -1, H.hz = (c & 2) ? wz : -1, H.kind = 6 + c;
   } else if ((e -= 4 * wx) < 4 * wz) {
     const int c = e / wz;
-    hz = e % wz, hx = (c & 1) ? wx : -1, hy = (c & 2) ? wy : -1, kind = 10 + c;
+    H.hz = e % wz, H.hx = (c & 1) ? wx : -1, H.hy = (c & 2) ? wy : -1, H.kind = 10 + c;
   } else {
     e -= 4 * wz;
     const int c = e / wy;
-    hy = e % wy, hx = (c & 1) ? wx : -1, hz = (c & 2) ? wz : -1, kind = 14 + c;
+    H.hy = e % wy, H.hx = (c & 1) ? wx : -1, H.hz = (c & 2) ? wz : -1, H.kind = 14 + c;
   }
-  int x = T.x0 + hx, y = T.y0 + hy, z = T.z0 + hz;
-  if (!home_wrap(x, P.nx, P.bc[0] == DW_BC_PERIODIC) || !home_wrap(y, P.ny, P.bc[2] == DW_BC_PERIODIC) ||
-      !home_wrap(z, P.nz, P.bc[4] == DW_BC_PERIODIC))
-    return;  // no node there: the face rules of the pull decide
-  if (SOL && any && s_sol[hz + 1][hy + 1][hx + 1] != 0) return;  // pulls from a solid node bounce
-  const uint32_t node = (uint32_t)x + (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
-  const Mom M = load_mom_at(min, P.L, node);
-  const bool outx = x == P.nx - 1 && P.bc[1] == DW_BC_OUTLET;
-  switch (kind) {
+  int x = T.x0 + H.hx, y = T.y0 + H.hy, z = T.z0 + H.hz;
+  H.live = home_wrap(x, P.nx, P.bc[0] == DW_BC_PERIODIC) && home_wrap(y, P.ny, P.bc[2] == DW_BC_PERIODIC) &&
+           home_wrap(z, P.nz, P.bc[4] == DW_BC_PERIODIC);  // else the face rules of the pull decide
+  H.x = x;
+  H.node = (uint32_t)x + (uint32_t)P.nx * ((uint32_t)y + (uint32_t)P.ny * (uint32_t)z);
+  return H;
+}
+
+// The populations a live halo node feeds into the tile (none from a solid
+// node: pulls from it bounce).
+template <bool SOL>
+__device__ __forceinline__ void home_halo_push(const LbmDev &P, const HomeTile &T,
+                                               const uint8_t (*s_sol)[HT_SY][HT_SX], bool any, float (*s_pop)[HT_N],
+                                               const HaloNode &H, const Mom &M) {
+  if (SOL && any && s_sol[H.hz + 1][H.hy + 1][H.hx + 1] != 0) return;
+  const bool outx = H.x == P.nx - 1 && P.bc[1] == DW_BC_OUTLET;
+  const int hx = H.hx, hy = H.hy, hz = H.hz;
+  switch (H.kind) {
     case 0: home_push_halo_set<3, 7, 11, 14, 17>(s_pop, T, hx, hy, hz, outx, M); break;   // y- face: c_y = +1
     case 1: home_push_halo_set<4, 8, 12, 13, 18>(s_pop, T, hx, hy, hz, outx, M); break;   // y+ face: c_y = -1
     case 2: home_push_halo_set<5, 9, 11, 16, 18>(s_pop, T, hx, hy, hz, outx, M); break;   // z- face: c_z = +1
@@ -993,9 +1012,17 @@ __device__ __forceinline__ bool home_tile_pulled(const LbmDev &P, const HomeTile
   const bool active = tx < T.wx && ty < T.wy && tz < T.wz;
   const int i = T.x0 + tx, j = T.y0 + ty, k = T.z0 + tz;
   node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
-  // this node's moments first: their loads overlap the staging and the halo
+  // this node's and this thread's halo node's moments first: their loads
+  // overlap the staging
   Mom M;
   if (active) M = load_mom_at(min, P.L, node);
+  const bool full = T.wx == HT_X && T.wy == HT_Y && T.wz == HT_Z;  // block-uniform
+  const int nh = 2 * (T.wz * T.wx + T.wy * T.wx + T.wz * T.wy) + 4 * (T.wx + T.wy + T.wz);
+  HaloNode H;
+  H.live = false;
+  if (tid < nh) H = full ? home_halo_at<true>(P, T, tid) : home_halo_at<false>(P, T, tid);
+  Mom HM;
+  if (H.live) HM = load_mom_at(min, P.L, H.node);
   // the inlet populations of the tile's rows (tiles at x = 0 of an inlet lattice)
   const bool inlet_tile = T.x0 == 0 && P.bc[0] == DW_BC_INLET;
   if (inlet_tile && tid < 5 * HT_Y * HT_Z) {
@@ -1025,12 +1052,7 @@ __device__ __forceinline__ bool home_tile_pulled(const LbmDev &P, const HomeTile
     any = __syncthreads_or(mine) != 0;
   }
   // halo populations that stream into the tile
-  const bool full = T.wx == HT_X && T.wy == HT_Y && T.wz == HT_Z;  // block-uniform
-  const int nh = 2 * (T.wz * T.wx + T.wy * T.wx + T.wz * T.wy) + 4 * (T.wx + T.wy + T.wz);
-  if (full)
-    for (int h = tid; h < nh; h += HT_N) home_halo_node<SOLID, true>(P, T, min, s_sol, any, s_pop, h);
-  else
-    for (int h = tid; h < nh; h += HT_N) home_halo_node<SOLID, false>(P, T, min, s_sol, any, s_pop, h);
+  if (H.live) home_halo_push<SOLID>(P, T, s_sol, any, s_pop, H, HM);
   // this node's populations, pushed to the nodes that pull them
   const int l = tid;
   float f[19];
@@ -1065,8 +1087,8 @@ __device__ __forceinline__ bool home_tile_pulled(const LbmDev &P, const HomeTile
   return true;
 }
 
-// 8 waves per SIMD (some scalar registers spill to vector lanes): four
-// tiles per CU, the 128 x 64 x 64 lattice's 1024 tiles in one round.
+// 8 waves per SIMD (some scalar registers spill to vector lanes): two
+// tiles per CU, the 128 x 64 x 64 lattice's 512 tiles in one round.
 template <bool SOLID>
 __global__ __launch_bounds__(HT_N) __attribute__((amdgpu_waves_per_eu(8))) void k_home_tile(
     LbmDev P, const float *__restrict__ min, float *__restrict__ mout, const uint8_t *__restrict__ solid,

@@ -90,9 +90,9 @@ CASES = {
     # one-node periodic y and z: every neighbour row is the node's own row
     "thin_periodic": dict(dims=(40, 1, 1), bc=(0,) * 6, force=(2e-5, 1e-5, -1e-5), gust=(0.0, 1.0, 0, 0, 0), tau=0.7,
                           solid=(slice(0, 1), slice(0, 1), slice(30, 34))),
-    # solids across the 32 x 4 x 4 tile seams, inlet and outlet in x
+    # solids across the x = 32, y = 8 and z = 4 seams of the 32 x 8 x 4 tiles, inlet and outlet in x
     "tile_seams": dict(dims=(70, 9, 10), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 60.0, 1.0, 1.0, 0.2), tau=0.6,
-                       solid=(slice(3, 6), slice(3, 6), slice(30, 35))),
+                       solid=(slice(3, 6), slice(6, 9), slice(30, 35))),
     # two-node periodic y, bounce-back z, solids on the outlet face across a z seam
     "periodic_ny2": dict(dims=(33, 2, 9), bc=(olbm.INLET, olbm.OUTLET, 0, 0, 1, 1), force=(0.0, 1e-5, 0.0),
                          gust=(0.0, 1.0, 0, 0, 0), tau=0.8, solid=(slice(3, 5), slice(0, 1), slice(31, 33))),
