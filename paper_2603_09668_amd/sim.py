@@ -169,11 +169,14 @@ class CoupledSim:
         fork = torch.cuda.Event()
         fork.record(main)
         side.wait_event(fork)
+        # the particle branch is issued first: in a graph replay the branch
+        # recorded first stays on the launch queue, whose dependent kernels
+        # start back to back, and the shorter wind branch takes the other
+        self.sort()
+        self.p2g()
         with torch.cuda.stream(side):
             self.voxelize()
             self.lbm()
-        self.sort()
-        self.p2g()
         join = torch.cuda.Event()
         join.record(side)
         main.wait_event(join)
