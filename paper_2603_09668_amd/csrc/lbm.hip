@@ -1389,25 +1389,41 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_adj_pull(LbmDev P, const floa
   const float uu = ux * ux + uy * uy + uz * uz;
   const float om = P.omega, kf = 1.0f - 0.5f * om;
   float g[19];
-  float rbar = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    g[q] = ld_node(gout + (size_t)q * P.L, node);
+  for (int q = 0; q < 19; ++q) g[q] = ld_node(gout + (size_t)q * P.L, node);
+  // a direction and its opposite together: with S = g_q + g_o, D = g_q - g_o
+  // (c_o = -c_q) their terms are om w [S (1 + 9/2 (c.u)^2 - 3/2 u.u) + 3 (c.u) D]
+  // for rho and om w rho [c (3 D + 9 (c.u) S) - 3 u S] for u
+  const float e0 = 1.f - 1.5f * uu;
+  float rbar = LW[0] * g[0] * e0, ws = LW[0] * g[0], bx = 0.f, by = 0.f, bz = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+  for (int q = 1; q < 19; q += 2) {
+    const float S = g[q] + g[q + 1], D = g[q] - g[q + 1];
     const float cu = LC[q][0] * ux + LC[q][1] * uy + LC[q][2] * uz;
-    // d feq_q / d rho at fixed u = feq_q / rho
-    rbar += om * g[q] * LW[q] * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
-    // d feq_q / d u = w rho (3 c + 9 (c.u) c - 3 u)
-    const float s = om * g[q] * LW[q] * rho;
-    bx += s * (3.f * LC[q][0] + 9.f * cu * LC[q][0] - 3.f * ux);
-    by += s * (3.f * LC[q][1] + 9.f * cu * LC[q][1] - 3.f * uy);
-    bz += s * (3.f * LC[q][2] + 9.f * cu * LC[q][2] - 3.f * uz);
+    rbar += LW[q] * (S * (e0 + 4.5f * cu * cu) + 3.f * cu * D);
+    ws += LW[q] * S;
+    const float T = LW[q] * (3.f * D + 9.f * cu * S);
+    if (LC[q][0] != 0) bx += LC[q][0] * T;
+    if (LC[q][1] != 0) by += LC[q][1] * T;
+    if (LC[q][2] != 0) bz += LC[q][2] * T;
     if (P.forced) {
       const float cF = LC[q][0] * P.F[0] + LC[q][1] * P.F[1] + LC[q][2] * P.F[2];
-      const float t = kf * g[q] * LW[q];
-      bx += t * (9.f * cF * LC[q][0] - 3.f * P.F[0]);
-      by += t * (9.f * cF * LC[q][1] - 3.f * P.F[1]);
-      bz += t * (9.f * cF * LC[q][2] - 3.f * P.F[2]);
+      const float t = LW[q] * S * 9.f * cF;
+      if (LC[q][0] != 0) fx += LC[q][0] * t;
+      if (LC[q][1] != 0) fy += LC[q][1] * t;
+      if (LC[q][2] != 0) fz += LC[q][2] * t;
     }
+  }
+  rbar *= om;
+  const float orho = om * rho;
+  bx = orho * (bx - 3.f * ux * ws);
+  by = orho * (by - 3.f * uy * ws);
+  bz = orho * (bz - 3.f * uz * ws);
+  if (P.forced) {
+    // kf w S (9 (c.F) c - 3 F), the rest direction included in the F part
+    bx += kf * (fx - 3.f * P.F[0] * ws);
+    by += kf * (fy - 3.f * P.F[1] * ws);
+    bz += kf * (fz - 3.f * P.F[2] * ws);
   }
   if (ubar_out) {
     bx += ld_node(ubar_out, node);
