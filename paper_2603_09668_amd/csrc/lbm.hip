@@ -488,77 +488,222 @@ __host__ __device__ constexpr int sidx(int a, int b) {
   return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
 }
 
-// a3_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b
-template <int A, int B>
-__device__ __forceinline__ float home_a3(const Mom &M) {
-  return M.S[sidx(A, A)] * M.u[B] + 2.f * M.S[sidx(A, B)] * M.u[A] - 2.f * M.u[A] * M.u[A] * M.u[B];
-}
+// The expansion of a node's moments into its populations,
+//   f_q = w_q rho [1 + 3 c.u + 9/2 H2(c):S + 27/2 sum_(a,a,b) (c_a^2 - 1/3) c_b a3_aab],
+// H2(c) = c c - I/3, stored as f_q - w_q.
+// Shared terms of f_q - w_q = w_q (drho + (1 + drho) s_q):
+//   c = +-e_a:                 s = E_a +- O_a
+//   c = sa e_a + sb e_b:       s = K + sa sb C + sa A + sb B   (pair ab, d the third axis)
+//   c = 0:                     s = -3/2 tr S
+// with a3_AB = u_B (S_AA - 2 u_A^2) + 2 S_AB u_A,
+//   E_a = 3 S_aa - 3/2 (S_bb + S_dd),
+//   O_a = 3 u_a - 9/2 [u_a (S_bb + S_dd - 2 u_b^2 - 2 u_d^2) + 2 (S_ab u_b + S_ad u_d)],
+//   K = 3 (S_aa + S_bb) - 3/2 S_dd,  C = 9 S_ab,
+//   A = 3 u_a + 9 a3_ba - 9/2 a3_da,  B = 3 u_b + 9 a3_ab - 9/2 a3_db;
+// the pairs keep K + C, K - C, A + B and A - B for their four sign cases.
+struct HomeTerms {
+  float s0;
+  float E[3], O[3];                    // axes x, y, z
+  float P1[3], P2[3], ApB[3], AmB[3];  // pairs xy, xz, yz
+  float wr[3], wd[3];                  // w (1 + drho), w drho for |c|^2 = 0, 1, 2
+};
 
-// f_q - w_q of the expansion
-//   f_q = w_q rho [1 + 3 c.u + 9/2 H2(c):S + 27/2 sum_(a,a,b) (c_a^2 - 1/3) c_b a3_aab]
-// terms with a zero velocity factor are dropped at compile time
-// the bracket s of f_q = w_q rho [1 + s]
-template <int Q>
-__device__ __forceinline__ float home_series(const Mom &M) {
-  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
-  constexpr float h[3] = {c[0] * c[0] - 1.f / 3.f, c[1] * c[1] - 1.f / 3.f, c[2] * c[2] - 1.f / 3.f};
-  float s = 4.5f * (h[0] * M.S[0] + h[1] * M.S[1] + h[2] * M.S[2]);
-  if constexpr (c[0] != 0) s += 3.f * c[0] * M.u[0];
-  if constexpr (c[1] != 0) s += 3.f * c[1] * M.u[1];
-  if constexpr (c[2] != 0) s += 3.f * c[2] * M.u[2];
-  if constexpr (c[0] * c[1] != 0) s += 9.f * (c[0] * c[1]) * M.S[3];
-  if constexpr (c[0] * c[2] != 0) s += 9.f * (c[0] * c[2]) * M.S[4];
-  if constexpr (c[1] * c[2] != 0) s += 9.f * (c[1] * c[2]) * M.S[5];
-  float t = 0.f;
-  if constexpr (c[1] != 0) t += c[1] * (h[0] * home_a3<0, 1>(M) + h[2] * home_a3<2, 1>(M));
-  if constexpr (c[0] != 0) t += c[0] * (h[1] * home_a3<1, 0>(M) + h[2] * home_a3<2, 0>(M));
-  if constexpr (c[2] != 0) t += c[2] * (h[0] * home_a3<0, 2>(M) + h[1] * home_a3<1, 2>(M));
-  s += 13.5f * t;
-  return s;
-}
-
-template <int Q>
-__device__ __forceinline__ float home_pop(const Mom &M) {
-  return LW[Q] * (M.drho + (1.f + M.drho) * home_series<Q>(M));
-}
-
-// reverse of a3_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b, adjoint ab
-template <int A, int B>
-__device__ __forceinline__ void home_a3_adj(const Mom &M, float ab, Mom &Mb) {
-  Mb.S[sidx(A, A)] += ab * M.u[B];
-  Mb.S[sidx(A, B)] += 2.f * ab * M.u[A];
-  Mb.u[B] += ab * (M.S[sidx(A, A)] - 2.f * M.u[A] * M.u[A]);
-  Mb.u[A] += ab * (2.f * M.S[sidx(A, B)] - 4.f * M.u[A] * M.u[B]);
-}
-
-// reverse of home_pop<Q>: adds pb * d(f_q - w_q)/dM into Mb
-template <int Q>
-__device__ __forceinline__ void home_pop_adj(const Mom &M, float pb, Mom &Mb) {
-  constexpr int c[3] = {LC[Q][0], LC[Q][1], LC[Q][2]};
-  constexpr float h[3] = {c[0] * c[0] - 1.f / 3.f, c[1] * c[1] - 1.f / 3.f, c[2] * c[2] - 1.f / 3.f};
-  Mb.drho += pb * LW[Q] * (1.f + home_series<Q>(M));
-  const float sb = pb * LW[Q] * (1.f + M.drho);
+__device__ __forceinline__ HomeTerms home_terms(const Mom &M) {
+  const float *u = M.u, *S = M.S;
+  float uu[3], D[3], p[3][3], a3[3][3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) Mb.S[a] += 4.5f * h[a] * sb;
-  if constexpr (c[0] != 0) Mb.u[0] += 3.f * c[0] * sb;
-  if constexpr (c[1] != 0) Mb.u[1] += 3.f * c[1] * sb;
-  if constexpr (c[2] != 0) Mb.u[2] += 3.f * c[2] * sb;
-  if constexpr (c[0] * c[1] != 0) Mb.S[3] += 9.f * (c[0] * c[1]) * sb;
-  if constexpr (c[0] * c[2] != 0) Mb.S[4] += 9.f * (c[0] * c[2]) * sb;
-  if constexpr (c[1] * c[2] != 0) Mb.S[5] += 9.f * (c[1] * c[2]) * sb;
-  const float tb = 13.5f * sb;
-  if constexpr (c[1] != 0) {
-    home_a3_adj<0, 1>(M, tb * c[1] * h[0], Mb);
-    home_a3_adj<2, 1>(M, tb * c[1] * h[2], Mb);
+  for (int a = 0; a < 3; ++a) {
+    uu[a] = u[a] * u[a];
+    D[a] = S[a] - 2.f * uu[a];
   }
-  if constexpr (c[0] != 0) {
-    home_a3_adj<1, 0>(M, tb * c[0] * h[1], Mb);
-    home_a3_adj<2, 0>(M, tb * c[0] * h[2], Mb);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (a == b) continue;
+      p[a][b] = S[sidx(a, b)] * u[a];
+      a3[a][b] = fmaf(u[b], D[a], 2.f * p[a][b]);
+    }
+  HomeTerms H;
+  H.s0 = -1.5f * (S[0] + S[1] + S[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, d = (a + 2) % 3;
+    const float T = S[b] + S[d];
+    const float X = T - 2.f * (uu[b] + uu[d]);
+    const float Z = fmaf(u[a], X, 2.f * (p[b][a] + p[d][a]));
+    H.E[a] = 3.f * S[a] - 1.5f * T;
+    H.O[a] = 3.f * u[a] - 4.5f * Z;
   }
-  if constexpr (c[2] != 0) {
-    home_a3_adj<0, 2>(M, tb * c[2] * h[0], Mb);
-    home_a3_adj<1, 2>(M, tb * c[2] * h[1], Mb);
+  constexpr int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2}, PD[3] = {2, 1, 0};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a = PA[e], b = PB[e], d = PD[e];
+    const float K = 3.f * (S[a] + S[b]) - 1.5f * S[d];
+    const float C = 9.f * S[sidx(a, b)];
+    const float A = 3.f * u[a] + (9.f * a3[b][a] - 4.5f * a3[d][a]);
+    const float B = 3.f * u[b] + (9.f * a3[a][b] - 4.5f * a3[d][b]);
+    H.P1[e] = K + C;
+    H.P2[e] = K - C;
+    H.ApB[e] = A + B;
+    H.AmB[e] = A - B;
   }
+  const float r = 1.f + M.drho;
+  constexpr float W[3] = {1.f / 3.f, 1.f / 18.f, 1.f / 36.f};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    H.wr[c] = W[c] * r;
+    H.wd[c] = W[c] * M.drho;
+  }
+  return H;
+}
+
+// Direction Q's class: |c|^2 (n), its axis (n = 1) or axis pair (n = 2)
+template <int Q>
+struct HomeDir {
+  static constexpr int c0 = LC[Q][0], c1 = LC[Q][1], c2 = LC[Q][2];
+  static constexpr int n = (c0 != 0) + (c1 != 0) + (c2 != 0);
+  static constexpr int axis = c0 != 0 ? 0 : (c1 != 0 ? 1 : 2);
+  static constexpr int pair = c2 == 0 ? 0 : (c1 == 0 ? 1 : 2);
+  static constexpr int pa = pair == 2 ? 1 : 0, pb = pair == 0 ? 1 : 2;
+};
+
+// the bracket s_Q of f_Q - w_Q = w_Q (drho + (1 + drho) s_Q)
+template <int Q>
+__device__ __forceinline__ float home_s_t(const HomeTerms &H) {
+  using Dq = HomeDir<Q>;
+  if constexpr (Dq::n == 0) {
+    return H.s0;
+  } else if constexpr (Dq::n == 1) {
+    constexpr int a = Dq::axis;
+    return LC[Q][a] > 0 ? H.E[a] + H.O[a] : H.E[a] - H.O[a];
+  } else {
+    constexpr int e = Dq::pair, sa = LC[Q][Dq::pa], sb = LC[Q][Dq::pb];
+    if constexpr (sa == sb) return sa > 0 ? H.P1[e] + H.ApB[e] : H.P1[e] - H.ApB[e];
+    else return sa > 0 ? H.P2[e] + H.AmB[e] : H.P2[e] - H.AmB[e];
+  }
+}
+
+// f_Q - w_Q from the shared terms
+template <int Q>
+__device__ __forceinline__ float home_pop_t(const HomeTerms &H) {
+  return fmaf(H.wr[HomeDir<Q>::n], home_s_t<Q>(H), H.wd[HomeDir<Q>::n]);
+}
+
+// Reverse of home_pop_t: the adjoint T of f_Q - w_Q added into the adjoints
+// of the shared terms (B, zero-initialised by the caller).
+template <int Q>
+__device__ __forceinline__ void home_pop_t_adj(const HomeTerms &H, float T, HomeTerms &B) {
+  using Dq = HomeDir<Q>;
+  constexpr int n = Dq::n;
+  B.wr[n] += T * home_s_t<Q>(H);
+  B.wd[n] += T;
+  const float bs = T * H.wr[n];
+  if constexpr (n == 0) {
+    B.s0 += bs;
+  } else if constexpr (n == 1) {
+    constexpr int a = Dq::axis;
+    B.E[a] += bs;
+    B.O[a] += LC[Q][a] > 0 ? bs : -bs;
+  } else {
+    constexpr int e = Dq::pair, sa = LC[Q][Dq::pa], sb = LC[Q][Dq::pb];
+    if constexpr (sa == sb) {
+      B.P1[e] += bs;
+      B.ApB[e] += sa > 0 ? bs : -bs;
+    } else {
+      B.P2[e] += bs;
+      B.AmB[e] += sa > 0 ? bs : -bs;
+    }
+  }
+}
+
+// Reverse of home_terms: the adjoints of the shared terms (B) taken back to
+// those of the moments, every step of home_terms in reverse order.
+__device__ __forceinline__ Mom home_terms_adj(const Mom &M, const HomeTerms &B) {
+  const float *u = M.u, *S = M.S;
+  float uu[3], D[3], p[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uu[a] = u[a] * u[a];
+    D[a] = S[a] - 2.f * uu[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      if (a != b) p[a][b] = S[sidx(a, b)] * u[a];
+  Mom Mb;
+  float buu[3] = {0.f, 0.f, 0.f}, bD[3] = {0.f, 0.f, 0.f}, bp[3][3] = {}, ba3[3][3] = {};
+  Mb.drho = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Mb.u[a] = 0.f;
+#pragma unroll
+  for (int s6 = 0; s6 < 6; ++s6) Mb.S[s6] = 0.f;
+  // wr = W (1 + drho), wd = W drho
+  constexpr float W[3] = {1.f / 3.f, 1.f / 18.f, 1.f / 36.f};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Mb.drho += W[c] * (B.wr[c] + B.wd[c]);
+  // pairs: P1 = K + C, P2 = K - C, ApB = A + B, AmB = A - B
+  constexpr int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2}, PD[3] = {2, 1, 0};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a = PA[e], b = PB[e], d = PD[e];
+    const float bK = B.P1[e] + B.P2[e], bC = B.P1[e] - B.P2[e];
+    const float bA = B.ApB[e] + B.AmB[e], bB = B.ApB[e] - B.AmB[e];
+    Mb.S[a] += 3.f * bK;
+    Mb.S[b] += 3.f * bK;
+    Mb.S[d] -= 1.5f * bK;
+    Mb.S[sidx(a, b)] += 9.f * bC;
+    Mb.u[a] += 3.f * bA;
+    ba3[b][a] += 9.f * bA;
+    ba3[d][a] -= 4.5f * bA;
+    Mb.u[b] += 3.f * bB;
+    ba3[a][b] += 9.f * bB;
+    ba3[d][b] -= 4.5f * bB;
+  }
+  // axes: E = 3 S_aa - 3/2 T, O = 3 u_a - 9/2 Z, Z = u_a X + 2 (p_ba + p_da),
+  // X = T - 2 (uu_b + uu_d), T = S_bb + S_dd
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, d = (a + 2) % 3;
+    const float T = S[b] + S[d];
+    const float X = T - 2.f * (uu[b] + uu[d]);
+    Mb.S[a] += 3.f * B.E[a];
+    Mb.u[a] += 3.f * B.O[a];
+    const float bZ = -4.5f * B.O[a];
+    Mb.u[a] += X * bZ;
+    const float bX = u[a] * bZ;
+    bp[b][a] += 2.f * bZ;
+    bp[d][a] += 2.f * bZ;
+    const float bT = bX - 1.5f * B.E[a];
+    buu[b] -= 2.f * bX;
+    buu[d] -= 2.f * bX;
+    Mb.S[b] += bT;
+    Mb.S[d] += bT;
+  }
+  // s0 = -3/2 tr S
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Mb.S[a] -= 1.5f * B.s0;
+  // a3_ab = u_b D_a + 2 p_ab, p_ab = S_ab u_a
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (a == b) continue;
+      Mb.u[b] += D[a] * ba3[a][b];
+      bD[a] += u[b] * ba3[a][b];
+      bp[a][b] += 2.f * ba3[a][b];
+      Mb.S[sidx(a, b)] += u[a] * bp[a][b];
+      Mb.u[a] += S[sidx(a, b)] * bp[a][b];
+    }
+  // D_a = S_aa - 2 uu_a, uu_a = u_a^2
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Mb.S[a] += bD[a];
+    buu[a] -= 2.f * bD[a];
+    Mb.u[a] += 2.f * u[a] * buu[a];
+  }
+  return Mb;
 }
 
 // moments of the pulled set
@@ -598,13 +743,13 @@ __device__ __forceinline__ float home_inlet_pop(const LbmDev &P, int t, int j, i
   int sj, sk;
   bool bounce;
   row_source(P, j, k, LC[q][1], LC[q][2], &sj, &sk, &bounce);
-  const Mom M = inlet_mom(P, sj, sk);
+  const HomeTerms H = home_terms(inlet_mom(P, sj, sk));
   switch (t) {
-    case 0: return home_pop<1>(M);
-    case 1: return home_pop<7>(M);
-    case 2: return home_pop<9>(M);
-    case 3: return home_pop<13>(M);
-    default: return home_pop<15>(M);
+    case 0: return home_pop_t<1>(H);
+    case 1: return home_pop_t<7>(H);
+    case 2: return home_pop_t<9>(H);
+    case 3: return home_pop_t<13>(H);
+    default: return home_pop_t<15>(H);
   }
 }
 
@@ -695,94 +840,6 @@ __device__ __forceinline__ HomeTile home_tile(const LbmDev &P) {
 static dim3 home_tile_grid(const LbmDev &P) {
   const int64_t nt = (int64_t)((P.nx + HT_X - 1) / HT_X) * ((P.ny + HT_Y - 1) / HT_Y) * ((P.nz + HT_Z - 1) / HT_Z);
   return dim3((unsigned)(((nt + N_XCD - 1) / N_XCD) * N_XCD));
-}
-
-// Shared terms of f_q - w_q = w_q (drho + (1 + drho) s_q):
-//   c = +-e_a:                 s = E_a +- O_a
-//   c = sa e_a + sb e_b:       s = K + sa sb C + sa A + sb B   (pair ab, d the third axis)
-//   c = 0:                     s = -3/2 tr S
-// with a3_AB = u_B (S_AA - 2 u_A^2) + 2 S_AB u_A,
-//   E_a = 3 S_aa - 3/2 (S_bb + S_dd),
-//   O_a = 3 u_a - 9/2 [u_a (S_bb + S_dd - 2 u_b^2 - 2 u_d^2) + 2 (S_ab u_b + S_ad u_d)],
-//   K = 3 (S_aa + S_bb) - 3/2 S_dd,  C = 9 S_ab,
-//   A = 3 u_a + 9 a3_ba - 9/2 a3_da,  B = 3 u_b + 9 a3_ab - 9/2 a3_db;
-// the pairs keep K + C, K - C, A + B and A - B for their four sign cases.
-struct HomeTerms {
-  float s0;
-  float E[3], O[3];                    // axes x, y, z
-  float P1[3], P2[3], ApB[3], AmB[3];  // pairs xy, xz, yz
-  float wr[3], wd[3];                  // w (1 + drho), w drho for |c|^2 = 0, 1, 2
-};
-
-__device__ __forceinline__ HomeTerms home_terms(const Mom &M) {
-  const float *u = M.u, *S = M.S;
-  float uu[3], D[3], p[3][3], a3[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    uu[a] = u[a] * u[a];
-    D[a] = S[a] - 2.f * uu[a];
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      if (a == b) continue;
-      p[a][b] = S[sidx(a, b)] * u[a];
-      a3[a][b] = fmaf(u[b], D[a], 2.f * p[a][b]);
-    }
-  HomeTerms H;
-  H.s0 = -1.5f * (S[0] + S[1] + S[2]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int b = (a + 1) % 3, d = (a + 2) % 3;
-    const float T = S[b] + S[d];
-    const float X = T - 2.f * (uu[b] + uu[d]);
-    const float Z = fmaf(u[a], X, 2.f * (p[b][a] + p[d][a]));
-    H.E[a] = 3.f * S[a] - 1.5f * T;
-    H.O[a] = 3.f * u[a] - 4.5f * Z;
-  }
-  constexpr int PA[3] = {0, 0, 1}, PB[3] = {1, 2, 2}, PD[3] = {2, 1, 0};
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int a = PA[e], b = PB[e], d = PD[e];
-    const float K = 3.f * (S[a] + S[b]) - 1.5f * S[d];
-    const float C = 9.f * S[sidx(a, b)];
-    const float A = 3.f * u[a] + (9.f * a3[b][a] - 4.5f * a3[d][a]);
-    const float B = 3.f * u[b] + (9.f * a3[a][b] - 4.5f * a3[d][b]);
-    H.P1[e] = K + C;
-    H.P2[e] = K - C;
-    H.ApB[e] = A + B;
-    H.AmB[e] = A - B;
-  }
-  const float r = 1.f + M.drho;
-  constexpr float W[3] = {1.f / 3.f, 1.f / 18.f, 1.f / 36.f};
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    H.wr[c] = W[c] * r;
-    H.wd[c] = W[c] * M.drho;
-  }
-  return H;
-}
-
-// f_Q - w_Q from the shared terms
-template <int Q>
-__device__ __forceinline__ float home_pop_t(const HomeTerms &H) {
-  constexpr int c0 = LC[Q][0], c1 = LC[Q][1], c2 = LC[Q][2];
-  constexpr int n = (c0 != 0) + (c1 != 0) + (c2 != 0);
-  float s;
-  if constexpr (n == 0) {
-    s = H.s0;
-  } else if constexpr (n == 1) {
-    constexpr int a = c0 != 0 ? 0 : (c1 != 0 ? 1 : 2);
-    s = LC[Q][a] > 0 ? H.E[a] + H.O[a] : H.E[a] - H.O[a];
-  } else {
-    constexpr int e = c2 == 0 ? 0 : (c1 == 0 ? 1 : 2);
-    constexpr int a = e == 2 ? 1 : 0, b = e == 0 ? 1 : 2;
-    constexpr int sa = LC[Q][a], sb = LC[Q][b];
-    if constexpr (sa == sb) s = sa > 0 ? H.P1[e] + H.ApB[e] : H.P1[e] - H.ApB[e];
-    else s = sa > 0 ? H.P2[e] + H.AmB[e] : H.P2[e] - H.AmB[e];
-  }
-  return fmaf(H.wr[n], s, H.wd[n]);
 }
 
 // Population Q of a tile node into the slot of the node at +c_Q when that is
@@ -1312,9 +1369,9 @@ __device__ __forceinline__ void gather_row(std::integer_sequence<int, Qs...>, co
 }
 
 template <int... Qs>
-__device__ __forceinline__ void pops_adj(std::integer_sequence<int, Qs...>, const Mom &M, const float T[19],
-                                         Mom &Mb) {
-  (home_pop_adj<Qs>(M, T[Qs], Mb), ...);
+__device__ __forceinline__ void home_pops_adj(std::integer_sequence<int, Qs...>, const HomeTerms &H, const float T[19],
+                                              HomeTerms &B) {
+  (home_pop_t_adj<Qs>(H, T[Qs], B), ...);
 }
 
 // Pass 2 of both reverse steps, per node: T_p gathered as above, then for
@@ -1340,8 +1397,9 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_adj_gather(LbmDev P, const float 
   else gather_row<0>(std::make_integer_sequence<int, 19>{}, P, gbar, s_sol, i, j, k, x0, node, T);
   if constexpr (HOME) {
     const Mom own = load_mom_at(min, P.L, node);
-    Mom Mb{};
-    pops_adj(std::make_integer_sequence<int, 19>{}, own, T, Mb);
+    HomeTerms B{};
+    home_pops_adj(std::make_integer_sequence<int, 19>{}, home_terms(own), T, B);
+    const Mom Mb = home_terms_adj(own, B);
     const float v[HM_N] = {Mb.drho, Mb.u[0], Mb.u[1], Mb.u[2], Mb.S[0], Mb.S[1], Mb.S[2], Mb.S[3], Mb.S[4], Mb.S[5]};
 #pragma unroll
     for (int q = 0; q < HM_N; ++q) {
