@@ -1144,8 +1144,8 @@ __device__ __forceinline__ bool home_tile_pulled(const LbmDev &P, const HomeTile
   return true;
 }
 
-// 8 waves per SIMD (some scalar registers spill to vector lanes): two
-// tiles per CU, the 128 x 64 x 64 lattice's 512 tiles in one round.
+// 8 waves per SIMD: two tiles per CU, the 128 x 64 x 64 lattice's 512 tiles
+// in one round.
 template <bool SOLID>
 __global__ __launch_bounds__(HT_N) __attribute__((amdgpu_waves_per_eu(8))) void k_home_tile(
     LbmDev P, const float *__restrict__ min, float *__restrict__ mout, const uint8_t *__restrict__ solid,
@@ -1419,7 +1419,9 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_adj_gather(LbmDev P, const float 
 // recompute the pulled populations and moments and write the adjoint of each
 // pulled population through the BGK collision to fbar [19][L] (zeros at a
 // solid node, whose stored rest state does not depend on the inputs).
-template <bool SOLID>
+// XCD: rows handed to the XCDs in contiguous runs (lattices that stay in the
+// last-level cache, as in the forward step), else one block per row block.
+template <bool SOLID, bool XCD>
 __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_adj_pull(LbmDev P, const float *__restrict__ fin,
                                                             const uint8_t *__restrict__ solid,
                                                             const float *__restrict__ gout,
@@ -1428,8 +1430,19 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_adj_pull(LbmDev P, const floa
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
   __shared__ int s_any[LBM_BLOCK / 64];
   __shared__ float s_inl[5];
-  const int x0 = blockIdx.x * LBM_BLOCK;
-  const int i = x0 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  int x0, j, k;
+  if (XCD) {
+    const RowBlock rb = xcd_row_block(P);
+    if (!rb.live) return;  // block-uniform
+    x0 = rb.x0;
+    j = rb.j;
+    k = rb.k;
+  } else {
+    x0 = blockIdx.x * LBM_BLOCK;
+    j = blockIdx.y;
+    k = blockIdx.z;
+  }
+  const int i = x0 + threadIdx.x;
   const uint32_t node = (uint32_t)i + (uint32_t)P.nx * ((uint32_t)j + (uint32_t)P.ny * (uint32_t)k);
   const bool inlet_row = x0 == 0 && P.bc[0] == DW_BC_INLET;
   if (inlet_row) stage_inlet(P, j, k, s_inl);
@@ -1660,14 +1673,23 @@ static int run_lbm_step_adj(const char *name, const dw_lattice *lat, const dw_lb
   DW_REQUIRE(f_in_bar != f_in && f_in_bar != f_out_bar, DW_EINVAL, "%s: f_in_bar must not alias", name);
   DW_REQUIRE(work != f_in && work != f_out_bar && work != f_in_bar && work != u_out_bar, DW_EINVAL,
              "%s: work must not alias another argument", name);
+  const bool big = lbm_streams(P);
   if (solid) {
-    hipLaunchKernelGGL(k_lbm_adj_pull<true>, lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, f_out_bar, u_out_bar,
-                       work);
+    if (big)
+      hipLaunchKernelGGL((k_lbm_adj_pull<true, false>), lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, f_out_bar,
+                         u_out_bar, work);
+    else
+      hipLaunchKernelGGL((k_lbm_adj_pull<true, true>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid,
+                         f_out_bar, u_out_bar, work);
     hipLaunchKernelGGL((k_adj_gather<true, false>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, work,
                        f_in_bar);
   } else {
-    hipLaunchKernelGGL(k_lbm_adj_pull<false>, lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, f_out_bar,
-                       u_out_bar, work);
+    if (big)
+      hipLaunchKernelGGL((k_lbm_adj_pull<false, false>), lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid,
+                         f_out_bar, u_out_bar, work);
+    else
+      hipLaunchKernelGGL((k_lbm_adj_pull<false, true>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid,
+                         f_out_bar, u_out_bar, work);
     hipLaunchKernelGGL((k_adj_gather<false, false>), xcd_lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, solid, work,
                        f_in_bar);
   }
