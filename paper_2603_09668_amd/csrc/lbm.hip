@@ -41,7 +41,11 @@ struct LbmDev {
 
 // launch shape: threads along x, one block row per (y, z) line
 constexpr int LBM_BLOCK = 128;
-constexpr int SOL_W = LBM_BLOCK + 8;  // staged solid bytes per row: x0 - 4 .. x0 + LBM_BLOCK + 3
+// the forward step's block width on large lattices whose rows are whole
+// multiples of it (one block per row: no x-shifted reads across a block seam)
+constexpr int LBM_BLOCK_WIDE = 256;
+// row pitch of the staged solid flags: x0 - 4 .. x0 + width + 3 for either width
+constexpr int SOL_W = LBM_BLOCK_WIDE + 8;
 
 // Where a pulled population comes from: the source node, this node's
 // opposite population (bounce-back), or the inlet ghost.
@@ -70,24 +74,31 @@ __device__ __forceinline__ float inlet_feq_shift(const LbmDev &P, int q, int j, 
 }
 
 // Solid flags of the 3 x 3 (y, z) rows around this block's row,
-// x0 - 4 .. x0 + LBM_BLOCK + 3, staged in LDS: row r = (dy + 1) + 3 (dz + 1).
+// x0 - 4 .. x0 + BW + 3 (BW: the block width), staged in LDS: row r =
+// (dy + 1) + 3 (dz + 1).
 // A periodic axis stages the wrapped row / positions, so every source that
 // is not a bounce-back or inlet source finds its flag here; rows beyond a
 // bounce-back face and positions beyond a non-periodic x face read as fluid.
 // Whole 4-byte words are loaded where the row is 4-byte aligned.
-constexpr int SOL_WORDS = 9 * (SOL_W / 4);
-constexpr int SOL_PER_THREAD = (SOL_WORDS + LBM_BLOCK - 1) / LBM_BLOCK;
+template <int BW>
+struct SolStage {
+  static constexpr int ROW_WORDS = (BW + 8) / 4;              // staged words per row
+  static constexpr int WORDS = 9 * ROW_WORDS;
+  static constexpr int PER_THREAD = (WORDS + BW - 1) / BW;
+};
 
+template <int BW>
 __device__ __forceinline__ void load_solid_rows(const LbmDev &P, const uint8_t *__restrict__ solid, int x0, int j,
-                                                int k, uint32_t v[SOL_PER_THREAD]) {
-  constexpr int WORDS = SOL_W / 4;
+                                                int k, uint32_t v[SolStage<BW>::PER_THREAD]) {
+  using St = SolStage<BW>;
+  constexpr int WORDS = St::ROW_WORDS;
   const bool aligned = (P.nx & 3) == 0 && (((uintptr_t)solid) & 3) == 0;
   const bool xper = P.bc[0] == DW_BC_PERIODIC;
 #pragma unroll
-  for (int u = 0; u < SOL_PER_THREAD; ++u) {
-    const int q = threadIdx.x + u * LBM_BLOCK;
+  for (int u = 0; u < St::PER_THREAD; ++u) {
+    const int q = threadIdx.x + u * BW;
     v[u] = 0;
-    if (q >= SOL_WORDS) continue;
+    if (q >= St::WORDS) continue;
     const int r = q / WORDS, w = q % WORDS;
     int jj = j + r % 3 - 1, kk = k + r / 3 - 1;
     if ((unsigned)jj >= (unsigned)P.ny) {
@@ -118,11 +129,15 @@ __device__ __forceinline__ void load_solid_rows(const LbmDev &P, const uint8_t *
   }
 }
 
-__device__ __forceinline__ void store_solid_rows(const uint32_t v[SOL_PER_THREAD], uint8_t (*s_sol)[SOL_W]) {
+template <int BW>
+__device__ __forceinline__ void store_solid_rows(const uint32_t v[SolStage<BW>::PER_THREAD],
+                                                 uint8_t (*s_sol)[SOL_W]) {
+  using St = SolStage<BW>;
 #pragma unroll
-  for (int u = 0; u < SOL_PER_THREAD; ++u) {
-    const int q = threadIdx.x + u * LBM_BLOCK;
-    if (q < SOL_WORDS) reinterpret_cast<uint32_t *>(&s_sol[0][0])[q] = v[u];
+  for (int u = 0; u < St::PER_THREAD; ++u) {
+    const int q = threadIdx.x + u * BW;
+    if (q < St::WORDS)
+      reinterpret_cast<uint32_t *>(&s_sol[0][0])[(q / St::ROW_WORDS) * (SOL_W / 4) + q % St::ROW_WORDS] = v[u];
   }
 }
 
@@ -335,7 +350,7 @@ __device__ __forceinline__ void st_out(float *__restrict__ plane, uint32_t node,
 // BIG: a lattice larger than the last-level cache (lbm_streams): the output
 // is stored with nontemporal stores.  Lanes past the lattice's x end return
 // after the block's staging barrier.
-template <bool SOLID, bool BIG>
+template <bool SOLID, bool BIG, int BW>
 __device__ __forceinline__ void lbm_row_block(const LbmDev &P, const float *__restrict__ fin,
                                               float *__restrict__ fout, const uint8_t *__restrict__ solid,
                                               float *__restrict__ rho_out, float *__restrict__ u_out, int x0, int j,
@@ -351,17 +366,17 @@ __device__ __forceinline__ void lbm_row_block(const LbmDev &P, const float *__re
   // plain pull (block-uniform branch).
   bool any = false;
   if (SOLID) {
-    uint32_t sv[SOL_PER_THREAD];
-    load_solid_rows(P, solid, x0, j, k, sv);
-    store_solid_rows(sv, s_sol);
+    uint32_t sv[SolStage<BW>::PER_THREAD];
+    load_solid_rows<BW>(P, solid, x0, j, k, sv);
+    store_solid_rows<BW>(sv, s_sol);
     uint32_t mine = 0;
 #pragma unroll
-    for (int u = 0; u < SOL_PER_THREAD; ++u) mine |= sv[u];
+    for (int u = 0; u < SolStage<BW>::PER_THREAD; ++u) mine |= sv[u];
     const bool wave_any = __ballot(mine != 0) != 0ull;
     if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = wave_any;
     __syncthreads();
 #pragma unroll
-    for (int w = 0; w < LBM_BLOCK / 64; ++w) any = any || s_any[w] != 0;
+    for (int w = 0; w < BW / 64; ++w) any = any || s_any[w] != 0;
   } else if (inlet_row) {
     __syncthreads();
   }
@@ -421,16 +436,19 @@ __device__ __forceinline__ void lbm_row_block(const LbmDev &P, const float *__re
 // (xcd_row_block) and the output stays cached.  Eight waves per SIMD: the
 // plane bases it would otherwise keep in scalar registers limit it to seven
 // (some spill to vector-register lanes instead).
-template <bool SOLID, bool BIG>
-__global__ __launch_bounds__(LBM_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_lbm_step(
+// BW: block width (LBM_BLOCK, or LBM_BLOCK_WIDE on a large lattice whose rows
+// are whole multiples of it); the XCD row runs are taken with LBM_BLOCK.
+template <bool SOLID, bool BIG, int BW = LBM_BLOCK>
+__global__ __launch_bounds__(BW) __attribute__((amdgpu_waves_per_eu(8))) void k_lbm_step(
     LbmDev P, const float *__restrict__ fin, float *__restrict__ fout, const uint8_t *__restrict__ solid,
     float *__restrict__ rho_out, float *__restrict__ u_out) {
+  static_assert(BIG || BW == LBM_BLOCK, "the XCD row runs are laid out in LBM_BLOCK blocks");
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
-  __shared__ int s_any[LBM_BLOCK / 64];
+  __shared__ int s_any[BW / 64];
   __shared__ float s_inl[5];
   int x0, j, k;
   if (BIG) {
-    x0 = blockIdx.x * LBM_BLOCK;
+    x0 = blockIdx.x * BW;
     j = blockIdx.y;
     k = blockIdx.z;
   } else {
@@ -440,7 +458,7 @@ __global__ __launch_bounds__(LBM_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) 
     j = rb.j;
     k = rb.k;
   }
-  lbm_row_block<SOLID, BIG>(P, fin, fout, solid, rho_out, u_out, x0, j, k, s_sol, s_any, s_inl);
+  lbm_row_block<SOLID, BIG, BW>(P, fin, fout, solid, rho_out, u_out, x0, j, k, s_sol, s_any, s_inl);
 }
 
 // The step behind a device switch (dw_lbm_params.skip, e.g. a fallback
@@ -462,8 +480,8 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_lbm_step_gated(LbmDev P, const fl
   const int64_t nblocks = (int64_t)nbx * P.ny * P.nz;
   for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
     const int64_t row = b / nbx;
-    lbm_row_block<SOLID, BIG>(P, fin, fout, solid, rho_out, u_out, (int)(b % nbx) * LBM_BLOCK, (int)(row % P.ny),
-                              (int)(row / P.ny), s_sol, s_any, s_inl);
+    lbm_row_block<SOLID, BIG, LBM_BLOCK>(P, fin, fout, solid, rho_out, u_out, (int)(b % nbx) * LBM_BLOCK,
+                                         (int)(row % P.ny), (int)(row / P.ny), s_sol, s_any, s_inl);
     __syncthreads();  // the next row block restages the shared rows
   }
 }
@@ -1286,12 +1304,12 @@ __device__ __forceinline__ void store_pop_bars(std::integer_sequence<int, Qs...>
 // is set (block-uniform; has a barrier).
 __device__ __forceinline__ bool stage_solid(const LbmDev &P, const uint8_t *__restrict__ solid, int x0, int j, int k,
                                             uint8_t (*s_sol)[SOL_W], int *s_any) {
-  uint32_t sv[SOL_PER_THREAD];
-  load_solid_rows(P, solid, x0, j, k, sv);
-  store_solid_rows(sv, s_sol);
+  uint32_t sv[SolStage<LBM_BLOCK>::PER_THREAD];
+  load_solid_rows<LBM_BLOCK>(P, solid, x0, j, k, sv);
+  store_solid_rows<LBM_BLOCK>(sv, s_sol);
   uint32_t mine = 0;
 #pragma unroll
-  for (int u = 0; u < SOL_PER_THREAD; ++u) mine |= sv[u];
+  for (int u = 0; u < SolStage<LBM_BLOCK>::PER_THREAD; ++u) mine |= sv[u];
   const bool wave_any = __ballot(mine != 0) != 0ull;
   if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = wave_any;
   __syncthreads();
@@ -1640,6 +1658,15 @@ extern "C" int lbm_step(const dw_lattice *lat, const dw_lbm_params *params, cons
     else
       hipLaunchKernelGGL((k_lbm_step_gated<false, false>), grid, dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid,
                          rho_out, u_out);
+  } else if (lbm_streams(P) && P.nx % LBM_BLOCK_WIDE == 0) {
+    // one block per row
+    const dim3 grid((unsigned)(P.nx / LBM_BLOCK_WIDE), (unsigned)P.ny, (unsigned)P.nz);
+    if (solid)
+      hipLaunchKernelGGL((k_lbm_step<true, true, LBM_BLOCK_WIDE>), grid, dim3(LBM_BLOCK_WIDE), 0, s, P, f_in, f_out,
+                         solid, rho_out, u_out);
+    else
+      hipLaunchKernelGGL((k_lbm_step<false, true, LBM_BLOCK_WIDE>), grid, dim3(LBM_BLOCK_WIDE), 0, s, P, f_in, f_out,
+                         solid, rho_out, u_out);
   } else if (lbm_streams(P)) {
     if (solid)
       hipLaunchKernelGGL((k_lbm_step<true, true>), lbm_grid(P), dim3(LBM_BLOCK), 0, s, P, f_in, f_out, solid, rho_out,

@@ -68,6 +68,19 @@ CASES = {
                             solid=[(slice(0, 5), slice(1, 3), slice(0, 2)), (slice(1, 4), slice(3, 5), slice(62, 64))]),
     "inlet_bb_waves": dict(dims=(64, 6, 5), bc=(2, 1, 0, 0, 1, 1), force=(0.0, 0.0, 0.0), gust=(0.05, 60.0, 1.0, 0.0, 0.0),
                            solid=[(slice(0, 5), slice(1, 3), slice(0, 2)), (slice(1, 4), slice(3, 5), slice(62, 64))]),
+    # lattices past the last-level cache (two population arrays > 256 MB, the
+    # streaming form of the step): 320-node rows in 128-node blocks, solids
+    # across both block seams and on the outlet face ...
+    "large_rows_320": dict(dims=(320, 96, 64), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 90.0, 1.0, 1.0, 0.4),
+                           solid=[(slice(10, 14), slice(40, 44), slice(126, 131)),
+                                  (slice(20, 24), slice(50, 54), slice(254, 259)),
+                                  (slice(30, 33), slice(60, 63), slice(316, 320))]),
+    # ... and 512-node rows in two 256-node blocks, solids across their seam
+    # and on the inlet and outlet faces
+    "large_rows_512": dict(dims=(512, 64, 64), bc=None, force=(0.0, 0.0, 0.0), gust=(0.05, 70.0, 0.0, 1.0, 0.9),
+                           solid=[(slice(10, 13), slice(20, 23), slice(253, 260)),
+                                  (slice(30, 33), slice(40, 43), slice(0, 3)),
+                                  (slice(40, 43), slice(10, 13), slice(509, 512))]),
 }
 
 
