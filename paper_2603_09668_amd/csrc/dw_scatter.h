@@ -96,19 +96,30 @@ __device__ __forceinline__ int sc_wave_scan(int v) {
 }
 
 // Wave 0: exclusive scan of the 64 cell counts into s_off / s_cur and the
-// unit descriptors (first slot | count << 10 | node base << 17).
+// unit descriptors (first slot | count << 10 | node base << 17).  The units
+// are listed whole ones first, then the partial ones (each cell's last) by
+// decreasing length, so that the two units a wave takes at a time have
+// nearly the same length and the matrix core idles less on the shorter.
+// The order depends only on the counts.
 __device__ __forceinline__ void sc_scan_units(int lane, const int *s_cnt, int *s_off, int *s_cur, int *s_udesc,
                                               int *s_nunits) {
   const int v = s_cnt[lane];
   const int inc = sc_wave_scan(v);
   s_off[lane] = inc - v;
   s_cur[lane] = inc - v;
-  const int nu = (v + SC_UNIT - 1) / SC_UNIT;
-  const int uinc = sc_wave_scan(nu);
-  const int u0 = uinc - nu;
   const int nbase = (lane & 3) + SC_L * (((lane >> 2) & 3) + SC_L * (lane >> 4));
-  for (int q = 0; q < nu; ++q) s_udesc[u0 + q] = (inc - v + q * SC_UNIT) | (min(SC_UNIT, v - q * SC_UNIT) << 10) | (nbase << 17);
-  if (lane == 63) *s_nunits = uinc;
+  const int nf = v / SC_UNIT, pl = v % SC_UNIT;  // whole units, length of the partial one
+  const int finc = sc_wave_scan(nf);
+  const int nfull = __shfl(finc, 63, 64);
+  for (int q = 0; q < nf; ++q) s_udesc[finc - nf + q] = (inc - v + q * SC_UNIT) | (SC_UNIT << 10) | (nbase << 17);
+  const uint64_t below = (1ull << lane) - 1ull;
+  int pos = nfull;
+  for (int len = SC_UNIT - 1; len > 0; --len) {
+    const uint64_t m = __ballot(pl == len);
+    if (pl == len) s_udesc[pos + __popcll(m & below)] = (inc - v + nf * SC_UNIT) | (len << 10) | (nbase << 17);
+    pos += __popcll(m);
+  }
+  if (lane == 63) *s_nunits = pos;
 }
 
 // Stage one particle at `slot`: f, then m, q, A (A row-major).
