@@ -135,14 +135,14 @@ __device__ __forceinline__ void sc_stage(float (*s_dat)[SC_PITCH], float4 *s_f, 
 }
 
 // Pass over the units on the matrix cores; wave `wid` adds into wnode.
-// Two units per wave at a time.
+// Two adjacent units of the list (nearly equal lengths) per wave at a time.
 __device__ __forceinline__ void sc_units_mfma(const ScLane &L, int wid, const float (*s_dat)[SC_PITCH],
                                               const float4 *s_f, const int *s_udesc, int nunits, float (*wnode)[4]) {
-  for (int u = wid; u < nunits; u += 2 * SC_WAVES) {
+  for (int u = 2 * wid; u < nunits; u += 2 * SC_WAVES) {
     int k0[2], kn[2], cb[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const int ue = u + e * SC_WAVES;
+      const int ue = u + e;
       const int d = ue < nunits ? s_udesc[ue] : 0;
       k0[e] = d & 1023;
       kn[e] = (d >> 10) & 127;
