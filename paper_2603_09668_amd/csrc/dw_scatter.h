@@ -173,10 +173,12 @@ __device__ __forceinline__ void sc_units_mfma(const ScLane &L, int wid, const fl
       for (int e = 0; e < 2; ++e)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
+          // no mask on w: a padding particle's feature operand is zero, a
+          // padding column (offset >= 27) is dropped below, and w is finite
+          // for both (f of a staged particle, the coefficients of offset 0)
           float w = 1.f;
 #pragma unroll
           for (int d = 0; d < 3; ++d) w *= L.cfa[t][d] + f3[e][d] * (L.cfb[t][d] + L.cfc[t][d] * f3[e][d]);
-          w = (live[e] && L.oo[t] < 27) ? w : 0.f;
           acc[e][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], w, acc[e][t], 0, 0, 0);
         }
     }
