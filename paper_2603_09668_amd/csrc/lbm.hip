@@ -998,7 +998,8 @@ struct HomeFaces {
 // source rules are those of the population step: a y / z face of the node
 // that the pull crosses bounces it; an x face bounces it, feeds the inlet,
 // or (outlet) clamps its source onto the outlet face of the source row.
-template <int Q, bool SOL>
+// FACES = false: the tile touches no non-periodic face (no face rule applies).
+template <int Q, bool SOL, bool FACES>
 __device__ __forceinline__ float home_take(const LbmDev &P, const float (*s_pop)[HT_N],
                                            const uint8_t (*s_sol)[HT_SY][HT_SX], const float (*s_inl)[5],
                                            bool inlet_tile, const HomeFaces &F, int l, int tx, int ty, int tz,
@@ -1008,10 +1009,10 @@ __device__ __forceinline__ float home_take(const LbmDev &P, const float (*s_pop)
   } else {
     constexpr int R = LOPP[Q], CX = LC[Q][0], CY = LC[Q][1], CZ = LC[Q][2];
     bool yz = false;
-    if constexpr (CY != 0) yz = CY > 0 ? F.lo[1] : F.hi[1];
-    if constexpr (CZ != 0) yz = yz || (CZ > 0 ? F.lo[2] : F.hi[2]);
+    if constexpr (FACES && CY != 0) yz = CY > 0 ? F.lo[1] : F.hi[1];
+    if constexpr (FACES && CZ != 0) yz = yz || (CZ > 0 ? F.lo[2] : F.hi[2]);
     bool xo = false;
-    if constexpr (CX != 0) xo = CX > 0 ? F.lo[0] : F.hi[0];
+    if constexpr (FACES && CX != 0) xo = CX > 0 ? F.lo[0] : F.hi[0];
     const int xrule = P.bc[CX > 0 ? 0 : 1];
     float g = s_pop[Q - 1][l];
     // an opaque register value: otherwise the selects below become one load
@@ -1023,19 +1024,19 @@ __device__ __forceinline__ float home_take(const LbmDev &P, const float (*s_pop)
       bb = bb || s_sol[tz + 1 - CZ][ty + 1 - CY][sx + 1] != 0;
     }
     g = bb ? f[R] : g;
-    if constexpr (inlet_slot(Q) >= 0) {
+    if constexpr (FACES && inlet_slot(Q) >= 0) {
       if (inlet_tile) g = (xo && !yz && xrule == DW_BC_INLET) ? s_inl[ty + HT_Y * tz][inlet_slot(Q)] : g;
     }
     return g;
   }
 }
 
-template <bool SOL, int... Qs>
+template <bool SOL, bool FACES, int... Qs>
 __device__ __forceinline__ void home_take_all(std::integer_sequence<int, Qs...>, const LbmDev &P,
                                               const float (*s_pop)[HT_N], const uint8_t (*s_sol)[HT_SY][HT_SX],
                                               const float (*s_inl)[5], bool inlet_tile, const HomeFaces &F, int l,
                                               int tx, int ty, int tz, const float f[19], float g[19]) {
-  ((g[Qs] = home_take<Qs, SOL>(P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty, tz, f)), ...);
+  ((g[Qs] = home_take<Qs, SOL, FACES>(P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty, tz, f)), ...);
 }
 
 // Moments of the pulled set from the sums and differences of opposite
@@ -1151,13 +1152,24 @@ __device__ __forceinline__ bool home_tile_pulled(const LbmDev &P, const HomeTile
   F.hi[1] = j == P.ny - 1 && P.bc[3] != DW_BC_PERIODIC;
   F.lo[2] = k == 0 && P.bc[4] != DW_BC_PERIODIC;
   F.hi[2] = k == P.nz - 1 && P.bc[5] != DW_BC_PERIODIC;
+  // a tile that touches no non-periodic face takes every pull from its slot
+  // or, next to a solid node, bounces it (block-uniform)
+  const bool faces = (T.x0 == 0 && P.bc[0] != DW_BC_PERIODIC) || (T.x0 + T.wx == P.nx && P.bc[1] != DW_BC_PERIODIC) ||
+                     (T.y0 == 0 && P.bc[2] != DW_BC_PERIODIC) || (T.y0 + T.wy == P.ny && P.bc[3] != DW_BC_PERIODIC) ||
+                     (T.z0 == 0 && P.bc[4] != DW_BC_PERIODIC) || (T.z0 + T.wz == P.nz && P.bc[5] != DW_BC_PERIODIC);
   float g[19];
-  if (any)
-    home_take_all<true>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty, tz,
-                        f, g);
+  if (any && faces)
+    home_take_all<true, true>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty,
+                              tz, f, g);
+  else if (any)
+    home_take_all<true, false>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx,
+                               ty, tz, f, g);
+  else if (faces)
+    home_take_all<false, true>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx,
+                               ty, tz, f, g);
   else
-    home_take_all<false>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx, ty,
-                         tz, f, g);
+    home_take_all<false, false>(std::make_integer_sequence<int, 19>{}, P, s_pop, s_sol, s_inl, inlet_tile, F, l, tx,
+                                ty, tz, f, g);
   A = home_pulled_moments(g);
   return true;
 }
