@@ -1408,8 +1408,12 @@ __device__ __forceinline__ void home_pops_adj(std::integer_sequence<int, Qs...>,
 // HOME (bar = m_in_bar [10][L]) sum_p T_p df_p/dM taken through the Hermite
 // expansion of this node's moments, for BGK (bar = f_in_bar [19][L]) T_p
 // itself.  A solid node's state feeds no population: it adds nothing.
+// Occupancy: BGK's pass asks for 8 waves per SIMD (7 % faster than the 7
+// its scalar registers allow otherwise); HOME's pass, which also takes the
+// expansion's adjoint, is faster at the occupancy its registers give, so it
+// asks for none (a minimum of 1).
 template <bool SOLID, bool HOME>
-__global__ __launch_bounds__(LBM_BLOCK) void k_adj_gather(LbmDev P, const float *__restrict__ min,
+__global__ __launch_bounds__(LBM_BLOCK) __attribute__((amdgpu_waves_per_eu(HOME ? 1 : 8))) void k_adj_gather(LbmDev P, const float *__restrict__ min,
                                                           const uint8_t *__restrict__ solid,
                                                           const float *__restrict__ gbar, float *__restrict__ bar) {
   __shared__ __attribute__((aligned(4))) uint8_t s_sol[9][SOL_W];
